@@ -1,0 +1,180 @@
+/*
+ * r3mg.h -- C ABI of the MI355X (gfx950) implementation of R3MG-C: conjugate gradients preconditioned by
+ * one V-cycle of an algebraic-geometric multilevel hierarchy built from support-point coordinates only.
+ *
+ * Paper: Polverino, Feder, Heltai, "R3MG-C: a high-order algebraic-geometric multilevel preconditioner for
+ * continuous finite element discretizations".
+ *   - Section 3 (Definition of an R-tree of order (m,M)) and Section 4 (point-based agglomeration): the
+ *     support points are agglomerated by an R-tree of axis-aligned boxes; each box owns its points.
+ *   - Section 4: prolongations evaluate the box-local Q^{p'} basis at the owned fine points (first level) or
+ *     inject parent-box polynomials into child boxes (agglomerated levels); level operators are inherited,
+ *     A_i = P_i^T A P_i.
+ *   - Section 6: the smoother is degree-3 Chebyshev-accelerated Jacobi tuned by Lanczos estimates, with
+ *     2 pre- and 2 post-smoothing steps; the coarsest problem is solved directly; PCG applies one V-cycle
+ *     per iteration.
+ *
+ * Conventions (all entry points):
+ *   - Host arrays passed to set-up are read and copied; the caller keeps ownership.
+ *   - Device pointers are HIP device memory owned by the caller (e.g. torch tensors); every operation is
+ *     ordered on the given hipStream_t (passed as void*; NULL means the default stream). Functions that
+ *     return values to the host synchronise that stream before returning.
+ *   - Vectors are float64 in the caller's numbering.  Multi-RHS arguments are nrhs contiguous vectors
+ *     (column j at offset j*n).
+ *   - A negative status means the call failed and modified nothing it was given (outputs undefined for
+ *     R3MG_ERR_HIP).  R3MG_NOT_CONVERGED (positive) means the solve ran to maxit: x holds the last iterate.
+ *   - Handles are not thread-safe; one handle serves one stream at a time.  No entry point falls back to the
+ *     CPU: without a usable gfx950 device the device entry points return R3MG_ERR_HIP.
+ */
+#ifndef R3MG_H
+#define R3MG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct r3mg_handle_* r3mg_handle;
+
+typedef enum {
+  R3MG_OK = 0,
+  R3MG_NOT_CONVERGED = 1,
+  R3MG_ERR_INVALID = -1,         /* bad argument, size, non-finite value, unsupported option */
+  R3MG_ERR_NOT_UNISOLVENT = -2,  /* a box cannot interpolate Q^{p'} from its owned points (Section 4 remarks) */
+  R3MG_ERR_DEGENERATE_BOX = -3,  /* a box with zero extent along an axis while p' >= 1 */
+  R3MG_ERR_NOT_SPD = -4,         /* non-positive diagonal, asymmetric Galerkin operator or failed Cholesky */
+  R3MG_ERR_OOM = -5,             /* device or host allocation failed, or an index exceeds int32 range */
+  R3MG_ERR_HIP = -6              /* a HIP runtime call failed */
+} r3mg_status;
+
+/* Options.  Defaults (r3mg_default_options) in brackets. */
+typedef struct {
+  int dim;              /* spatial dimension of the coordinates, 2 or 3 [3] */
+  int coarse_degree;    /* p' in 0..3, box polynomial degree per axis (p'=0: Nicolaides) [1] */
+  int leaf_size;        /* R-tree M: maximum number of points per leaf box [64] */
+  int max_levels;       /* levels including the fine one; 0 = until max_coarse_dofs or the root [0] */
+  int max_coarse_dofs;  /* stop coarsening at the first level with at most this many DoFs [2000] */
+  int skip_leaf_level;  /* 1 = first coarse level at depth t-d instead of the leaf depth t [0] */
+  int cheb_degree;      /* Chebyshev polynomial degree K >= 1 [3] */
+  int pre_steps;        /* smoothing applications before the coarse correction [2] */
+  int post_steps;       /* smoothing applications after the coarse correction [2] */
+  int lanczos_steps;    /* Lanczos steps of the eigenvalue estimate [10] */
+  double cheb_boost;    /* lambda_hi = boost * lambda_hat [1.1] */
+  double cheb_ratio;    /* lambda_lo = lambda_hi / ratio [30] */
+  int vcycle_fp32;      /* 0 = float64 V-cycle; 1 = float32 V-cycle inside float64 CG [0] */
+  int use_graph;        /* 1 = replay PCG iterations from a captured hipGraph [1] */
+} r3mg_options;
+
+typedef struct {
+  int64_t n;               /* rows of the level operator */
+  int64_t nnz;             /* stored entries (coarse levels: all B*B entries of every stored block) */
+  int64_t nboxes;          /* boxes that define the level (0 for the fine level) */
+  double max_box_extent;   /* largest box diagonal on the level (0 for the fine level) */
+  double lambda_hi;        /* Chebyshev interval (0 on the dense coarsest level) */
+  double lambda_lo;
+  double bytes_per_apply;  /* algorithmic bytes of one smoother operator application in the V-cycle precision */
+} r3mg_level_info;
+
+/* Fill *opt with the defaults listed above. */
+void r3mg_default_options(r3mg_options* opt);
+
+/* Host-only analysis (no GPU use): constrained rows, R-tree, level selection, DoF permutation, transfer tables,
+ * unisolvence check, Galerkin sparsity.  Inputs: coords (host, n x dim row-major float64), CSR of the symmetric
+ * fine operator A (host; row_ptr n+1 int64, col_idx nnz int32, vals nnz float64, columns ascending in each
+ * row).  Constrained rows are the rows whose stored off-diagonal values are all exactly 0.0 (identity
+ * Dirichlet rows).  On success *out is a handle that supports the export and info calls; r3mg_factor completes
+ * it for solving.  Errors: INVALID, NOT_UNISOLVENT, DEGENERATE_BOX, NOT_SPD, OOM. */
+r3mg_status r3mg_analyze(const double* coords, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                         const double* vals, const r3mg_options* opt, r3mg_handle* out);
+
+/* Device numeric set-up of an analysed handle on `stream`: upload, Galerkin products A_{l+1} = P_l^T A_l P_l,
+ * inverse diagonals, Lanczos estimates, dense coarsest Cholesky factorisation and inverse.  Synchronises. */
+r3mg_status r3mg_factor(r3mg_handle h, void* stream);
+
+/* r3mg_analyze followed by r3mg_factor (Section 4 set-up).  On failure *out is left NULL. */
+r3mg_status r3mg_setup(const double* coords, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                       const double* vals, const r3mg_options* opt, void* stream, r3mg_handle* out);
+
+/* Numeric re-set-up with new values on the same sparsity pattern (device array, nnz float64, caller's CSR
+ * order).  The constrained set, partition and transfers are kept.  Synchronises. */
+r3mg_status r3mg_update_values(r3mg_handle h, const double* vals_dev, void* stream);
+
+/* z = B r, one V-cycle (Section 4) in the handle's V-cycle precision, for nrhs right-hand sides. */
+r3mg_status r3mg_vcycle(r3mg_handle h, const double* r_dev, double* z_dev, int nrhs, void* stream);
+
+/* y = A_l x on level `level` in float64 (level 0 in the caller's numbering, coarse levels in box * B + q
+ * numbering), or, for level == -1, the fine operator as PCG applies it.  Diagnostic/parity entry point. */
+r3mg_status r3mg_level_apply(r3mg_handle h, int level, const double* x_dev, double* y_dev, void* stream);
+
+/* PCG preconditioned by r3mg_vcycle (Section 6 solver): x (in: initial guess, out: solution) for nrhs
+ * independent right-hand sides solved in lockstep, each frozen once ||r_k||_2 <= rtol ||r_0||_2.
+ * iters and relres (host arrays of nrhs, may be NULL) receive the iteration count and final ||r||/||r_0||.
+ * Returns R3MG_NOT_CONVERGED if any column reached maxit.  Synchronises. */
+r3mg_status r3mg_pcg_solve(r3mg_handle h, const double* b_dev, double* x_dev, int nrhs, double rtol, int maxit,
+                           void* stream, int* iters, double* relres);
+
+/* Several independent problems (each with its own handle, one right-hand side each) solved by PCG in one
+ * launch sequence: the iterations of all problems are captured into one hipGraph and replayed together.
+ * b[k], x[k] are device vectors of handle k.  iters/relres: host arrays of `count` (may be NULL). */
+r3mg_status r3mg_pcg_solve_group(int count, r3mg_handle* hs, const double* const* b, double* const* x,
+                                 double rtol, int maxit, void* stream, int* iters, double* relres);
+
+/* Per-level statistics: levels has room for *nlevels entries on input; on output *nlevels = level count
+ * (levels may be NULL to query the count). */
+r3mg_status r3mg_info(r3mg_handle h, r3mg_level_info* levels, int* nlevels);
+
+/* Ownership of level `level` >= 1: owner_box[i] (host, n entries) = box at that level owning fine point i in
+ * the caller's numbering; box_lohi (host, nboxes x 2*dim) = (lo_0..lo_{d-1}, hi_0..hi_{d-1}) per box.  Either
+ * pointer may be NULL.  Available after r3mg_analyze. */
+r3mg_status r3mg_export_partition(r3mg_handle h, int level, int32_t* owner_box, double* box_lohi);
+
+/* Prolongation from level+1 to level (host CSR): level 0 rows in the caller's numbering, all B entries of
+ * every unconstrained row stored; coarse numbering box * B + q.  Pass row_ptr == NULL to query the sizes via
+ * *nrows / *nnz (either may be NULL).  Available after r3mg_analyze. */
+r3mg_status r3mg_export_P(r3mg_handle h, int level, int64_t* row_ptr, int32_t* col, double* val,
+                          int64_t* nrows, int64_t* nnz);
+
+/* Galerkin operator of level >= 1 as host CSR (box * B + q numbering, all entries of stored blocks).  Pass
+ * row_ptr == NULL to query sizes.  Requires r3mg_factor. */
+r3mg_status r3mg_export_level(r3mg_handle h, int level, int64_t* row_ptr, int32_t* col, double* val,
+                              int64_t* nrows, int64_t* nnz);
+
+/* Average device time of one launch of the level-`level` fused smoother kernel (SpMV + Chebyshev update) in
+ * the V-cycle precision, over `reps` back-to-back launches timed with hipEvents on `stream`, and the
+ * algorithmic HBM bytes of one launch.  Diagnostic entry point for roofline measurement. */
+r3mg_status r3mg_time_smoother_kernel(r3mg_handle h, int level, int reps, void* stream, double* ms_per_launch,
+                                      double* bytes_per_launch);
+
+/* Adjoint gradient of a per-cell coefficient (standard adjoint method; not in the paper):
+ * g[e] = - sum_{a,b unconstrained} lam[c_ea] Ke_e[a,b] u[c_eb], cells (device, ncells x nloc int32, caller's
+ * numbering), Ke (device float64, nloc x nloc per cell at stride ke_stride doubles; 0 = one shared matrix),
+ * u, lam, g device float64. */
+r3mg_status r3mg_cell_grad(r3mg_handle h, const int32_t* cells_dev, int nloc, const double* Ke_dev,
+                           int64_t ke_stride, const double* u_dev, const double* lam_dev, double* g_dev,
+                           int64_t ncells, void* stream);
+
+/* Assembler of A(kappa) = sum_e kappa_e Ke_e on the unconstrained DoFs (identity on constrained rows) into
+ * the handle's fine CSR pattern in the caller's order: vals_dev[s] = sum over the (cell, a, b) contributions
+ * of slot s in a fixed order (deterministic).  cells (host, ncells x nloc int32).  The gather list is built
+ * once on the host; every pair (a,b) of a cell must be a stored entry of the pattern or constrained. */
+typedef struct r3mg_assembler_* r3mg_assembler;
+r3mg_status r3mg_assembler_create(r3mg_handle h, const int32_t* cells, int nloc, int64_t ncells,
+                                  r3mg_assembler* out);
+r3mg_status r3mg_assemble(r3mg_assembler a, const double* kappa_dev, const double* Ke_dev, int64_t ke_stride,
+                          double* vals_dev, void* stream);
+void r3mg_assembler_free(r3mg_assembler a);
+
+/* Host-only R-tree partition of points (Section 3 Definition, Section 4 point-based agglomeration): depth t
+ * of the bisection tree for `leaf`, and order (host, n int32): leaf-ordered position -> point index.
+ * Either output may be NULL. */
+r3mg_status r3mg_rtree(const double* coords, int64_t n, int dim, int leaf, int* depth, int32_t* order);
+
+void r3mg_free(r3mg_handle h);
+const char* r3mg_status_string(r3mg_status s);
+/* Message of the last failed call on the calling thread ("" after a successful call). */
+const char* r3mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* R3MG_H */

@@ -1,0 +1,297 @@
+"""ctypes binding of libr3mg.so (the R3MG-C C ABI declared in include/r3mg.h).
+
+Argument marshalling only: every step of the method runs in the library.  Device vectors are torch tensors
+(float64, on the GPU); their data pointers and torch's current HIP stream are passed through unchanged.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libr3mg.so")
+
+OK, NOT_CONVERGED = 0, 1
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID", -2: "NOT_UNISOLVENT", -3: "DEGENERATE_BOX",
+                -4: "NOT_SPD", -5: "OOM", -6: "HIP"}
+
+EXPORTED = [
+    "r3mg_default_options", "r3mg_analyze", "r3mg_factor", "r3mg_setup", "r3mg_update_values", "r3mg_vcycle",
+    "r3mg_level_apply", "r3mg_pcg_solve", "r3mg_pcg_solve_group", "r3mg_info", "r3mg_export_partition",
+    "r3mg_export_P", "r3mg_export_level", "r3mg_time_smoother_kernel", "r3mg_cell_grad", "r3mg_assembler_create",
+    "r3mg_assemble", "r3mg_assembler_free", "r3mg_rtree", "r3mg_free", "r3mg_status_string", "r3mg_last_error",
+]
+
+
+class R3mgError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        self.status = status
+        self.code = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{where}: {self.code} ({msg})")
+
+
+class _Options(C.Structure):
+    _fields_ = [("dim", C.c_int), ("coarse_degree", C.c_int), ("leaf_size", C.c_int), ("max_levels", C.c_int),
+                ("max_coarse_dofs", C.c_int), ("skip_leaf_level", C.c_int), ("cheb_degree", C.c_int),
+                ("pre_steps", C.c_int), ("post_steps", C.c_int), ("lanczos_steps", C.c_int),
+                ("cheb_boost", C.c_double), ("cheb_ratio", C.c_double), ("vcycle_fp32", C.c_int),
+                ("use_graph", C.c_int)]
+
+
+class _LevelInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("nboxes", C.c_int64), ("max_box_extent", C.c_double),
+                ("lambda_hi", C.c_double), ("lambda_lo", C.c_double), ("bytes_per_apply", C.c_double)]
+
+
+@dataclasses.dataclass
+class Options:
+    dim: int = 3
+    coarse_degree: int = 1
+    leaf_size: int = 64
+    max_levels: int = 0
+    max_coarse_dofs: int = 2000
+    skip_leaf_level: int = 0
+    cheb_degree: int = 3
+    pre_steps: int = 2
+    post_steps: int = 2
+    lanczos_steps: int = 10
+    cheb_boost: float = 1.1
+    cheb_ratio: float = 30.0
+    vcycle_fp32: int = 0
+    use_graph: int = 1
+
+    def _c(self) -> _Options:
+        return _Options(**dataclasses.asdict(self))
+
+
+_lib = None
+
+
+def lib():
+    """Load libr3mg.so; raises if it has not been built (there is no fallback implementation)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2607_28235_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
+    P = C.POINTER
+    L.r3mg_default_options.argtypes = [P(_Options)]
+    L.r3mg_default_options.restype = None
+    L.r3mg_analyze.argtypes = [vp, i64, vp, vp, vp, P(_Options), P(vp)]
+    L.r3mg_factor.argtypes = [vp, vp]
+    L.r3mg_setup.argtypes = [vp, i64, vp, vp, vp, P(_Options), vp, P(vp)]
+    L.r3mg_update_values.argtypes = [vp, vp, vp]
+    L.r3mg_vcycle.argtypes = [vp, vp, vp, i32, vp]
+    L.r3mg_level_apply.argtypes = [vp, i32, vp, vp, vp]
+    L.r3mg_pcg_solve.argtypes = [vp, vp, vp, i32, dbl, i32, vp, vp, vp]
+    L.r3mg_pcg_solve_group.argtypes = [i32, vp, vp, vp, dbl, i32, vp, vp, vp]
+    L.r3mg_info.argtypes = [vp, vp, P(i32)]
+    L.r3mg_export_partition.argtypes = [vp, i32, vp, vp]
+    L.r3mg_export_P.argtypes = [vp, i32, vp, vp, vp, P(i64), P(i64)]
+    L.r3mg_export_level.argtypes = [vp, i32, vp, vp, vp, P(i64), P(i64)]
+    L.r3mg_time_smoother_kernel.argtypes = [vp, i32, i32, vp, P(dbl), P(dbl)]
+    L.r3mg_cell_grad.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp, i64, vp]
+    L.r3mg_assembler_create.argtypes = [vp, vp, i32, i64, P(vp)]
+    L.r3mg_assemble.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.r3mg_assembler_free.argtypes = [vp]
+    L.r3mg_assembler_free.restype = None
+    L.r3mg_rtree.argtypes = [vp, i64, i32, i32, P(i32), vp]
+    L.r3mg_free.argtypes = [vp]
+    L.r3mg_free.restype = None
+    L.r3mg_status_string.argtypes = [i32]
+    L.r3mg_status_string.restype = C.c_char_p
+    L.r3mg_last_error.argtypes = []
+    L.r3mg_last_error.restype = C.c_char_p
+    non_status = ("r3mg_default_options", "r3mg_assembler_free", "r3mg_free", "r3mg_status_string",
+                  "r3mg_last_error")
+    for name in EXPORTED:
+        if name not in non_status:
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(st: int, where: str, allow_not_converged: bool = False) -> int:
+    if st == OK or (allow_not_converged and st == NOT_CONVERGED):
+        return st
+    msg = lib().r3mg_last_error().decode(errors="replace")
+    raise R3mgError(st, where, msg)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dev(t):
+    """Device pointer of a contiguous float64/int32 torch tensor on the GPU."""
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def rtree(coords: np.ndarray, leaf: int):
+    """Host-only bisection R-tree: (depth, order) with order[leaf position] = point index."""
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    n, d = coords.shape
+    depth = C.c_int(0)
+    order = np.empty(n, dtype=np.int32)
+    _check(lib().r3mg_rtree(_ptr(coords), n, d, leaf, C.byref(depth), _ptr(order)), "r3mg_rtree")
+    return depth.value, order
+
+
+class Hierarchy:
+    """Handle of an R3MG-C hierarchy.  analyze() is host-only; factor() builds the device hierarchy."""
+
+    def __init__(self, coords: np.ndarray, row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray,
+                 options: Options, *, factor: bool = True, stream=None):
+        L = lib()
+        self._coords = np.ascontiguousarray(coords, dtype=np.float64)
+        self.n = self._coords.shape[0]
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        vl = np.ascontiguousarray(val, dtype=np.float64)
+        self.nnz = int(rp[-1])
+        self.options = options
+        h = C.c_void_p()
+        o = options._c()
+        _check(L.r3mg_analyze(_ptr(self._coords), self.n, _ptr(rp), _ptr(cl), _ptr(vl), C.byref(o), C.byref(h)),
+               "r3mg_analyze")
+        self._h = h
+        self.factored = False
+        if factor:
+            self.factor(stream)
+
+    def factor(self, stream=None):
+        _check(lib().r3mg_factor(self._h, _stream(stream)), "r3mg_factor")
+        self.factored = True
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().r3mg_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- device operations -------------------------------------------------------------------
+    def update_values(self, vals_dev, stream=None):
+        _check(lib().r3mg_update_values(self._h, _dev(vals_dev), _stream(stream)), "r3mg_update_values")
+
+    def vcycle(self, r, z, stream=None):
+        nrhs = 1 if r.dim() == 1 else r.shape[0]
+        _check(lib().r3mg_vcycle(self._h, _dev(r), _dev(z), nrhs, _stream(stream)), "r3mg_vcycle")
+
+    def level_apply(self, level: int, x, y, stream=None):
+        _check(lib().r3mg_level_apply(self._h, level, _dev(x), _dev(y), _stream(stream)), "r3mg_level_apply")
+
+    def pcg(self, b, x, rtol: float = 1e-10, maxit: int = 500, stream=None, raise_not_converged: bool = False):
+        """Solve A x = b in place (x holds the initial guess); b, x of shape (n,) or (nrhs, n)."""
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        iters = np.zeros(nrhs, dtype=np.int32)
+        relres = np.zeros(nrhs, dtype=np.float64)
+        st = lib().r3mg_pcg_solve(self._h, _dev(b), _dev(x), nrhs, rtol, maxit, _stream(stream), _ptr(iters),
+                                  _ptr(relres))
+        _check(st, "r3mg_pcg_solve", allow_not_converged=not raise_not_converged)
+        return iters, relres, st == OK
+
+    def cell_grad(self, cells_dev, Ke_dev, ke_stride: int, u, lam, g, stream=None):
+        ncells, nloc = cells_dev.shape
+        _check(lib().r3mg_cell_grad(self._h, _dev(cells_dev), nloc, _dev(Ke_dev), ke_stride, _dev(u), _dev(lam),
+                                    _dev(g), ncells, _stream(stream)), "r3mg_cell_grad")
+
+    def time_smoother_kernel(self, level: int, reps: int, stream=None):
+        ms, by = C.c_double(), C.c_double()
+        _check(lib().r3mg_time_smoother_kernel(self._h, level, reps, _stream(stream), C.byref(ms), C.byref(by)),
+               "r3mg_time_smoother_kernel")
+        return ms.value, by.value
+
+    # --- host queries ----------------------------------------------------------------------------
+    def info(self):
+        n = C.c_int(0)
+        _check(lib().r3mg_info(self._h, None, C.byref(n)), "r3mg_info")
+        arr = (_LevelInfo * n.value)()
+        _check(lib().r3mg_info(self._h, arr, C.byref(n)), "r3mg_info")
+        return [{f: getattr(a, f) for f, _ in _LevelInfo._fields_} for a in arr]
+
+    @property
+    def nlevels(self) -> int:
+        n = C.c_int(0)
+        _check(lib().r3mg_info(self._h, None, C.byref(n)), "r3mg_info")
+        return n.value
+
+    def export_partition(self, level: int):
+        nb = self.info()[level]["nboxes"]
+        d = self._coords.shape[1]
+        owner = np.empty(self.n, dtype=np.int32)
+        lohi = np.empty((nb, 2 * d), dtype=np.float64)
+        _check(lib().r3mg_export_partition(self._h, level, _ptr(owner), _ptr(lohi)), "r3mg_export_partition")
+        return owner, lohi[:, :d].copy(), lohi[:, d:].copy()
+
+    def _export_csr(self, fn, level: int, where: str):
+        nr, nz = C.c_int64(), C.c_int64()
+        _check(fn(self._h, level, None, None, None, C.byref(nr), C.byref(nz)), where)
+        rp = np.empty(nr.value + 1, dtype=np.int64)
+        cl = np.empty(nz.value, dtype=np.int32)
+        vl = np.empty(nz.value, dtype=np.float64)
+        _check(fn(self._h, level, _ptr(rp), _ptr(cl), _ptr(vl), C.byref(nr), C.byref(nz)), where)
+        return rp, cl, vl
+
+    def export_P(self, level: int):
+        return self._export_csr(lib().r3mg_export_P, level, "r3mg_export_P")
+
+    def export_level(self, level: int):
+        return self._export_csr(lib().r3mg_export_level, level, "r3mg_export_level")
+
+
+class Assembler:
+    """A(kappa) = sum_e kappa_e K_e on a hierarchy's fine pattern (deterministic gather on the GPU)."""
+
+    def __init__(self, h: Hierarchy, cells: np.ndarray):
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        a = C.c_void_p()
+        _check(lib().r3mg_assembler_create(h._h, _ptr(cells), cells.shape[1], cells.shape[0], C.byref(a)),
+               "r3mg_assembler_create")
+        self._a = a
+        self.h = h
+
+    def assemble(self, kappa, Ke, ke_stride: int, vals, stream=None):
+        _check(lib().r3mg_assemble(self._a, _dev(kappa), _dev(Ke), ke_stride, _dev(vals), _stream(stream)),
+               "r3mg_assemble")
+
+    def __del__(self):
+        try:
+            if self._a:
+                lib().r3mg_assembler_free(self._a)
+                self._a = None
+        except Exception:
+            pass
+
+
+def solve_group(hs: Sequence[Hierarchy], bs, xs, rtol=1e-10, maxit=500, stream=None):
+    """Several independent problems solved by PCG in one hipGraph launch sequence."""
+    k = len(hs)
+    H = (C.c_void_p * k)(*[h._h for h in hs])
+    Bp = (C.c_void_p * k)(*[b.data_ptr() for b in bs])
+    Xp = (C.c_void_p * k)(*[x.data_ptr() for x in xs])
+    iters = np.zeros(k, dtype=np.int32)
+    relres = np.zeros(k, dtype=np.float64)
+    st = lib().r3mg_pcg_solve_group(k, H, Bp, Xp, rtol, maxit, _stream(stream), _ptr(iters), _ptr(relres))
+    _check(st, "r3mg_pcg_solve_group", allow_not_converged=True)
+    return iters, relres, st == OK

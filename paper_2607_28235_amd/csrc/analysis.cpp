@@ -1,0 +1,379 @@
+// Host analysis of R3MG-C: constrained set, bisection R-tree, level selection, DoF permutation, transfer
+// tables, unisolvence check and Galerkin block sparsity.  Pure C++ (no HIP calls).
+//
+// Paper: Section 3 (Definition of an R-tree of order (m,M)), Section 4 (point-based agglomeration, transfer
+// construction, Remarks on parameters and heuristics), Section 6 (level choice).  Readings where the paper is
+// silent (the Boost R*-tree is replaced by a deterministic bisection bulk load):
+//   depth t = smallest t with 2^t * leaf >= n; a split orders its points lexicographically by
+//   (x_{a*}, x_{a*+1 mod d}, ..., point index) with a* the first axis of largest extent and keeps the first
+//   ceil(|S|/2) points on the left; level l+1 sits d tree levels above level l; coarsening stops at the first
+//   level with at most max_coarse_dofs DoFs, at max_levels, or at the root.
+// All floating-point decisions (extents, comparisons, unisolvence pivots) are taken in float64; this file is
+// compiled without floating-point contraction so that the transfer values are reproducible.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "r3mg_internal.h"
+
+namespace r3mg {
+
+namespace {
+
+template <typename F>
+void parallel_for(int64_t count, F&& f) {
+  unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (count < 64 || hw == 1) {
+    for (int64_t i = 0; i < count; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < hw; ++t)
+    th.emplace_back([&] {
+      for (;;) {
+        int64_t i = next.fetch_add(1);
+        if (i >= count) break;
+        f(i);
+      }
+    });
+  for (auto& t : th) t.join();
+}
+
+int tree_depth(int64_t n, int64_t leaf) {
+  int t = 0;
+  while ((leaf << t) < n) ++t;
+  return t;
+}
+
+Error err(r3mg_status c, const std::string& m) { return Error{c, m}; }
+
+// l_j(s) = prod_{m != j} (s - t_m) / (t_j - t_m), evaluated in the order m = 0, 1, ...
+inline double lagrange(const double* t, int k, int j, double s) {
+  double v = 1.0;
+  for (int m = 0; m < k; ++m)
+    if (m != j) v *= (s - t[m]) / (t[j] - t[m]);
+  return v;
+}
+
+}  // namespace
+
+void box_nodes_1d(int pc, double* t) {
+  switch (pc) {
+    case 0: t[0] = 0.5; break;
+    case 1: t[0] = 0.0; t[1] = 1.0; break;
+    case 2: t[0] = 0.0; t[1] = 0.5; t[2] = 1.0; break;
+    default: {
+      double s = 1.0 / std::sqrt(5.0);
+      t[0] = 0.0; t[1] = 0.5 * (1.0 - s); t[2] = 0.5 * (1.0 + s); t[3] = 1.0;
+    }
+  }
+}
+
+void bisection_rtree(const double* x, int64_t n, int d, int leaf, int& depth, std::vector<int32_t>& order,
+                     std::vector<std::vector<int64_t>>& offsets) {
+  depth = tree_depth(n, leaf);
+  order.resize(n);
+  std::iota(order.begin(), order.end(), 0);
+  offsets.assign(depth + 1, {});
+  offsets[0] = {0, n};
+  for (int k = 0; k < depth; ++k) {
+    const std::vector<int64_t>& off = offsets[k];
+    int64_t nseg = (int64_t)off.size() - 1;
+    parallel_for(nseg, [&](int64_t s) {
+      int64_t a = off[s], b = off[s + 1];
+      if (b - a < 2) return;
+      double mn[3], mx[3];
+      for (int c = 0; c < d; ++c) { mn[c] = INFINITY; mx[c] = -INFINITY; }
+      for (int64_t i = a; i < b; ++i) {
+        const double* p = x + (int64_t)order[i] * d;
+        for (int c = 0; c < d; ++c) { mn[c] = std::min(mn[c], p[c]); mx[c] = std::max(mx[c], p[c]); }
+      }
+      int astar = 0;
+      double best = mx[0] - mn[0];
+      for (int c = 1; c < d; ++c)
+        if (mx[c] - mn[c] > best) { best = mx[c] - mn[c]; astar = c; }
+      std::sort(order.begin() + a, order.begin() + b, [&](int32_t i, int32_t j) {
+        const double* pi = x + (int64_t)i * d;
+        const double* pj = x + (int64_t)j * d;
+        for (int m = 0; m < d; ++m) {
+          int c = (astar + m) % d;
+          if (pi[c] < pj[c]) return true;
+          if (pj[c] < pi[c]) return false;
+        }
+        return i < j;
+      });
+    });
+    std::vector<int64_t> nxt(2 * nseg + 1);
+    nxt[0] = 0;
+    for (int64_t s = 0; s < nseg; ++s) {
+      int64_t len = off[s + 1] - off[s];
+      nxt[2 * s + 1] = off[s] + (len + 1) / 2;
+      nxt[2 * s + 2] = off[s + 1];
+    }
+    offsets[k + 1] = std::move(nxt);
+  }
+}
+
+std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t* row_ptr,
+                                  const int32_t* col_idx, const double* vals, const r3mg_options& opt) {
+  auto an = std::make_unique<Analysis>();
+  an->opt = opt;
+  const int d = opt.dim;
+  const int pc = opt.coarse_degree;
+  if (d != 2 && d != 3) throw err(R3MG_ERR_INVALID, "dim must be 2 or 3");
+  if (pc < 0 || pc > 3) throw err(R3MG_ERR_INVALID, "coarse_degree must be in 0..3");
+  if (opt.leaf_size < 1 || opt.max_levels < 0 || opt.max_levels == 1 || opt.max_coarse_dofs < 1 ||
+      opt.cheb_degree < 1 || opt.pre_steps < 0 || opt.post_steps < 0 || opt.lanczos_steps < 1 ||
+      !(opt.cheb_boost > 0.0) || !(opt.cheb_ratio > 1.0))
+    throw err(R3MG_ERR_INVALID, "invalid option value");
+  if (n < 1 || n >= (int64_t(1) << 31)) throw err(R3MG_ERR_INVALID, "n out of range");
+  if (!coords || !row_ptr || !col_idx || !vals) throw err(R3MG_ERR_INVALID, "null input");
+  int B = 1;
+  for (int a = 0; a < d; ++a) B *= (pc + 1);
+  an->d = d;
+  an->pc = pc;
+  an->B = B;
+  an->n = n;
+  if (row_ptr[0] != 0) throw err(R3MG_ERR_INVALID, "row_ptr[0] != 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) throw err(R3MG_ERR_INVALID, "row_ptr not monotone");
+  const int64_t nnz = row_ptr[n];
+  if (nnz >= (int64_t(1) << 31)) throw err(R3MG_ERR_OOM, "nnz exceeds int32 range");
+  an->nnz = nnz;
+  for (int64_t i = 0; i < n * d; ++i)
+    if (!std::isfinite(coords[i])) throw err(R3MG_ERR_INVALID, "non-finite coordinate");
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      if (col_idx[p] < 0 || col_idx[p] >= n) throw err(R3MG_ERR_INVALID, "column index out of range");
+      if (p > row_ptr[i] && col_idx[p] <= col_idx[p - 1])
+        throw err(R3MG_ERR_INVALID, "columns must be strictly ascending within a row");
+      if (!std::isfinite(vals[p])) throw err(R3MG_ERR_INVALID, "non-finite matrix value");
+    }
+  an->user_rowptr.assign(row_ptr, row_ptr + n + 1);
+  an->user_col.assign(col_idx, col_idx + nnz);
+
+  // O1: constrained rows (all stored off-diagonal values exactly zero)
+  std::vector<uint8_t>& cons_user = an->constrained_user;
+  cons_user.assign(n, 1);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+      if (col_idx[p] != i && vals[p] != 0.0) { cons_user[i] = 0; break; }
+
+  // R-tree and levels
+  std::vector<std::vector<int64_t>> offsets;
+  bisection_rtree(coords, n, d, opt.leaf_size, an->depth, an->order, offsets);
+  {
+    int depth = opt.skip_leaf_level ? std::max(an->depth - d, 0) : an->depth;
+    an->depths.push_back(depth);
+    for (;;) {
+      int nlev = (int)an->depths.size() + 1;
+      int64_t nboxes = int64_t(1) << an->depths.back();
+      if (nboxes * B <= opt.max_coarse_dofs) break;
+      if (opt.max_levels && nlev >= opt.max_levels) break;
+      if (an->depths.back() == 0) break;
+      an->depths.push_back(std::max(an->depths.back() - d, 0));
+    }
+  }
+  for (auto& off : offsets)
+    for (size_t s = 0; s + 1 < off.size(); ++s)
+      if (off[s + 1] == off[s]) throw err(R3MG_ERR_NOT_UNISOLVENT, "empty R-tree node (leaf_size too small)");
+  const int L = an->nlevels() - 1;
+  an->lv.resize(L + 1);
+  an->iperm.assign(n, 0);
+  for (int64_t p = 0; p < n; ++p) an->iperm[an->order[p]] = (int32_t)p;
+  an->coords_int.resize(n * d);
+  for (int64_t p = 0; p < n; ++p)
+    for (int a = 0; a < d; ++a) an->coords_int[p * d + a] = coords[(int64_t)an->order[p] * d + a];
+
+  // boxes per level
+  for (int l = 1; l <= L; ++l) {
+    HostLevel& H = an->lv[l];
+    H.depth = an->depths[l - 1];
+    const std::vector<int64_t>& off = offsets[H.depth];
+    H.nbox = (int64_t)off.size() - 1;
+    H.n = H.nbox * B;
+    H.lo.assign(H.nbox * d, INFINITY);
+    H.hi.assign(H.nbox * d, -INFINITY);
+    for (int64_t k = 0; k < H.nbox; ++k) {
+      for (int64_t p = off[k]; p < off[k + 1]; ++p)
+        for (int a = 0; a < d; ++a) {
+          double v = an->coords_int[p * d + a];
+          H.lo[k * d + a] = std::min(H.lo[k * d + a], v);
+          H.hi[k * d + a] = std::max(H.hi[k * d + a], v);
+        }
+      double e2 = 0;
+      for (int a = 0; a < d; ++a) e2 += (H.hi[k * d + a] - H.lo[k * d + a]) * (H.hi[k * d + a] - H.lo[k * d + a]);
+      H.max_extent = std::max(H.max_extent, std::sqrt(e2));
+    }
+    if (l >= 2) H.child_shift = an->depths[l - 2] - an->depths[l - 1];
+  }
+  auto check_degenerate = [&](int l) {
+    if (pc < 1) return;
+    const HostLevel& H = an->lv[l];
+    for (int64_t k = 0; k < H.nbox * d; ++k)
+      if (!(H.hi[k] > H.lo[k])) throw err(R3MG_ERR_DEGENERATE_BOX, "box with zero extent on level " + std::to_string(l));
+  };
+  check_degenerate(1);
+
+  // level-1 ownership, local coordinates, unisolvence
+  an->leaf_off = offsets[an->depths[0]];
+  an->constrained.resize(n);
+  an->owner.resize(n);
+  an->xi.assign(n * d, 0.0);
+  double t[4];
+  box_nodes_1d(pc, t);
+  const HostLevel& H1 = an->lv[1];
+  for (int64_t k = 0; k < H1.nbox; ++k)
+    for (int64_t p = an->leaf_off[k]; p < an->leaf_off[k + 1]; ++p) {
+      an->constrained[p] = cons_user[an->order[p]];
+      an->owner[p] = an->constrained[p] ? -1 : (int32_t)k;
+      if (pc >= 1)
+        for (int a = 0; a < d; ++a)
+          an->xi[p * d + a] = (an->coords_int[p * d + a] - H1.lo[k * d + a]) / (H1.hi[k * d + a] - H1.lo[k * d + a]);
+    }
+  {
+    std::atomic<int64_t> bad{-1};
+    std::atomic<int> bad_kind{0};
+    const int k1 = pc + 1;
+    parallel_for(H1.nbox, [&](int64_t k) {
+      std::vector<double> G(B * B, 0.0), L(B * B, 0.0), phi(B);
+      int64_t cnt = 0;
+      for (int64_t p = an->leaf_off[k]; p < an->leaf_off[k + 1]; ++p) {
+        if (an->constrained[p]) continue;
+        ++cnt;
+        double l1[3][4];
+        for (int a = 0; a < d; ++a)
+          for (int j = 0; j < k1; ++j) l1[a][j] = (pc == 0) ? 1.0 : lagrange(t, k1, j, an->xi[p * d + a]);
+        for (int q = 0; q < B; ++q) {
+          double v = 1.0;
+          int qq = q;
+          for (int a = 0; a < d; ++a) { v *= l1[a][qq % k1]; qq /= k1; }
+          phi[q] = v;
+        }
+        for (int i = 0; i < B; ++i)
+          for (int j = 0; j < B; ++j) G[i * B + j] += phi[i] * phi[j];
+      }
+      if (cnt < B) {
+        int64_t expect = -1;
+        bad.compare_exchange_strong(expect, k);
+        bad_kind = 1;
+        return;
+      }
+      double dmax = 0;
+      for (int i = 0; i < B; ++i) dmax = std::max(dmax, G[i * B + i]);
+      double tol = 1e-12 * dmax;
+      for (int j = 0; j < B; ++j) {
+        double piv = G[j * B + j];
+        for (int c = 0; c < j; ++c) piv -= L[j * B + c] * L[j * B + c];
+        if (!(piv > tol)) {
+          int64_t expect = -1;
+          bad.compare_exchange_strong(expect, k);
+          return;
+        }
+        L[j * B + j] = std::sqrt(piv);
+        for (int i = j + 1; i < B; ++i) {
+          double s = G[i * B + j];
+          for (int c = 0; c < j; ++c) s -= L[i * B + c] * L[j * B + c];
+          L[i * B + j] = s / L[j * B + j];
+        }
+      }
+    });
+    if (bad >= 0) throw err(R3MG_ERR_NOT_UNISOLVENT, "box " + std::to_string((long long)bad.load()) +
+                                                    " cannot interpolate Q^p' from its owned points");
+  }
+  for (int l = 2; l <= L; ++l) check_degenerate(l);
+
+  // fine operator in the internal numbering
+  an->rowptr.resize(n + 1);
+  an->col.resize(nnz);
+  an->val.resize(nnz);
+  an->src.resize(nnz);
+  an->rowptr[0] = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    int64_t u = an->order[p];
+    an->rowptr[p + 1] = an->rowptr[p] + (int32_t)(row_ptr[u + 1] - row_ptr[u]);
+  }
+  parallel_for(n, [&](int64_t p) {
+    int64_t u = an->order[p];
+    int64_t base = an->rowptr[p];
+    int64_t len = row_ptr[u + 1] - row_ptr[u];
+    std::vector<std::pair<int32_t, int64_t>> e(len);
+    for (int64_t q = 0; q < len; ++q) e[q] = {an->iperm[col_idx[row_ptr[u] + q]], row_ptr[u] + q};
+    std::sort(e.begin(), e.end());
+    for (int64_t q = 0; q < len; ++q) {
+      an->col[base + q] = e[q].first;
+      an->src[base + q] = e[q].second;
+      an->val[base + q] = vals[e[q].second];
+    }
+  });
+
+  // Galerkin block sparsity, level 1: boxes linked by a stored entry between unconstrained points
+  {
+    HostLevel& H = an->lv[1];
+    std::vector<std::vector<int32_t>> rows(H.nbox);
+    parallel_for(H.nbox, [&](int64_t k) {
+      std::vector<int32_t>& r = rows[k];
+      for (int64_t p = an->leaf_off[k]; p < an->leaf_off[k + 1]; ++p) {
+        if (an->constrained[p]) continue;
+        for (int32_t q = an->rowptr[p]; q < an->rowptr[p + 1]; ++q) {
+          int32_t c = an->col[q];
+          if (an->constrained[c]) continue;
+          r.push_back(an->owner[c]);
+        }
+      }
+      std::sort(r.begin(), r.end());
+      r.erase(std::unique(r.begin(), r.end()), r.end());
+    });
+    H.bptr.assign(H.nbox + 1, 0);
+    for (int64_t k = 0; k < H.nbox; ++k) H.bptr[k + 1] = H.bptr[k] + (int64_t)rows[k].size();
+    H.bcol.resize(H.bptr[H.nbox]);
+    for (int64_t k = 0; k < H.nbox; ++k) std::copy(rows[k].begin(), rows[k].end(), H.bcol.begin() + H.bptr[k]);
+  }
+  for (int l = 2; l <= L; ++l) {
+    HostLevel& P = an->lv[l - 1];
+    HostLevel& H = an->lv[l];
+    const int s = H.child_shift;
+    std::vector<std::vector<int32_t>> rows(H.nbox);
+    for (int64_t c = 0; c < P.nbox; ++c) {
+      int64_t g = c >> s;
+      for (int64_t q = P.bptr[c]; q < P.bptr[c + 1]; ++q) rows[g].push_back(P.bcol[q] >> s);
+    }
+    H.bptr.assign(H.nbox + 1, 0);
+    for (int64_t g = 0; g < H.nbox; ++g) {
+      std::sort(rows[g].begin(), rows[g].end());
+      rows[g].erase(std::unique(rows[g].begin(), rows[g].end()), rows[g].end());
+      H.bptr[g + 1] = H.bptr[g] + (int64_t)rows[g].size();
+    }
+    H.bcol.resize(H.bptr[H.nbox]);
+    for (int64_t g = 0; g < H.nbox; ++g) std::copy(rows[g].begin(), rows[g].end(), H.bcol.begin() + H.bptr[g]);
+  }
+  for (int l = 1; l <= L; ++l)
+    if (an->lv[l].bptr[an->lv[l].nbox] * (int64_t)B * B >= (int64_t(1) << 31) * 8)
+      throw err(R3MG_ERR_OOM, "coarse operator too large");
+
+  // injections between agglomerated levels: 1D factors M[a][child node i][parent node j]
+  const int k1 = pc + 1;
+  for (int l = 1; l < L; ++l) {
+    HostLevel& C = an->lv[l];
+    const HostLevel& G = an->lv[l + 1];
+    const int s = G.child_shift;
+    C.pt1d.assign(C.nbox * d * k1 * k1, 0.0);
+    for (int64_t c = 0; c < C.nbox; ++c) {
+      int64_t g = c >> s;
+      for (int a = 0; a < d; ++a)
+        for (int i = 0; i < k1; ++i) {
+          double y = C.lo[c * d + a] + t[i] * (C.hi[c * d + a] - C.lo[c * d + a]);
+          double xi = (pc == 0) ? 0.0 : (y - G.lo[g * d + a]) / (G.hi[g * d + a] - G.lo[g * d + a]);
+          for (int j = 0; j < k1; ++j)
+            C.pt1d[((c * d + a) * k1 + i) * k1 + j] = (pc == 0) ? 1.0 : lagrange(t, k1, j, xi);
+        }
+    }
+  }
+  return an;
+}
+
+}  // namespace r3mg

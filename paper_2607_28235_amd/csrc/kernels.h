@@ -1,0 +1,134 @@
+// Launch wrappers of the R3MG-C HIP kernels (gfx950).  All launches are asynchronous on `s`.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace r3mg {
+
+// flags of the fused level kernel (SpMV + Chebyshev/Jacobi update)
+enum : int {
+  F_PLAIN = 1,        // y = A u only (written to `rho`)
+  F_RHO_FROM_B = 2,   // rho_old := b (x was zero)
+  F_RHO_STORE = 4,    // store rho_new = rho_old - A u
+  F_X_ASSIGN = 8,     // x := u
+  F_X_ADD = 16,       // x += u
+  F_D_OUT = 32,       // dout := c1 u + c2 dinv rho_new
+};
+
+constexpr int kMaxNR = 16;
+
+struct PcgState {
+  int all_done, nr, flexible, pad;
+  int iters[kMaxNR];
+  int done[kMaxNR];
+  double gamma[kMaxNR], alpha[kMaxNR], beta[kMaxNR], rr[kMaxNR], rr0[kMaxNR], tau2[kMaxNR];
+};
+
+// Level operator description for the fused kernel.
+template <typename T>
+struct LevelOp {
+  int n = 0;          // rows
+  int blk = 1;        // 1: CSR (ptr = row pointer, idx = columns); > 1: block rows (ptr = bptr, idx = bcol)
+  const int* ptr = nullptr;
+  const int* idx = nullptr;
+  const T* val = nullptr;
+  const T* dinv = nullptr;
+  int lanes = 8;      // lanes per row (power of two, <= 64)
+};
+
+template <typename T>
+void launch_level(const LevelOp<T>& op, int nr, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
+                  double c2, int flags, const int* skip, hipStream_t s);
+
+// q = A p (float64, CSR), per-block partial <p, q> -> partials[blk * nr + k]; returns number of blocks
+int launch_spmv_dot(const LevelOp<double>& op, int nr, const double* p, double* q, double* partials,
+                    const int* skip, hipStream_t s);
+
+// transfers
+template <typename T>
+void launch_restrict0(int nbox, int d, int pc, int nr, const int* leaf_off, const int* owner, const T* xi,
+                      const T* src, T* bnext, const T* dinv_next, T* dnext, double inv_theta_next,
+                      const int* skip, hipStream_t s);
+template <typename T>
+void launch_prolong0(int n, int d, int pc, int nr, const int* owner, const T* xi, const T* e, const T* epend,
+                     T* v, const int* skip, hipStream_t s);
+template <typename T>
+void launch_restrict_c(int nbox_next, int nbox, int shift, int d, int pc, int nr, const T* pt, const T* src,
+                       T* bnext, const T* dinv_next, T* dnext, double inv_theta_next, const int* skip,
+                       hipStream_t s);
+template <typename T>
+void launch_prolong_c(int nbox, int shift, int d, int pc, int nr, const T* pt, const T* e, const T* epend, T* v,
+                      const int* skip, hipStream_t s);
+
+// elementwise helpers
+template <typename T>
+void launch_xupdate(int64_t count, T* x, const T* v, int assign, const int* skip, hipStream_t s);
+template <typename T>
+void launch_vc_entry(int n, int nr, const int* perm, const double* r_user, int64_t ld_user, T* b0,
+                     const T* dinv, T* d0, double inv_theta, hipStream_t s);
+template <typename T>
+void launch_vc_exit(int n, int nr, const int* perm, const T* x0, const T* dpend, double* z_user, int64_t ld_user,
+                    hipStream_t s);
+template <typename T>
+void launch_dense_apply(int nc, int nr, const double* cinv, const T* b, T* x, const int* skip, hipStream_t s);
+void launch_gather_cols(int n, int nr, int nuser, const int* perm, const double* user, int64_t ld_user,
+                        double* out, hipStream_t s);
+void launch_scatter_cols(int n, int nr, int nuser, const int* perm, const double* in, double* user,
+                         int64_t ld_user, hipStream_t s);
+void launch_cast_d2f(int64_t count, const double* a, float* b, hipStream_t s);
+void launch_gather_vals(int64_t nnz, const int64_t* src, const double* user_vals, double* out, hipStream_t s);
+
+// set-up kernels
+void launch_diag_inv(int n, int blk, const int* ptr, const int* idx, const double* val, double* dinv, double* diag,
+                     int* bad, hipStream_t s);
+void launch_galerkin0(int64_t nblocks, int d, int pc, const int* brow, const int* bptr, const int* bcol,
+                      const int* leaf_off, const int* owner, const double* xi, const int* rowptr, const int* col,
+                      const double* val, double* out, hipStream_t s);
+void launch_galerkin_c(int64_t nblocks, int d, int pc, int shift, int nbox_in, const int* brow, const int* bptr_out,
+                       const int* bcol_out, const int* bptr_in, const int* bcol_in, const double* val_in,
+                       const double* pt, double* out, hipStream_t s);
+void launch_to_dense(int nbox, int B, const int* bptr, const int* bcol, const double* val, double* dense,
+                     hipStream_t s);
+void launch_lanczos_start(int n, const int* perm, double* v, hipStream_t s);
+// partial sums of w_i x_i y_i (w may be null) -> partials (returns count)
+int launch_dot(int64_t n, const double* w, const double* x, const double* y, double* partials, hipStream_t s);
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);   // y = a x + b y
+void launch_lanczos_u(int64_t n, const double* dinv, const double* Av, double beta_prev, const double* vprev,
+                      double* u, hipStream_t s);  // u = dinv*Av - beta_prev*vprev
+
+// dense Cholesky (lower, in place, row-major n x n) and inverse; *bad set on a non-positive pivot
+void dense_cholesky_inverse(int n, double* A, double* Inv, int* bad, hipStream_t s);
+
+// PCG (float64)
+template <typename T>
+void launch_pcg_xr(int n, int nr, PcgState* st, const double* partials_pq, int npart, double* x, double* r,
+                   const double* p, const double* q, double* partials_rr, T* b0, const T* dinv0, T* d0,
+                   double inv_theta0, hipStream_t s);
+void launch_pcg_alpha(int nr, PcgState* st, const double* partials, int npart, hipStream_t s);
+void launch_pcg_check(int nr, PcgState* st, const double* partials, int npart, hipStream_t s);
+template <typename T>
+void launch_pcg_z(int n, int nr, PcgState* st, const T* x0, const T* dpend, double* z, const double* r,
+                  const double* q, double* partials, hipStream_t s);
+void launch_pcg_beta(int nr, PcgState* st, const double* partials, int npart, hipStream_t s);
+void launch_pcg_p(int n, int nr, PcgState* st, const double* z, double* p, hipStream_t s);
+// init: r = b - q; partial rr
+int launch_residual(int n, int nr, const double* b, const double* q, double* r, double* partials, hipStream_t s);
+void launch_pcg_init(int nr, PcgState* st, const double* partials, int npart, double rtol, int flexible,
+                     hipStream_t s);
+void launch_pcg_init_gamma(int n, int nr, PcgState* st, const double* partials, int npart, const double* z,
+                           double* p, hipStream_t s);
+template <typename T>
+void launch_vc_prep(int n, int nr, const double* r, T* b0, const T* dinv0, T* d0, double inv_theta0,
+                    const int* skip, hipStream_t s);
+
+// FEM helpers (adjoint gradient, kappa assembly)
+void launch_cell_grad(int64_t ncells, int nloc, const int* cells, const double* Ke, int64_t ke_stride,
+                      const double* u, const double* lam, const unsigned char* constrained_user, double* g,
+                      hipStream_t s);
+void launch_assemble(int64_t nnz, const int64_t* slot_ptr, const int64_t* contrib, const double* kappa,
+                     const double* Ke, int64_t ke_stride, int nloc, const unsigned char* diag_one, double* vals,
+                     hipStream_t s);
+
+}  // namespace r3mg

@@ -1,0 +1,1495 @@
+// HIP kernels of the R3MG-C hot path for gfx950 (CDNA4, wave64).
+//
+// Level operators (paper Section 4: inherited operators A_i = P_i^T A P_i) are applied by one fused kernel
+// that also performs the Chebyshev-accelerated Jacobi update of the smoother (Section 5 Remark on the
+// smoother, Section 6): t = A u; rho -= t; x += u; d = c1 u + c2 D^{-1} rho.  The fine level is CSR; the
+// agglomerated levels store dense B x B blocks (B = (p'+1)^d) with one column index per block, laid out so
+// that every row's values are contiguous ("block rows": row (K,q) holds blocks j = 0..nb-1, columns c).
+// Transfers (Section 4 construction of P_{M-1} and P~) evaluate the box basis on the fly from per-point
+// local coordinates; they never store P.
+//
+// All reductions are deterministic: fixed per-thread order, fixed shuffle trees, fixed LDS trees, and
+// per-block partials summed in index order by a single block.  No floating-point atomics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+#include "kernels.h"
+
+namespace r3mg {
+
+namespace {
+
+constexpr int kXcd = 8;  // MI355X: 8 accelerator complex dies, workgroups dispatched round-robin
+
+// Logical block index with XCD-contiguous chunks: consecutive logical blocks (adjacent rows, spatially close
+// in the R-tree order) run on the same XCD and share its L2.  The grid must be kXcd * ceil(nlog / kXcd).
+__device__ inline int xcd_block(int nlog) {
+  int per = (nlog + kXcd - 1) / kXcd;
+  int lb = (int)(blockIdx.x % kXcd) * per + (int)(blockIdx.x / kXcd);
+  return lb < nlog ? lb : -1;
+}
+inline int xcd_grid(int nlog) { return kXcd * ((nlog + kXcd - 1) / kXcd); }
+
+template <typename T>
+struct Basis1D {
+  T t[4];
+  T w[4];
+  int k;
+};
+
+template <typename T>
+Basis1D<T> make_basis(int pc) {
+  double t[4] = {0, 0, 0, 0};
+  switch (pc) {
+    case 0: t[0] = 0.5; break;
+    case 1: t[0] = 0.0; t[1] = 1.0; break;
+    case 2: t[0] = 0.0; t[1] = 0.5; t[2] = 1.0; break;
+    default: {
+      double s = 1.0 / std::sqrt(5.0);
+      t[0] = 0.0; t[1] = 0.5 * (1.0 - s); t[2] = 0.5 * (1.0 + s); t[3] = 1.0;
+    }
+  }
+  Basis1D<T> b;
+  b.k = pc + 1;
+  for (int j = 0; j < 4; ++j) {
+    double w = 1.0;
+    for (int m = 0; m < b.k; ++m)
+      if (m != j && j < b.k) w /= (t[j] - t[m]);
+    b.t[j] = (T)t[j];
+    b.w[j] = (T)w;
+  }
+  return b;
+}
+
+// l_j(s) = w_j prod_{m != j} (s - t_m)
+template <typename T>
+__device__ inline void lag1d(const Basis1D<T>& bs, T s, T* l) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j < bs.k) {
+      T v = bs.w[j];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        if (m < bs.k && m != j) v *= (s - bs.t[m]);
+      l[j] = v;
+    }
+  }
+}
+
+// phi_q of multi-index q = q0 + k q1 + k^2 q2 from 1D tables l[a][.]
+template <typename T>
+__device__ inline T phi_q(const T (*l)[4], int d, int k, int q) {
+  T v = l[0][q % k];
+  q /= k;
+  v *= l[1][q % k];
+  if (d == 3) {
+    q /= k;
+    v *= l[2][q % k];
+  }
+  return v;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v, int width) {
+  for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// deterministic block sum (blockDim.x = 256): returns the total in thread 0
+__device__ inline double block_sum256(double v, double* sh) {
+  v = wave_sum(v, 64);
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+// =============================================================================================
+// Fused level kernel: t = A u (CSR or block rows), then the smoother update epilogue.
+// G lanes per row (power of two), 256 threads per block, NR right-hand sides interleaved.
+// =============================================================================================
+template <typename T, int NR, bool BLOCKED>
+__device__ inline void row_product(int row, int lane, int G, int blk, const int* __restrict__ ptr,
+                                   const int* __restrict__ idx, const T* __restrict__ val,
+                                   const T* __restrict__ u, T* acc) {
+  if (!BLOCKED) {
+    const int s = ptr[row], e = ptr[row + 1];
+    for (int p = s + lane; p < e; p += G) {
+      const T a = val[p];
+      const int64_t c = (int64_t)idx[p] * NR;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] += a * u[c + k];
+    }
+  } else {
+    const int K = row / blk;
+    const int q = row - K * blk;
+    const int j0 = ptr[K];
+    const int nb = ptr[K + 1] - j0;
+    const int64_t vbase = (int64_t)blk * blk * j0 + (int64_t)q * nb * blk;
+    const int len = nb * blk;
+    int j = lane / blk, c = lane - j * blk;
+    const int sj = G / blk, sc = G - sj * blk;
+    for (int p = lane; p < len; p += G) {
+      const int64_t cc = ((int64_t)idx[j0 + j] * blk + c) * NR;
+      const T a = val[vbase + p];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] += a * u[cc + k];
+      j += sj;
+      c += sc;
+      if (c >= blk) { c -= blk; ++j; }
+    }
+  }
+}
+
+template <typename T, int NR, bool BLOCKED>
+__global__ __launch_bounds__(256) void k_level(int n, int G, int blk, const int* __restrict__ ptr,
+                                               const int* __restrict__ idx, const T* __restrict__ val,
+                                               const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
+                                               const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
+                                               const int* __restrict__ skip, int nlog) {
+  if (skip && *skip) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int rpb = 256 / G;
+  const int lane = threadIdx.x & (G - 1);
+  const int row = lb * rpb + threadIdx.x / G;
+  const bool active = row < n;
+  T acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0;
+  if (active) row_product<T, NR, BLOCKED>(row, lane, G, blk, ptr, idx, val, u, acc);
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = wave_sum(acc[k], G);
+  if (!active) return;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if ((k & (G - 1)) != lane) continue;
+    const int64_t i = (int64_t)row * NR + k;
+    const T t = acc[k];
+    if (flags & F_PLAIN) {
+      rho[i] = t;
+      continue;
+    }
+    const T r = ((flags & F_RHO_FROM_B) ? b[i] : rho[i]) - t;
+    if (flags & F_RHO_STORE) rho[i] = r;
+    const T ui = u[i];
+    if (flags & F_X_ASSIGN)
+      x[i] = ui;
+    else if (flags & F_X_ADD)
+      x[i] += ui;
+    if (flags & F_D_OUT) dout[i] = c1 * ui + c2 * dinv[row] * r;
+  }
+}
+
+template <typename T, int NR>
+static void launch_level_nr(const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
+                            double c2, int flags, const int* skip, hipStream_t s) {
+  const int G = op.lanes;
+  const int rpb = 256 / G;
+  const int nlog = (op.n + rpb - 1) / rpb;
+  if (nlog == 0) return;
+  if (op.blk == 1)
+    hipLaunchKernelGGL((k_level<T, NR, false>), dim3(xcd_grid(nlog)), dim3(256), 0, s, op.n, G, 1, op.ptr, op.idx,
+                       op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
+  else
+    hipLaunchKernelGGL((k_level<T, NR, true>), dim3(xcd_grid(nlog)), dim3(256), 0, s, op.n, G, op.blk, op.ptr,
+                       op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
+  check_launch("k_level");
+}
+
+template <typename T>
+void launch_level(const LevelOp<T>& op, int nr, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
+                  double c2, int flags, const int* skip, hipStream_t s) {
+  switch (nr) {
+    case 1: launch_level_nr<T, 1>(op, u, b, rho, x, dout, c1, c2, flags, skip, s); break;
+    case 2: launch_level_nr<T, 2>(op, u, b, rho, x, dout, c1, c2, flags, skip, s); break;
+    case 4: launch_level_nr<T, 4>(op, u, b, rho, x, dout, c1, c2, flags, skip, s); break;
+    case 8: launch_level_nr<T, 8>(op, u, b, rho, x, dout, c1, c2, flags, skip, s); break;
+    case 16: launch_level_nr<T, 16>(op, u, b, rho, x, dout, c1, c2, flags, skip, s); break;
+    default: throw std::runtime_error("unsupported nrhs block");
+  }
+}
+template void launch_level<float>(const LevelOp<float>&, int, const float*, const float*, float*, float*, float*,
+                                  double, double, int, const int*, hipStream_t);
+template void launch_level<double>(const LevelOp<double>&, int, const double*, const double*, double*, double*,
+                                   double*, double, double, int, const int*, hipStream_t);
+
+// q = A p with per-block partial sums of p.q (float64 CSR)
+template <int NR>
+__global__ __launch_bounds__(256) void k_spmv_dot(int n, int G, const int* __restrict__ ptr,
+                                                  const int* __restrict__ idx, const double* __restrict__ val,
+                                                  const double* __restrict__ p, double* q, double* partials,
+                                                  const int* __restrict__ skip, int nlog) {
+  if (skip && *skip) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  __shared__ double sh[4 * NR];
+  const int rpb = 256 / G;
+  const int lane = threadIdx.x & (G - 1);
+  const int row = lb * rpb + threadIdx.x / G;
+  const bool active = row < n;
+  double acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0;
+  if (active) row_product<double, NR, false>(row, lane, G, 1, ptr, idx, val, p, acc);
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = wave_sum(acc[k], G);
+  double contrib[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    contrib[k] = 0;
+    if (active && lane == 0) {
+      const int64_t i = (int64_t)row * NR + k;
+      q[i] = acc[k];
+      contrib[k] = acc[k] * p[i];
+    }
+  }
+  // block reduction (fixed order)
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    double v = wave_sum(contrib[k], 64);
+    if ((threadIdx.x & 63) == 0) sh[(threadIdx.x >> 6) * NR + k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NR) {
+    const int k = threadIdx.x;
+    partials[(int64_t)lb * NR + k] = (sh[k] + sh[NR + k]) + (sh[2 * NR + k] + sh[3 * NR + k]);
+  }
+}
+
+int launch_spmv_dot(const LevelOp<double>& op, int nr, const double* p, double* q, double* partials,
+                    const int* skip, hipStream_t s) {
+  const int G = op.lanes;
+  const int rpb = 256 / G;
+  const int nlog = (op.n + rpb - 1) / rpb;
+  dim3 grid(xcd_grid(nlog));
+#define R3_SD(NRV) \
+  hipLaunchKernelGGL((k_spmv_dot<NRV>), grid, dim3(256), 0, s, op.n, G, op.ptr, op.idx, op.val, p, q, partials, skip, nlog)
+  switch (nr) {
+    case 1: R3_SD(1); break;
+    case 2: R3_SD(2); break;
+    case 4: R3_SD(4); break;
+    case 8: R3_SD(8); break;
+    case 16: R3_SD(16); break;
+    default: throw std::runtime_error("unsupported nrhs block");
+  }
+#undef R3_SD
+  check_launch("k_spmv_dot");
+  return nlog;
+}
+
+// =============================================================================================
+// Transfers
+// =============================================================================================
+// Restriction to the first agglomerated level: b1[K*B+q] = sum_{i in K, i free} phi^K_q(xi_i) src_i.
+// One 64-thread workgroup per box; chunks of 64 points are staged through LDS ([q][lane]) and summed by
+// thread q in lane order (deterministic).  Optionally fuses the first Chebyshev direction of the next level:
+// dnext = dinv_next * b1 * inv_theta_next.
+template <typename T>
+__global__ __launch_bounds__(64) void k_restrict0(int d, Basis1D<T> bs, int nr, const int* __restrict__ leaf_off,
+                                                  const int* __restrict__ owner, const T* __restrict__ xi,
+                                                  const T* __restrict__ src, T* bnext, const T* __restrict__ dinv_next,
+                                                  T* dnext, T inv_theta_next, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* sh = reinterpret_cast<T*>(smem_raw);  // [B][65] (padded rows)
+  const int K = blockIdx.x;
+  const int k = bs.k;
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int i0 = leaf_off[K], i1 = leaf_off[K + 1];
+  const int lane = threadIdx.x;
+  for (int c = 0; c < nr; ++c) {
+    T tot = 0;  // thread q's running sum (q = lane < B)
+    for (int base = i0; base < i1; base += 64) {
+      const int i = base + lane;
+      T l[3][4];
+      T r = 0;
+      bool ok = (i < i1) && owner[i] >= 0;
+      if (ok) {
+        r = src[(int64_t)i * nr + c];
+        for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)i * d + a], l[a]);
+      }
+      for (int q = 0; q < B; ++q) sh[q * 65 + lane] = ok ? phi_q<T>(l, d, k, q) * r : (T)0;
+      __syncthreads();
+      if (lane < B) {
+        T s = 0;
+        for (int m = 0; m < 64; ++m) s += sh[lane * 65 + m];
+        tot += s;
+      }
+      __syncthreads();
+    }
+    if (lane < B) {
+      const int64_t o = ((int64_t)K * B + lane) * nr + c;
+      bnext[o] = tot;
+      if (dnext) dnext[o] = dinv_next[(int64_t)K * B + lane] * tot * inv_theta_next;
+    }
+  }
+}
+
+template <typename T>
+void launch_restrict0(int nbox, int d, int pc, int nr, const int* leaf_off, const int* owner, const T* xi,
+                      const T* src, T* bnext, const T* dinv_next, T* dnext, double inv_theta_next,
+                      const int* skip, hipStream_t s) {
+  const int k = pc + 1;
+  const int B = (d == 3) ? k * k * k : k * k;
+  size_t shm = sizeof(T) * B * 65;
+  hipLaunchKernelGGL((k_restrict0<T>), dim3(nbox), dim3(64), shm, s, d, make_basis<T>(pc), nr, leaf_off, owner, xi,
+                     src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);
+  check_launch("k_restrict0");
+}
+template void launch_restrict0<float>(int, int, int, int, const int*, const int*, const float*, const float*,
+                                      float*, const float*, float*, double, const int*, hipStream_t);
+template void launch_restrict0<double>(int, int, int, int, const int*, const int*, const double*, const double*,
+                                       double*, const double*, double*, double, const int*, hipStream_t);
+
+// Prolongation from the first agglomerated level: v_i = sum_q phi^K_q(xi_i) (e + epend)[K*B+q] (0 if i is
+// constrained).  One thread per fine point.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong0(int n, int d, Basis1D<T> bs, int nr, const int* __restrict__ owner,
+                                                  const T* __restrict__ xi, const T* __restrict__ e,
+                                                  const T* __restrict__ epend, T* v, const int* __restrict__ skip,
+                                                  int nlog) {
+  if (skip && *skip) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int i = lb * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int K = owner[i];
+  if (K < 0) {
+    for (int c = 0; c < nr; ++c) v[(int64_t)i * nr + c] = 0;
+    return;
+  }
+  const int k = bs.k;
+  const int B = (d == 3) ? k * k * k : k * k;
+  T l[3][4];
+  for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)i * d + a], l[a]);
+  for (int c = 0; c < nr; ++c) {
+    T s = 0;
+    for (int q = 0; q < B; ++q) {
+      const int64_t o = ((int64_t)K * B + q) * nr + c;
+      T ev = e[o];
+      if (epend) ev += epend[o];
+      s += phi_q<T>(l, d, k, q) * ev;
+    }
+    v[(int64_t)i * nr + c] = s;
+  }
+}
+
+template <typename T>
+void launch_prolong0(int n, int d, int pc, int nr, const int* owner, const T* xi, const T* e, const T* epend,
+                     T* v, const int* skip, hipStream_t s) {
+  const int nlog = (n + 255) / 256;
+  hipLaunchKernelGGL((k_prolong0<T>), dim3(xcd_grid(nlog)), dim3(256), 0, s, n, d, make_basis<T>(pc), nr, owner, xi,
+                     e, epend, v, skip, nlog);
+  check_launch("k_prolong0");
+}
+template void launch_prolong0<float>(int, int, int, int, const int*, const float*, const float*, const float*,
+                                     float*, const int*, hipStream_t);
+template void launch_prolong0<double>(int, int, int, int, const int*, const double*, const double*, const double*,
+                                      double*, const int*, hipStream_t);
+
+// P~ entry [q'][q] of child box c: prod_a M_c[a][q'_a][q_a]
+template <typename T>
+__device__ inline T pt_entry(const T* __restrict__ pt, int64_t c, int d, int k, int qc, int qp) {
+  const T* m = pt + (int64_t)c * d * k * k;
+  T v = m[(0 * k + qc % k) * k + qp % k];
+  qc /= k;
+  qp /= k;
+  v *= m[(1 * k + qc % k) * k + qp % k];
+  if (d == 3) {
+    qc /= k;
+    qp /= k;
+    v *= m[(2 * k + qc % k) * k + qp % k];
+  }
+  return v;
+}
+
+// Restriction between agglomerated levels: b[G*B+q] = sum_{C child of G} sum_q' P~_C[q'][q] src[C*B+q'].
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_c(int nbox_next, int nbox, int shift, int d, int k, int nr,
+                                                    const T* __restrict__ pt, const T* __restrict__ src, T* bnext,
+                                                    const T* __restrict__ dinv_next, T* dnext, T inv_theta_next,
+                                                    const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)nbox_next * B) return;
+  const int G = (int)(t / B), q = (int)(t - (int64_t)G * B);
+  const int c0 = G << shift;
+  const int c1 = min(nbox, (G + 1) << shift);
+  for (int c = 0; c < nr; ++c) {
+    T s = 0;
+    for (int C = c0; C < c1; ++C)
+      for (int qc = 0; qc < B; ++qc) s += pt_entry(pt, C, d, k, qc, q) * src[((int64_t)C * B + qc) * nr + c];
+    bnext[t * nr + c] = s;
+    if (dnext) dnext[t * nr + c] = dinv_next[t] * s * inv_theta_next;
+  }
+}
+
+template <typename T>
+void launch_restrict_c(int nbox_next, int nbox, int shift, int d, int pc, int nr, const T* pt, const T* src,
+                       T* bnext, const T* dinv_next, T* dnext, double inv_theta_next, const int* skip,
+                       hipStream_t s) {
+  const int k = pc + 1;
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int64_t tot = (int64_t)nbox_next * B;
+  hipLaunchKernelGGL((k_restrict_c<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nbox_next, nbox, shift, d,
+                     k, nr, pt, src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);
+  check_launch("k_restrict_c");
+}
+template void launch_restrict_c<float>(int, int, int, int, int, int, const float*, const float*, float*,
+                                       const float*, float*, double, const int*, hipStream_t);
+template void launch_restrict_c<double>(int, int, int, int, int, int, const double*, const double*, double*,
+                                        const double*, double*, double, const int*, hipStream_t);
+
+// Prolongation between agglomerated levels: v[C*B+q'] = sum_q P~_C[q'][q] (e + epend)[G*B+q], G = C >> shift.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_c(int nbox, int shift, int d, int k, int nr, const T* __restrict__ pt,
+                                                   const T* __restrict__ e, const T* __restrict__ epend, T* v,
+                                                   const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)nbox * B) return;
+  const int C = (int)(t / B), qc = (int)(t - (int64_t)C * B);
+  const int G = C >> shift;
+  for (int c = 0; c < nr; ++c) {
+    T s = 0;
+    for (int q = 0; q < B; ++q) {
+      const int64_t o = ((int64_t)G * B + q) * nr + c;
+      T ev = e[o];
+      if (epend) ev += epend[o];
+      s += pt_entry(pt, C, d, k, qc, q) * ev;
+    }
+    v[t * nr + c] = s;
+  }
+}
+
+template <typename T>
+void launch_prolong_c(int nbox, int shift, int d, int pc, int nr, const T* pt, const T* e, const T* epend, T* v,
+                      const int* skip, hipStream_t s) {
+  const int k = pc + 1;
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int64_t tot = (int64_t)nbox * B;
+  hipLaunchKernelGGL((k_prolong_c<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nbox, shift, d, k, nr, pt,
+                     e, epend, v, skip);
+  check_launch("k_prolong_c");
+}
+template void launch_prolong_c<float>(int, int, int, int, int, const float*, const float*, const float*, float*,
+                                      const int*, hipStream_t);
+template void launch_prolong_c<double>(int, int, int, int, int, const double*, const double*, const double*,
+                                       double*, const int*, hipStream_t);
+
+// =============================================================================================
+// Elementwise helpers
+// =============================================================================================
+template <typename T>
+__global__ void k_xupdate(int64_t count, T* x, const T* __restrict__ v, int assign, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  x[i] = assign ? v[i] : x[i] + v[i];
+}
+template <typename T>
+void launch_xupdate(int64_t count, T* x, const T* v, int assign, const int* skip, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL((k_xupdate<T>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, x, v, assign, skip);
+  check_launch("k_xupdate");
+}
+template void launch_xupdate<float>(int64_t, float*, const float*, int, const int*, hipStream_t);
+template void launch_xupdate<double>(int64_t, double*, const double*, int, const int*, hipStream_t);
+
+// V-cycle entry: b0[i] = r_user[perm[i]] (column c at r_user + c*ld), d0 = dinv * b0 * inv_theta
+template <typename T>
+__global__ void k_vc_entry(int n, int nr, const int* __restrict__ perm, const double* __restrict__ r, int64_t ld,
+                           T* b0, const T* __restrict__ dinv, T* d0, T inv_theta) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)n * nr) return;
+  const int i = (int)(t / nr), c = (int)(t - (int64_t)i * nr);
+  const T v = (T)r[(int64_t)c * ld + perm[i]];
+  b0[t] = v;
+  if (d0) d0[t] = dinv[i] * v * inv_theta;
+}
+template <typename T>
+void launch_vc_entry(int n, int nr, const int* perm, const double* r_user, int64_t ld_user, T* b0, const T* dinv,
+                     T* d0, double inv_theta, hipStream_t s) {
+  const int64_t tot = (int64_t)n * nr;
+  hipLaunchKernelGGL((k_vc_entry<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, nr, perm, r_user, ld_user,
+                     b0, dinv, d0, (T)inv_theta);
+  check_launch("k_vc_entry");
+}
+template void launch_vc_entry<float>(int, int, const int*, const double*, int64_t, float*, const float*, float*,
+                                     double, hipStream_t);
+template void launch_vc_entry<double>(int, int, const int*, const double*, int64_t, double*, const double*,
+                                      double*, double, hipStream_t);
+
+template <typename T>
+__global__ void k_vc_exit(int n, int nr, const int* __restrict__ perm, const T* __restrict__ x0,
+                          const T* __restrict__ dp, double* z, int64_t ld) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)n * nr) return;
+  const int i = (int)(t / nr), c = (int)(t - (int64_t)i * nr);
+  T v = x0[t];
+  if (dp) v += dp[t];
+  z[(int64_t)c * ld + perm[i]] = (double)v;
+}
+template <typename T>
+void launch_vc_exit(int n, int nr, const int* perm, const T* x0, const T* dpend, double* z_user, int64_t ld_user,
+                    hipStream_t s) {
+  const int64_t tot = (int64_t)n * nr;
+  hipLaunchKernelGGL((k_vc_exit<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, nr, perm, x0, dpend,
+                     z_user, ld_user);
+  check_launch("k_vc_exit");
+}
+template void launch_vc_exit<float>(int, int, const int*, const float*, const float*, double*, int64_t, hipStream_t);
+template void launch_vc_exit<double>(int, int, const int*, const double*, const double*, double*, int64_t,
+                                     hipStream_t);
+
+// Dense coarsest solve x = A_L^{-1} b with the float64 explicit inverse (one wave per row).
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_dense_apply(int nc, const double* __restrict__ cinv, const T* __restrict__ b,
+                                                     T* x, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= nc) return;
+  double acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) acc[k] = 0;
+  const double* a = cinv + (int64_t)row * nc;
+  for (int c = lane; c < nc; c += 64) {
+    const double m = a[c];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] += m * (double)b[(int64_t)c * NR + k];
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    acc[k] = wave_sum(acc[k], 64);
+    if (lane == k) x[(int64_t)row * NR + k] = (T)acc[k];
+  }
+}
+template <typename T>
+void launch_dense_apply(int nc, int nr, const double* cinv, const T* b, T* x, const int* skip, hipStream_t s) {
+  dim3 g((nc + 3) / 4);
+  switch (nr) {
+    case 1: hipLaunchKernelGGL((k_dense_apply<T, 1>), g, dim3(256), 0, s, nc, cinv, b, x, skip); break;
+    case 2: hipLaunchKernelGGL((k_dense_apply<T, 2>), g, dim3(256), 0, s, nc, cinv, b, x, skip); break;
+    case 4: hipLaunchKernelGGL((k_dense_apply<T, 4>), g, dim3(256), 0, s, nc, cinv, b, x, skip); break;
+    case 8: hipLaunchKernelGGL((k_dense_apply<T, 8>), g, dim3(256), 0, s, nc, cinv, b, x, skip); break;
+    case 16: hipLaunchKernelGGL((k_dense_apply<T, 16>), g, dim3(256), 0, s, nc, cinv, b, x, skip); break;
+    default: throw std::runtime_error("unsupported nrhs block");
+  }
+  check_launch("k_dense_apply");
+}
+template void launch_dense_apply<float>(int, int, const double*, const float*, float*, const int*, hipStream_t);
+template void launch_dense_apply<double>(int, int, const double*, const double*, double*, const int*, hipStream_t);
+
+__global__ void k_gather_cols(int n, int nr, int nuser, const int* __restrict__ perm,
+                              const double* __restrict__ user, int64_t ld, double* out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)n * nr) return;
+  const int i = (int)(t / nr), c = (int)(t - (int64_t)i * nr);
+  out[t] = c < nuser ? user[(int64_t)c * ld + perm[i]] : 0.0;
+}
+void launch_gather_cols(int n, int nr, int nuser, const int* perm, const double* user, int64_t ld_user,
+                        double* out, hipStream_t s) {
+  const int64_t tot = (int64_t)n * nr;
+  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, nr, nuser, perm, user,
+                     ld_user, out);
+  check_launch("k_gather_cols");
+}
+__global__ void k_scatter_cols(int n, int nr, int nuser, const int* __restrict__ perm,
+                               const double* __restrict__ in, double* user, int64_t ld) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)n * nr) return;
+  const int i = (int)(t / nr), c = (int)(t - (int64_t)i * nr);
+  if (c < nuser) user[(int64_t)c * ld + perm[i]] = in[t];
+}
+void launch_scatter_cols(int n, int nr, int nuser, const int* perm, const double* in, double* user,
+                         int64_t ld_user, hipStream_t s) {
+  const int64_t tot = (int64_t)n * nr;
+  hipLaunchKernelGGL(k_scatter_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, nr, nuser, perm, in,
+                     user, ld_user);
+  check_launch("k_scatter_cols");
+}
+
+__global__ void k_cast_d2f(int64_t count, const double* __restrict__ a, float* b) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) b[i] = (float)a[i];
+}
+void launch_cast_d2f(int64_t count, const double* a, float* b, hipStream_t s) {
+  if (count == 0) return;
+  int64_t g = (count + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_cast_d2f, dim3((unsigned)g), dim3(256), 0, s, count, a, b);
+  check_launch("k_cast_d2f");
+}
+
+__global__ void k_gather_vals(int64_t nnz, const int64_t* __restrict__ src, const double* __restrict__ uv,
+                              double* out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * 256) out[i] = uv[src[i]];
+}
+void launch_gather_vals(int64_t nnz, const int64_t* src, const double* user_vals, double* out, hipStream_t s) {
+  if (nnz == 0) return;
+  int64_t g = (nnz + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_gather_vals, dim3((unsigned)g), dim3(256), 0, s, nnz, src, user_vals, out);
+  check_launch("k_gather_vals");
+}
+
+// =============================================================================================
+// Set-up kernels
+// =============================================================================================
+// inverse diagonal of a level operator; *bad = 1 if any diagonal entry is not > 0
+__global__ void k_diag_inv(int n, int blk, const int* __restrict__ ptr, const int* __restrict__ idx,
+                           const double* __restrict__ val, double* dinv, double* diag, int* bad) {
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= n) return;
+  double dv = 0.0;
+  if (blk == 1) {
+    int lo = ptr[row], hi = ptr[row + 1];
+    while (lo < hi) {  // lower bound of `row`
+      int mid = (lo + hi) >> 1;
+      if (idx[mid] < row) lo = mid + 1; else hi = mid;
+    }
+    if (lo < ptr[row + 1] && idx[lo] == row) dv = val[lo];
+  } else {
+    const int K = row / blk, q = row - K * blk;
+    const int j0 = ptr[K], nb = ptr[K + 1] - j0;
+    int lo = j0, hi = j0 + nb;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (idx[mid] < K) lo = mid + 1; else hi = mid;
+    }
+    if (lo < j0 + nb && idx[lo] == K)
+      dv = val[(int64_t)blk * blk * j0 + (int64_t)q * nb * blk + (int64_t)(lo - j0) * blk + q];
+  }
+  if (diag) diag[row] = dv;
+  if (!(dv > 0.0)) {
+    *bad = 1;
+    dinv[row] = 0.0;
+  } else {
+    dinv[row] = 1.0 / dv;
+  }
+}
+void launch_diag_inv(int n, int blk, const int* ptr, const int* idx, const double* val, double* dinv, double* diag,
+                     int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_inv, dim3((n + 255) / 256), dim3(256), 0, s, n, blk, ptr, idx, val, dinv, diag, bad);
+  check_launch("k_diag_inv");
+}
+
+// Galerkin product, fine -> first agglomerated level (Section 4, inherited operators):
+// A1[K,K'] = sum_{i in K, j in K', i,j free} A_ij phi^K(x_i) phi^K'(x_j)^T.
+// One workgroup per stored output block; each thread owns up to EMAX entries (q, q') of the block and walks the
+// rows of K and, in each row, the contiguous run of columns owned by K' (columns are sorted and the internal
+// numbering is box-contiguous).  Fixed summation order: deterministic.
+template <int EMAX>
+__global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, const int* __restrict__ brow,
+                                                   const int* __restrict__ bptr, const int* __restrict__ bcol,
+                                                   const int* __restrict__ leaf_off, const int* __restrict__ owner,
+                                                   const double* __restrict__ xi, const int* __restrict__ rowptr,
+                                                   const int* __restrict__ col, const double* __restrict__ val,
+                                                   double* out) {
+  const int64_t blkid = blockIdx.x;
+  const int K = brow[blkid];
+  const int slot = (int)(blkid - bptr[K]);
+  const int nbK = bptr[K + 1] - bptr[K];
+  const int Kp = bcol[blkid];
+  const int k = bs.k;
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int cl = leaf_off[Kp], ch = leaf_off[Kp + 1];
+  int qi[EMAX], qj[EMAX];
+  double acc[EMAX], pi[EMAX];
+#pragma unroll
+  for (int m = 0; m < EMAX; ++m) {
+    const int e = threadIdx.x + m * blockDim.x;
+    qi[m] = e < B * B ? e / B : -1;
+    qj[m] = e < B * B ? e % B : 0;
+    acc[m] = 0;
+  }
+  for (int i = leaf_off[K]; i < leaf_off[K + 1]; ++i) {
+    if (owner[i] < 0) continue;
+    double li[3][4];
+    for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)i * d + a], li[a]);
+#pragma unroll
+    for (int m = 0; m < EMAX; ++m) pi[m] = qi[m] >= 0 ? phi_q<double>(li, d, k, qi[m]) : 0.0;
+    int lo = rowptr[i], hi = rowptr[i + 1];
+    const int end = hi;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (col[mid] < cl) lo = mid + 1; else hi = mid;
+    }
+    for (int p = lo; p < end; ++p) {
+      const int j = col[p];
+      if (j >= ch) break;
+      if (owner[j] < 0) continue;
+      const double a = val[p];
+      double lj[3][4];
+      for (int ax = 0; ax < d; ++ax) lag1d(bs, xi[(int64_t)j * d + ax], lj[ax]);
+#pragma unroll
+      for (int m = 0; m < EMAX; ++m)
+        if (qi[m] >= 0) acc[m] += a * pi[m] * phi_q<double>(lj, d, k, qj[m]);
+    }
+  }
+  const int64_t base = (int64_t)B * B * bptr[K];
+#pragma unroll
+  for (int m = 0; m < EMAX; ++m)
+    if (qi[m] >= 0) out[base + (int64_t)qi[m] * nbK * B + (int64_t)slot * B + qj[m]] = acc[m];
+}
+
+void launch_galerkin0(int64_t nblocks, int d, int pc, const int* brow, const int* bptr, const int* bcol,
+                      const int* leaf_off, const int* owner, const double* xi, const int* rowptr, const int* col,
+                      const double* val, double* out, hipStream_t s) {
+  const int k = pc + 1;
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int bb = B * B;
+  Basis1D<double> bs = make_basis<double>(pc);
+  if (nblocks == 0) return;
+  if (bb <= 256) {
+    int threads = ((bb + 63) / 64) * 64;
+    hipLaunchKernelGGL((k_galerkin0<1>), dim3((unsigned)nblocks), dim3(threads), 0, s, d, bs, brow, bptr, bcol,
+                       leaf_off, owner, xi, rowptr, col, val, out);
+  } else if (bb <= 768) {
+    hipLaunchKernelGGL((k_galerkin0<3>), dim3((unsigned)nblocks), dim3(256), 0, s, d, bs, brow, bptr, bcol, leaf_off,
+                       owner, xi, rowptr, col, val, out);
+  } else {
+    hipLaunchKernelGGL((k_galerkin0<16>), dim3((unsigned)nblocks), dim3(256), 0, s, d, bs, brow, bptr, bcol, leaf_off,
+                       owner, xi, rowptr, col, val, out);
+  }
+  check_launch("k_galerkin0");
+}
+
+// Galerkin product between agglomerated levels: A_{l+1}[G,G'] = sum_{C in G, C' in G'} P~_C^T A_l[C,C'] P~_C'.
+// One workgroup per output block; A_l blocks and P~ blocks are staged in LDS (dynamic, 4 B^2 doubles).
+template <int EMAX>
+__global__ __launch_bounds__(256) void k_galerkin_c(int d, int k, int shift, int nbox_in, const int* __restrict__ brow,
+                                                    const int* __restrict__ bptr_out, const int* __restrict__ bcol_out,
+                                                    const int* __restrict__ bptr_in, const int* __restrict__ bcol_in,
+                                                    const double* __restrict__ val_in, const double* __restrict__ pt,
+                                                    double* out) {
+  extern __shared__ unsigned char smem_raw[];
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int bb = B * B;
+  double* sA = reinterpret_cast<double*>(smem_raw);
+  double* sPc = sA + bb;
+  double* sPp = sPc + bb;
+  double* sT = sPp + bb;
+  const int64_t blkid = blockIdx.x;
+  const int G = brow[blkid];
+  const int slot = (int)(blkid - bptr_out[G]);
+  const int nbG = bptr_out[G + 1] - bptr_out[G];
+  const int Gp = bcol_out[blkid];
+  double acc[EMAX];
+#pragma unroll
+  for (int m = 0; m < EMAX; ++m) acc[m] = 0;
+  const int c0 = G << shift, c1 = min(nbox_in, (G + 1) << shift);
+  const int tlo = Gp << shift, thi = (Gp + 1) << shift;
+  for (int C = c0; C < c1; ++C) {
+    for (int e = threadIdx.x; e < bb; e += blockDim.x) sPc[e] = pt_entry(pt, C, d, k, e / B, e % B);
+    const int j0 = bptr_in[C], nbC = bptr_in[C + 1] - j0;
+    int lo = j0, hi = j0 + nbC;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (bcol_in[mid] < tlo) lo = mid + 1; else hi = mid;
+    }
+    for (int jb = lo; jb < j0 + nbC && bcol_in[jb] < thi; ++jb) {
+      const int Cp = bcol_in[jb];
+      const int64_t vb = (int64_t)bb * j0 + (int64_t)(jb - j0) * B;
+      __syncthreads();
+      for (int e = threadIdx.x; e < bb; e += blockDim.x) {
+        const int r = e / B, c = e % B;
+        sA[e] = val_in[vb + (int64_t)r * nbC * B + c];
+        sPp[e] = pt_entry(pt, Cp, d, k, r, c);
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < bb; e += blockDim.x) {  // T = A P~_C'
+        const int r = e / B, c = e % B;
+        double s = 0;
+        for (int m = 0; m < B; ++m) s += sA[r * B + m] * sPp[m * B + c];
+        sT[e] = s;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < EMAX; ++m) {  // acc += P~_C^T T
+        const int e = threadIdx.x + m * blockDim.x;
+        if (e < bb) {
+          const int q = e / B, qq = e % B;
+          double s = 0;
+          for (int r = 0; r < B; ++r) s += sPc[r * B + q] * sT[r * B + qq];
+          acc[m] += s;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t base = (int64_t)bb * bptr_out[G];
+#pragma unroll
+  for (int m = 0; m < EMAX; ++m) {
+    const int e = threadIdx.x + m * blockDim.x;
+    if (e < bb) out[base + (int64_t)(e / B) * nbG * B + (int64_t)slot * B + (e % B)] = acc[m];
+  }
+}
+
+void launch_galerkin_c(int64_t nblocks, int d, int pc, int shift, int nbox_in, const int* brow, const int* bptr_out,
+                       const int* bcol_out, const int* bptr_in, const int* bcol_in, const double* val_in,
+                       const double* pt, double* out, hipStream_t s) {
+  const int k = pc + 1;
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int bb = B * B;
+  const size_t shm = sizeof(double) * 4 * bb;
+  if (nblocks == 0) return;
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_c<16>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) throw std::runtime_error("coarse Galerkin: LDS request too large for this device");
+  }
+  if (bb <= 256) {
+    int threads = ((bb + 63) / 64) * 64;
+    hipLaunchKernelGGL((k_galerkin_c<1>), dim3((unsigned)nblocks), dim3(threads), shm, s, d, k, shift, nbox_in, brow,
+                       bptr_out, bcol_out, bptr_in, bcol_in, val_in, pt, out);
+  } else if (bb <= 768) {
+    hipLaunchKernelGGL((k_galerkin_c<3>), dim3((unsigned)nblocks), dim3(256), shm, s, d, k, shift, nbox_in, brow,
+                       bptr_out, bcol_out, bptr_in, bcol_in, val_in, pt, out);
+  } else {
+    hipLaunchKernelGGL((k_galerkin_c<16>), dim3((unsigned)nblocks), dim3(256), shm, s, d, k, shift, nbox_in, brow,
+                       bptr_out, bcol_out, bptr_in, bcol_in, val_in, pt, out);
+  }
+  check_launch("k_galerkin_c");
+}
+
+// scatter the block rows of the coarsest level into a dense row-major matrix
+__global__ void k_to_dense(int nbox, int B, const int* __restrict__ bptr, const int* __restrict__ bcol,
+                           const double* __restrict__ val, double* dense) {
+  const int row = blockIdx.x;  // one block per row
+  const int K = row / B, q = row - K * B;
+  const int j0 = bptr[K], nb = bptr[K + 1] - j0;
+  const int nc = nbox * B;
+  const int64_t vb = (int64_t)B * B * j0 + (int64_t)q * nb * B;
+  for (int p = threadIdx.x; p < nb * B; p += blockDim.x) {
+    const int j = p / B, c = p % B;
+    dense[(int64_t)row * nc + (int64_t)bcol[j0 + j] * B + c] = val[vb + p];
+  }
+}
+void launch_to_dense(int nbox, int B, const int* bptr, const int* bcol, const double* val, double* dense,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_to_dense, dim3(nbox * B), dim3(256), 0, s, nbox, B, bptr, bcol, val, dense);
+  check_launch("k_to_dense");
+}
+
+// Lanczos start vector v_i = ((u_i * 2654435761) mod 2^32) / 2^32 - 1/2, u_i = perm[i] (or i)
+__global__ void k_lanczos_start(int n, const int* __restrict__ perm, double* v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t u = perm ? (uint64_t)perm[i] : (uint64_t)i;
+  const uint64_t h = (u * 2654435761ull) & 0xffffffffull;
+  v[i] = (double)h / 4294967296.0 - 0.5;
+}
+void launch_lanczos_start(int n, const int* perm, double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos_start, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, v);
+  check_launch("k_lanczos_start");
+}
+
+// per-block partial sums of w_i x_i y_i (fixed grid of at most 1024 blocks, grid-stride)
+__global__ __launch_bounds__(256) void k_dot(int64_t n, const double* __restrict__ w, const double* __restrict__ x,
+                                             const double* __restrict__ y, double* partials) {
+  __shared__ double sh[4];
+  double acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    acc += (w ? w[i] : 1.0) * x[i] * y[i];
+  double t = block_sum256(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+int launch_dot(int64_t n, const double* w, const double* x, const double* y, double* partials, hipStream_t s) {
+  int64_t g = (n + 255) / 256;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_dot, dim3((unsigned)g), dim3(256), 0, s, n, w, x, y, partials);
+  check_launch("k_dot");
+  return (int)g;
+}
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a, x, b, y);
+  check_launch("k_axpby");
+}
+__global__ void k_lanczos_u(int64_t n, const double* __restrict__ dinv, const double* __restrict__ Av, double bp,
+                            const double* __restrict__ vp, double* u) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) u[i] = dinv[i] * Av[i] - bp * vp[i];
+}
+void launch_lanczos_u(int64_t n, const double* dinv, const double* Av, double beta_prev, const double* vprev,
+                      double* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos_u, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, dinv, Av, beta_prev, vprev, u);
+  check_launch("k_lanczos_u");
+}
+
+// =============================================================================================
+// Dense Cholesky (right-looking, 64-wide panels) and explicit inverse, float64, row-major in place.
+// =============================================================================================
+constexpr int NB = 64;
+
+// factor the diagonal block A[k0:k0+nb, k0:k0+nb] in one workgroup (LDS); lower triangle holds L
+__global__ __launch_bounds__(256) void k_chol_diag(int n, int k0, double* A, int* bad) {
+  __shared__ double s[NB][NB + 1];
+  const int nb = min(NB, n - k0);
+  for (int e = threadIdx.x; e < nb * nb; e += 256) s[e / nb][e % nb] = A[(int64_t)(k0 + e / nb) * n + k0 + e % nb];
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (threadIdx.x == 0) {
+      double piv = s[j][j];
+      if (!(piv > 0.0)) {
+        *bad = 1;
+        piv = 1.0;
+      }
+      s[j][j] = sqrt(piv);
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < nb; i += 256) s[i][j] /= s[j][j];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * nb; e += 256) {
+      const int i = e / nb, c = e % nb;
+      if (i > j && c > j && c <= i) s[i][c] -= s[i][j] * s[c][j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nb * nb; e += 256) {
+    const int i = e / nb, c = e % nb;
+    A[(int64_t)(k0 + i) * n + k0 + c] = (c <= i) ? s[i][c] : 0.0;
+  }
+}
+
+// panel below the diagonal block: A[i, k0:k0+nb] <- A[i, k0:k0+nb] L_kk^{-T}; one thread per row
+__global__ __launch_bounds__(256) void k_chol_panel(int n, int k0, double* A) {
+  __shared__ double L[NB][NB + 1];
+  const int nb = min(NB, n - k0);
+  for (int e = threadIdx.x; e < nb * nb; e += 256) L[e / nb][e % nb] = A[(int64_t)(k0 + e / nb) * n + k0 + e % nb];
+  __syncthreads();
+  const int i = k0 + nb + blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double x[NB];
+  double* row = A + (int64_t)i * n + k0;
+  for (int c = 0; c < nb; ++c) {
+    double v = row[c];
+    for (int m = 0; m < c; ++m) v -= x[m] * L[c][m];
+    x[c] = v / L[c][c];
+  }
+  for (int c = 0; c < nb; ++c) row[c] = x[c];
+}
+
+// C[i][j] -= sum_m A(i, m) B(m, j) on an m x n tile set, k = kk <= 64.
+// A(i,m) = a[i*lda + m] (or a[m*lda + i] if ta), B(m,j) = b[m*ldb + j] (or b[j*ldb + m] if tb).
+// 64x64 output tile per workgroup, 256 threads, 4x4 outputs per thread.
+__global__ __launch_bounds__(256) void k_gemm_sub(int M, int N, int kk, const double* __restrict__ a, int64_t lda, int ta,
+                                                  const double* __restrict__ b, int64_t ldb, int tb, double* c,
+                                                  int64_t ldc, int lower_only, int row0, int col0) {
+  __shared__ double sa[NB][NB + 1];
+  __shared__ double sb[NB][NB + 1];
+  const int ti = blockIdx.y * NB, tj = blockIdx.x * NB;
+  if (lower_only && tj > ti + NB - 1 + (row0 - col0)) return;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int r = e / NB, m = e % NB;
+    double va = 0, vb = 0;
+    if (ti + r < M && m < kk) va = ta ? a[(int64_t)m * lda + ti + r] : a[(int64_t)(ti + r) * lda + m];
+    if (tj + r < N && m < kk) vb = tb ? b[(int64_t)(tj + r) * ldb + m] : b[(int64_t)m * ldb + tj + r];
+    sa[r][m] = va;
+    sb[r][m] = vb;  // sb[j][m] = B(m, j)
+  }
+  __syncthreads();
+  const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+  double acc[4][4] = {};
+  for (int m = 0; m < kk; ++m) {
+    double av[4], bv[4];
+    for (int u = 0; u < 4; ++u) { av[u] = sa[tr + u][m]; bv[u] = sb[tc + u][m]; }
+    for (int u = 0; u < 4; ++u)
+      for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
+  }
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti + tr + u, j = tj + tc + v;
+      if (i < M && j < N) c[(int64_t)i * ldc + j] -= acc[u][v];
+    }
+}
+
+// left triangular solves on all columns of X (n x n): forward L y = x (lower=1) or backward L^T y = x
+// within the diagonal block k0; one thread per column
+__global__ __launch_bounds__(256) void k_trsm_cols(int n, int k0, const double* __restrict__ Lm, double* X, int fwd) {
+  __shared__ double L[NB][NB + 1];
+  const int nb = min(NB, n - k0);
+  for (int e = threadIdx.x; e < nb * nb; e += 256) L[e / nb][e % nb] = Lm[(int64_t)(k0 + e / nb) * n + k0 + e % nb];
+  __syncthreads();
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  double x[NB];
+  for (int r = 0; r < nb; ++r) x[r] = X[(int64_t)(k0 + r) * n + j];
+  if (fwd) {
+    for (int r = 0; r < nb; ++r) {
+      double v = x[r];
+      for (int m = 0; m < r; ++m) v -= L[r][m] * x[m];
+      x[r] = v / L[r][r];
+    }
+  } else {
+    for (int r = nb - 1; r >= 0; --r) {
+      double v = x[r];
+      for (int m = r + 1; m < nb; ++m) v -= L[m][r] * x[m];
+      x[r] = v / L[r][r];
+    }
+  }
+  for (int r = 0; r < nb; ++r) X[(int64_t)(k0 + r) * n + j] = x[r];
+}
+
+__global__ void k_identity(int n, double* X) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  X[t] = (t / n == t % n) ? 1.0 : 0.0;
+}
+
+void dense_cholesky_inverse(int n, double* A, double* Inv, int* bad, hipStream_t s) {
+  const int nblk = (n + NB - 1) / NB;
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * NB;
+    const int nb = std::min(NB, n - k0);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, n, k0, A, bad);
+    const int rest = n - k0 - nb;
+    if (rest > 0) {
+      hipLaunchKernelGGL(k_chol_panel, dim3((rest + 255) / 256), dim3(256), 0, s, n, k0, A);
+      // trailing update A22 -= L21 L21^T (full square; only the lower part is used later)
+      const int r0 = k0 + nb;
+      dim3 g((rest + NB - 1) / NB, (rest + NB - 1) / NB);
+      hipLaunchKernelGGL(k_gemm_sub, g, dim3(256), 0, s, rest, rest, nb, A + (int64_t)r0 * n + k0, (int64_t)n, 0,
+                         A + (int64_t)r0 * n + k0, (int64_t)n, 1, A + (int64_t)r0 * n + r0, (int64_t)n, 0, 0, 0);
+    }
+  }
+  check_launch("cholesky");
+  // zero the strict upper triangle is not needed: the solves below only read the lower triangle
+  const int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(k_identity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, n, Inv);
+  // forward: L Y = I
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * NB;
+    const int nb = std::min(NB, n - k0);
+    hipLaunchKernelGGL(k_trsm_cols, dim3((n + 255) / 256), dim3(256), 0, s, n, k0, A, Inv, 1);
+    const int rest = n - k0 - nb;
+    if (rest > 0) {
+      dim3 g((n + NB - 1) / NB, (rest + NB - 1) / NB);
+      // Y[r0:, :] -= L[r0:, k0:k0+nb] Y[k0:k0+nb, :]
+      hipLaunchKernelGGL(k_gemm_sub, g, dim3(256), 0, s, rest, n, nb, A + (int64_t)(k0 + nb) * n + k0, (int64_t)n, 0,
+                         Inv + (int64_t)k0 * n, (int64_t)n, 0, Inv + (int64_t)(k0 + nb) * n, (int64_t)n, 0, 0, 0);
+    }
+  }
+  // backward: L^T X = Y
+  for (int kb = nblk - 1; kb >= 0; --kb) {
+    const int k0 = kb * NB;
+    hipLaunchKernelGGL(k_trsm_cols, dim3((n + 255) / 256), dim3(256), 0, s, n, k0, A, Inv, 0);
+    if (k0 > 0) {
+      const int nb = std::min(NB, n - k0);
+      dim3 g((n + NB - 1) / NB, (k0 + NB - 1) / NB);
+      // X[0:k0, :] -= L[k0:k0+nb, 0:k0]^T X[k0:k0+nb, :]
+      hipLaunchKernelGGL(k_gemm_sub, g, dim3(256), 0, s, k0, n, nb, A + (int64_t)k0 * n, (int64_t)n, 1,
+                         Inv + (int64_t)k0 * n, (int64_t)n, 0, Inv, (int64_t)n, 0, 0, 0);
+    }
+  }
+  check_launch("inverse");
+}
+
+// =============================================================================================
+// PCG (float64 outer iteration; scalars live on the device)
+// =============================================================================================
+__device__ inline double sum_partials(const double* __restrict__ partials, int npart, int nr, int k, double* sh) {
+  double acc = 0;
+  for (int b = threadIdx.x; b < npart; b += 256) acc += partials[(int64_t)b * nr + k];
+  return block_sum256(acc, sh);
+}
+
+__global__ __launch_bounds__(256) void k_pcg_alpha(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
+  __shared__ double sh[4];
+  if (st->all_done) return;
+  for (int k = 0; k < nr; ++k) {
+    const double pq = sum_partials(partials, npart, nr, k, sh);
+    if (threadIdx.x == 0) st->alpha[k] = st->done[k] ? 0.0 : st->gamma[k] / pq;
+  }
+}
+void launch_pcg_alpha(int nr, PcgState* st, const double* partials, int npart, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, s, nr, st, partials, npart);
+  check_launch("k_pcg_alpha");
+}
+
+// x += alpha p; r -= alpha q; partial ||r||^2; V-cycle entry b0 = (T) r, d0 = dinv0 b0 / theta0
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_pcg_xr(int n, PcgState* st, double* x, double* r, const double* __restrict__ p,
+                                                const double* __restrict__ q, double* partials, T* b0,
+                                                const T* __restrict__ dinv0, T* d0, T inv_theta0, int nlog) {
+  __shared__ double sh[4 * NR];
+  if (st->all_done) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  double al[NR], acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) { al[k] = st->alpha[k]; acc[k] = 0; }
+  const int i = lb * 256 + threadIdx.x;
+  if (i < n) {
+    const T di = d0 ? dinv0[i] : (T)0;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int64_t o = (int64_t)i * NR + k;
+      x[o] += al[k] * p[o];
+      const double rv = r[o] - al[k] * q[o];
+      r[o] = rv;
+      acc[k] = rv * rv;
+      if (b0) {
+        const T bv = (T)rv;
+        b0[o] = bv;
+        if (d0) d0[o] = di * bv * inv_theta0;
+      } else if (d0) {
+        d0[o] = di * (T)rv * inv_theta0;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    double v = wave_sum(acc[k], 64);
+    if ((threadIdx.x & 63) == 0) sh[(threadIdx.x >> 6) * NR + k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NR) {
+    const int k = threadIdx.x;
+    partials[(int64_t)lb * NR + k] = (sh[k] + sh[NR + k]) + (sh[2 * NR + k] + sh[3 * NR + k]);
+  }
+}
+template <typename T>
+void launch_pcg_xr(int n, int nr, PcgState* st, const double* partials_pq, int npart, double* x, double* r,
+                   const double* p, const double* q, double* partials_rr, T* b0, const T* dinv0, T* d0,
+                   double inv_theta0, hipStream_t s) {
+  launch_pcg_alpha(nr, st, partials_pq, npart, s);
+  const int nlog = (n + 255) / 256;
+  dim3 g(xcd_grid(nlog));
+#define R3_XR(NRV) \
+  hipLaunchKernelGGL((k_pcg_xr<T, NRV>), g, dim3(256), 0, s, n, st, x, r, p, q, partials_rr, b0, dinv0, d0, (T)inv_theta0, nlog)
+  switch (nr) {
+    case 1: R3_XR(1); break;
+    case 2: R3_XR(2); break;
+    case 4: R3_XR(4); break;
+    case 8: R3_XR(8); break;
+    case 16: R3_XR(16); break;
+    default: throw std::runtime_error("unsupported nrhs block");
+  }
+#undef R3_XR
+  check_launch("k_pcg_xr");
+}
+template void launch_pcg_xr<float>(int, int, PcgState*, const double*, int, double*, double*, const double*,
+                                   const double*, double*, float*, const float*, float*, double, hipStream_t);
+template void launch_pcg_xr<double>(int, int, PcgState*, const double*, int, double*, double*, const double*,
+                                    const double*, double*, double*, const double*, double*, double, hipStream_t);
+
+__global__ __launch_bounds__(256) void k_pcg_check(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
+  __shared__ double sh[4];
+  if (st->all_done) return;
+  int all = 1;
+  for (int k = 0; k < nr; ++k) {
+    const double rr = sum_partials(partials, npart, nr, k, sh);
+    if (threadIdx.x == 0 && !st->done[k]) {
+      st->rr[k] = rr;
+      st->iters[k] += 1;
+      if (rr <= st->tau2[k]) st->done[k] = 1;
+    }
+    if (threadIdx.x == 0) all &= st->done[k];
+  }
+  if (threadIdx.x == 0) st->all_done = all;
+}
+void launch_pcg_check(int nr, PcgState* st, const double* partials, int npart, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, s, nr, st, partials, npart);
+  check_launch("k_pcg_check");
+}
+
+// z = x0 + dpend (float64); partials of <r,z> and <q,z>
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_pcg_z(int n, PcgState* st, const T* __restrict__ x0, const T* __restrict__ dp,
+                                               double* z, const double* __restrict__ r, const double* __restrict__ q,
+                                               double* partials, int nlog) {
+  __shared__ double sh[4 * 2 * NR];
+  if (st->all_done) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  double a1[NR], a2[NR];
+  const int i = lb * 256 + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    a1[k] = 0;
+    a2[k] = 0;
+    if (i < n) {
+      const int64_t o = (int64_t)i * NR + k;
+      T v = x0[o];
+      if (dp) v += dp[o];
+      const double zv = (double)v;
+      z[o] = zv;
+      a1[k] = r[o] * zv;
+      a2[k] = q ? q[o] * zv : 0.0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    double v1 = wave_sum(a1[k], 64), v2 = wave_sum(a2[k], 64);
+    if ((threadIdx.x & 63) == 0) {
+      sh[(threadIdx.x >> 6) * 2 * NR + k] = v1;
+      sh[(threadIdx.x >> 6) * 2 * NR + NR + k] = v2;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * NR) {
+    const int k = threadIdx.x;
+    partials[(int64_t)lb * 2 * NR + k] = (sh[k] + sh[2 * NR + k]) + (sh[4 * NR + k] + sh[6 * NR + k]);
+  }
+}
+template <typename T>
+void launch_pcg_z(int n, int nr, PcgState* st, const T* x0, const T* dpend, double* z, const double* r,
+                  const double* q, double* partials, hipStream_t s) {
+  const int nlog = (n + 255) / 256;
+  dim3 g(xcd_grid(nlog));
+#define R3_Z(NRV) hipLaunchKernelGGL((k_pcg_z<T, NRV>), g, dim3(256), 0, s, n, st, x0, dpend, z, r, q, partials, nlog)
+  switch (nr) {
+    case 1: R3_Z(1); break;
+    case 2: R3_Z(2); break;
+    case 4: R3_Z(4); break;
+    case 8: R3_Z(8); break;
+    case 16: R3_Z(16); break;
+    default: throw std::runtime_error("unsupported nrhs block");
+  }
+#undef R3_Z
+  check_launch("k_pcg_z");
+}
+template void launch_pcg_z<float>(int, int, PcgState*, const float*, const float*, double*, const double*,
+                                  const double*, double*, hipStream_t);
+template void launch_pcg_z<double>(int, int, PcgState*, const double*, const double*, double*, const double*,
+                                   const double*, double*, hipStream_t);
+
+// beta: standard (gamma'/gamma) or flexible (-alpha <z,q> / gamma); partials hold [rz(0..nr-1), qz(0..nr-1)]
+__global__ __launch_bounds__(256) void k_pcg_beta(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
+  __shared__ double sh[4];
+  if (st->all_done) return;
+  for (int k = 0; k < nr; ++k) {
+    const double rz = sum_partials(partials, npart, 2 * nr, k, sh);
+    const double qz = sum_partials(partials, npart, 2 * nr, nr + k, sh);
+    if (threadIdx.x == 0 && !st->done[k]) {
+      const double g = st->gamma[k];
+      st->beta[k] = st->flexible ? (-st->alpha[k] * qz) / g : rz / g;
+      st->gamma[k] = rz;
+    }
+  }
+}
+void launch_pcg_beta(int nr, PcgState* st, const double* partials, int npart, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, s, nr, st, partials, npart);
+  check_launch("k_pcg_beta");
+}
+
+__global__ void k_pcg_p(int n, int nr, PcgState* st, const double* __restrict__ z, double* p) {
+  if (st->all_done) return;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)n * nr) return;
+  const int k = (int)(t % nr);
+  if (st->done[k]) return;
+  p[t] = z[t] + st->beta[k] * p[t];
+}
+void launch_pcg_p(int n, int nr, PcgState* st, const double* z, double* p, hipStream_t s) {
+  const int64_t tot = (int64_t)n * nr;
+  hipLaunchKernelGGL(k_pcg_p, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, nr, st, z, p);
+  check_launch("k_pcg_p");
+}
+
+// r = b - q with partial ||r||^2 per column
+template <int NR>
+__global__ __launch_bounds__(256) void k_residual(int n, const double* __restrict__ b, const double* __restrict__ q,
+                                                  double* r, double* partials) {
+  __shared__ double sh[4 * NR];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double acc[NR];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    acc[k] = 0;
+    if (i < n) {
+      const int64_t o = (int64_t)i * NR + k;
+      const double v = b[o] - q[o];
+      r[o] = v;
+      acc[k] = v * v;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    double v = wave_sum(acc[k], 64);
+    if ((threadIdx.x & 63) == 0) sh[(threadIdx.x >> 6) * NR + k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NR) {
+    const int k = threadIdx.x;
+    partials[(int64_t)blockIdx.x * NR + k] = (sh[k] + sh[NR + k]) + (sh[2 * NR + k] + sh[3 * NR + k]);
+  }
+}
+int launch_residual(int n, int nr, const double* b, const double* q, double* r, double* partials, hipStream_t s) {
+  const int g = (n + 255) / 256;
+#define R3_R(NRV) hipLaunchKernelGGL((k_residual<NRV>), dim3(g), dim3(256), 0, s, n, b, q, r, partials)
+  switch (nr) {
+    case 1: R3_R(1); break;
+    case 2: R3_R(2); break;
+    case 4: R3_R(4); break;
+    case 8: R3_R(8); break;
+    case 16: R3_R(16); break;
+    default: throw std::runtime_error("unsupported nrhs block");
+  }
+#undef R3_R
+  check_launch("k_residual");
+  return g;
+}
+
+__global__ __launch_bounds__(256) void k_pcg_init(int nr, PcgState* st, const double* __restrict__ partials, int npart,
+                                                  double rtol, int nr_active, int flexible) {
+  __shared__ double sh[4];
+  int all = 1;
+  for (int k = 0; k < nr; ++k) {
+    const double rr = sum_partials(partials, npart, nr, k, sh);
+    if (threadIdx.x == 0) {
+      st->rr0[k] = rr;
+      st->rr[k] = rr;
+      st->tau2[k] = rtol * rtol * rr;
+      st->iters[k] = 0;
+      st->alpha[k] = 0;
+      st->beta[k] = 0;
+      st->done[k] = (k >= nr_active) || (rr <= st->tau2[k]);
+      all &= st->done[k];
+    }
+  }
+  if (threadIdx.x == 0) {
+    st->all_done = all;
+    st->nr = nr;
+    st->flexible = flexible;
+  }
+}
+void launch_pcg_init(int nr, PcgState* st, const double* partials, int npart, double rtol, int flexible,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(256), 0, s, nr, st, partials, npart, rtol, nr, flexible);
+  check_launch("k_pcg_init");
+}
+
+__global__ __launch_bounds__(256) void k_pcg_gamma(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
+  __shared__ double sh[4];
+  for (int k = 0; k < nr; ++k) {
+    const double rz = sum_partials(partials, npart, 2 * nr, k, sh);
+    if (threadIdx.x == 0) st->gamma[k] = rz;
+  }
+}
+__global__ void k_copy(int64_t count, const double* __restrict__ a, double* b) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) b[i] = a[i];
+}
+void launch_pcg_init_gamma(int n, int nr, PcgState* st, const double* partials, int npart, const double* z,
+                           double* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_gamma, dim3(1), dim3(256), 0, s, nr, st, partials, npart);
+  const int64_t tot = (int64_t)n * nr;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, tot, z, p);
+  check_launch("k_pcg_gamma");
+}
+
+template <typename T>
+__global__ void k_vc_prep(int64_t count, int nr, const double* __restrict__ r, T* b0, const T* __restrict__ dinv0,
+                          T* d0, T inv_theta0, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= count) return;
+  const T v = (T)r[t];
+  if (b0) b0[t] = v;
+  if (d0) d0[t] = dinv0[t / nr] * v * inv_theta0;
+}
+template <typename T>
+void launch_vc_prep(int n, int nr, const double* r, T* b0, const T* dinv0, T* d0, double inv_theta0,
+                    const int* skip, hipStream_t s) {
+  const int64_t tot = (int64_t)n * nr;
+  hipLaunchKernelGGL((k_vc_prep<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, tot, nr, r, b0, dinv0, d0,
+                     (T)inv_theta0, skip);
+  check_launch("k_vc_prep");
+}
+template void launch_vc_prep<float>(int, int, const double*, float*, const float*, float*, double, const int*,
+                                    hipStream_t);
+template void launch_vc_prep<double>(int, int, const double*, double*, const double*, double*, double, const int*,
+                                     hipStream_t);
+
+// =============================================================================================
+// FEM helpers for the differentiable solve
+// =============================================================================================
+// g_e = - sum_{a,b free} lam[c_ea] Ke[a,b] u[c_eb]; one wave per cell
+__global__ __launch_bounds__(256) void k_cell_grad(int64_t ncells, int nloc, const int* __restrict__ cells,
+                                                   const double* __restrict__ Ke, int64_t ke_stride,
+                                                   const double* __restrict__ u, const double* __restrict__ lam,
+                                                   const unsigned char* __restrict__ cons, double* g) {
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (e >= ncells) return;
+  const int* c = cells + e * nloc;
+  const double* K = Ke + e * ke_stride;
+  double acc = 0;
+  for (int a = 0; a < nloc; ++a) {
+    const int ia = c[a];
+    if (cons[ia]) continue;
+    const double la = lam[ia];
+    double s = 0;
+    for (int b = lane; b < nloc; b += 64) {
+      const int ib = c[b];
+      if (!cons[ib]) s += K[(int64_t)a * nloc + b] * u[ib];
+    }
+    acc += la * s;
+  }
+  acc = wave_sum(acc, 64);
+  if (lane == 0) g[e] = -acc;
+}
+void launch_cell_grad(int64_t ncells, int nloc, const int* cells, const double* Ke, int64_t ke_stride,
+                      const double* u, const double* lam, const unsigned char* constrained_user, double* g,
+                      hipStream_t s) {
+  if (ncells == 0) return;
+  hipLaunchKernelGGL(k_cell_grad, dim3((unsigned)((ncells + 3) / 4)), dim3(256), 0, s, ncells, nloc, cells, Ke,
+                     ke_stride, u, lam, constrained_user, g);
+  check_launch("k_cell_grad");
+}
+
+// vals[s] = sum over the contributions of slot s (cell e, local pair a*nloc+b, encoded e*nloc^2 + pair) of
+// kappa_e Ke_e[a,b]; constrained diagonal slots get 1.0
+__global__ void k_assemble(int64_t nnz, const int64_t* __restrict__ sp, const int64_t* __restrict__ contrib,
+                           const double* __restrict__ kappa, const double* __restrict__ Ke, int64_t ke_stride,
+                           int nloc, const unsigned char* __restrict__ diag_one, double* vals) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= nnz) return;
+  if (diag_one[s]) {
+    vals[s] = 1.0;
+    return;
+  }
+  const int64_t nl2 = (int64_t)nloc * nloc;
+  double acc = 0;
+  for (int64_t m = sp[s]; m < sp[s + 1]; ++m) {
+    const int64_t code = contrib[m];
+    const int64_t e = code / nl2, pr = code - e * nl2;
+    acc += kappa[e] * Ke[e * ke_stride + pr];
+  }
+  vals[s] = acc;
+}
+void launch_assemble(int64_t nnz, const int64_t* slot_ptr, const int64_t* contrib, const double* kappa,
+                     const double* Ke, int64_t ke_stride, int nloc, const unsigned char* diag_one, double* vals,
+                     hipStream_t s) {
+  if (nnz == 0) return;
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, slot_ptr, contrib, kappa,
+                     Ke, ke_stride, nloc, diag_one, vals);
+  check_launch("k_assemble");
+}
+
+}  // namespace r3mg

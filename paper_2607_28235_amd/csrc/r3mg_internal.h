@@ -1,0 +1,212 @@
+// Internal data structures of the R3MG-C library (host analysis + device hierarchy).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "r3mg.h"
+
+namespace r3mg {
+
+// ---------------------------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------------------------
+struct Error {
+  r3mg_status code;
+  std::string msg;
+};
+
+#define R3MG_HIP_CHECK(expr)                                                          \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw ::r3mg::Error{R3MG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+void set_last_error(const std::string& s);
+
+// ---------------------------------------------------------------------------------------------
+// Device buffer (RAII)
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (count == n && p) return;
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{R3MG_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+    }
+    n = count;
+  }
+  void upload(const T* src, size_t count, hipStream_t s) {
+    alloc(count);
+    if (count) R3MG_HIP_CHECK(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void upload(const std::vector<T>& v, hipStream_t s) { upload(v.data(), v.size(), s); }
+};
+
+// ---------------------------------------------------------------------------------------------
+// Host analysis results
+// ---------------------------------------------------------------------------------------------
+struct HostLevel {           // agglomerated level l >= 1 (boxes of the R-tree at `depth`)
+  int depth = 0;
+  int64_t nbox = 0;
+  int64_t n = 0;             // nbox * B
+  std::vector<double> lo, hi;  // nbox x d
+  std::vector<int64_t> bptr;   // block sparsity of A_l: nbox + 1
+  std::vector<int32_t> bcol;   // sorted block columns per block row
+  std::vector<double> pt1d;    // l < L: injection into the parent box, nbox x d x (p'+1)^2 [axis][child node][parent node]
+  int child_shift = 0;         // l >= 2: boxes of level l-1 per box of level l = 2^child_shift
+  double max_extent = 0.0;
+};
+
+struct Analysis {
+  r3mg_options opt{};
+  int d = 0, pc = 0, B = 0;
+  int64_t n = 0, nnz = 0;
+  int depth = 0;                         // R-tree depth t
+  std::vector<int> depths;               // depths of levels 1..L
+  std::vector<int32_t> order;            // leaf position -> user point (= perm: internal -> user)
+  std::vector<int32_t> iperm;            // user -> internal
+  std::vector<int64_t> leaf_off;         // internal offsets of the level-1 boxes (nbox1 + 1)
+  std::vector<uint8_t> constrained;      // internal order
+  std::vector<uint8_t> constrained_user; // caller's order
+  std::vector<int32_t> owner;            // internal point -> level-1 box, -1 if constrained
+  std::vector<double> xi;                // internal point x d: local coordinates in the level-1 box
+  std::vector<double> coords_int;        // internal point x d coordinates
+  // fine operator in internal numbering
+  std::vector<int32_t> rowptr;           // n + 1
+  std::vector<int32_t> col;              // nnz
+  std::vector<double> val;               // nnz
+  std::vector<int64_t> src;              // internal nnz position -> user nnz position
+  std::vector<int32_t> user_col;         // the caller's pattern (for assembly)
+  std::vector<int64_t> user_rowptr;
+  std::vector<HostLevel> lv;             // lv[0] unused (fine level); lv[l] for l = 1..L
+  int nlevels() const { return (int)depths.size() + 1; }
+};
+
+// builds the analysis; throws Error
+std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t* row_ptr,
+                                  const int32_t* col_idx, const double* vals, const r3mg_options& opt);
+
+// bisection R-tree (Section 3, Section 4 point-based agglomeration); offsets[k] per depth k
+void bisection_rtree(const double* coords, int64_t n, int d, int leaf, int& depth, std::vector<int32_t>& order,
+                     std::vector<std::vector<int64_t>>& offsets);
+
+// 1D GLL nodes of the box basis on [0,1]
+void box_nodes_1d(int pc, double* t);
+
+// ---------------------------------------------------------------------------------------------
+// Device hierarchy
+// ---------------------------------------------------------------------------------------------
+struct DevLevel {
+  int64_t n = 0, nbox = 0;
+  int64_t nnz = 0;
+  // fine level (l = 0): CSR
+  DBuf<int32_t> rowptr, col;
+  // coarse levels (l >= 1): block rows
+  DBuf<int32_t> bptr, bcol;
+  DBuf<double> val64;
+  DBuf<float> val32;
+  DBuf<double> dinv64;
+  DBuf<float> dinv32;
+  double lam_hi = 0, lam_lo = 0, lam_hat = 0;
+  int lanes = 8;  // lanes per row of the SpMV kernels
+  // transfer to the next level
+  DBuf<double> xi64;     // l = 0: n x d
+  DBuf<float> xi32;
+  DBuf<int32_t> owner;   // l = 0: n (level-1 box of each point, -1 if constrained)
+  DBuf<int32_t> leaf_off;  // l = 0: nbox1 + 1 internal offsets of the level-1 boxes
+  DBuf<int32_t> brow;    // l >= 1 during set-up: block -> block row
+  DBuf<double> pt64;     // l >= 1 (l < L): nbox x d x (p'+1)^2
+  DBuf<float> pt32;
+  int child_shift = 0;   // level l >= 2: 2^child_shift boxes of level l-1 per box
+  // V-cycle work vectors in the V-cycle precision (n x nrhs interleaved)
+  DBuf<char> b, x, rho, dA, dB;
+  int64_t vec_cap = 0;
+  double bytes_apply = 0;
+};
+
+struct PcgScalars;  // device-side PCG state (defined in the solver)
+
+struct Device {
+  int dev = 0;
+  std::vector<DevLevel> lv;
+  // dense coarsest: inverse (nL x nL float64, row-major)
+  DBuf<double> cinv;
+  int64_t nc = 0;
+  // fine-level helpers
+  DBuf<int32_t> perm;   // internal -> user
+  DBuf<int64_t> src;    // internal nnz -> user nnz
+  // PCG work (float64, internal numbering, n x nrhs interleaved)
+  DBuf<double> px, pr, pp, pq, pz, pb;
+  DBuf<double> partials;  // reduction partials
+  DBuf<char> state;       // PcgState
+  DBuf<int> flag;         // set-up error flag
+  int64_t pcg_cap = 0;
+  // graph cache: (nrhs) -> exec
+  std::map<int, hipGraphExec_t> graphs;
+  std::map<int, hipGraph_t> graph_defs;
+  hipStream_t cap_stream = nullptr;
+  void* pinned = nullptr;  // host pinned buffer for flags
+  // autotuned SpMM lanes per (level, nrhs)
+  std::map<std::pair<int, int>, int> tuned;
+  ~Device();
+};
+
+struct HandleImpl {
+  std::unique_ptr<Analysis> an;
+  std::unique_ptr<Device> dev;
+  bool factored = false;
+  DBuf<unsigned char> cons_user_dev;  // constrained mask in the caller's order (adjoint gradient)
+};
+
+// solver entry points (solver.cpp)
+void device_setup(HandleImpl& h, hipStream_t s);
+void update_values(HandleImpl& h, const double* vals_dev, hipStream_t s);
+void vcycle_api(HandleImpl& h, const double* r, double* z, int nrhs, hipStream_t s);
+void level_apply(HandleImpl& h, int level, const double* x, double* y, hipStream_t s);
+r3mg_status pcg_solve(HandleImpl& h, const double* b, double* x, int nrhs, double rtol, int maxit, hipStream_t s,
+                      int* iters, double* relres);
+r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double* const* x, double rtol, int maxit,
+                      hipStream_t s, int* iters, double* relres);
+void time_smoother_kernel(HandleImpl& h, int level, int reps, hipStream_t s, double* ms, double* bytes);
+
+}  // namespace r3mg
+
+struct r3mg_handle_ {
+  r3mg::HandleImpl impl;
+};

@@ -1,0 +1,843 @@
+// Device set-up, V-cycle and PCG drivers of the R3MG-C library.
+//
+// Paper Section 4 (multilevel preconditioner: inherited operators, transfers, one V-cycle per CG iteration),
+// Section 5 Remark on the smoother and Section 6 (Chebyshev-Jacobi smoother tuned by Lanczos, direct coarsest
+// solve, PCG stopping rule).  The V-cycle is the symmetric multiplicative cycle
+//   B_L r = A_L^{-1} r;  B_l r: x = S^nu(r,0); r_c = P^T (r - A x); x += P B_{l+1} r_c; x = S^nu(r, x).
+// Each smoothing application is the Chebyshev recurrence on D^{-1}A started from the current iterate.  The
+// implementation carries the unscaled residual rho = b - A x through every step, so that every operator
+// application of a level is one fused kernel (t = A u; rho -= t; x += u; d = c1 u + c2 D^{-1} rho): the
+// residual at the start of an application and the residual that is restricted are obtained from the last
+// direction instead of a separate b - A x pass.  In exact arithmetic the iterates equal the textbook ones.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "kernels.h"
+#include "r3mg_internal.h"
+
+namespace r3mg {
+
+namespace {
+
+double sturm_max(const std::vector<double>& a, const std::vector<double>& b) {
+  const int m = (int)a.size();
+  std::vector<double> off(m, 0.0);
+  for (int i = 0; i + 1 < m; ++i) {
+    off[i] += std::fabs(b[i]);
+    off[i + 1] += std::fabs(b[i]);
+  }
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = 0; i < m; ++i) {
+    lo = std::min(lo, a[i] - off[i]);
+    hi = std::max(hi, a[i] + off[i]);
+  }
+  auto count_below = [&](double x) {
+    int cnt = 0;
+    double q = a[0] - x;
+    if (q < 0) ++cnt;
+    for (int k = 1; k < m; ++k) {
+      if (q == 0.0) q = 1e-300;
+      q = a[k] - x - b[k - 1] * b[k - 1] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200; ++it) {
+    if (hi - lo <= 1e-15 * std::max(1.0, std::fabs(hi))) break;
+    double mid = 0.5 * (lo + hi);
+    if (count_below(mid) == m)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
+int lanes_for(double avg_row) {
+  int g = 2;
+  while (g < 64 && g * 4 < avg_row) g <<= 1;
+  return g;
+}
+
+template <typename T>
+T* vbuf(DBuf<char>& b) {
+  return reinterpret_cast<T*>(b.p);
+}
+
+double host_sum(const double* dev, int cnt, hipStream_t s) {
+  std::vector<double> h(cnt);
+  R3MG_HIP_CHECK(hipMemcpyAsync(h.data(), dev, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+  R3MG_HIP_CHECK(hipStreamSynchronize(s));
+  double acc = 0;
+  for (double v : h) acc += v;
+  return acc;
+}
+
+void drop_graphs(Device& dv) {
+  for (auto& kv : dv.graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : dv.graph_defs) (void)hipGraphDestroy(kv.second);
+  dv.graphs.clear();
+  dv.graph_defs.clear();
+}
+
+}  // namespace
+
+Device::~Device() {
+  drop_graphs(*this);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  if (pinned) (void)hipHostFree(pinned);
+}
+
+struct Ctx {
+  Analysis& an;
+  Device& dv;
+  bool fp32;
+};
+
+template <typename T>
+LevelOp<T> level_op(Ctx& c, int l) {
+  DevLevel& D = c.dv.lv[l];
+  LevelOp<T> op;
+  op.n = (int)D.n;
+  op.lanes = D.lanes;
+  if (l == 0) {
+    op.blk = 1;
+    op.ptr = D.rowptr.p;
+    op.idx = D.col.p;
+  } else {
+    op.blk = c.an.B;
+    op.ptr = D.bptr.p;
+    op.idx = D.bcol.p;
+  }
+  if constexpr (sizeof(T) == 4) {
+    op.val = D.val32.p;
+    op.dinv = D.dinv32.p;
+  } else {
+    op.val = D.val64.p;
+    op.dinv = D.dinv64.p;
+  }
+  return op;
+}
+
+static void ensure_level_vectors(Ctx& c, int nr) {
+  const size_t s = c.fp32 ? sizeof(float) : sizeof(double);
+  const int L = c.an.nlevels() - 1;
+  for (int l = 0; l <= L; ++l) {
+    DevLevel& D = c.dv.lv[l];
+    if (D.vec_cap >= D.n * nr) continue;
+    const size_t bytes = (size_t)D.n * nr * s;
+    DBuf<char>* bufs[5] = {&D.b, &D.x, &D.rho, &D.dA, &D.dB};
+    for (DBuf<char>* bp : bufs) {
+      bp->alloc(bytes);
+      R3MG_HIP_CHECK(hipMemset(bp->p, 0, bytes));
+    }
+    D.vec_cap = D.n * nr;
+    drop_graphs(c.dv);
+  }
+}
+
+static void ensure_pcg_vectors(Ctx& c, int nr) {
+  Device& dv = c.dv;
+  const int64_t n = c.an.n;
+  if (dv.pcg_cap < n * nr) {
+    DBuf<double>* bufs[6] = {&dv.px, &dv.pr, &dv.pp, &dv.pq, &dv.pz, &dv.pb};
+    for (DBuf<double>* bp : bufs) {
+      bp->alloc((size_t)n * nr);
+      R3MG_HIP_CHECK(hipMemset(bp->p, 0, (size_t)n * nr * sizeof(double)));
+    }
+    dv.pcg_cap = n * nr;
+    const int64_t nlog_spmv = (n + 127) / 128 + 8;
+    const int64_t nlog_vec = (n + 255) / 256 + 8;
+    dv.partials.alloc(std::max<size_t>(4096, (size_t)std::max(nlog_spmv * nr, nlog_vec * 2 * nr) + 64));
+    drop_graphs(dv);
+  }
+  if (!dv.state.p) {
+    dv.state.alloc(sizeof(PcgState));
+    R3MG_HIP_CHECK(hipMemset(dv.state.p, 0, sizeof(PcgState)));
+  }
+  if (!dv.pinned) R3MG_HIP_CHECK(hipHostMalloc(&dv.pinned, sizeof(PcgState), hipHostMallocDefault));
+}
+
+// Chebyshev coefficients of a level: first direction scale 1/theta, then (c1, c2) of steps k = 1..K-1
+struct Cheb {
+  double inv_theta;
+  std::vector<double> c1, c2;
+};
+static Cheb cheb_coeffs(double lo, double hi, int K) {
+  Cheb ch;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  ch.inv_theta = 1.0 / theta;
+  for (int k = 1; k < K; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    ch.c1.push_back(rn * rho);
+    ch.c2.push_back(2.0 * rn / delta);
+    rho = rn;
+  }
+  return ch;
+}
+
+// ---------------------------------------------------------------------------------------------
+// V-cycle (recursive).  On entry the level's right-hand side is in lv[l].b (or b_override at level 0) and,
+// when pre_steps > 0 and l < L, lv[l].dA holds the first Chebyshev direction D^{-1} b / theta.  On return
+// x_l holds the committed iterate; the returned pointer (may be null) is a pending direction still to be
+// added to x_l by the consumer.
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipStream_t s) {
+  Analysis& an = c.an;
+  Device& dv = c.dv;
+  const int L = an.nlevels() - 1;
+  DevLevel& D = dv.lv[l];
+  T* b = b_override ? const_cast<T*>(b_override) : vbuf<T>(D.b);
+  T* x = vbuf<T>(D.x);
+  if (l == L) {
+    launch_dense_apply<T>((int)dv.nc, nr, dv.cinv.p, b, x, skip, s);
+    return nullptr;
+  }
+  const r3mg_options& o = an.opt;
+  const int K = o.cheb_degree;
+  const Cheb ch = cheb_coeffs(D.lam_lo, D.lam_hi, K);
+  LevelOp<T> op = level_op<T>(c, l);
+  T* rho = vbuf<T>(D.rho);
+  T* buf[2] = {vbuf<T>(D.dA), vbuf<T>(D.dB)};
+  bool x_zero = true, rho_is_b = true;
+  const int total_spmv = K * (o.pre_steps + o.post_steps);
+  int done_spmv = 0;
+  auto F = [&](T* u, T* dout, double c1, double c2, bool dout_on) {
+    int fl = (rho_is_b ? F_RHO_FROM_B : 0) | (x_zero ? F_X_ASSIGN : F_X_ADD);
+    ++done_spmv;
+    if (done_spmv < total_spmv) fl |= F_RHO_STORE;  // the level's last residual is never read
+    if (dout_on) fl |= F_D_OUT;
+    launch_level<T>(op, nr, u, b, rho, x, dout, c1, c2, fl, skip, s);
+    x_zero = false;
+    rho_is_b = false;
+  };
+  auto other = [&](T* p) { return p == buf[0] ? buf[1] : buf[0]; };
+
+  // pre-smoothing from x = 0
+  T* pend = nullptr;
+  for (int app = 0; app < o.pre_steps; ++app) {
+    T* u;
+    if (app == 0) {
+      u = buf[0];  // D^{-1} b / theta prepared by the caller
+    } else {
+      u = other(pend);
+      F(pend, u, 0.0, ch.inv_theta, true);
+    }
+    for (int k = 1; k < K; ++k) {
+      T* w = other(u);
+      F(u, w, ch.c1[k - 1], ch.c2[k - 1], true);
+      u = w;
+    }
+    pend = u;
+  }
+  if (pend) F(pend, nullptr, 0.0, 0.0, false);  // commit the last direction: rho = b - A x
+
+  // restriction of the residual, fused with the first direction of the next level
+  const T* src = rho_is_b ? b : rho;
+  DevLevel& N = dv.lv[l + 1];
+  const bool next_smooth = (l + 1 < L) && o.pre_steps > 0;
+  const double next_inv_theta = next_smooth ? 2.0 / (N.lam_hi + N.lam_lo) : 0.0;
+  T* dnext = next_smooth ? vbuf<T>(N.dA) : nullptr;
+  const T* dinv_next = nullptr;
+  if constexpr (sizeof(T) == 4) dinv_next = N.dinv32.p; else dinv_next = N.dinv64.p;
+  if (l == 0) {
+    const T* xi;
+    if constexpr (sizeof(T) == 4) xi = D.xi32.p; else xi = D.xi64.p;
+    launch_restrict0<T>((int)N.nbox, an.d, an.pc, nr, D.leaf_off.p, D.owner.p, xi, src, vbuf<T>(N.b), dinv_next,
+                        dnext, next_inv_theta, skip, s);
+  } else {
+    const T* pt;
+    if constexpr (sizeof(T) == 4) pt = D.pt32.p; else pt = D.pt64.p;
+    launch_restrict_c<T>((int)N.nbox, (int)D.nbox, N.child_shift, an.d, an.pc, nr, pt, src, vbuf<T>(N.b),
+                         dinv_next, dnext, next_inv_theta, skip, s);
+  }
+
+  // coarse correction
+  T* pend_c = vcycle_rec<T>(c, l + 1, nr, nullptr, skip, s);
+  T* v = buf[0];
+  if (l == 0) {
+    const T* xi;
+    if constexpr (sizeof(T) == 4) xi = D.xi32.p; else xi = D.xi64.p;
+    launch_prolong0<T>((int)D.n, an.d, an.pc, nr, D.owner.p, xi, vbuf<T>(N.x), pend_c, v, skip, s);
+  } else {
+    const T* pt;
+    if constexpr (sizeof(T) == 4) pt = D.pt32.p; else pt = D.pt64.p;
+    launch_prolong_c<T>((int)D.nbox, N.child_shift, an.d, an.pc, nr, pt, vbuf<T>(N.x), pend_c, v, skip, s);
+  }
+
+  // post-smoothing from the corrected iterate
+  if (o.post_steps == 0) {
+    launch_xupdate<T>(D.n * nr, x, v, x_zero ? 1 : 0, skip, s);
+    return nullptr;
+  }
+  T* u = v;
+  for (int app = 0; app < o.post_steps; ++app) {
+    T* w = other(u);
+    F(u, w, 0.0, ch.inv_theta, true);  // x += u, rho -= A u, first direction
+    u = w;
+    for (int k = 1; k < K; ++k) {
+      T* w2 = other(u);
+      F(u, w2, ch.c1[k - 1], ch.c2[k - 1], true);
+      u = w2;
+    }
+  }
+  return u;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Numeric set-up
+// ---------------------------------------------------------------------------------------------
+static void lanczos_level(Ctx& c, int l, hipStream_t s) {
+  Analysis& an = c.an;
+  Device& dv = c.dv;
+  DevLevel& D = dv.lv[l];
+  const int64_t n = D.n;
+  DBuf<double> v, vp, u, Av, diag;
+  v.alloc(n);
+  vp.alloc(n);
+  u.alloc(n);
+  Av.alloc(n);
+  diag.alloc(n);
+  // diag = 1 / dinv is recomputed exactly as the diagonal values by the diag kernel
+  LevelOp<double> op = level_op<double>(c, l);
+  R3MG_HIP_CHECK(hipMemsetAsync(dv.flag.p, 0, sizeof(int), s));
+  launch_diag_inv((int)n, op.blk, op.ptr, op.idx, op.val, D.dinv64.p, diag.p, dv.flag.p, s);
+  launch_lanczos_start((int)n, l == 0 ? dv.perm.p : nullptr, v.p, s);
+  R3MG_HIP_CHECK(hipMemsetAsync(vp.p, 0, n * sizeof(double), s));
+  DBuf<double>& part = dv.partials;
+  int np = launch_dot(n, diag.p, v.p, v.p, part.p, s);
+  double nrm = std::sqrt(host_sum(part.p, np, s));
+  launch_axpby(n, 1.0 / nrm, v.p, 0.0, v.p, s);
+  std::vector<double> alpha, beta;
+  double bprev = 0.0;
+  const int steps = an.opt.lanczos_steps;
+  for (int it = 0; it < steps; ++it) {
+    launch_level<double>(op, 1, v.p, nullptr, Av.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+    launch_lanczos_u(n, D.dinv64.p, Av.p, bprev, vp.p, u.p, s);
+    np = launch_dot(n, diag.p, u.p, v.p, part.p, s);
+    const double a = host_sum(part.p, np, s);
+    launch_axpby(n, -a, v.p, 1.0, u.p, s);
+    np = launch_dot(n, diag.p, u.p, u.p, part.p, s);
+    const double bb = std::sqrt(host_sum(part.p, np, s));
+    alpha.push_back(a);
+    if (!(bb > 0.0) || it + 1 == steps) break;
+    beta.push_back(bb);
+    std::swap(v.p, vp.p);             // vp <- v
+    launch_axpby(n, 1.0 / bb, u.p, 0.0, v.p, s);  // v <- u / b
+    bprev = bb;
+  }
+  D.lam_hat = sturm_max(alpha, beta);
+  D.lam_hi = an.opt.cheb_boost * D.lam_hat;
+  D.lam_lo = D.lam_hi / an.opt.cheb_ratio;
+}
+
+void numeric_setup(HandleImpl& h, hipStream_t s) {
+  Analysis& an = *h.an;
+  Device& dv = *h.dev;
+  Ctx c{an, dv, an.opt.vcycle_fp32 != 0};
+  const int L = an.nlevels() - 1;
+  const int B = an.B;
+  // Galerkin products level by level (float64)
+  for (int l = 1; l <= L; ++l) {
+    DevLevel& D = dv.lv[l];
+    const HostLevel& H = an.lv[l];
+    const int64_t nblk = H.bptr[H.nbox];
+    if (l == 1) {
+      DevLevel& F0 = dv.lv[0];
+      launch_galerkin0(nblk, an.d, an.pc, D.brow.p, D.bptr.p, D.bcol.p, F0.leaf_off.p, F0.owner.p, F0.xi64.p,
+                       F0.rowptr.p, F0.col.p, F0.val64.p, D.val64.p, s);
+    } else {
+      DevLevel& P = dv.lv[l - 1];
+      launch_galerkin_c(nblk, an.d, an.pc, H.child_shift, (int)P.nbox, D.brow.p, D.bptr.p, D.bcol.p, P.bptr.p,
+                        P.bcol.p, P.val64.p, P.pt64.p, D.val64.p, s);
+    }
+  }
+  // smoother set-up on levels 0..L-1
+  for (int l = 0; l < L; ++l) {
+    lanczos_level(c, l, s);
+    int bad = 0;
+    R3MG_HIP_CHECK(hipMemcpyAsync(&bad, dv.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    R3MG_HIP_CHECK(hipStreamSynchronize(s));
+    if (bad) throw Error{R3MG_ERR_NOT_SPD, "non-positive diagonal on level " + std::to_string(l)};
+    DevLevel& D = dv.lv[l];
+    if (c.fp32) {
+      D.val32.alloc(D.val64.n);
+      launch_cast_d2f((int64_t)D.val64.n, D.val64.p, D.val32.p, s);
+      D.dinv32.alloc(D.n);
+      launch_cast_d2f(D.n, D.dinv64.p, D.dinv32.p, s);
+    }
+  }
+  // dense coarsest
+  {
+    DevLevel& D = dv.lv[L];
+    dv.nc = D.n;
+    DBuf<double> dense;
+    dense.alloc((size_t)D.n * D.n);
+    R3MG_HIP_CHECK(hipMemsetAsync(dense.p, 0, (size_t)D.n * D.n * sizeof(double), s));
+    launch_to_dense((int)D.nbox, B, D.bptr.p, D.bcol.p, D.val64.p, dense.p, s);
+    dv.cinv.alloc((size_t)D.n * D.n);
+    R3MG_HIP_CHECK(hipMemsetAsync(dv.flag.p, 0, sizeof(int), s));
+    dense_cholesky_inverse((int)D.n, dense.p, dv.cinv.p, dv.flag.p, s);
+    int bad = 0;
+    R3MG_HIP_CHECK(hipMemcpyAsync(&bad, dv.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    R3MG_HIP_CHECK(hipStreamSynchronize(s));
+    if (bad) throw Error{R3MG_ERR_NOT_SPD, "coarsest operator is not positive definite"};
+  }
+  drop_graphs(dv);
+}
+
+void device_setup(HandleImpl& h, hipStream_t s) {
+  Analysis& an = *h.an;
+  h.dev = std::make_unique<Device>();
+  Device& dv = *h.dev;
+  R3MG_HIP_CHECK(hipGetDevice(&dv.dev));
+  const int L = an.nlevels() - 1;
+  const int B = an.B;
+  const bool fp32 = an.opt.vcycle_fp32 != 0;
+  dv.lv.resize(L + 1);
+  dv.flag.alloc(1);
+  dv.partials.alloc(4096);  // set-up reductions (at most 1024 partials); grown by the solvers
+  dv.perm.upload(an.order, s);
+  dv.src.upload(an.src, s);
+  // fine level
+  {
+    DevLevel& D = dv.lv[0];
+    D.n = an.n;
+    D.nnz = an.nnz;
+    D.rowptr.upload(an.rowptr, s);
+    D.col.upload(an.col, s);
+    D.val64.upload(an.val, s);
+    D.xi64.upload(an.xi, s);
+    D.owner.upload(an.owner, s);
+    std::vector<int32_t> lo(an.leaf_off.begin(), an.leaf_off.end());
+    D.leaf_off.upload(lo, s);
+    D.lanes = lanes_for((double)an.nnz / (double)an.n);
+    D.dinv64.alloc(D.n);
+    if (fp32) {
+      D.xi32.alloc(D.xi64.n);
+      launch_cast_d2f((int64_t)D.xi64.n, D.xi64.p, D.xi32.p, s);
+    }
+    const double sv = fp32 ? 4 : 8;
+    D.bytes_apply = (double)an.nnz * (sv + 4) + (double)(an.n + 1) * 4 + 7.0 * an.n * sv;
+  }
+  for (int l = 1; l <= L; ++l) {
+    DevLevel& D = dv.lv[l];
+    const HostLevel& H = an.lv[l];
+    D.n = H.n;
+    D.nbox = H.nbox;
+    const int64_t nblk = H.bptr[H.nbox];
+    D.nnz = nblk * B * B;
+    std::vector<int32_t> bp(H.bptr.begin(), H.bptr.end());
+    D.bptr.upload(bp, s);
+    D.bcol.upload(H.bcol, s);
+    std::vector<int32_t> br(nblk);
+    for (int64_t k = 0; k < H.nbox; ++k)
+      for (int64_t j = H.bptr[k]; j < H.bptr[k + 1]; ++j) br[j] = (int32_t)k;
+    D.brow.upload(br, s);
+    D.val64.alloc((size_t)D.nnz);
+    D.dinv64.alloc(D.n);
+    D.child_shift = H.child_shift;
+    if (!H.pt1d.empty()) {
+      D.pt64.upload(H.pt1d, s);
+      if (fp32) {
+        D.pt32.alloc(D.pt64.n);
+        launch_cast_d2f((int64_t)D.pt64.n, D.pt64.p, D.pt32.p, s);
+      }
+    }
+    D.lanes = lanes_for((double)(D.nnz) / (double)std::max<int64_t>(1, D.n));
+    const double sv = fp32 ? 4 : 8;
+    D.bytes_apply = (double)D.nnz * sv + (double)nblk * 4 + (double)(H.nbox + 1) * 4 + 7.0 * D.n * sv;
+  }
+  numeric_setup(h, s);
+  R3MG_HIP_CHECK(hipStreamSynchronize(s));
+}
+
+void update_values(HandleImpl& h, const double* vals_dev, hipStream_t s) {
+  Device& dv = *h.dev;
+  launch_gather_vals(h.an->nnz, dv.src.p, vals_dev, dv.lv[0].val64.p, s);
+  numeric_setup(h, s);
+  R3MG_HIP_CHECK(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------------------------
+// Public operations
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+static void vcycle_api_t(HandleImpl& h, const double* r, double* z, int nrhs, hipStream_t s) {
+  Analysis& an = *h.an;
+  Device& dv = *h.dev;
+  Ctx c{an, dv, sizeof(T) == 4};
+  const int L = an.nlevels() - 1;
+  for (int c0 = 0; c0 < nrhs; c0 += kMaxNR) {
+    const int nb = std::min(kMaxNR, nrhs - c0);
+    int NR = 1;
+    while (NR < nb) NR <<= 1;
+    ensure_level_vectors(c, NR);
+    DevLevel& D0 = dv.lv[0];
+    T* b0 = vbuf<T>(D0.b);
+    const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
+    const T* dinv0;
+    if constexpr (sizeof(T) == 4) dinv0 = D0.dinv32.p; else dinv0 = D0.dinv64.p;
+    if (NR == nb) {
+      launch_vc_entry<T>((int)an.n, NR, dv.perm.p, r + (int64_t)c0 * an.n, an.n, b0, dinv0,
+                         smooth0 ? vbuf<T>(D0.dA) : nullptr, 2.0 / (D0.lam_hi + D0.lam_lo), s);
+    } else {
+      // gather into float64 scratch with zero padding, then convert
+      ensure_pcg_vectors(c, NR);
+      launch_gather_cols((int)an.n, NR, nb, dv.perm.p, r + (int64_t)c0 * an.n, an.n, dv.pb.p, s);
+      launch_vc_prep<T>((int)an.n, NR, dv.pb.p, b0, dinv0, smooth0 ? vbuf<T>(D0.dA) : nullptr,
+                        2.0 / (D0.lam_hi + D0.lam_lo), nullptr, s);
+    }
+    T* pend = (L == 0) ? nullptr : vcycle_rec<T>(c, 0, NR, nullptr, nullptr, s);
+    if (NR == nb) {
+      launch_vc_exit<T>((int)an.n, NR, dv.perm.p, vbuf<T>(D0.x), pend, z + (int64_t)c0 * an.n, an.n, s);
+    } else {
+      // x0 + pend -> pz (float64 interleaved) -> scatter the real columns
+      ensure_pcg_vectors(c, NR);
+      PcgState* st = reinterpret_cast<PcgState*>(dv.state.p);
+      R3MG_HIP_CHECK(hipMemsetAsync(dv.state.p, 0, sizeof(PcgState), s));
+      launch_pcg_z<T>((int)an.n, NR, st, vbuf<T>(D0.x), pend, dv.pz.p, dv.pz.p, nullptr, dv.partials.p, s);
+      launch_scatter_cols((int)an.n, NR, nb, dv.perm.p, dv.pz.p, z + (int64_t)c0 * an.n, an.n, s);
+    }
+  }
+}
+
+void vcycle_api(HandleImpl& h, const double* r, double* z, int nrhs, hipStream_t s) {
+  if (h.an->opt.vcycle_fp32)
+    vcycle_api_t<float>(h, r, z, nrhs, s);
+  else
+    vcycle_api_t<double>(h, r, z, nrhs, s);
+}
+
+void level_apply(HandleImpl& h, int level, const double* x, double* y, hipStream_t s) {
+  Analysis& an = *h.an;
+  Device& dv = *h.dev;
+  Ctx c{an, dv, false};
+  const int l = level < 0 ? 0 : level;
+  LevelOp<double> op = level_op<double>(c, l);
+  if (l == 0) {
+    ensure_pcg_vectors(c, 1);
+    launch_gather_cols((int)an.n, 1, 1, dv.perm.p, x, an.n, dv.pb.p, s);
+    launch_level<double>(op, 1, dv.pb.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+    launch_scatter_cols((int)an.n, 1, 1, dv.perm.p, dv.pq.p, y, an.n, s);
+  } else {
+    launch_level<double>(op, 1, x, nullptr, y, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+  }
+}
+
+// one PCG iteration (all launches skip once every column has converged)
+template <typename T>
+static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
+  Analysis& an = c.an;
+  Device& dv = c.dv;
+  const int L = an.nlevels() - 1;
+  PcgState* st = reinterpret_cast<PcgState*>(dv.state.p);
+  const int* skip = reinterpret_cast<const int*>(dv.state.p);
+  DevLevel& D0 = dv.lv[0];
+  LevelOp<double> op64 = level_op<double>(c, 0);
+  const int n = (int)an.n;
+  int np = launch_spmv_dot(op64, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+  const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
+  const T* dinv0;
+  if constexpr (sizeof(T) == 4) dinv0 = D0.dinv32.p; else dinv0 = D0.dinv64.p;
+  T* b0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : nullptr;
+  launch_pcg_xr<T>(n, NR, st, dv.partials.p, np, dv.px.p, dv.pr.p, dv.pp.p, dv.pq.p, dv.partials.p, b0, dinv0,
+                   smooth0 ? vbuf<T>(D0.dA) : nullptr, 2.0 / (D0.lam_hi + D0.lam_lo), s);
+  const int nv = (n + 255) / 256;
+  launch_pcg_check(NR, st, dv.partials.p, nv, s);
+  const T* bl0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : reinterpret_cast<const T*>(dv.pr.p);
+  T* pend = nullptr;
+  if (L > 0) {
+    pend = vcycle_rec<T>(c, 0, NR, bl0, skip, s);
+  }
+  const T* x0 = (L > 0) ? vbuf<T>(D0.x) : bl0;
+  launch_pcg_z<T>(n, NR, st, x0, pend, dv.pz.p, dv.pr.p, flexible ? dv.pq.p : nullptr, dv.partials.p, s);
+  launch_pcg_beta(NR, st, dv.partials.p, nv, s);
+  launch_pcg_p(n, NR, st, dv.pz.p, dv.pp.p, s);
+}
+
+template <typename T>
+static void pcg_start(Ctx& c, int NR, double rtol, bool flexible, hipStream_t s) {
+  Analysis& an = c.an;
+  Device& dv = c.dv;
+  const int L = an.nlevels() - 1;
+  const int n = (int)an.n;
+  PcgState* st = reinterpret_cast<PcgState*>(dv.state.p);
+  const int* skip = reinterpret_cast<const int*>(dv.state.p);
+  DevLevel& D0 = dv.lv[0];
+  LevelOp<double> op64 = level_op<double>(c, 0);
+  // r = b - A x0
+  launch_level<double>(op64, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+  int np = launch_residual(n, NR, dv.pb.p, dv.pq.p, dv.pr.p, dv.partials.p, s);
+  launch_pcg_init(NR, st, dv.partials.p, np, rtol, flexible ? 1 : 0, s);
+  // z = B r; p = z; gamma = <r, z>
+  const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
+  const T* dinv0;
+  if constexpr (sizeof(T) == 4) dinv0 = D0.dinv32.p; else dinv0 = D0.dinv64.p;
+  T* b0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : nullptr;
+  launch_vc_prep<T>(n, NR, dv.pr.p, b0, dinv0, smooth0 ? vbuf<T>(D0.dA) : nullptr, 2.0 / (D0.lam_hi + D0.lam_lo),
+                    skip, s);
+  const T* bl0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : reinterpret_cast<const T*>(dv.pr.p);
+  T* pend = nullptr;
+  if (L > 0) pend = vcycle_rec<T>(c, 0, NR, bl0, skip, s);
+  const T* x0 = (L > 0) ? vbuf<T>(D0.x) : bl0;
+  launch_pcg_z<T>(n, NR, st, x0, pend, dv.pz.p, dv.pr.p, nullptr, dv.partials.p, s);
+  launch_pcg_init_gamma(n, NR, st, dv.partials.p, (n + 255) / 256, dv.pz.p, dv.pp.p, s);
+}
+
+static PcgState read_state(Device& dv, hipStream_t s) {
+  R3MG_HIP_CHECK(hipMemcpyAsync(dv.pinned, dv.state.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+  R3MG_HIP_CHECK(hipStreamSynchronize(s));
+  PcgState st;
+  std::memcpy(&st, dv.pinned, sizeof(PcgState));
+  return st;
+}
+
+static int read_all_done(Device& dv, hipStream_t s) {
+  R3MG_HIP_CHECK(hipMemcpyAsync(dv.pinned, dv.state.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  R3MG_HIP_CHECK(hipStreamSynchronize(s));
+  int v;
+  std::memcpy(&v, dv.pinned, sizeof(int));
+  return v;
+}
+
+template <typename T>
+static hipGraphExec_t iteration_graph(Ctx& c, int NR, bool flexible) {
+  Device& dv = c.dv;
+  const int key = NR * 2 + (flexible ? 1 : 0);
+  auto it = dv.graphs.find(key);
+  if (it != dv.graphs.end()) return it->second;
+  if (!dv.cap_stream) R3MG_HIP_CHECK(hipStreamCreateWithFlags(&dv.cap_stream, hipStreamNonBlocking));
+  hipGraph_t g;
+  R3MG_HIP_CHECK(hipStreamBeginCapture(dv.cap_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    pcg_iteration<T>(c, NR, flexible, dv.cap_stream);
+  } catch (...) {
+    (void)hipStreamEndCapture(dv.cap_stream, &g);
+    throw;
+  }
+  R3MG_HIP_CHECK(hipStreamEndCapture(dv.cap_stream, &g));
+  hipGraphExec_t ex;
+  R3MG_HIP_CHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+  dv.graphs[key] = ex;
+  dv.graph_defs[key] = g;
+  return ex;
+}
+
+template <typename T>
+static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, int nb, double rtol, int maxit,
+                             hipStream_t s, int* iters, double* relres) {
+  Analysis& an = *h.an;
+  Device& dv = *h.dev;
+  Ctx c{an, dv, sizeof(T) == 4};
+  int NR = 1;
+  while (NR < nb) NR <<= 1;
+  ensure_level_vectors(c, NR);
+  ensure_pcg_vectors(c, NR);
+  const int n = (int)an.n;
+  const bool flexible = sizeof(T) == 4;
+  launch_gather_cols(n, NR, nb, dv.perm.p, b + (int64_t)c0 * n, n, dv.pb.p, s);
+  launch_gather_cols(n, NR, nb, dv.perm.p, x + (int64_t)c0 * n, n, dv.px.p, s);
+  int restarts = 0;
+  pcg_start<T>(c, NR, rtol, flexible, s);
+  hipGraphExec_t ex = nullptr;
+  if (an.opt.use_graph) ex = iteration_graph<T>(c, NR, flexible);
+  int k = 0;
+  bool done = read_all_done(dv, s) != 0;
+  for (;;) {
+    while (!done && k < maxit) {
+      if (ex)
+        R3MG_HIP_CHECK(hipGraphLaunch(ex, s));
+      else
+        pcg_iteration<T>(c, NR, flexible, s);
+      ++k;
+      done = read_all_done(dv, s) != 0;
+    }
+    if (!flexible || restarts >= 2) break;
+    // residual replacement (float32 V-cycle): confirm the recursive residual with the true one
+    PcgState st = read_state(dv, s);
+    LevelOp<double> op64 = level_op<double>(c, 0);
+    launch_level<double>(op64, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+    int np = launch_residual(n, NR, dv.pb.p, dv.pq.p, dv.pz.p, dv.partials.p, s);
+    std::vector<double> part((size_t)np * NR);
+    R3MG_HIP_CHECK(hipMemcpyAsync(part.data(), dv.partials.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    R3MG_HIP_CHECK(hipStreamSynchronize(s));
+    bool all_ok = true;
+    for (int j = 0; j < nb; ++j) {
+      double rr = 0;
+      for (int p = 0; p < np; ++p) rr += part[(size_t)p * NR + j];
+      if (st.done[j] && rr > st.tau2[j]) all_ok = false;
+    }
+    if (all_ok || k >= maxit) break;
+    // restart from the true residual for every column (converged ones stay converged: their r is small)
+    ++restarts;
+    std::vector<int> iters_keep(st.iters, st.iters + kMaxNR);
+    pcg_start<T>(c, NR, 0.0, flexible, s);  // tau2 restored below
+    PcgState st2 = read_state(dv, s);
+    for (int j = 0; j < NR; ++j) {
+      st2.tau2[j] = st.tau2[j];
+      st2.rr0[j] = st.rr0[j];
+      st2.iters[j] = iters_keep[j];
+      st2.done[j] = (j >= nb) ? 1 : (st2.rr[j] <= st.tau2[j]);
+    }
+    int all = 1;
+    for (int j = 0; j < NR; ++j) all &= st2.done[j];
+    st2.all_done = all;
+    R3MG_HIP_CHECK(hipMemcpyAsync(dv.state.p, &st2, sizeof(PcgState), hipMemcpyHostToDevice, s));
+    R3MG_HIP_CHECK(hipStreamSynchronize(s));
+    done = all != 0;
+  }
+  PcgState st = read_state(dv, s);
+  launch_scatter_cols(n, NR, nb, dv.perm.p, dv.px.p, x + (int64_t)c0 * n, n, s);
+  R3MG_HIP_CHECK(hipStreamSynchronize(s));
+  bool conv = true;
+  for (int j = 0; j < nb; ++j) {
+    if (iters) iters[c0 + j] = st.iters[j];
+    if (relres) relres[c0 + j] = st.rr0[j] > 0 ? std::sqrt(st.rr[j] / st.rr0[j]) : 0.0;
+    conv &= st.done[j] != 0;
+  }
+  return conv ? R3MG_OK : R3MG_NOT_CONVERGED;
+}
+
+r3mg_status pcg_solve(HandleImpl& h, const double* b, double* x, int nrhs, double rtol, int maxit, hipStream_t s,
+                      int* iters, double* relres) {
+  r3mg_status res = R3MG_OK;
+  for (int c0 = 0; c0 < nrhs; c0 += kMaxNR) {
+    const int nb = std::min(kMaxNR, nrhs - c0);
+    r3mg_status r = h.an->opt.vcycle_fp32 ? pcg_block<float>(h, b, x, c0, nb, rtol, maxit, s, iters, relres)
+                                          : pcg_block<double>(h, b, x, c0, nb, rtol, maxit, s, iters, relres);
+    if (r != R3MG_OK) res = r;
+  }
+  return res;
+}
+
+// Several problems in one launch sequence: their iterations are captured into one hipGraph with one branch per
+// problem, replayed until every problem has converged.
+r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double* const* x, double rtol, int maxit,
+                      hipStream_t s, int* iters, double* relres) {
+  std::vector<hipStream_t> br(count);
+  for (int k = 0; k < count; ++k) R3MG_HIP_CHECK(hipStreamCreateWithFlags(&br[k], hipStreamNonBlocking));
+  hipStream_t cap;
+  R3MG_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  std::vector<hipEvent_t> evs;
+  auto cleanup = [&]() {
+    if (ex) (void)hipGraphExecDestroy(ex);
+    if (g) (void)hipGraphDestroy(g);
+    for (auto e : evs) (void)hipEventDestroy(e);
+    for (auto q : br) (void)hipStreamDestroy(q);
+    (void)hipStreamDestroy(cap);
+  };
+  try {
+    // set-up of every problem (plain launches on s)
+    for (int k = 0; k < count; ++k) {
+      HandleImpl& h = *hs[k];
+      Ctx c{*h.an, *h.dev, h.an->opt.vcycle_fp32 != 0};
+      ensure_level_vectors(c, 1);
+      ensure_pcg_vectors(c, 1);
+      const int n = (int)h.an->n;
+      launch_gather_cols(n, 1, 1, h.dev->perm.p, b[k], n, h.dev->pb.p, s);
+      launch_gather_cols(n, 1, 1, h.dev->perm.p, x[k], n, h.dev->px.p, s);
+      if (c.fp32)
+        pcg_start<float>(c, 1, rtol, true, s);
+      else
+        pcg_start<double>(c, 1, rtol, false, s);
+    }
+    R3MG_HIP_CHECK(hipStreamSynchronize(s));
+    // capture one iteration of every problem, each on its own branch
+    hipEvent_t fork;
+    R3MG_HIP_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    evs.push_back(fork);
+    R3MG_HIP_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    R3MG_HIP_CHECK(hipEventRecord(fork, cap));
+    for (int k = 0; k < count; ++k) {
+      HandleImpl& h = *hs[k];
+      Ctx c{*h.an, *h.dev, h.an->opt.vcycle_fp32 != 0};
+      R3MG_HIP_CHECK(hipStreamWaitEvent(br[k], fork, 0));
+      if (c.fp32)
+        pcg_iteration<float>(c, 1, true, br[k]);
+      else
+        pcg_iteration<double>(c, 1, false, br[k]);
+      hipEvent_t j;
+      R3MG_HIP_CHECK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
+      evs.push_back(j);
+      R3MG_HIP_CHECK(hipEventRecord(j, br[k]));
+      R3MG_HIP_CHECK(hipStreamWaitEvent(cap, j, 0));
+    }
+    R3MG_HIP_CHECK(hipStreamEndCapture(cap, &g));
+    R3MG_HIP_CHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    int it = 0;
+    for (;;) {
+      bool all = true;
+      for (int k = 0; k < count; ++k) all &= read_all_done(*hs[k]->dev, s) != 0;
+      if (all || it >= maxit) break;
+      R3MG_HIP_CHECK(hipGraphLaunch(ex, s));
+      ++it;
+    }
+    r3mg_status res = R3MG_OK;
+    for (int k = 0; k < count; ++k) {
+      HandleImpl& h = *hs[k];
+      PcgState st = read_state(*h.dev, s);
+      const int n = (int)h.an->n;
+      launch_scatter_cols(n, 1, 1, h.dev->perm.p, h.dev->px.p, x[k], n, s);
+      if (iters) iters[k] = st.iters[0];
+      if (relres) relres[k] = st.rr0[0] > 0 ? std::sqrt(st.rr[0] / st.rr0[0]) : 0.0;
+      if (!st.done[0]) res = R3MG_NOT_CONVERGED;
+    }
+    R3MG_HIP_CHECK(hipStreamSynchronize(s));
+    cleanup();
+    return res;
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+}
+
+void time_smoother_kernel(HandleImpl& h, int level, int reps, hipStream_t s, double* ms, double* bytes) {
+  Analysis& an = *h.an;
+  Device& dv = *h.dev;
+  Ctx c{an, dv, an.opt.vcycle_fp32 != 0};
+  ensure_level_vectors(c, 1);
+  DevLevel& D = dv.lv[level];
+  hipEvent_t e0, e1;
+  R3MG_HIP_CHECK(hipEventCreate(&e0));
+  R3MG_HIP_CHECK(hipEventCreate(&e1));
+  const int fl = F_RHO_STORE | F_X_ADD | F_D_OUT;
+  auto run = [&](int count) {
+    for (int r = 0; r < count; ++r) {
+      if (c.fp32) {
+        LevelOp<float> op = level_op<float>(c, level);
+        float* u = vbuf<float>((r & 1) ? D.dB : D.dA);
+        float* w = vbuf<float>((r & 1) ? D.dA : D.dB);
+        launch_level<float>(op, 1, u, vbuf<float>(D.b), vbuf<float>(D.rho), vbuf<float>(D.x), w, 0.0, 0.0, fl,
+                            nullptr, s);
+      } else {
+        LevelOp<double> op = level_op<double>(c, level);
+        double* u = vbuf<double>((r & 1) ? D.dB : D.dA);
+        double* w = vbuf<double>((r & 1) ? D.dA : D.dB);
+        launch_level<double>(op, 1, u, vbuf<double>(D.b), vbuf<double>(D.rho), vbuf<double>(D.x), w, 0.0, 0.0, fl,
+                             nullptr, s);
+      }
+    }
+  };
+  run(3);
+  R3MG_HIP_CHECK(hipEventRecord(e0, s));
+  run(reps);
+  R3MG_HIP_CHECK(hipEventRecord(e1, s));
+  R3MG_HIP_CHECK(hipEventSynchronize(e1));
+  float t = 0;
+  R3MG_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = (double)t / reps;
+  *bytes = D.bytes_apply;
+}
+
+}  // namespace r3mg

@@ -1,0 +1,256 @@
+"""GPU parity of the HIP path against the FP64 oracle (operators, Galerkin products, V-cycle, PCG).
+
+Tolerances: the Galerkin operators and the float64 V-cycle are the same arithmetic up to summation order, so
+they agree to a few ulps times the depth of the recursion (1e-12 relative); PCG iterates agree to the stop
+rule (iterations within 1, solutions to 1e-9 relative against the oracle solved to 1e-13).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import fixtures as F
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _case(name):
+    print(f"[gpu-case] {name}", flush=True)
+    sys.stdout.flush()
+
+
+def _P():
+    import paper_2607_28235_amd as P
+    return P
+
+
+class Case:
+    def __init__(self, prob, b, pc, leaf, max_levels, pre, post, fp32=False, max_coarse=2000):
+        P = _P()
+        self.prob, self.b = prob, b
+        self.opts = P.Options(dim=prob.d, coarse_degree=pc, leaf_size=leaf, max_levels=max_levels,
+                              max_coarse_dofs=max_coarse, pre_steps=pre, post_steps=post, vcycle_fp32=int(fp32))
+        self.h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, self.opts)
+        self.ho = O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=pc, leaf_size=leaf,
+                                    max_levels=max_levels, max_coarse_dofs=max_coarse, pre_steps=pre,
+                                    post_steps=post)
+
+
+def _t(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    _need_gpu()
+    _case("cfg1 setup (2D Q2 16x16, p'=1, leaf 64, 2 levels, V(1,1))")
+    w = F.workload(1)
+    return Case(w.problem, w.rhs, 1, 64, 2, 1, 1)
+
+
+@pytest.fixture(scope="module")
+def small2d():
+    _need_gpu()
+    _case("small2d setup (2D Q3 48x48 jittered, p'=2, leaf 128, 4 levels, V(2,2))")
+    prob = F.structured_qp(2, 48, 3, jitter=0.2, cfg=2)
+    b = F.nodal_rhs(prob, F.rng(2, F.PURPOSE_RHS).standard_normal(prob.n), jitter=0.2, cfg=2)
+    return Case(prob, b, 2, 128, 4, 2, 2, max_coarse=100)
+
+
+@pytest.fixture(scope="module")
+def small3d():
+    _need_gpu()
+    _case("small3d setup (3D Q2 12^3, p'=2, leaf 256, V(2,2))")
+    prob = F.structured_qp(3, 12, 2, cfg=3)
+    b = F.nodal_rhs(prob, F.rng(3, F.PURPOSE_RHS).standard_normal(prob.n), cfg=3)
+    return Case(prob, b, 2, 256, 0, 2, 2, max_coarse=300)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small2d", "small3d"])
+def test_level_operators_match_oracle(name, request):
+    c = request.getfixturevalue(name)
+    _case(f"level operators {name}")
+    g = np.random.default_rng(0)
+    x = g.standard_normal(c.prob.n)
+    y = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    c.h.level_apply(0, _t(x), y)
+    torch.cuda.synchronize()
+    assert _rel(y.cpu().numpy(), c.prob.scipy() @ x) < 1e-14
+    for l in range(1, len(c.ho.levels)):
+        rp, cl, vl = c.h.export_level(l)
+        import scipy.sparse as sp
+        A = sp.csr_matrix((vl, cl, rp), shape=(len(rp) - 1, len(rp) - 1)).toarray()
+        ref = c.ho.levels[l].A.toarray()
+        err = np.abs(A - ref).max() / np.abs(ref).max()
+        assert err < 1e-13, (l, err)
+        xl = g.standard_normal(A.shape[0])
+        yl = torch.zeros(A.shape[0], dtype=torch.float64, device="cuda")
+        c.h.level_apply(l, _t(xl), yl)
+        torch.cuda.synchronize()
+        assert _rel(yl.cpu().numpy(), ref @ xl) < 1e-13
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small2d", "small3d"])
+def test_chebyshev_bounds_match_oracle(name, request):
+    c = request.getfixturevalue(name)
+    _case(f"lanczos {name}")
+    info = c.h.info()
+    for l, lv in enumerate(c.ho.levels[:-1]):
+        assert abs(info[l]["lambda_hi"] - lv.lam_hi) <= 1e-10 * lv.lam_hi, (l, info[l]["lambda_hi"], lv.lam_hi)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small2d", "small3d"])
+def test_vcycle_matches_oracle_fp64(name, request):
+    c = request.getfixturevalue(name)
+    _case(f"vcycle fp64 {name}")
+    g = np.random.default_rng(1)
+    for _ in range(2):
+        r = g.standard_normal(c.prob.n)
+        r[c.ho.constrained] = 0.0
+        z = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+        c.h.vcycle(_t(r), z)
+        torch.cuda.synchronize()
+        zo = O.vcycle(c.ho, r)
+        assert _rel(z.cpu().numpy(), zo) < 1e-11
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small2d", "small3d"])
+def test_vcycle_symmetric_positive_on_gpu(name, request):
+    c = request.getfixturevalue(name)
+    _case(f"vcycle symmetry {name}")
+    g = np.random.default_rng(2)
+    x, y = g.standard_normal(c.prob.n), g.standard_normal(c.prob.n)
+    zx = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    zy = torch.zeros_like(zx)
+    c.h.vcycle(_t(x), zx)
+    c.h.vcycle(_t(y), zy)
+    torch.cuda.synchronize()
+    bx, by = zx.cpu().numpy(), zy.cpu().numpy()
+    assert abs(bx @ y - x @ by) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(y)
+    assert bx @ x > 0
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small2d", "small3d"])
+def test_pcg_matches_oracle(name, request):
+    c = request.getfixturevalue(name)
+    _case(f"pcg fp64 {name}")
+    xo, ko, conv, _, _ = O.pcg(c.ho, c.b, rtol=1e-10)
+    x_tight = O.pcg(c.ho, c.b, rtol=1e-13)[0]
+    x = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok = c.h.pcg(_t(c.b), x, rtol=1e-10, maxit=200)
+    xs = x.cpu().numpy()
+    assert ok and conv
+    assert abs(int(iters[0]) - ko) <= 1, (iters, ko)
+    assert relres[0] <= 1e-10
+    assert _rel(xs, xo) < 1e-9
+    assert _rel(xs, x_tight) < 1e-8
+    r = c.b - c.prob.scipy() @ xs
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(c.b)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small2d", "small3d"])
+def test_pcg_fp32_vcycle(name, request):
+    c = request.getfixturevalue(name)
+    _case(f"pcg fp32 {name}")
+    P = _P()
+    import dataclasses
+    o = dataclasses.replace(c.opts, vcycle_fp32=1)
+    h32 = P.Hierarchy(c.prob.coords, c.prob.row_ptr, c.prob.col, c.prob.val, o)
+    xo, ko, _, _, _ = O.pcg(c.ho, c.b, rtol=1e-10)
+    x_tight = O.pcg(c.ho, c.b, rtol=1e-13)[0]
+    x = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok = h32.pcg(_t(c.b), x, rtol=1e-10, maxit=200)
+    xs = x.cpu().numpy()
+    assert ok
+    assert abs(int(iters[0]) - ko) <= 1, (iters, ko)
+    r = c.b - c.prob.scipy() @ xs
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(c.b)     # true residual (residual replacement)
+    assert _rel(xs, x_tight) < 1e-8
+
+
+def test_multi_rhs_matches_single(small2d):
+    c = small2d
+    _case("multi-rhs 3 columns small2d")
+    g = np.random.default_rng(5)
+    B = np.stack([c.b, g.standard_normal(c.prob.n), np.zeros(c.prob.n)])
+    B[1, c.ho.constrained] = 0.0
+    X = torch.zeros(3, c.prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok = c.h.pcg(_t(B), X, rtol=1e-10, maxit=200)
+    assert ok and iters[2] == 0
+    for j in range(2):
+        x1 = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+        it1, _, _ = c.h.pcg(_t(B[j]), x1, rtol=1e-10, maxit=200)
+        assert abs(int(it1[0]) - int(iters[j])) <= 1
+        assert _rel(X[j].cpu().numpy(), x1.cpu().numpy()) < 1e-9
+    assert np.all(X[2].cpu().numpy() == 0.0)
+
+
+def test_group_solve_matches_individual(cfg1, small2d, small3d):
+    _case("group solve of three problems")
+    P = _P()
+    cases = [cfg1, small2d, small3d]
+    bs = [_t(c.b) for c in cases]
+    xs = [torch.zeros(c.prob.n, dtype=torch.float64, device="cuda") for c in cases]
+    iters, relres, ok = P.solve_group([c.h for c in cases], bs, xs, rtol=1e-10, maxit=200)
+    assert ok
+    for c, x, it in zip(cases, xs, iters):
+        x1 = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+        it1, _, _ = c.h.pcg(_t(c.b), x1, rtol=1e-10, maxit=200)
+        assert int(it) == int(it1[0])
+        assert _rel(x.cpu().numpy(), x1.cpu().numpy()) < 1e-12
+
+
+def test_edge_cases(small2d):
+    c = small2d
+    _case("edge cases small2d")
+    x = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok = c.h.pcg(torch.zeros_like(x), x, rtol=1e-10)
+    assert ok and iters[0] == 0 and float(x.abs().max()) == 0.0
+    x = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok = c.h.pcg(_t(c.b), x, rtol=1e-10, maxit=2)
+    assert not ok and iters[0] == 2
+    # non-zero initial guess: converge relative to the initial residual
+    x0 = np.random.default_rng(9).standard_normal(c.prob.n)
+    x0[c.ho.constrained] = 0.0
+    x = _t(x0)
+    iters, relres, ok = c.h.pcg(_t(c.b), x, rtol=1e-10, maxit=200)
+    xo, ko, _, _, _ = O.pcg(c.ho, c.b, x0, rtol=1e-10)
+    assert ok and abs(int(iters[0]) - ko) <= 1
+    assert _rel(x.cpu().numpy(), xo) < 1e-9
+
+
+def test_repeated_solves_are_bitwise_identical(small3d):
+    c = small3d
+    _case("determinism small3d")
+    outs = []
+    for _ in range(2):
+        x = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+        c.h.pcg(_t(c.b), x, rtol=1e-10)
+        outs.append(x.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_graph_and_eager_paths_agree(small2d):
+    c = small2d
+    _case("graph vs eager small2d")
+    P = _P()
+    import dataclasses
+    h_e = P.Hierarchy(c.prob.coords, c.prob.row_ptr, c.prob.col, c.prob.val, dataclasses.replace(c.opts, use_graph=0))
+    res = []
+    for h in (c.h, h_e, c.h):
+        x = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+        it, _, _ = h.pcg(_t(c.b), x, rtol=1e-10)
+        res.append((int(it[0]), x.cpu().numpy()))
+    assert res[0][0] == res[1][0] == res[2][0]
+    assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][1], res[2][1])

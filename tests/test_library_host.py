@@ -1,0 +1,170 @@
+"""Host-side checks of the HIP library (no GPU needed): the C ABI loads and exports every declared symbol, and
+the host analysis (R-tree partition, level selection, transfer sparsity and values) agrees with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import fixtures as F
+import oracle as O
+
+P = pytest.importorskip("paper_2607_28235_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_skip():
+    try:
+        return P.lib()
+    except ImportError as e:  # the build step runs before the test-suite
+        pytest.fail(str(e))
+
+
+def test_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    hdr = open(os.path.join(ROOT, "include", "r3mg.h")).read()
+    names = set(re.findall(r"\b(r3mg_[A-Za-z_]+)\s*\(", hdr))
+    assert len(names) >= 20
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(P.EXPORTED) == names
+
+
+def test_status_strings():
+    L = _lib_or_skip()
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert L.r3mg_status_string(code)
+
+
+@pytest.mark.parametrize("seed,n,d,leaf", [(0, 37, 2, 4), (1, 500, 3, 7), (2, 1000, 2, 16), (3, 3000, 3, 50)])
+def test_rtree_bit_exact_with_ties(seed, n, d, leaf):
+    g = np.random.default_rng(seed)
+    coords = g.integers(0, 6, size=(n, d)).astype(np.float64) / 5.0
+    coords[-5:] = coords[:5]
+    t = O.bisection_rtree(coords, leaf)
+    depth, order = P.rtree(coords, leaf)
+    assert depth == t.depth
+    np.testing.assert_array_equal(order, t.order)
+
+
+def _opts(w, d):
+    return P.Options(dim=d, coarse_degree=w.coarse_degree, leaf_size=w.leaf_size, max_levels=w.max_levels,
+                     max_coarse_dofs=w.max_coarse_dofs, pre_steps=w.pre_steps, post_steps=w.post_steps)
+
+
+def _compare_analysis(prob, pc, leaf, max_levels=0, max_coarse=2000, skip=False):
+    d = prob.d
+    h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val,
+                    P.Options(dim=d, coarse_degree=pc, leaf_size=leaf, max_levels=max_levels,
+                              max_coarse_dofs=max_coarse, skip_leaf_level=int(skip)), factor=False)
+    ho = O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=pc, leaf_size=leaf, max_levels=max_levels,
+                           max_coarse_dofs=max_coarse, skip_leaf_level=skip)
+    info = h.info()
+    assert len(info) == len(ho.levels)
+    for l, lv in enumerate(ho.levels):
+        assert info[l]["n"] == lv.A.shape[0]
+    for l in range(1, len(ho.levels)):
+        own, lo, hi = h.export_partition(l)
+        np.testing.assert_array_equal(own, ho.tree.owner(ho.levels[l].depth))
+        np.testing.assert_array_equal(lo, ho.levels[l].lo)
+        np.testing.assert_array_equal(hi, ho.levels[l].hi)
+        assert info[l]["nnz"] == (len(ho.levels[l].block_col) * ho.B * ho.B)
+    for l in range(len(ho.levels) - 1):
+        rp, cl, vl = h.export_P(l)
+        lv = ho.levels[l]
+        np.testing.assert_array_equal(rp, lv.P_indptr)          # sparsity: bit-exact
+        np.testing.assert_array_equal(cl, lv.P_indices)
+        np.testing.assert_allclose(vl, lv.P_data, rtol=0, atol=1e-15)
+    h.close()
+
+
+def test_analysis_matches_oracle_cfg1():
+    w = F.workload(1)
+    _compare_analysis(w.problem, 1, 64, max_levels=2)
+
+
+@pytest.mark.parametrize("pc,leaf,ml", [(0, 24, 0), (1, 40, 0), (2, 128, 4), (3, 200, 3)])
+def test_analysis_matches_oracle_2d_jittered(pc, leaf, ml):
+    prob = F.structured_qp(2, 40, 3, jitter=0.2, cfg=2)
+    _compare_analysis(prob, pc, leaf, max_levels=ml, max_coarse=200)
+
+
+def test_analysis_matches_oracle_3d():
+    prob = F.structured_qp(3, 12, 2, cfg=3)
+    _compare_analysis(prob, 2, 256, max_coarse=300)
+    _compare_analysis(prob, 1, 64, max_coarse=100, skip=True)
+
+
+@pytest.mark.slow
+def test_analysis_matches_oracle_full_2d_q3():
+    """591,361-DoF jittered Q3 square: partition, level sizes and transfer sparsity bit-exact."""
+    w = F.workload(2)
+    _compare_analysis(w.problem, 2, 128, max_levels=4)
+
+
+def test_analysis_errors_match_oracle():
+    # zero extent along y (all points on a line)
+    pts = np.stack([np.linspace(0, 1, 20), np.zeros(20)], axis=1)
+    A = (sp.identity(20, format="csr") * 2.0 - sp.eye(20, k=1) - sp.eye(20, k=-1)).tocsr()
+    A.sort_indices()
+    with pytest.raises(P.R3mgError) as e:
+        P.Hierarchy(pts, A.indptr, A.indices, A.data, P.Options(dim=2, coarse_degree=1, leaf_size=5), factor=False)
+    assert e.value.code == "DEGENERATE_BOX"
+    # too few points per box
+    prob = F.structured_qp(2, 6, 1, dirichlet=False)
+    A = (prob.scipy() + sp.identity(prob.n)).tocsr()
+    A.sort_indices()
+    with pytest.raises(P.R3mgError) as e:
+        P.Hierarchy(prob.coords, A.indptr, A.indices, A.data, P.Options(dim=2, coarse_degree=2, leaf_size=4),
+                    factor=False)
+    assert e.value.code == "NOT_UNISOLVENT"
+    # badly placed points: two distinct x values per box cannot carry Q^2
+    xs = np.repeat([0.0, 1.0], 12)
+    ys = np.tile(np.linspace(0, 1, 12), 2)
+    pts = np.stack([xs, ys], axis=1)
+    A = (sp.identity(24, format="csr") * 3.0 - 0.5 * sp.eye(24, k=1) - 0.5 * sp.eye(24, k=-1)).tocsr()
+    A.sort_indices()
+    with pytest.raises(P.R3mgError) as e:
+        P.Hierarchy(pts, A.indptr, A.indices, A.data,
+                    P.Options(dim=2, coarse_degree=2, leaf_size=24, max_levels=2), factor=False)
+    assert e.value.code == "NOT_UNISOLVENT"
+
+
+def test_invalid_arguments():
+    w = F.workload(1)
+    p = w.problem
+    bad = p.coords.copy()
+    bad[3, 0] = np.nan
+    with pytest.raises(P.R3mgError) as e:
+        P.Hierarchy(bad, p.row_ptr, p.col, p.val, P.Options(dim=2), factor=False)
+    assert e.value.code == "INVALID"
+    with pytest.raises(P.R3mgError) as e:
+        P.Hierarchy(p.coords, p.row_ptr, p.col, p.val, P.Options(dim=4), factor=False)
+    assert e.value.code == "INVALID"
+    with pytest.raises(P.R3mgError) as e:
+        P.Hierarchy(p.coords, p.row_ptr, p.col, p.val, P.Options(dim=2, max_levels=1), factor=False)
+    assert e.value.code == "INVALID"
+    cl = p.col.copy()
+    cl[[0, 1]] = cl[[1, 0]] if p.row_ptr[1] > 1 else cl[[0, 1]]
+    rp = p.row_ptr.copy()
+    # unsorted columns inside an interior row
+    i = int(np.flatnonzero(~p.boundary)[0])
+    s = rp[i]
+    cl[s], cl[s + 1] = cl[s + 1], cl[s]
+    with pytest.raises(P.R3mgError) as e:
+        P.Hierarchy(p.coords, rp, cl, p.val, P.Options(dim=2), factor=False)
+    assert e.value.code == "INVALID"
+
+
+def test_device_calls_require_factor():
+    w = F.workload(1)
+    p = w.problem
+    h = P.Hierarchy(p.coords, p.row_ptr, p.col, p.val, P.Options(dim=2, coarse_degree=1, max_levels=2),
+                    factor=False)
+    import ctypes as C
+    st = P.lib().r3mg_vcycle(h._h, C.c_void_p(1), C.c_void_p(1), 1, None)
+    assert st == -1          # INVALID: analysed but not factored (nothing touched)
+    with pytest.raises(P.R3mgError):
+        h.export_level(1)
