@@ -76,6 +76,13 @@ double host_sum(const double* dev, int cnt, hipStream_t s) {
   return acc;
 }
 
+// every kernel that writes per-block partial sums is checked against the buffer before launch
+void need_partials(Device& dv, int64_t count) {
+  if (count > (int64_t)dv.partials.n)
+    throw Error{R3MG_ERR_INVALID, "internal: reduction buffer too small (" + std::to_string(count) + " > " +
+                                      std::to_string(dv.partials.n) + ")"};
+}
+
 void drop_graphs(Device& dv) {
   for (auto& kv : dv.graphs) (void)hipGraphExecDestroy(kv.second);
   for (auto& kv : dv.graph_defs) (void)hipGraphDestroy(kv.second);
@@ -149,9 +156,11 @@ static void ensure_pcg_vectors(Ctx& c, int nr) {
       R3MG_HIP_CHECK(hipMemset(bp->p, 0, (size_t)n * nr * sizeof(double)));
     }
     dv.pcg_cap = n * nr;
-    const int64_t nlog_spmv = (n + 127) / 128 + 8;
-    const int64_t nlog_vec = (n + 255) / 256 + 8;
-    dv.partials.alloc(std::max<size_t>(4096, (size_t)std::max(nlog_spmv * nr, nlog_vec * 2 * nr) + 64));
+    // the fine-level SpMV uses 256 / lanes rows per block; vector kernels 256 rows per block
+    const int64_t rpb = 256 / std::max(1, dv.lv[0].lanes);
+    const int64_t nlog_spmv = (n + rpb - 1) / rpb;
+    const int64_t nlog_vec = (n + 255) / 256;
+    dv.partials.alloc(std::max<size_t>(4096, (size_t)std::max(nlog_spmv * nr, nlog_vec * 2 * nr)));
     drop_graphs(dv);
   }
   if (!dv.state.p) {
@@ -501,6 +510,7 @@ static void vcycle_api_t(HandleImpl& h, const double* r, double* z, int nrhs, hi
       // x0 + pend -> pz (float64 interleaved) -> scatter the real columns
       ensure_pcg_vectors(c, NR);
       PcgState* st = reinterpret_cast<PcgState*>(dv.state.p);
+      need_partials(dv, (int64_t)((an.n + 255) / 256) * 2 * NR);
       R3MG_HIP_CHECK(hipMemsetAsync(dv.state.p, 0, sizeof(PcgState), s));
       launch_pcg_z<T>((int)an.n, NR, st, vbuf<T>(D0.x), pend, dv.pz.p, dv.pz.p, nullptr, dv.partials.p, s);
       launch_scatter_cols((int)an.n, NR, nb, dv.perm.p, dv.pz.p, z + (int64_t)c0 * an.n, an.n, s);
@@ -542,6 +552,8 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
   DevLevel& D0 = dv.lv[0];
   LevelOp<double> op64 = level_op<double>(c, 0);
   const int n = (int)an.n;
+  need_partials(dv, (int64_t)((n + 256 / op64.lanes - 1) / (256 / op64.lanes)) * NR);
+  need_partials(dv, (int64_t)((n + 255) / 256) * 2 * NR);
   int np = launch_spmv_dot(op64, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
   const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
   const T* dinv0;
@@ -572,6 +584,7 @@ static void pcg_start(Ctx& c, int NR, double rtol, bool flexible, hipStream_t s)
   const int* skip = reinterpret_cast<const int*>(dv.state.p);
   DevLevel& D0 = dv.lv[0];
   LevelOp<double> op64 = level_op<double>(c, 0);
+  need_partials(dv, (int64_t)((n + 255) / 256) * 2 * NR);
   // r = b - A x0
   launch_level<double>(op64, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
   int np = launch_residual(n, NR, dv.pb.p, dv.pq.p, dv.pr.p, dv.partials.p, s);

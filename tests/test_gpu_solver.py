@@ -254,3 +254,41 @@ def test_graph_and_eager_paths_agree(small2d):
         res.append((int(it[0]), x.cpu().numpy()))
     assert res[0][0] == res[1][0] == res[2][0]
     assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][1], res[2][1])
+
+
+@pytest.fixture(scope="module")
+def full2d():
+    _need_gpu()
+    _case("full2d setup (2D Q3 256x256 jittered, 591,361 DoFs, p'=2, leaf 128, 4 levels, V(2,2))")
+    w = F.workload(2)
+    return Case(w.problem, w.rhs, 2, 128, 4, 2, 2)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_full_size_2d_q3_pcg(full2d, fp32):
+    """The benchmark workload at full size (more reduction partials than any small case): iterations within
+    one of the oracle and solutions within 1e-9 of the oracle's."""
+    c = full2d
+    _case(f"full2d pcg fp32={fp32}")
+    P = _P()
+    import dataclasses
+    h = c.h if not fp32 else P.Hierarchy(c.prob.coords, c.prob.row_ptr, c.prob.col, c.prob.val,
+                                         dataclasses.replace(c.opts, vcycle_fp32=1))
+    if not hasattr(c, "xo"):
+        c.xo, c.ko, _, _, _ = O.pcg(c.ho, c.b, rtol=1e-10)
+    x = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok = h.pcg(_t(c.b), x, rtol=1e-10, maxit=200)
+    xs = x.cpu().numpy()
+    assert ok and abs(int(iters[0]) - c.ko) <= 1, (iters, c.ko)
+    r = c.b - c.prob.scipy() @ xs
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(c.b)
+    assert _rel(xs, c.xo) < 1e-9
+    # sampled V-cycle parity at full size (float64 path only)
+    if not fp32:
+        g = np.random.default_rng(11)
+        rv = g.standard_normal(c.prob.n)
+        rv[c.ho.constrained] = 0.0
+        z = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+        h.vcycle(_t(rv), z)
+        torch.cuda.synchronize()
+        assert _rel(z.cpu().numpy(), O.vcycle(c.ho, rv)) < 1e-11
