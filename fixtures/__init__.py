@@ -322,7 +322,8 @@ def structured_qp(d: int, N: int, p: int, *, jitter: float = 0.0, cfg: int = 0,
 
 def mass_apply(d: int, N: int, p: int, f: np.ndarray, *, jitter: float = 0.0, cfg: int = 0,
                chunk: int = 8192) -> np.ndarray:
-    """b = M f with the consistent Q_p mass matrix (Gauss (p+1)^d quadrature), unconstrained form."""
+    """b = M f with the consistent Q_p mass matrix (Gauss (p+1)^d quadrature), unconstrained form.
+    f may be (n,) or (k, n) for k right-hand sides at once."""
     tab = _reference_tables(d, p)
     offs = tab["offs"]
     M1 = p * N + 1
@@ -342,15 +343,22 @@ def mass_apply(d: int, N: int, p: int, f: np.ndarray, *, jitter: float = 0.0, cf
     ncells = cgrid.shape[0]
     cells = ((cgrid[:, None, :] * p + offs[None, :, :]) * strides).sum(-1)
     cell_verts = ((cgrid[:, None, :] + tab["voffs"][None, :, :]) * vstr).sum(-1)
-    b = np.zeros(M1 ** d)
+    F2 = np.atleast_2d(f)
+    b = np.zeros_like(F2, dtype=np.float64)
+    uniform = jitter == 0.0
+    if uniform:
+        _, Mm1 = _element_matrices(vx[cell_verts[:1]], tab)
     for c0 in range(0, ncells, chunk):
         c1 = min(ncells, c0 + chunk)
-        _, Mm = _element_matrices(vx[cell_verts[c0:c1]], tab)
         cl = cells[c0:c1]
-        be = np.einsum("cab,cb->ca", Mm, f[cl])
+        if uniform:
+            be = np.einsum("ab,kcb->kca", Mm1[0], F2[:, cl])
+        else:
+            _, Mm = _element_matrices(vx[cell_verts[c0:c1]], tab)
+            be = np.einsum("cab,kcb->kca", Mm, F2[:, cl])
         for a in range(cl.shape[1]):
-            b[cl[:, a]] += be[:, a]
-    return b
+            b[:, cl[:, a]] += be[:, :, a]
+    return b if f.ndim == 2 else b[0]
 
 
 # ----------------------------------------------------------------------------------------------
@@ -368,6 +376,7 @@ class Workload:
     pre_steps: int
     post_steps: int
     extra: dict = dataclasses.field(default_factory=dict)
+    skip_leaf_level: int = 0
 
 
 def nodal_rhs(prob: QpProblem, f: np.ndarray, *, jitter: float = 0.0, cfg: int = 0) -> np.ndarray:
@@ -414,14 +423,15 @@ def workload(cfg: int, *, scale: Optional[int] = None) -> Workload:
         f = rng(3, PURPOSE_RHS).standard_normal(prob.n)
         b = nodal_rhs(prob, f, cfg=3)
         return Workload("3D Poisson Q2 64^3 (2,146,689 DoFs), p'=2, leaf 256, <=2000 coarse, V(2,2)",
-                        prob, b, 2, 256, 0, 2000, 2, 2)
+                        prob, b, 2, 256, 0, 2000, 2, 2, skip_leaf_level=1)
     if cfg == 4:
         N = scale or 48
         prob = structured_qp(3, N, 3, cfg=4)
-        B = np.stack([nodal_rhs(prob, rng(4, PURPOSE_RHS, j).standard_normal(prob.n), cfg=4)
-                      for j in range(16)])
+        Fm = np.stack([rng(4, PURPOSE_RHS, j).standard_normal(prob.n) for j in range(16)])
+        B = mass_apply(3, N, 3, Fm, cfg=4)
+        B[:, prob.boundary] = 0.0
         return Workload("3D Poisson Q3 48^3 (3,048,625 DoFs), 16 RHS, p'=2, leaf 256",
-                        prob, B, 2, 256, 0, 2000, 2, 2)
+                        prob, B, 2, 256, 0, 2000, 2, 2, skip_leaf_level=1)
     if cfg == 5:
         N = scale or 64
         ncells = N ** 3
@@ -431,10 +441,21 @@ def workload(cfg: int, *, scale: Optional[int] = None) -> Workload:
         ut = smooth_target(prob.coords, 5)
         fd = rng(5, PURPOSE_FDCELLS).choice(ncells, size=min(32, ncells), replace=False)
         return Workload("3D -div(kappa grad u)=1, Q2 64^3, lognormal kappa per cell",
-                        prob, b, 2, 256, 0, 2000, 2, 2, extra=dict(target=ut, fd_cells=fd))
+                        prob, b, 2, 256, 0, 2000, 2, 2, extra=dict(target=ut, fd_cells=fd), skip_leaf_level=1)
     raise ValueError(cfg)
 
 
 def uneven_batch_sizes():
     """Q2 meshes of the second batch: N in {16,21,25,30,34,39,43,48}."""
     return [16, 21, 25, 30, 34, 39, 43, 48]
+
+
+def uneven_batch(sizes=None):
+    """Second batch of the multi-RHS workload: independent 3D Q2 Poisson problems of different sizes, one seeded
+    Gaussian nodal right-hand side each (purpose 1, j = problem index)."""
+    out = []
+    for j, N in enumerate(sizes or uneven_batch_sizes()):
+        prob = structured_qp(3, N, 2, cfg=4)
+        f = rng(4, PURPOSE_RHS, 100 + j).standard_normal(prob.n)
+        out.append((prob, nodal_rhs(prob, f, cfg=4)))
+    return out

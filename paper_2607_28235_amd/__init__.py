@@ -5,5 +5,14 @@ adds the differentiable solve (autograd.py).  Nothing here falls back to a CPU i
 """
 from ._lib import (Assembler, Hierarchy, Options, R3mgError, lib, rtree, solve_group, EXPORTED, LIB_PATH)
 
+
+def __getattr__(name):
+    # the autograd wrapper imports torch; load it on first use only
+    if name in ("AdjointPoisson", "PoissonSolve"):
+        from . import autograd
+        return getattr(autograd, name)
+    raise AttributeError(name)
+
+
 __all__ = ["Assembler", "Hierarchy", "Options", "R3mgError", "lib", "rtree", "solve_group", "EXPORTED",
-           "LIB_PATH"]
+           "LIB_PATH", "AdjointPoisson", "PoissonSolve"]

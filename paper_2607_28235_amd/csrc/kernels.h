@@ -42,6 +42,21 @@ template <typename T>
 void launch_level(const LevelOp<T>& op, int nr, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
                   double c2, int flags, const int* skip, hipStream_t s);
 
+// Row-block variant for the CSR fine level and one right-hand side (rb: nrb + 1 row offsets, each block <= 64
+// rows and <= 2048 nonzeros unless it is a single row).  With partials != null (F_PLAIN only) each block also
+// writes the partial sum of u_i (A u)_i to partials[block].
+constexpr int kStreamCapHost = 2048;
+constexpr int kStreamRowsHost = 64;
+template <typename T>
+void launch_level_stream(int nrb, const int* rb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x, T* dout,
+                         double c1, double c2, int flags, const int* skip, double* partials, hipStream_t s);
+
+// Block-row variant for the agglomerated levels and one right-hand side (one wave per box; maxnb = largest
+// number of stored blocks in a block row).
+template <typename T>
+void launch_level_blockrow(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
+                           double c2, int flags, const int* skip, hipStream_t s);
+
 // q = A p (float64, CSR), per-block partial <p, q> -> partials[blk * nr + k]; returns number of blocks
 int launch_spmv_dot(const LevelOp<double>& op, int nr, const double* p, double* q, double* partials,
                     const int* skip, hipStream_t s);

@@ -229,6 +229,220 @@ template void launch_level<float>(const LevelOp<float>&, int, const float*, cons
 template void launch_level<double>(const LevelOp<double>&, int, const double*, const double*, double*, double*,
                                    double*, double, double, int, const int*, hipStream_t);
 
+// Row-block ("stream") variant of the fused kernel for the CSR fine level, one right-hand side.  Each
+// workgroup owns a host-computed block of <= 64 consecutive rows holding <= kStreamCap nonzeros: phase 1
+// streams the block's values and column indices with fully coalesced loads and stages val * u[col] in LDS,
+// phase 2 sums each row with 4 lanes and applies the same epilogue as k_level.  A row longer than kStreamCap
+// forms a block of its own and is summed by the whole workgroup.  With DOT the block also writes the partial
+// sum of u_i * (A u)_i (PCG's <p, A p>).
+constexpr int kStreamCap = 2048;
+constexpr int kStreamRows = 64;
+
+template <typename T, bool DOT>
+__global__ __launch_bounds__(256) void k_level_stream(int nrb, const int* __restrict__ rb, const int* __restrict__ ptr,
+                                                      const int* __restrict__ idx, const T* __restrict__ val,
+                                                      const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
+                                                      const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
+                                                      const int* __restrict__ skip, double* partials) {
+  if (skip && *skip) return;
+  const int lb = xcd_block(nrb);
+  if (lb < 0) return;
+  __shared__ T prod[kStreamCap];
+  __shared__ double sh[4];
+  const int r0 = rb[lb], r1 = rb[lb + 1];
+  const int e0 = ptr[r0], e1 = ptr[r1];
+  const int nz = e1 - e0;
+  // epilogue operands of the row this thread may finalise, fetched before the matrix stream
+  const int prow = r0 + (threadIdx.x >> 2);
+  const bool pre = (threadIdx.x & 3) == 0 && prow < r1 && nz <= kStreamCap && !(flags & F_PLAIN);
+  T p_old = 0, p_x = 0, p_u = 0, p_di = 0;
+  if (pre) {
+    p_old = (flags & F_RHO_FROM_B) ? b[prow] : rho[prow];
+    p_u = u[prow];
+    if (flags & F_X_ADD) p_x = x[prow];
+    if (flags & F_D_OUT) p_di = dinv[prow];
+  }
+  T t = 0;
+  int row = -1;
+  if (nz <= kStreamCap) {
+    // all loads of the block issued before any gather (8 elements per thread: kStreamCap = 8 * 256); the
+    // matrix is streamed once per application, so its loads bypass the caches' retention (non-temporal)
+    int ci[kStreamCap / 256];
+    T vv[kStreamCap / 256];
+#pragma unroll
+    for (int m = 0; m < kStreamCap / 256; ++m) {
+      const int e = threadIdx.x + m * 256;
+      if (e < nz) {
+        ci[m] = __builtin_nontemporal_load(idx + e0 + e);
+        vv[m] = __builtin_nontemporal_load(val + e0 + e);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kStreamCap / 256; ++m) {
+      const int e = threadIdx.x + m * 256;
+      if (e < nz) prod[e] = vv[m] * u[ci[m]];
+    }
+    __syncthreads();
+    const int rl = threadIdx.x >> 2, sub = threadIdx.x & 3;
+    T acc = 0;
+    if (r0 + rl < r1) {
+      const int s = ptr[r0 + rl] - e0, e = ptr[r0 + rl + 1] - e0;
+      for (int k = s + sub; k < e; k += 4) acc += prod[k];
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (sub == 0 && r0 + rl < r1) {
+      row = r0 + rl;
+      t = acc;
+    }
+  } else {  // one long row
+    T acc = 0;
+    for (int e = e0 + threadIdx.x; e < e1; e += 256) acc += val[e] * u[idx[e]];
+    acc = wave_sum(acc, 64);
+    __shared__ T shr[4];
+    if ((threadIdx.x & 63) == 0) shr[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      row = r0;
+      t = (shr[0] + shr[1]) + (shr[2] + shr[3]);
+    }
+  }
+  double contrib = 0.0;
+  if (row >= 0) {
+    if (flags & F_PLAIN) {
+      rho[row] = t;
+      if (DOT) contrib = (double)t * (double)u[row];
+    } else {
+      if (!pre) {  // the long-row path did not prefetch
+        p_old = (flags & F_RHO_FROM_B) ? b[row] : rho[row];
+        p_u = u[row];
+        if (flags & F_X_ADD) p_x = x[row];
+        if (flags & F_D_OUT) p_di = dinv[row];
+      }
+      const T r = p_old - t;
+      if (flags & F_RHO_STORE) rho[row] = r;
+      if (flags & F_X_ASSIGN)
+        x[row] = p_u;
+      else if (flags & F_X_ADD)
+        x[row] = p_x + p_u;
+      if (flags & F_D_OUT) dout[row] = c1 * p_u + c2 * p_di * r;
+    }
+  }
+  if (DOT) {
+    const double s = block_sum256(contrib, sh);
+    if (threadIdx.x == 0) partials[lb] = s;
+  }
+}
+
+template <typename T>
+void launch_level_stream(int nrb, const int* rb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x, T* dout,
+                         double c1, double c2, int flags, const int* skip, double* partials, hipStream_t s) {
+  if (nrb == 0) return;
+  if (partials)
+    hipLaunchKernelGGL((k_level_stream<T, true>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, rb, op.ptr, op.idx, op.val,
+                       u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, partials);
+  else
+    hipLaunchKernelGGL((k_level_stream<T, false>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, rb, op.ptr, op.idx,
+                       op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, partials);
+  check_launch("k_level_stream");
+}
+template void launch_level_stream<float>(int, const int*, const LevelOp<float>&, const float*, const float*, float*,
+                                         float*, float*, double, double, int, const int*, double*, hipStream_t);
+template void launch_level_stream<double>(int, const int*, const LevelOp<double>&, const double*, const double*,
+                                          double*, double*, double*, double, double, int, const int*, double*,
+                                          hipStream_t);
+
+// Block-row variant of the fused kernel for the agglomerated levels, one right-hand side.  One wave per box
+// K: the nb*B entries of u that the block row touches (nb stored blocks of B consecutive columns) are staged in
+// LDS once and shared by the B rows of the box; row (K,q) then streams its nb*B contiguous values with
+// coalesced loads against the LDS copy (the LDS layout [j][c] equals the row layout), 4 rows at a time, and
+// lane q applies the epilogue of row (K,q).  Dynamic LDS: 4 waves x maxw entries, maxw = max_K nb_K * B.
+template <typename T>
+__global__ __launch_bounds__(256) void k_level_blockrow(int nbox, int blk, int maxw, const int* __restrict__ bptr,
+                                                        const int* __restrict__ bcol, const T* __restrict__ val,
+                                                        const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
+                                                        const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
+                                                        const int* __restrict__ skip, int nlog) {
+  if (skip && *skip) return;
+  extern __shared__ unsigned char smem_raw[];
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int K = lb * 4 + wv;
+  if (K >= nbox) return;  // whole wave leaves; no block-wide barrier follows
+  T* xs = reinterpret_cast<T*>(smem_raw) + (size_t)wv * maxw;
+  T* rs = reinterpret_cast<T*>(smem_raw) + (size_t)4 * maxw + wv * 64;
+  const int j0 = bptr[K], nb = bptr[K + 1] - j0;
+  const int w = nb * blk;
+  for (int p = lane; p < w; p += 64) {
+    const int j = p / blk, c = p - j * blk;
+    xs[p] = u[(int64_t)bcol[j0 + j] * blk + c];
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int64_t vb = (int64_t)blk * blk * j0;
+  for (int q0 = 0; q0 < blk; q0 += 4) {
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    const T* v0 = val + vb + (int64_t)q0 * w;
+    const bool h1 = q0 + 1 < blk, h2 = q0 + 2 < blk, h3 = q0 + 3 < blk;
+    for (int p = lane; p < w; p += 64) {
+      const T xp = xs[p];
+      a0 += v0[p] * xp;
+      if (h1) a1 += v0[w + p] * xp;
+      if (h2) a2 += v0[2 * w + p] * xp;
+      if (h3) a3 += v0[3 * w + p] * xp;
+    }
+    a0 = wave_sum(a0, 64);
+    a1 = wave_sum(a1, 64);
+    a2 = wave_sum(a2, 64);
+    a3 = wave_sum(a3, 64);
+    if (lane == 0) {
+      rs[q0] = a0;
+      if (h1) rs[q0 + 1] = a1;
+      if (h2) rs[q0 + 2] = a2;
+      if (h3) rs[q0 + 3] = a3;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane < blk) {
+    const int row = K * blk + lane;
+    const T t = rs[lane];
+    if (flags & F_PLAIN) {
+      rho[row] = t;
+    } else {
+      const T r = ((flags & F_RHO_FROM_B) ? b[row] : rho[row]) - t;
+      if (flags & F_RHO_STORE) rho[row] = r;
+      const T ui = u[row];
+      if (flags & F_X_ASSIGN)
+        x[row] = ui;
+      else if (flags & F_X_ADD)
+        x[row] += ui;
+      if (flags & F_D_OUT) dout[row] = c1 * ui + c2 * dinv[row] * r;
+    }
+  }
+}
+
+template <typename T>
+void launch_level_blockrow(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
+                           double c2, int flags, const int* skip, hipStream_t s) {
+  const int nbox = op.n / op.blk;
+  const int nlog = (nbox + 3) / 4;
+  if (nlog == 0) return;
+  const int maxw = maxnb * op.blk;
+  const size_t shm = sizeof(T) * ((size_t)4 * maxw + 4 * 64);
+  if (shm > 65536) throw std::runtime_error("block-row kernel: block row too wide for LDS");
+  hipLaunchKernelGGL((k_level_blockrow<T>), dim3(xcd_grid(nlog)), dim3(256), shm, s, nbox, op.blk, maxw, op.ptr, op.idx,
+                     op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
+  check_launch("k_level_blockrow");
+}
+template void launch_level_blockrow<float>(const LevelOp<float>&, int, const float*, const float*, float*, float*,
+                                           float*, double, double, int, const int*, hipStream_t);
+template void launch_level_blockrow<double>(const LevelOp<double>&, int, const double*, const double*, double*,
+                                            double*, double*, double, double, int, const int*, hipStream_t);
+
 // q = A p with per-block partial sums of p.q (float64 CSR)
 template <int NR>
 __global__ __launch_bounds__(256) void k_spmv_dot(int n, int G, const int* __restrict__ ptr,
@@ -572,7 +786,15 @@ __global__ __launch_bounds__(256) void k_dense_apply(int nc, const double* __res
 #pragma unroll
   for (int k = 0; k < NR; ++k) acc[k] = 0;
   const double* a = cinv + (int64_t)row * nc;
-  for (int c = lane; c < nc; c += 64) {
+  int c = lane;
+  for (; c + 192 < nc; c += 256) {  // four independent loads in flight per lane
+    const double m0 = a[c], m1 = a[c + 64], m2 = a[c + 128], m3 = a[c + 192];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      acc[k] += (m0 * (double)b[(int64_t)c * NR + k] + m1 * (double)b[(int64_t)(c + 64) * NR + k]) +
+                (m2 * (double)b[(int64_t)(c + 128) * NR + k] + m3 * (double)b[(int64_t)(c + 192) * NR + k]);
+  }
+  for (; c < nc; c += 64) {
     const double m = a[c];
 #pragma unroll
     for (int k = 0; k < NR; ++k) acc[k] += m * (double)b[(int64_t)c * NR + k];
@@ -1111,14 +1333,32 @@ void dense_cholesky_inverse(int n, double* A, double* Inv, int* bad, hipStream_t
 // =============================================================================================
 // PCG (float64 outer iteration; scalars live on the device)
 // =============================================================================================
+// sum of partials[b * nr + k] over b < npart by one 1024-thread block (fixed order: deterministic);
+// the total is returned in thread 0.  sh must hold 16 doubles.
 __device__ inline double sum_partials(const double* __restrict__ partials, int npart, int nr, int k, double* sh) {
-  double acc = 0;
-  for (int b = threadIdx.x; b < npart; b += 256) acc += partials[(int64_t)b * nr + k];
-  return block_sum256(acc, sh);
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int b = threadIdx.x;
+  for (; b + 3 * 1024 < npart; b += 4 * 1024) {
+    a0 += partials[(int64_t)b * nr + k];
+    a1 += partials[(int64_t)(b + 1024) * nr + k];
+    a2 += partials[(int64_t)(b + 2048) * nr + k];
+    a3 += partials[(int64_t)(b + 3072) * nr + k];
+  }
+  for (; b < npart; b += 1024) a0 += partials[(int64_t)b * nr + k];
+  double v = wave_sum((a0 + a1) + (a2 + a3), 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 16; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;
 }
 
-__global__ __launch_bounds__(256) void k_pcg_alpha(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
-  __shared__ double sh[4];
+__global__ __launch_bounds__(1024) void k_pcg_alpha(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
+  __shared__ double sh[16];
   if (st->all_done) return;
   for (int k = 0; k < nr; ++k) {
     const double pq = sum_partials(partials, npart, nr, k, sh);
@@ -1126,7 +1366,7 @@ __global__ __launch_bounds__(256) void k_pcg_alpha(int nr, PcgState* st, const d
   }
 }
 void launch_pcg_alpha(int nr, PcgState* st, const double* partials, int npart, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, s, nr, st, partials, npart);
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1024), 0, s, nr, st, partials, npart);
   check_launch("k_pcg_alpha");
 }
 
@@ -1197,8 +1437,8 @@ template void launch_pcg_xr<float>(int, int, PcgState*, const double*, int, doub
 template void launch_pcg_xr<double>(int, int, PcgState*, const double*, int, double*, double*, const double*,
                                     const double*, double*, double*, const double*, double*, double, hipStream_t);
 
-__global__ __launch_bounds__(256) void k_pcg_check(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
-  __shared__ double sh[4];
+__global__ __launch_bounds__(1024) void k_pcg_check(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
+  __shared__ double sh[16];
   if (st->all_done) return;
   int all = 1;
   for (int k = 0; k < nr; ++k) {
@@ -1213,7 +1453,7 @@ __global__ __launch_bounds__(256) void k_pcg_check(int nr, PcgState* st, const d
   if (threadIdx.x == 0) st->all_done = all;
 }
 void launch_pcg_check(int nr, PcgState* st, const double* partials, int npart, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, s, nr, st, partials, npart);
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1024), 0, s, nr, st, partials, npart);
   check_launch("k_pcg_check");
 }
 
@@ -1279,8 +1519,8 @@ template void launch_pcg_z<double>(int, int, PcgState*, const double*, const dou
                                    const double*, double*, hipStream_t);
 
 // beta: standard (gamma'/gamma) or flexible (-alpha <z,q> / gamma); partials hold [rz(0..nr-1), qz(0..nr-1)]
-__global__ __launch_bounds__(256) void k_pcg_beta(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
-  __shared__ double sh[4];
+__global__ __launch_bounds__(1024) void k_pcg_beta(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
+  __shared__ double sh[16];
   if (st->all_done) return;
   for (int k = 0; k < nr; ++k) {
     const double rz = sum_partials(partials, npart, 2 * nr, k, sh);
@@ -1293,7 +1533,7 @@ __global__ __launch_bounds__(256) void k_pcg_beta(int nr, PcgState* st, const do
   }
 }
 void launch_pcg_beta(int nr, PcgState* st, const double* partials, int npart, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, s, nr, st, partials, npart);
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1024), 0, s, nr, st, partials, npart);
   check_launch("k_pcg_beta");
 }
 
@@ -1355,9 +1595,9 @@ int launch_residual(int n, int nr, const double* b, const double* q, double* r, 
   return g;
 }
 
-__global__ __launch_bounds__(256) void k_pcg_init(int nr, PcgState* st, const double* __restrict__ partials, int npart,
+__global__ __launch_bounds__(1024) void k_pcg_init(int nr, PcgState* st, const double* __restrict__ partials, int npart,
                                                   double rtol, int nr_active, int flexible) {
-  __shared__ double sh[4];
+  __shared__ double sh[16];
   int all = 1;
   for (int k = 0; k < nr; ++k) {
     const double rr = sum_partials(partials, npart, nr, k, sh);
@@ -1380,12 +1620,12 @@ __global__ __launch_bounds__(256) void k_pcg_init(int nr, PcgState* st, const do
 }
 void launch_pcg_init(int nr, PcgState* st, const double* partials, int npart, double rtol, int flexible,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(256), 0, s, nr, st, partials, npart, rtol, nr, flexible);
+  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(1024), 0, s, nr, st, partials, npart, rtol, nr, flexible);
   check_launch("k_pcg_init");
 }
 
-__global__ __launch_bounds__(256) void k_pcg_gamma(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
-  __shared__ double sh[4];
+__global__ __launch_bounds__(1024) void k_pcg_gamma(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
+  __shared__ double sh[16];
   for (int k = 0; k < nr; ++k) {
     const double rz = sum_partials(partials, npart, 2 * nr, k, sh);
     if (threadIdx.x == 0) st->gamma[k] = rz;
@@ -1397,7 +1637,7 @@ __global__ void k_copy(int64_t count, const double* __restrict__ a, double* b) {
 }
 void launch_pcg_init_gamma(int n, int nr, PcgState* st, const double* partials, int npart, const double* z,
                            double* p, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_gamma, dim3(1), dim3(256), 0, s, nr, st, partials, npart);
+  hipLaunchKernelGGL(k_pcg_gamma, dim3(1), dim3(1024), 0, s, nr, st, partials, npart);
   const int64_t tot = (int64_t)n * nr;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, tot, z, p);
   check_launch("k_pcg_gamma");

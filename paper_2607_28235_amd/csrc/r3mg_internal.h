@@ -145,6 +145,9 @@ struct DevLevel {
   DBuf<float> dinv32;
   double lam_hi = 0, lam_lo = 0, lam_hat = 0;
   int lanes = 8;  // lanes per row of the SpMV kernels
+  DBuf<int32_t> rb;  // l = 0: row blocks of the single-RHS stream kernel
+  int nrb = 0;
+  int maxnb = 0;     // l >= 1: largest number of stored blocks in a block row
   // transfer to the next level
   DBuf<double> xi64;     // l = 0: n x d
   DBuf<float> xi32;

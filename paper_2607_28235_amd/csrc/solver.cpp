@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <vector>
 
@@ -129,6 +130,27 @@ LevelOp<T> level_op(Ctx& c, int l) {
   return op;
 }
 
+// level operator application: the row-block kernel on the fine level for one right-hand side, the
+// lanes-per-row kernel otherwise
+template <typename T>
+void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T* dout, double c1, double c2, int flags,
+                 const int* skip, hipStream_t s) {
+  LevelOp<T> op = level_op<T>(c, l);
+  DevLevel& D = c.dv.lv[l];
+  if (l == 0 && nr == 1 && D.nrb > 0)
+    launch_level_stream<T>(D.nrb, D.rb.p, op, u, b, rho, x, dout, c1, c2, flags, skip, nullptr, s);
+  else if (l > 0 && nr == 1 && D.maxnb > 0 &&
+           (int64_t)D.maxnb * c.an.B <= (int64_t)(65536 / sizeof(T) - 256) / 4)
+    launch_level_blockrow<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags, skip, s);
+  else {
+    if (nr > 1) {
+      auto it = c.dv.tuned.find({l, nr * 2 + (sizeof(T) == 4 ? 1 : 0)});
+      if (it != c.dv.tuned.end()) op.lanes = it->second;
+    }
+    launch_level<T>(op, nr, u, b, rho, x, dout, c1, c2, flags, skip, s);
+  }
+}
+
 static void ensure_level_vectors(Ctx& c, int nr) {
   const size_t s = c.fp32 ? sizeof(float) : sizeof(double);
   const int L = c.an.nlevels() - 1;
@@ -157,10 +179,11 @@ static void ensure_pcg_vectors(Ctx& c, int nr) {
     }
     dv.pcg_cap = n * nr;
     // the fine-level SpMV uses 256 / lanes rows per block; vector kernels 256 rows per block
-    const int64_t rpb = 256 / std::max(1, dv.lv[0].lanes);
+    const int64_t rpb = 256 / std::max(nr > 1 ? 8 : 1, dv.lv[0].lanes);
     const int64_t nlog_spmv = (n + rpb - 1) / rpb;
     const int64_t nlog_vec = (n + 255) / 256;
-    dv.partials.alloc(std::max<size_t>(4096, (size_t)std::max(nlog_spmv * nr, nlog_vec * 2 * nr)));
+    dv.partials.alloc(std::max<size_t>({(size_t)4096, (size_t)(nlog_spmv * nr), (size_t)(nlog_vec * 2 * nr),
+                                        (size_t)dv.lv[0].nrb}));
     drop_graphs(dv);
   }
   if (!dv.state.p) {
@@ -168,6 +191,73 @@ static void ensure_pcg_vectors(Ctx& c, int nr) {
     R3MG_HIP_CHECK(hipMemset(dv.state.p, 0, sizeof(PcgState)));
   }
   if (!dv.pinned) R3MG_HIP_CHECK(hipHostMalloc(&dv.pinned, sizeof(PcgState), hipHostMallocDefault));
+}
+
+// Multi-RHS SpMM tile autotuner: the lanes-per-row tile of every level kernel (and of PCG's float64 SpMV) is
+// chosen per (level, nrhs, precision) by timing each candidate with hipEvents on the level's own work vectors
+// (3 warm-up + 5 timed launches), once per handle; the choice is cached and used by every later solve.  Must run
+// outside graph capture (it synchronises).
+static float time_launches(hipStream_t s, int reps, const std::function<void()>& f) {
+  hipEvent_t e0, e1;
+  R3MG_HIP_CHECK(hipEventCreate(&e0));
+  R3MG_HIP_CHECK(hipEventCreate(&e1));
+  for (int r = 0; r < 3; ++r) f();
+  R3MG_HIP_CHECK(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) f();
+  R3MG_HIP_CHECK(hipEventRecord(e1, s));
+  R3MG_HIP_CHECK(hipEventSynchronize(e1));
+  float ms = 0;
+  R3MG_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
+template <typename T>
+static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
+  if (nr <= 1) return;
+  Device& dv = c.dv;
+  const int L = c.an.nlevels() - 1;
+  const int tag = nr * 2 + (sizeof(T) == 4 ? 1 : 0);
+  for (int l = 0; l < L; ++l) {
+    if (dv.tuned.count({l, tag})) continue;
+    DevLevel& D = dv.lv[l];
+    LevelOp<T> op = level_op<T>(c, l);
+    float best = 1e30f;
+    int bestG = D.lanes;
+    for (int G = 1; G <= 64; G <<= 1) {
+      op.lanes = G;
+      const float ms = time_launches(s, 5, [&] {
+        launch_level<T>(op, nr, vbuf<T>(D.dA), vbuf<T>(D.b), vbuf<T>(D.rho), vbuf<T>(D.x), vbuf<T>(D.dB), 0.0, 0.0,
+                        F_RHO_STORE | F_X_ADD | F_D_OUT, nullptr, s);
+      });
+      if (ms < best) {
+        best = ms;
+        bestG = G;
+      }
+    }
+    dv.tuned[{l, tag}] = bestG;
+    R3MG_HIP_CHECK(hipMemsetAsync(D.x.p, 0, D.x.n, s));
+  }
+  // PCG's float64 SpMV with partial dot products (at most 8 lanes: bounded number of partials)
+  if (!dv.tuned.count({-1, nr * 2})) {
+    LevelOp<double> op = level_op<double>(c, 0);
+    float best = 1e30f;
+    int bestG = 1;
+    for (int G = 1; G <= 8; G <<= 1) {
+      op.lanes = G;
+      need_partials(dv, (int64_t)((c.an.n + 256 / G - 1) / (256 / G)) * nr);
+      const float ms = time_launches(s, 5, [&] {
+        launch_spmv_dot(op, nr, dv.pp.p, dv.pq.p, dv.partials.p, nullptr, s);
+      });
+      if (ms < best) {
+        best = ms;
+        bestG = G;
+      }
+    }
+    dv.tuned[{-1, nr * 2}] = bestG;
+  }
+  R3MG_HIP_CHECK(hipStreamSynchronize(s));
 }
 
 // Chebyshev coefficients of a level: first direction scale 1/theta, then (c1, c2) of steps k = 1..K-1
@@ -222,7 +312,7 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
     ++done_spmv;
     if (done_spmv < total_spmv) fl |= F_RHO_STORE;  // the level's last residual is never read
     if (dout_on) fl |= F_D_OUT;
-    launch_level<T>(op, nr, u, b, rho, x, dout, c1, c2, fl, skip, s);
+    apply_level<T>(c, l, nr, u, b, rho, x, dout, c1, c2, fl, skip, s);
     x_zero = false;
     rho_is_b = false;
   };
@@ -327,7 +417,7 @@ static void lanczos_level(Ctx& c, int l, hipStream_t s) {
   double bprev = 0.0;
   const int steps = an.opt.lanczos_steps;
   for (int it = 0; it < steps; ++it) {
-    launch_level<double>(op, 1, v.p, nullptr, Av.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+    apply_level<double>(c, l, 1, v.p, nullptr, Av.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
     launch_lanczos_u(n, D.dinv64.p, Av.p, bprev, vp.p, u.p, s);
     np = launch_dot(n, diag.p, u.p, v.p, part.p, s);
     const double a = host_sum(part.p, np, s);
@@ -427,6 +517,18 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     std::vector<int32_t> lo(an.leaf_off.begin(), an.leaf_off.end());
     D.leaf_off.upload(lo, s);
     D.lanes = lanes_for((double)an.nnz / (double)an.n);
+    {  // row blocks of the stream kernel: <= kStreamRowsHost rows and <= kStreamCapHost nonzeros each
+      std::vector<int32_t> rb{0};
+      int64_t r = 0;
+      while (r < an.n) {
+        int64_t r1 = r + 1;
+        while (r1 < an.n && r1 - r < kStreamRowsHost && an.rowptr[r1 + 1] - an.rowptr[r] <= kStreamCapHost) ++r1;
+        rb.push_back((int32_t)r1);
+        r = r1;
+      }
+      D.nrb = (int)rb.size() - 1;
+      D.rb.upload(rb, s);
+    }
     D.dinv64.alloc(D.n);
     if (fp32) {
       D.xi32.alloc(D.xi64.n);
@@ -452,6 +554,7 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     D.val64.alloc((size_t)D.nnz);
     D.dinv64.alloc(D.n);
     D.child_shift = H.child_shift;
+    for (int64_t k = 0; k < H.nbox; ++k) D.maxnb = std::max<int>(D.maxnb, (int)(H.bptr[k + 1] - H.bptr[k]));
     if (!H.pt1d.empty()) {
       D.pt64.upload(H.pt1d, s);
       if (fp32) {
@@ -488,6 +591,10 @@ static void vcycle_api_t(HandleImpl& h, const double* r, double* z, int nrhs, hi
     int NR = 1;
     while (NR < nb) NR <<= 1;
     ensure_level_vectors(c, NR);
+    if (NR > 1) {
+      ensure_pcg_vectors(c, NR);
+      autotune_spmm<T>(c, NR, s);
+    }
     DevLevel& D0 = dv.lv[0];
     T* b0 = vbuf<T>(D0.b);
     const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
@@ -534,7 +641,7 @@ void level_apply(HandleImpl& h, int level, const double* x, double* y, hipStream
   if (l == 0) {
     ensure_pcg_vectors(c, 1);
     launch_gather_cols((int)an.n, 1, 1, dv.perm.p, x, an.n, dv.pb.p, s);
-    launch_level<double>(op, 1, dv.pb.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+    apply_level<double>(c, 0, 1, dv.pb.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
     launch_scatter_cols((int)an.n, 1, 1, dv.perm.p, dv.pq.p, y, an.n, s);
   } else {
     launch_level<double>(op, 1, x, nullptr, y, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
@@ -552,9 +659,19 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
   DevLevel& D0 = dv.lv[0];
   LevelOp<double> op64 = level_op<double>(c, 0);
   const int n = (int)an.n;
-  need_partials(dv, (int64_t)((n + 256 / op64.lanes - 1) / (256 / op64.lanes)) * NR);
   need_partials(dv, (int64_t)((n + 255) / 256) * 2 * NR);
-  int np = launch_spmv_dot(op64, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+  need_partials(dv, D0.nrb);
+  int np;
+  if (NR == 1 && D0.nrb > 0) {
+    launch_level_stream<double>(D0.nrb, D0.rb.p, op64, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN,
+                                skip, dv.partials.p, s);
+    np = D0.nrb;
+  } else {
+    auto it = dv.tuned.find({-1, NR * 2});
+    if (it != dv.tuned.end()) op64.lanes = it->second;
+    need_partials(dv, (int64_t)((n + 256 / op64.lanes - 1) / (256 / op64.lanes)) * NR);
+    np = launch_spmv_dot(op64, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+  }
   const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
   const T* dinv0;
   if constexpr (sizeof(T) == 4) dinv0 = D0.dinv32.p; else dinv0 = D0.dinv64.p;
@@ -586,7 +703,7 @@ static void pcg_start(Ctx& c, int NR, double rtol, bool flexible, hipStream_t s)
   LevelOp<double> op64 = level_op<double>(c, 0);
   need_partials(dv, (int64_t)((n + 255) / 256) * 2 * NR);
   // r = b - A x0
-  launch_level<double>(op64, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+  apply_level<double>(c, 0, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
   int np = launch_residual(n, NR, dv.pb.p, dv.pq.p, dv.pr.p, dv.partials.p, s);
   launch_pcg_init(NR, st, dv.partials.p, np, rtol, flexible ? 1 : 0, s);
   // z = B r; p = z; gamma = <r, z>
@@ -653,6 +770,7 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
   while (NR < nb) NR <<= 1;
   ensure_level_vectors(c, NR);
   ensure_pcg_vectors(c, NR);
+  autotune_spmm<T>(c, NR, s);
   const int n = (int)an.n;
   const bool flexible = sizeof(T) == 4;
   launch_gather_cols(n, NR, nb, dv.perm.p, b + (int64_t)c0 * n, n, dv.pb.p, s);
@@ -675,8 +793,7 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
     if (!flexible || restarts >= 2) break;
     // residual replacement (float32 V-cycle): confirm the recursive residual with the true one
     PcgState st = read_state(dv, s);
-    LevelOp<double> op64 = level_op<double>(c, 0);
-    launch_level<double>(op64, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+    apply_level<double>(c, 0, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
     int np = launch_residual(n, NR, dv.pb.p, dv.pq.p, dv.pz.p, dv.partials.p, s);
     std::vector<double> part((size_t)np * NR);
     R3MG_HIP_CHECK(hipMemcpyAsync(part.data(), dv.partials.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -826,17 +943,15 @@ void time_smoother_kernel(HandleImpl& h, int level, int reps, hipStream_t s, dou
   auto run = [&](int count) {
     for (int r = 0; r < count; ++r) {
       if (c.fp32) {
-        LevelOp<float> op = level_op<float>(c, level);
         float* u = vbuf<float>((r & 1) ? D.dB : D.dA);
         float* w = vbuf<float>((r & 1) ? D.dA : D.dB);
-        launch_level<float>(op, 1, u, vbuf<float>(D.b), vbuf<float>(D.rho), vbuf<float>(D.x), w, 0.0, 0.0, fl,
-                            nullptr, s);
+        apply_level<float>(c, level, 1, u, vbuf<float>(D.b), vbuf<float>(D.rho), vbuf<float>(D.x), w, 0.0, 0.0, fl,
+                           nullptr, s);
       } else {
-        LevelOp<double> op = level_op<double>(c, level);
         double* u = vbuf<double>((r & 1) ? D.dB : D.dA);
         double* w = vbuf<double>((r & 1) ? D.dA : D.dB);
-        launch_level<double>(op, 1, u, vbuf<double>(D.b), vbuf<double>(D.rho), vbuf<double>(D.x), w, 0.0, 0.0, fl,
-                             nullptr, s);
+        apply_level<double>(c, level, 1, u, vbuf<double>(D.b), vbuf<double>(D.rho), vbuf<double>(D.x), w, 0.0, 0.0,
+                            fl, nullptr, s);
       }
     }
   };

@@ -168,3 +168,19 @@ def test_device_calls_require_factor():
     assert st == -1          # INVALID: analysed but not factored (nothing touched)
     with pytest.raises(P.R3mgError):
         h.export_level(1)
+
+
+def test_leaf_boxes_not_unisolvent_and_skipping_the_leaf_level():
+    """Section 4 remarks: an agglomerate can hold enough points and still not carry Q^{p'}.  On the 25^3 Q2 cube
+    with leaf 256 and p'=2 some bisection leaves next to the boundary are such boxes; oracle and library report
+    it, and skipping the leaf level (the remedy of the Remark on parameters, used in every experiment of
+    Section 6) gives an admissible hierarchy on which both agree."""
+    prob = F.structured_qp(3, 25, 2, cfg=3)
+    with pytest.raises(O.R3mgError) as eo:
+        O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=2, leaf_size=256)
+    assert eo.value.code == "NOT_UNISOLVENT"
+    with pytest.raises(P.R3mgError) as el:
+        P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val,
+                    P.Options(dim=3, coarse_degree=2, leaf_size=256), factor=False)
+    assert el.value.code == "NOT_UNISOLVENT"
+    _compare_analysis(prob, 2, 256, skip=True)
