@@ -36,7 +36,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU (oracle) baseline leg")
     ap.add_argument("--scale", type=int, default=None, help="override N (cells per side) for quick runs")
     ap.add_argument("--workload", default="solve2d",
-                    choices=["solve2d", "batch16", "uneven8", "adjoint"],
+                    choices=["solve2d", "solve3d", "batch16", "uneven8", "adjoint"],
                     help="solve2d: the headline (591k-DoF Q3 square); batch16: 16-RHS block PCG on the 48^3 Q3 "
                          "cube; uneven8: 8 Q2 cubes of 16^3..48^3 in one graph; adjoint: kappa-gradient on 64^3 Q2")
     ap.add_argument("--fd-cells", type=int, default=32)
@@ -45,7 +45,7 @@ def main():
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    if args.workload != "solve2d":
+    if args.workload not in ("solve2d", "solve3d"):
         {"batch16": bench_batch16, "uneven8": bench_uneven8, "adjoint": bench_adjoint}[args.workload](args)
         return
 
@@ -56,14 +56,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     t0 = time.time()
-    w = F.workload(2, scale=args.scale)
+    w = F.workload(2 if args.workload == "solve2d" else 3, scale=args.scale)
     prob = w.problem
     log(f"inputs: n={prob.n} nnz={prob.nnz} ({time.time() - t0:.1f}s)")
 
     def make(fp32: int):
-        o = P.Options(dim=2, coarse_degree=w.coarse_degree, leaf_size=w.leaf_size, max_levels=w.max_levels,
+        o = P.Options(dim=prob.d, coarse_degree=w.coarse_degree, leaf_size=w.leaf_size, max_levels=w.max_levels,
                       max_coarse_dofs=w.max_coarse_dofs, pre_steps=w.pre_steps, post_steps=w.post_steps,
-                      vcycle_fp32=fp32)
+                      vcycle_fp32=fp32, skip_leaf_level=w.skip_leaf_level)
         ta = time.time()
         h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o, factor=False)
         tb = time.time()
@@ -158,7 +158,8 @@ def main():
         ta = time.time()
         ho = O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=w.coarse_degree, leaf_size=w.leaf_size,
                                max_levels=w.max_levels, max_coarse_dofs=w.max_coarse_dofs,
-                               pre_steps=w.pre_steps, post_steps=w.post_steps)
+                               pre_steps=w.pre_steps, post_steps=w.post_steps,
+                               skip_leaf_level=bool(w.skip_leaf_level))
         t_set = time.time() - ta
         ta = time.time()
         xo, ko, conv, _, _ = O.pcg(ho, w.rhs, rtol=1e-10)
@@ -166,7 +167,7 @@ def main():
         # sparse products run on one thread; the dense coarsest solves use the BLAS pool
         cores = max([d.get("num_threads", 1) for d in threadpoolctl.threadpool_info()] + [1])
         cpu = {"value": prob.n / t_sol, "unit": "DoF/s", "cores": cores, "kind": "oracle",
-               "sample": f"one full FP64 oracle PCG solve of the same 591,361-DoF system (rtol 1e-10, {ko} "
+               "sample": f"one full FP64 oracle PCG solve of the same {prob.n:,}-DoF system (rtol 1e-10, {ko} "
                          f"iterations, {t_sol:.1f}s; oracle set-up {t_set:.1f}s excluded)",
                "iters": ko}
         err = {"fp32_vs_oracle": float(np.linalg.norm(x32 - xo) / np.linalg.norm(xo)),
