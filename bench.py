@@ -22,6 +22,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E peak
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_level_stream_2d_q3_591k.md")
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the fine-level fused kernel from the committed rocprofv3 --pmc summary (FETCH_SIZE
+    and WRITE_SIZE scaled by a plain-copy calibration), or None if the kernel source changed since."""
+    import hashlib
+    try:
+        md = open(TRAFFIC_PROFILE).read()
+        src = open(os.path.join(ROOT, "paper_2607_28235_amd", "csrc", "kernels.hip")).read()
+    except OSError:
+        return None
+    i = src.find("template <typename T, bool DOT>\n__global__ __launch_bounds__(256) void k_level_stream(")
+    j = src.find("template void launch_level_stream<double>", i)
+    if i < 0 or j < 0:
+        return None
+    h = hashlib.sha256(src[i:j].encode()).hexdigest()
+    rec = dict(line.split(": ", 1) for line in md.splitlines() if ": " in line and not line.startswith("|"))
+    if rec.get("kernel_source_sha256", "").strip() != h:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -40,6 +61,8 @@ def main():
                     help="solve2d: the headline (591k-DoF Q3 square); batch16: 16-RHS block PCG on the 48^3 Q3 "
                          "cube; uneven8: 8 Q2 cubes of 16^3..48^3 in one graph; adjoint: kappa-gradient on 64^3 Q2")
     ap.add_argument("--fd-cells", type=int, default=32)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (the HBM-counter calibration kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
@@ -201,12 +224,19 @@ def main():
         "smoother_kernel_per_level_fp32": per_level,
         "solution_rel_diff": err,
         "roofline": {"bound": "hbm", "achieved": kgbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": kgbs / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "k_level<float,1,false> (fine-level fused SpMV + Chebyshev step)",
+                     "frac": kgbs / PEAK_HBM_GBS,
+                     "traffic": recorded_traffic() if (args.workload == "solve2d" and args.scale is None) else None,
+                     "kernel": "k_level_stream<float,false> (fine-level fused SpMV + Chebyshev step)",
                      "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if args.copy_calibration:
+        src = torch.ones(1 << 26, dtype=torch.float32, device=dev)   # 256 MiB read + 256 MiB written per pass
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.mul(src, 1.0, out=dst)                              # plain elementwise copy kernel
+        torch.cuda.synchronize()
 
 
 def _timed(fn, steps, warmup):

@@ -221,6 +221,7 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
 
   // level-1 ownership, local coordinates, unisolvence
   an->leaf_off = offsets[an->depths[0]];
+  an->tree_leaf_off = offsets[an->depth];
   an->constrained.resize(n);
   an->owner.resize(n);
   an->xi.assign(n * d, 0.0);
@@ -373,7 +374,22 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
         }
     }
   }
+  encode_fine(*an);
   return an;
+}
+
+// Row blocks of the fine-level stream kernel: consecutive rows, at most 64 rows and 2048 nonzeros per block
+// (a longer row forms a block of its own).
+void encode_fine(Analysis& an) {
+  const int64_t n = an.n;
+  const int kRows = 64, kCap = 2048;
+  an.rb.assign(1, 0);
+  for (int64_t r = 0; r < n;) {
+    int64_t r1 = r + 1;
+    while (r1 < n && r1 - r < kRows && (int64_t)an.rowptr[r1 + 1] - an.rowptr[r] <= kCap) ++r1;
+    an.rb.push_back((int32_t)r1);
+    r = r1;
+  }
 }
 
 }  // namespace r3mg

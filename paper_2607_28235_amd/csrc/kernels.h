@@ -57,6 +57,11 @@ template <typename T>
 void launch_level_blockrow(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
                            double c2, int flags, const int* skip, hipStream_t s);
 
+// Wide block rows (maxnb * blk large): one workgroup per (box, 8-row chunk).
+template <typename T>
+void launch_level_blockrow_wg(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout,
+                              double c1, double c2, int flags, const int* skip, hipStream_t s);
+
 // q = A p (float64, CSR), per-block partial <p, q> -> partials[blk * nr + k]; returns number of blocks
 int launch_spmv_dot(const LevelOp<double>& op, int nr, const double* p, double* q, double* partials,
                     const int* skip, hipStream_t s);

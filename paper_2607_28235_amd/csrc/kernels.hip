@@ -443,6 +443,86 @@ template void launch_level_blockrow<float>(const LevelOp<float>&, int, const flo
 template void launch_level_blockrow<double>(const LevelOp<double>&, int, const double*, const double*, double*,
                                             double*, double*, double, double, int, const int*, hipStream_t);
 
+// Wide block rows (3D agglomerated levels): one 256-thread workgroup per (box K, chunk of 8 of its B rows),
+// grid = nbox * ceil(B/8).  The workgroup stages the nb*B entries of u touched by box K in LDS, then each wave
+// computes two rows against the LDS copy with coalesced value loads; threads 0..7 apply the epilogue.
+template <typename T>
+__global__ __launch_bounds__(256) void k_level_blockrow_wg(int nbox, int blk, int nchunk, const int* __restrict__ bptr,
+                                                           const int* __restrict__ bcol, const T* __restrict__ val,
+                                                           const T* __restrict__ u, const T* __restrict__ b, T* rho,
+                                                           T* x, const T* __restrict__ dinv, T* dout, T c1, T c2,
+                                                           int flags, const int* __restrict__ skip, int nlog) {
+  if (skip && *skip) return;
+  extern __shared__ unsigned char smem_raw[];
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int K = lb / nchunk;
+  const int q0 = (lb - K * nchunk) * 8;
+  T* xs = reinterpret_cast<T*>(smem_raw);
+  __shared__ T rs[8];
+  const int j0 = bptr[K], nb = bptr[K + 1] - j0;
+  const int w = nb * blk;
+  for (int p = threadIdx.x; p < w; p += 256) {
+    const int j = p / blk, c = p - j * blk;
+    xs[p] = u[(int64_t)bcol[j0 + j] * blk + c];
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int qa = q0 + 2 * wv, qb = qa + 1;
+  const int64_t vb = (int64_t)blk * blk * j0;
+  T a0 = 0, a1 = 0;
+  if (qa < blk) {
+    const T* va = val + vb + (int64_t)qa * w;
+    const bool hb = qb < blk;
+    for (int p = lane; p < w; p += 64) {
+      const T xp = xs[p];
+      a0 += __builtin_nontemporal_load(va + p) * xp;
+      if (hb) a1 += __builtin_nontemporal_load(va + w + p) * xp;
+    }
+  }
+  a0 = wave_sum(a0, 64);
+  a1 = wave_sum(a1, 64);
+  if (lane == 0) {
+    rs[2 * wv] = a0;
+    rs[2 * wv + 1] = a1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8 && q0 + (int)threadIdx.x < blk) {
+    const int row = K * blk + q0 + threadIdx.x;
+    const T t = rs[threadIdx.x];
+    if (flags & F_PLAIN) {
+      rho[row] = t;
+    } else {
+      const T r = ((flags & F_RHO_FROM_B) ? b[row] : rho[row]) - t;
+      if (flags & F_RHO_STORE) rho[row] = r;
+      const T ui = u[row];
+      if (flags & F_X_ASSIGN)
+        x[row] = ui;
+      else if (flags & F_X_ADD)
+        x[row] += ui;
+      if (flags & F_D_OUT) dout[row] = c1 * ui + c2 * dinv[row] * r;
+    }
+  }
+}
+
+template <typename T>
+void launch_level_blockrow_wg(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout,
+                              double c1, double c2, int flags, const int* skip, hipStream_t s) {
+  const int nbox = op.n / op.blk;
+  const int nchunk = (op.blk + 7) / 8;
+  const int nlog = nbox * nchunk;
+  if (nlog == 0) return;
+  const size_t shm = sizeof(T) * (size_t)maxnb * op.blk;
+  if (shm > 65536) throw std::runtime_error("block-row kernel: block row too wide for LDS");
+  hipLaunchKernelGGL((k_level_blockrow_wg<T>), dim3(xcd_grid(nlog)), dim3(256), shm, s, nbox, op.blk, nchunk, op.ptr,
+                     op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
+  check_launch("k_level_blockrow_wg");
+}
+template void launch_level_blockrow_wg<float>(const LevelOp<float>&, int, const float*, const float*, float*, float*,
+                                              float*, double, double, int, const int*, hipStream_t);
+template void launch_level_blockrow_wg<double>(const LevelOp<double>&, int, const double*, const double*, double*,
+                                               double*, double*, double, double, int, const int*, hipStream_t);
+
 // q = A p with per-block partial sums of p.q (float64 CSR)
 template <int NR>
 __global__ __launch_bounds__(256) void k_spmv_dot(int n, int G, const int* __restrict__ ptr,

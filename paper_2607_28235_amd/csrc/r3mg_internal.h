@@ -102,6 +102,9 @@ struct Analysis {
   std::vector<int32_t> order;            // leaf position -> user point (= perm: internal -> user)
   std::vector<int32_t> iperm;            // user -> internal
   std::vector<int64_t> leaf_off;         // internal offsets of the level-1 boxes (nbox1 + 1)
+  std::vector<int64_t> tree_leaf_off;    // internal offsets of the R-tree leaves (depth t)
+  // fine-level row blocks (<= 64 rows, <= 2048 nonzeros)
+  std::vector<int32_t> rb;
   std::vector<uint8_t> constrained;      // internal order
   std::vector<uint8_t> constrained_user; // caller's order
   std::vector<int32_t> owner;            // internal point -> level-1 box, -1 if constrained
@@ -121,6 +124,8 @@ struct Analysis {
 // builds the analysis; throws Error
 std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t* row_ptr,
                                   const int32_t* col_idx, const double* vals, const r3mg_options& opt);
+
+void encode_fine(Analysis& an);
 
 // bisection R-tree (Section 3, Section 4 point-based agglomeration); offsets[k] per depth k
 void bisection_rtree(const double* coords, int64_t n, int d, int leaf, int& depth, std::vector<int32_t>& order,

@@ -139,6 +139,9 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
   DevLevel& D = c.dv.lv[l];
   if (l == 0 && nr == 1 && D.nrb > 0)
     launch_level_stream<T>(D.nrb, D.rb.p, op, u, b, rho, x, dout, c1, c2, flags, skip, nullptr, s);
+  else if (l > 0 && nr == 1 && D.maxnb > 0 && c.an.B >= 8 && (int64_t)D.maxnb * c.an.B >= 256 &&
+           (int64_t)D.maxnb * c.an.B * (int64_t)sizeof(T) <= 65536)
+    launch_level_blockrow_wg<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags, skip, s);
   else if (l > 0 && nr == 1 && D.maxnb > 0 &&
            (int64_t)D.maxnb * c.an.B <= (int64_t)(65536 / sizeof(T) - 256) / 4)
     launch_level_blockrow<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags, skip, s);
@@ -517,25 +520,16 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     std::vector<int32_t> lo(an.leaf_off.begin(), an.leaf_off.end());
     D.leaf_off.upload(lo, s);
     D.lanes = lanes_for((double)an.nnz / (double)an.n);
-    {  // row blocks of the stream kernel: <= kStreamRowsHost rows and <= kStreamCapHost nonzeros each
-      std::vector<int32_t> rb{0};
-      int64_t r = 0;
-      while (r < an.n) {
-        int64_t r1 = r + 1;
-        while (r1 < an.n && r1 - r < kStreamRowsHost && an.rowptr[r1 + 1] - an.rowptr[r] <= kStreamCapHost) ++r1;
-        rb.push_back((int32_t)r1);
-        r = r1;
-      }
-      D.nrb = (int)rb.size() - 1;
-      D.rb.upload(rb, s);
-    }
+    D.nrb = (int)an.rb.size() - 1;
+    D.rb.upload(an.rb, s);
     D.dinv64.alloc(D.n);
     if (fp32) {
       D.xi32.alloc(D.xi64.n);
       launch_cast_d2f((int64_t)D.xi64.n, D.xi64.p, D.xi32.p, s);
     }
     const double sv = fp32 ? 4 : 8;
-    D.bytes_apply = (double)an.nnz * (sv + 4) + (double)(an.n + 1) * 4 + 7.0 * an.n * sv;
+    // values and columns, row pointers, row-block offsets, 7 vector streams
+    D.bytes_apply = (double)an.nnz * (sv + 4) + (double)(an.n + 1) * 4 + 4.0 * an.rb.size() + 7.0 * an.n * sv;
   }
   for (int l = 1; l <= L; ++l) {
     DevLevel& D = dv.lv[l];
