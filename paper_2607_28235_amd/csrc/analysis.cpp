@@ -11,6 +11,7 @@
 // All floating-point decisions (extents, comparisons, unisolvence pivots) are taken in float64; this file is
 // compiled without floating-point contraction so that the transfer values are reproducible.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -334,6 +335,62 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
     H.bcol.resize(H.bptr[H.nbox]);
     for (int64_t k = 0; k < H.nbox; ++k) std::copy(rows[k].begin(), rows[k].end(), H.bcol.begin() + H.bptr[k]);
   }
+  // Galerkin work lists of level 1: for every stored block (K, K') the rows i of K (unconstrained) whose
+  // columns meet box K', with the contiguous run [s, e) of those columns (columns are sorted and boxes are
+  // contiguous in the internal numbering); the kernel visits only these runs.
+  {
+    HostLevel& H = an->lv[1];
+    const int64_t nblk = H.bptr[H.nbox];
+    std::vector<int32_t> box_all(n);
+    for (int64_t k = 0; k < H.nbox; ++k)
+      for (int64_t p = an->leaf_off[k]; p < an->leaf_off[k + 1]; ++p) box_all[p] = (int32_t)k;
+    std::vector<std::vector<std::array<int32_t, 4>>> per(H.nbox);  // (slot, row, s, e)
+    parallel_for(H.nbox, [&](int64_t k) {
+      auto& v = per[k];
+      const int32_t* bc = H.bcol.data() + H.bptr[k];
+      const int64_t nb = H.bptr[k + 1] - H.bptr[k];
+      for (int64_t p = an->leaf_off[k]; p < an->leaf_off[k + 1]; ++p) {
+        if (an->constrained[p]) continue;
+        int32_t q = an->rowptr[p];
+        const int32_t qe = an->rowptr[p + 1];
+        while (q < qe) {
+          const int32_t kb = box_all[an->col[q]];
+          int32_t r = q;
+          bool any = false;
+          while (r < qe && box_all[an->col[r]] == kb) {
+            any |= !an->constrained[an->col[r]];
+            ++r;
+          }
+          if (any) {
+            const int32_t slot = (int32_t)(std::lower_bound(bc, bc + nb, kb) - bc);
+            v.push_back({slot, (int32_t)p, q, r});
+          }
+          q = r;
+        }
+      }
+      std::stable_sort(v.begin(), v.end(), [](const std::array<int32_t, 4>& x, const std::array<int32_t, 4>& y) {
+        return x[0] < y[0];
+      });
+    });
+    an->gal_ptr.assign(nblk + 1, 0);
+    for (int64_t k = 0; k < H.nbox; ++k)
+      for (auto& e : per[k]) an->gal_ptr[H.bptr[k] + e[0] + 1] += 1;
+    for (int64_t b = 0; b < nblk; ++b) an->gal_ptr[b + 1] += an->gal_ptr[b];
+    an->gal_ent.resize((size_t)an->gal_ptr[nblk] * 3);
+    for (int64_t k = 0; k < H.nbox; ++k) {
+      int64_t prev_slot = -1, w = 0;
+      for (auto& e : per[k]) {
+        if (e[0] != prev_slot) {
+          prev_slot = e[0];
+          w = an->gal_ptr[H.bptr[k] + e[0]];
+        }
+        an->gal_ent[w * 3 + 0] = e[1];
+        an->gal_ent[w * 3 + 1] = e[2];
+        an->gal_ent[w * 3 + 2] = e[3];
+        ++w;
+      }
+    }
+  }
   for (int l = 2; l <= L; ++l) {
     HostLevel& P = an->lv[l - 1];
     HostLevel& H = an->lv[l];
@@ -378,17 +435,21 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
   return an;
 }
 
-// Row blocks of the fine-level stream kernel: consecutive rows, at most 64 rows and 2048 nonzeros per block
-// (a longer row forms a block of its own).
+// Row blocks of the fine-level stream kernel, one set per block shape: consecutive rows, at most `rows` rows
+// and `cap` nonzeros per block (a longer row forms a block of its own).
 void encode_fine(Analysis& an) {
   const int64_t n = an.n;
-  const int kRows = 64, kCap = 2048;
-  an.rb.assign(1, 0);
-  for (int64_t r = 0; r < n;) {
-    int64_t r1 = r + 1;
-    while (r1 < n && r1 - r < kRows && (int64_t)an.rowptr[r1 + 1] - an.rowptr[r] <= kCap) ++r1;
-    an.rb.push_back((int32_t)r1);
-    r = r1;
+  const int shapes[3][2] = {{2048, 64}, {4096, 128}, {4096, 64}};
+  for (int sh = 0; sh < 3; ++sh) {
+    const int cap = shapes[sh][0], rows = shapes[sh][1];
+    std::vector<int32_t>& rb = an.rb[sh];
+    rb.assign(1, 0);
+    for (int64_t r = 0; r < n;) {
+      int64_t r1 = r + 1;
+      while (r1 < n && r1 - r < rows && (int64_t)an.rowptr[r1 + 1] - an.rowptr[r] <= cap) ++r1;
+      rb.push_back((int32_t)r1);
+      r = r1;
+    }
   }
 }
 

@@ -42,14 +42,15 @@ template <typename T>
 void launch_level(const LevelOp<T>& op, int nr, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
                   double c2, int flags, const int* skip, hipStream_t s);
 
-// Row-block variant for the CSR fine level and one right-hand side (rb: nrb + 1 row offsets, each block <= 64
-// rows and <= 2048 nonzeros unless it is a single row).  With partials != null (F_PLAIN only) each block also
-// writes the partial sum of u_i (A u)_i to partials[block].
-constexpr int kStreamCapHost = 2048;
-constexpr int kStreamRowsHost = 64;
+// Row-block variant for the CSR fine level and one right-hand side.  Shapes (nonzeros, rows per block):
+// 0 = (2048, 64), 1 = (4096, 128), 2 = (4096, 64); rb holds the nrb + 1 row offsets built for that shape.  With
+// partials != null (F_PLAIN only) each block also writes the partial sum of u_i (A u)_i to partials[block].
+constexpr int kStreamShapes = 3;
+constexpr int kStreamCapOf[kStreamShapes] = {2048, 4096, 4096};
+constexpr int kStreamRowsOf[kStreamShapes] = {64, 128, 64};
 template <typename T>
-void launch_level_stream(int nrb, const int* rb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x, T* dout,
-                         double c1, double c2, int flags, const int* skip, double* partials, hipStream_t s);
+void launch_level_stream(int shape, int nrb, const int* rb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
+                         T* dout, double c1, double c2, int flags, const int* skip, double* partials, hipStream_t s);
 
 // Block-row variant for the agglomerated levels and one right-hand side (one wave per box; maxnb = largest
 // number of stored blocks in a block row).
@@ -103,9 +104,9 @@ void launch_gather_vals(int64_t nnz, const int64_t* src, const double* user_vals
 // set-up kernels
 void launch_diag_inv(int n, int blk, const int* ptr, const int* idx, const double* val, double* dinv, double* diag,
                      int* bad, hipStream_t s);
-void launch_galerkin0(int64_t nblocks, int d, int pc, const int* brow, const int* bptr, const int* bcol,
-                      const int* leaf_off, const int* owner, const double* xi, const int* rowptr, const int* col,
-                      const double* val, double* out, hipStream_t s);
+void launch_galerkin0(int64_t nblocks, int d, int pc, const int* brow, const int* bptr, const int* gal_ptr,
+                      const int* gal_ent, const int* owner, const double* xi, const int* col, const double* val,
+                      double* out, hipStream_t s);
 void launch_galerkin_c(int64_t nblocks, int d, int pc, int shift, int nbox_in, const int* brow, const int* bptr_out,
                        const int* bcol_out, const int* bptr_in, const int* bcol_in, const double* val_in,
                        const double* pt, double* out, hipStream_t s);

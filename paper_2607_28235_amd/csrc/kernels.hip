@@ -230,31 +230,30 @@ template void launch_level<double>(const LevelOp<double>&, int, const double*, c
                                    double*, double, double, int, const int*, hipStream_t);
 
 // Row-block ("stream") variant of the fused kernel for the CSR fine level, one right-hand side.  Each
-// workgroup owns a host-computed block of <= 64 consecutive rows holding <= kStreamCap nonzeros: phase 1
-// streams the block's values and column indices with fully coalesced loads and stages val * u[col] in LDS,
-// phase 2 sums each row with 4 lanes and applies the same epilogue as k_level.  A row longer than kStreamCap
-// forms a block of its own and is summed by the whole workgroup.  With DOT the block also writes the partial
-// sum of u_i * (A u)_i (PCG's <p, A p>).
-constexpr int kStreamCap = 2048;
-constexpr int kStreamRows = 64;
-
-template <typename T, bool DOT>
+// workgroup owns a host-computed block of <= RPB consecutive rows holding <= CAP nonzeros: phase 1 streams the
+// block's values and column indices with fully coalesced loads (all issued before any gather) and stages
+// val * u[col] in LDS, phase 2 sums each row with 256/RPB lanes and applies the same epilogue as k_level.  A row
+// longer than CAP forms a block of its own and is summed by the whole workgroup.  With DOT the block also writes
+// the partial sum of u_i (A u)_i (PCG's <p, A p>).  The (CAP, RPB) shape is chosen per matrix by timing.
+template <typename T, bool DOT, int CAP, int RPB>
 __global__ __launch_bounds__(256) void k_level_stream(int nrb, const int* __restrict__ rb, const int* __restrict__ ptr,
                                                       const int* __restrict__ idx, const T* __restrict__ val,
                                                       const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
                                                       const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
                                                       const int* __restrict__ skip, double* partials) {
+  constexpr int TPR = 256 / RPB;   // lanes per row in phase 2
+  constexpr int EPT = CAP / 256;   // elements per thread in phase 1
   if (skip && *skip) return;
   const int lb = xcd_block(nrb);
   if (lb < 0) return;
-  __shared__ T prod[kStreamCap];
+  __shared__ T prod[CAP];
   __shared__ double sh[4];
   const int r0 = rb[lb], r1 = rb[lb + 1];
   const int e0 = ptr[r0], e1 = ptr[r1];
   const int nz = e1 - e0;
   // epilogue operands of the row this thread may finalise, fetched before the matrix stream
-  const int prow = r0 + (threadIdx.x >> 2);
-  const bool pre = (threadIdx.x & 3) == 0 && prow < r1 && nz <= kStreamCap && !(flags & F_PLAIN);
+  const int prow = r0 + (threadIdx.x / TPR);
+  const bool pre = (threadIdx.x % TPR) == 0 && prow < r1 && nz <= CAP && !(flags & F_PLAIN);
   T p_old = 0, p_x = 0, p_u = 0, p_di = 0;
   if (pre) {
     p_old = (flags & F_RHO_FROM_B) ? b[prow] : rho[prow];
@@ -264,13 +263,12 @@ __global__ __launch_bounds__(256) void k_level_stream(int nrb, const int* __rest
   }
   T t = 0;
   int row = -1;
-  if (nz <= kStreamCap) {
-    // all loads of the block issued before any gather (8 elements per thread: kStreamCap = 8 * 256); the
-    // matrix is streamed once per application, so its loads bypass the caches' retention (non-temporal)
-    int ci[kStreamCap / 256];
-    T vv[kStreamCap / 256];
+  if (nz <= CAP) {
+    // the matrix is streamed once per application: non-temporal loads keep u resident in the caches
+    int ci[EPT];
+    T vv[EPT];
 #pragma unroll
-    for (int m = 0; m < kStreamCap / 256; ++m) {
+    for (int m = 0; m < EPT; ++m) {
       const int e = threadIdx.x + m * 256;
       if (e < nz) {
         ci[m] = __builtin_nontemporal_load(idx + e0 + e);
@@ -278,19 +276,19 @@ __global__ __launch_bounds__(256) void k_level_stream(int nrb, const int* __rest
       }
     }
 #pragma unroll
-    for (int m = 0; m < kStreamCap / 256; ++m) {
+    for (int m = 0; m < EPT; ++m) {
       const int e = threadIdx.x + m * 256;
       if (e < nz) prod[e] = vv[m] * u[ci[m]];
     }
     __syncthreads();
-    const int rl = threadIdx.x >> 2, sub = threadIdx.x & 3;
+    const int rl = threadIdx.x / TPR, sub = threadIdx.x % TPR;
     T acc = 0;
     if (r0 + rl < r1) {
       const int s = ptr[r0 + rl] - e0, e = ptr[r0 + rl + 1] - e0;
-      for (int k = s + sub; k < e; k += 4) acc += prod[k];
+      for (int k = s + sub; k < e; k += TPR) acc += prod[k];
     }
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
+#pragma unroll
+    for (int off = TPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (sub == 0 && r0 + rl < r1) {
       row = r0 + rl;
       t = acc;
@@ -334,21 +332,33 @@ __global__ __launch_bounds__(256) void k_level_stream(int nrb, const int* __rest
   }
 }
 
-template <typename T>
-void launch_level_stream(int nrb, const int* rb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x, T* dout,
-                         double c1, double c2, int flags, const int* skip, double* partials, hipStream_t s) {
-  if (nrb == 0) return;
+template <typename T, int CAP, int RPB>
+static void launch_stream_shape(int nrb, const int* rb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
+                                T* dout, double c1, double c2, int flags, const int* skip, double* partials,
+                                hipStream_t s) {
   if (partials)
-    hipLaunchKernelGGL((k_level_stream<T, true>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, rb, op.ptr, op.idx, op.val,
-                       u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, partials);
+    hipLaunchKernelGGL((k_level_stream<T, true, CAP, RPB>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, rb, op.ptr,
+                       op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, partials);
   else
-    hipLaunchKernelGGL((k_level_stream<T, false>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, rb, op.ptr, op.idx,
-                       op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, partials);
+    hipLaunchKernelGGL((k_level_stream<T, false, CAP, RPB>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, rb, op.ptr,
+                       op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, partials);
+}
+
+template <typename T>
+void launch_level_stream(int shape, int nrb, const int* rb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
+                         T* dout, double c1, double c2, int flags, const int* skip, double* partials, hipStream_t s) {
+  if (nrb == 0) return;
+  switch (shape) {
+    case 0: launch_stream_shape<T, 2048, 64>(nrb, rb, op, u, b, rho, x, dout, c1, c2, flags, skip, partials, s); break;
+    case 1: launch_stream_shape<T, 4096, 128>(nrb, rb, op, u, b, rho, x, dout, c1, c2, flags, skip, partials, s); break;
+    case 2: launch_stream_shape<T, 4096, 64>(nrb, rb, op, u, b, rho, x, dout, c1, c2, flags, skip, partials, s); break;
+    default: throw std::runtime_error("unknown row-block shape");
+  }
   check_launch("k_level_stream");
 }
-template void launch_level_stream<float>(int, const int*, const LevelOp<float>&, const float*, const float*, float*,
-                                         float*, float*, double, double, int, const int*, double*, hipStream_t);
-template void launch_level_stream<double>(int, const int*, const LevelOp<double>&, const double*, const double*,
+template void launch_level_stream<float>(int, int, const int*, const LevelOp<float>&, const float*, const float*,
+                                         float*, float*, float*, double, double, int, const int*, double*, hipStream_t);
+template void launch_level_stream<double>(int, int, const int*, const LevelOp<double>&, const double*, const double*,
                                           double*, double*, double*, double, double, int, const int*, double*,
                                           hipStream_t);
 
@@ -995,83 +1005,95 @@ void launch_diag_inv(int n, int blk, const int* ptr, const int* idx, const doubl
 }
 
 // Galerkin product, fine -> first agglomerated level (Section 4, inherited operators):
-// A1[K,K'] = sum_{i in K, j in K', i,j free} A_ij phi^K(x_i) phi^K'(x_j)^T.
-// One workgroup per stored output block; each thread owns up to EMAX entries (q, q') of the block and walks the
-// rows of K and, in each row, the contiguous run of columns owned by K' (columns are sorted and the internal
-// numbering is box-contiguous).  Fixed summation order: deterministic.
+// A1[K,K'] = sum_{i in K free} phi^K(x_i) T_i^T,  T_i[q'] = sum_{j in K' free} A_ij phi^K'_q'(x_j).
+// One 256-thread workgroup per stored output block.  The host lists, per block, the rows i of K whose sorted
+// columns meet box K' with the column run [s, e).  Eight 32-lane groups take eight entries at a time: group g
+// evaluates phi^K(x_i) and T_i into LDS; then every thread adds sum_g phi_g[q] T_g[q'] to the entries (q, q') it
+// owns.  The summation order is fixed (deterministic).
 template <int EMAX>
 __global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, const int* __restrict__ brow,
-                                                   const int* __restrict__ bptr, const int* __restrict__ bcol,
-                                                   const int* __restrict__ leaf_off, const int* __restrict__ owner,
-                                                   const double* __restrict__ xi, const int* __restrict__ rowptr,
-                                                   const int* __restrict__ col, const double* __restrict__ val,
-                                                   double* out) {
+                                                   const int* __restrict__ bptr, const int* __restrict__ gal_ptr,
+                                                   const int* __restrict__ gal_ent, const int* __restrict__ owner,
+                                                   const double* __restrict__ xi, const int* __restrict__ col,
+                                                   const double* __restrict__ val, double* out) {
+  __shared__ double spi[8][64];
+  __shared__ double sT[8][64];
   const int64_t blkid = blockIdx.x;
   const int K = brow[blkid];
   const int slot = (int)(blkid - bptr[K]);
   const int nbK = bptr[K + 1] - bptr[K];
-  const int Kp = bcol[blkid];
   const int k = bs.k;
   const int B = (d == 3) ? k * k * k : k * k;
-  const int cl = leaf_off[Kp], ch = leaf_off[Kp + 1];
   int qi[EMAX], qj[EMAX];
-  double acc[EMAX], pi[EMAX];
+  double acc[EMAX];
 #pragma unroll
   for (int m = 0; m < EMAX; ++m) {
-    const int e = threadIdx.x + m * blockDim.x;
+    const int e = threadIdx.x + m * 256;
     qi[m] = e < B * B ? e / B : -1;
     qj[m] = e < B * B ? e % B : 0;
     acc[m] = 0;
   }
-  for (int i = leaf_off[K]; i < leaf_off[K + 1]; ++i) {
-    if (owner[i] < 0) continue;
-    double li[3][4];
-    for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)i * d + a], li[a]);
-#pragma unroll
-    for (int m = 0; m < EMAX; ++m) pi[m] = qi[m] >= 0 ? phi_q<double>(li, d, k, qi[m]) : 0.0;
-    int lo = rowptr[i], hi = rowptr[i + 1];
-    const int end = hi;
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      if (col[mid] < cl) lo = mid + 1; else hi = mid;
+  const int g = threadIdx.x >> 5, lt = threadIdx.x & 31;
+  const int en0 = gal_ptr[blkid], en1 = gal_ptr[blkid + 1];
+  for (int base = en0; base < en1; base += 8) {
+    const int ent = base + g;
+    if (ent < en1) {
+      const int i = gal_ent[3 * ent], s = gal_ent[3 * ent + 1], e = gal_ent[3 * ent + 2];
+      double li[3][4];
+      for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)i * d + a], li[a]);
+      for (int q = lt; q < B; q += 32) spi[g][q] = phi_q<double>(li, d, k, q);
+      for (int q = lt; q < B; q += 32) {
+        double t = 0;
+        for (int p = s; p < e; ++p) {
+          const int j = col[p];
+          if (owner[j] < 0) continue;
+          double lj[3][4];
+          for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)j * d + a], lj[a]);
+          t += val[p] * phi_q<double>(lj, d, k, q);
+        }
+        sT[g][q] = t;
+      }
+    } else {
+      for (int q = lt; q < B; q += 32) {
+        spi[g][q] = 0.0;
+        sT[g][q] = 0.0;
+      }
     }
-    for (int p = lo; p < end; ++p) {
-      const int j = col[p];
-      if (j >= ch) break;
-      if (owner[j] < 0) continue;
-      const double a = val[p];
-      double lj[3][4];
-      for (int ax = 0; ax < d; ++ax) lag1d(bs, xi[(int64_t)j * d + ax], lj[ax]);
+    __syncthreads();
 #pragma unroll
-      for (int m = 0; m < EMAX; ++m)
-        if (qi[m] >= 0) acc[m] += a * pi[m] * phi_q<double>(lj, d, k, qj[m]);
+    for (int m = 0; m < EMAX; ++m) {
+      if (qi[m] >= 0) {
+        double sacc = 0;
+#pragma unroll
+        for (int gg = 0; gg < 8; ++gg) sacc += spi[gg][qi[m]] * sT[gg][qj[m]];
+        acc[m] += sacc;
+      }
     }
+    __syncthreads();
   }
-  const int64_t base = (int64_t)B * B * bptr[K];
+  const int64_t obase = (int64_t)B * B * bptr[K];
 #pragma unroll
   for (int m = 0; m < EMAX; ++m)
-    if (qi[m] >= 0) out[base + (int64_t)qi[m] * nbK * B + (int64_t)slot * B + qj[m]] = acc[m];
+    if (qi[m] >= 0) out[obase + (int64_t)qi[m] * nbK * B + (int64_t)slot * B + qj[m]] = acc[m];
 }
 
-void launch_galerkin0(int64_t nblocks, int d, int pc, const int* brow, const int* bptr, const int* bcol,
-                      const int* leaf_off, const int* owner, const double* xi, const int* rowptr, const int* col,
-                      const double* val, double* out, hipStream_t s) {
+void launch_galerkin0(int64_t nblocks, int d, int pc, const int* brow, const int* bptr, const int* gal_ptr,
+                      const int* gal_ent, const int* owner, const double* xi, const int* col, const double* val,
+                      double* out, hipStream_t s) {
   const int k = pc + 1;
   const int B = (d == 3) ? k * k * k : k * k;
   const int bb = B * B;
   Basis1D<double> bs = make_basis<double>(pc);
   if (nblocks == 0) return;
-  if (bb <= 256) {
-    int threads = ((bb + 63) / 64) * 64;
-    hipLaunchKernelGGL((k_galerkin0<1>), dim3((unsigned)nblocks), dim3(threads), 0, s, d, bs, brow, bptr, bcol,
-                       leaf_off, owner, xi, rowptr, col, val, out);
-  } else if (bb <= 768) {
-    hipLaunchKernelGGL((k_galerkin0<3>), dim3((unsigned)nblocks), dim3(256), 0, s, d, bs, brow, bptr, bcol, leaf_off,
-                       owner, xi, rowptr, col, val, out);
-  } else {
-    hipLaunchKernelGGL((k_galerkin0<16>), dim3((unsigned)nblocks), dim3(256), 0, s, d, bs, brow, bptr, bcol, leaf_off,
-                       owner, xi, rowptr, col, val, out);
-  }
+  if (bb <= 256)
+    hipLaunchKernelGGL((k_galerkin0<1>), dim3((unsigned)nblocks), dim3(256), 0, s, d, bs, brow, bptr, gal_ptr, gal_ent,
+                       owner, xi, col, val, out);
+  else if (bb <= 768)
+    hipLaunchKernelGGL((k_galerkin0<3>), dim3((unsigned)nblocks), dim3(256), 0, s, d, bs, brow, bptr, gal_ptr, gal_ent,
+                       owner, xi, col, val, out);
+  else
+    hipLaunchKernelGGL((k_galerkin0<16>), dim3((unsigned)nblocks), dim3(256), 0, s, d, bs, brow, bptr, gal_ptr,
+                       gal_ent, owner, xi, col, val, out);
   check_launch("k_galerkin0");
 }
 

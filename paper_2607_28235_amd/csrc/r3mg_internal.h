@@ -103,8 +103,8 @@ struct Analysis {
   std::vector<int32_t> iperm;            // user -> internal
   std::vector<int64_t> leaf_off;         // internal offsets of the level-1 boxes (nbox1 + 1)
   std::vector<int64_t> tree_leaf_off;    // internal offsets of the R-tree leaves (depth t)
-  // fine-level row blocks (<= 64 rows, <= 2048 nonzeros)
-  std::vector<int32_t> rb;
+  // fine-level row blocks of the three stream-kernel shapes (2048/64, 4096/128, 4096/64 nonzeros/rows)
+  std::vector<int32_t> rb[3];
   std::vector<uint8_t> constrained;      // internal order
   std::vector<uint8_t> constrained_user; // caller's order
   std::vector<int32_t> owner;            // internal point -> level-1 box, -1 if constrained
@@ -118,6 +118,8 @@ struct Analysis {
   std::vector<int32_t> user_col;         // the caller's pattern (for assembly)
   std::vector<int64_t> user_rowptr;
   std::vector<HostLevel> lv;             // lv[0] unused (fine level); lv[l] for l = 1..L
+  std::vector<int32_t> gal_ptr;          // level-1 Galerkin work lists: per stored block, entries (row, s, e)
+  std::vector<int32_t> gal_ent;
   int nlevels() const { return (int)depths.size() + 1; }
 };
 
@@ -150,8 +152,9 @@ struct DevLevel {
   DBuf<float> dinv32;
   double lam_hi = 0, lam_lo = 0, lam_hat = 0;
   int lanes = 8;  // lanes per row of the SpMV kernels
-  DBuf<int32_t> rb;  // l = 0: row blocks of the single-RHS stream kernel
-  int nrb = 0;
+  DBuf<int32_t> rb[3];  // l = 0: row blocks of the single-RHS stream kernel, per block shape
+  int nrb[3] = {0, 0, 0};
+  int shape = 0;        // l = 0: block shape chosen by timing at set-up
   int maxnb = 0;     // l >= 1: largest number of stored blocks in a block row
   // transfer to the next level
   DBuf<double> xi64;     // l = 0: n x d
@@ -159,6 +162,7 @@ struct DevLevel {
   DBuf<int32_t> owner;   // l = 0: n (level-1 box of each point, -1 if constrained)
   DBuf<int32_t> leaf_off;  // l = 0: nbox1 + 1 internal offsets of the level-1 boxes
   DBuf<int32_t> brow;    // l >= 1 during set-up: block -> block row
+  DBuf<int32_t> gal_ptr, gal_ent;  // l = 1: Galerkin work lists
   DBuf<double> pt64;     // l >= 1 (l < L): nbox x d x (p'+1)^2
   DBuf<float> pt32;
   int child_shift = 0;   // level l >= 2: 2^child_shift boxes of level l-1 per box
@@ -189,7 +193,8 @@ struct Device {
   std::map<int, hipGraphExec_t> graphs;
   std::map<int, hipGraph_t> graph_defs;
   hipStream_t cap_stream = nullptr;
-  void* pinned = nullptr;  // host pinned buffer for flags
+  void* pinned = nullptr;  // host pinned buffer: PcgState copy + two convergence-flag slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
   // autotuned SpMM lanes per (level, nrhs)
   std::map<std::pair<int, int>, int> tuned;
   ~Device();

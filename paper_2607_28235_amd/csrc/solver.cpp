@@ -95,6 +95,8 @@ void drop_graphs(Device& dv) {
 
 Device::~Device() {
   drop_graphs(*this);
+  for (auto e : ev)
+    if (e) (void)hipEventDestroy(e);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (pinned) (void)hipHostFree(pinned);
 }
@@ -137,8 +139,9 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
                  const int* skip, hipStream_t s) {
   LevelOp<T> op = level_op<T>(c, l);
   DevLevel& D = c.dv.lv[l];
-  if (l == 0 && nr == 1 && D.nrb > 0)
-    launch_level_stream<T>(D.nrb, D.rb.p, op, u, b, rho, x, dout, c1, c2, flags, skip, nullptr, s);
+  if (l == 0 && nr == 1 && D.nrb[D.shape] > 0)
+    launch_level_stream<T>(D.shape, D.nrb[D.shape], D.rb[D.shape].p, op, u, b, rho, x, dout, c1, c2, flags, skip,
+                           nullptr, s);
   else if (l > 0 && nr == 1 && D.maxnb > 0 && c.an.B >= 8 && (int64_t)D.maxnb * c.an.B >= 256 &&
            (int64_t)D.maxnb * c.an.B * (int64_t)sizeof(T) <= 65536)
     launch_level_blockrow_wg<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags, skip, s);
@@ -186,14 +189,15 @@ static void ensure_pcg_vectors(Ctx& c, int nr) {
     const int64_t nlog_spmv = (n + rpb - 1) / rpb;
     const int64_t nlog_vec = (n + 255) / 256;
     dv.partials.alloc(std::max<size_t>({(size_t)4096, (size_t)(nlog_spmv * nr), (size_t)(nlog_vec * 2 * nr),
-                                        (size_t)dv.lv[0].nrb}));
+                                        (size_t)dv.lv[0].nrb[0], (size_t)dv.lv[0].nrb[1],
+                                        (size_t)dv.lv[0].nrb[2]}));
     drop_graphs(dv);
   }
   if (!dv.state.p) {
     dv.state.alloc(sizeof(PcgState));
     R3MG_HIP_CHECK(hipMemset(dv.state.p, 0, sizeof(PcgState)));
   }
-  if (!dv.pinned) R3MG_HIP_CHECK(hipHostMalloc(&dv.pinned, sizeof(PcgState), hipHostMallocDefault));
+  if (!dv.pinned) R3MG_HIP_CHECK(hipHostMalloc(&dv.pinned, sizeof(PcgState) + 64, hipHostMallocDefault));
 }
 
 // Multi-RHS SpMM tile autotuner: the lanes-per-row tile of every level kernel (and of PCG's float64 SpMV) is
@@ -452,8 +456,8 @@ void numeric_setup(HandleImpl& h, hipStream_t s) {
     const int64_t nblk = H.bptr[H.nbox];
     if (l == 1) {
       DevLevel& F0 = dv.lv[0];
-      launch_galerkin0(nblk, an.d, an.pc, D.brow.p, D.bptr.p, D.bcol.p, F0.leaf_off.p, F0.owner.p, F0.xi64.p,
-                       F0.rowptr.p, F0.col.p, F0.val64.p, D.val64.p, s);
+      launch_galerkin0(nblk, an.d, an.pc, D.brow.p, D.bptr.p, D.gal_ptr.p, D.gal_ent.p, F0.owner.p, F0.xi64.p,
+                       F0.col.p, F0.val64.p, D.val64.p, s);
     } else {
       DevLevel& P = dv.lv[l - 1];
       launch_galerkin_c(nblk, an.d, an.pc, H.child_shift, (int)P.nbox, D.brow.p, D.bptr.p, D.bcol.p, P.bptr.p,
@@ -494,6 +498,44 @@ void numeric_setup(HandleImpl& h, hipStream_t s) {
   drop_graphs(dv);
 }
 
+// Fine-level row-block shape: each candidate shape runs the V-cycle-precision smoother step on level 0 (3
+// warm-up + 5 timed launches, hipEvents); the fastest is kept for every later single-RHS application.
+static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
+  Analysis& an = *h.an;
+  Device& dv = *h.dev;
+  Ctx c{an, dv, an.opt.vcycle_fp32 != 0};
+  ensure_level_vectors(c, 1);
+  DevLevel& D = dv.lv[0];
+  const int fl = F_RHO_STORE | F_X_ADD | F_D_OUT;
+  float best = 1e30f;
+  int bestS = 0;
+  for (int sh = 0; sh < kStreamShapes; ++sh) {
+    float ms;
+    if (c.fp32) {
+      LevelOp<float> op = level_op<float>(c, 0);
+      ms = time_launches(s, 5, [&] {
+        launch_level_stream<float>(sh, D.nrb[sh], D.rb[sh].p, op, vbuf<float>(D.dA), vbuf<float>(D.b),
+                                   vbuf<float>(D.rho), vbuf<float>(D.x), vbuf<float>(D.dB), 0.0, 0.0, fl, nullptr,
+                                   nullptr, s);
+      });
+    } else {
+      LevelOp<double> op = level_op<double>(c, 0);
+      ms = time_launches(s, 5, [&] {
+        launch_level_stream<double>(sh, D.nrb[sh], D.rb[sh].p, op, vbuf<double>(D.dA), vbuf<double>(D.b),
+                                    vbuf<double>(D.rho), vbuf<double>(D.x), vbuf<double>(D.dB), 0.0, 0.0, fl, nullptr,
+                                    nullptr, s);
+      });
+    }
+    if (ms < best) {
+      best = ms;
+      bestS = sh;
+    }
+  }
+  D.shape = bestS;
+  R3MG_HIP_CHECK(hipMemsetAsync(D.x.p, 0, D.x.n, s));
+  R3MG_HIP_CHECK(hipMemsetAsync(D.rho.p, 0, D.rho.n, s));
+}
+
 void device_setup(HandleImpl& h, hipStream_t s) {
   Analysis& an = *h.an;
   h.dev = std::make_unique<Device>();
@@ -520,8 +562,10 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     std::vector<int32_t> lo(an.leaf_off.begin(), an.leaf_off.end());
     D.leaf_off.upload(lo, s);
     D.lanes = lanes_for((double)an.nnz / (double)an.n);
-    D.nrb = (int)an.rb.size() - 1;
-    D.rb.upload(an.rb, s);
+    for (int sh = 0; sh < kStreamShapes; ++sh) {
+      D.nrb[sh] = (int)an.rb[sh].size() - 1;
+      D.rb[sh].upload(an.rb[sh], s);
+    }
     D.dinv64.alloc(D.n);
     if (fp32) {
       D.xi32.alloc(D.xi64.n);
@@ -529,7 +573,7 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     }
     const double sv = fp32 ? 4 : 8;
     // values and columns, row pointers, row-block offsets, 7 vector streams
-    D.bytes_apply = (double)an.nnz * (sv + 4) + (double)(an.n + 1) * 4 + 4.0 * an.rb.size() + 7.0 * an.n * sv;
+    D.bytes_apply = (double)an.nnz * (sv + 4) + (double)(an.n + 1) * 4 + 4.0 * an.rb[0].size() + 7.0 * an.n * sv;
   }
   for (int l = 1; l <= L; ++l) {
     DevLevel& D = dv.lv[l];
@@ -545,6 +589,10 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     for (int64_t k = 0; k < H.nbox; ++k)
       for (int64_t j = H.bptr[k]; j < H.bptr[k + 1]; ++j) br[j] = (int32_t)k;
     D.brow.upload(br, s);
+    if (l == 1) {
+      D.gal_ptr.upload(an.gal_ptr, s);
+      D.gal_ent.upload(an.gal_ent, s);
+    }
     D.val64.alloc((size_t)D.nnz);
     D.dinv64.alloc(D.n);
     D.child_shift = H.child_shift;
@@ -561,6 +609,7 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     D.bytes_apply = (double)D.nnz * sv + (double)nblk * 4 + (double)(H.nbox + 1) * 4 + 7.0 * D.n * sv;
   }
   numeric_setup(h, s);
+  tune_stream_shape(h, s);
   R3MG_HIP_CHECK(hipStreamSynchronize(s));
 }
 
@@ -654,12 +703,12 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
   LevelOp<double> op64 = level_op<double>(c, 0);
   const int n = (int)an.n;
   need_partials(dv, (int64_t)((n + 255) / 256) * 2 * NR);
-  need_partials(dv, D0.nrb);
+  need_partials(dv, D0.nrb[D0.shape]);
   int np;
-  if (NR == 1 && D0.nrb > 0) {
-    launch_level_stream<double>(D0.nrb, D0.rb.p, op64, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN,
-                                skip, dv.partials.p, s);
-    np = D0.nrb;
+  if (NR == 1 && D0.nrb[D0.shape] > 0) {
+    launch_level_stream<double>(D0.shape, D0.nrb[D0.shape], D0.rb[D0.shape].p, op64, dv.pp.p, nullptr, dv.pq.p,
+                                nullptr, nullptr, 0, 0, F_PLAIN, skip, dv.partials.p, s);
+    np = D0.nrb[D0.shape];
   } else {
     auto it = dv.tuned.find({-1, NR * 2});
     if (it != dv.tuned.end()) op64.lanes = it->second;
@@ -775,14 +824,34 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
   if (an.opt.use_graph) ex = iteration_graph<T>(c, NR, flexible);
   int k = 0;
   bool done = read_all_done(dv, s) != 0;
+  // The host stays one iteration ahead of the device: iteration k+1 is enqueued before the convergence flag of
+  // iteration k is read back (its kernels skip themselves once the flag is set), so the device never idles
+  // waiting for the host between iterations.
+  volatile int* slot = reinterpret_cast<volatile int*>(static_cast<char*>(dv.pinned) + sizeof(PcgState));
+  if (!dv.ev[0]) {
+    R3MG_HIP_CHECK(hipEventCreateWithFlags(&dv.ev[0], hipEventDisableTiming));
+    R3MG_HIP_CHECK(hipEventCreateWithFlags(&dv.ev[1], hipEventDisableTiming));
+  }
+  auto launch_one = [&]() {
+    if (ex)
+      R3MG_HIP_CHECK(hipGraphLaunch(ex, s));
+    else
+      pcg_iteration<T>(c, NR, flexible, s);
+    ++k;
+    R3MG_HIP_CHECK(hipMemcpyAsync(const_cast<int*>(&slot[k & 1]), dv.state.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    R3MG_HIP_CHECK(hipEventRecord(dv.ev[k & 1], s));
+  };
   for (;;) {
-    while (!done && k < maxit) {
-      if (ex)
-        R3MG_HIP_CHECK(hipGraphLaunch(ex, s));
-      else
-        pcg_iteration<T>(c, NR, flexible, s);
-      ++k;
-      done = read_all_done(dv, s) != 0;
+    if (!done && k < maxit) {
+      launch_one();
+      while (true) {
+        const int waiting = k;
+        if (k < maxit) launch_one();  // speculative next iteration
+        R3MG_HIP_CHECK(hipEventSynchronize(dv.ev[waiting & 1]));
+        done = slot[waiting & 1] != 0;
+        if (done || waiting == k) break;  // converged, or maxit reached with nothing more in flight
+      }
+      R3MG_HIP_CHECK(hipStreamSynchronize(s));
     }
     if (!flexible || restarts >= 2) break;
     // residual replacement (float32 V-cycle): confirm the recursive residual with the true one
