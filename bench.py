@@ -25,24 +25,26 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E peak
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_level_stream_2d_q3_591k.md")
 
 
-def recorded_traffic():
+def recorded_traffic(kernel: str):
     """HBM bytes per launch of the fine-level fused kernel from the committed rocprofv3 --pmc summary (FETCH_SIZE
-    and WRITE_SIZE scaled by a plain-copy calibration), or None if the kernel source changed since."""
+    and WRITE_SIZE scaled by a plain-copy calibration), or None if the kernel source changed since or the
+    summary covers another row-block shape than the one this run chose."""
     import hashlib
     try:
         md = open(TRAFFIC_PROFILE).read()
         src = open(os.path.join(ROOT, "paper_2607_28235_amd", "csrc", "kernels.hip")).read()
     except OSError:
         return None
-    i = src.find("template <typename T, bool DOT>\n__global__ __launch_bounds__(256) void k_level_stream(")
+    i = src.find("template <typename T, bool DOT, int CAP, int RPB>\n__global__ __launch_bounds__(256) void k_level_stream(")
     j = src.find("template void launch_level_stream<double>", i)
     if i < 0 or j < 0:
         return None
     h = hashlib.sha256(src[i:j].encode()).hexdigest()
     rec = dict(line.split(": ", 1) for line in md.splitlines() if ": " in line and not line.startswith("|"))
-    if rec.get("kernel_source_sha256", "").strip() != h:
+    key = f"traffic[{kernel}]"
+    if rec.get("kernel_source_sha256", "").strip() != h or key not in rec:
         return None
-    return float(rec["traffic_bytes_per_launch"])
+    return float(rec[key])
 
 
 def log(*a):
@@ -168,7 +170,8 @@ def main():
     per_level = []
     for l in range(len(info) - 1):
         ms_l, by_l = h32.time_smoother_kernel(l, 100)
-        per_level.append({"level": l, "n": info[l]["n"], "nnz": info[l]["nnz"], "us_per_launch": ms_l * 1e3,
+        per_level.append({"level": l, "kernel": info[l]["kernel"], "n": info[l]["n"], "nnz": info[l]["nnz"],
+                          "us_per_launch": ms_l * 1e3,
                           "bytes_per_launch": by_l, "GBps": by_l / (ms_l * 1e-3) / 1e9})
     log(f"level-0 fp32 smoother kernel: {kms * 1e3:.1f} us, {kgbs:.0f} GB/s")
 
@@ -184,14 +187,20 @@ def main():
                                pre_steps=w.pre_steps, post_steps=w.post_steps,
                                skip_leaf_level=bool(w.skip_leaf_level))
         t_set = time.time() - ta
-        ta = time.time()
-        xo, ko, conv, _, _ = O.pcg(ho, w.rhs, rtol=1e-10)
-        t_sol = time.time() - ta
+        # repeat the whole solve until about 10 s of CPU work have been timed (one solve takes ~1 s)
+        reps, t_tot = 0, 0.0
+        while t_tot < 10.0 and reps < 30:
+            ta = time.time()
+            xo, ko, conv, _, _ = O.pcg(ho, w.rhs, rtol=1e-10)
+            t_tot += time.time() - ta
+            reps += 1
+        t_sol = t_tot / reps
         # sparse products run on one thread; the dense coarsest solves use the BLAS pool
         cores = max([d.get("num_threads", 1) for d in threadpoolctl.threadpool_info()] + [1])
         cpu = {"value": prob.n / t_sol, "unit": "DoF/s", "cores": cores, "kind": "oracle",
-               "sample": f"one full FP64 oracle PCG solve of the same {prob.n:,}-DoF system (rtol 1e-10, {ko} "
-                         f"iterations, {t_sol:.1f}s; oracle set-up {t_set:.1f}s excluded)",
+               "sample": f"{reps} full FP64 oracle PCG solves of the same {prob.n:,}-DoF system (rtol 1e-10, {ko} "
+                         f"iterations, {t_tot:.1f}s in total, {t_sol:.2f}s each; oracle set-up {t_set:.1f}s "
+                         f"excluded)",
                "iters": ko}
         err = {"fp32_vs_oracle": float(np.linalg.norm(x32 - xo) / np.linalg.norm(xo)),
                "fp64_vs_oracle": float(np.linalg.norm(x64 - xo) / np.linalg.norm(xo))}
@@ -225,8 +234,9 @@ def main():
         "solution_rel_diff": err,
         "roofline": {"bound": "hbm", "achieved": kgbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": kgbs / PEAK_HBM_GBS,
-                     "traffic": recorded_traffic() if (args.workload == "solve2d" and args.scale is None) else None,
-                     "kernel": "k_level_stream<float,false> (fine-level fused SpMV + Chebyshev step)",
+                     "traffic": (recorded_traffic(info[0]["kernel"])
+                                 if (args.workload == "solve2d" and args.scale is None) else None),
+                     "kernel": info[0]["kernel"] + " (fine-level fused SpMV + Chebyshev step)",
                      "bytes_per_launch": kbytes, "us_per_launch": kms * 1e3},
         "cpu_baseline": cpu,
     }

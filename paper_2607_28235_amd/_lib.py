@@ -44,7 +44,8 @@ class _Options(C.Structure):
 
 class _LevelInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("nboxes", C.c_int64), ("max_box_extent", C.c_double),
-                ("lambda_hi", C.c_double), ("lambda_lo", C.c_double), ("bytes_per_apply", C.c_double)]
+                ("lambda_hi", C.c_double), ("lambda_lo", C.c_double), ("bytes_per_apply", C.c_double),
+                ("kernel", C.c_char * 48)]
 
 
 @dataclasses.dataclass
@@ -228,7 +229,8 @@ class Hierarchy:
         _check(lib().r3mg_info(self._h, None, C.byref(n)), "r3mg_info")
         arr = (_LevelInfo * n.value)()
         _check(lib().r3mg_info(self._h, arr, C.byref(n)), "r3mg_info")
-        return [{f: getattr(a, f) for f, _ in _LevelInfo._fields_} for a in arr]
+        return [{f: (getattr(a, f).decode() if f == "kernel" else getattr(a, f)) for f, _ in _LevelInfo._fields_}
+                for a in arr]
 
     @property
     def nlevels(self) -> int:

@@ -1,6 +1,7 @@
 // C ABI of the R3MG-C library: argument checking, error mapping, exports and the kappa assembler.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -204,13 +205,17 @@ r3mg_status r3mg_info(r3mg_handle h, r3mg_level_info* levels, int* nlevels) {
         }
         if (h->impl.factored) {
           const DevLevel& D = h->impl.dev->lv[l];
+          std::string kn;
           if (l < nl - 1) {
             I.lambda_hi = D.lam_hi;
             I.lambda_lo = D.lam_lo;
             I.bytes_per_apply = D.bytes_apply;
+            kn = level_kernel_name(an, D, l, an.opt.vcycle_fp32 ? 4 : 8);
           } else {
             I.bytes_per_apply = (double)D.n * D.n * 8.0;
+            kn = "dense";
           }
+          std::snprintf(I.kernel, sizeof(I.kernel), "%s", kn.c_str());
         }
       }
     }

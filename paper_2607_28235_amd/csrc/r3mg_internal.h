@@ -207,6 +207,11 @@ struct HandleImpl {
   DBuf<unsigned char> cons_user_dev;  // constrained mask in the caller's order (adjoint gradient)
 };
 
+// kernel family that applies a level operator (solver.cpp chooses; r3mg_info reports it)
+enum class LevelKernel { Stream, BlockRowWG, BlockRow, Lanes };
+LevelKernel level_kernel(const Analysis& an, const DevLevel& D, int l, int nr, int esz);
+std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int esz);
+
 // solver entry points (solver.cpp)
 void device_setup(HandleImpl& h, hipStream_t s);
 void update_values(HandleImpl& h, const double* vals_dev, hipStream_t s);
