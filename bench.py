@@ -35,7 +35,7 @@ def recorded_traffic(kernel: str):
         src = open(os.path.join(ROOT, "paper_2607_28235_amd", "csrc", "kernels.hip")).read()
     except OSError:
         return None
-    i = src.find("template <typename T, bool DOT, int CAP, int RPB>\n__global__ __launch_bounds__(256) void k_level_stream(")
+    i = src.find("template <typename T, bool DOT, int CAP, int RPB, bool VEC>\n__global__ __launch_bounds__(256) void k_level_stream(")
     j = src.find("template void launch_level_stream<double>", i)
     if i < 0 or j < 0:
         return None

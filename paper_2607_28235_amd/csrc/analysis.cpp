@@ -18,6 +18,7 @@
 #include <numeric>
 #include <thread>
 
+#include "kernels.h"
 #include "r3mg_internal.h"
 
 namespace r3mg {
@@ -129,7 +130,8 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
   if (pc < 0 || pc > 3) throw err(R3MG_ERR_INVALID, "coarse_degree must be in 0..3");
   if (opt.leaf_size < 1 || opt.max_levels < 0 || opt.max_levels == 1 || opt.max_coarse_dofs < 1 ||
       opt.cheb_degree < 1 || opt.pre_steps < 0 || opt.post_steps < 0 || opt.lanczos_steps < 1 ||
-      !(opt.cheb_boost > 0.0) || !(opt.cheb_ratio > 1.0))
+      !(opt.cheb_boost > 0.0) || !(opt.cheb_ratio > 1.0) || opt.fine_kernel < -1 ||
+      opt.fine_kernel >= kStreamShapes)
     throw err(R3MG_ERR_INVALID, "invalid option value");
   if (n < 1 || n >= (int64_t(1) << 31)) throw err(R3MG_ERR_INVALID, "n out of range");
   if (!coords || !row_ptr || !col_idx || !vals) throw err(R3MG_ERR_INVALID, "null input");
@@ -435,14 +437,14 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
   return an;
 }
 
-// Row blocks of the fine-level stream kernel, one set per block shape: consecutive rows, at most `rows` rows
-// and `cap` nonzeros per block (a longer row forms a block of its own).
-void encode_fine(Analysis& an) {
+// Row blocks of the fine-level CSR row-block kernels, one set per geometry: consecutive rows, at most `rows` rows
+// and `cap` - 3 nonzeros per block (the 16-byte loads start up to 3 entries before the block); a longer row forms
+// a block of its own.
+static void encode_csr_blocks(Analysis& an) {
   const int64_t n = an.n;
-  const int shapes[3][2] = {{2048, 64}, {4096, 128}, {4096, 64}};
-  for (int sh = 0; sh < 3; ++sh) {
-    const int cap = shapes[sh][0], rows = shapes[sh][1];
-    std::vector<int32_t>& rb = an.rb[sh];
+  for (int g = 0; g < kCsrGeoms; ++g) {
+    const int cap = kStreamCapOf[g] - 3, rows = kStreamRowsOf[g];
+    std::vector<int32_t>& rb = an.rb[g];
     rb.assign(1, 0);
     for (int64_t r = 0; r < n;) {
       int64_t r1 = r + 1;
@@ -451,6 +453,86 @@ void encode_fine(Analysis& an) {
       r = r1;
     }
   }
+}
+
+// Local-column row blocks of geometry g: rows are taken greedily (within independent row segments) while the
+// block stays within `rows` rows, `cap` - 3 nonzeros and `ucap` distinct columns; the distinct columns are listed
+// in ascending order and every nonzero stores the position of its column in the list.  A single row beyond
+// the limits forms a block of its own with its full column list (the kernel reads such a block through the
+// CSR columns).
+static void encode_local_blocks(Analysis& an, int g) {
+  const int64_t n = an.n;
+  const int cap = kLocalCap[g] - 3, rows = kLocalRows[g], ucap = kLocalUcap[g], ib = kLocalIdxBytes[g];
+  const int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(256, n / 4096));
+  struct Seg {
+    std::vector<int32_t> ends, ucnt, ucol;
+  };
+  std::vector<Seg> segs((size_t)nseg);
+  std::vector<uint8_t>& lidx = an.lidx[g];
+  lidx.assign((size_t)(an.nnz + kFinePad) * ib, 0);  // padding: the pipelined kernel's 4-byte loads
+  parallel_for(nseg, [&](int64_t sg) {
+    static thread_local std::vector<uint8_t> mark;
+    static thread_local std::vector<int32_t> pos;
+    if ((int64_t)mark.size() < n) {
+      mark.assign((size_t)n, 0);
+      pos.assign((size_t)n, 0);
+    }
+    Seg& S = segs[(size_t)sg];
+    const int64_t ra = sg * n / nseg, rz = (sg + 1) * n / nseg;
+    std::vector<int32_t> uq;
+    for (int64_t r = ra; r < rz;) {
+      uq.clear();
+      int64_t r1 = r, nz = 0;
+      while (r1 < rz && r1 - r < rows) {
+        const int32_t a = an.rowptr[r1], b = an.rowptr[r1 + 1];
+        int64_t add = 0;
+        for (int32_t e = a; e < b; ++e) add += mark[an.col[e]] ? 0 : 1;
+        if (r1 > r && (nz + (b - a) > cap || (int64_t)uq.size() + add > ucap)) break;
+        for (int32_t e = a; e < b; ++e)
+          if (!mark[an.col[e]]) {
+            mark[an.col[e]] = 1;
+            uq.push_back(an.col[e]);
+          }
+        nz += b - a;
+        ++r1;
+      }
+      std::sort(uq.begin(), uq.end());
+      for (size_t i = 0; i < uq.size(); ++i) {
+        pos[uq[i]] = (int32_t)i;
+        mark[uq[i]] = 0;
+      }
+      if ((int64_t)uq.size() <= ucap)
+        for (int32_t e = an.rowptr[r]; e < an.rowptr[r1]; ++e) {
+          const int32_t li = pos[an.col[e]];
+          if (ib == 1)
+            lidx[(size_t)e] = (uint8_t)li;
+          else
+            std::memcpy(&lidx[(size_t)e * 2], &li, 2);  // little-endian low half
+        }
+      S.ends.push_back((int32_t)r1);
+      S.ucnt.push_back((int32_t)uq.size());
+      S.ucol.insert(S.ucol.end(), uq.begin(), uq.end());
+      r = r1;
+    }
+  });
+  std::vector<int32_t>& rb = an.lrb[g];
+  std::vector<int32_t>& ubp = an.lubp[g];
+  std::vector<int32_t>& ucol = an.lucol[g];
+  rb.assign(1, 0);
+  ubp.assign(1, 0);
+  ucol.clear();
+  for (const Seg& S : segs) {
+    for (size_t k = 0; k < S.ends.size(); ++k) {
+      rb.push_back(S.ends[k]);
+      ubp.push_back(ubp.back() + S.ucnt[k]);
+    }
+    ucol.insert(ucol.end(), S.ucol.begin(), S.ucol.end());
+  }
+}
+
+void encode_fine(Analysis& an) {
+  encode_csr_blocks(an);
+  for (int g = 0; g < kLocalGeoms; ++g) encode_local_blocks(an, g);
 }
 
 }  // namespace r3mg

@@ -42,15 +42,45 @@ template <typename T>
 void launch_level(const LevelOp<T>& op, int nr, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
                   double c2, int flags, const int* skip, hipStream_t s);
 
-// Row-block variant for the CSR fine level and one right-hand side.  Shapes (nonzeros, rows per block):
-// 0 = (2048, 64), 1 = (4096, 128), 2 = (4096, 64); rb holds the nrb + 1 row offsets built for that shape.  With
-// partials != null (F_PLAIN only) each block also writes the partial sum of u_i (A u)_i to partials[block].
-constexpr int kStreamShapes = 3;
-constexpr int kStreamCapOf[kStreamShapes] = {2048, 4096, 4096};
-constexpr int kStreamRowsOf[kStreamShapes] = {64, 128, 64};
+// Fine-level row blocks of one kernel shape (device pointers).  A block is a run of consecutive rows.  CSR
+// shapes use rb only; local-column shapes also carry, per block, its distinct columns ucol[ubp[b] .. ubp[b+1])
+// (ascending) and, per nonzero, the position of its column in that list (lidx: 1 or 2 bytes per nonzero).  A
+// block whose distinct columns exceed the shape's staging capacity holds a single row and is read through the
+// CSR column array.
+struct FineBlocks {
+  int nrb = 0;
+  const int* rb = nullptr;
+  const int* ubp = nullptr;
+  const int* ucol = nullptr;
+  const void* lidx = nullptr;
+};
+
+// Fine-level row-block kernel for one right-hand side.  Shapes:
+//   0..2  CSR blocks, one workgroup per block; geometry (staging capacity in nonzeros, rows per block)
+//         (2048, 64), (4096, 128), (4096, 64); blocks of several rows hold at most capacity - 3 nonzeros;
+//   3..5  the same blocks, persistent and software-pipelined with 16-byte matrix loads (the column and value
+//         arrays must carry kFinePad zero entries after the last nonzero);
+//   6..8  local-column blocks, one workgroup per block: (1-byte indices, 2048 nonzeros, 64 rows, 256 distinct
+//         columns), (2-byte, 4096, 64, 1024), (2-byte, 4096, 128, 1024); blocks of several rows hold at most
+//         capacity - 3 nonzeros;
+//   9     the blocks of shape 6 with 16-byte value loads and 4-byte loads of four packed positions (values and
+//         positions must carry kFinePad padding entries).
+// With partials != null (F_PLAIN only; shapes 0..8) the launch writes partial sums of u_i (A u)_i to
+// partials[0..np) and returns np (<= fb.nrb).
+constexpr int kCsrGeoms = 3;
+constexpr int kStreamShapes = 10;
+constexpr int kLocalFirst = 6;
+constexpr int kStreamCapOf[kCsrGeoms] = {2048, 4096, 4096};
+constexpr int kStreamRowsOf[kCsrGeoms] = {64, 128, 64};
+constexpr int kLocalGeoms = 3;
+constexpr int kLocalCap[kLocalGeoms] = {2048, 4096, 4096};
+constexpr int kLocalRows[kLocalGeoms] = {64, 64, 128};
+constexpr int kLocalUcap[kLocalGeoms] = {256, 1024, 1024};
+constexpr int kLocalIdxBytes[kLocalGeoms] = {1, 2, 2};
+constexpr int kFinePad = 4;
 template <typename T>
-void launch_level_stream(int shape, int nrb, const int* rb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
-                         T* dout, double c1, double c2, int flags, const int* skip, double* partials, hipStream_t s);
+int launch_level_stream(int shape, const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
+                        T* dout, double c1, double c2, int flags, const int* skip, double* partials, hipStream_t s);
 
 // Block-row variant for the agglomerated levels and one right-hand side (one wave per box; maxnb = largest
 // number of stored blocks in a block row).
@@ -113,6 +143,8 @@ void launch_galerkin_c(int64_t nblocks, int d, int pc, int shift, int nbox_in, c
 void launch_to_dense(int nbox, int B, const int* bptr, const int* bcol, const double* val, double* dense,
                      hipStream_t s);
 void launch_lanczos_start(int n, const int* perm, double* v, hipStream_t s);
+// partial sums of p_i q_i for one PCG column in a fixed partition (returns the count, <= 1024)
+int launch_pcg_dot(int n, const double* p, const double* q, double* partials, const int* skip, hipStream_t s);
 // partial sums of w_i x_i y_i (w may be null) -> partials (returns count)
 int launch_dot(int64_t n, const double* w, const double* x, const double* y, double* partials, hipStream_t s);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);   // y = a x + b y

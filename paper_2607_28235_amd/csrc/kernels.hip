@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <algorithm>
 #include <stdexcept>
 #include <string>
 
@@ -229,12 +230,36 @@ template void launch_level<float>(const LevelOp<float>&, int, const float*, cons
 template void launch_level<double>(const LevelOp<double>&, int, const double*, const double*, double*, double*,
                                    double*, double, double, int, const int*, hipStream_t);
 
+// Sum of the staged products prod[s..e) of one row by TPR consecutive lanes (TPR = 4 or 2) in one canonical
+// order, the same for every row-block shape: a_v = prod[s+v] + prod[s+v+4] + ... (v = 0..3, in increasing
+// position), row sum = (a_0 + a_2) + (a_1 + a_3).  With TPR = 2 each lane carries two of the four partial sums.
+// Lane sub = 0 of the group holds the result.
+template <typename T, int TPR>
+__device__ inline T row_sum_canonical(const T* prod, int s, int e, int sub) {
+  static_assert(TPR == 4 || TPR == 2, "lanes per row");
+  if constexpr (TPR == 4) {
+    T a = 0;
+    for (int k = s + sub; k < e; k += 4) a += prod[k];
+    a += __shfl_xor(a, 2, 64);
+    a += __shfl_xor(a, 1, 64);
+    return a;
+  } else {
+    T a = 0, c = 0;
+    for (int k = s + sub; k < e; k += 4) a += prod[k];
+    for (int k = s + sub + 2; k < e; k += 4) c += prod[k];
+    T t = a + c;
+    t += __shfl_xor(t, 1, 64);
+    return t;
+  }
+}
+
 // Row-block ("stream") variant of the fused kernel for the CSR fine level, one right-hand side.  Each
-// workgroup owns a host-computed block of <= RPB consecutive rows holding <= CAP nonzeros: phase 1 streams the
-// block's values and column indices with fully coalesced loads (all issued before any gather) and stages
+// workgroup owns a host-computed block of <= RPB consecutive rows holding <= CAP - 3 nonzeros: phase 1 streams
+// the block's values and column indices with fully coalesced loads (all issued before any gather) and stages
 // val * u[col] in LDS, phase 2 sums each row with 256/RPB lanes and applies the same epilogue as k_level.  A row
 // longer than CAP forms a block of its own and is summed by the whole workgroup.  With DOT the block also writes
-// the partial sum of u_i (A u)_i (PCG's <p, A p>).  The (CAP, RPB) shape is chosen per matrix by timing.
+// the partial sum of u_i (A u)_i (PCG's <p, A p>).  The (CAP, RPB) shape and the kernel form are chosen per
+// matrix by timing.
 template <typename T, bool DOT, int CAP, int RPB>
 __global__ __launch_bounds__(256) void k_level_stream(int nrb, const int* __restrict__ rb, const int* __restrict__ ptr,
                                                       const int* __restrict__ idx, const T* __restrict__ val,
@@ -282,13 +307,12 @@ __global__ __launch_bounds__(256) void k_level_stream(int nrb, const int* __rest
     }
     __syncthreads();
     const int rl = threadIdx.x / TPR, sub = threadIdx.x % TPR;
-    T acc = 0;
+    int s = 0, e = 0;
     if (r0 + rl < r1) {
-      const int s = ptr[r0 + rl] - e0, e = ptr[r0 + rl + 1] - e0;
-      for (int k = s + sub; k < e; k += TPR) acc += prod[k];
+      s = ptr[r0 + rl] - e0;
+      e = ptr[r0 + rl + 1] - e0;
     }
-#pragma unroll
-    for (int off = TPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    const T acc = row_sum_canonical<T, TPR>(prod, s, e, sub);
     if (sub == 0 && r0 + rl < r1) {
       row = r0 + rl;
       t = acc;
@@ -332,35 +356,535 @@ __global__ __launch_bounds__(256) void k_level_stream(int nrb, const int* __rest
   }
 }
 
+// Persistent, software-pipelined row-block kernel with 16-byte matrix loads.  Workgroup w owns the contiguous
+// row blocks [w nrb / nwg, (w + 1) nrb / nwg) and, while it sums block i, has the matrix stream of block i + 1 in
+// flight: per block the gathers of u and the per-row operands are issued before the next block's stream, so
+// waiting for them (memory counters retire in order) never waits for the prefetch.  Products are staged in two
+// alternating LDS buffers, so one barrier per block suffices.  (i) Each thread streams four consecutive entries per step, starting from the
+// block's first entry rounded down to a multiple of four (entries outside the block are masked; the column and
+// value arrays carry four padding entries at the end), and stages the four products with one aligned LDS write
+// at their offset from that rounded start; (ii) each wave loads the row pointers of its rows once and spreads
+// them with lane shuffles; (iii) the row sums go to LDS and the epilogue of a block runs one iteration later in
+// wave 0, one row per lane with coalesced loads and stores (its operands are fetched before the next stream).
+// Same summation order as the other row-block kernels.
+template <typename T>
+struct Vec4 {
+  typedef T type __attribute__((ext_vector_type(4)));
+};
+typedef int i4v __attribute__((ext_vector_type(4)));
+
+template <typename T, bool DOT, int CAP, int RPB>
+__global__ __launch_bounds__(256) void k_level_stream_pv(int nrb, int nwg, const int* __restrict__ rb,
+                                                         const int* __restrict__ ptr, const int* __restrict__ idx,
+                                                         const T* __restrict__ val, const T* __restrict__ u,
+                                                         const T* __restrict__ b, T* rho, T* x,
+                                                         const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
+                                                         const int* __restrict__ skip, double* partials) {
+  using V4 = typename Vec4<T>::type;
+  constexpr int TPR = 256 / RPB;  // lanes per row
+  constexpr int RPW = 64 / TPR;   // rows per wave
+  constexpr int NCH = CAP / 1024; // four-entry chunks per thread
+  constexpr int EPL = RPB / 64;   // epilogue rows per lane of wave 0
+  static_assert(RPB % 64 == 0 && CAP % 1024 == 0, "row-block shape");
+  if (skip && *skip) return;
+  const int w = xcd_block(nwg);
+  if (w < 0) return;
+  const int lbA = (int)((int64_t)w * nrb / nwg), lbB = (int)((int64_t)(w + 1) * nrb / nwg);
+  __shared__ __align__(32) T prod[2][CAP];
+  __shared__ T rsum[2][RPB];
+  __shared__ T shr[2][4];
+  __shared__ double sh[4];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rl = threadIdx.x / TPR, sub = threadIdx.x % TPR;
+  double contrib = 0.0;
+  int r0 = 0, r1 = 0, e0 = 0, e1 = 0;
+  i4v ci[NCH];
+  V4 vv[NCH];
+  if (lbA < lbB) {
+    r0 = rb[lbA];
+    r1 = rb[lbA + 1];
+    e0 = ptr[r0];
+    e1 = ptr[r1];
+    const int a0 = e0 & ~3;
+    if (e1 - a0 <= CAP) {
+#pragma unroll
+      for (int m = 0; m < NCH; ++m) {
+        const int e = a0 + 4 * (threadIdx.x + m * 256);
+        if (e < e1) {
+          ci[m] = __builtin_nontemporal_load(reinterpret_cast<const i4v*>(idx + e));
+          vv[m] = __builtin_nontemporal_load(reinterpret_cast<const V4*>(val + e));
+        }
+      }
+    }
+  }
+  int pr0 = 0, pr1 = 0;  // rows of the block whose epilogue is pending
+  int it = 0;
+  for (int lb = lbA; lb < lbB; ++lb, it ^= 1) {
+    const int a0 = e0 & ~3;
+    const bool staged = e1 - a0 <= CAP;
+    // (a) everything this block and the pending epilogue still read
+    V4 g[NCH];
+    if (staged) {
+#pragma unroll
+      for (int m = 0; m < NCH; ++m) {
+        const int e = a0 + 4 * (threadIdx.x + m * 256);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[m][q] = (e + q >= e0 && e + q < e1) ? u[ci[m][q]] : (T)0;
+      }
+    }
+    int rp = e1;
+    if (lane <= RPW) {
+      const int rr = r0 + wv * RPW + lane;
+      rp = ptr[rr < r1 ? rr : r1];
+    }
+    T eo[EPL], eu[EPL], ex[EPL], ed[EPL];
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      eo[q] = eu[q] = ex[q] = ed[q] = 0;
+      const int row = pr0 + lane + 64 * q;
+      if (wv == 0 && row < pr1) {
+        eu[q] = u[row];
+        if (!(flags & F_PLAIN)) {
+          eo[q] = (flags & F_RHO_FROM_B) ? b[row] : rho[row];
+          if (flags & F_X_ADD) ex[q] = x[row];
+          if (flags & F_D_OUT) ed[q] = dinv[row];
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // (b) the next block's matrix stream
+    int nr0 = 0, nr1 = 0, ne0 = 0, ne1 = 0;
+    i4v nci[NCH];
+    V4 nvv[NCH];
+    if (lb + 1 < lbB) {
+      nr0 = r1;
+      nr1 = rb[lb + 2];
+      ne0 = e1;
+      ne1 = ptr[nr1];
+      const int na0 = ne0 & ~3;
+      if (ne1 - na0 <= CAP) {
+#pragma unroll
+        for (int m = 0; m < NCH; ++m) {
+          const int e = na0 + 4 * (threadIdx.x + m * 256);
+          if (e < ne1) {
+            nci[m] = __builtin_nontemporal_load(reinterpret_cast<const i4v*>(idx + e));
+            nvv[m] = __builtin_nontemporal_load(reinterpret_cast<const V4*>(val + e));
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // (c) row sums of this block into rsum[it]
+    if (staged) {
+#pragma unroll
+      for (int m = 0; m < NCH; ++m) {
+        const int e = a0 + 4 * (threadIdx.x + m * 256);
+        if (e < e1) *reinterpret_cast<V4*>(&prod[it][e - a0]) = vv[m] * g[m];
+      }
+      const int rs = __shfl(rp, lane / TPR, 64), re = __shfl(rp, lane / TPR + 1, 64);
+      __syncthreads();
+      const T acc = row_sum_canonical<T, TPR>(prod[it], rs - a0, re - a0, sub);
+      if (sub == 0) rsum[it][rl] = acc;
+    } else {  // one long row
+      T acc = 0;
+      for (int e = e0 + threadIdx.x; e < e1; e += 256) acc += val[e] * u[idx[e]];
+      acc = wave_sum(acc, 64);
+      if (lane == 0) shr[it][wv] = acc;
+      __syncthreads();
+      if (threadIdx.x == 0) rsum[it][0] = (shr[it][0] + shr[it][1]) + (shr[it][2] + shr[it][3]);
+    }
+    // (d) epilogue of the previous block (its row sums were published by the barrier above)
+    if (wv == 0) {
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) {
+        const int row = pr0 + lane + 64 * q;
+        if (row < pr1) {
+          const T t = rsum[it ^ 1][lane + 64 * q];
+          if (flags & F_PLAIN) {
+            rho[row] = t;
+            if (DOT) contrib += (double)t * (double)eu[q];
+          } else {
+            const T r = eo[q] - t;
+            if (flags & F_RHO_STORE) rho[row] = r;
+            if (flags & F_X_ASSIGN)
+              x[row] = eu[q];
+            else if (flags & F_X_ADD)
+              x[row] = ex[q] + eu[q];
+            if (flags & F_D_OUT) dout[row] = c1 * eu[q] + c2 * ed[q] * r;
+          }
+        }
+      }
+    }
+    pr0 = r0;
+    pr1 = r1;
+    r0 = nr0;
+    r1 = nr1;
+    e0 = ne0;
+    e1 = ne1;
+#pragma unroll
+    for (int m = 0; m < NCH; ++m) {
+      ci[m] = nci[m];
+      vv[m] = nvv[m];
+    }
+  }
+  // epilogue of the last block
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      const int row = pr0 + lane + 64 * q;
+      if (row < pr1) {
+        const T t = rsum[it ^ 1][lane + 64 * q];
+        const T uu = u[row];
+        if (flags & F_PLAIN) {
+          rho[row] = t;
+          if (DOT) contrib += (double)t * (double)uu;
+        } else {
+          const T r = ((flags & F_RHO_FROM_B) ? b[row] : rho[row]) - t;
+          if (flags & F_RHO_STORE) rho[row] = r;
+          if (flags & F_X_ASSIGN)
+            x[row] = uu;
+          else if (flags & F_X_ADD)
+            x[row] = x[row] + uu;
+          if (flags & F_D_OUT) dout[row] = c1 * uu + c2 * dinv[row] * r;
+        }
+      }
+    }
+  }
+  if (DOT) {
+    const double s = block_sum256(contrib, sh);
+    if (threadIdx.x == 0) partials[w] = s;
+  }
+}
+
+// Local-column row-block kernel (one workgroup per block).  The block's distinct columns are gathered once into
+// LDS (us); the matrix stream then carries the values and 1- or 2-byte positions into that list instead of 4-byte
+// column indices, and each product reads its u entry from LDS.  Phase 2 and the epilogue are those of
+// k_level_stream, with the same summation order.  A block with more than UCAP distinct columns is a single row,
+// summed by the whole workgroup through the CSR columns.
+template <typename T, typename IX, bool DOT, int CAP, int RPB, int UCAP>
+__global__ __launch_bounds__(256) void k_level_local(int nrb, const int* __restrict__ rb, const int* __restrict__ ubp,
+                                                     const int* __restrict__ ucol, const IX* __restrict__ lidx,
+                                                     const int* __restrict__ ptr, const int* __restrict__ idx,
+                                                     const T* __restrict__ val, const T* __restrict__ u,
+                                                     const T* __restrict__ b, T* rho, T* x,
+                                                     const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
+                                                     const int* __restrict__ skip, double* partials) {
+  constexpr int TPR = 256 / RPB;
+  constexpr int EPT = CAP / 256;
+  constexpr int UPT = (UCAP + 255) / 256;
+  if (skip && *skip) return;
+  const int lb = xcd_block(nrb);
+  if (lb < 0) return;
+  __shared__ T us[UCAP];
+  __shared__ T prod[CAP];
+  __shared__ double sh[4];
+  const int r0 = rb[lb], r1 = rb[lb + 1];
+  const int e0 = ptr[r0], e1 = ptr[r1];
+  const int nz = e1 - e0;
+  const int u0 = ubp[lb], nu = ubp[lb + 1] - u0;
+  const bool staged = nu <= UCAP;
+  const int prow = r0 + (threadIdx.x / TPR);
+  const bool pre = (threadIdx.x % TPR) == 0 && prow < r1 && staged && !(flags & F_PLAIN);
+  T p_old = 0, p_x = 0, p_u = 0, p_di = 0;
+  if (pre) {
+    p_old = (flags & F_RHO_FROM_B) ? b[prow] : rho[prow];
+    p_u = u[prow];
+    if (flags & F_X_ADD) p_x = x[prow];
+    if (flags & F_D_OUT) p_di = dinv[prow];
+  }
+  T t = 0;
+  int row = -1;
+  if (staged) {
+    T ug[UPT];
+#pragma unroll
+    for (int m = 0; m < UPT; ++m) {
+      const int c = threadIdx.x + m * 256;
+      if (c < nu) ug[m] = u[ucol[u0 + c]];
+    }
+    IX li[EPT];
+    T vv[EPT];
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int e = threadIdx.x + m * 256;
+      if (e < nz) {
+        li[m] = __builtin_nontemporal_load(lidx + e0 + e);
+        vv[m] = __builtin_nontemporal_load(val + e0 + e);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < UPT; ++m) {
+      const int c = threadIdx.x + m * 256;
+      if (c < nu) us[c] = ug[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int e = threadIdx.x + m * 256;
+      if (e < nz) prod[e] = vv[m] * us[li[m]];
+    }
+    __syncthreads();
+    const int rl = threadIdx.x / TPR, sub = threadIdx.x % TPR;
+    int s = 0, e = 0;
+    if (r0 + rl < r1) {
+      s = ptr[r0 + rl] - e0;
+      e = ptr[r0 + rl + 1] - e0;
+    }
+    const T acc = row_sum_canonical<T, TPR>(prod, s, e, sub);
+    if (sub == 0 && r0 + rl < r1) {
+      row = r0 + rl;
+      t = acc;
+    }
+  } else {  // one long row
+    T acc = 0;
+    for (int e = e0 + threadIdx.x; e < e1; e += 256) acc += val[e] * u[idx[e]];
+    acc = wave_sum(acc, 64);
+    __shared__ T shr[4];
+    if ((threadIdx.x & 63) == 0) shr[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      row = r0;
+      t = (shr[0] + shr[1]) + (shr[2] + shr[3]);
+    }
+  }
+  double contrib = 0.0;
+  if (row >= 0) {
+    if (flags & F_PLAIN) {
+      rho[row] = t;
+      if (DOT) contrib = (double)t * (double)u[row];
+    } else {
+      if (!pre) {
+        p_old = (flags & F_RHO_FROM_B) ? b[row] : rho[row];
+        p_u = u[row];
+        if (flags & F_X_ADD) p_x = x[row];
+        if (flags & F_D_OUT) p_di = dinv[row];
+      }
+      const T r = p_old - t;
+      if (flags & F_RHO_STORE) rho[row] = r;
+      if (flags & F_X_ASSIGN)
+        x[row] = p_u;
+      else if (flags & F_X_ADD)
+        x[row] = p_x + p_u;
+      if (flags & F_D_OUT) dout[row] = c1 * p_u + c2 * p_di * r;
+    }
+  }
+  if (DOT) {
+    const double s = block_sum256(contrib, sh);
+    if (threadIdx.x == 0) partials[lb] = s;
+  }
+}
+
+// Local-column kernel with vector loads (1-byte column positions, one workgroup per block).  As k_level_local,
+// but each thread streams four consecutive entries per step (16-byte value loads, 4-byte loads of four packed
+// positions) from the block's first entry rounded down to a multiple of four (outside entries masked; values and
+// positions carry kFinePad padding entries), stages the four products with one aligned LDS write, and each wave
+// loads its rows' row pointers once and spreads them with lane shuffles.
+template <typename T, int CAP, int RPB, int UCAP>
+__global__ __launch_bounds__(256) void k_level_local_vec(int nrb, const int* __restrict__ rb,
+                                                         const int* __restrict__ ubp, const int* __restrict__ ucol,
+                                                         const uint8_t* __restrict__ lidx, const int* __restrict__ ptr,
+                                                         const int* __restrict__ idx, const T* __restrict__ val,
+                                                         const T* __restrict__ u, const T* __restrict__ b, T* rho,
+                                                         T* x, const T* __restrict__ dinv, T* dout, T c1, T c2,
+                                                         int flags, const int* __restrict__ skip) {
+  using V4 = typename Vec4<T>::type;
+  constexpr int TPR = 256 / RPB;
+  constexpr int RPW = 64 / TPR;
+  constexpr int NCH = CAP / 1024;
+  constexpr int UPT = UCAP / 256;
+  static_assert(CAP % 1024 == 0 && UCAP % 256 == 0, "local block shape");
+  if (skip && *skip) return;
+  const int lb = xcd_block(nrb);
+  if (lb < 0) return;
+  __shared__ T us[UCAP];
+  __shared__ __align__(32) T prod[CAP];
+  __shared__ T shr[4];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = rb[lb], r1 = rb[lb + 1];
+  const int e0 = ptr[r0], e1 = ptr[r1];
+  const int u0 = ubp[lb], nu = ubp[lb + 1] - u0;
+  const bool staged = nu <= UCAP;
+  const int rl = threadIdx.x / TPR, sub = threadIdx.x % TPR;
+  const int prow = r0 + rl;
+  const bool pre = sub == 0 && prow < r1 && !(flags & F_PLAIN);
+  T p_old = 0, p_x = 0, p_u = 0, p_di = 0;
+  if (pre) {
+    p_old = (flags & F_RHO_FROM_B) ? b[prow] : rho[prow];
+    p_u = u[prow];
+    if (flags & F_X_ADD) p_x = x[prow];
+    if (flags & F_D_OUT) p_di = dinv[prow];
+  }
+  T t = 0;
+  if (staged) {
+    T ug[UPT];
+#pragma unroll
+    for (int m = 0; m < UPT; ++m) {
+      const int c = threadIdx.x + m * 256;
+      if (c < nu) ug[m] = u[ucol[u0 + c]];
+    }
+    const int a0 = e0 & ~3;
+    uint32_t li[NCH];
+    V4 vv[NCH];
+#pragma unroll
+    for (int m = 0; m < NCH; ++m) {
+      const int e = a0 + 4 * (threadIdx.x + m * 256);
+      if (e < e1) {
+        li[m] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(lidx + e));
+        vv[m] = __builtin_nontemporal_load(reinterpret_cast<const V4*>(val + e));
+      }
+    }
+    int rp = e1;
+    if (lane <= RPW) {
+      const int rr = r0 + wv * RPW + lane;
+      rp = ptr[rr < r1 ? rr : r1];
+    }
+#pragma unroll
+    for (int m = 0; m < UPT; ++m) {
+      const int c = threadIdx.x + m * 256;
+      if (c < nu) us[c] = ug[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NCH; ++m) {
+      const int e = a0 + 4 * (threadIdx.x + m * 256);
+      if (e < e1) {
+        V4 g;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = (e + q >= e0 && e + q < e1) ? us[(li[m] >> (8 * q)) & 0xff] : (T)0;
+        *reinterpret_cast<V4*>(&prod[e - a0]) = vv[m] * g;
+      }
+    }
+    const int rs = __shfl(rp, lane / TPR, 64), re = __shfl(rp, lane / TPR + 1, 64);
+    __syncthreads();
+    t = row_sum_canonical<T, TPR>(prod, rs - a0, re - a0, sub);
+  } else {  // one long row
+    T acc = 0;
+    for (int e = e0 + threadIdx.x; e < e1; e += 256) acc += val[e] * u[idx[e]];
+    acc = wave_sum(acc, 64);
+    if (lane == 0) shr[wv] = acc;
+    __syncthreads();
+    t = (shr[0] + shr[1]) + (shr[2] + shr[3]);
+  }
+  if (sub == 0 && prow < r1 && (staged || rl == 0)) {
+    const int row = prow;
+    if (flags & F_PLAIN) {
+      rho[row] = t;
+    } else {
+      const T r = p_old - t;
+      if (flags & F_RHO_STORE) rho[row] = r;
+      if (flags & F_X_ASSIGN)
+        x[row] = p_u;
+      else if (flags & F_X_ADD)
+        x[row] = p_x + p_u;
+      if (flags & F_D_OUT) dout[row] = c1 * p_u + c2 * p_di * r;
+    }
+  }
+}
+
 template <typename T, int CAP, int RPB>
-static void launch_stream_shape(int nrb, const int* rb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
-                                T* dout, double c1, double c2, int flags, const int* skip, double* partials,
-                                hipStream_t s) {
+static int launch_stream_block(const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
+                               T* dout, double c1, double c2, int flags, const int* skip, double* partials,
+                               hipStream_t s) {
+  const int nrb = fb.nrb;
   if (partials)
-    hipLaunchKernelGGL((k_level_stream<T, true, CAP, RPB>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, rb, op.ptr,
+    hipLaunchKernelGGL((k_level_stream<T, true, CAP, RPB>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, fb.rb, op.ptr,
                        op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, partials);
   else
-    hipLaunchKernelGGL((k_level_stream<T, false, CAP, RPB>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, rb, op.ptr,
+    hipLaunchKernelGGL((k_level_stream<T, false, CAP, RPB>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, fb.rb, op.ptr,
                        op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, partials);
+  return nrb;
+}
+
+// workgroups of a persistent kernel: as many as are resident at once on the device (capped by the work)
+template <typename K>
+static int resident_groups(K kernel) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    throw std::runtime_error("occupancy query of the pipelined row-block kernel failed");
+  return std::max(1, per_cu) * std::max(1, cus);
+}
+
+template <typename T, bool DOT, int CAP, int RPB>
+static int pipe_groups(int nrb) {
+  static const int g = resident_groups(k_level_stream_pv<T, DOT, CAP, RPB>);
+  return std::min(nrb, g);
+}
+
+template <typename T, int CAP, int RPB>
+static int launch_stream_pipe(const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
+                              T* dout, double c1, double c2, int flags, const int* skip, double* partials,
+                              hipStream_t s) {
+  const int nrb = fb.nrb;
+  const int nwg = partials ? pipe_groups<T, true, CAP, RPB>(nrb) : pipe_groups<T, false, CAP, RPB>(nrb);
+  const dim3 grid(xcd_grid(nwg));
+  if (partials)
+    hipLaunchKernelGGL((k_level_stream_pv<T, true, CAP, RPB>), grid, dim3(256), 0, s, nrb, nwg, fb.rb, op.ptr, op.idx,
+                       op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, partials);
+  else
+    hipLaunchKernelGGL((k_level_stream_pv<T, false, CAP, RPB>), grid, dim3(256), 0, s, nrb, nwg, fb.rb, op.ptr,
+                       op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, partials);
+  return nwg;
+}
+
+template <typename T, typename IX, int CAP, int RPB, int UCAP>
+static int launch_stream_local(const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
+                               T* dout, double c1, double c2, int flags, const int* skip, double* partials,
+                               hipStream_t s) {
+  const int nrb = fb.nrb;
+  const IX* li = static_cast<const IX*>(fb.lidx);
+  if (partials)
+    hipLaunchKernelGGL((k_level_local<T, IX, true, CAP, RPB, UCAP>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, fb.rb,
+                       fb.ubp, fb.ucol, li, op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags,
+                       skip, partials);
+  else
+    hipLaunchKernelGGL((k_level_local<T, IX, false, CAP, RPB, UCAP>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb,
+                       fb.rb, fb.ubp, fb.ucol, li, op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2,
+                       flags, skip, partials);
+  return nrb;
+}
+
+template <typename T, int CAP, int RPB, int UCAP>
+static int launch_stream_local_vec(const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
+                                   T* dout, double c1, double c2, int flags, const int* skip, double* partials,
+                                   hipStream_t s) {
+  if (partials) throw std::runtime_error("local-column vector kernel: no partial sums");
+  const int nrb = fb.nrb;
+  hipLaunchKernelGGL((k_level_local_vec<T, CAP, RPB, UCAP>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, fb.rb,
+                     fb.ubp, fb.ucol, static_cast<const uint8_t*>(fb.lidx), op.ptr, op.idx, op.val, u, b, rho, x,
+                     op.dinv, dout, (T)c1, (T)c2, flags, skip);
+  return nrb;
 }
 
 template <typename T>
-void launch_level_stream(int shape, int nrb, const int* rb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
-                         T* dout, double c1, double c2, int flags, const int* skip, double* partials, hipStream_t s) {
-  if (nrb == 0) return;
+int launch_level_stream(int shape, const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
+                        T* dout, double c1, double c2, int flags, const int* skip, double* partials, hipStream_t s) {
+  if (fb.nrb == 0) return 0;
+  int np = 0;
+#define R3MG_ARGS fb, op, u, b, rho, x, dout, c1, c2, flags, skip, partials, s
   switch (shape) {
-    case 0: launch_stream_shape<T, 2048, 64>(nrb, rb, op, u, b, rho, x, dout, c1, c2, flags, skip, partials, s); break;
-    case 1: launch_stream_shape<T, 4096, 128>(nrb, rb, op, u, b, rho, x, dout, c1, c2, flags, skip, partials, s); break;
-    case 2: launch_stream_shape<T, 4096, 64>(nrb, rb, op, u, b, rho, x, dout, c1, c2, flags, skip, partials, s); break;
+    case 0: np = launch_stream_block<T, 2048, 64>(R3MG_ARGS); break;
+    case 1: np = launch_stream_block<T, 4096, 128>(R3MG_ARGS); break;
+    case 2: np = launch_stream_block<T, 4096, 64>(R3MG_ARGS); break;
+    case 3: np = launch_stream_pipe<T, 2048, 64>(R3MG_ARGS); break;
+    case 4: np = launch_stream_pipe<T, 4096, 128>(R3MG_ARGS); break;
+    case 5: np = launch_stream_pipe<T, 4096, 64>(R3MG_ARGS); break;
+    case 6: np = launch_stream_local<T, uint8_t, 2048, 64, 256>(R3MG_ARGS); break;
+    case 7: np = launch_stream_local<T, uint16_t, 4096, 64, 1024>(R3MG_ARGS); break;
+    case 8: np = launch_stream_local<T, uint16_t, 4096, 128, 1024>(R3MG_ARGS); break;
+    case 9: np = launch_stream_local_vec<T, 2048, 64, 256>(R3MG_ARGS); break;
     default: throw std::runtime_error("unknown row-block shape");
   }
+#undef R3MG_ARGS
   check_launch("k_level_stream");
+  return np;
 }
-template void launch_level_stream<float>(int, int, const int*, const LevelOp<float>&, const float*, const float*,
-                                         float*, float*, float*, double, double, int, const int*, double*, hipStream_t);
-template void launch_level_stream<double>(int, int, const int*, const LevelOp<double>&, const double*, const double*,
-                                          double*, double*, double*, double, double, int, const int*, double*,
-                                          hipStream_t);
+template int launch_level_stream<float>(int, const FineBlocks&, const LevelOp<float>&, const float*, const float*,
+                                        float*, float*, float*, double, double, int, const int*, double*, hipStream_t);
+template int launch_level_stream<double>(int, const FineBlocks&, const LevelOp<double>&, const double*,
+                                         const double*, double*, double*, double*, double, double, int, const int*,
+                                         double*, hipStream_t);
 
 // Block-row variant of the fused kernel for the agglomerated levels, one right-hand side.  One wave per box
 // K: the nb*B entries of u that the block row touches (nb stored blocks of B consecutive columns) are staged in
@@ -1228,6 +1752,25 @@ void launch_lanczos_start(int n, const int* perm, double* v, hipStream_t s) {
 }
 
 // per-block partial sums of w_i x_i y_i (fixed grid of at most 1024 blocks, grid-stride)
+// <p, q> of one PCG column in a fixed partition (at most 1024 blocks, grid-stride), independent of the kernel
+// that formed q: partials[0..g) for k_pcg_alpha.
+__global__ __launch_bounds__(256) void k_pcg_dot(int n, const double* __restrict__ p, const double* __restrict__ q,
+                                                 double* partials, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double sh[4];
+  double acc = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) acc += p[i] * q[i];
+  const double t = block_sum256(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+int launch_pcg_dot(int n, const double* p, const double* q, double* partials, const int* skip, hipStream_t s) {
+  int g = (n + 255) / 256;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_pcg_dot, dim3(g), dim3(256), 0, s, n, p, q, partials, skip);
+  check_launch("k_pcg_dot");
+  return g;
+}
 __global__ __launch_bounds__(256) void k_dot(int64_t n, const double* __restrict__ w, const double* __restrict__ x,
                                              const double* __restrict__ y, double* partials) {
   __shared__ double sh[4];

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "kernels.h"
 #include "r3mg.h"
 
 namespace r3mg {
@@ -103,8 +104,11 @@ struct Analysis {
   std::vector<int32_t> iperm;            // user -> internal
   std::vector<int64_t> leaf_off;         // internal offsets of the level-1 boxes (nbox1 + 1)
   std::vector<int64_t> tree_leaf_off;    // internal offsets of the R-tree leaves (depth t)
-  // fine-level row blocks of the three stream-kernel shapes (2048/64, 4096/128, 4096/64 nonzeros/rows)
+  // fine-level row blocks: CSR geometries (2048/64, 4096/128, 4096/64 nonzeros/rows) and local-column
+  // geometries (block offsets, distinct-column offsets and lists, local column index bytes per nonzero)
   std::vector<int32_t> rb[3];
+  std::vector<int32_t> lrb[3], lubp[3], lucol[3];
+  std::vector<uint8_t> lidx[3];
   std::vector<uint8_t> constrained;      // internal order
   std::vector<uint8_t> constrained_user; // caller's order
   std::vector<int32_t> owner;            // internal point -> level-1 box, -1 if constrained
@@ -152,9 +156,12 @@ struct DevLevel {
   DBuf<float> dinv32;
   double lam_hi = 0, lam_lo = 0, lam_hat = 0;
   int lanes = 8;  // lanes per row of the SpMV kernels
-  DBuf<int32_t> rb[3];  // l = 0: row blocks of the single-RHS stream kernel, per block shape
-  int nrb[3] = {0, 0, 0};
-  int shape = 0;        // l = 0: block shape chosen by timing at set-up
+  DBuf<int32_t> rb[3];  // l = 0: CSR row blocks of the single-RHS row-block kernels, per geometry
+  DBuf<int32_t> lrb[3], lubp[3], lucol[3];  // l = 0: local-column row blocks, per geometry
+  DBuf<uint8_t> lidx[3];
+  FineBlocks fb[kStreamShapes];  // l = 0: row blocks of every kernel shape
+  double shape_bytes[kStreamShapes] = {};  // algorithmic bytes of one application with each shape
+  int shape = 0;        // l = 0: kernel shape chosen by timing at set-up
   int maxnb = 0;     // l >= 1: largest number of stored blocks in a block row
   // transfer to the next level
   DBuf<double> xi64;     // l = 0: n x d

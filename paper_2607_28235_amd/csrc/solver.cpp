@@ -136,7 +136,7 @@ LevelOp<T> level_op(Ctx& c, int l) {
 // level for one right-hand side, a block-row kernel on coarse levels whose block rows fit LDS, the
 // lanes-per-row kernel otherwise.
 LevelKernel level_kernel(const Analysis& an, const DevLevel& D, int l, int nr, int esz) {
-  if (l == 0 && nr == 1 && D.nrb[D.shape] > 0) return LevelKernel::Stream;
+  if (l == 0 && nr == 1 && D.fb[D.shape].nrb > 0) return LevelKernel::Stream;
   if (l > 0 && nr == 1 && D.maxnb > 0 && an.B >= 8 && (int64_t)D.maxnb * an.B >= 256 &&
       (int64_t)D.maxnb * an.B * esz <= 65536)
     return LevelKernel::BlockRowWG;
@@ -149,8 +149,14 @@ std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int 
   const char* t = esz == 4 ? "float" : "double";
   switch (level_kernel(an, D, l, 1, esz)) {
     case LevelKernel::Stream:
-      return std::string("k_level_stream<") + t + "," + std::to_string(kStreamCapOf[D.shape]) + "," +
-             std::to_string(kStreamRowsOf[D.shape]) + ">";
+      if (D.shape >= kLocalFirst) {
+        const int g = D.shape == kLocalFirst + kLocalGeoms ? 0 : D.shape - kLocalFirst;
+        return std::string("k_level_local<") + t + ",u" + std::to_string(8 * kLocalIdxBytes[g]) + "," +
+               std::to_string(kLocalCap[g]) + "," + std::to_string(kLocalRows[g]) + "," +
+               std::to_string(kLocalUcap[g]) + (D.shape == kLocalFirst + kLocalGeoms ? ",vec>" : ",block>");
+      }
+      return std::string("k_level_stream<") + t + "," + std::to_string(kStreamCapOf[D.shape % kCsrGeoms]) + "," +
+             std::to_string(kStreamRowsOf[D.shape % kCsrGeoms]) + (D.shape >= kCsrGeoms ? ",pipe16>" : ",block>");
     case LevelKernel::BlockRowWG: return std::string("k_level_blockrow_wg<") + t + ">";
     case LevelKernel::BlockRow: return std::string("k_level_blockrow<") + t + ">";
     default: return std::string("k_level<") + t + ">";
@@ -164,7 +170,7 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
   DevLevel& D = c.dv.lv[l];
   switch (level_kernel(c.an, D, l, nr, (int)sizeof(T))) {
     case LevelKernel::Stream:
-      launch_level_stream<T>(D.shape, D.nrb[D.shape], D.rb[D.shape].p, op, u, b, rho, x, dout, c1, c2, flags, skip,
+      launch_level_stream<T>(D.shape, D.fb[D.shape], op, u, b, rho, x, dout, c1, c2, flags, skip,
                              nullptr, s);
       break;
     case LevelKernel::BlockRowWG:
@@ -214,9 +220,10 @@ static void ensure_pcg_vectors(Ctx& c, int nr) {
     const int64_t rpb = 256 / std::max(nr > 1 ? 8 : 1, dv.lv[0].lanes);
     const int64_t nlog_spmv = (n + rpb - 1) / rpb;
     const int64_t nlog_vec = (n + 255) / 256;
-    dv.partials.alloc(std::max<size_t>({(size_t)4096, (size_t)(nlog_spmv * nr), (size_t)(nlog_vec * 2 * nr),
-                                        (size_t)dv.lv[0].nrb[0], (size_t)dv.lv[0].nrb[1],
-                                        (size_t)dv.lv[0].nrb[2]}));
+    size_t nrb_max = 0;
+    for (int sh = 0; sh < kStreamShapes; ++sh) nrb_max = std::max(nrb_max, (size_t)dv.lv[0].fb[sh].nrb);
+    dv.partials.alloc(
+        std::max<size_t>({(size_t)4096, (size_t)(nlog_spmv * nr), (size_t)(nlog_vec * 2 * nr), nrb_max}));
     drop_graphs(dv);
   }
   if (!dv.state.p) {
@@ -532,6 +539,11 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
   Ctx c{an, dv, an.opt.vcycle_fp32 != 0};
   ensure_level_vectors(c, 1);
   DevLevel& D = dv.lv[0];
+  if (an.opt.fine_kernel >= 0) {
+    D.shape = an.opt.fine_kernel;
+    D.bytes_apply = D.shape_bytes[D.shape];
+    return;
+  }
   const int fl = F_RHO_STORE | F_X_ADD | F_D_OUT;
   // two interleaved rounds, best of each shape; another shape replaces the first one only when it is at least
   // 3% faster, so that timing noise does not flip the choice between runs
@@ -543,14 +555,14 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
       if (c.fp32) {
         LevelOp<float> op = level_op<float>(c, 0);
         ms = time_launches(s, 20, [&] {
-          launch_level_stream<float>(sh, D.nrb[sh], D.rb[sh].p, op, vbuf<float>(D.dA), vbuf<float>(D.b),
+          launch_level_stream<float>(sh, D.fb[sh], op, vbuf<float>(D.dA), vbuf<float>(D.b),
                                      vbuf<float>(D.rho), vbuf<float>(D.x), vbuf<float>(D.dB), 0.0, 0.0, fl, nullptr,
                                      nullptr, s);
         });
       } else {
         LevelOp<double> op = level_op<double>(c, 0);
         ms = time_launches(s, 20, [&] {
-          launch_level_stream<double>(sh, D.nrb[sh], D.rb[sh].p, op, vbuf<double>(D.dA), vbuf<double>(D.b),
+          launch_level_stream<double>(sh, D.fb[sh], op, vbuf<double>(D.dA), vbuf<double>(D.b),
                                       vbuf<double>(D.rho), vbuf<double>(D.x), vbuf<double>(D.dB), 0.0, 0.0, fl,
                                       nullptr, nullptr, s);
         });
@@ -562,6 +574,7 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
   for (int sh = 1; sh < kStreamShapes; ++sh)
     if (best[sh] < 0.97f * best[bestS]) bestS = sh;
   D.shape = bestS;
+  D.bytes_apply = D.shape_bytes[D.shape];
   R3MG_HIP_CHECK(hipMemsetAsync(D.x.p, 0, D.x.n, s));
   R3MG_HIP_CHECK(hipMemsetAsync(D.rho.p, 0, D.rho.n, s));
 }
@@ -585,25 +598,58 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     D.n = an.n;
     D.nnz = an.nnz;
     D.rowptr.upload(an.rowptr, s);
-    D.col.upload(an.col, s);
-    D.val64.upload(an.val, s);
+    {
+      // kFinePad zero entries after the last nonzero: the 16-byte loads of the row-block kernel may read them
+      std::vector<int32_t> colp(an.col);
+      colp.resize(colp.size() + kFinePad, 0);
+      D.col.upload(colp, s);
+      std::vector<double> valp(an.val);
+      valp.resize(valp.size() + kFinePad, 0.0);
+      D.val64.upload(valp, s);
+    }
     D.xi64.upload(an.xi, s);
     D.owner.upload(an.owner, s);
     std::vector<int32_t> lo(an.leaf_off.begin(), an.leaf_off.end());
     D.leaf_off.upload(lo, s);
     D.lanes = lanes_for((double)an.nnz / (double)an.n);
-    for (int sh = 0; sh < kStreamShapes; ++sh) {
-      D.nrb[sh] = (int)an.rb[sh].size() - 1;
-      D.rb[sh].upload(an.rb[sh], s);
+    const double sv0 = fp32 ? 4 : 8;
+    for (int g = 0; g < kCsrGeoms; ++g) {
+      D.rb[g].upload(an.rb[g], s);
+      const int nrb = (int)an.rb[g].size() - 1;
+      // values and columns, row pointers, row-block offsets, 7 vector streams
+      const double by = (double)an.nnz * (sv0 + 4) + (double)(an.n + 1) * 4 + 4.0 * (nrb + 1) + 7.0 * an.n * sv0;
+      for (int sh : {g, g + kCsrGeoms}) {
+        D.fb[sh].nrb = nrb;
+        D.fb[sh].rb = D.rb[g].p;
+        D.shape_bytes[sh] = by;
+      }
     }
+    for (int g = 0; g < kLocalGeoms; ++g) {
+      D.lrb[g].upload(an.lrb[g], s);
+      D.lubp[g].upload(an.lubp[g], s);
+      D.lucol[g].upload(an.lucol[g], s);
+      D.lidx[g].upload(an.lidx[g], s);
+      FineBlocks& f = D.fb[kLocalFirst + g];
+      f.nrb = (int)an.lrb[g].size() - 1;
+      f.rb = D.lrb[g].p;
+      f.ubp = D.lubp[g].p;
+      f.ucol = D.lucol[g].p;
+      f.lidx = D.lidx[g].p;
+      // values and local column positions, distinct-column lists and offsets, row pointers, block offsets,
+      // 7 vector streams
+      D.shape_bytes[kLocalFirst + g] = (double)an.nnz * (sv0 + kLocalIdxBytes[g]) + 4.0 * an.lucol[g].size() +
+                                       4.0 * (f.nrb + 1) + (double)(an.n + 1) * 4 + 4.0 * (f.nrb + 1) +
+                                       7.0 * an.n * sv0;
+    }
+    // shape 9: the vector-load kernel over the blocks of local geometry 0
+    D.fb[kLocalFirst + kLocalGeoms] = D.fb[kLocalFirst];
+    D.shape_bytes[kLocalFirst + kLocalGeoms] = D.shape_bytes[kLocalFirst];
     D.dinv64.alloc(D.n);
     if (fp32) {
       D.xi32.alloc(D.xi64.n);
       launch_cast_d2f((int64_t)D.xi64.n, D.xi64.p, D.xi32.p, s);
     }
-    const double sv = fp32 ? 4 : 8;
-    // values and columns, row pointers, row-block offsets, 7 vector streams
-    D.bytes_apply = (double)an.nnz * (sv + 4) + (double)(an.n + 1) * 4 + 4.0 * an.rb[0].size() + 7.0 * an.n * sv;
+    D.bytes_apply = D.shape_bytes[0];  // replaced by the chosen shape's bytes once the shape is timed
   }
   for (int l = 1; l <= L; ++l) {
     DevLevel& D = dv.lv[l];
@@ -733,12 +779,13 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
   LevelOp<double> op64 = level_op<double>(c, 0);
   const int n = (int)an.n;
   need_partials(dv, (int64_t)((n + 255) / 256) * 2 * NR);
-  need_partials(dv, D0.nrb[D0.shape]);
   int np;
-  if (NR == 1 && D0.nrb[D0.shape] > 0) {
-    launch_level_stream<double>(D0.shape, D0.nrb[D0.shape], D0.rb[D0.shape].p, op64, dv.pp.p, nullptr, dv.pq.p,
-                                nullptr, nullptr, 0, 0, F_PLAIN, skip, dv.partials.p, s);
-    np = D0.nrb[D0.shape];
+  if (NR == 1 && D0.fb[D0.shape].nrb > 0) {
+    // q = A p with the fine row-block kernel, then <p, q> in a fixed partition: the iterates do not depend on
+    // the kernel shape chosen by timing
+    launch_level_stream<double>(D0.shape, D0.fb[D0.shape], op64, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0,
+                                F_PLAIN, skip, nullptr, s);
+    np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
   } else {
     auto it = dv.tuned.find({-1, NR * 2});
     if (it != dv.tuned.end()) op64.lanes = it->second;

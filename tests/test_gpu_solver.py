@@ -292,3 +292,95 @@ def test_full_size_2d_q3_pcg(full2d, fp32):
         h.vcycle(_t(rv), z)
         torch.cuda.synchronize()
         assert _rel(z.cpu().numpy(), O.vcycle(c.ho, rv)) < 1e-11
+
+
+@pytest.mark.parametrize("shape", list(range(10)))
+def test_fine_kernel_shapes_full_size(full2d, shape):
+    """Every row-block kernel shape of the fine level (CSR blocks, one workgroup each; the same blocks in the
+    persistent pipelined kernel, several blocks per workgroup at this size; local-column blocks with 1- and 2-byte
+    column positions) on the 591,361-DoF workload: the operator
+    application against scipy, the float64 V-cycle against the oracle, and PCG (whose <p, A p> partial sums come
+    from the same kernel) against the oracle."""
+    c = full2d
+    _case(f"full2d fine kernel shape {shape}")
+    P = _P()
+    import dataclasses
+    h = P.Hierarchy(c.prob.coords, c.prob.row_ptr, c.prob.col, c.prob.val,
+                    dataclasses.replace(c.opts, fine_kernel=shape))
+    assert h.info()[0]["kernel"].startswith(("k_level_stream<double,", "k_level_local<double,"))
+    g = np.random.default_rng(12)
+    if not hasattr(c, "rv"):
+        c.rv = g.standard_normal(c.prob.n)
+        c.rv[c.ho.constrained] = 0.0
+        c.zv = O.vcycle(c.ho, c.rv)
+        c.xo, c.ko, _, _, _ = O.pcg(c.ho, c.b, rtol=1e-10)
+    y = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    h.level_apply(0, _t(c.rv), y)
+    z = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    h.vcycle(_t(c.rv), z)
+    torch.cuda.synchronize()
+    assert _rel(y.cpu().numpy(), c.prob.scipy() @ c.rv) < 1e-14
+    assert _rel(z.cpu().numpy(), c.zv) < 1e-11
+    x = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok = h.pcg(_t(c.b), x, rtol=1e-10, maxit=200)
+    assert ok and abs(int(iters[0]) - c.ko) <= 1, (iters, c.ko)
+    assert _rel(x.cpu().numpy(), c.xo) < 1e-9
+    # every shape sums each row in the same order and PCG reduces <p, A p> in a fixed partition: the results do
+    # not depend on the shape (no row here has more than 256 nonzeros)
+    res = (y.cpu().numpy(), z.cpu().numpy(), x.cpu().numpy(), int(iters[0]))
+    if not hasattr(c, "shape_ref"):
+        c.shape_ref = res
+    assert all(np.array_equal(a, b) for a, b in zip(res[:3], c.shape_ref[:3])) and res[3] == c.shape_ref[3]
+    h.close()
+
+
+@pytest.fixture(scope="module")
+def dense_row():
+    """small2d's operator plus a symmetric positive semi-definite coupling of one interior DoF k with every
+    unconstrained DoF: sum_j delta (e_k + e_j)(e_k + e_j)^T.  Row k then holds ~21,000 nonzeros (and as many
+    distinct columns), beyond every row-block and column-list capacity, so the fine kernels take their long-row
+    path."""
+    _need_gpu()
+    _case("dense-row setup (small2d + one dense row/column)")
+    import scipy.sparse as sp
+    prob = F.structured_qp(2, 48, 3, jitter=0.2, cfg=2)
+    A = prob.scipy().tocsr()
+    free = np.flatnonzero(~prob.boundary)
+    k = int(free[len(free) // 2])
+    js = free[free != k]
+    delta = 1e-2 * float(A.diagonal()[free].min())
+    rows = np.concatenate([np.full(len(js), k), js, js, [k]])
+    cols = np.concatenate([js, np.full(len(js), k), js, [k]])
+    vals = np.concatenate([np.full(2 * len(js), delta), np.full(len(js), delta), [delta * len(js)]])
+    C = sp.csr_matrix((vals, (rows, cols)), shape=A.shape)
+    A2 = (A + C).tocsr()
+    A2.sort_indices()
+    b = F.nodal_rhs(prob, F.rng(2, F.PURPOSE_RHS).standard_normal(prob.n), jitter=0.2, cfg=2)
+    ho = O.build_hierarchy(prob.coords, A2, coarse_degree=2, leaf_size=128, max_levels=4, max_coarse_dofs=100)
+    return prob, A2, b, ho
+
+
+@pytest.mark.parametrize("shape", list(range(10)))
+def test_fine_kernel_long_row(dense_row, shape):
+    prob, A2, b, ho = dense_row
+    _case(f"dense-row fine kernel shape {shape}")
+    P = _P()
+    h = P.Hierarchy(prob.coords, A2.indptr.astype(np.int64), A2.indices.astype(np.int32), A2.data,
+                    P.Options(dim=2, coarse_degree=2, leaf_size=128, max_levels=4, max_coarse_dofs=100,
+                              fine_kernel=shape))
+    g = np.random.default_rng(13)
+    r = g.standard_normal(prob.n)
+    r[ho.constrained] = 0.0
+    y = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+    h.level_apply(0, _t(r), y)
+    z = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+    h.vcycle(_t(r), z)
+    torch.cuda.synchronize()
+    assert _rel(y.cpu().numpy(), A2 @ r) < 1e-14
+    assert _rel(z.cpu().numpy(), O.vcycle(ho, r)) < 1e-11
+    x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok = h.pcg(_t(b), x, rtol=1e-10, maxit=300)
+    xo, ko, _, _, _ = O.pcg(ho, b, rtol=1e-10, maxit=300)
+    assert ok and abs(int(iters[0]) - ko) <= 1, (iters, ko)
+    assert _rel(x.cpu().numpy(), xo) < 1e-9
+    h.close()
