@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E peak
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_level_stream_2d_q3_591k.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_fine_kernels_2d_q3_591k.md")
 
 
 def recorded_traffic(kernel: str):
@@ -35,8 +35,8 @@ def recorded_traffic(kernel: str):
         src = open(os.path.join(ROOT, "paper_2607_28235_amd", "csrc", "kernels.hip")).read()
     except OSError:
         return None
-    i = src.find("template <typename T, bool DOT, int CAP, int RPB, bool VEC>\n__global__ __launch_bounds__(256) void k_level_stream(")
-    j = src.find("template void launch_level_stream<double>", i)
+    i = src.find("// ==== fine-level row-block kernels ====")
+    j = src.find("// ==== end of fine-level row-block kernels ====", i)
     if i < 0 or j < 0:
         return None
     h = hashlib.sha256(src[i:j].encode()).hexdigest()

@@ -230,6 +230,8 @@ template void launch_level<float>(const LevelOp<float>&, int, const float*, cons
 template void launch_level<double>(const LevelOp<double>&, int, const double*, const double*, double*, double*,
                                    double*, double, double, int, const int*, hipStream_t);
 
+// ==== fine-level row-block kernels ====
+
 // Sum of the staged products prod[s..e) of one row by TPR consecutive lanes (TPR = 4 or 2) in one canonical
 // order, the same for every row-block shape: a_v = prod[s+v] + prod[s+v+4] + ... (v = 0..3, in increasing
 // position), row sum = (a_0 + a_2) + (a_1 + a_3).  With TPR = 2 each lane carries two of the four partial sums.
@@ -885,6 +887,7 @@ template int launch_level_stream<float>(int, const FineBlocks&, const LevelOp<fl
 template int launch_level_stream<double>(int, const FineBlocks&, const LevelOp<double>&, const double*,
                                          const double*, double*, double*, double*, double, double, int, const int*,
                                          double*, hipStream_t);
+// ==== end of fine-level row-block kernels ====
 
 // Block-row variant of the fused kernel for the agglomerated levels, one right-hand side.  One wave per box
 // K: the nb*B entries of u that the block row touches (nb stored blocks of B consecutive columns) are staged in
