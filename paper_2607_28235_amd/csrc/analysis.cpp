@@ -455,27 +455,28 @@ static void encode_csr_blocks(Analysis& an) {
   }
 }
 
-// Local-column row blocks of geometry g: rows are taken greedily (within independent row segments) while the
-// block stays within `rows` rows, `cap` - 3 nonzeros and `ucap` distinct columns; the distinct columns are listed
-// in ascending order and every nonzero stores the position of its column in the list.  A single row beyond
-// the limits forms a block of its own with its full column list (the kernel reads such a block through the
-// CSR columns).
-static void encode_local_blocks(Analysis& an, int g) {
-  const int64_t n = an.n;
+// Local-column row blocks of geometry g over a CSR pattern: rows are taken greedily (within independent row
+// segments) while the block stays within `rows` rows, `cap` - 3 nonzeros and `ucap` distinct columns; the
+// distinct columns are listed in ascending order and every nonzero stores the position of its column in the
+// list.  A single row beyond the limits forms a block of its own with its full column list (the kernel reads
+// such a block through the CSR columns).
+static void encode_local_blocks(const int32_t* rowptr, const int32_t* col, int64_t n, int64_t ncol, int g,
+                                LocalBlocks& out) {
+  const int64_t nnz = rowptr[n];
   const int cap = kLocalCap[g] - 3, rows = kLocalRows[g], ucap = kLocalUcap[g], ib = kLocalIdxBytes[g];
   const int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(256, n / 4096));
   struct Seg {
     std::vector<int32_t> ends, ucnt, ucol;
   };
   std::vector<Seg> segs((size_t)nseg);
-  std::vector<uint8_t>& lidx = an.lidx[g];
-  lidx.assign((size_t)(an.nnz + kFinePad) * ib, 0);  // padding: the pipelined kernel's 4-byte loads
+  std::vector<uint8_t>& lidx = out.lidx;
+  lidx.assign((size_t)(nnz + kFinePad) * ib, 0);  // padding: the vector kernel's 4-byte loads
   parallel_for(nseg, [&](int64_t sg) {
     static thread_local std::vector<uint8_t> mark;
     static thread_local std::vector<int32_t> pos;
-    if ((int64_t)mark.size() < n) {
-      mark.assign((size_t)n, 0);
-      pos.assign((size_t)n, 0);
+    if ((int64_t)mark.size() < ncol) {
+      mark.assign((size_t)ncol, 0);
+      pos.assign((size_t)ncol, 0);
     }
     Seg& S = segs[(size_t)sg];
     const int64_t ra = sg * n / nseg, rz = (sg + 1) * n / nseg;
@@ -484,14 +485,14 @@ static void encode_local_blocks(Analysis& an, int g) {
       uq.clear();
       int64_t r1 = r, nz = 0;
       while (r1 < rz && r1 - r < rows) {
-        const int32_t a = an.rowptr[r1], b = an.rowptr[r1 + 1];
+        const int32_t a = rowptr[r1], b = rowptr[r1 + 1];
         int64_t add = 0;
-        for (int32_t e = a; e < b; ++e) add += mark[an.col[e]] ? 0 : 1;
+        for (int32_t e = a; e < b; ++e) add += mark[col[e]] ? 0 : 1;
         if (r1 > r && (nz + (b - a) > cap || (int64_t)uq.size() + add > ucap)) break;
         for (int32_t e = a; e < b; ++e)
-          if (!mark[an.col[e]]) {
-            mark[an.col[e]] = 1;
-            uq.push_back(an.col[e]);
+          if (!mark[col[e]]) {
+            mark[col[e]] = 1;
+            uq.push_back(col[e]);
           }
         nz += b - a;
         ++r1;
@@ -502,8 +503,8 @@ static void encode_local_blocks(Analysis& an, int g) {
         mark[uq[i]] = 0;
       }
       if ((int64_t)uq.size() <= ucap)
-        for (int32_t e = an.rowptr[r]; e < an.rowptr[r1]; ++e) {
-          const int32_t li = pos[an.col[e]];
+        for (int32_t e = rowptr[r]; e < rowptr[r1]; ++e) {
+          const int32_t li = pos[col[e]];
           if (ib == 1)
             lidx[(size_t)e] = (uint8_t)li;
           else
@@ -515,24 +516,45 @@ static void encode_local_blocks(Analysis& an, int g) {
       r = r1;
     }
   });
-  std::vector<int32_t>& rb = an.lrb[g];
-  std::vector<int32_t>& ubp = an.lubp[g];
-  std::vector<int32_t>& ucol = an.lucol[g];
-  rb.assign(1, 0);
-  ubp.assign(1, 0);
-  ucol.clear();
+  out.rb.assign(1, 0);
+  out.ubp.assign(1, 0);
+  out.ucol.clear();
   for (const Seg& S : segs) {
     for (size_t k = 0; k < S.ends.size(); ++k) {
-      rb.push_back(S.ends[k]);
-      ubp.push_back(ubp.back() + S.ucnt[k]);
+      out.rb.push_back(S.ends[k]);
+      out.ubp.push_back(out.ubp.back() + S.ucnt[k]);
     }
-    ucol.insert(ucol.end(), S.ucol.begin(), S.ucol.end());
+    out.ucol.insert(out.ucol.end(), S.ucol.begin(), S.ucol.end());
   }
 }
 
 void encode_fine(Analysis& an) {
   encode_csr_blocks(an);
-  for (int g = 0; g < kLocalGeoms; ++g) encode_local_blocks(an, g);
+  for (int g = 0; g < kLocalGeoms; ++g) encode_local_blocks(an.rowptr.data(), an.col.data(), an.n, an.n, g, an.loc[g]);
+  // agglomerated levels with narrow block rows (the 2D hierarchies): CSR row pointers and 1-byte local blocks
+  const int L = an.nlevels() - 1;
+  const int B = an.B;
+  for (int l = 1; l < L; ++l) {
+    HostLevel& H = an.lv[l];
+    int64_t maxw = 0;
+    for (int64_t K = 0; K < H.nbox; ++K) maxw = std::max<int64_t>(maxw, (H.bptr[K + 1] - H.bptr[K]) * B);
+    const int64_t nnz = H.bptr[H.nbox] * (int64_t)B * B;
+    if (maxw > kLocalUcap[0] || nnz >= (int64_t(1) << 31) - kFinePad) continue;
+    H.rowptr.assign(H.n + 1, 0);
+    std::vector<int32_t> col((size_t)nnz);
+    parallel_for(H.nbox, [&](int64_t K) {
+      const int64_t nb = H.bptr[K + 1] - H.bptr[K];
+      const int64_t w = nb * B;
+      for (int q = 0; q < B; ++q) {
+        const int64_t r0 = (int64_t)B * B * H.bptr[K] + q * w;
+        H.rowptr[K * B + q] = (int32_t)r0;
+        for (int64_t j = 0; j < nb; ++j)
+          for (int c = 0; c < B; ++c) col[(size_t)(r0 + j * B + c)] = (int32_t)(H.bcol[H.bptr[K] + j] * B + c);
+      }
+    });
+    H.rowptr[H.n] = (int32_t)nnz;
+    encode_local_blocks(H.rowptr.data(), col.data(), H.n, H.n, 0, H.loc);
+  }
 }
 
 }  // namespace r3mg

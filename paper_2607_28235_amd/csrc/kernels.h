@@ -83,7 +83,8 @@ int launch_level_stream(int shape, const FineBlocks& fb, const LevelOp<T>& op, c
                         T* dout, double c1, double c2, int flags, const int* skip, double* partials, hipStream_t s);
 
 // Block-row variant for the agglomerated levels and one right-hand side (one wave per box; maxnb = largest
-// number of stored blocks in a block row).
+// number of stored blocks in a block row).  Needs blockrow_lds_bytes(B, maxnb * B, sizeof(T)) <= 64 KiB.
+size_t blockrow_lds_bytes(int blk, int maxw, size_t esz);
 template <typename T>
 void launch_level_blockrow(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
                            double c2, int flags, const int* skip, hipStream_t s);

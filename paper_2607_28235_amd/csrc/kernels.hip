@@ -889,12 +889,14 @@ template int launch_level_stream<double>(int, const FineBlocks&, const LevelOp<d
                                          double*, hipStream_t);
 // ==== end of fine-level row-block kernels ====
 
-// Block-row variant of the fused kernel for the agglomerated levels, one right-hand side.  One wave per box
-// K: the nb*B entries of u that the block row touches (nb stored blocks of B consecutive columns) are staged in
-// LDS once and shared by the B rows of the box; row (K,q) then streams its nb*B contiguous values with
-// coalesced loads against the LDS copy (the LDS layout [j][c] equals the row layout), 4 rows at a time, and
-// lane q applies the epilogue of row (K,q).  Dynamic LDS: 4 waves x maxw entries, maxw = max_K nb_K * B.
-template <typename T>
+// Block-row variant of the fused kernel for the agglomerated levels, one right-hand side.  One wave per box K,
+// L = floor(64 / B) lanes per row: lane (q, s) owns the columns p = s, s + L, ... of row (K, q) (w = nb*B values,
+// one contiguous run per row).  Every memory access of the box is put in flight at once: the row's first KMAX
+// values per lane (registers), the epilogue operands, and the w entries of u the block row touches (nb stored
+// blocks of B consecutive columns, staged in LDS once and shared by the B rows).  Each lane then sums its
+// columns in ascending order, the L lane sums of a row are added in lane order through LDS, and lane q applies
+// the epilogue of row (K, q).  Dynamic LDS: 4 waves x (maxw + 64) entries, maxw = max_K nb_K * B.
+template <typename T, int KMAX>
 __global__ __launch_bounds__(256) void k_level_blockrow(int nbox, int blk, int maxw, const int* __restrict__ bptr,
                                                         const int* __restrict__ bcol, const T* __restrict__ val,
                                                         const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
@@ -907,10 +909,28 @@ __global__ __launch_bounds__(256) void k_level_blockrow(int nbox, int blk, int m
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int K = lb * 4 + wv;
   if (K >= nbox) return;  // whole wave leaves; no block-wide barrier follows
-  T* xs = reinterpret_cast<T*>(smem_raw) + (size_t)wv * maxw;
-  T* rs = reinterpret_cast<T*>(smem_raw) + (size_t)4 * maxw + wv * 64;
+  T* xs = reinterpret_cast<T*>(smem_raw) + (size_t)wv * (maxw + 64);
+  T* part = xs + maxw;
+  const int L = 64 / blk;
+  const int q = lane / L, sv = lane - q * L;
+  const bool active = q < blk;
   const int j0 = bptr[K], nb = bptr[K + 1] - j0;
   const int w = nb * blk;
+  const T* vrow = val + (int64_t)blk * blk * j0 + (int64_t)q * w;
+  T v[KMAX];
+#pragma unroll
+  for (int m = 0; m < KMAX; ++m) {
+    const int p = sv + L * m;
+    v[m] = (active && p < w) ? __builtin_nontemporal_load(vrow + p) : (T)0;
+  }
+  const int row = K * blk + lane;
+  T p_old = 0, p_u = 0, p_x = 0, p_di = 0;
+  if (lane < blk && !(flags & F_PLAIN)) {
+    p_old = (flags & F_RHO_FROM_B) ? b[row] : rho[row];
+    p_u = u[row];
+    if (flags & F_X_ADD) p_x = x[row];
+    if (flags & F_D_OUT) p_di = dinv[row];
+  }
   for (int p = lane; p < w; p += 64) {
     const int j = p / blk, c = p - j * blk;
     xs[p] = u[(int64_t)bcol[j0 + j] * blk + c];
@@ -918,48 +938,40 @@ __global__ __launch_bounds__(256) void k_level_blockrow(int nbox, int blk, int m
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int64_t vb = (int64_t)blk * blk * j0;
-  for (int q0 = 0; q0 < blk; q0 += 4) {
-    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    const T* v0 = val + vb + (int64_t)q0 * w;
-    const bool h1 = q0 + 1 < blk, h2 = q0 + 2 < blk, h3 = q0 + 3 < blk;
-    for (int p = lane; p < w; p += 64) {
-      const T xp = xs[p];
-      a0 += v0[p] * xp;
-      if (h1) a1 += v0[w + p] * xp;
-      if (h2) a2 += v0[2 * w + p] * xp;
-      if (h3) a3 += v0[3 * w + p] * xp;
+  T acc = 0;
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < KMAX; ++m) {
+      const int p = sv + L * m;
+      if (p < w) acc += v[m] * xs[p];
     }
-    a0 = wave_sum(a0, 64);
-    a1 = wave_sum(a1, 64);
-    a2 = wave_sum(a2, 64);
-    a3 = wave_sum(a3, 64);
-    if (lane == 0) {
-      rs[q0] = a0;
-      if (h1) rs[q0 + 1] = a1;
-      if (h2) rs[q0 + 2] = a2;
-      if (h3) rs[q0 + 3] = a3;
-    }
+    for (int p = sv + L * KMAX; p < w; p += L) acc += vrow[p] * xs[p];  // rows longer than L * KMAX
   }
+  part[lane] = acc;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (lane < blk) {
-    const int row = K * blk + lane;
-    const T t = rs[lane];
+    T t = 0;
+    for (int s2 = 0; s2 < L; ++s2) t += part[lane * L + s2];
     if (flags & F_PLAIN) {
       rho[row] = t;
     } else {
-      const T r = ((flags & F_RHO_FROM_B) ? b[row] : rho[row]) - t;
+      const T r = p_old - t;
       if (flags & F_RHO_STORE) rho[row] = r;
-      const T ui = u[row];
       if (flags & F_X_ASSIGN)
-        x[row] = ui;
+        x[row] = p_u;
       else if (flags & F_X_ADD)
-        x[row] += ui;
-      if (flags & F_D_OUT) dout[row] = c1 * ui + c2 * dinv[row] * r;
+        x[row] = p_x + p_u;
+      if (flags & F_D_OUT) dout[row] = c1 * p_u + c2 * p_di * r;
     }
   }
+}
+
+// LDS bytes of k_level_blockrow for block rows of at most maxw entries
+size_t blockrow_lds_bytes(int blk, int maxw, size_t esz) {
+  (void)blk;
+  return esz * (size_t)4 * (maxw + 64);
 }
 
 template <typename T>
@@ -969,10 +981,11 @@ void launch_level_blockrow(const LevelOp<T>& op, int maxnb, const T* u, const T*
   const int nlog = (nbox + 3) / 4;
   if (nlog == 0) return;
   const int maxw = maxnb * op.blk;
-  const size_t shm = sizeof(T) * ((size_t)4 * maxw + 4 * 64);
+  const size_t shm = blockrow_lds_bytes(op.blk, maxw, sizeof(T));
   if (shm > 65536) throw std::runtime_error("block-row kernel: block row too wide for LDS");
-  hipLaunchKernelGGL((k_level_blockrow<T>), dim3(xcd_grid(nlog)), dim3(256), shm, s, nbox, op.blk, maxw, op.ptr, op.idx,
-                     op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
+  if (op.blk > 64) throw std::runtime_error("block-row kernel: more than 64 rows per box");
+  hipLaunchKernelGGL((k_level_blockrow<T, 16>), dim3(xcd_grid(nlog)), dim3(256), shm, s, nbox, op.blk, maxw, op.ptr,
+                     op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
   check_launch("k_level_blockrow");
 }
 template void launch_level_blockrow<float>(const LevelOp<float>&, int, const float*, const float*, float*, float*,
@@ -1009,12 +1022,26 @@ __global__ __launch_bounds__(256) void k_level_blockrow_wg(int nbox, int blk, in
   const int64_t vb = (int64_t)blk * blk * j0;
   T a0 = 0, a1 = 0;
   if (qa < blk) {
+    // 8 steps of both rows in flight per batch; each lane still sums in ascending column order
     const T* va = val + vb + (int64_t)qa * w;
     const bool hb = qb < blk;
-    for (int p = lane; p < w; p += 64) {
-      const T xp = xs[p];
-      a0 += __builtin_nontemporal_load(va + p) * xp;
-      if (hb) a1 += __builtin_nontemporal_load(va + w + p) * xp;
+    for (int p0 = 0; p0 < w; p0 += 8 * 64) {
+      T ta[8], tb[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int p = p0 + lane + 64 * m;
+        ta[m] = p < w ? __builtin_nontemporal_load(va + p) : (T)0;
+        tb[m] = (hb && p < w) ? __builtin_nontemporal_load(va + w + p) : (T)0;
+      }
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int p = p0 + lane + 64 * m;
+        if (p < w) {
+          const T xp = xs[p];
+          a0 += ta[m] * xp;
+          if (hb) a1 += tb[m] * xp;
+        }
+      }
     }
   }
   a0 = wave_sum(a0, 64);

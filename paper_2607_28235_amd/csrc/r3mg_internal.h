@@ -82,6 +82,11 @@ struct DBuf {
 // ---------------------------------------------------------------------------------------------
 // Host analysis results
 // ---------------------------------------------------------------------------------------------
+struct LocalBlocks {  // local-column row blocks of a CSR pattern (device form: FineBlocks)
+  std::vector<int32_t> rb, ubp, ucol;
+  std::vector<uint8_t> lidx;  // 1 or 2 bytes per nonzero, plus kFinePad padding entries
+};
+
 struct HostLevel {           // agglomerated level l >= 1 (boxes of the R-tree at `depth`)
   int depth = 0;
   int64_t nbox = 0;
@@ -92,6 +97,10 @@ struct HostLevel {           // agglomerated level l >= 1 (boxes of the R-tree a
   std::vector<double> pt1d;    // l < L: injection into the parent box, nbox x d x (p'+1)^2 [axis][child node][parent node]
   int child_shift = 0;         // l >= 2: boxes of level l-1 per box of level l = 2^child_shift
   double max_extent = 0.0;
+  // l < L, when no block row is wider than 256 columns: the level as CSR (row (K, q) starts at
+  // B^2 bptr[K] + q nb_K B) and its 1-byte local-column row blocks
+  std::vector<int32_t> rowptr;
+  LocalBlocks loc;
 };
 
 struct Analysis {
@@ -107,8 +116,7 @@ struct Analysis {
   // fine-level row blocks: CSR geometries (2048/64, 4096/128, 4096/64 nonzeros/rows) and local-column
   // geometries (block offsets, distinct-column offsets and lists, local column index bytes per nonzero)
   std::vector<int32_t> rb[3];
-  std::vector<int32_t> lrb[3], lubp[3], lucol[3];
-  std::vector<uint8_t> lidx[3];
+  LocalBlocks loc[3];
   std::vector<uint8_t> constrained;      // internal order
   std::vector<uint8_t> constrained_user; // caller's order
   std::vector<int32_t> owner;            // internal point -> level-1 box, -1 if constrained

@@ -136,11 +136,11 @@ LevelOp<T> level_op(Ctx& c, int l) {
 // level for one right-hand side, a block-row kernel on coarse levels whose block rows fit LDS, the
 // lanes-per-row kernel otherwise.
 LevelKernel level_kernel(const Analysis& an, const DevLevel& D, int l, int nr, int esz) {
-  if (l == 0 && nr == 1 && D.fb[D.shape].nrb > 0) return LevelKernel::Stream;
+  if (nr == 1 && D.fb[D.shape].nrb > 0 && (l == 0 || D.shape == kLocalFirst + kLocalGeoms)) return LevelKernel::Stream;
   if (l > 0 && nr == 1 && D.maxnb > 0 && an.B >= 8 && (int64_t)D.maxnb * an.B >= 256 &&
       (int64_t)D.maxnb * an.B * esz <= 65536)
     return LevelKernel::BlockRowWG;
-  if (l > 0 && nr == 1 && D.maxnb > 0 && (int64_t)D.maxnb * an.B <= (int64_t)(65536 / esz - 256) / 4)
+  if (l > 0 && nr == 1 && D.maxnb > 0 && an.B <= 64 && blockrow_lds_bytes(an.B, D.maxnb * an.B, esz) <= 65536)
     return LevelKernel::BlockRow;
   return LevelKernel::Lanes;
 }
@@ -170,6 +170,8 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
   DevLevel& D = c.dv.lv[l];
   switch (level_kernel(c.an, D, l, nr, (int)sizeof(T))) {
     case LevelKernel::Stream:
+      op.ptr = D.rowptr.p;  // CSR row pointers (coarse levels: of the block-row layout)
+      op.idx = D.col.p;     // CSR columns (fine level only; coarse rows never take the long-row path)
       launch_level_stream<T>(D.shape, D.fb[D.shape], op, u, b, rho, x, dout, c1, c2, flags, skip,
                              nullptr, s);
       break;
@@ -579,6 +581,28 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
   R3MG_HIP_CHECK(hipMemsetAsync(D.rho.p, 0, D.rho.n, s));
 }
 
+// uploads local-column row blocks into slot g of a level and points the kernel shape kLocalFirst + g at them
+static void upload_local(DevLevel& D, int g, const LocalBlocks& lb, hipStream_t s) {
+  D.lrb[g].upload(lb.rb, s);
+  D.lubp[g].upload(lb.ubp, s);
+  D.lucol[g].upload(lb.ucol, s);
+  D.lidx[g].upload(lb.lidx, s);
+  FineBlocks& f = D.fb[kLocalFirst + g];
+  f.nrb = (int)lb.rb.size() - 1;
+  f.rb = D.lrb[g].p;
+  f.ubp = D.lubp[g].p;
+  f.ucol = D.lucol[g].p;
+  f.lidx = D.lidx[g].p;
+}
+
+// algorithmic bytes of one application with local-column blocks: values and local column positions,
+// distinct-column lists and offsets, row pointers, block offsets, 7 vector streams
+static double local_bytes(int64_t nnz, int64_t n, int g, const LocalBlocks& lb, double sv) {
+  const double nrb = (double)lb.rb.size() - 1;
+  return (double)nnz * (sv + kLocalIdxBytes[g]) + 4.0 * lb.ucol.size() + 4.0 * (nrb + 1) + (double)(n + 1) * 4 +
+         4.0 * (nrb + 1) + 7.0 * n * sv;
+}
+
 void device_setup(HandleImpl& h, hipStream_t s) {
   Analysis& an = *h.an;
   h.dev = std::make_unique<Device>();
@@ -625,21 +649,8 @@ void device_setup(HandleImpl& h, hipStream_t s) {
       }
     }
     for (int g = 0; g < kLocalGeoms; ++g) {
-      D.lrb[g].upload(an.lrb[g], s);
-      D.lubp[g].upload(an.lubp[g], s);
-      D.lucol[g].upload(an.lucol[g], s);
-      D.lidx[g].upload(an.lidx[g], s);
-      FineBlocks& f = D.fb[kLocalFirst + g];
-      f.nrb = (int)an.lrb[g].size() - 1;
-      f.rb = D.lrb[g].p;
-      f.ubp = D.lubp[g].p;
-      f.ucol = D.lucol[g].p;
-      f.lidx = D.lidx[g].p;
-      // values and local column positions, distinct-column lists and offsets, row pointers, block offsets,
-      // 7 vector streams
-      D.shape_bytes[kLocalFirst + g] = (double)an.nnz * (sv0 + kLocalIdxBytes[g]) + 4.0 * an.lucol[g].size() +
-                                       4.0 * (f.nrb + 1) + (double)(an.n + 1) * 4 + 4.0 * (f.nrb + 1) +
-                                       7.0 * an.n * sv0;
+      upload_local(D, g, an.loc[g], s);
+      D.shape_bytes[kLocalFirst + g] = local_bytes(an.nnz, an.n, g, an.loc[g], sv0);
     }
     // shape 9: the vector-load kernel over the blocks of local geometry 0
     D.fb[kLocalFirst + kLocalGeoms] = D.fb[kLocalFirst];
@@ -669,7 +680,8 @@ void device_setup(HandleImpl& h, hipStream_t s) {
       D.gal_ptr.upload(an.gal_ptr, s);
       D.gal_ent.upload(an.gal_ent, s);
     }
-    D.val64.alloc((size_t)D.nnz);
+    D.val64.alloc((size_t)D.nnz + kFinePad);  // zero padding: the local-column kernel's vector loads
+    R3MG_HIP_CHECK(hipMemsetAsync(D.val64.p, 0, D.val64.n * sizeof(double), s));
     D.dinv64.alloc(D.n);
     D.child_shift = H.child_shift;
     for (int64_t k = 0; k < H.nbox; ++k) D.maxnb = std::max<int>(D.maxnb, (int)(H.bptr[k + 1] - H.bptr[k]));
@@ -683,6 +695,13 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     D.lanes = lanes_for((double)(D.nnz) / (double)std::max<int64_t>(1, D.n));
     const double sv = fp32 ? 4 : 8;
     D.bytes_apply = (double)D.nnz * sv + (double)nblk * 4 + (double)(H.nbox + 1) * 4 + 7.0 * D.n * sv;
+    if (!H.rowptr.empty()) {  // narrow block rows: the level is also held as 1-byte local-column blocks
+      D.rowptr.upload(H.rowptr, s);
+      upload_local(D, 0, H.loc, s);
+      D.fb[kLocalFirst + kLocalGeoms] = D.fb[kLocalFirst];
+      D.shape = kLocalFirst + kLocalGeoms;
+      D.bytes_apply = local_bytes(D.nnz, D.n, 0, H.loc, sv);
+    }
   }
   numeric_setup(h, s);
   tune_stream_shape(h, s);
