@@ -100,8 +100,8 @@ int launch_spmv_dot(const LevelOp<double>& op, int nr, const double* p, double* 
 
 // transfers
 template <typename T>
-void launch_restrict0(int nbox, int d, int pc, int nr, const int* leaf_off, const int* owner, const T* xi,
-                      const T* src, T* bnext, const T* dinv_next, T* dnext, double inv_theta_next,
+void launch_restrict0(int nbox, int64_t n_points, int d, int pc, int nr, const int* leaf_off, const int* owner,
+                      const T* xi, const T* src, T* bnext, const T* dinv_next, T* dnext, double inv_theta_next,
                       const int* skip, hipStream_t s);
 template <typename T>
 void launch_prolong0(int n, int d, int pc, int nr, const int* owner, const T* xi, const T* e, const T* epend,

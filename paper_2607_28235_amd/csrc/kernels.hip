@@ -82,6 +82,34 @@ __device__ inline void lag1d(const Basis1D<T>& bs, T s, T* l) {
   }
 }
 
+// compile-time forms of lag1d / phi_q (same operations in the same order)
+template <typename T, int KB>
+__device__ inline void lag1d_k(const Basis1D<T>& bs, T s, T* l) {
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    T v = bs.w[j];
+#pragma unroll
+    for (int m = 0; m < KB; ++m)
+      if (m != j) v *= (s - bs.t[m]);
+    l[j] = v;
+  }
+}
+// calls f(q, phi_q) for q = 0 .. KB^D - 1 in ascending order
+template <typename T, int D, int KB, typename F>
+__device__ inline void for_each_phi(const T (*l)[4], F&& f) {
+  int q = 0;
+#pragma unroll
+  for (int q2 = 0; q2 < (D == 3 ? KB : 1); ++q2)
+#pragma unroll
+    for (int q1 = 0; q1 < KB; ++q1)
+#pragma unroll
+      for (int q0 = 0; q0 < KB; ++q0) {
+        T v = l[0][q0] * l[1][q1];
+        if (D == 3) v *= l[2][q2];
+        f(q++, v);
+      }
+}
+
 // phi_q of multi-index q = q0 + k q1 + k^2 q2 from 1D tables l[a][.]
 template <typename T>
 __device__ inline T phi_q(const T (*l)[4], int d, int k, int q) {
@@ -1155,73 +1183,129 @@ int launch_spmv_dot(const LevelOp<double>& op, int nr, const double* p, double* 
 // Transfers
 // =============================================================================================
 // Restriction to the first agglomerated level: b1[K*B+q] = sum_{i in K, i free} phi^K_q(xi_i) src_i.
-// One 64-thread workgroup per box; chunks of 64 points are staged through LDS ([q][lane]) and summed by
-// thread q in lane order (deterministic).  Optionally fuses the first Chebyshev direction of the next level:
-// dnext = dinv_next * b1 * inv_theta_next.
-template <typename T>
-__global__ __launch_bounds__(64) void k_restrict0(int d, Basis1D<T> bs, int nr, const int* __restrict__ leaf_off,
-                                                  const int* __restrict__ owner, const T* __restrict__ xi,
-                                                  const T* __restrict__ src, T* bnext, const T* __restrict__ dinv_next,
-                                                  T* dnext, T inv_theta_next, const int* __restrict__ skip) {
+// One workgroup of W waves per box (W = 1, 2 or 4: about one per 128-point chunk of an average box).  Wave w takes the box's points in chunks of 128
+// (chunk w, w + W, ...), two points per lane: the lane's two products per q go to LDS ([q][lane]), then
+// L = floor(64 / B) lanes sum each q-row of the chunk (lane s takes columns s, s + L, ...) and lane q adds the L
+// sums in lane order to its running total.  Finally wave 0 adds the W wave totals in wave order (deterministic).
+// Optionally fuses the first Chebyshev direction of the next level: dnext = dinv_next * b1 * inv_theta_next.
+template <typename T, int D, int KB>
+__global__ __launch_bounds__(256) void k_restrict0(Basis1D<T> bs, int nr, const int* __restrict__ leaf_off,
+                                                   const int* __restrict__ owner, const T* __restrict__ xi,
+                                                   const T* __restrict__ src, T* bnext, const T* __restrict__ dinv_next,
+                                                   T* dnext, T inv_theta_next, const int* __restrict__ skip) {
+  constexpr int B = D == 3 ? KB * KB * KB : KB * KB;
+  constexpr int L = 64 / B;
   if (skip && *skip) return;
   extern __shared__ unsigned char smem_raw[];
-  T* sh = reinterpret_cast<T*>(smem_raw);  // [B][65] (padded rows)
+  const int W = blockDim.x >> 6;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T* sh = reinterpret_cast<T*>(smem_raw) + (size_t)wv * (B * 65 + 64);  // [B][65] products, then [64] sums
+  T* part = sh + B * 65;
+  T* wtot = reinterpret_cast<T*>(smem_raw) + (size_t)W * (B * 65 + 64);  // [W][64]
   const int K = blockIdx.x;
-  const int k = bs.k;
-  const int B = (d == 3) ? k * k * k : k * k;
   const int i0 = leaf_off[K], i1 = leaf_off[K + 1];
-  const int lane = threadIdx.x;
+  const int q = lane / L, sv = lane - q * L;
   for (int c = 0; c < nr; ++c) {
-    T tot = 0;  // thread q's running sum (q = lane < B)
-    for (int base = i0; base < i1; base += 64) {
-      const int i = base + lane;
-      T l[3][4];
-      T r = 0;
-      bool ok = (i < i1) && owner[i] >= 0;
-      if (ok) {
-        r = src[(int64_t)i * nr + c];
-        for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)i * d + a], l[a]);
+    T tot = 0;  // lane q's running sum (q = lane < B)
+    for (int base = i0 + wv * 128; base < i1; base += W * 128) {
+      const int ia = base + lane, ib = base + 64 + lane;
+      const bool oka = ia < i1 && owner[ia] >= 0, okb = ib < i1 && owner[ib] >= 0;
+      T la[3][4], lbv[3][4];
+      T ra = 0, rb = 0;
+      if (oka) {
+        ra = src[(int64_t)ia * nr + c];
+#pragma unroll
+        for (int a = 0; a < D; ++a) lag1d_k<T, KB>(bs, xi[(int64_t)ia * D + a], la[a]);
+      } else {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int j = 0; j < KB; ++j) la[a][j] = 0;
       }
-      for (int q = 0; q < B; ++q) sh[q * 65 + lane] = ok ? phi_q<T>(l, d, k, q) * r : (T)0;
-      __syncthreads();
+      if (okb) {
+        rb = src[(int64_t)ib * nr + c];
+#pragma unroll
+        for (int a = 0; a < D; ++a) lag1d_k<T, KB>(bs, xi[(int64_t)ib * D + a], lbv[a]);
+      }
+      for_each_phi<T, D, KB>(la, [&](int qq, T ph) { sh[qq * 65 + lane] = ph * ra; });
+      if (okb) for_each_phi<T, D, KB>(lbv, [&](int qq, T ph) { sh[qq * 65 + lane] += ph * rb; });
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      T a = 0;
+      if (q < B)
+        for (int m = sv; m < 64; m += L) a += sh[q * 65 + m];
+      part[lane] = a;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (lane < B) {
-        T s = 0;
-        for (int m = 0; m < 64; ++m) s += sh[lane * 65 + m];
-        tot += s;
+        T t = 0;
+#pragma unroll
+        for (int s2 = 0; s2 < L; ++s2) t += part[lane * L + s2];
+        tot += t;
       }
-      __syncthreads();
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (lane < B) {
+    wtot[wv * 64 + lane] = tot;
+    __syncthreads();
+    if (wv == 0 && lane < B) {
+      T t = 0;
+      for (int w2 = 0; w2 < W; ++w2) t += wtot[w2 * 64 + lane];
       const int64_t o = ((int64_t)K * B + lane) * nr + c;
-      bnext[o] = tot;
-      if (dnext) dnext[o] = dinv_next[(int64_t)K * B + lane] * tot * inv_theta_next;
+      bnext[o] = t;
+      if (dnext) dnext[o] = dinv_next[(int64_t)K * B + lane] * t * inv_theta_next;
     }
+    __syncthreads();
   }
 }
 
 template <typename T>
-void launch_restrict0(int nbox, int d, int pc, int nr, const int* leaf_off, const int* owner, const T* xi,
-                      const T* src, T* bnext, const T* dinv_next, T* dnext, double inv_theta_next,
+void launch_restrict0(int nbox, int64_t n_points, int d, int pc, int nr, const int* leaf_off, const int* owner,
+                      const T* xi, const T* src, T* bnext, const T* dinv_next, T* dnext, double inv_theta_next,
                       const int* skip, hipStream_t s) {
   const int k = pc + 1;
   const int B = (d == 3) ? k * k * k : k * k;
-  size_t shm = sizeof(T) * B * 65;
-  hipLaunchKernelGGL((k_restrict0<T>), dim3(nbox), dim3(64), shm, s, d, make_basis<T>(pc), nr, leaf_off, owner, xi,
-                     src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);
+  if (nbox == 0) return;
+  // waves per box: one per 128-point chunk of an average box, at most 4
+  int W = 1;
+  while (W < 4 && (int64_t)W * 128 * nbox < n_points) W <<= 1;
+  auto lds = [&](int w) { return sizeof(T) * ((size_t)w * (B * 65 + 64) + (size_t)w * 64); };
+  while (W > 1 && lds(W) > 65536) W >>= 1;
+  const Basis1D<T> bs = make_basis<T>(pc);
+#define R3MG_R0(DD, KK)                                                                                           \
+  hipLaunchKernelGGL((k_restrict0<T, DD, KK>), dim3(nbox), dim3(64 * W), lds(W), s, bs, nr, leaf_off, owner, xi, src, \
+                     bnext, dinv_next, dnext, (T)inv_theta_next, skip)
+  switch (d * 8 + k) {
+    case 17: R3MG_R0(2, 1); break;
+    case 18: R3MG_R0(2, 2); break;
+    case 19: R3MG_R0(2, 3); break;
+    case 20: R3MG_R0(2, 4); break;
+    case 25: R3MG_R0(3, 1); break;
+    case 26: R3MG_R0(3, 2); break;
+    case 27: R3MG_R0(3, 3); break;
+    case 28: R3MG_R0(3, 4); break;
+    default: throw std::runtime_error("restriction: unsupported dimension or degree");
+  }
+#undef R3MG_R0
   check_launch("k_restrict0");
 }
-template void launch_restrict0<float>(int, int, int, int, const int*, const int*, const float*, const float*,
-                                      float*, const float*, float*, double, const int*, hipStream_t);
-template void launch_restrict0<double>(int, int, int, int, const int*, const int*, const double*, const double*,
-                                       double*, const double*, double*, double, const int*, hipStream_t);
+template void launch_restrict0<float>(int, int64_t, int, int, int, const int*, const int*, const float*,
+                                      const float*, float*, const float*, float*, double, const int*, hipStream_t);
+template void launch_restrict0<double>(int, int64_t, int, int, int, const int*, const int*, const double*,
+                                       const double*, double*, const double*, double*, double, const int*,
+                                       hipStream_t);
 
 // Prolongation from the first agglomerated level: v_i = sum_q phi^K_q(xi_i) (e + epend)[K*B+q] (0 if i is
 // constrained).  One thread per fine point.
-template <typename T>
-__global__ __launch_bounds__(256) void k_prolong0(int n, int d, Basis1D<T> bs, int nr, const int* __restrict__ owner,
+template <typename T, int D, int KB>
+__global__ __launch_bounds__(256) void k_prolong0(int n, Basis1D<T> bs, int nr, const int* __restrict__ owner,
                                                   const T* __restrict__ xi, const T* __restrict__ e,
                                                   const T* __restrict__ epend, T* v, const int* __restrict__ skip,
                                                   int nlog) {
+  constexpr int B = D == 3 ? KB * KB * KB : KB * KB;
   if (skip && *skip) return;
   const int lb = xcd_block(nlog);
   if (lb < 0) return;
@@ -1232,18 +1316,17 @@ __global__ __launch_bounds__(256) void k_prolong0(int n, int d, Basis1D<T> bs, i
     for (int c = 0; c < nr; ++c) v[(int64_t)i * nr + c] = 0;
     return;
   }
-  const int k = bs.k;
-  const int B = (d == 3) ? k * k * k : k * k;
   T l[3][4];
-  for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)i * d + a], l[a]);
+#pragma unroll
+  for (int a = 0; a < D; ++a) lag1d_k<T, KB>(bs, xi[(int64_t)i * D + a], l[a]);
   for (int c = 0; c < nr; ++c) {
     T s = 0;
-    for (int q = 0; q < B; ++q) {
+    for_each_phi<T, D, KB>(l, [&](int q, T ph) {
       const int64_t o = ((int64_t)K * B + q) * nr + c;
       T ev = e[o];
       if (epend) ev += epend[o];
-      s += phi_q<T>(l, d, k, q) * ev;
-    }
+      s += ph * ev;
+    });
     v[(int64_t)i * nr + c] = s;
   }
 }
@@ -1252,8 +1335,23 @@ template <typename T>
 void launch_prolong0(int n, int d, int pc, int nr, const int* owner, const T* xi, const T* e, const T* epend,
                      T* v, const int* skip, hipStream_t s) {
   const int nlog = (n + 255) / 256;
-  hipLaunchKernelGGL((k_prolong0<T>), dim3(xcd_grid(nlog)), dim3(256), 0, s, n, d, make_basis<T>(pc), nr, owner, xi,
-                     e, epend, v, skip, nlog);
+  if (nlog == 0) return;
+  const Basis1D<T> bs = make_basis<T>(pc);
+#define R3MG_P0(DD, KK)                                                                                            \
+  hipLaunchKernelGGL((k_prolong0<T, DD, KK>), dim3(xcd_grid(nlog)), dim3(256), 0, s, n, bs, nr, owner, xi, e, epend, v, \
+                     skip, nlog)
+  switch (d * 8 + pc + 1) {
+    case 17: R3MG_P0(2, 1); break;
+    case 18: R3MG_P0(2, 2); break;
+    case 19: R3MG_P0(2, 3); break;
+    case 20: R3MG_P0(2, 4); break;
+    case 25: R3MG_P0(3, 1); break;
+    case 26: R3MG_P0(3, 2); break;
+    case 27: R3MG_P0(3, 3); break;
+    case 28: R3MG_P0(3, 4); break;
+    default: throw std::runtime_error("prolongation: unsupported dimension or degree");
+  }
+#undef R3MG_P0
   check_launch("k_prolong0");
 }
 template void launch_prolong0<float>(int, int, int, int, const int*, const float*, const float*, const float*,
@@ -1278,24 +1376,60 @@ __device__ inline T pt_entry(const T* __restrict__ pt, int64_t c, int d, int k, 
 }
 
 // Restriction between agglomerated levels: b[G*B+q] = sum_{C child of G} sum_q' P~_C[q'][q] src[C*B+q'].
+// One wave per parent box G (4 per workgroup): the children's entries and 1D injection factors are staged in
+// LDS, then lane q sums over the children in order and over q' in ascending order, each P~ entry formed as the
+// product of its 1D factors in axis order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict_c(int nbox_next, int nbox, int shift, int d, int k, int nr,
                                                     const T* __restrict__ pt, const T* __restrict__ src, T* bnext,
                                                     const T* __restrict__ dinv_next, T* dnext, T inv_theta_next,
                                                     const int* __restrict__ skip) {
   if (skip && *skip) return;
+  extern __shared__ unsigned char smem_raw[];
   const int B = (d == 3) ? k * k * k : k * k;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)nbox_next * B) return;
-  const int G = (int)(t / B), q = (int)(t - (int64_t)G * B);
+  const int kk = k * k;
+  const int nch = 1 << shift;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int G = blockIdx.x * 4 + wv;
+  if (G >= nbox_next) return;  // whole wave leaves; only wave-level barriers follow
+  T* srcs = reinterpret_cast<T*>(smem_raw) + (size_t)wv * nch * (B + d * kk);
+  T* pts = srcs + nch * B;
   const int c0 = G << shift;
   const int c1 = min(nbox, (G + 1) << shift);
+  const int nc = c1 - c0;
+  for (int t = lane; t < nc * d * kk; t += 64) pts[t] = pt[(int64_t)c0 * d * kk + t];
+  int q0 = 0, q1 = 0, q2 = 0;
+  if (lane < B) {
+    q0 = lane % k;
+    q1 = (lane / k) % k;
+    q2 = lane / kk;
+  }
   for (int c = 0; c < nr; ++c) {
-    T s = 0;
-    for (int C = c0; C < c1; ++C)
-      for (int qc = 0; qc < B; ++qc) s += pt_entry(pt, C, d, k, qc, q) * src[((int64_t)C * B + qc) * nr + c];
-    bnext[t * nr + c] = s;
-    if (dnext) dnext[t * nr + c] = dinv_next[t] * s * inv_theta_next;
+    for (int t = lane; t < nc * B; t += 64) srcs[t] = src[((int64_t)c0 * B + t) * nr + c];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < B) {
+      T s = 0;
+      for (int C = 0; C < nc; ++C) {
+        const T* m = pts + C * d * kk;
+        const T* sc = srcs + C * B;
+        int qc = 0;
+        for (int a2 = 0; a2 < (d == 3 ? k : 1); ++a2)
+          for (int a1 = 0; a1 < k; ++a1)
+            for (int a0 = 0; a0 < k; ++a0, ++qc) {
+              T v = m[a0 * k + q0] * m[kk + a1 * k + q1];
+              if (d == 3) v *= m[2 * kk + a2 * k + q2];
+              s += v * sc[qc];
+            }
+      }
+      const int64_t t = (int64_t)G * B + lane;
+      bnext[t * nr + c] = s;
+      if (dnext) dnext[t * nr + c] = dinv_next[t] * s * inv_theta_next;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -1305,9 +1439,11 @@ void launch_restrict_c(int nbox_next, int nbox, int shift, int d, int pc, int nr
                        hipStream_t s) {
   const int k = pc + 1;
   const int B = (d == 3) ? k * k * k : k * k;
-  const int64_t tot = (int64_t)nbox_next * B;
-  hipLaunchKernelGGL((k_restrict_c<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nbox_next, nbox, shift, d,
-                     k, nr, pt, src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);
+  if (nbox_next == 0) return;
+  if (B > 64) throw std::runtime_error("restriction: more than 64 coarse functions per box");
+  const size_t shm = sizeof(T) * (size_t)4 * (1 << shift) * (B + d * k * k);
+  hipLaunchKernelGGL((k_restrict_c<T>), dim3((unsigned)((nbox_next + 3) / 4)), dim3(256), shm, s, nbox_next, nbox, shift,
+                     d, k, nr, pt, src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);
   check_launch("k_restrict_c");
 }
 template void launch_restrict_c<float>(int, int, int, int, int, int, const float*, const float*, float*,

@@ -390,7 +390,7 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   if (l == 0) {
     const T* xi;
     if constexpr (sizeof(T) == 4) xi = D.xi32.p; else xi = D.xi64.p;
-    launch_restrict0<T>((int)N.nbox, an.d, an.pc, nr, D.leaf_off.p, D.owner.p, xi, src, vbuf<T>(N.b), dinv_next,
+    launch_restrict0<T>((int)N.nbox, an.n, an.d, an.pc, nr, D.leaf_off.p, D.owner.p, xi, src, vbuf<T>(N.b), dinv_next,
                         dnext, next_inv_theta, skip, s);
   } else {
     const T* pt;
