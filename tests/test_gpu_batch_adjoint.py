@@ -138,6 +138,9 @@ def test_adjoint_gradient_matches_oracle(adjoint_small):
 
 
 def test_adjoint_gradient_finite_differences(adjoint_small):
+    """Central differences in the difference form (no cancellation between two full solves): with
+    A(kappa +- h e_e) du = -+ h K_e u_e on the unconstrained rows, L(kappa +- h) - L = (u - u_t).du + |du|^2 / 2.
+    Relative agreement 1e-6 on six seeded cells."""
     prob, kappa, ut, op = adjoint_small
     _case("adjoint gradient vs central differences")
     kt = _t(kappa).requires_grad_(True)
@@ -145,15 +148,24 @@ def test_adjoint_gradient_finite_differences(adjoint_small):
     L = 0.5 * torch.sum((u - _t(ut)) ** 2)
     L.backward()
     g = kt.grad.cpu().numpy()
+    un = u.detach().cpu().numpy()
     cells = F.rng(5, F.PURPOSE_FDCELLS).choice(len(kappa), size=6, replace=False)
     for e in cells:
         h = 1e-3 * kappa[e]
-        vals = []
+        nodes = prob.cells[e]
+        Ke = prob.Ke if prob.Ke.ndim == 2 else prob.Ke[e]
+        Ku = Ke @ un[nodes]
+        dL = []
         for sgn in (1.0, -1.0):
             kp = kappa.copy()
             kp[e] += sgn * h
-            with torch.no_grad():
-                up = op(_t(kp))
-            vals.append(0.5 * float(torch.sum((up - _t(ut)) ** 2)))
-        fd = (vals[0] - vals[1]) / (2 * h)
-        assert abs(fd - g[e]) <= 1e-5 * max(abs(g[e]), 1e-3 * np.abs(g).max()), (e, fd, g[e])
+            op.set_kappa(_t(kp))
+            rhs = np.zeros(prob.n)
+            np.add.at(rhs, nodes, -sgn * h * Ku)
+            rhs[prob.boundary] = 0.0
+            du, _ = op.solve_field(_t(rhs))
+            du = du.cpu().numpy()
+            dL.append((un - ut) @ du + 0.5 * du @ du)
+        op.invalidate()
+        fd = (dL[0] - dL[1]) / (2 * h)
+        assert abs(fd - g[e]) <= 1e-6 * max(abs(g[e]), 1e-3 * np.abs(g).max()), (e, fd, g[e])
