@@ -71,6 +71,11 @@ typedef struct {
                            (4096, 64, 1024) and (4096, 128, 1024)); 9: shape 6 with vector loads.  Every shape sums a row
                            in the same order, so results do not depend on this choice when no row has more than
                            256 nonzeros. */
+  int multi_rhs_kernel; /* fine-level kernel for several right-hand sides: -1 = the fastest timed at the first
+                           multi-RHS solve [-1]; 0 = lanes-per-row CSR kernel (each lane all columns of its
+                           nonzeros); 1 / 2 = local-column blocks with 1- / 2-byte positions (each block's distinct
+                           columns gathered once per column group); 3 = CSR with the columns split over lanes (each
+                           nonzero's u row read as consecutive 16-byte pieces) */
 } r3mg_options;
 
 typedef struct {

@@ -39,7 +39,7 @@ class _Options(C.Structure):
                 ("max_coarse_dofs", C.c_int), ("skip_leaf_level", C.c_int), ("cheb_degree", C.c_int),
                 ("pre_steps", C.c_int), ("post_steps", C.c_int), ("lanczos_steps", C.c_int),
                 ("cheb_boost", C.c_double), ("cheb_ratio", C.c_double), ("vcycle_fp32", C.c_int),
-                ("use_graph", C.c_int), ("fine_kernel", C.c_int)]
+                ("use_graph", C.c_int), ("fine_kernel", C.c_int), ("multi_rhs_kernel", C.c_int)]
 
 
 class _LevelInfo(C.Structure):
@@ -65,6 +65,7 @@ class Options:
     vcycle_fp32: int = 0
     use_graph: int = 1
     fine_kernel: int = -1
+    multi_rhs_kernel: int = -1
 
     def _c(self) -> _Options:
         return _Options(**dataclasses.asdict(self))

@@ -144,6 +144,22 @@ void launch_galerkin_c(int64_t nblocks, int d, int pc, int shift, int nbox_in, c
 void launch_to_dense(int nbox, int B, const int* bptr, const int* bcol, const double* val, double* dense,
                      hipStream_t s);
 void launch_lanczos_start(int n, const int* perm, double* v, hipStream_t s);
+// Multi-right-hand-side CSR kernel with the columns split over lanes: G lanes per row, NR / GW column groups of
+// GW = 16 / sizeof(T) columns each (G a power of two, nr / GW <= G <= 64; CSR operators only).  Same flags and
+// epilogue as launch_level.  Returns false (nothing launched) for an unsupported nr or G.
+template <typename T>
+bool launch_level_split(const LevelOp<T>& op, int nr, int G, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
+                        double c2, int flags, const int* skip, hipStream_t s);
+// Multi-right-hand-side form of the local-column kernel over the blocks of local geometry geom (0: 1-byte
+// positions, 256 distinct columns; 1: 2-byte, 1024): nr in {2, 4, 8, 16} (float: 4, 8, 16).  Same flags and
+// epilogue as launch_level.  Returns false (nothing launched) for an unsupported nr or geometry.
+template <typename T>
+bool launch_level_local_mr(int geom, const FineBlocks& fb, const LevelOp<T>& op, int nr, const T* u, const T* b,
+                           T* rho, T* x, T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s);
+// partial sums of p_k q_k per column of n x nr interleaved vectors in a fixed partition:
+// partials[blk * nr + k]; returns the number of blocks (<= 1024)
+int launch_pcg_dot_mr(int n, int nr, const double* p, const double* q, double* partials, const int* skip,
+                      hipStream_t s);
 // partial sums of p_i q_i for one PCG column in a fixed partition (returns the count, <= 1024)
 int launch_pcg_dot(int n, const double* p, const double* q, double* partials, const int* skip, hipStream_t s);
 // partial sums of w_i x_i y_i (w may be null) -> partials (returns count)

@@ -157,12 +157,41 @@ __device__ inline void row_product(int row, int lane, int G, int blk, const int*
                                    const int* __restrict__ idx, const T* __restrict__ val,
                                    const T* __restrict__ u, T* acc) {
   if (!BLOCKED) {
+    // UNR steps per batch: their column, value and u loads are all in flight before the products (each lane
+    // still accumulates its entries in ascending order)
+    constexpr int UNR = NR >= 16 ? 2 : 32 / NR;
     const int s = ptr[row], e = ptr[row + 1];
-    for (int p = s + lane; p < e; p += G) {
-      const T a = val[p];
-      const int64_t c = (int64_t)idx[p] * NR;
+    for (int p0 = s + lane; p0 < e; p0 += UNR * G) {
+      T a[UNR];
+      int64_t c[UNR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] += a * u[c + k];
+      for (int m = 0; m < UNR; ++m) {
+        const int p = p0 + m * G;
+        a[m] = p < e ? val[p] : (T)0;
+        c[m] = p < e ? (int64_t)idx[p] * NR : 0;
+      }
+      T uv[UNR][NR];
+      constexpr int VW = 16 / (int)sizeof(T);  // entries per 16-byte load (u rows are NR-aligned)
+      if constexpr (NR % VW == 0) {
+        typedef T V16 __attribute__((ext_vector_type(VW)));
+#pragma unroll
+        for (int m = 0; m < UNR; ++m)
+#pragma unroll
+          for (int k = 0; k < NR; k += VW) {
+            const V16 t = *reinterpret_cast<const V16*>(u + c[m] + k);
+#pragma unroll
+            for (int w = 0; w < VW; ++w) uv[m][k + w] = t[w];
+          }
+      } else {
+#pragma unroll
+        for (int m = 0; m < UNR; ++m)
+#pragma unroll
+          for (int k = 0; k < NR; ++k) uv[m][k] = u[c[m] + k];
+      }
+#pragma unroll
+      for (int m = 0; m < UNR; ++m)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] += a[m] * uv[m][k];
     }
   } else {
     const int K = row / blk;
@@ -916,6 +945,286 @@ template int launch_level_stream<double>(int, const FineBlocks&, const LevelOp<d
                                          const double*, double*, double*, double*, double, double, int, const int*,
                                          double*, hipStream_t);
 // ==== end of fine-level row-block kernels ====
+
+// Multi-right-hand-side CSR kernel with the columns split over lanes (NR columns, interleaved n x NR vectors).
+// G lanes per row (G a power of two, NG <= G <= 64, NG = NR / GW, GW = 16 / sizeof(T)): lane (j, s) owns the
+// column group j (GW consecutive columns, one 16-byte load per nonzero) and the row's entries s, s + G/NG, ...;
+// so the NG lanes of one nonzero read its u row as consecutive 16-byte pieces.  The G/NG entry lanes of a group
+// are combined by a butterfly and lane s = 0 applies the epilogue of k_level to its GW columns.
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_level_split(int n, int G, const int* __restrict__ ptr,
+                                                     const int* __restrict__ idx, const T* __restrict__ val,
+                                                     const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
+                                                     const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
+                                                     const int* __restrict__ skip, int nlog) {
+  constexpr int GW = 16 / (int)sizeof(T);
+  constexpr int NG = NR / GW;
+  constexpr int UNR = 4;
+  static_assert(NR % GW == 0, "column groups");
+  typedef T VG __attribute__((ext_vector_type(GW)));
+  if (skip && *skip) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int rpb = 256 / G;
+  const int li = threadIdx.x % G;
+  const int j = li % NG, sv = li / NG, S = G / NG;
+  const int row = lb * rpb + threadIdx.x / G;
+  VG acc = (VG)0;
+  if (row < n) {
+    const int s = ptr[row], e = ptr[row + 1];
+    for (int p0 = s + sv; p0 < e; p0 += UNR * S) {
+      T a[UNR];
+      int64_t c[UNR];
+#pragma unroll
+      for (int m = 0; m < UNR; ++m) {
+        const int p = p0 + m * S;
+        a[m] = p < e ? val[p] : (T)0;
+        c[m] = p < e ? (int64_t)idx[p] * NR + j * GW : j * GW;
+      }
+      VG uv[UNR];
+#pragma unroll
+      for (int m = 0; m < UNR; ++m) uv[m] = *reinterpret_cast<const VG*>(u + c[m]);
+#pragma unroll
+      for (int m = 0; m < UNR; ++m) acc += a[m] * uv[m];
+    }
+  }
+  for (int off = NG; off < G; off <<= 1)
+#pragma unroll
+    for (int w = 0; w < GW; ++w) acc[w] += __shfl_xor(acc[w], off, 64);
+  if (sv == 0 && row < n) {
+    const int64_t o = (int64_t)row * NR + j * GW;
+    if (flags & F_PLAIN) {
+      *reinterpret_cast<VG*>(rho + o) = acc;
+    } else {
+      const VG old = (flags & F_RHO_FROM_B) ? *reinterpret_cast<const VG*>(b + o) : *reinterpret_cast<VG*>(rho + o);
+      const VG r = old - acc;
+      if (flags & F_RHO_STORE) *reinterpret_cast<VG*>(rho + o) = r;
+      const VG ui = *reinterpret_cast<const VG*>(u + o);
+      if (flags & F_X_ASSIGN)
+        *reinterpret_cast<VG*>(x + o) = ui;
+      else if (flags & F_X_ADD)
+        *reinterpret_cast<VG*>(x + o) = *reinterpret_cast<VG*>(x + o) + ui;
+      if (flags & F_D_OUT) *reinterpret_cast<VG*>(dout + o) = c1 * ui + (c2 * dinv[row]) * r;
+    }
+  }
+}
+
+template <typename T>
+bool launch_level_split(const LevelOp<T>& op, int nr, int G, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
+                        double c2, int flags, const int* skip, hipStream_t s) {
+  constexpr int GW = 16 / (int)sizeof(T);
+  if (nr % GW != 0 || G < nr / GW || G > 64 || (G & (G - 1)) != 0 || op.blk != 1) return false;
+  const int rpb = 256 / G;
+  const int nlog = (op.n + rpb - 1) / rpb;
+  if (nlog == 0) return true;
+#define R3MG_SPLIT(NRV)                                                                                             \
+  hipLaunchKernelGGL((k_level_split<T, (NRV < GW ? GW : NRV)>), dim3(xcd_grid(nlog)), dim3(256), 0, s, op.n, G, op.ptr, \
+                     op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog)
+  switch (nr) {
+    case 2: R3MG_SPLIT(2); break;
+    case 4: R3MG_SPLIT(4); break;
+    case 8: R3MG_SPLIT(8); break;
+    case 16: R3MG_SPLIT(16); break;
+    default: return false;
+  }
+#undef R3MG_SPLIT
+  check_launch("k_level_split");
+  return true;
+}
+template bool launch_level_split<float>(const LevelOp<float>&, int, int, const float*, const float*, float*, float*,
+                                        float*, double, double, int, const int*, hipStream_t);
+template bool launch_level_split<double>(const LevelOp<double>&, int, int, const double*, const double*, double*,
+                                         double*, double*, double, double, int, const int*, hipStream_t);
+
+// Multi-right-hand-side local-column kernel (NR columns, interleaved n x NR vectors).  One workgroup per
+// local-column row block: the block's values and column positions are staged in LDS once; then for each group of
+// GW = 16 / sizeof(T) columns, u at the block's distinct columns is gathered with one 16-byte load per column
+// into LDS, each row is summed by TPR = 256 / RPB lanes (lane s takes the row's entries s, s + TPR, ...; the lane
+// sums are combined by a butterfly) and lane 0 of the row applies the epilogue of k_level to the GW columns with
+// 16-byte loads and stores.  A block with more than UCAP distinct columns is a single row, summed by the whole
+// workgroup through the CSR columns.
+template <typename T, int NR, typename IX, int CAP, int RPB, int UCAP>
+__global__ __launch_bounds__(256) void k_level_local_mr(int nrb, const int* __restrict__ rb,
+                                                        const int* __restrict__ ubp, const int* __restrict__ ucol,
+                                                        const IX* __restrict__ lidx, const int* __restrict__ ptr,
+                                                        const int* __restrict__ idx, const T* __restrict__ val,
+                                                        const T* __restrict__ u, const T* __restrict__ b, T* rho,
+                                                        T* x, const T* __restrict__ dinv, T* dout, T c1, T c2,
+                                                        int flags, const int* __restrict__ skip) {
+  constexpr int GW = 16 / (int)sizeof(T);
+  constexpr int NG = NR / GW;
+  constexpr int TPR = 256 / RPB;
+  static_assert(NR % GW == 0, "column groups");
+  typedef T VG __attribute__((ext_vector_type(GW)));
+  if (skip && *skip) return;
+  const int lb = xcd_block(nrb);
+  if (lb < 0) return;
+  __shared__ T sval[CAP];
+  __shared__ IX spos[CAP];
+  __shared__ VG us[UCAP];
+  __shared__ VG shr[4];
+  const int r0 = rb[lb], r1 = rb[lb + 1];
+  const int e0 = ptr[r0], e1 = ptr[r1];
+  const int nz = e1 - e0;
+  const int u0 = ubp[lb], nu = ubp[lb + 1] - u0;
+  const bool staged = nu <= UCAP;
+  const int rl = threadIdx.x / TPR, sub = threadIdx.x % TPR;
+  const int row = r0 + rl;
+  int rs = 0, re = 0;
+  if (staged) {
+    constexpr int EPT = CAP / 256;
+    T vv[EPT];
+    IX pp[EPT];
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int e = threadIdx.x + 256 * m;
+      if (e < nz) {
+        vv[m] = __builtin_nontemporal_load(val + e0 + e);
+        pp[m] = __builtin_nontemporal_load(lidx + e0 + e);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int e = threadIdx.x + 256 * m;
+      if (e < nz) {
+        sval[e] = vv[m];
+        spos[e] = pp[m];
+      }
+    }
+    if (row < r1) {
+      rs = ptr[row] - e0;
+      re = ptr[row + 1] - e0;
+    }
+  }
+  for (int g = 0; g < NG; ++g) {
+    VG t;
+    int trow = -1;
+    if (staged) {
+      for (int c = threadIdx.x; c < nu; c += 256)
+        us[c] = *reinterpret_cast<const VG*>(u + (int64_t)ucol[u0 + c] * NR + g * GW);
+      __syncthreads();
+      VG acc = (VG)0;
+      for (int kk = rs + sub; kk < re; kk += TPR) acc += sval[kk] * us[spos[kk]];
+#pragma unroll
+      for (int off = TPR / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int w = 0; w < GW; ++w) acc[w] += __shfl_xor(acc[w], off, 64);
+      t = acc;
+      if (sub == 0 && row < r1) trow = row;
+      __syncthreads();  // us is restaged by the next group
+    } else {  // one long row
+      VG acc = (VG)0;
+      for (int e = e0 + threadIdx.x; e < e1; e += 256)
+        acc += val[e] * *reinterpret_cast<const VG*>(u + (int64_t)idx[e] * NR + g * GW);
+#pragma unroll
+      for (int w = 0; w < GW; ++w) acc[w] = wave_sum(acc[w], 64);
+      if ((threadIdx.x & 63) == 0) shr[threadIdx.x >> 6] = acc;
+      __syncthreads();
+      t = (shr[0] + shr[1]) + (shr[2] + shr[3]);
+      if (threadIdx.x == 0) trow = r0;
+      __syncthreads();
+    }
+    if (trow >= 0) {
+      const int64_t o = (int64_t)trow * NR + g * GW;
+      if (flags & F_PLAIN) {
+        *reinterpret_cast<VG*>(rho + o) = t;
+      } else {
+        const VG old = (flags & F_RHO_FROM_B) ? *reinterpret_cast<const VG*>(b + o) : *reinterpret_cast<VG*>(rho + o);
+        const VG r = old - t;
+        if (flags & F_RHO_STORE) *reinterpret_cast<VG*>(rho + o) = r;
+        const VG ui = *reinterpret_cast<const VG*>(u + o);
+        if (flags & F_X_ASSIGN)
+          *reinterpret_cast<VG*>(x + o) = ui;
+        else if (flags & F_X_ADD)
+          *reinterpret_cast<VG*>(x + o) = *reinterpret_cast<VG*>(x + o) + ui;
+        if (flags & F_D_OUT) *reinterpret_cast<VG*>(dout + o) = c1 * ui + (c2 * dinv[trow]) * r;
+      }
+    }
+  }
+}
+
+template <typename T, int NR, typename IX, int CAP, int RPB, int UCAP>
+static void launch_local_mr_t(const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
+                              T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL((k_level_local_mr<T, NR, IX, CAP, RPB, UCAP>), dim3(xcd_grid(fb.nrb)), dim3(256), 0, s, fb.nrb,
+                     fb.rb, fb.ubp, fb.ucol, static_cast<const IX*>(fb.lidx), op.ptr, op.idx, op.val, u, b, rho, x,
+                     op.dinv, dout, (T)c1, (T)c2, flags, skip);
+}
+
+template <typename T>
+bool launch_level_local_mr(int geom, const FineBlocks& fb, const LevelOp<T>& op, int nr, const T* u, const T* b,
+                           T* rho, T* x, T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s) {
+  constexpr int GW = 16 / (int)sizeof(T);
+  if (fb.nrb == 0 || nr % GW != 0 || (geom != 0 && geom != 1)) return false;
+#define R3MG_MR(NRV)                                                                                              \
+  do {                                                                                                            \
+    if (geom == 0)                                                                                                \
+      launch_local_mr_t<T, (NRV < GW ? GW : NRV), uint8_t, 2048, 64, 256>(fb, op, u, b, rho, x, dout, c1, c2, flags, \
+                                                                          skip, s);                                \
+    else                                                                                                          \
+      launch_local_mr_t<T, (NRV < GW ? GW : NRV), uint16_t, 4096, 64, 1024>(fb, op, u, b, rho, x, dout, c1, c2,    \
+                                                                            flags, skip, s);                       \
+  } while (0)
+  switch (nr) {
+    case 2: R3MG_MR(2); break;
+    case 4: R3MG_MR(4); break;
+    case 8: R3MG_MR(8); break;
+    case 16: R3MG_MR(16); break;
+    default: return false;
+  }
+#undef R3MG_MR
+  check_launch("k_level_local_mr");
+  return true;
+}
+template bool launch_level_local_mr<float>(int, const FineBlocks&, const LevelOp<float>&, int, const float*,
+                                           const float*, float*, float*, float*, double, double, int, const int*,
+                                           hipStream_t);
+template bool launch_level_local_mr<double>(int, const FineBlocks&, const LevelOp<double>&, int, const double*,
+                                            const double*, double*, double*, double*, double, double, int, const int*,
+                                            hipStream_t);
+
+// <p_k, q_k> per column k of n x NR interleaved vectors in a fixed partition: thread t of a block always handles
+// column t % NR (256 % NR == 0) of 256-row chunks (coalesced), the lanes of one column are combined by a
+// butterfly, the four waves in order.  partials[blk * NR + k]; returns the number of blocks.
+template <int NR>
+__global__ __launch_bounds__(256) void k_pcg_dot_mr(int n, const double* __restrict__ p, const double* __restrict__ q,
+                                                    double* partials, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double sh[4][NR];
+  double acc = 0;
+  const int64_t tot = (int64_t)n * NR;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * NR; base < tot; base += (int64_t)gridDim.x * 256 * NR)
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      const int64_t o = base + threadIdx.x + 256 * m;
+      if (o < tot) acc += p[o] * q[o];
+    }
+#pragma unroll
+  for (int off = 32; off >= NR; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  const int lane = threadIdx.x & 63;
+  if (lane < NR) sh[threadIdx.x >> 6][lane] = acc;
+  __syncthreads();
+  if (threadIdx.x < NR) {
+    const int kk = threadIdx.x;
+    partials[(int64_t)blockIdx.x * NR + kk] = (sh[0][kk] + sh[1][kk]) + (sh[2][kk] + sh[3][kk]);
+  }
+}
+int launch_pcg_dot_mr(int n, int nr, const double* p, const double* q, double* partials, const int* skip,
+                      hipStream_t s) {
+  int g = (n + 255) / 256;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  switch (nr) {
+    case 2: hipLaunchKernelGGL(k_pcg_dot_mr<2>, dim3(g), dim3(256), 0, s, n, p, q, partials, skip); break;
+    case 4: hipLaunchKernelGGL(k_pcg_dot_mr<4>, dim3(g), dim3(256), 0, s, n, p, q, partials, skip); break;
+    case 8: hipLaunchKernelGGL(k_pcg_dot_mr<8>, dim3(g), dim3(256), 0, s, n, p, q, partials, skip); break;
+    case 16: hipLaunchKernelGGL(k_pcg_dot_mr<16>, dim3(g), dim3(256), 0, s, n, p, q, partials, skip); break;
+    default: throw std::runtime_error("unsupported nrhs block");
+  }
+  check_launch("k_pcg_dot_mr");
+  return g;
+}
+
 
 // Block-row variant of the fused kernel for the agglomerated levels, one right-hand side.  One wave per box K,
 // L = floor(64 / B) lanes per row: lane (q, s) owns the columns p = s, s + L, ... of row (K, q) (w = nb*B values,
@@ -2182,6 +2491,22 @@ void launch_pcg_alpha(int nr, PcgState* st, const double* partials, int npart, h
 }
 
 // x += alpha p; r -= alpha q; partial ||r||^2; V-cycle entry b0 = (T) r, d0 = dinv0 b0 / theta0
+// Block lb covers rows [256 lb, 256 lb + 256) of the n x NR interleaved vectors; thread t handles the
+// elements 256 NR lb + t + 256 m (m < NR), all of column k = t % NR (256 % NR == 0): consecutive threads touch
+// consecutive elements.  Column sums: butterfly over the lanes of one column, then the four waves in order.
+template <int NR>
+__device__ inline void column_partials(double acc, double* sh, double* out) {
+#pragma unroll
+  for (int off = 32; off >= NR; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  const int lane = threadIdx.x & 63;
+  if (lane < NR) sh[(threadIdx.x >> 6) * NR + lane] = acc;
+  __syncthreads();
+  if (threadIdx.x < NR) {
+    const int k = threadIdx.x;
+    out[k] = (sh[k] + sh[NR + k]) + (sh[2 * NR + k] + sh[3 * NR + k]);
+  }
+}
+
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_pcg_xr(int n, PcgState* st, double* x, double* r, const double* __restrict__ p,
                                                 const double* __restrict__ q, double* partials, T* b0,
@@ -2190,38 +2515,29 @@ __global__ __launch_bounds__(256) void k_pcg_xr(int n, PcgState* st, double* x, 
   if (st->all_done) return;
   const int lb = xcd_block(nlog);
   if (lb < 0) return;
-  double al[NR], acc[NR];
+  const int k = threadIdx.x % NR;
+  const double al = st->alpha[k];
+  const int64_t tot = (int64_t)n * NR;
+  const int64_t base = (int64_t)lb * 256 * NR;
+  double acc = 0;
 #pragma unroll
-  for (int k = 0; k < NR; ++k) { al[k] = st->alpha[k]; acc[k] = 0; }
-  const int i = lb * 256 + threadIdx.x;
-  if (i < n) {
-    const T di = d0 ? dinv0[i] : (T)0;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const int64_t o = (int64_t)i * NR + k;
-      x[o] += al[k] * p[o];
-      const double rv = r[o] - al[k] * q[o];
+  for (int m = 0; m < NR; ++m) {
+    const int64_t o = base + threadIdx.x + 256 * m;
+    if (o < tot) {
+      x[o] += al * p[o];
+      const double rv = r[o] - al * q[o];
       r[o] = rv;
-      acc[k] = rv * rv;
+      acc += rv * rv;
       if (b0) {
         const T bv = (T)rv;
         b0[o] = bv;
-        if (d0) d0[o] = di * bv * inv_theta0;
+        if (d0) d0[o] = dinv0[o / NR] * bv * inv_theta0;
       } else if (d0) {
-        d0[o] = di * (T)rv * inv_theta0;
+        d0[o] = dinv0[o / NR] * (T)rv * inv_theta0;
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    double v = wave_sum(acc[k], 64);
-    if ((threadIdx.x & 63) == 0) sh[(threadIdx.x >> 6) * NR + k] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < NR) {
-    const int k = threadIdx.x;
-    partials[(int64_t)lb * NR + k] = (sh[k] + sh[NR + k]) + (sh[2 * NR + k] + sh[3 * NR + k]);
-  }
+  column_partials<NR>(acc, sh, partials + (int64_t)lb * NR);
 }
 template <typename T>
 void launch_pcg_xr(int n, int nr, PcgState* st, const double* partials_pq, int npart, double* x, double* r,
@@ -2273,39 +2589,29 @@ template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_pcg_z(int n, PcgState* st, const T* __restrict__ x0, const T* __restrict__ dp,
                                                double* z, const double* __restrict__ r, const double* __restrict__ q,
                                                double* partials, int nlog) {
-  __shared__ double sh[4 * 2 * NR];
+  __shared__ double sh[4 * NR];
   if (st->all_done) return;
   const int lb = xcd_block(nlog);
   if (lb < 0) return;
-  double a1[NR], a2[NR];
-  const int i = lb * 256 + threadIdx.x;
+  const int64_t tot = (int64_t)n * NR;
+  const int64_t base = (int64_t)lb * 256 * NR;
+  double a1 = 0, a2 = 0;
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    a1[k] = 0;
-    a2[k] = 0;
-    if (i < n) {
-      const int64_t o = (int64_t)i * NR + k;
+  for (int m = 0; m < NR; ++m) {
+    const int64_t o = base + threadIdx.x + 256 * m;
+    if (o < tot) {
       T v = x0[o];
       if (dp) v += dp[o];
       const double zv = (double)v;
       z[o] = zv;
-      a1[k] = r[o] * zv;
-      a2[k] = q ? q[o] * zv : 0.0;
+      a1 += r[o] * zv;
+      if (q) a2 += q[o] * zv;
     }
   }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    double v1 = wave_sum(a1[k], 64), v2 = wave_sum(a2[k], 64);
-    if ((threadIdx.x & 63) == 0) {
-      sh[(threadIdx.x >> 6) * 2 * NR + k] = v1;
-      sh[(threadIdx.x >> 6) * 2 * NR + NR + k] = v2;
-    }
-  }
+  double* out = partials + (int64_t)lb * 2 * NR;
+  column_partials<NR>(a1, sh, out);
   __syncthreads();
-  if (threadIdx.x < 2 * NR) {
-    const int k = threadIdx.x;
-    partials[(int64_t)lb * 2 * NR + k] = (sh[k] + sh[2 * NR + k]) + (sh[4 * NR + k] + sh[6 * NR + k]);
-  }
+  column_partials<NR>(a2, sh, out + NR);
 }
 template <typename T>
 void launch_pcg_z(int n, int nr, PcgState* st, const T* x0, const T* dpend, double* z, const double* r,

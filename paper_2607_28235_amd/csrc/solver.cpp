@@ -132,6 +132,11 @@ LevelOp<T> level_op(Ctx& c, int l) {
   return op;
 }
 
+// Tuned multi-RHS kernel codes, per (level, nr, precision): G in 1..64 = lanes-per-row CSR/block-row kernel with
+// G lanes; kCodeSplit + G = column-split CSR kernel with G lanes; -1 - g = local-column kernel over local
+// geometry g.  Level -1 holds PCG's float64 q = A p (with its dot products).
+constexpr int kCodeSplit = 100;
+
 // Kernel that applies level l for nr right-hand sides in element size esz: the row-block kernel on the fine
 // level for one right-hand side, a block-row kernel on coarse levels whose block rows fit LDS, the
 // lanes-per-row kernel otherwise.
@@ -184,7 +189,25 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
     default: {
       if (nr > 1) {
         auto it = c.dv.tuned.find({l, nr * 2 + (sizeof(T) == 4 ? 1 : 0)});
-        if (it != c.dv.tuned.end()) op.lanes = it->second;
+        if (it != c.dv.tuned.end()) {
+          if (it->second < 0) {  // fine level: local-column multi-RHS kernel
+            const int g = -1 - it->second;
+            op.ptr = D.rowptr.p;
+            op.idx = D.col.p;
+            if (!launch_level_local_mr<T>(g, D.fb[kLocalFirst + g], op, nr, u, b, rho, x, dout, c1, c2, flags, skip,
+                                          s))
+              throw std::runtime_error("multi-RHS local-column kernel: unsupported block");
+            break;
+          }
+          if (it->second >= kCodeSplit) {  // fine level: column-split CSR kernel
+            op.ptr = D.rowptr.p;
+            op.idx = D.col.p;
+            if (!launch_level_split<T>(op, nr, it->second - kCodeSplit, u, b, rho, x, dout, c1, c2, flags, skip, s))
+              throw std::runtime_error("multi-RHS column-split kernel: unsupported shape");
+            break;
+          }
+          op.lanes = it->second;
+        }
       }
       launch_level<T>(op, nr, u, b, rho, x, dout, c1, c2, flags, skip, s);
     }
@@ -261,43 +284,102 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
   Device& dv = c.dv;
   const int L = c.an.nlevels() - 1;
   const int tag = nr * 2 + (sizeof(T) == 4 ? 1 : 0);
+  const int forced = c.an.opt.multi_rhs_kernel;  // -1 timed, 0 lanes, 1 / 2 local-column, 3 column-split
+  const int fl = F_RHO_STORE | F_X_ADD | F_D_OUT;
   for (int l = 0; l < L; ++l) {
     if (dv.tuned.count({l, tag})) continue;
     DevLevel& D = dv.lv[l];
     LevelOp<T> op = level_op<T>(c, l);
     float best = 1e30f;
-    int bestG = D.lanes;
+    int bestCode = D.lanes;
+    auto consider = [&](int code, float ms, bool ok, bool allowed) {
+      if (ok && allowed && ms < best) {
+        best = ms;
+        bestCode = code;
+      }
+    };
+    const bool fine = l == 0;
     for (int G = 1; G <= 64; G <<= 1) {
       op.lanes = G;
       const float ms = time_launches(s, 5, [&] {
-        launch_level<T>(op, nr, vbuf<T>(D.dA), vbuf<T>(D.b), vbuf<T>(D.rho), vbuf<T>(D.x), vbuf<T>(D.dB), 0.0, 0.0,
-                        F_RHO_STORE | F_X_ADD | F_D_OUT, nullptr, s);
+        launch_level<T>(op, nr, vbuf<T>(D.dA), vbuf<T>(D.b), vbuf<T>(D.rho), vbuf<T>(D.x), vbuf<T>(D.dB), 0.0, 0.0, fl,
+                        nullptr, s);
       });
-      if (ms < best) {
-        best = ms;
-        bestG = G;
-      }
+      consider(G, ms, true, !fine || forced <= 0);
     }
-    dv.tuned[{l, tag}] = bestG;
+    if (fine) {
+      LevelOp<T> opc = op;
+      opc.ptr = D.rowptr.p;
+      opc.idx = D.col.p;
+      for (int g = 0; g < 2; ++g) {
+        if (forced != -1 && forced != 1 + g) continue;
+        bool ok = true;
+        const float ms = time_launches(s, 5, [&] {
+          ok = launch_level_local_mr<T>(g, D.fb[kLocalFirst + g], opc, nr, vbuf<T>(D.dA), vbuf<T>(D.b), vbuf<T>(D.rho),
+                                        vbuf<T>(D.x), vbuf<T>(D.dB), 0.0, 0.0, fl, nullptr, s);
+        });
+        consider(-1 - g, ms, ok, true);
+      }
+      if (forced == -1 || forced == 3)
+        for (int G = 1; G <= 64; G <<= 1) {
+          bool ok = true;
+          const float ms = time_launches(s, 5, [&] {
+            ok = launch_level_split<T>(opc, nr, G, vbuf<T>(D.dA), vbuf<T>(D.b), vbuf<T>(D.rho), vbuf<T>(D.x),
+                                       vbuf<T>(D.dB), 0.0, 0.0, fl, nullptr, s);
+          });
+          consider(kCodeSplit + G, ms, ok, true);
+        }
+    }
+    dv.tuned[{l, tag}] = bestCode;
     R3MG_HIP_CHECK(hipMemsetAsync(D.x.p, 0, D.x.n, s));
   }
-  // PCG's float64 SpMV with partial dot products (at most 8 lanes: bounded number of partials)
+  // PCG's float64 q = A p and <p, q>: lanes kernel with fused partial dots (at most 8 lanes: bounded number of
+  // partials), or the local-column / column-split kernel followed by the per-column dot in a fixed partition
   if (!dv.tuned.count({-1, nr * 2})) {
     LevelOp<double> op = level_op<double>(c, 0);
+    DevLevel& D0 = dv.lv[0];
     float best = 1e30f;
-    int bestG = 1;
-    for (int G = 1; G <= 8; G <<= 1) {
-      op.lanes = G;
-      need_partials(dv, (int64_t)((c.an.n + 256 / G - 1) / (256 / G)) * nr);
+    int bestCode = 1;
+    if (forced <= 0)
+      for (int G = 1; G <= 8; G <<= 1) {
+        op.lanes = G;
+        need_partials(dv, (int64_t)((c.an.n + 256 / G - 1) / (256 / G)) * nr);
+        const float ms = time_launches(s, 5, [&] { launch_spmv_dot(op, nr, dv.pp.p, dv.pq.p, dv.partials.p, nullptr, s); });
+        if (ms < best) {
+          best = ms;
+          bestCode = G;
+        }
+      }
+    op.ptr = D0.rowptr.p;
+    op.idx = D0.col.p;
+    need_partials(dv, (int64_t)1024 * nr);
+    for (int g = 0; g < 2; ++g) {
+      if (forced != -1 && forced != 1 + g) continue;
+      bool ok = true;
       const float ms = time_launches(s, 5, [&] {
-        launch_spmv_dot(op, nr, dv.pp.p, dv.pq.p, dv.partials.p, nullptr, s);
+        ok = launch_level_local_mr<double>(g, D0.fb[kLocalFirst + g], op, nr, dv.pp.p, nullptr, dv.pq.p, nullptr,
+                                           nullptr, 0.0, 0.0, F_PLAIN, nullptr, s);
+        if (ok) launch_pcg_dot_mr((int)c.an.n, nr, dv.pp.p, dv.pq.p, dv.partials.p, nullptr, s);
       });
-      if (ms < best) {
+      if (ok && ms < best) {
         best = ms;
-        bestG = G;
+        bestCode = -1 - g;
       }
     }
-    dv.tuned[{-1, nr * 2}] = bestG;
+    if (forced == -1 || forced == 3)
+      for (int G = 1; G <= 64; G <<= 1) {
+        bool ok = true;
+        const float ms = time_launches(s, 5, [&] {
+          ok = launch_level_split<double>(op, nr, G, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN,
+                                          nullptr, s);
+          if (ok) launch_pcg_dot_mr((int)c.an.n, nr, dv.pp.p, dv.pq.p, dv.partials.p, nullptr, s);
+        });
+        if (ok && ms < best) {
+          best = ms;
+          bestCode = kCodeSplit + G;
+        }
+      }
+    dv.tuned[{-1, nr * 2}] = bestCode;
   }
   R3MG_HIP_CHECK(hipStreamSynchronize(s));
 }
@@ -807,9 +889,24 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
     np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
   } else {
     auto it = dv.tuned.find({-1, NR * 2});
-    if (it != dv.tuned.end()) op64.lanes = it->second;
-    need_partials(dv, (int64_t)((n + 256 / op64.lanes - 1) / (256 / op64.lanes)) * NR);
-    np = launch_spmv_dot(op64, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+    if (it != dv.tuned.end() && (it->second < 0 || it->second >= kCodeSplit)) {  // then the per-column dot
+      op64.ptr = D0.rowptr.p;
+      op64.idx = D0.col.p;
+      bool ok;
+      if (it->second < 0)
+        ok = launch_level_local_mr<double>(-1 - it->second, D0.fb[kLocalFirst - 1 - it->second], op64, NR, dv.pp.p,
+                                           nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
+      else
+        ok = launch_level_split<double>(op64, NR, it->second - kCodeSplit, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr,
+                                        0.0, 0.0, F_PLAIN, skip, s);
+      if (!ok) throw std::runtime_error("multi-RHS fine-level kernel: unsupported shape");
+      need_partials(dv, (int64_t)1024 * NR);
+      np = launch_pcg_dot_mr(n, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+    } else {
+      if (it != dv.tuned.end()) op64.lanes = it->second;
+      need_partials(dv, (int64_t)((n + 256 / op64.lanes - 1) / (256 / op64.lanes)) * NR);
+      np = launch_spmv_dot(op64, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+    }
   }
   const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
   const T* dinv0;

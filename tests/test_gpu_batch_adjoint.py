@@ -39,13 +39,17 @@ def small3d_q3():
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
-def test_sixteen_rhs_block_pcg(small3d_q3, fp32):
-    """16 right-hand sides in lockstep (autotuned SpMM tiles) match the oracle per column."""
+@pytest.mark.parametrize("kernel", [-1, 0, 1, 2, 3])
+def test_sixteen_rhs_block_pcg(small3d_q3, fp32, kernel):
+    """16 right-hand sides in lockstep match the oracle per column, with the fine-level multi-RHS kernel chosen by
+    timing (-1) or forced: lanes-per-row CSR (0), local-column blocks with 1-byte (1) or 2-byte (2) positions,
+    CSR with the columns split over lanes (3)."""
     import paper_2607_28235_amd as P
     w = small3d_q3
     prob = w.problem
-    _case(f"16-rhs block pcg fp32={fp32} n={prob.n}")
-    o = P.Options(dim=3, coarse_degree=2, leaf_size=256, max_coarse_dofs=600, vcycle_fp32=fp32)
+    _case(f"16-rhs block pcg fp32={fp32} kernel={kernel} n={prob.n}")
+    o = P.Options(dim=3, coarse_degree=2, leaf_size=256, max_coarse_dofs=600, vcycle_fp32=fp32,
+                  multi_rhs_kernel=kernel)
     h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o)
     ho = O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=2, leaf_size=256, max_coarse_dofs=600)
     X = torch.zeros(16, prob.n, dtype=torch.float64, device="cuda")

@@ -179,14 +179,19 @@ def test_pcg_fp32_vcycle(name, request):
     assert _rel(xs, x_tight) < 1e-8
 
 
-def test_multi_rhs_matches_single(small2d):
+@pytest.mark.parametrize("kernel", [-1, 0, 1, 2, 3])
+def test_multi_rhs_matches_single(small2d, kernel):
     c = small2d
-    _case("multi-rhs 3 columns small2d")
+    _case(f"multi-rhs 3 columns small2d kernel={kernel}")
+    P = _P()
+    import dataclasses
+    h = c.h if kernel == -1 else P.Hierarchy(c.prob.coords, c.prob.row_ptr, c.prob.col, c.prob.val,
+                                             dataclasses.replace(c.opts, multi_rhs_kernel=kernel))
     g = np.random.default_rng(5)
     B = np.stack([c.b, g.standard_normal(c.prob.n), np.zeros(c.prob.n)])
     B[1, c.ho.constrained] = 0.0
     X = torch.zeros(3, c.prob.n, dtype=torch.float64, device="cuda")
-    iters, relres, ok = c.h.pcg(_t(B), X, rtol=1e-10, maxit=200)
+    iters, relres, ok = h.pcg(_t(B), X, rtol=1e-10, maxit=200)
     assert ok and iters[2] == 0
     for j in range(2):
         x1 = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
