@@ -129,6 +129,14 @@ r3mg_status r3mg_level_apply(r3mg_handle h, int level, const double* x_dev, doub
 r3mg_status r3mg_pcg_solve(r3mg_handle h, const double* b_dev, double* x_dev, int nrhs, double rtol, int maxit,
                            void* stream, int* iters, double* relres);
 
+/* r3mg_pcg_solve with the stop rule of the paper's experiments (Section 6: an absolute residual norm below a
+ * threshold or a given reduction): each column stops once ||r_k||_2 <= max(rtol ||r_0||_2, atol).  cond (host
+ * array of nrhs, may be NULL) receives the condition estimate of the preconditioned operator from the CG
+ * coefficients (largest over smallest eigenvalue of the Lanczos tridiagonal of the iterations taken; the
+ * "Cond." column of the paper's tables); 1 when no iteration was taken.  Errors as r3mg_pcg_solve. */
+r3mg_status r3mg_pcg_solve_ex(r3mg_handle h, const double* b_dev, double* x_dev, int nrhs, double rtol, double atol,
+                              int maxit, void* stream, int* iters, double* relres, double* cond);
+
 /* Several independent problems (each with its own handle, one right-hand side each) solved by PCG in one
  * launch sequence: the iterations of all problems are captured into one hipGraph and replayed together.
  * b[k], x[k] are device vectors of handle k.  iters/relres: host arrays of `count` (may be NULL). */

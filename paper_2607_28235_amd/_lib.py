@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID", -2: "NOT_UNISOLVENT"
 
 EXPORTED = [
     "r3mg_default_options", "r3mg_analyze", "r3mg_factor", "r3mg_setup", "r3mg_update_values", "r3mg_vcycle",
-    "r3mg_level_apply", "r3mg_pcg_solve", "r3mg_pcg_solve_group", "r3mg_info", "r3mg_export_partition",
+    "r3mg_level_apply", "r3mg_pcg_solve", "r3mg_pcg_solve_ex", "r3mg_pcg_solve_group", "r3mg_info", "r3mg_export_partition",
     "r3mg_export_P", "r3mg_export_level", "r3mg_time_smoother_kernel", "r3mg_cell_grad", "r3mg_assembler_create",
     "r3mg_assemble", "r3mg_assembler_free", "r3mg_rtree", "r3mg_free", "r3mg_status_string", "r3mg_last_error",
 ]
@@ -93,6 +93,7 @@ def lib():
     L.r3mg_vcycle.argtypes = [vp, vp, vp, i32, vp]
     L.r3mg_level_apply.argtypes = [vp, i32, vp, vp, vp]
     L.r3mg_pcg_solve.argtypes = [vp, vp, vp, i32, dbl, i32, vp, vp, vp]
+    L.r3mg_pcg_solve_ex.argtypes = [vp, vp, vp, i32, dbl, dbl, i32, vp, vp, vp, vp]
     L.r3mg_pcg_solve_group.argtypes = [i32, vp, vp, vp, dbl, i32, vp, vp, vp]
     L.r3mg_info.argtypes = [vp, vp, P(i32)]
     L.r3mg_export_partition.argtypes = [vp, i32, vp, vp]
@@ -204,15 +205,18 @@ class Hierarchy:
     def level_apply(self, level: int, x, y, stream=None):
         _check(lib().r3mg_level_apply(self._h, level, _dev(x), _dev(y), _stream(stream)), "r3mg_level_apply")
 
-    def pcg(self, b, x, rtol: float = 1e-10, maxit: int = 500, stream=None, raise_not_converged: bool = False):
-        """Solve A x = b in place (x holds the initial guess); b, x of shape (n,) or (nrhs, n)."""
+    def pcg(self, b, x, rtol: float = 1e-10, maxit: int = 500, stream=None, raise_not_converged: bool = False,
+            atol: float = 0.0, return_cond: bool = False):
+        """Solve A x = b in place (x holds the initial guess); b, x of shape (n,) or (nrhs, n).  Each column stops
+        at ||r|| <= max(rtol ||r0||, atol).  Returns (iters, relres, converged[, condition estimates])."""
         nrhs = 1 if b.dim() == 1 else b.shape[0]
         iters = np.zeros(nrhs, dtype=np.int32)
         relres = np.zeros(nrhs, dtype=np.float64)
-        st = lib().r3mg_pcg_solve(self._h, _dev(b), _dev(x), nrhs, rtol, maxit, _stream(stream), _ptr(iters),
-                                  _ptr(relres))
-        _check(st, "r3mg_pcg_solve", allow_not_converged=not raise_not_converged)
-        return iters, relres, st == OK
+        cond = np.zeros(nrhs, dtype=np.float64)
+        st = lib().r3mg_pcg_solve_ex(self._h, _dev(b), _dev(x), nrhs, rtol, atol, maxit, _stream(stream),
+                                     _ptr(iters), _ptr(relres), _ptr(cond) if return_cond else None)
+        _check(st, "r3mg_pcg_solve_ex", allow_not_converged=not raise_not_converged)
+        return (iters, relres, st == OK, cond) if return_cond else (iters, relres, st == OK)
 
     def cell_grad(self, cells_dev, Ke_dev, ke_stride: int, u, lam, g, stream=None):
         ncells, nloc = cells_dev.shape

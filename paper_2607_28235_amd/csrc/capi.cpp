@@ -161,11 +161,16 @@ r3mg_status r3mg_level_apply(r3mg_handle h, int level, const double* x_dev, doub
 
 r3mg_status r3mg_pcg_solve(r3mg_handle h, const double* b_dev, double* x_dev, int nrhs, double rtol, int maxit,
                            void* stream, int* iters, double* relres) {
+  return r3mg_pcg_solve_ex(h, b_dev, x_dev, nrhs, rtol, 0.0, maxit, stream, iters, relres, nullptr);
+}
+
+r3mg_status r3mg_pcg_solve_ex(r3mg_handle h, const double* b_dev, double* x_dev, int nrhs, double rtol, double atol,
+                              int maxit, void* stream, int* iters, double* relres, double* cond) {
   return guard([&] {
     require_factored(h);
-    if (!b_dev || !x_dev || nrhs < 1 || !(rtol >= 0.0) || maxit < 0)
+    if (!b_dev || !x_dev || nrhs < 1 || !(rtol >= 0.0) || !(atol >= 0.0) || maxit < 0)
       throw Error{R3MG_ERR_INVALID, "bad pcg arguments"};
-    return pcg_solve(h->impl, b_dev, x_dev, nrhs, rtol, maxit, S(stream), iters, relres);
+    return pcg_solve(h->impl, b_dev, x_dev, nrhs, rtol, atol, maxit, S(stream), cond, iters, relres);
   });
 }
 

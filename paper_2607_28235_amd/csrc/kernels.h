@@ -24,6 +24,10 @@ struct PcgState {
   int iters[kMaxNR];
   int done[kMaxNR];
   double gamma[kMaxNR], alpha[kMaxNR], beta[kMaxNR], rr[kMaxNR], rr0[kMaxNR], tau2[kMaxNR];
+  // CG coefficients per iteration j < hist_rows (Lanczos condition estimate): alpha_j of column k at
+  // hist[2 j kMaxNR + k], beta_j at hist[(2 j + 1) kMaxNR + k]
+  double* hist;
+  int hist_rows, pad2;
 };
 
 // Level operator description for the fused kernel.
@@ -185,7 +189,8 @@ void launch_pcg_beta(int nr, PcgState* st, const double* partials, int npart, hi
 void launch_pcg_p(int n, int nr, PcgState* st, const double* z, double* p, hipStream_t s);
 // init: r = b - q; partial rr
 int launch_residual(int n, int nr, const double* b, const double* q, double* r, double* partials, hipStream_t s);
-void launch_pcg_init(int nr, PcgState* st, const double* partials, int npart, double rtol, int flexible,
+void launch_pcg_init(int nr, PcgState* st, const double* partials, int npart, double rtol, double atol, int flexible,
+                     double* hist, int hist_rows,
                      hipStream_t s);
 void launch_pcg_init_gamma(int n, int nr, PcgState* st, const double* partials, int npart, const double* z,
                            double* p, hipStream_t s);

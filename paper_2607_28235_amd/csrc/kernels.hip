@@ -2482,7 +2482,11 @@ __global__ __launch_bounds__(1024) void k_pcg_alpha(int nr, PcgState* st, const 
   if (st->all_done) return;
   for (int k = 0; k < nr; ++k) {
     const double pq = sum_partials(partials, npart, nr, k, sh);
-    if (threadIdx.x == 0) st->alpha[k] = st->done[k] ? 0.0 : st->gamma[k] / pq;
+    if (threadIdx.x == 0) {
+      st->alpha[k] = st->done[k] ? 0.0 : st->gamma[k] / pq;
+      const int j = st->iters[k];
+      if (!st->done[k] && st->hist && j < st->hist_rows) st->hist[(int64_t)2 * j * kMaxNR + k] = st->alpha[k];
+    }
   }
 }
 void launch_pcg_alpha(int nr, PcgState* st, const double* partials, int npart, hipStream_t s) {
@@ -2646,6 +2650,8 @@ __global__ __launch_bounds__(1024) void k_pcg_beta(int nr, PcgState* st, const d
       const double g = st->gamma[k];
       st->beta[k] = st->flexible ? (-st->alpha[k] * qz) / g : rz / g;
       st->gamma[k] = rz;
+      const int j = st->iters[k] - 1;  // the check of iteration j has counted it
+      if (st->hist && j >= 0 && j < st->hist_rows) st->hist[(int64_t)(2 * j + 1) * kMaxNR + k] = st->beta[k];
     }
   }
 }
@@ -2713,7 +2719,8 @@ int launch_residual(int n, int nr, const double* b, const double* q, double* r, 
 }
 
 __global__ __launch_bounds__(1024) void k_pcg_init(int nr, PcgState* st, const double* __restrict__ partials, int npart,
-                                                  double rtol, int nr_active, int flexible) {
+                                                  double rtol, double atol, int nr_active, int flexible, double* hist,
+                                                  int hist_rows) {
   __shared__ double sh[16];
   int all = 1;
   for (int k = 0; k < nr; ++k) {
@@ -2721,7 +2728,7 @@ __global__ __launch_bounds__(1024) void k_pcg_init(int nr, PcgState* st, const d
     if (threadIdx.x == 0) {
       st->rr0[k] = rr;
       st->rr[k] = rr;
-      st->tau2[k] = rtol * rtol * rr;
+      st->tau2[k] = fmax(rtol * rtol * rr, atol * atol);  // ||r|| <= max(rtol ||r0||, atol)
       st->iters[k] = 0;
       st->alpha[k] = 0;
       st->beta[k] = 0;
@@ -2733,11 +2740,14 @@ __global__ __launch_bounds__(1024) void k_pcg_init(int nr, PcgState* st, const d
     st->all_done = all;
     st->nr = nr;
     st->flexible = flexible;
+    st->hist = hist;
+    st->hist_rows = hist_rows;
   }
 }
-void launch_pcg_init(int nr, PcgState* st, const double* partials, int npart, double rtol, int flexible,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(1024), 0, s, nr, st, partials, npart, rtol, nr, flexible);
+void launch_pcg_init(int nr, PcgState* st, const double* partials, int npart, double rtol, double atol, int flexible,
+                     double* hist, int hist_rows, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(1024), 0, s, nr, st, partials, npart, rtol, atol, nr, flexible, hist,
+                     hist_rows);
   check_launch("k_pcg_init");
 }
 

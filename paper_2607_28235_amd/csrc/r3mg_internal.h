@@ -202,6 +202,8 @@ struct Device {
   DBuf<double> px, pr, pp, pq, pz, pb;
   DBuf<double> partials;  // reduction partials
   DBuf<char> state;       // PcgState
+  DBuf<double> hist;      // CG coefficients per iteration (PcgState::hist)
+  int hist_rows = 0;
   DBuf<int> flag;         // set-up error flag
   int64_t pcg_cap = 0;
   // graph cache: (nrhs) -> exec
@@ -232,7 +234,8 @@ void device_setup(HandleImpl& h, hipStream_t s);
 void update_values(HandleImpl& h, const double* vals_dev, hipStream_t s);
 void vcycle_api(HandleImpl& h, const double* r, double* z, int nrhs, hipStream_t s);
 void level_apply(HandleImpl& h, int level, const double* x, double* y, hipStream_t s);
-r3mg_status pcg_solve(HandleImpl& h, const double* b, double* x, int nrhs, double rtol, int maxit, hipStream_t s,
+r3mg_status pcg_solve(HandleImpl& h, const double* b, double* x, int nrhs, double rtol, double atol, int maxit,
+                      hipStream_t s, double* cond,
                       int* iters, double* relres);
 r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double* const* x, double rtol, int maxit,
                       hipStream_t s, int* iters, double* relres);

@@ -57,6 +57,54 @@ double sturm_max(const std::vector<double>& a, const std::vector<double>& b) {
   return hi;
 }
 
+// smallest eigenvalue of the symmetric tridiagonal (a, b) by Sturm bisection
+static double sturm_min(const std::vector<double>& a, const std::vector<double>& b) {
+  const int m = (int)a.size();
+  std::vector<double> off(m, 0.0);
+  for (int i = 0; i + 1 < m; ++i) {
+    off[i] += std::fabs(b[i]);
+    off[i + 1] += std::fabs(b[i]);
+  }
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = 0; i < m; ++i) {
+    lo = std::min(lo, a[i] - off[i]);
+    hi = std::max(hi, a[i] + off[i]);
+  }
+  auto count_below = [&](double x) {
+    int cnt = 0;
+    double q = a[0] - x;
+    if (q < 0) ++cnt;
+    for (int k = 1; k < m; ++k) {
+      if (q == 0.0) q = 1e-300;
+      q = a[k] - x - b[k - 1] * b[k - 1] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200; ++it) {
+    if (hi - lo <= 1e-15 * std::max(std::fabs(lo), std::fabs(hi))) break;
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= 1)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Condition estimate of the preconditioned operator from m CG steps (the Lanczos tridiagonal of the CG
+// coefficients): T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_j,j+1 = sqrt(beta_j)/alpha_j; lambda_max / lambda_min.
+static double cg_condition(const std::vector<double>& alpha, const std::vector<double>& beta) {
+  const int m = (int)alpha.size();
+  if (m == 0) return 1.0;
+  std::vector<double> a(m), b(m > 1 ? m - 1 : 0);
+  for (int j = 0; j < m; ++j) {
+    a[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+    if (j + 1 < m) b[j] = std::sqrt(beta[j]) / alpha[j];
+  }
+  return sturm_max(a, b) / sturm_min(a, b);
+}
+
 int lanes_for(double avg_row) {
   int g = 2;
   while (g < 64 && g * 4 < avg_row) g <<= 1;
@@ -927,8 +975,16 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
   launch_pcg_p(n, NR, st, dv.pz.p, dv.pp.p, s);
 }
 
+// room for the CG coefficients of maxit iterations (a reallocation invalidates the captured graphs)
+static void ensure_hist(Device& dv, int maxit) {
+  if (dv.hist_rows >= maxit) return;
+  dv.hist.alloc((size_t)2 * kMaxNR * maxit);
+  dv.hist_rows = maxit;
+  drop_graphs(dv);
+}
+
 template <typename T>
-static void pcg_start(Ctx& c, int NR, double rtol, bool flexible, hipStream_t s) {
+static void pcg_start(Ctx& c, int NR, double rtol, double atol, bool flexible, hipStream_t s) {
   Analysis& an = c.an;
   Device& dv = c.dv;
   const int L = an.nlevels() - 1;
@@ -941,7 +997,7 @@ static void pcg_start(Ctx& c, int NR, double rtol, bool flexible, hipStream_t s)
   // r = b - A x0
   apply_level<double>(c, 0, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
   int np = launch_residual(n, NR, dv.pb.p, dv.pq.p, dv.pr.p, dv.partials.p, s);
-  launch_pcg_init(NR, st, dv.partials.p, np, rtol, flexible ? 1 : 0, s);
+  launch_pcg_init(NR, st, dv.partials.p, np, rtol, atol, flexible ? 1 : 0, dv.hist.p, dv.hist_rows, s);
   // z = B r; p = z; gamma = <r, z>
   const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
   const T* dinv0;
@@ -997,8 +1053,8 @@ static hipGraphExec_t iteration_graph(Ctx& c, int NR, bool flexible) {
 }
 
 template <typename T>
-static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, int nb, double rtol, int maxit,
-                             hipStream_t s, int* iters, double* relres) {
+static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, int nb, double rtol, double atol,
+                             int maxit, hipStream_t s, int* iters, double* relres, double* cond) {
   Analysis& an = *h.an;
   Device& dv = *h.dev;
   Ctx c{an, dv, sizeof(T) == 4};
@@ -1006,13 +1062,14 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
   while (NR < nb) NR <<= 1;
   ensure_level_vectors(c, NR);
   ensure_pcg_vectors(c, NR);
+  ensure_hist(dv, maxit);
   autotune_spmm<T>(c, NR, s);
   const int n = (int)an.n;
   const bool flexible = sizeof(T) == 4;
   launch_gather_cols(n, NR, nb, dv.perm.p, b + (int64_t)c0 * n, n, dv.pb.p, s);
   launch_gather_cols(n, NR, nb, dv.perm.p, x + (int64_t)c0 * n, n, dv.px.p, s);
   int restarts = 0;
-  pcg_start<T>(c, NR, rtol, flexible, s);
+  pcg_start<T>(c, NR, rtol, atol, flexible, s);
   hipGraphExec_t ex = nullptr;
   if (an.opt.use_graph) ex = iteration_graph<T>(c, NR, flexible);
   int k = 0;
@@ -1064,7 +1121,7 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
     // restart from the true residual for every column (converged ones stay converged: their r is small)
     ++restarts;
     std::vector<int> iters_keep(st.iters, st.iters + kMaxNR);
-    pcg_start<T>(c, NR, 0.0, flexible, s);  // tau2 restored below
+    pcg_start<T>(c, NR, 0.0, 0.0, flexible, s);  // tau2 restored below
     PcgState st2 = read_state(dv, s);
     for (int j = 0; j < NR; ++j) {
       st2.tau2[j] = st.tau2[j];
@@ -1088,16 +1145,31 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
     if (relres) relres[c0 + j] = st.rr0[j] > 0 ? std::sqrt(st.rr[j] / st.rr0[j]) : 0.0;
     conv &= st.done[j] != 0;
   }
+  if (cond) {
+    int mmax = 0;
+    for (int j = 0; j < nb; ++j) mmax = std::max(mmax, std::min(st.iters[j], dv.hist_rows));
+    std::vector<double> hh((size_t)2 * kMaxNR * std::max(1, mmax));
+    if (mmax > 0)
+      R3MG_HIP_CHECK(hipMemcpy(hh.data(), dv.hist.p, (size_t)2 * kMaxNR * mmax * sizeof(double), hipMemcpyDeviceToHost));
+    for (int j = 0; j < nb; ++j) {
+      const int m = std::min(st.iters[j], dv.hist_rows);
+      std::vector<double> al(m), be(m > 0 ? m - 1 : 0);
+      for (int i = 0; i < m; ++i) al[i] = hh[(size_t)2 * i * kMaxNR + j];
+      for (int i = 0; i + 1 < m; ++i) be[i] = hh[(size_t)(2 * i + 1) * kMaxNR + j];
+      cond[c0 + j] = cg_condition(al, be);
+    }
+  }
   return conv ? R3MG_OK : R3MG_NOT_CONVERGED;
 }
 
-r3mg_status pcg_solve(HandleImpl& h, const double* b, double* x, int nrhs, double rtol, int maxit, hipStream_t s,
-                      int* iters, double* relres) {
+r3mg_status pcg_solve(HandleImpl& h, const double* b, double* x, int nrhs, double rtol, double atol, int maxit,
+                      hipStream_t s, double* cond, int* iters, double* relres) {
   r3mg_status res = R3MG_OK;
   for (int c0 = 0; c0 < nrhs; c0 += kMaxNR) {
     const int nb = std::min(kMaxNR, nrhs - c0);
-    r3mg_status r = h.an->opt.vcycle_fp32 ? pcg_block<float>(h, b, x, c0, nb, rtol, maxit, s, iters, relres)
-                                          : pcg_block<double>(h, b, x, c0, nb, rtol, maxit, s, iters, relres);
+    r3mg_status r = h.an->opt.vcycle_fp32
+                        ? pcg_block<float>(h, b, x, c0, nb, rtol, atol, maxit, s, iters, relres, cond)
+                        : pcg_block<double>(h, b, x, c0, nb, rtol, atol, maxit, s, iters, relres, cond);
     if (r != R3MG_OK) res = r;
   }
   return res;
@@ -1128,13 +1200,14 @@ r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double
       Ctx c{*h.an, *h.dev, h.an->opt.vcycle_fp32 != 0};
       ensure_level_vectors(c, 1);
       ensure_pcg_vectors(c, 1);
+      ensure_hist(*h.dev, maxit);
       const int n = (int)h.an->n;
       launch_gather_cols(n, 1, 1, h.dev->perm.p, b[k], n, h.dev->pb.p, s);
       launch_gather_cols(n, 1, 1, h.dev->perm.p, x[k], n, h.dev->px.p, s);
       if (c.fp32)
-        pcg_start<float>(c, 1, rtol, true, s);
+        pcg_start<float>(c, 1, rtol, 0.0, true, s);
       else
-        pcg_start<double>(c, 1, rtol, false, s);
+        pcg_start<double>(c, 1, rtol, 0.0, false, s);
     }
     R3MG_HIP_CHECK(hipStreamSynchronize(s));
     // capture one iteration of every problem, each on its own branch

@@ -389,3 +389,68 @@ def test_fine_kernel_long_row(dense_row, shape):
     assert ok and abs(int(iters[0]) - ko) <= 1, (iters, ko)
     assert _rel(x.cpu().numpy(), xo) < 1e-9
     h.close()
+
+
+def test_condition_estimate_and_absolute_stop(small2d):
+    """The condition estimate from the CG coefficients (the paper's "Cond." column) and the absolute stop rule
+    max(rtol ||r0||, atol) agree with the oracle's PCG on the same hierarchy."""
+    c = small2d
+    _case("condition estimate and absolute stop small2d")
+    x = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok, cond = c.h.pcg(_t(c.b), x, rtol=1e-10, maxit=200, return_cond=True)
+    xo, ko, _, _, co = O.pcg(c.ho, c.b, rtol=1e-10)
+    assert ok and int(iters[0]) == ko
+    assert abs(cond[0] - co) <= 1e-6 * co, (cond[0], co)
+    atol = 1e-4 * float(np.linalg.norm(c.b))
+    x = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok, cond = c.h.pcg(_t(c.b), x, rtol=1e-14, atol=atol, maxit=200, return_cond=True)
+    xo, ko, _, hist, co = O.pcg(c.ho, c.b, rtol=1e-14, atol=atol)
+    assert ok and int(iters[0]) == ko and hist[-1] <= atol
+    r = c.b - c.prob.scipy() @ x.cpu().numpy()
+    assert np.linalg.norm(r) <= 1.001 * atol
+    assert abs(cond[0] - co) <= 1e-6 * co
+
+
+@pytest.fixture(scope="module")
+def q1_sweep():
+    """Structured Q1 unit square after 6 and 7 refinements (4,225 and 16,641 DoFs, the paper's Table of fixed
+    H/h), point agglomeration with leaf size M = 8 (the paper's m = 2 leaves corner boxes with fewer free points
+    than Q^1 needs under this build's unisolvence test), leaf level skipped, two levels, V(2,2) Chebyshev-3, stop
+    at a 1e-6 reduction or 1e-9 absolute (Section 6)."""
+    _need_gpu()
+    P = _P()
+    out = {}
+    for ref in (6, 7):
+        prob = F.structured_qp(2, 2 ** ref, 1, cfg=1)
+        b = F.nodal_rhs(prob, F.rng(1, F.PURPOSE_RHS, ref).uniform(-1, 1, prob.n), cfg=1)
+        for pc in (0, 1):
+            _case(f"paper sweep ref={ref} p'={pc} n={prob.n}")
+            o = P.Options(dim=2, coarse_degree=pc, leaf_size=8, max_levels=2, skip_leaf_level=1)
+            h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o)
+            x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+            it, _, ok, cond = h.pcg(_t(b), x, rtol=1e-6, atol=1e-9, maxit=300, return_cond=True)
+            ho = O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=pc, leaf_size=8, max_levels=2,
+                                   skip_leaf_level=True)
+            xo, ko, conv, _, co = O.pcg(ho, b, rtol=1e-6, atol=1e-9, maxit=300)
+            out[(ref, pc)] = (int(it[0]), float(cond[0]), ko, co, ok and conv, prob.n)
+            h.close()
+    return out
+
+
+def test_paper_replication_sweep_matches_oracle(q1_sweep):
+    for key, (it, cond, ko, co, ok, n) in q1_sweep.items():
+        assert ok, key
+        assert abs(it - ko) <= 1, (key, it, ko)
+        if it == ko:
+            assert abs(cond - co) <= 1e-6 * co, (key, cond, co)
+
+
+def test_paper_replication_sweep_trends(q1_sweep):
+    """Section 6.1 trends: the Q^1 coarse space needs fewer iterations and has a smaller condition estimate than
+    the Q^0 (Nicolaides) one, and its iteration counts stay flat under refinement at a fixed number of levels
+    (the paper's exact counts come from a different R-tree and are not reproduced)."""
+    s = q1_sweep
+    for ref in (6, 7):
+        assert s[(ref, 1)][0] < s[(ref, 0)][0], (ref, s[(ref, 1)], s[(ref, 0)])
+        assert s[(ref, 1)][1] < s[(ref, 0)][1]
+    assert abs(s[(7, 1)][0] - s[(6, 1)][0]) <= 1
