@@ -432,31 +432,39 @@ def bench_adjoint(args):
         "fd_cells": int(len(fd_err)), "fd_max_rel_err": float(max(fd_err)) if fd_err else None}), flush=True)
 
 
-# Section 6.1 tables on the structured Q1 square (point agglomeration, p' = 0 and 1): (refinements, levels, the
-# paper's iterations and condition estimates for p' = 0 and p' = 1), for context only -- its R-tree (Boost's
-# R*-tree, m = 2) differs from this build's bisection tree (leaf size 8, the leaf level skipped).
-PAPER_Q1_FIXED = [(6, 2, 12, 3.84, 4, 1.04), (7, 2, 15, 4.30, 4, 1.04), (8, 2, 16, 4.48, 4, 1.04)]
-PAPER_Q1_REFINED = [(6, 3, 12, 5.11, 5, 1.07), (7, 4, 17, 9.70, 5, 1.19), (8, 5, 24, 18.52, 7, 1.54),
-                    (9, 6, 35, 36.37, 10, 2.16), (10, 7, 49, 71.66, 14, 3.73)]
+# Section 6.1 tables on the structured Q1 square (p' = 0 and 1), for context only -- the paper's R-tree (Boost's
+# R*-tree, m = 2) differs from this build's bisection tree: per (agglomeration, table), rows of (refinements,
+# levels, the paper's iterations and condition estimates for p' = 0, then for p' = 1).
+PAPER_Q1 = {
+    ("point", "fixed_levels"): [(6, 2, 12, 3.84, 4, 1.04), (7, 2, 15, 4.30, 4, 1.04), (8, 2, 16, 4.48, 4, 1.04)],
+    ("cell", "fixed_levels"): [(6, 2, 11, 3.63, 4, 1.03), (7, 2, 14, 3.98, 4, 1.02), (8, 2, 15, 4.08, 3, 1.01)],
+    ("point", "growing_levels"): [(6, 3, 12, 5.11, 5, 1.07), (7, 4, 17, 9.70, 5, 1.19), (8, 5, 24, 18.52, 7, 1.54),
+                                  (9, 6, 35, 36.37, 10, 2.16), (10, 7, 49, 71.66, 14, 3.73)],
+    ("cell", "growing_levels"): [(6, 2, 11, 3.63, 4, 1.03), (7, 3, 15, 6.85, 4, 1.02), (8, 4, 22, 13.25, 4, 1.04),
+                                 (9, 5, 30, 26.13, 6, 1.35), (10, 6, 42, 52.10, 8, 2.05)],
+}
 
 
 def bench_replicate(args):
     """Paper-replication mode: the structured Q1 square tables of Section 6.1 (fixed levels, then levels growing
-    with the refinement), PCG stopped at a 1e-6 reduction or 1e-9 absolute, V(2,2) Chebyshev-3."""
+    with the refinement) for point- and cell-based agglomeration, PCG stopped at a 1e-6 reduction or 1e-9
+    absolute, V(2,2) Chebyshev-3, the leaf level skipped; leaf size 8 points (point-based) or 4 cells
+    (cell-based, the paper's m_cells = 2)."""
     import torch
     import fixtures as F
     import paper_2607_28235_amd as P
     rows = []
-    for table, spec in (("fixed_levels", PAPER_Q1_FIXED), ("growing_levels", PAPER_Q1_REFINED)):
+    for (agg, table), spec in PAPER_Q1.items():
         for ref, lv, pit0, pcond0, pit1, pcond1 in spec:
             prob = F.structured_qp(2, 2 ** ref, 1, cfg=1)
             b = torch.from_numpy(F.nodal_rhs(prob, F.rng(1, F.PURPOSE_RHS, ref).uniform(-1, 1, prob.n), cfg=1)).cuda()
-            row = {"table": table, "ref": ref, "dofs": prob.n, "levels": lv,
+            row = {"agglomeration": agg, "table": table, "ref": ref, "dofs": prob.n, "levels": lv,
                    "paper": {"iters_p0": pit0, "cond_p0": pcond0, "iters_p1": pit1, "cond_p1": pcond1}}
             for pc in (0, 1):
-                o = P.Options(dim=2, coarse_degree=pc, leaf_size=8, max_levels=lv, max_coarse_dofs=1,
-                              skip_leaf_level=1, vcycle_fp32=0)
-                h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o)
+                o = P.Options(dim=2, coarse_degree=pc, leaf_size=8 if agg == "point" else 4, max_levels=lv,
+                              max_coarse_dofs=1, skip_leaf_level=1, vcycle_fp32=0)
+                h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o,
+                                cells=prob.cells if agg == "cell" else None)
                 info = h.info()
                 x = torch.zeros_like(b)
                 it, _, ok, cond = h.pcg(b, x, rtol=1e-6, atol=1e-9, maxit=500, return_cond=True)
@@ -466,15 +474,15 @@ def bench_replicate(args):
                                  "H_over_h": info[-1]["max_box_extent"] / hmax, "levels": len(info),
                                  "solve_ms": t * 1e3}
                 h.close()
-            log(f"{table} ref {ref} n={prob.n} lvls {lv}: p'=0 {row['p0']['iters']} it (cond {row['p0']['cond']:.2f}), "
-                f"p'=1 {row['p1']['iters']} it (cond {row['p1']['cond']:.2f}), H/h {row['p1']['H_over_h']:.2f}; "
-                f"paper {pit0}/{pit1}")
+            log(f"{agg} {table} ref {ref} n={prob.n} lvls {lv}: p'=0 {row['p0']['iters']} it (cond "
+                f"{row['p0']['cond']:.2f}), p'=1 {row['p1']['iters']} it (cond {row['p1']['cond']:.2f}), H/h "
+                f"{row['p1']['H_over_h']:.2f}; paper {pit0}/{pit1}")
             rows.append(row)
     print(json.dumps({"metric": "paper replication: PCG iterations and condition estimates, structured Q1 square",
                       "unit": "iterations", "n_gpus": 1, "data": "synthetic",
-                      "config": {"workload": "Section 6.1 structured Q1 square, point agglomeration, leaf 8, "
-                                             "skip leaf level, V(2,2) Chebyshev-3, stop 1e-6 reduction or 1e-9 "
-                                             "absolute"},
+                      "config": {"workload": "Section 6.1 structured Q1 square, point (leaf 8) and cell (leaf 4 "
+                                             "cells) agglomeration, skip leaf level, V(2,2) Chebyshev-3, stop 1e-6 "
+                                             "reduction or 1e-9 absolute"},
                       "rows": rows}), flush=True)
 
 

@@ -103,6 +103,16 @@ void r3mg_default_options(r3mg_options* opt);
 r3mg_status r3mg_analyze(const double* coords, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                          const double* vals, const r3mg_options* opt, r3mg_handle* out);
 
+/* r3mg_analyze with cell-based agglomeration (Section 4): the R-tree's leaves are the mesh cells (cells: host
+ * ncells x nloc support-point indices in the caller's numbering, row-major; ordered in the tree by the centres
+ * of their bounding boxes), each agglomerate's box is the bounding box of its cells' support points, and every
+ * support point is owned by the first level-1 agglomerate, in array order, holding one of its cells (the
+ * paper's unique assignment of shared support points).  leaf_size counts cells.  Errors as r3mg_analyze, and
+ * INVALID for a cell index out of range or a support point in no cell. */
+r3mg_status r3mg_analyze_cells(const double* coords, int64_t n, const int32_t* cells, int64_t ncells, int nloc,
+                               const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
+                               const r3mg_options* opt, r3mg_handle* out);
+
 /* Device numeric set-up of an analysed handle on `stream`: upload, Galerkin products A_{l+1} = P_l^T A_l P_l,
  * inverse diagonals, Lanczos estimates, dense coarsest Cholesky factorisation and inverse.  Synchronises. */
 r3mg_status r3mg_factor(r3mg_handle h, void* stream);

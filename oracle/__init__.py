@@ -24,7 +24,7 @@ Readings where the paper is silent are listed in the module docstrings (bisectio
 Boost R*-tree, GLL box nodes, Chebyshev interval parameters, Lanczos start vector, stop rule form).
 All arithmetic is float64.
 """
-from .rtree import bisection_rtree, select_levels, RTree
+from .rtree import bisection_rtree, cell_rtree, select_levels, RTree, CellTree
 from .basis import box_nodes_1d, box_basis_values
 from .hierarchy import Hierarchy, build_hierarchy, R3mgError
 from .smoother import lanczos_max_eig, sturm_max_eig, chebyshev_apply
@@ -32,7 +32,7 @@ from .solve import vcycle, pcg, pcg_batched
 from .adjoint import assemble_kappa, cell_gradient, loss_and_gradient
 
 __all__ = [
-    "bisection_rtree", "select_levels", "RTree", "box_nodes_1d", "box_basis_values", "Hierarchy",
+    "bisection_rtree", "cell_rtree", "CellTree", "select_levels", "RTree", "box_nodes_1d", "box_basis_values", "Hierarchy",
     "build_hierarchy", "R3mgError", "lanczos_max_eig", "sturm_max_eig", "chebyshev_apply", "vcycle",
     "pcg", "pcg_batched", "assemble_kappa", "cell_gradient", "loss_and_gradient",
 ]

@@ -34,7 +34,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from .basis import box_basis_values, box_node_points
-from .rtree import RTree, bisection_rtree, select_levels
+from .rtree import RTree, bisection_rtree, cell_rtree, select_levels
 from .smoother import lanczos_max_eig
 
 
@@ -163,7 +163,9 @@ def block_pattern(A: sp.csr_matrix, row_box: np.ndarray, nbox: int):
 def build_hierarchy(coords, A: sp.csr_matrix, *, coarse_degree: int, leaf_size: int, max_levels: int = 0,
                     max_coarse_dofs: int = 2000, skip_leaf_level: bool = False, cheb_degree: int = 3,
                     pre_steps: int = 2, post_steps: int = 2, lanczos_steps: int = 10,
-                    cheb_boost: float = 1.1, cheb_ratio: float = 30.0) -> Hierarchy:
+                    cheb_boost: float = 1.1, cheb_ratio: float = 30.0, cells=None) -> Hierarchy:
+    """Section 4 set-up.  cells (ncells x nloc support-point indices) selects cell-based agglomeration
+    (oracle.rtree.CellTree, leaf_size counting cells); point-based agglomeration otherwise."""
     coords = np.asarray(coords, dtype=np.float64)
     A = sp.csr_matrix(A, dtype=np.float64)
     n, d = coords.shape
@@ -172,7 +174,7 @@ def build_hierarchy(coords, A: sp.csr_matrix, *, coarse_degree: int, leaf_size: 
     if not (np.all(np.isfinite(coords)) and np.all(np.isfinite(A.data))):
         raise R3mgError("INVALID", "non-finite input")
     C = constrained_set(A)
-    tree = bisection_rtree(coords, leaf_size)
+    tree = bisection_rtree(coords, leaf_size) if cells is None else cell_rtree(coords, cells, leaf_size)
     depths = select_levels(tree, d, B, max_levels=max_levels, max_coarse_dofs=max_coarse_dofs,
                            skip_leaf_level=skip_leaf_level)
     levels: List[Level] = []

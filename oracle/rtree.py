@@ -121,3 +121,57 @@ def select_levels(tree: RTree, d: int, B: int, *, max_levels: int = 0, max_coars
             break
         depths.append(max(depths[-1] - d, 0))
     return depths
+
+
+@dataclasses.dataclass
+class CellTree:
+    """Cell-based agglomeration (Section 4): an R-tree whose leaves are the mesh cells.
+
+    The bisection bulk load above runs on one point per cell, the centre of the cell's bounding box (a reading:
+    the paper inserts the cell MBRs into Boost's R*-tree).  An agglomerate at depth k is a node of this tree; its
+    box is the bounding box of all support points of its cells.  Support points shared by several agglomerates
+    are assigned uniquely: the agglomerates are visited in array order and each takes the points of its cells
+    not yet taken, i.e. a point belongs to the smallest node index among the nodes holding one of its cells.
+    """
+    depth: int
+    cells: np.ndarray            # (ncells, nloc) support-point indices
+    n: int                       # number of support points
+    cell_tree: RTree             # the bisection tree over cell centres
+
+    def cell_node(self, k: int) -> np.ndarray:
+        """Node index at depth k of every cell."""
+        return self.cell_tree.owner(k)
+
+    def owner(self, k: int) -> np.ndarray:
+        """Node at depth k that owns each support point (first-come over the nodes in array order)."""
+        node = self.cell_node(k)
+        own = np.full(self.n, np.iinfo(np.int64).max, dtype=np.int64)
+        for j in range(self.cells.shape[1]):
+            np.minimum.at(own, self.cells[:, j], node)
+        if np.any(own == np.iinfo(np.int64).max):
+            raise ValueError("support point in no cell")
+        return own
+
+    def boxes(self, coords: np.ndarray, k: int):
+        """(lo, hi): bounding boxes of the depth-k nodes over all support points of their cells."""
+        node = self.cell_node(k)
+        nb = 1 << k
+        d = coords.shape[1]
+        lo = np.full((nb, d), np.inf)
+        hi = np.full((nb, d), -np.inf)
+        for j in range(self.cells.shape[1]):
+            x = coords[self.cells[:, j]]
+            for a in range(d):
+                np.minimum.at(lo[:, a], node, x[:, a])
+                np.maximum.at(hi[:, a], node, x[:, a])
+        return lo, hi
+
+
+def cell_rtree(coords: np.ndarray, cells: np.ndarray, leaf: int) -> CellTree:
+    """Cell-based R-tree with at most `leaf` cells per leaf."""
+    coords = np.asarray(coords, dtype=np.float64)
+    cells = np.asarray(cells, dtype=np.int64)
+    x = coords[cells]                                   # (ncells, nloc, d)
+    centres = 0.5 * (x.min(axis=1) + x.max(axis=1))
+    t = bisection_rtree(centres, leaf)
+    return CellTree(depth=t.depth, cells=cells, n=coords.shape[0], cell_tree=t)

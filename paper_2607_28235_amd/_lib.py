@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID", -2: "NOT_UNISOLVENT"
                 -4: "NOT_SPD", -5: "OOM", -6: "HIP"}
 
 EXPORTED = [
+    "r3mg_analyze_cells",
     "r3mg_default_options", "r3mg_analyze", "r3mg_factor", "r3mg_setup", "r3mg_update_values", "r3mg_vcycle",
     "r3mg_level_apply", "r3mg_pcg_solve", "r3mg_pcg_solve_ex", "r3mg_pcg_solve_group", "r3mg_info", "r3mg_export_partition",
     "r3mg_export_P", "r3mg_export_level", "r3mg_time_smoother_kernel", "r3mg_cell_grad", "r3mg_assembler_create",
@@ -87,6 +88,7 @@ def lib():
     L.r3mg_default_options.argtypes = [P(_Options)]
     L.r3mg_default_options.restype = None
     L.r3mg_analyze.argtypes = [vp, i64, vp, vp, vp, P(_Options), P(vp)]
+    L.r3mg_analyze_cells.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp, P(_Options), P(vp)]
     L.r3mg_factor.argtypes = [vp, vp]
     L.r3mg_setup.argtypes = [vp, i64, vp, vp, vp, P(_Options), vp, P(vp)]
     L.r3mg_update_values.argtypes = [vp, vp, vp]
@@ -161,7 +163,8 @@ class Hierarchy:
     """Handle of an R3MG-C hierarchy.  analyze() is host-only; factor() builds the device hierarchy."""
 
     def __init__(self, coords: np.ndarray, row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray,
-                 options: Options, *, factor: bool = True, stream=None):
+                 options: Options, *, factor: bool = True, stream=None, cells: np.ndarray = None):
+        """cells (ncells x nloc support-point indices) selects cell-based agglomeration; point-based otherwise."""
         L = lib()
         self._coords = np.ascontiguousarray(coords, dtype=np.float64)
         self.n = self._coords.shape[0]
@@ -172,8 +175,13 @@ class Hierarchy:
         self.options = options
         h = C.c_void_p()
         o = options._c()
-        _check(L.r3mg_analyze(_ptr(self._coords), self.n, _ptr(rp), _ptr(cl), _ptr(vl), C.byref(o), C.byref(h)),
-               "r3mg_analyze")
+        if cells is None:
+            _check(L.r3mg_analyze(_ptr(self._coords), self.n, _ptr(rp), _ptr(cl), _ptr(vl), C.byref(o),
+                                  C.byref(h)), "r3mg_analyze")
+        else:
+            ce = np.ascontiguousarray(cells, dtype=np.int32)
+            _check(L.r3mg_analyze_cells(_ptr(self._coords), self.n, _ptr(ce), ce.shape[0], ce.shape[1], _ptr(rp),
+                                        _ptr(cl), _ptr(vl), C.byref(o), C.byref(h)), "r3mg_analyze_cells")
         self._h = h
         self.factored = False
         if factor:

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -121,7 +122,8 @@ void bisection_rtree(const double* x, int64_t n, int d, int leaf, int& depth, st
 }
 
 std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t* row_ptr,
-                                  const int32_t* col_idx, const double* vals, const r3mg_options& opt) {
+                                  const int32_t* col_idx, const double* vals, const r3mg_options& opt,
+                                  const int32_t* cells, int64_t ncells, int nloc) {
   auto an = std::make_unique<Analysis>();
   an->opt = opt;
   const int d = opt.dim;
@@ -166,9 +168,34 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
     for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
       if (col_idx[p] != i && vals[p] != 0.0) { cons_user[i] = 0; break; }
 
-  // R-tree and levels
-  std::vector<std::vector<int64_t>> offsets;
-  bisection_rtree(coords, n, d, opt.leaf_size, an->depth, an->order, offsets);
+  // R-tree and levels.  Point-based agglomeration (Section 4): the tree's leaves are the support points.
+  // Cell-based agglomeration (Section 4): the tree's leaves are the cells (ordered by the centres of their
+  // bounding boxes), a box is the bounding box of its cells' support points, and every support point belongs to
+  // the first level-1 agglomerate, in array order, that holds one of its cells.
+  std::vector<std::vector<int64_t>> offsets;  // per tree depth: point offsets of the nodes in the internal order
+  std::vector<int32_t> cag;                    // cell-based: level-1 agglomerate of every cell
+  std::vector<int32_t> corder;
+  std::vector<std::vector<int64_t>> coff;
+  an->cell_based = cells != nullptr;
+  if (!an->cell_based) {
+    bisection_rtree(coords, n, d, opt.leaf_size, an->depth, an->order, offsets);
+  } else {
+    if (ncells < 1 || nloc < 1 || ncells >= (int64_t(1) << 31)) throw err(R3MG_ERR_INVALID, "bad cell array");
+    std::vector<double> cen((size_t)ncells * d);
+    for (int64_t c = 0; c < ncells; ++c) {
+      double lo3[3] = {INFINITY, INFINITY, INFINITY}, hi3[3] = {-INFINITY, -INFINITY, -INFINITY};
+      for (int j = 0; j < nloc; ++j) {
+        const int32_t v = cells[c * nloc + j];
+        if (v < 0 || v >= n) throw err(R3MG_ERR_INVALID, "cell node index out of range");
+        for (int a = 0; a < d; ++a) {
+          lo3[a] = std::min(lo3[a], coords[(int64_t)v * d + a]);
+          hi3[a] = std::max(hi3[a], coords[(int64_t)v * d + a]);
+        }
+      }
+      for (int a = 0; a < d; ++a) cen[c * d + a] = 0.5 * (lo3[a] + hi3[a]);
+    }
+    bisection_rtree(cen.data(), ncells, d, opt.leaf_size, an->depth, corder, coff);
+  }
   {
     int depth = opt.skip_leaf_level ? std::max(an->depth - d, 0) : an->depth;
     an->depths.push_back(depth);
@@ -181,9 +208,49 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
       an->depths.push_back(std::max(an->depths.back() - d, 0));
     }
   }
-  for (auto& off : offsets)
-    for (size_t s = 0; s + 1 < off.size(); ++s)
-      if (off[s + 1] == off[s]) throw err(R3MG_ERR_NOT_UNISOLVENT, "empty R-tree node (leaf_size too small)");
+  if (an->cell_based) {
+    for (auto& off : coff)
+      for (size_t s = 0; s + 1 < off.size(); ++s)
+        if (off[s + 1] == off[s]) throw err(R3MG_ERR_NOT_UNISOLVENT, "empty R-tree node (leaf_size too small)");
+    // first-come ownership: agglomerates are visited in array order, so a point goes to the smallest agglomerate
+    // index among its cells
+    const int d1 = an->depths[0];
+    cag.assign(ncells, 0);
+    for (size_t k = 0; k + 1 < coff[d1].size(); ++k)
+      for (int64_t p = coff[d1][k]; p < coff[d1][k + 1]; ++p) cag[corder[p]] = (int32_t)k;
+    std::vector<int32_t> pown(n, INT32_MAX);
+    for (int64_t c = 0; c < ncells; ++c)
+      for (int j = 0; j < nloc; ++j) {
+        int32_t& o = pown[cells[c * nloc + j]];
+        o = std::min(o, cag[c]);
+      }
+    const int64_t nb1 = int64_t(1) << d1;
+    std::vector<int64_t> cnt(nb1 + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      if (pown[i] == INT32_MAX) throw err(R3MG_ERR_INVALID, "support point in no cell");
+      ++cnt[pown[i] + 1];
+    }
+    for (int64_t k = 0; k < nb1; ++k) cnt[k + 1] += cnt[k];
+    // internal order: by owner, then by caller index
+    an->order.assign(n, 0);
+    {
+      std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+      for (int64_t i = 0; i < n; ++i) an->order[pos[pown[i]]++] = (int32_t)i;
+    }
+    // point offsets of the nodes at every depth up to d1 (ancestors of the level-1 agglomerates)
+    offsets.assign(d1 + 1, {});
+    for (int k = 0; k <= d1; ++k) {
+      const int sh = d1 - k;
+      std::vector<int64_t>& off = offsets[k];
+      off.assign((int64_t(1) << k) + 1, 0);
+      for (int64_t b = 0; b < nb1; ++b) off[(b >> sh) + 1] += cnt[b + 1] - cnt[b];
+      for (size_t b = 0; b + 1 < off.size(); ++b) off[b + 1] += off[b];
+    }
+  } else {
+    for (auto& off : offsets)
+      for (size_t s = 0; s + 1 < off.size(); ++s)
+        if (off[s + 1] == off[s]) throw err(R3MG_ERR_NOT_UNISOLVENT, "empty R-tree node (leaf_size too small)");
+  }
   const int L = an->nlevels() - 1;
   an->lv.resize(L + 1);
   an->iperm.assign(n, 0);
@@ -201,13 +268,26 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
     H.n = H.nbox * B;
     H.lo.assign(H.nbox * d, INFINITY);
     H.hi.assign(H.nbox * d, -INFINITY);
+    if (an->cell_based) {  // bounding box of the node's cells
+      const int sh = an->depths[0] - H.depth;
+      for (int64_t c = 0; c < ncells; ++c) {
+        const int64_t k = cag[c] >> sh;
+        for (int j = 0; j < nloc; ++j)
+          for (int a = 0; a < d; ++a) {
+            const double v = coords[(int64_t)cells[c * nloc + j] * d + a];
+            H.lo[k * d + a] = std::min(H.lo[k * d + a], v);
+            H.hi[k * d + a] = std::max(H.hi[k * d + a], v);
+          }
+      }
+    }
     for (int64_t k = 0; k < H.nbox; ++k) {
-      for (int64_t p = off[k]; p < off[k + 1]; ++p)
-        for (int a = 0; a < d; ++a) {
-          double v = an->coords_int[p * d + a];
-          H.lo[k * d + a] = std::min(H.lo[k * d + a], v);
-          H.hi[k * d + a] = std::max(H.hi[k * d + a], v);
-        }
+      if (!an->cell_based)
+        for (int64_t p = off[k]; p < off[k + 1]; ++p)
+          for (int a = 0; a < d; ++a) {
+            double v = an->coords_int[p * d + a];
+            H.lo[k * d + a] = std::min(H.lo[k * d + a], v);
+            H.hi[k * d + a] = std::max(H.hi[k * d + a], v);
+          }
       double e2 = 0;
       for (int a = 0; a < d; ++a) e2 += (H.hi[k * d + a] - H.lo[k * d + a]) * (H.hi[k * d + a] - H.lo[k * d + a]);
       H.max_extent = std::max(H.max_extent, std::sqrt(e2));
@@ -224,7 +304,6 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
 
   // level-1 ownership, local coordinates, unisolvence
   an->leaf_off = offsets[an->depths[0]];
-  an->tree_leaf_off = offsets[an->depth];
   an->constrained.resize(n);
   an->owner.resize(n);
   an->xi.assign(n * d, 0.0);

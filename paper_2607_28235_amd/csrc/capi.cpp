@@ -100,6 +100,20 @@ r3mg_status r3mg_analyze(const double* coords, int64_t n, const int64_t* row_ptr
   });
 }
 
+r3mg_status r3mg_analyze_cells(const double* coords, int64_t n, const int32_t* cells, int64_t ncells, int nloc,
+                               const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
+                               const r3mg_options* opt, r3mg_handle* out) {
+  return guard([&] {
+    if (!out || !opt || !cells) throw Error{R3MG_ERR_INVALID, "null argument"};
+    *out = nullptr;
+    auto an = analyze(coords, n, row_ptr, col_idx, vals, *opt, cells, ncells, nloc);
+    r3mg_handle h = new r3mg_handle_();
+    h->impl.an = std::move(an);
+    *out = h;
+    return R3MG_OK;
+  });
+}
+
 r3mg_status r3mg_factor(r3mg_handle h, void* stream) {
   return guard([&] {
     if (!h) throw Error{R3MG_ERR_INVALID, "null handle"};

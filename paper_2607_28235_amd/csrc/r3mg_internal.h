@@ -112,7 +112,7 @@ struct Analysis {
   std::vector<int32_t> order;            // leaf position -> user point (= perm: internal -> user)
   std::vector<int32_t> iperm;            // user -> internal
   std::vector<int64_t> leaf_off;         // internal offsets of the level-1 boxes (nbox1 + 1)
-  std::vector<int64_t> tree_leaf_off;    // internal offsets of the R-tree leaves (depth t)
+  bool cell_based = false;               // agglomeration of cells (else of support points)
   // fine-level row blocks: CSR geometries (2048/64, 4096/128, 4096/64 nonzeros/rows) and local-column
   // geometries (block offsets, distinct-column offsets and lists, local column index bytes per nonzero)
   std::vector<int32_t> rb[3];
@@ -136,8 +136,10 @@ struct Analysis {
 };
 
 // builds the analysis; throws Error
+// cells (optional, host ncells x nloc support-point indices): cell-based agglomeration
 std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t* row_ptr,
-                                  const int32_t* col_idx, const double* vals, const r3mg_options& opt);
+                                  const int32_t* col_idx, const double* vals, const r3mg_options& opt,
+                                  const int32_t* cells = nullptr, int64_t ncells = 0, int nloc = 0);
 
 void encode_fine(Analysis& an);
 

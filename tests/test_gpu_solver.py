@@ -454,3 +454,81 @@ def test_paper_replication_sweep_trends(q1_sweep):
         assert s[(ref, 1)][0] < s[(ref, 0)][0], (ref, s[(ref, 1)], s[(ref, 0)])
         assert s[(ref, 1)][1] < s[(ref, 0)][1]
     assert abs(s[(7, 1)][0] - s[(6, 1)][0]) <= 1
+
+
+@pytest.mark.parametrize("case", ["q3_jittered_2d", "q2_cube"])
+def test_cell_based_hierarchy_matches_oracle(case):
+    """Cell-based agglomeration (Section 4) through the whole GPU path: Galerkin operators, float64 V-cycle and
+    PCG against the oracle built on the same cells; float32 V-cycle PCG meets the same iteration bar."""
+    _need_gpu()
+    P = _P()
+    if case == "q3_jittered_2d":
+        d, N, p, pc, leaf, skip, mc, ml, jit = 2, 48, 3, 2, 8, False, 100, 4, 0.2
+    else:
+        d, N, p, pc, leaf, skip, mc, ml, jit = 3, 8, 2, 2, 4, True, 300, 0, 0.0
+    _case(f"cell-based {case}")
+    prob = F.structured_qp(d, N, p, jitter=jit, cfg=2)
+    b = F.nodal_rhs(prob, F.rng(2, F.PURPOSE_RHS).standard_normal(prob.n), jitter=jit, cfg=2)
+    ho = O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=pc, leaf_size=leaf, max_levels=ml,
+                           max_coarse_dofs=mc, skip_leaf_level=skip, cells=prob.cells)
+    xo, ko, _, _, _ = O.pcg(ho, b, rtol=1e-10)
+    for fp32 in (0, 1):
+        o = P.Options(dim=d, coarse_degree=pc, leaf_size=leaf, max_levels=ml, max_coarse_dofs=mc,
+                      skip_leaf_level=int(skip), vcycle_fp32=fp32)
+        h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o, cells=prob.cells)
+        if not fp32:
+            for l in range(1, len(ho.levels)):
+                import scipy.sparse as sp
+                rp, cl, vl = h.export_level(l)
+                A = sp.csr_matrix((vl, cl, rp), shape=(len(rp) - 1, len(rp) - 1)).toarray()
+                ref = ho.levels[l].A.toarray()
+                assert np.abs(A - ref).max() <= 1e-13 * np.abs(ref).max(), l
+            r = np.random.default_rng(4).standard_normal(prob.n)
+            r[ho.constrained] = 0.0
+            z = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+            h.vcycle(_t(r), z)
+            torch.cuda.synchronize()
+            assert _rel(z.cpu().numpy(), O.vcycle(ho, r)) < 1e-11
+        x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        iters, relres, ok = h.pcg(_t(b), x, rtol=1e-10, maxit=200)
+        assert ok and abs(int(iters[0]) - ko) <= 1, (fp32, iters, ko)
+        assert _rel(x.cpu().numpy(), xo) < 1e-9
+        h.close()
+
+
+@pytest.fixture(scope="module")
+def q1_sweep_cells():
+    """The fixed-levels Q1 square sweep with cell-based agglomeration (leaf size M = 4 cells, i.e. the paper's
+    m_cells = 2, leaf level skipped, two levels)."""
+    _need_gpu()
+    P = _P()
+    out = {}
+    for ref in (6, 7):
+        prob = F.structured_qp(2, 2 ** ref, 1, cfg=1)
+        b = F.nodal_rhs(prob, F.rng(1, F.PURPOSE_RHS, ref).uniform(-1, 1, prob.n), cfg=1)
+        for pc in (0, 1):
+            _case(f"paper sweep (cells) ref={ref} p'={pc} n={prob.n}")
+            o = P.Options(dim=2, coarse_degree=pc, leaf_size=4, max_levels=2, skip_leaf_level=1)
+            h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o, cells=prob.cells)
+            x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+            it, _, ok, cond = h.pcg(_t(b), x, rtol=1e-6, atol=1e-9, maxit=300, return_cond=True)
+            ho = O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=pc, leaf_size=4, max_levels=2,
+                                   skip_leaf_level=True, cells=prob.cells)
+            xo, ko, conv, _, co = O.pcg(ho, b, rtol=1e-6, atol=1e-9, maxit=300)
+            out[(ref, pc)] = (int(it[0]), float(cond[0]), ko, co, ok and conv, prob.n)
+            h.close()
+    return out
+
+
+def test_paper_replication_sweep_cells(q1_sweep_cells):
+    """Cell-based sweep: GPU iterations and condition estimates match the oracle; Q^1 beats Q^0 and stays flat
+    under refinement (Section 6.1, cell agglomeration table)."""
+    s = q1_sweep_cells
+    for key, (it, cond, ko, co, ok, n) in s.items():
+        assert ok, key
+        assert abs(it - ko) <= 1, (key, it, ko)
+        if it == ko:
+            assert abs(cond - co) <= 1e-6 * co, (key, cond, co)
+    for ref in (6, 7):
+        assert s[(ref, 1)][0] < s[(ref, 0)][0]
+    assert abs(s[(7, 1)][0] - s[(6, 1)][0]) <= 1

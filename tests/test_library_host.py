@@ -184,3 +184,51 @@ def test_leaf_boxes_not_unisolvent_and_skipping_the_leaf_level():
                     P.Options(dim=3, coarse_degree=2, leaf_size=256), factor=False)
     assert el.value.code == "NOT_UNISOLVENT"
     _compare_analysis(prob, 2, 256, skip=True)
+
+
+def _compare_cells(prob, pc, leaf, max_levels=0, max_coarse=2000, skip=False):
+    h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val,
+                    P.Options(dim=prob.d, coarse_degree=pc, leaf_size=leaf, max_levels=max_levels,
+                              max_coarse_dofs=max_coarse, skip_leaf_level=int(skip)), factor=False, cells=prob.cells)
+    ho = O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=pc, leaf_size=leaf, max_levels=max_levels,
+                           max_coarse_dofs=max_coarse, skip_leaf_level=skip, cells=prob.cells)
+    info = h.info()
+    assert len(info) == len(ho.levels)
+    for l in range(1, len(ho.levels)):
+        own, lo, hi = h.export_partition(l)
+        np.testing.assert_array_equal(own, ho.tree.owner(ho.levels[l].depth))
+        np.testing.assert_array_equal(lo, ho.levels[l].lo)
+        np.testing.assert_array_equal(hi, ho.levels[l].hi)
+    for l in range(len(ho.levels) - 1):
+        rp, cl, vl = h.export_P(l)
+        lv = ho.levels[l]
+        np.testing.assert_array_equal(rp, lv.P_indptr)
+        np.testing.assert_array_equal(cl, lv.P_indices)
+        np.testing.assert_allclose(vl, lv.P_data, rtol=0, atol=1e-15)
+    h.close()
+
+
+@pytest.mark.parametrize("case", ["q1_square", "q3_jittered", "q2_cube"])
+def test_cell_based_analysis_matches_oracle(case):
+    """Cell-based agglomeration (Section 4): first-come ownership, cell bounding boxes and transfers bit-exact."""
+    if case == "q1_square":
+        prob = F.structured_qp(2, 64, 1, cfg=1)
+        for pc in (0, 1):
+            _compare_cells(prob, pc, 4, max_levels=3, max_coarse=1, skip=True)
+    elif case == "q3_jittered":
+        _compare_cells(F.structured_qp(2, 24, 3, jitter=0.2, cfg=2), 2, 4, max_coarse=200)
+    else:
+        _compare_cells(F.structured_qp(3, 8, 2, cfg=3), 2, 4, max_coarse=300, skip=True)
+
+
+def test_cell_based_errors():
+    prob = F.structured_qp(2, 4, 1, cfg=1)
+    o = P.Options(dim=2, coarse_degree=0, leaf_size=2)
+    bad = prob.cells.copy()
+    bad[0, 0] = prob.n
+    with pytest.raises(P.R3mgError) as e:
+        P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o, factor=False, cells=bad)
+    assert e.value.code == "INVALID"
+    with pytest.raises(P.R3mgError) as e:   # the last cell dropped: its far corner is in no cell
+        P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o, factor=False, cells=prob.cells[:-1])
+    assert e.value.code == "INVALID"
