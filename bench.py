@@ -435,6 +435,7 @@ def bench_adjoint(args):
 # Section 6.1 tables on the structured Q1 square (p' = 0 and 1), for context only -- the paper's R-tree (Boost's
 # R*-tree, m = 2) differs from this build's bisection tree: per (agglomeration, table), rows of (refinements,
 # levels, the paper's iterations and condition estimates for p' = 0, then for p' = 1).
+# (ref, levels, paper iters / cond with the lower coarse degree, then with the higher one)
 PAPER_Q1 = {
     ("point", "fixed_levels"): [(6, 2, 12, 3.84, 4, 1.04), (7, 2, 15, 4.30, 4, 1.04), (8, 2, 16, 4.48, 4, 1.04)],
     ("cell", "fixed_levels"): [(6, 2, 11, 3.63, 4, 1.03), (7, 2, 14, 3.98, 4, 1.02), (8, 2, 15, 4.08, 3, 1.01)],
@@ -443,25 +444,26 @@ PAPER_Q1 = {
     ("cell", "growing_levels"): [(6, 2, 11, 3.63, 4, 1.03), (7, 3, 15, 6.85, 4, 1.02), (8, 4, 22, 13.25, 4, 1.04),
                                  (9, 5, 30, 26.13, 6, 1.35), (10, 6, 42, 52.10, 8, 2.05)],
 }
+# Section 6, simplicial unit square with P1 elements, fixed levels (the paper's mesh starts from 942 triangles;
+# refinement r has about 942 * 4^r triangles, matched here by N = 87 * 2^(r - 2) squares per side).  Two levels
+# at a fixed H/h make the coarsest level grow with the mesh; refinements 5 and 6 would exceed the dense coarsest
+# solve (R3MG_MAX_COARSEST_DOFS), where the paper uses a sparse direct solver.
+PAPER_P1_SIMPLEX = {
+    ("point", "fixed_levels"): [(2, 2, 16, 5.13, 5, 1.13), (3, 2, 19, 6.09, 5, 1.15), (4, 2, 21, 6.89, 5, 1.16)],
+    ("cell", "fixed_levels"): [(2, 2, 17, 6.21, 5, 1.17), (3, 2, 21, 7.96, 7, 1.60), (4, 2, 22, 7.49, 6, 1.41)],
+}
 
 
-def bench_replicate(args):
-    """Paper-replication mode: the structured Q1 square tables of Section 6.1 (fixed levels, then levels growing
-    with the refinement) for point- and cell-based agglomeration, PCG stopped at a 1e-6 reduction or 1e-9
-    absolute, V(2,2) Chebyshev-3, the leaf level skipped; leaf size 8 points (point-based) or 4 cells
-    (cell-based, the paper's m_cells = 2)."""
-    import torch
-    import fixtures as F
-    import paper_2607_28235_amd as P
+def _replicate_table(P, torch, family, tables, make, leaf, hmax_of):
     rows = []
-    for (agg, table), spec in PAPER_Q1.items():
+    for (agg, table), spec in tables.items():
         for ref, lv, pit0, pcond0, pit1, pcond1 in spec:
-            prob = F.structured_qp(2, 2 ** ref, 1, cfg=1)
-            b = torch.from_numpy(F.nodal_rhs(prob, F.rng(1, F.PURPOSE_RHS, ref).uniform(-1, 1, prob.n), cfg=1)).cuda()
-            row = {"agglomeration": agg, "table": table, "ref": ref, "dofs": prob.n, "levels": lv,
-                   "paper": {"iters_p0": pit0, "cond_p0": pcond0, "iters_p1": pit1, "cond_p1": pcond1}}
+            prob, b_np = make(ref)
+            b = torch.from_numpy(b_np).cuda()
+            row = {"family": family, "agglomeration": agg, "table": table, "ref": ref, "dofs": prob.n,
+                   "levels": lv, "paper": {"iters_p0": pit0, "cond_p0": pcond0, "iters_p1": pit1, "cond_p1": pcond1}}
             for pc in (0, 1):
-                o = P.Options(dim=2, coarse_degree=pc, leaf_size=8 if agg == "point" else 4, max_levels=lv,
+                o = P.Options(dim=2, coarse_degree=pc, leaf_size=leaf[agg], max_levels=lv,
                               max_coarse_dofs=1, skip_leaf_level=1, vcycle_fp32=0)
                 h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o,
                                 cells=prob.cells if agg == "cell" else None)
@@ -469,20 +471,46 @@ def bench_replicate(args):
                 x = torch.zeros_like(b)
                 it, _, ok, cond = h.pcg(b, x, rtol=1e-6, atol=1e-9, maxit=500, return_cond=True)
                 t = _timed(lambda: (x.zero_(), h.pcg(b, x, rtol=1e-6, atol=1e-9, maxit=500)), 3, 1)[0]
-                hmax = np.sqrt(2.0) / 2 ** ref  # cell diagonal of the uniform mesh
                 row[f"p{pc}"] = {"iters": int(it[0]), "cond": float(cond[0]), "converged": bool(ok),
-                                 "H_over_h": info[-1]["max_box_extent"] / hmax, "levels": len(info),
-                                 "solve_ms": t * 1e3}
+                                 "H_over_h": info[-1]["max_box_extent"] / hmax_of(prob, ref),
+                                 "levels": len(info), "solve_ms": t * 1e3}
                 h.close()
-            log(f"{agg} {table} ref {ref} n={prob.n} lvls {lv}: p'=0 {row['p0']['iters']} it (cond "
+            log(f"{family} {agg} {table} ref {ref} n={prob.n} lvls {lv}: p'=0 {row['p0']['iters']} it (cond "
                 f"{row['p0']['cond']:.2f}), p'=1 {row['p1']['iters']} it (cond {row['p1']['cond']:.2f}), H/h "
                 f"{row['p1']['H_over_h']:.2f}; paper {pit0}/{pit1}")
             rows.append(row)
-    print(json.dumps({"metric": "paper replication: PCG iterations and condition estimates, structured Q1 square",
+    return rows
+
+
+def bench_replicate(args):
+    """Paper-replication mode, PCG stopped at a 1e-6 reduction or 1e-9 absolute, V(2,2) Chebyshev-3, the leaf
+    level skipped:
+    - the structured Q1 square tables of Section 6.1 (fixed levels, then levels growing with the refinement),
+      leaf size 8 points (point-based) or 4 cells (cell-based, the paper's m_cells = 2);
+    - the simplicial P1 square table with fixed levels (Section 6), leaf size 4 points (m_points = 2) or
+      16 cells (m_cells = 4), on a jittered structured triangulation standing in for the paper's unstructured
+      one (H/h against the longest triangle edge)."""
+    import torch
+    import fixtures as F
+    import paper_2607_28235_amd as P
+
+    def q1(ref):
+        prob = F.structured_qp(2, 2 ** ref, 1, cfg=1)
+        return prob, F.nodal_rhs(prob, F.rng(1, F.PURPOSE_RHS, ref).uniform(-1, 1, prob.n), cfg=1)
+
+    def p1_simplex(ref):
+        prob = F.simplicial_pp(87 * 2 ** (ref - 2), 1, jitter=0.2, cfg=2)
+        return prob, F.nodal_rhs(prob, F.rng(2, F.PURPOSE_RHS, ref).uniform(-1, 1, prob.n))
+
+    rows = _replicate_table(P, torch, "structured_q1_square", PAPER_Q1, q1, {"point": 8, "cell": 4},
+                            lambda prob, ref: np.sqrt(2.0) / 2 ** ref)   # cell diagonal of the uniform mesh
+    rows += _replicate_table(P, torch, "simplicial_p1_square", PAPER_P1_SIMPLEX, p1_simplex,
+                             {"point": 4, "cell": 16}, lambda prob, ref: prob.h)
+    print(json.dumps({"metric": "paper replication: PCG iterations and condition estimates",
                       "unit": "iterations", "n_gpus": 1, "data": "synthetic",
-                      "config": {"workload": "Section 6.1 structured Q1 square, point (leaf 8) and cell (leaf 4 "
-                                             "cells) agglomeration, skip leaf level, V(2,2) Chebyshev-3, stop 1e-6 "
-                                             "reduction or 1e-9 absolute"},
+                      "config": {"workload": "Section 6.1 structured Q1 square (point leaf 8, cell leaf 4) and "
+                                             "simplicial P1 square (point leaf 4, cell leaf 16), skip leaf level, "
+                                             "V(2,2) Chebyshev-3, stop 1e-6 reduction or 1e-9 absolute"},
                       "rows": rows}), flush=True)
 
 

@@ -381,9 +381,132 @@ class Workload:
 
 def nodal_rhs(prob: QpProblem, f: np.ndarray, *, jitter: float = 0.0, cfg: int = 0) -> np.ndarray:
     """b = M f_h zeroed on constrained points (f given at the support points)."""
-    b = mass_apply(prob.d, prob.N, prob.p, f, jitter=jitter, cfg=cfg)
+    if getattr(prob, "mass", None) is not None:    # simplicial problems carry their assembled mass matrix
+        b = prob.mass @ f
+    else:
+        b = mass_apply(prob.d, prob.N, prob.p, f, jitter=jitter, cfg=cfg)
     b[prob.boundary] = 0.0
     return b
+
+
+# ---------------------------------------------------------------------------------------------------------
+# Simplicial P_p meshes (the paper's simplicial experiments use Lagrange elements of total degree p on
+# uniformly spaced nodes): the unit square, N x N squares each split along the diagonal from (x, y) to
+# (x+1, y+1) into two triangles, optional jitter of the interior vertices (the same vertices as structured_qp).
+# ---------------------------------------------------------------------------------------------------------
+def _simplex_reference(p: int):
+    """Equispaced nodes (i/p, j/p), i + j <= p, of the reference triangle, the monomial coefficients of the
+    Lagrange basis on them, and the exact reference stiffness blocks S_ab = int d_a phi_i d_b phi_j and mass
+    int phi_i phi_j (monomial integrals int x^m y^n = m! n! / (m + n + 2)!)."""
+    from math import factorial
+    ij = [(i, j) for j in range(p + 1) for i in range(p + 1 - j)]
+    mono = [(a, b) for b in range(p + 1) for a in range(p + 1 - b)]
+    X = np.array([[i / p, j / p] for i, j in ij]) if p > 0 else np.zeros((1, 2))
+    V = np.array([[x ** a * y ** b for a, b in mono] for x, y in X])
+    Cf = np.linalg.inv(V)                                  # phi_i = sum_k Cf[k, i] x^a_k y^b_k
+    m = len(mono)
+
+    def integ(a, b):
+        return factorial(a) * factorial(b) / factorial(a + b + 2)
+    # monomial Gram matrices: <m_k, m_l>, <d_x m_k, d_x m_l>, ...
+    G = np.array([[integ(a1 + a2, b1 + b2) for a2, b2 in mono] for a1, b1 in mono])
+
+    def dmono(k, axis):
+        a, b = mono[k]
+        if axis == 0:
+            return (a, max(a - 1, 0), b) if a > 0 else (0, 0, 0)
+        return (b, a, max(b - 1, 0)) if b > 0 else (0, 0, 0)
+    Gd = np.zeros((2, 2, m, m))
+    for ax in range(2):
+        for bx in range(2):
+            for k in range(m):
+                ck, ak, bk = dmono(k, ax)
+                if ck == 0:
+                    continue
+                for l in range(m):
+                    cl, al, bl = dmono(l, bx)
+                    if cl == 0:
+                        continue
+                    Gd[ax, bx, k, l] = ck * cl * integ(ak + al, bk + bl)
+    S = np.einsum("ki,abkl,lj->abij", Cf, Gd, Cf)
+    Mref = Cf.T @ G @ Cf
+    return np.array(ij), S, 0.5 * (Mref + Mref.T)
+
+
+def simplicial_pp(N: int, p: int, *, jitter: float = 0.0, cfg: int = 0, dirichlet: bool = True,
+                  keep_ke: bool = False) -> QpProblem:
+    """P_p stiffness matrix on the triangulated unit square (2 N^2 triangles, (pN + 1)^2 support points on the
+    lattice, numbered x fastest), Dirichlet rows as in structured_qp.  The returned problem also carries the
+    assembled consistent mass matrix (`mass`) for right-hand sides."""
+    import scipy.sparse as sp
+    M1 = p * N + 1
+    n = M1 * M1
+    Nv = N + 1
+    vx = np.stack(np.meshgrid(np.arange(Nv), np.arange(Nv), indexing="xy"), axis=-1).reshape(-1, 2) / N
+    vgrid = np.rint(vx * N).astype(np.int64)
+    if jitter > 0.0:
+        g = rng(cfg, PURPOSE_JITTER)
+        shift = g.uniform(-jitter / N, jitter / N, size=vx.shape)
+        interior = np.all((vgrid > 0) & (vgrid < N), axis=1)
+        vx = vx.copy()
+        vx[interior] += shift[interior]
+    ij, S, Mref = _simplex_reference(p)
+    nloc = ij.shape[0]
+    cx, cy = np.meshgrid(np.arange(N), np.arange(N), indexing="xy")
+    cx, cy = cx.ravel(), cy.ravel()
+    v00, v10 = cy * Nv + cx, cy * Nv + cx + 1
+    v01, v11 = (cy + 1) * Nv + cx, (cy + 1) * Nv + cx + 1
+    tris, offs = [], []
+    # T0 = (v00, v10, v11): lattice offset of node (i, j) = (i + j, j); T1 = (v00, v11, v01): (i, i + j)
+    for verts, off in (((v00, v10, v11), np.stack([ij[:, 0] + ij[:, 1], ij[:, 1]], 1)),
+                       ((v00, v11, v01), np.stack([ij[:, 0], ij[:, 0] + ij[:, 1]], 1))):
+        tris.append(np.stack(verts, 1))
+        lx = p * cx[:, None] + off[None, :, 0]
+        ly = p * cy[:, None] + off[None, :, 1]
+        offs.append(ly * M1 + lx)
+    tv = np.concatenate(tris)                               # (2 N^2, 3) vertex indices
+    cells = np.concatenate(offs).astype(np.int64)           # (2 N^2, nloc) support points
+    ncells = tv.shape[0]
+    XA, XB, XC = vx[tv[:, 0]], vx[tv[:, 1]], vx[tv[:, 2]]
+    J = np.stack([XB - XA, XC - XA], axis=2)                 # (c, 2, 2): columns dX/dxi, dX/deta
+    det = np.linalg.det(J)
+    if np.any(det <= 0):
+        raise ValueError("inverted triangle")
+    Jinv = np.linalg.inv(J)
+    Gm = np.einsum("cak,cbk->cab", Jinv, Jinv)              # J^-1 J^-T (grad_x = J^-T grad_xi)
+    Ke = det[:, None, None] * np.einsum("cab,abij->cij", Gm, S)
+    Ke = 0.5 * (Ke + Ke.transpose(0, 2, 1))                   # exact up to the basis' rounding: symmetrise
+    Me = det[:, None, None] * Mref[None, :, :]
+    coords = np.empty((n, 2))
+    lam = ij / max(p, 1)
+    coords[cells] = (XA[:, None, :] + lam[None, :, 0:1] * (XB - XA)[:, None, :] +
+                     lam[None, :, 1:2] * (XC - XA)[:, None, :])
+    rows = np.repeat(cells, nloc, axis=1).ravel()
+    colsi = np.tile(cells, (1, nloc)).ravel()
+    A = sp.csr_matrix((Ke.ravel(), (rows, colsi)), shape=(n, n))
+    M = sp.csr_matrix((Me.ravel(), (rows, colsi)), shape=(n, n))
+    A.sum_duplicates()
+    M.sum_duplicates()
+    gx, gy = np.arange(n) % M1, np.arange(n) // M1
+    boundary = (gx == 0) | (gx == M1 - 1) | (gy == 0) | (gy == M1 - 1)
+    if not dirichlet:
+        boundary[:] = False
+    if boundary.any():
+        keep = ~boundary
+        D = sp.diags(keep.astype(np.float64))
+        A = (D @ A @ D + sp.diags(boundary.astype(np.float64))).tocsr()
+        A.eliminate_zeros()
+        # keep the constrained rows' diagonal even where the product removed it
+        A = A.tocsr()
+    A.sort_indices()
+    Mw = np.asarray(M.sum(axis=1)).ravel()
+    Mw[boundary] = 0.0
+    h = float(np.max(np.linalg.norm(np.stack([XB - XA, XC - XB, XA - XC], 1), axis=2)))
+    prob = QpProblem(d=2, N=N, p=p, coords=coords, row_ptr=A.indptr.astype(np.int64),
+                     col=A.indices.astype(np.int32), val=A.data.astype(np.float64), boundary=boundary,
+                     cells=cells.astype(np.int32), mass_rhs_weights=Mw, Ke=Ke if keep_ke else None, h=h)
+    prob.mass = M.tocsr()
+    return prob
 
 
 def smooth_target(coords: np.ndarray, cfg: int = 5) -> np.ndarray:

@@ -36,6 +36,11 @@ extern "C" {
 
 typedef struct r3mg_handle_* r3mg_handle;
 
+/* Largest coarsest level, in DoFs, that the dense float64 Cholesky inverse takes: two n x n float64 arrays,
+   2 x 34 GB at this size.  The paper's coarsest solve is a sparse direct one (Section 6); this library inverts
+   the coarsest operator densely on the device, which fits HBM up to this size. */
+#define R3MG_MAX_COARSEST_DOFS 65536
+
 typedef enum {
   R3MG_OK = 0,
   R3MG_NOT_CONVERGED = 1,
@@ -53,7 +58,8 @@ typedef struct {
   int coarse_degree;    /* p' in 0..3, box polynomial degree per axis (p'=0: Nicolaides) [1] */
   int leaf_size;        /* R-tree M: maximum number of points per leaf box [64] */
   int max_levels;       /* levels including the fine one; 0 = until max_coarse_dofs or the root [0] */
-  int max_coarse_dofs;  /* stop coarsening at the first level with at most this many DoFs [2000] */
+  int max_coarse_dofs;  /* stop coarsening at the first level with at most this many DoFs [2000]; a coarsest
+                           level above R3MG_MAX_COARSEST_DOFS (max_levels reached first) is R3MG_ERR_INVALID */
   int skip_leaf_level;  /* 1 = first coarse level at depth t-d instead of the leaf depth t [0] */
   int cheb_degree;      /* Chebyshev polynomial degree K >= 1 [3] */
   int pre_steps;        /* smoothing applications before the coarse correction [2] */

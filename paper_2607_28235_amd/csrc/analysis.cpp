@@ -207,6 +207,11 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
       if (an->depths.back() == 0) break;
       an->depths.push_back(std::max(an->depths.back() - d, 0));
     }
+    const int64_t ncoarse = (int64_t(1) << an->depths.back()) * B;
+    if (ncoarse > R3MG_MAX_COARSEST_DOFS)
+      throw err(R3MG_ERR_INVALID, "coarsest level would have " + std::to_string(ncoarse) +
+                                      " DoFs, more than the dense coarsest solve takes (" +
+                                      std::to_string(R3MG_MAX_COARSEST_DOFS) + "): allow more levels");
   }
   if (an->cell_based) {
     for (auto& off : coff)

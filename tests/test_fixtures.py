@@ -101,3 +101,49 @@ def test_seeded_inputs_are_reproducible():
     w1 = F.workload(1)
     w2 = F.workload(1)
     assert np.array_equal(w1.rhs, w2.rhs) and np.array_equal(w1.problem.val, w2.problem.val)
+
+
+# ---- simplicial P_p stand-in meshes (the paper's simplicial experiments) -----------------------------------
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_simplicial_counts_and_element_matrices(p):
+    """(pN+1)^2 lattice support points, 2N^2 triangles; element stiffness symmetric with zero row sums and
+    exact energy |grad u|^2 area for linear u; element mass exact for u^2 of linear u (degree 2 <= 2p)."""
+    N = 5
+    prob = F.simplicial_pp(N, p, jitter=0.2, cfg=2, keep_ke=True, dirichlet=False)
+    assert prob.n == (p * N + 1) ** 2 and prob.cells.shape == (2 * N * N, (p + 1) * (p + 2) // 2)
+    Ke = prob.Ke
+    assert np.abs(Ke - Ke.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(Ke).max()
+    assert np.abs(Ke.sum(axis=2)).max() <= 1e-11 * np.abs(Ke).max()
+    a, b, c0 = 0.7, -1.3, 0.4
+    x = prob.coords[prob.cells]                                     # (cells, nloc, 2)
+    u = a * x[..., 0] + b * x[..., 1] + c0
+    # the element's vertices: local nodes (0,0), (p,0), (0,p) in the (i, j) listing
+    ij = F._simplex_reference(p)[0]
+    iA = int(np.flatnonzero((ij[:, 0] == 0) & (ij[:, 1] == 0))[0])
+    iB = int(np.flatnonzero((ij[:, 0] == p) & (ij[:, 1] == 0))[0])
+    iC = int(np.flatnonzero((ij[:, 0] == 0) & (ij[:, 1] == p))[0])
+    XA, XB, XC = x[:, iA], x[:, iB], x[:, iC]
+    area = 0.5 * np.abs((XB - XA)[:, 0] * (XC - XA)[:, 1] - (XB - XA)[:, 1] * (XC - XA)[:, 0])
+    energy = np.einsum("ci,cij,cj->c", u, Ke, u)
+    np.testing.assert_allclose(energy, (a * a + b * b) * area, rtol=1e-11)
+    M = prob.mass
+    assert abs(M.sum() - 1.0) <= 1e-12                              # area of the unit square
+    ug = a * prob.coords[:, 0] + b * prob.coords[:, 1] + c0
+    # int_{[0,1]^2} (a x + b y + c)^2 dx dy in closed form
+    exact = a * a / 3 + b * b / 3 + c0 * c0 + a * b / 2 + a * c0 + b * c0
+    assert abs(ug @ (M @ ug) - exact) <= 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_simplicial_manufactured_solution_converges(p):
+    """-Lap u = 2 pi^2 sin(pi x) sin(pi y) with homogeneous Dirichlet data: nodal max error O(h^{p+1})."""
+    import scipy.sparse.linalg as spla
+    errs = []
+    for N in (8, 16):
+        prob = F.simplicial_pp(N, p, jitter=0.0, cfg=2)
+        ue = np.sin(np.pi * prob.coords[:, 0]) * np.sin(np.pi * prob.coords[:, 1])
+        b = F.nodal_rhs(prob, 2 * np.pi ** 2 * ue)
+        uh = spla.spsolve(prob.scipy().tocsc(), b)
+        errs.append(np.abs(uh - ue).max())
+    rate = np.log2(errs[0] / errs[1])
+    assert rate >= p + 0.7, (errs, rate)

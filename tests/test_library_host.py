@@ -232,3 +232,42 @@ def test_cell_based_errors():
     with pytest.raises(P.R3mgError) as e:   # the last cell dropped: its far corner is in no cell
         P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o, factor=False, cells=prob.cells[:-1])
     assert e.value.code == "INVALID"
+
+
+@pytest.mark.parametrize("p,pc", [(1, 1), (2, 2), (3, 2)])
+def test_simplicial_analysis_matches_oracle(p, pc):
+    """Simplicial P_p meshes (Section 6 uses simplicial discretisations beside the box ones): the box hierarchy
+    does not depend on the element shape, so point- and cell-based analyses of a jittered triangulation still
+    agree bit for bit with the oracle (ownership, boxes, transfers)."""
+    prob = F.simplicial_pp(24 if p < 3 else 16, p, jitter=0.2, cfg=2)
+    leaf = {1: 16, 2: 24, 3: 40}[p]
+    _compare_analysis(prob, pc, leaf, max_coarse=200)
+    _compare_cells(prob, pc, {1: 24, 2: 24, 3: 8}[p], max_coarse=200)
+    _compare_cells(prob, pc, 8, max_coarse=200, skip=True)
+
+
+def test_simplicial_cell_boxes_not_unisolvent_like_the_oracle():
+    """First-come ownership on a triangulation can leave a leaf box whose owned points do not determine Q^p';
+    library and oracle reject the same box."""
+    prob = F.simplicial_pp(24, 2, jitter=0.2, cfg=2)
+    o = P.Options(dim=2, coarse_degree=2, leaf_size=8, max_coarse_dofs=200)
+    with pytest.raises(P.R3mgError) as e:
+        P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o, factor=False, cells=prob.cells)
+    assert e.value.code == "NOT_UNISOLVENT"
+    box = re.search(r"box (\d+)", str(e.value)).group(1)
+    from oracle.hierarchy import R3mgError as OracleError
+    with pytest.raises(OracleError) as eo:
+        O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=2, leaf_size=8, max_coarse_dofs=200,
+                          cells=prob.cells)
+    assert eo.value.code == "NOT_UNISOLVENT"
+    assert re.search(r"box (\d+)", str(eo.value)).group(1) == box
+
+
+def test_coarsest_level_above_the_dense_limit_is_rejected():
+    """Two levels on a 66k-DoF problem with 2-point leaves: the coarsest level would exceed the dense coarsest
+    solve's limit, which the analysis rejects before any device work."""
+    prob = F.structured_qp(2, 256, 1, cfg=1)
+    o = P.Options(dim=2, coarse_degree=1, leaf_size=2, max_levels=2)
+    with pytest.raises(P.R3mgError) as e:
+        P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o, factor=False)
+    assert e.value.code == "INVALID" and "dense coarsest" in str(e.value)
