@@ -59,7 +59,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU (oracle) baseline leg")
     ap.add_argument("--scale", type=int, default=None, help="override N (cells per side) for quick runs")
     ap.add_argument("--workload", default="solve2d",
-                    choices=["solve2d", "solve3d", "batch16", "uneven8", "adjoint", "replicate"],
+                    choices=["solve2d", "solve3d", "batch16", "uneven8", "adjoint", "replicate", "matfree"],
                     help="solve2d: the headline (591k-DoF Q3 square); batch16: 16-RHS block PCG on the 48^3 Q3 "
                          "cube; uneven8: 8 Q2 cubes of 16^3..48^3 in one graph; adjoint: kappa-gradient on 64^3 Q2")
     ap.add_argument("--fd-cells", type=int, default=32)
@@ -72,7 +72,7 @@ def main():
         sys.exit(2)
     if args.workload not in ("solve2d", "solve3d"):
         {"batch16": bench_batch16, "uneven8": bench_uneven8, "adjoint": bench_adjoint,
-         "replicate": bench_replicate}[args.workload](args)
+         "replicate": bench_replicate, "matfree": bench_matfree}[args.workload](args)
         return
 
     import torch
@@ -452,6 +452,58 @@ PAPER_P1_SIMPLEX = {
     ("point", "fixed_levels"): [(2, 2, 16, 5.13, 5, 1.13), (3, 2, 19, 6.09, 5, 1.15), (4, 2, 21, 6.89, 5, 1.16)],
     ("cell", "fixed_levels"): [(2, 2, 17, 6.21, 5, 1.17), (3, 2, 21, 7.96, 7, 1.60), (4, 2, 22, 7.49, 6, 1.41)],
 }
+
+
+def bench_matfree(args):
+    """Matrix-free fine operator against the CSR fine matrix on the 2D Q3 256^2 jittered square (591,361 DoFs,
+    multilinear cells) and the 3D Q2 64^3 cube (2,146,689 DoFs, affine cells): solve time to rtol 1e-10 in both
+    V-cycle precisions, the fused fine-level smoother step (both launches of the matrix-free form) and its
+    algorithmic bytes."""
+    import torch
+    import fixtures as F
+    import paper_2607_28235_amd as P
+    rows = []
+    for cfg in (2, 3):
+        w = F.workload(cfg, scale=args.scale)
+        prob = w.problem
+        b = torch.from_numpy(w.rhs).cuda()
+        for fp32 in (1, 0):
+            o = P.Options(dim=prob.d, coarse_degree=w.coarse_degree, leaf_size=w.leaf_size, max_levels=w.max_levels,
+                          max_coarse_dofs=w.max_coarse_dofs, pre_steps=w.pre_steps, post_steps=w.post_steps,
+                          vcycle_fp32=fp32, skip_leaf_level=w.skip_leaf_level)
+            h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o)
+            row = {"workload": w.name, "n": prob.n, "vcycle": "fp32" if fp32 else "fp64"}
+            xs = {}
+            for mode in ("csr", "matrix_free"):
+                if mode == "matrix_free":
+                    ta = time.time()
+                    h.set_matrix_free(prob.cells, prob.p)
+                    row["matrix_free_setup_s"] = time.time() - ta
+                x = torch.zeros_like(b)
+
+                def solve():
+                    x.zero_()
+                    return h.pcg(b, x, rtol=1e-10, maxit=500)
+                t, res = _timed(solve, args.steps, args.warmup)
+                it, _, ok = res
+                kms, kby = h.time_smoother_kernel(0, 100)
+                xs[mode] = x.cpu().numpy()
+                row[mode] = {"ms_per_solve": t * 1e3, "DoF_per_s": prob.n / t, "iters": int(it[0]),
+                             "converged": bool(ok), "fine_kernel": h.info()[0]["kernel"],
+                             "fine_step_us": kms * 1e3, "fine_step_bytes": kby,
+                             "fine_step_GBps": kby / (kms * 1e-3) / 1e9}
+            row["solution_rel_diff"] = float(np.linalg.norm(xs["matrix_free"] - xs["csr"]) /
+                                             np.linalg.norm(xs["csr"]))
+            row["speedup"] = row["csr"]["ms_per_solve"] / row["matrix_free"]["ms_per_solve"]
+            log(f"{w.name} {row['vcycle']}: CSR {row['csr']['ms_per_solve']:.2f} ms ({row['csr']['fine_step_us']:.1f} "
+                f"us fine step), matrix-free {row['matrix_free']['ms_per_solve']:.2f} ms "
+                f"({row['matrix_free']['fine_step_us']:.1f} us, {row['matrix_free']['fine_step_GBps']:.0f} GB/s), "
+                f"iters {row['csr']['iters']}/{row['matrix_free']['iters']}, diff {row['solution_rel_diff']:.1e}")
+            rows.append(row)
+            h.close()
+    print(json.dumps({"metric": "DoF/s solved to rtol 1e-10, matrix-free vs CSR fine operator", "unit": "DoF/s",
+                      "n_gpus": 1, "data": "synthetic", "steps": args.steps, "warmup": args.warmup,
+                      "rows": rows}), flush=True)
 
 
 def _replicate_table(P, torch, family, tables, make, leaf, hmax_of):

@@ -128,8 +128,28 @@ r3mg_status r3mg_setup(const double* coords, int64_t n, const int64_t* row_ptr, 
                        const double* vals, const r3mg_options* opt, void* stream, r3mg_handle* out);
 
 /* Numeric re-set-up with new values on the same sparsity pattern (device array, nnz float64, caller's CSR
- * order).  The constrained set, partition and transfers are kept.  Synchronises. */
+ * order).  The constrained set, partition and transfers are kept.  A matrix-free fine operator set by
+ * r3mg_set_matrix_free is dropped (the solver returns to the CSR matrix).  Synchronises. */
 r3mg_status r3mg_update_values(r3mg_handle h, const double* vals_dev, void* stream);
+
+/* Matrix-free fine-level operator (not in the paper; an alternative to streaming the CSR matrix).  Describes the
+ * handle's fine matrix as the Q_p Laplace stiffness matrix of the Poisson problem of Section 6: the sum over
+ * cells e of kappa_e K_e with (K_e)_ab = integral over the cell of grad phi_a . grad phi_b, computed with
+ * Gauss-Legendre quadrature of p + 1 points per axis, the basis phi being the tensor Lagrange polynomials on
+ * the p + 1 Gauss-Lobatto nodes per axis mapped by the multilinear map of the cell's 2^d corner support
+ * points; constrained rows and columns (the handle's constrained set) are removed and the constrained rows keep
+ * their diagonal entry.
+ *   cells   host int32 array, ncells x (p+1)^d, row-major: the caller's support-point indices of each cell in
+ *           tensor order (local node (i_0, .., i_{d-1}) at position i_0 + (p+1) i_1 + (p+1)^2 i_2, node i_a at
+ *           the a-th coordinate's Gauss-Lobatto point), copied; NULL drops a matrix-free operator set before
+ *   degree  p in 1..3;   kappa  host float64 per cell, positive, or NULL for 1
+ * The operator is applied to y = A v for a fixed pseudo-random v and compared with the CSR matrix; a maximum
+ * difference above 1e-10 max|A v| (wrong degree, node order, geometry or quadrature) is R3MG_ERR_INVALID and
+ * leaves the CSR matrix in use.  Once set, every single-right-hand-side application of the fine operator
+ * (smoother, residual, PCG's A p) is matrix-free; multi-right-hand-side solves keep the CSR kernels.
+ * Results then differ from the CSR path by rounding only.  Synchronises. */
+r3mg_status r3mg_set_matrix_free(r3mg_handle h, const int32_t* cells, int64_t ncells, int degree, const double* kappa,
+                                 void* stream);
 
 /* z = B r, one V-cycle (Section 4) in the handle's V-cycle precision, for nrhs right-hand sides. */
 r3mg_status r3mg_vcycle(r3mg_handle h, const double* r_dev, double* z_dev, int nrhs, void* stream);

@@ -19,6 +19,8 @@ multilevel preconditioner for continuous finite element discretizations"):
                 the two-level error propagator, Section 6 stopping rule)
   adjoint.py    adjoint gradient of 1/2||u-u_t||^2 with respect to per-cell kappa (standard adjoint
                 method; not in the paper)
+  matfree.py    Q_p Laplace stiffness action cell by cell from its definition (the operator of Section 6,
+                the reference of the matrix-free fine operator)
 
 Readings where the paper is silent are listed in the module docstrings (bisection R-tree instead of the
 Boost R*-tree, GLL box nodes, Chebyshev interval parameters, Lanczos start vector, stop rule form).
@@ -30,9 +32,11 @@ from .hierarchy import Hierarchy, build_hierarchy, R3mgError
 from .smoother import lanczos_max_eig, sturm_max_eig, chebyshev_apply
 from .solve import vcycle, pcg, pcg_batched
 from .adjoint import assemble_kappa, cell_gradient, loss_and_gradient
+from .matfree import element_stiffness, stiffness_apply
 
 __all__ = [
     "bisection_rtree", "cell_rtree", "CellTree", "select_levels", "RTree", "box_nodes_1d", "box_basis_values", "Hierarchy",
     "build_hierarchy", "R3mgError", "lanczos_max_eig", "sturm_max_eig", "chebyshev_apply", "vcycle",
-    "pcg", "pcg_batched", "assemble_kappa", "cell_gradient", "loss_and_gradient",
+    "pcg", "pcg_batched", "assemble_kappa", "cell_gradient", "loss_and_gradient", "element_stiffness",
+    "stiffness_apply",
 ]

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID", -2: "NOT_UNISOLVENT"
                 -4: "NOT_SPD", -5: "OOM", -6: "HIP"}
 
 EXPORTED = [
-    "r3mg_analyze_cells",
+    "r3mg_analyze_cells", "r3mg_set_matrix_free",
     "r3mg_default_options", "r3mg_analyze", "r3mg_factor", "r3mg_setup", "r3mg_update_values", "r3mg_vcycle",
     "r3mg_level_apply", "r3mg_pcg_solve", "r3mg_pcg_solve_ex", "r3mg_pcg_solve_group", "r3mg_info", "r3mg_export_partition",
     "r3mg_export_P", "r3mg_export_level", "r3mg_time_smoother_kernel", "r3mg_cell_grad", "r3mg_assembler_create",
@@ -92,6 +92,7 @@ def lib():
     L.r3mg_factor.argtypes = [vp, vp]
     L.r3mg_setup.argtypes = [vp, i64, vp, vp, vp, P(_Options), vp, P(vp)]
     L.r3mg_update_values.argtypes = [vp, vp, vp]
+    L.r3mg_set_matrix_free.argtypes = [vp, vp, i64, i32, vp, vp]
     L.r3mg_vcycle.argtypes = [vp, vp, vp, i32, vp]
     L.r3mg_level_apply.argtypes = [vp, i32, vp, vp, vp]
     L.r3mg_pcg_solve.argtypes = [vp, vp, vp, i32, dbl, i32, vp, vp, vp]
@@ -205,6 +206,21 @@ class Hierarchy:
     # --- device operations -------------------------------------------------------------------
     def update_values(self, vals_dev, stream=None):
         _check(lib().r3mg_update_values(self._h, _dev(vals_dev), _stream(stream)), "r3mg_update_values")
+
+    def set_matrix_free(self, cells, degree: int, kappa=None, stream=None):
+        """Apply the fine level matrix-free from the Q_p cells (host ncells x (p+1)^d, tensor order); None
+        returns to the CSR matrix."""
+        if cells is None:
+            _check(lib().r3mg_set_matrix_free(self._h, None, 0, 0, None, _stream(stream)), "r3mg_set_matrix_free")
+            return
+        ce = np.ascontiguousarray(cells, dtype=np.int32)
+        if ce.ndim != 2 or ce.shape[1] != (degree + 1) ** self.options.dim:
+            raise ValueError("cells must be (ncells, (degree + 1)^dim)")
+        kp = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+        if kp is not None and kp.shape != (ce.shape[0],):
+            raise ValueError("kappa must hold one value per cell")
+        _check(lib().r3mg_set_matrix_free(self._h, _ptr(ce), ce.shape[0], degree, None if kp is None else _ptr(kp),
+                                          _stream(stream)), "r3mg_set_matrix_free")
 
     def vcycle(self, r, z, stream=None):
         nrhs = 1 if r.dim() == 1 else r.shape[0]

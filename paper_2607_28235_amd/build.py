@@ -16,13 +16,14 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libr3mg.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "solver.cpp", "capi.cpp", "analysis.cpp"]
+SOURCES = ["kernels.hip", "matfree.hip", "solver.cpp", "capi.cpp", "analysis.cpp", "matfree.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
 PER_FILE = {
     # host decisions (tree comparisons, unisolvence pivots, transfer values) without FMA contraction
     "analysis.cpp": ["-ffp-contract=off"],
+    "matfree.cpp": ["-ffp-contract=off"],
 }
 
 

@@ -154,6 +154,20 @@ r3mg_status r3mg_update_values(r3mg_handle h, const double* vals_dev, void* stre
   });
 }
 
+r3mg_status r3mg_set_matrix_free(r3mg_handle h, const int32_t* cells, int64_t ncells, int degree, const double* kappa,
+                                 void* stream) {
+  return guard([&] {
+    require_factored(h);
+    if (!cells) {
+      detach_matrix_free(h->impl);
+      return R3MG_OK;
+    }
+    MatFreeHost m = build_matrix_free(*h->impl.an, cells, ncells, degree, kappa);
+    attach_matrix_free(h->impl, std::move(m), S(stream));
+    return R3MG_OK;
+  });
+}
+
 r3mg_status r3mg_vcycle(r3mg_handle h, const double* r_dev, double* z_dev, int nrhs, void* stream) {
   return guard([&] {
     require_factored(h);

@@ -172,6 +172,36 @@ void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hip
 void launch_lanczos_u(int64_t n, const double* dinv, const double* Av, double beta_prev, const double* vprev,
                       double* u, hipStream_t s);  // u = dinv*Av - beta_prev*vprev
 
+// ---- matrix-free fine operator: the Q_p Laplace stiffness action on multilinear cells ----
+// 1D tables of the cell kernel: B[q][i] = l_i(g_q) and G[q][i] = l_i'(g_q) for the Lagrange basis l_i on the
+// k = p + 1 Gauss-Lobatto nodes of [0, 1] at the k Gauss-Legendre points g_q, and the Gauss weights W[q].
+template <typename T>
+struct MfTables {
+  T B[4][4];
+  T G[4][4];
+  T W[4];
+};
+// Device description (pointers into the handle's buffers).  conn: ncells x nlocp internal DoFs per cell in
+// tensor order (x fastest; -1 for constrained DoFs and padding, nlocp = k^d rounded up to a multiple of 4).
+// Geometry, structure of arrays over cells: affine cells store C = |det J| J^-1 J^-T once per cell
+// (geo[c * ncells + e], c over the d(d+1)/2 entries of the upper triangle, row by row); general cells store
+// C_q = w_q |det J_q| J_q^-1 J_q^-T per Gauss point (geo[(q * ncomp + c) * ncells + e]).  inc_ptr / inc: per
+// internal DoF, the positions e * nlocp + a of its cell-local outputs in ascending order (empty for
+// constrained DoFs, whose row is cd[i] u_i).
+struct MfOp {
+  int d = 0, k = 0, n = 0, ncells = 0, nlocp = 0;
+  bool affine = false;
+  const int* conn = nullptr;
+  const int* inc_ptr = nullptr;
+  const int* inc = nullptr;
+};
+// t = A u by two launches (cell-local outputs Y, then per-DoF sums in a fixed order), followed by the epilogue
+// of launch_level (one right-hand side).
+template <typename T>
+void launch_mf_apply(const MfOp& m, const MfTables<T>& tb, const T* geo, const T* cd, T* Y, const T* dinv,
+                     const T* u, const T* b, T* rho, T* x, T* dout, double c1, double c2, int flags, const int* skip,
+                     hipStream_t s);
+
 // dense Cholesky (lower, in place, row-major n x n) and inverse; *bad set on a non-positive pivot
 void dense_cholesky_inverse(int n, double* A, double* Inv, int* bad, hipStream_t s);
 

@@ -19,22 +19,16 @@
 #include <stdexcept>
 #include <string>
 
+#include "hip_util.h"
 #include "kernels.h"
 
 namespace r3mg {
 
 namespace {
 
-constexpr int kXcd = 8;  // MI355X: 8 accelerator complex dies, workgroups dispatched round-robin
-
-// Logical block index with XCD-contiguous chunks: consecutive logical blocks (adjacent rows, spatially close
-// in the R-tree order) run on the same XCD and share its L2.  The grid must be kXcd * ceil(nlog / kXcd).
-__device__ inline int xcd_block(int nlog) {
-  int per = (nlog + kXcd - 1) / kXcd;
-  int lb = (int)(blockIdx.x % kXcd) * per + (int)(blockIdx.x / kXcd);
-  return lb < nlog ? lb : -1;
-}
-inline int xcd_grid(int nlog) { return kXcd * ((nlog + kXcd - 1) / kXcd); }
+using hiputil::check_launch;
+using hiputil::xcd_block;
+using hiputil::xcd_grid;
 
 template <typename T>
 struct Basis1D {
@@ -139,11 +133,6 @@ __device__ inline double block_sum256(double v, double* sh) {
   if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
   __syncthreads();
   return r;
-}
-
-void check_launch(const char* what) {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
 }
 
 }  // namespace

@@ -151,8 +151,38 @@ void bisection_rtree(const double* coords, int64_t n, int d, int leaf, int& dept
 void box_nodes_1d(int pc, double* t);
 
 // ---------------------------------------------------------------------------------------------
+// Matrix-free fine operator (host form; device layout described at MfOp in kernels.h)
+// ---------------------------------------------------------------------------------------------
+struct MatFreeHost {
+  int d = 0, p = 0, k = 0, nloc = 0, nlocp = 0, ncomp = 0, nq = 0;
+  int64_t ncells = 0;
+  bool affine = false;
+  std::vector<int32_t> conn;            // ncells x nlocp internal DoFs (-1: constrained or padding)
+  std::vector<double> geo;              // affine: ncomp x ncells; else (nq * ncomp) x ncells
+  std::vector<int32_t> inc_ptr, inc;    // per internal DoF: cell-local output positions, ascending
+  std::vector<double> cd;               // diagonal of constrained rows (0 elsewhere)
+  double B[4][4], G[4][4], W[4];        // 1D tables (MfTables)
+};
+// cells: host ncells x (p+1)^d caller indices in tensor order (x fastest); kappa: host ncells or null
+MatFreeHost build_matrix_free(const Analysis& an, const int32_t* cells, int64_t ncells, int p, const double* kappa);
+
+// ---------------------------------------------------------------------------------------------
 // Device hierarchy
 // ---------------------------------------------------------------------------------------------
+struct MatFreeDev {
+  bool on = false;
+  MfOp op;
+  bool affine = false;
+  int p = 0;
+  int64_t nincid = 0;
+  DBuf<int32_t> conn, inc_ptr, inc;
+  DBuf<double> geo64, cd64, y64;
+  DBuf<float> geo32, cd32, y32;
+  MfTables<float> t32;
+  MfTables<double> t64;
+  double bytes32 = 0, bytes64 = 0;  // algorithmic bytes of one application (7 vector streams included)
+};
+
 struct DevLevel {
   int64_t n = 0, nbox = 0;
   int64_t nnz = 0;
@@ -187,6 +217,7 @@ struct DevLevel {
   DBuf<char> b, x, rho, dA, dB;
   int64_t vec_cap = 0;
   double bytes_apply = 0;
+  const MatFreeDev* mf = nullptr;  // l = 0: matrix-free operator in use for one right-hand side (null: CSR)
 };
 
 struct PcgScalars;  // device-side PCG state (defined in the solver)
@@ -216,6 +247,7 @@ struct Device {
   hipEvent_t ev[2] = {nullptr, nullptr};
   // autotuned SpMM lanes per (level, nrhs)
   std::map<std::pair<int, int>, int> tuned;
+  MatFreeDev mf;
   ~Device();
 };
 
@@ -227,7 +259,7 @@ struct HandleImpl {
 };
 
 // kernel family that applies a level operator (solver.cpp chooses; r3mg_info reports it)
-enum class LevelKernel { Stream, BlockRowWG, BlockRow, Lanes };
+enum class LevelKernel { Stream, BlockRowWG, BlockRow, Lanes, MatFree };
 LevelKernel level_kernel(const Analysis& an, const DevLevel& D, int l, int nr, int esz);
 std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int esz);
 
@@ -242,6 +274,9 @@ r3mg_status pcg_solve(HandleImpl& h, const double* b, double* x, int nrhs, doubl
 r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double* const* x, double rtol, int maxit,
                       hipStream_t s, int* iters, double* relres);
 void time_smoother_kernel(HandleImpl& h, int level, int reps, hipStream_t s, double* ms, double* bytes);
+// matrix-free fine operator: upload, check against the CSR operator, switch level 0 to it; detach returns to CSR
+void attach_matrix_free(HandleImpl& h, MatFreeHost&& m, hipStream_t s);
+void detach_matrix_free(HandleImpl& h);
 
 }  // namespace r3mg
 

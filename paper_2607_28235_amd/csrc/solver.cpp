@@ -189,6 +189,7 @@ constexpr int kCodeSplit = 100;
 // level for one right-hand side, a block-row kernel on coarse levels whose block rows fit LDS, the
 // lanes-per-row kernel otherwise.
 LevelKernel level_kernel(const Analysis& an, const DevLevel& D, int l, int nr, int esz) {
+  if (l == 0 && nr == 1 && D.mf) return LevelKernel::MatFree;
   if (nr == 1 && D.fb[D.shape].nrb > 0 && (l == 0 || D.shape == kLocalFirst + kLocalGeoms)) return LevelKernel::Stream;
   if (l > 0 && nr == 1 && D.maxnb > 0 && an.B >= 8 && (int64_t)D.maxnb * an.B >= 256 &&
       (int64_t)D.maxnb * an.B * esz <= 65536)
@@ -210,6 +211,9 @@ std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int 
       }
       return std::string("k_level_stream<") + t + "," + std::to_string(kStreamCapOf[D.shape % kCsrGeoms]) + "," +
              std::to_string(kStreamRowsOf[D.shape % kCsrGeoms]) + (D.shape >= kCsrGeoms ? ",pipe16>" : ",block>");
+    case LevelKernel::MatFree:
+      return std::string("k_mf_cell<") + t + "," + std::to_string(D.mf->op.d) + "D,Q" + std::to_string(D.mf->p) +
+             (D.mf->affine ? ",affine>" : ",multilinear>") + "+k_mf_gather<" + t + ">";
     case LevelKernel::BlockRowWG: return std::string("k_level_blockrow_wg<") + t + ">";
     case LevelKernel::BlockRow: return std::string("k_level_blockrow<") + t + ">";
     default: return std::string("k_level<") + t + ">";
@@ -222,6 +226,16 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
   LevelOp<T> op = level_op<T>(c, l);
   DevLevel& D = c.dv.lv[l];
   switch (level_kernel(c.an, D, l, nr, (int)sizeof(T))) {
+    case LevelKernel::MatFree: {
+      const MatFreeDev& F = *D.mf;
+      if constexpr (sizeof(T) == 4)
+        launch_mf_apply<float>(F.op, F.t32, F.geo32.p, F.cd32.p, F.y32.p, op.dinv, u, b, rho, x,
+                               dout, c1, c2, flags, skip, s);
+      else
+        launch_mf_apply<double>(F.op, F.t64, F.geo64.p, F.cd64.p, F.y64.p, op.dinv, u, b, rho,
+                                x, dout, c1, c2, flags, skip, s);
+      break;
+    }
     case LevelKernel::Stream:
       op.ptr = D.rowptr.p;  // CSR row pointers (coarse levels: of the block-row layout)
       op.idx = D.col.p;     // CSR columns (fine level only; coarse rows never take the long-row path)
@@ -839,6 +853,7 @@ void device_setup(HandleImpl& h, hipStream_t s) {
 }
 
 void update_values(HandleImpl& h, const double* vals_dev, hipStream_t s) {
+  detach_matrix_free(h);  // the cell description no longer matches the new values
   Device& dv = *h.dev;
   launch_gather_vals(h.an->nnz, dv.src.p, vals_dev, dv.lv[0].val64.p, s);
   numeric_setup(h, s);
@@ -929,7 +944,11 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
   const int n = (int)an.n;
   need_partials(dv, (int64_t)((n + 255) / 256) * 2 * NR);
   int np;
-  if (NR == 1 && D0.fb[D0.shape].nrb > 0) {
+  if (NR == 1 && D0.mf) {
+    // q = A p with the matrix-free operator, then <p, q> in the fixed partition
+    apply_level<double>(c, 0, 1, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
+    np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+  } else if (NR == 1 && D0.fb[D0.shape].nrb > 0) {
     // q = A p with the fine row-block kernel, then <p, q> in a fixed partition: the iterates do not depend on
     // the kernel shape chosen by timing
     launch_level_stream<double>(D0.shape, D0.fb[D0.shape], op64, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0,
@@ -1257,6 +1276,116 @@ r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double
     cleanup();
     throw;
   }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Matrix-free fine operator
+// ---------------------------------------------------------------------------------------------
+void detach_matrix_free(HandleImpl& h) {
+  if (!h.dev) return;
+  Device& dv = *h.dev;
+  DevLevel& D0 = dv.lv[0];
+  const bool was_on = D0.mf != nullptr;
+  D0.mf = nullptr;
+  D0.bytes_apply = D0.shape_bytes[D0.shape];
+  MatFreeDev& F = dv.mf;
+  F.on = false;
+  F.conn.release();
+  F.inc_ptr.release();
+  F.inc.release();
+  F.geo64.release();
+  F.cd64.release();
+  F.y64.release();
+  F.geo32.release();
+  F.cd32.release();
+  F.y32.release();
+  if (was_on) drop_graphs(dv);
+}
+
+void attach_matrix_free(HandleImpl& h, MatFreeHost&& m, hipStream_t s) {
+  detach_matrix_free(h);
+  Analysis& an = *h.an;
+  Device& dv = *h.dev;
+  Ctx c{an, dv, an.opt.vcycle_fp32 != 0};
+  MatFreeDev& F = dv.mf;
+  const int64_t n = an.n;
+  try {
+    F.conn.upload(m.conn, s);
+    F.inc_ptr.upload(m.inc_ptr, s);
+    F.inc.upload(m.inc, s);
+    F.geo64.upload(m.geo, s);
+    F.cd64.upload(m.cd, s);
+    F.y64.alloc((size_t)m.ncells * m.nlocp);
+    if (c.fp32) {
+      F.geo32.alloc(m.geo.size());
+      launch_cast_d2f((int64_t)m.geo.size(), F.geo64.p, F.geo32.p, s);
+      F.cd32.alloc(n);
+      launch_cast_d2f(n, F.cd64.p, F.cd32.p, s);
+      F.y32.alloc((size_t)m.ncells * m.nlocp);
+    }
+    F.affine = m.affine;
+    F.p = m.p;
+    F.nincid = (int64_t)m.inc.size();
+    F.op.d = m.d;
+    F.op.k = m.k;
+    F.op.n = (int)n;
+    F.op.ncells = (int)m.ncells;
+    F.op.nlocp = m.nlocp;
+    F.op.affine = m.affine;
+    F.op.conn = F.conn.p;
+    F.op.inc_ptr = F.inc_ptr.p;
+    F.op.inc = F.inc.p;
+    for (int q = 0; q < 4; ++q) {
+      F.t64.W[q] = m.W[q];
+      F.t32.W[q] = (float)m.W[q];
+      for (int i = 0; i < 4; ++i) {
+        F.t64.B[q][i] = m.B[q][i];
+        F.t64.G[q][i] = m.G[q][i];
+        F.t32.B[q][i] = (float)m.B[q][i];
+        F.t32.G[q][i] = (float)m.G[q][i];
+      }
+    }
+    // algorithmic bytes: connectivity, geometry, cell-local outputs written and read back, incidence lists,
+    // 7 vector streams (as for the CSR kernels)
+    for (int sv = 4; sv <= 8; sv += 4) {
+      const double by = (double)m.ncells * m.nloc * 4 + (double)m.geo.size() * sv +
+                        (double)m.ncells * m.nloc * sv + (double)(n + 1) * 4 + (double)F.nincid * (4 + sv) +
+                        7.0 * n * sv;
+      (sv == 4 ? F.bytes32 : F.bytes64) = by;
+    }
+    // the operator must reproduce the caller's matrix: y = A v for a fixed pseudo-random v, both ways
+    ensure_pcg_vectors(c, 1);
+    std::vector<double> v(n), y1(n), y2(n);
+    for (int64_t i = 0; i < n; ++i) v[i] = (double)((uint32_t)((uint64_t)i * 2654435761u)) / 4294967296.0 - 0.5;
+    R3MG_HIP_CHECK(hipMemcpyAsync(dv.pb.p, v.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_level<double>(level_op<double>(c, 0), 1, dv.pb.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN,
+                         nullptr, s);
+    launch_mf_apply<double>(F.op, F.t64, F.geo64.p, F.cd64.p, F.y64.p, dv.lv[0].dinv64.p, dv.pb.p, nullptr,
+                            dv.pz.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, nullptr, s);
+    R3MG_HIP_CHECK(hipMemcpyAsync(y1.data(), dv.pq.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    R3MG_HIP_CHECK(hipMemcpyAsync(y2.data(), dv.pz.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    R3MG_HIP_CHECK(hipStreamSynchronize(s));
+    double ymax = 0.0, dmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      ymax = std::max(ymax, std::fabs(y1[i]));
+      dmax = std::max(dmax, std::fabs(y1[i] - y2[i]));
+    }
+    if (!(dmax <= 1e-10 * ymax)) {
+      char msg[160];
+      snprintf(msg, sizeof msg,
+               "matrix-free operator does not reproduce the matrix (max |difference| %.3e, max |A v| %.3e)", dmax,
+               ymax);
+      throw Error{R3MG_ERR_INVALID, msg};
+    }
+  } catch (...) {
+    detach_matrix_free(h);
+    throw;
+  }
+  F.on = true;
+  DevLevel& D0 = dv.lv[0];
+  D0.mf = &F;
+  D0.bytes_apply = c.fp32 ? F.bytes32 : F.bytes64;
+  drop_graphs(dv);
 }
 
 void time_smoother_kernel(HandleImpl& h, int level, int reps, hipStream_t s, double* ms, double* bytes) {
