@@ -174,20 +174,23 @@ void launch_lanczos_u(int64_t n, const double* dinv, const double* Av, double be
 
 // ---- matrix-free fine operator: the Q_p Laplace stiffness action on multilinear cells ----
 // 1D tables of the cell kernel: B[q][i] = l_i(g_q) and G[q][i] = l_i'(g_q) for the Lagrange basis l_i on the
-// k = p + 1 Gauss-Lobatto nodes of [0, 1] at the k Gauss-Legendre points g_q, and the Gauss weights W[q].
+// k = p + 1 Gauss-Lobatto nodes of [0, 1] at the k Gauss-Legendre points g_q = X[q], and the Gauss weights W[q].
 template <typename T>
 struct MfTables {
   T B[4][4];
   T G[4][4];
   T W[4];
+  T X[4];
 };
 // Device description (pointers into the handle's buffers).  conn: ncells x nlocp internal DoFs per cell in
 // tensor order (x fastest; -1 for constrained DoFs and padding, nlocp = k^d rounded up to a multiple of 4).
-// Geometry, structure of arrays over cells: affine cells store C = |det J| J^-1 J^-T once per cell
-// (geo[c * ncells + e], c over the d(d+1)/2 entries of the upper triangle, row by row); general cells store
-// C_q = w_q |det J_q| J_q^-1 J_q^-T per Gauss point (geo[(q * ncomp + c) * ncells + e]).  inc_ptr / inc: per
-// internal DoF, the positions e * nlocp + a of its cell-local outputs in ascending order (empty for
-// constrained DoFs, whose row is cd[i] u_i).
+// Geometry, structure of arrays over cells (plane c at geo[c * ncells + e]):
+//   affine cells:      C = kappa |det J| J^-1 J^-T (the d(d+1)/2 entries of the upper triangle, row by row);
+//   multilinear cells: the coefficients of the map's derivative, x(xi) = sum over subsets S of the axes of
+//                      c_S prod_{a in S} xi_a: 2D c_1, c_2, c_12 (2 values each), 3D c_1, c_2, c_3, c_12, c_13,
+//                      c_23, c_123 (3 values each), then kappa; C at a Gauss point is kappa adj(J) adj(J)^T / det J.
+// inc_ptr / inc: per internal DoF, the positions e * nlocp + a of its cell-local outputs in ascending order
+// (empty for constrained DoFs, whose row is cd[i] u_i).
 struct MfOp {
   int d = 0, k = 0, n = 0, ncells = 0, nlocp = 0;
   bool affine = false;

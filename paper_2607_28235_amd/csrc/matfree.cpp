@@ -95,6 +95,7 @@ MatFreeHost build_matrix_free(const Analysis& an, const int32_t* cells, int64_t 
   gauss_01(k, g, w);
   for (int q = 0; q < 4; ++q) {
     m.W[q] = q < k ? w[q] : 0.0;
+    m.X[q] = q < k ? g[q] : 0.0;
     for (int i = 0; i < 4; ++i) m.B[q][i] = m.G[q][i] = 0.0;
   }
   for (int q = 0; q < k; ++q) lagrange(k, t, g[q], m.B[q], m.G[q]);
@@ -120,10 +121,13 @@ MatFreeHost build_matrix_free(const Analysis& an, const int32_t* cells, int64_t 
   for (int64_t i = 0; i < n; ++i)
     if (!an.constrained[i] && cnt[i] == 0) throw invalid("matrix-free operator: an unconstrained DoF is in no cell");
 
-  // geometry at the Gauss points: J = sum_v X_v (grad psi_v)^T over the 2^d corner nodes
+  // geometry at the Gauss points: J = sum_v X_v (grad psi_v)^T over the 2^d corner nodes.  Affine cells keep
+  // C = kappa |det J| J^-1 J^-T; multilinear cells keep the coefficients c_S of x(xi) = sum_S c_S prod_{a in S}
+  // xi_a for the non-empty subsets S (c_S = sum over corners v inside S of (-1)^{|S| - |v|} X_v) and kappa.
   const int nv = 1 << d;
+  const int ncoef = d == 2 ? 7 : 22;
   std::vector<double> Jq((size_t)m.nq * 9);
-  std::vector<double> geo_q((size_t)ncells * m.nq * m.ncomp), geo_a((size_t)ncells * m.ncomp);
+  std::vector<double> geo_c((size_t)ncells * ncoef), geo_a((size_t)ncells * m.ncomp);
   bool affine = true;
   for (int64_t s = 0; s < ncells; ++s) {
     const int64_t e = ord[s];
@@ -138,10 +142,29 @@ MatFreeHost build_matrix_free(const Analysis& an, const int32_t* cells, int64_t 
       for (int ax = 0; ax < d; ++ax) X[v][ax] = an.coords_int[(int64_t)i * d + ax];
     }
     const double kap = kappa ? kappa[e] : 1.0;
+    {
+      // subsets in the order 1, 2, (3,) 12, (13, 23, 123) of the axes, as bit masks over the corner index bits
+      static const int sub2[3] = {1, 2, 3};
+      static const int sub3[7] = {1, 2, 4, 3, 5, 6, 7};
+      const int* sub = d == 2 ? sub2 : sub3;
+      const int nsub = d == 2 ? 3 : 7;
+      for (int t2 = 0; t2 < nsub; ++t2) {
+        const int S = sub[t2];
+        for (int ax = 0; ax < d; ++ax) {
+          double acc = 0.0;
+          for (int v = 0; v < nv; ++v) {
+            if ((v & ~S) != 0) continue;
+            const int sgn = (__builtin_popcount(S) - __builtin_popcount(v)) & 1 ? -1 : 1;
+            acc += sgn * X[v][ax];
+          }
+          geo_c[((size_t)t2 * d + ax) * ncells + s] = acc;
+        }
+      }
+      geo_c[(size_t)(ncoef - 1) * ncells + s] = kap;
+    }
     double jmax = 0.0, jdiff = 0.0;
     for (int q = 0; q < m.nq; ++q) {
       double xi[3] = {g[q % k], g[(q / k) % k], d == 3 ? g[q / (k * k)] : 0.0};
-      double wq = w[q % k] * w[(q / k) % k] * (d == 3 ? w[q / (k * k)] : 1.0);
       double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // J[i][c] = dx_i / dxi_c
       for (int v = 0; v < nv; ++v)
         for (int c = 0; c < d; ++c) {
@@ -186,16 +209,14 @@ MatFreeHost build_matrix_free(const Analysis& an, const int32_t* cells, int64_t 
         for (int s2 = r; s2 < d; ++s2) {
           double acc = 0.0;
           for (int i = 0; i < d; ++i) acc += inv[r][i] * inv[s2][i];
-          const double v = kap * det * acc;
-          if (q == 0) geo_a[(size_t)c * ncells + s] = v;
-          geo_q[((size_t)q * m.ncomp + c) * ncells + s] = wq * v;
+          if (q == 0) geo_a[(size_t)c * ncells + s] = kap * det * acc;
           ++c;
         }
     }
     if (jdiff > 1e-12 * jmax) affine = false;
   }
   m.affine = affine;
-  m.geo = affine ? std::move(geo_a) : std::move(geo_q);
+  m.geo = affine ? std::move(geo_a) : std::move(geo_c);
 
   // connectivity (constrained DoFs -> -1) and incidence lists in ascending (cell, node) order
   m.conn.assign((size_t)ncells * m.nlocp, -1);

@@ -5,12 +5,15 @@
 //
 // Two launches, both deterministic (no floating-point atomics):
 //   k_mf_cell    one thread per cell: gather u_e, y_e = K_e u_e by sum factorisation (one Gauss-point slice at
-//                a time along the last axis, which bounds the registers), store y_e to the cell-local buffer Y;
+//                a time along the last axis, which bounds the registers; the geometric factors of multilinear
+//                cells evaluated at each Gauss point from the map's coefficients), store y_e to the cell-local
+//                buffer Y;
 //   k_mf_gather  one thread per DoF: t_i = sum of its cell-local outputs in ascending (cell, node) order, then
 //                the smoother epilogue of the CSR level kernels.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <stdexcept>
 
 #include "hip_util.h"
 #include "kernels.h"
@@ -23,42 +26,121 @@ using hiputil::check_launch;
 using hiputil::xcd_block;
 using hiputil::xcd_grid;
 
-// geometry entry c of Gauss point q (pre-scaled by the Gauss weight on general cells)
-template <typename T, int NC, bool AFF>
-__device__ inline T geo_at(const T* __restrict__ geo, const T* ca, int ncells, int e, int q, int c, T w) {
-  if constexpr (AFF)
-    return w * ca[c];
-  else
-    return geo[(int64_t)(q * NC + c) * ncells + e];
+// Geometry at one Gauss point: the upper triangle of C = w kappa adj(J) adj(J)^T / det J.  Affine cells store
+// kappa |det J| J^-1 J^-T per cell; multilinear cells store the map's derivative coefficients.
+template <typename T, int D, bool AFF>
+__device__ inline void geo_point(const T* gm, T w, T x1, T x2, T x3, T* c) {
+  if constexpr (AFF) {
+#pragma unroll
+    for (int k = 0; k < (D == 2 ? 3 : 6); ++k) c[k] = w * gm[k];
+  } else if constexpr (D == 2) {
+    // columns of J: dx/dxi1 = c_1 + xi2 c_12, dx/dxi2 = c_2 + xi1 c_12
+    const T a = gm[0] + x2 * gm[4], cc = gm[1] + x2 * gm[5];
+    const T b = gm[2] + x1 * gm[4], d = gm[3] + x1 * gm[5];
+    const T s = w * gm[6] / (a * d - b * cc);
+    c[0] = s * (b * b + d * d);
+    c[1] = -s * (a * b + cc * d);
+    c[2] = s * (a * a + cc * cc);
+  } else {
+    T j0[3], j1[3], j2[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      j0[i] = gm[i] + x2 * gm[9 + i] + x3 * (gm[12 + i] + x2 * gm[18 + i]);
+      j1[i] = gm[3 + i] + x1 * gm[9 + i] + x3 * (gm[15 + i] + x1 * gm[18 + i]);
+      j2[i] = gm[6 + i] + x1 * gm[12 + i] + x2 * (gm[15 + i] + x1 * gm[18 + i]);
+    }
+    // rows of adj(J) = det J^-1: j1 x j2, j2 x j0, j0 x j1
+    T m[3][3];
+    m[0][0] = j1[1] * j2[2] - j1[2] * j2[1];
+    m[0][1] = j1[2] * j2[0] - j1[0] * j2[2];
+    m[0][2] = j1[0] * j2[1] - j1[1] * j2[0];
+    m[1][0] = j2[1] * j0[2] - j2[2] * j0[1];
+    m[1][1] = j2[2] * j0[0] - j2[0] * j0[2];
+    m[1][2] = j2[0] * j0[1] - j2[1] * j0[0];
+    m[2][0] = j0[1] * j1[2] - j0[2] * j1[1];
+    m[2][1] = j0[2] * j1[0] - j0[0] * j1[2];
+    m[2][2] = j0[0] * j1[1] - j0[1] * j1[0];
+    const T det = j0[0] * m[0][0] + j0[1] * m[0][1] + j0[2] * m[0][2];
+    const T s = w * gm[21] / det;
+    int k = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int t = r; t < 3; ++t) c[k++] = s * (m[r][0] * m[t][0] + m[r][1] * m[t][1] + m[r][2] * m[t][2]);
+  }
 }
 
+// One thread per cell.  When a wave's connectivity and outputs fit LDS (256 cells x nlocp entries <= 64 KiB),
+// both are staged through it so that the global loads and stores are contiguous 16-byte accesses.
 template <typename T, int D, int K, bool AFF>
-__global__ __launch_bounds__(256) void k_mf_cell(int ncells, int nlocp, const int* __restrict__ conn,
-                                                 const T* __restrict__ geo, MfTables<T> tb,
-                                                 const T* __restrict__ u, T* __restrict__ Y,
+__global__ __launch_bounds__(256) void k_mf_cell(int ncells, const int* __restrict__ conn, const T* __restrict__ geo,
+                                                 MfTables<T> tb, const T* __restrict__ u, T* __restrict__ Y,
                                                  const int* __restrict__ skip, int nlog) {
-  if (skip && *skip) return;
-  const int lb = xcd_block(nlog);
-  if (lb < 0) return;
-  const int e = lb * 256 + (int)threadIdx.x;
-  if (e >= ncells) return;
   constexpr int NL = D == 2 ? K * K : K * K * K;
   constexpr int NP = (NL + 3) / 4 * 4;
   constexpr int NC = D == 2 ? 3 : 6;
-  // gather u_e (constrained DoFs and padding read as zero)
-  T ue[NL];
-  const int* cp = conn + (int64_t)e * nlocp;
+  constexpr int NG = AFF ? NC : (D == 2 ? 7 : 22);
+  constexpr int ES = sizeof(T) > 4 ? (int)sizeof(T) : 4;
+  constexpr bool STAGE = 256 * NP * ES <= 65536;
+  constexpr int VW = 16 / (int)sizeof(T);
+  typedef T V16 __attribute__((ext_vector_type(VW)));
+  __shared__ __attribute__((aligned(16))) char lds[STAGE ? 256 * NP * ES : 16];
+  if (skip && *skip) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  const int e = lb * 256 + (int)threadIdx.x;
+  const bool valid = e < ncells;
+  const int64_t total = (int64_t)ncells * NP;
+  const int64_t wbase = (int64_t)(lb * 256 + wv * 64) * NP;  // first entry of this wave's cells
+  char* wlds = lds + wv * 64 * NP * ES;
+
+  int cidx[NP];
+  if constexpr (STAGE) {
+    int* li = reinterpret_cast<int*>(wlds);
 #pragma unroll
-  for (int a4 = 0; a4 < NP / 4; ++a4) {
-    const int4 c4 = *reinterpret_cast<const int4*>(cp + 4 * a4);
-    const int cc[4] = {c4.x, c4.y, c4.z, c4.w};
+    for (int j = 0; j < NP / 4; ++j) {
+      const int q = j * 64 + lane;
+      const int64_t off = wbase + 4 * (int64_t)q;
+      int4 c4 = make_int4(-1, -1, -1, -1);
+      if (off < total) c4 = *reinterpret_cast<const int4*>(conn + off);
+      *reinterpret_cast<int4*>(li + 4 * q) = c4;
+    }
+    __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-      if (4 * a4 + m < NL) ue[4 * a4 + m] = cc[m] >= 0 ? u[cc[m]] : (T)0;
+    for (int a4 = 0; a4 < NP / 4; ++a4) {
+      const int4 c4 = *reinterpret_cast<const int4*>(li + lane * NP + 4 * a4);
+      cidx[4 * a4] = c4.x;
+      cidx[4 * a4 + 1] = c4.y;
+      cidx[4 * a4 + 2] = c4.z;
+      cidx[4 * a4 + 3] = c4.w;
+    }
+  } else {
+#pragma unroll
+    for (int a4 = 0; a4 < NP / 4; ++a4) {
+      int4 c4 = make_int4(-1, -1, -1, -1);
+      if (valid) c4 = *reinterpret_cast<const int4*>(conn + (int64_t)e * NP + 4 * a4);
+      cidx[4 * a4] = c4.x;
+      cidx[4 * a4 + 1] = c4.y;
+      cidx[4 * a4 + 2] = c4.z;
+      cidx[4 * a4 + 3] = c4.w;
+    }
   }
-  T ca[NC];
+  // gather u_e (constrained DoFs, padding and cells past the end read as zero)
+  T ue[NL];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) ca[c] = AFF ? geo[(int64_t)c * ncells + e] : (T)0;
+  for (int a = 0; a < NL; ++a) ue[a] = cidx[a] >= 0 ? u[cidx[a]] : (T)0;
+  T gm[NG];
+#pragma unroll
+  for (int c = 0; c < NG; ++c) gm[c] = valid ? geo[(int64_t)c * ncells + e] : (T)(c == NG - 1 ? 1 : 0);
+  if constexpr (!AFF) {
+    if (!valid) {  // a harmless unit square / cube for the idle lanes
+#pragma unroll
+      for (int c = 0; c < NG; ++c) gm[c] = 0;
+      if constexpr (D == 2) { gm[0] = 1; gm[3] = 1; gm[6] = 1; }
+      else { gm[0] = 1; gm[4] = 1; gm[8] = 1; gm[21] = 1; }
+    }
+  }
   T v[NL];
 #pragma unroll
   for (int a = 0; a < NL; ++a) v[a] = 0;
@@ -88,13 +170,10 @@ __global__ __launch_bounds__(256) void k_mf_cell(int ncells, int nlocp, const in
           gx += tb.G[qx][ix] * z0[ix];
           gy += tb.B[qx][ix] * z1[ix];
         }
-        const int q = qx + K * qy;
-        const T w = AFF ? tb.W[qx] * tb.W[qy] : (T)1;
-        const T c00 = geo_at<T, NC, AFF>(geo, ca, ncells, e, q, 0, w);
-        const T c01 = geo_at<T, NC, AFF>(geo, ca, ncells, e, q, 1, w);
-        const T c11 = geo_at<T, NC, AFF>(geo, ca, ncells, e, q, 2, w);
-        fx[qx] = c00 * gx + c01 * gy;
-        fy[qx] = c01 * gx + c11 * gy;
+        T c[3];
+        geo_point<T, 2, AFF>(gm, tb.W[qx] * tb.W[qy], tb.X[qx], tb.X[qy], (T)0, c);
+        fx[qx] = c[0] * gx + c[1] * gy;
+        fy[qx] = c[1] * gx + c[2] * gy;
       }
       // transposed contractions back to the nodes
 #pragma unroll
@@ -154,17 +233,11 @@ __global__ __launch_bounds__(256) void k_mf_cell(int ncells, int nlocp, const in
             gy += tb.B[qx][ix] * y01[ix];
             gz += tb.B[qx][ix] * y10[ix];
           }
-          const int q = qx + K * qy + K * K * qz;
-          const T w = AFF ? tb.W[qx] * tb.W[qy] * tb.W[qz] : (T)1;
-          const T c00 = geo_at<T, NC, AFF>(geo, ca, ncells, e, q, 0, w);
-          const T c01 = geo_at<T, NC, AFF>(geo, ca, ncells, e, q, 1, w);
-          const T c02 = geo_at<T, NC, AFF>(geo, ca, ncells, e, q, 2, w);
-          const T c11 = geo_at<T, NC, AFF>(geo, ca, ncells, e, q, 3, w);
-          const T c12 = geo_at<T, NC, AFF>(geo, ca, ncells, e, q, 4, w);
-          const T c22 = geo_at<T, NC, AFF>(geo, ca, ncells, e, q, 5, w);
-          fx[qx] = c00 * gx + c01 * gy + c02 * gz;
-          fy[qx] = c01 * gx + c11 * gy + c12 * gz;
-          fz[qx] = c02 * gx + c12 * gy + c22 * gz;
+          T c[6];
+          geo_point<T, 3, AFF>(gm, tb.W[qx] * tb.W[qy] * tb.W[qz], tb.X[qx], tb.X[qy], tb.X[qz], c);
+          fx[qx] = c[0] * gx + c[1] * gy + c[2] * gz;
+          fy[qx] = c[1] * gx + c[3] * gy + c[4] * gz;
+          fz[qx] = c[2] * gx + c[4] * gy + c[5] * gz;
         }
 #pragma unroll
         for (int ix = 0; ix < K; ++ix) {
@@ -189,16 +262,34 @@ __global__ __launch_bounds__(256) void k_mf_cell(int ncells, int nlocp, const in
     }
   }
 
-  // store y_e (16-byte stores; padding entries are written as zero)
-  constexpr int VW = 16 / (int)sizeof(T);
-  typedef T V16 __attribute__((ext_vector_type(VW)));
-  T* yp = Y + (int64_t)e * nlocp;
+  // store y_e (padding entries are written as zero)
+  if constexpr (STAGE) {
+    T* lt = reinterpret_cast<T*>(wlds);
+    __syncthreads();  // every lane has read its connectivity: the tile now holds outputs
 #pragma unroll
-  for (int a0 = 0; a0 < NP; a0 += VW) {
-    V16 t;
+    for (int a0 = 0; a0 < NP; a0 += VW) {
+      V16 t;
 #pragma unroll
-    for (int m = 0; m < VW; ++m) t[m] = (a0 + m < NL) ? v[a0 + m] : (T)0;
-    *reinterpret_cast<V16*>(yp + a0) = t;
+      for (int m = 0; m < VW; ++m) t[m] = (a0 + m < NL) ? v[a0 + m] : (T)0;
+      *reinterpret_cast<V16*>(lt + lane * NP + a0) = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NP / VW; ++j) {
+      const int q = j * 64 + lane;
+      const int64_t off = wbase + (int64_t)VW * q;
+      if (off < total) *reinterpret_cast<V16*>(Y + off) = *reinterpret_cast<const V16*>(lt + VW * q);
+    }
+  } else {
+    if (!valid) return;
+    T* yp = Y + (int64_t)e * NP;
+#pragma unroll
+    for (int a0 = 0; a0 < NP; a0 += VW) {
+      V16 t;
+#pragma unroll
+      for (int m = 0; m < VW; ++m) t[m] = (a0 + m < NL) ? v[a0 + m] : (T)0;
+      *reinterpret_cast<V16*>(yp + a0) = t;
+    }
   }
 }
 
@@ -247,12 +338,14 @@ template <typename T, int D, int K>
 void launch_cell(const MfOp& m, const MfTables<T>& tb, const T* geo, const T* u, T* Y, const int* skip,
                  hipStream_t s) {
   const int nlog = (m.ncells + 255) / 256;
+  constexpr int NL = D == 2 ? K * K : K * K * K;
+  if (m.nlocp != (NL + 3) / 4 * 4) throw std::runtime_error("matrix-free operator: connectivity stride mismatch");
   if (m.affine)
-    hipLaunchKernelGGL((k_mf_cell<T, D, K, true>), dim3(xcd_grid(nlog)), dim3(256), 0, s, m.ncells, m.nlocp, m.conn,
-                       geo, tb, u, Y, skip, nlog);
+    hipLaunchKernelGGL((k_mf_cell<T, D, K, true>), dim3(xcd_grid(nlog)), dim3(256), 0, s, m.ncells, m.conn, geo, tb,
+                       u, Y, skip, nlog);
   else
-    hipLaunchKernelGGL((k_mf_cell<T, D, K, false>), dim3(xcd_grid(nlog)), dim3(256), 0, s, m.ncells, m.nlocp,
-                       m.conn, geo, tb, u, Y, skip, nlog);
+    hipLaunchKernelGGL((k_mf_cell<T, D, K, false>), dim3(xcd_grid(nlog)), dim3(256), 0, s, m.ncells, m.conn, geo,
+                       tb, u, Y, skip, nlog);
 }
 
 }  // namespace

@@ -158,10 +158,10 @@ struct MatFreeHost {
   int64_t ncells = 0;
   bool affine = false;
   std::vector<int32_t> conn;            // ncells x nlocp internal DoFs (-1: constrained or padding)
-  std::vector<double> geo;              // affine: ncomp x ncells; else (nq * ncomp) x ncells
+  std::vector<double> geo;              // affine: ncomp x ncells; multilinear: map coefficients and kappa
   std::vector<int32_t> inc_ptr, inc;    // per internal DoF: cell-local output positions, ascending
   std::vector<double> cd;               // diagonal of constrained rows (0 elsewhere)
-  double B[4][4], G[4][4], W[4];        // 1D tables (MfTables)
+  double B[4][4], G[4][4], W[4], X[4];  // 1D tables (MfTables)
 };
 // cells: host ncells x (p+1)^d caller indices in tensor order (x fastest); kappa: host ncells or null
 MatFreeHost build_matrix_free(const Analysis& an, const int32_t* cells, int64_t ncells, int p, const double* kappa);

@@ -1338,6 +1338,8 @@ void attach_matrix_free(HandleImpl& h, MatFreeHost&& m, hipStream_t s) {
     for (int q = 0; q < 4; ++q) {
       F.t64.W[q] = m.W[q];
       F.t32.W[q] = (float)m.W[q];
+      F.t64.X[q] = m.X[q];
+      F.t32.X[q] = (float)m.X[q];
       for (int i = 0; i < 4; ++i) {
         F.t64.B[q][i] = m.B[q][i];
         F.t64.G[q][i] = m.G[q][i];
