@@ -243,7 +243,9 @@ struct Device {
   std::map<int, hipGraphExec_t> graphs;
   std::map<int, hipGraph_t> graph_defs;
   hipStream_t cap_stream = nullptr;
-  void* pinned = nullptr;  // host pinned buffer: PcgState copy + two convergence-flag slots
+  void* pinned = nullptr;  // host pinned buffer: PcgState copy + two per-iteration PcgState snapshots
+  void* pinned_part = nullptr;  // host pinned buffer: reduction partials read back after a solve
+  size_t pinned_part_bytes = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
   // autotuned SpMM lanes per (level, nrhs)
   std::map<std::pair<int, int>, int> tuned;

@@ -147,6 +147,7 @@ Device::~Device() {
     if (e) (void)hipEventDestroy(e);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (pinned) (void)hipHostFree(pinned);
+  if (pinned_part) (void)hipHostFree(pinned_part);
 }
 
 struct Ctx {
@@ -317,7 +318,8 @@ static void ensure_pcg_vectors(Ctx& c, int nr) {
     dv.state.alloc(sizeof(PcgState));
     R3MG_HIP_CHECK(hipMemset(dv.state.p, 0, sizeof(PcgState)));
   }
-  if (!dv.pinned) R3MG_HIP_CHECK(hipHostMalloc(&dv.pinned, sizeof(PcgState) + 64, hipHostMallocDefault));
+  // pinned host memory: one PcgState for reads of the state, then the two per-iteration snapshot slots
+  if (!dv.pinned) R3MG_HIP_CHECK(hipHostMalloc(&dv.pinned, 3 * sizeof(PcgState) + 64, hipHostMallocDefault));
 }
 
 // Multi-RHS SpMM tile autotuner: the lanes-per-row tile of every level kernel (and of PCG's float64 SpMV) is
@@ -1087,49 +1089,84 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
   const bool flexible = sizeof(T) == 4;
   launch_gather_cols(n, NR, nb, dv.perm.p, b + (int64_t)c0 * n, n, dv.pb.p, s);
   launch_gather_cols(n, NR, nb, dv.perm.p, x + (int64_t)c0 * n, n, dv.px.p, s);
-  int restarts = 0;
   pcg_start<T>(c, NR, rtol, atol, flexible, s);
   hipGraphExec_t ex = nullptr;
   if (an.opt.use_graph) ex = iteration_graph<T>(c, NR, flexible);
-  int k = 0;
-  bool done = read_all_done(dv, s) != 0;
-  // The host stays one iteration ahead of the device: iteration k+1 is enqueued before the convergence flag of
-  // iteration k is read back (its kernels skip themselves once the flag is set), so the device never idles
-  // waiting for the host between iterations.
-  volatile int* slot = reinterpret_cast<volatile int*>(static_cast<char*>(dv.pinned) + sizeof(PcgState));
+  // The host keeps one iteration ahead of the device: iteration k+1 is enqueued before the state after iteration
+  // k is read back (its kernels skip themselves once every column has converged), so the device does not idle
+  // while the host decides.  When the residual history predicts that the iteration in flight converges, the
+  // host waits for it instead of enqueuing one more (a skipped iteration still costs a full launch sequence).
   if (!dv.ev[0]) {
     R3MG_HIP_CHECK(hipEventCreateWithFlags(&dv.ev[0], hipEventDisableTiming));
     R3MG_HIP_CHECK(hipEventCreateWithFlags(&dv.ev[1], hipEventDisableTiming));
   }
+  PcgState* snap = reinterpret_cast<PcgState*>(static_cast<char*>(dv.pinned) + sizeof(PcgState));  // 2 slots
+  int k = 0;  // iterations enqueued; snapshot j (state after iteration j) lands in slot j & 1
+  auto snapshot = [&]() {
+    R3MG_HIP_CHECK(hipMemcpyAsync(&snap[k & 1], dv.state.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    R3MG_HIP_CHECK(hipEventRecord(dv.ev[k & 1], s));
+  };
   auto launch_one = [&]() {
     if (ex)
       R3MG_HIP_CHECK(hipGraphLaunch(ex, s));
     else
       pcg_iteration<T>(c, NR, flexible, s);
     ++k;
-    R3MG_HIP_CHECK(hipMemcpyAsync(const_cast<int*>(&slot[k & 1]), dv.state.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    R3MG_HIP_CHECK(hipEventRecord(dv.ev[k & 1], s));
+    snapshot();
   };
-  for (;;) {
-    if (!done && k < maxit) {
-      launch_one();
-      while (true) {
-        const int waiting = k;
-        if (k < maxit) launch_one();  // speculative next iteration
-        R3MG_HIP_CHECK(hipEventSynchronize(dv.ev[waiting & 1]));
-        done = slot[waiting & 1] != 0;
-        if (done || waiting == k) break;  // converged, or maxit reached with nothing more in flight
+  PcgState st;
+  auto run_iterations = [&]() {
+    std::vector<double> rr1, rr2;  // recursive residuals after the last two known iterations
+    int kn = k - 1;                // last snapshot read by the host
+    snapshot();                    // the state before the first iteration of this run
+    while (true) {
+      // one iteration in flight (snapshot kn + 1 pending): enqueue another unless it is predicted to converge
+      if (k == kn + 1 && k < maxit) {
+        bool predicted = !rr2.empty();
+        for (int j = 0; j < nb && predicted; ++j) {
+          if (st.done[j]) continue;
+          predicted = rr2[j] > 0.0 && rr1[j] * (rr1[j] / rr2[j]) <= st.tau2[j];
+        }
+        if (!predicted) launch_one();
       }
-      R3MG_HIP_CHECK(hipStreamSynchronize(s));
+      R3MG_HIP_CHECK(hipEventSynchronize(dv.ev[(kn + 1) & 1]));
+      std::memcpy(&st, &snap[(kn + 1) & 1], sizeof(PcgState));
+      ++kn;
+      if (st.all_done) break;
+      rr2.swap(rr1);
+      rr1.assign(st.rr, st.rr + nb);
+      if (k == kn) {  // nothing in flight
+        if (k >= maxit) break;
+        launch_one();
+      }
     }
-    if (!flexible || restarts >= 2) break;
-    // residual replacement (float32 V-cycle): confirm the recursive residual with the true one
-    PcgState st = read_state(dv, s);
+  };
+  int restarts = 0;
+  const int nparts = (n + 255) / 256;
+  for (;;) {
+    run_iterations();
+    if (!flexible || restarts >= 2) {
+      // the final state is known; write the solution back
+      launch_scatter_cols(n, NR, nb, dv.perm.p, dv.px.p, x + (int64_t)c0 * n, n, s);
+      R3MG_HIP_CHECK(hipStreamSynchronize(s));
+      break;
+    }
+    // residual replacement (float32 V-cycle): confirm the recursive residual with the true one; the solution is
+    // written back in the same sequence (one synchronisation) and again after a restart
     apply_level<double>(c, 0, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
-    int np = launch_residual(n, NR, dv.pb.p, dv.pq.p, dv.pz.p, dv.partials.p, s);
-    std::vector<double> part((size_t)np * NR);
-    R3MG_HIP_CHECK(hipMemcpyAsync(part.data(), dv.partials.p, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    const int np = launch_residual(n, NR, dv.pb.p, dv.pq.p, dv.pz.p, dv.partials.p, s);
+    if (np != nparts) throw Error{R3MG_ERR_INVALID, "internal: residual partition"};
+    const size_t need = (size_t)np * NR * sizeof(double);
+    if (dv.pinned_part_bytes < need) {
+      if (dv.pinned_part) R3MG_HIP_CHECK(hipHostFree(dv.pinned_part));
+      dv.pinned_part = nullptr;
+      R3MG_HIP_CHECK(hipHostMalloc(&dv.pinned_part, need, hipHostMallocDefault));
+      dv.pinned_part_bytes = need;
+    }
+    R3MG_HIP_CHECK(hipMemcpyAsync(dv.pinned_part, dv.partials.p, need, hipMemcpyDeviceToHost, s));
+    launch_scatter_cols(n, NR, nb, dv.perm.p, dv.px.p, x + (int64_t)c0 * n, n, s);
     R3MG_HIP_CHECK(hipStreamSynchronize(s));
+    const double* part = static_cast<const double*>(dv.pinned_part);
     bool all_ok = true;
     for (int j = 0; j < nb; ++j) {
       double rr = 0;
@@ -1153,11 +1190,7 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
     st2.all_done = all;
     R3MG_HIP_CHECK(hipMemcpyAsync(dv.state.p, &st2, sizeof(PcgState), hipMemcpyHostToDevice, s));
     R3MG_HIP_CHECK(hipStreamSynchronize(s));
-    done = all != 0;
   }
-  PcgState st = read_state(dv, s);
-  launch_scatter_cols(n, NR, nb, dv.perm.p, dv.px.p, x + (int64_t)c0 * n, n, s);
-  R3MG_HIP_CHECK(hipStreamSynchronize(s));
   bool conv = true;
   for (int j = 0; j < nb; ++j) {
     if (iters) iters[c0 + j] = st.iters[j];
