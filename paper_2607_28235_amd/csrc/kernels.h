@@ -57,6 +57,8 @@ struct FineBlocks {
   const int* ubp = nullptr;
   const int* ucol = nullptr;
   const void* lidx = nullptr;
+  const int* meta = nullptr;  // local-column blocks: per block (first row, first nonzero, first distinct column, 0),
+                              // 16-byte records, nrb + 1 of them
 };
 
 // Fine-level row-block kernel for one right-hand side.  Shapes:

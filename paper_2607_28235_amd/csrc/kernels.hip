@@ -728,8 +728,8 @@ __global__ __launch_bounds__(256) void k_level_local(int nrb, const int* __restr
 // positions carry kFinePad padding entries), stages the four products with one aligned LDS write, and each wave
 // loads its rows' row pointers once and spreads them with lane shuffles.
 template <typename T, int CAP, int RPB, int UCAP>
-__global__ __launch_bounds__(256) void k_level_local_vec(int nrb, const int* __restrict__ rb,
-                                                         const int* __restrict__ ubp, const int* __restrict__ ucol,
+__global__ __launch_bounds__(256) void k_level_local_vec(int nrb, const int4* __restrict__ meta,
+                                                         const int* __restrict__ ucol,
                                                          const uint8_t* __restrict__ lidx, const int* __restrict__ ptr,
                                                          const int* __restrict__ idx, const T* __restrict__ val,
                                                          const T* __restrict__ u, const T* __restrict__ b, T* rho,
@@ -748,9 +748,11 @@ __global__ __launch_bounds__(256) void k_level_local_vec(int nrb, const int* __r
   __shared__ __align__(32) T prod[CAP];
   __shared__ T shr[4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = rb[lb], r1 = rb[lb + 1];
-  const int e0 = ptr[r0], e1 = ptr[r1];
-  const int u0 = ubp[lb], nu = ubp[lb + 1] - u0;
+  // first row, first nonzero and first distinct column of this block and of the next (one round trip)
+  const int4 m0 = meta[lb], m1 = meta[lb + 1];
+  const int r0 = m0.x, r1 = m1.x;
+  const int e0 = m0.y, e1 = m1.y;
+  const int u0 = m0.z, nu = m1.z - u0;
   const bool staged = nu <= UCAP;
   const int rl = threadIdx.x / TPR, sub = threadIdx.x % TPR;
   const int prow = r0 + rl;
@@ -899,9 +901,10 @@ static int launch_stream_local_vec(const FineBlocks& fb, const LevelOp<T>& op, c
                                    hipStream_t s) {
   if (partials) throw std::runtime_error("local-column vector kernel: no partial sums");
   const int nrb = fb.nrb;
-  hipLaunchKernelGGL((k_level_local_vec<T, CAP, RPB, UCAP>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, fb.rb,
-                     fb.ubp, fb.ucol, static_cast<const uint8_t*>(fb.lidx), op.ptr, op.idx, op.val, u, b, rho, x,
-                     op.dinv, dout, (T)c1, (T)c2, flags, skip);
+  if (!fb.meta) throw std::runtime_error("local-column vector kernel: block records missing");
+  hipLaunchKernelGGL((k_level_local_vec<T, CAP, RPB, UCAP>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb,
+                     reinterpret_cast<const int4*>(fb.meta), fb.ucol, static_cast<const uint8_t*>(fb.lidx), op.ptr,
+                     op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip);
   return nrb;
 }
 

@@ -199,6 +199,7 @@ struct DevLevel {
   DBuf<int32_t> rb[3];  // l = 0: CSR row blocks of the single-RHS row-block kernels, per geometry
   DBuf<int32_t> lrb[3], lubp[3], lucol[3];  // l = 0: local-column row blocks, per geometry
   DBuf<uint8_t> lidx[3];
+  DBuf<int32_t> lmeta[3];  // l = 0: per-block records of the local-column blocks (FineBlocks::meta)
   FineBlocks fb[kStreamShapes];  // l = 0: row blocks of every kernel shape
   double shape_bytes[kStreamShapes] = {};  // algorithmic bytes of one application with each shape
   int shape = 0;        // l = 0: kernel shape chosen by timing at set-up

@@ -728,17 +728,26 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
 }
 
 // uploads local-column row blocks into slot g of a level and points the kernel shape kLocalFirst + g at them
-static void upload_local(DevLevel& D, int g, const LocalBlocks& lb, hipStream_t s) {
+static void upload_local(DevLevel& D, int g, const LocalBlocks& lb, const std::vector<int32_t>& rowptr,
+                         hipStream_t s) {
   D.lrb[g].upload(lb.rb, s);
   D.lubp[g].upload(lb.ubp, s);
   D.lucol[g].upload(lb.ucol, s);
   D.lidx[g].upload(lb.lidx, s);
+  std::vector<int32_t> meta(lb.rb.size() * 4, 0);
+  for (size_t b = 0; b < lb.rb.size(); ++b) {
+    meta[4 * b] = lb.rb[b];
+    meta[4 * b + 1] = rowptr[lb.rb[b]];
+    meta[4 * b + 2] = lb.ubp[b];
+  }
+  D.lmeta[g].upload(meta, s);
   FineBlocks& f = D.fb[kLocalFirst + g];
   f.nrb = (int)lb.rb.size() - 1;
   f.rb = D.lrb[g].p;
   f.ubp = D.lubp[g].p;
   f.ucol = D.lucol[g].p;
   f.lidx = D.lidx[g].p;
+  f.meta = D.lmeta[g].p;
 }
 
 // algorithmic bytes of one application with local-column blocks: values and local column positions,
@@ -795,7 +804,7 @@ void device_setup(HandleImpl& h, hipStream_t s) {
       }
     }
     for (int g = 0; g < kLocalGeoms; ++g) {
-      upload_local(D, g, an.loc[g], s);
+      upload_local(D, g, an.loc[g], an.rowptr, s);
       D.shape_bytes[kLocalFirst + g] = local_bytes(an.nnz, an.n, g, an.loc[g], sv0);
     }
     // shape 9: the vector-load kernel over the blocks of local geometry 0
@@ -843,7 +852,7 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     D.bytes_apply = (double)D.nnz * sv + (double)nblk * 4 + (double)(H.nbox + 1) * 4 + 7.0 * D.n * sv;
     if (!H.rowptr.empty()) {  // narrow block rows: the level is also held as 1-byte local-column blocks
       D.rowptr.upload(H.rowptr, s);
-      upload_local(D, 0, H.loc, s);
+      upload_local(D, 0, H.loc, H.rowptr, s);
       D.fb[kLocalFirst + kLocalGeoms] = D.fb[kLocalFirst];
       D.shape = kLocalFirst + kLocalGeoms;
       D.bytes_apply = local_bytes(D.nnz, D.n, 0, H.loc, sv);
