@@ -63,6 +63,8 @@ def main():
                     help="solve2d: the headline (591k-DoF Q3 square); batch16: 16-RHS block PCG on the 48^3 Q3 "
                          "cube; uneven8: 8 Q2 cubes of 16^3..48^3 in one graph; adjoint: kappa-gradient on 64^3 Q2")
     ap.add_argument("--fd-cells", type=int, default=32)
+    ap.add_argument("--matfree", action="store_true",
+                    help="batch16: also time the solves with the matrix-free fine operator")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (the HBM-counter calibration kernel)")
     args = ap.parse_args()
@@ -300,6 +302,21 @@ def bench_batch16(args):
     Xh = X.cpu().numpy()
     res = np.linalg.norm(R - (prob.scipy() @ Xh.T).T, axis=1) / np.linalg.norm(R, axis=1)
     log(f"16 rhs: {t16 * 1e3:.1f} ms ({16 * prob.n / t16:.3e} DoF/s), 1 rhs: {t1 * 1e3:.1f} ms")
+    mf = None
+    if args.matfree:
+        # the same solves with the matrix-free fine operator (cell kernel looping over the 16 columns)
+        ta = time.time()
+        h.set_matrix_free(prob.cells, prob.p)
+        t_att = time.time() - ta
+        t16m, (it16m, _, ok16m) = _timed(solve16, args.steps, args.warmup)
+        x16m = X.cpu().numpy()
+        t1m, (it1m, _, _) = _timed(solve1, args.steps, args.warmup)
+        resm = np.linalg.norm(R - (prob.scipy() @ x16m.T).T, axis=1) / np.linalg.norm(R, axis=1)
+        mf = {"ms_16rhs": t16m * 1e3, "DoF_per_s_16rhs": 16 * prob.n / t16m, "iters": [int(i) for i in it16m],
+              "all_converged": bool(ok16m), "max_true_relres": float(resm.max()), "ms_1rhs": t1m * 1e3,
+              "speedup_over_csr_16rhs": t16 / t16m, "set_up_s": t_att,
+              "solution_rel_diff_vs_csr": float(np.linalg.norm(x16m - Xh) / np.linalg.norm(Xh))}
+        log(f"matrix-free: 16 rhs {t16m * 1e3:.1f} ms ({16 * prob.n / t16m:.3e} DoF/s), 1 rhs {t1m * 1e3:.1f} ms")
     print(json.dumps({
         "metric": "DoF/s solved to rtol 1e-10, 16 right-hand sides in lockstep (FP32 V-cycle in FP64 CG)",
         "value": 16 * prob.n / t16, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -308,7 +325,7 @@ def bench_batch16(args):
                    "level_sizes": [lv["n"] for lv in info]},
         "iters": [int(i) for i in it16], "max_true_relres": float(res.max()), "all_converged": bool(ok16),
         "single_rhs_ms": t1 * 1e3, "single_rhs_iters": int(it1[0]),
-        "per_rhs_speedup_of_batching": 16 * t1 / t16, "setup_s": t_setup}), flush=True)
+        "per_rhs_speedup_of_batching": 16 * t1 / t16, "setup_s": t_setup, "matrix_free": mf}), flush=True)
 
 
 def bench_uneven8(args):

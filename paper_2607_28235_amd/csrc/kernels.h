@@ -207,6 +207,12 @@ void launch_mf_apply(const MfOp& m, const MfTables<T>& tb, const T* geo, const T
                      const T* u, const T* b, T* rho, T* x, T* dout, double c1, double c2, int flags, const int* skip,
                      hipStream_t s);
 
+// The same for nr in {2, 4, 8, 16} interleaved right-hand sides; Y holds ncells x nlocp x nr entries.
+template <typename T>
+void launch_mf_apply_mr(const MfOp& m, int nr, const MfTables<T>& tb, const T* geo, const T* cd, T* Y, const T* dinv,
+                        const T* u, const T* b, T* rho, T* x, T* dout, double c1, double c2, int flags,
+                        const int* skip, hipStream_t s);
+
 // dense Cholesky (lower, in place, row-major n x n) and inverse; *bad set on a non-positive pivot
 void dense_cholesky_inverse(int n, double* A, double* Inv, int* bad, hipStream_t s);
 

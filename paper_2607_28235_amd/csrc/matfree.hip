@@ -70,78 +70,11 @@ __device__ inline void geo_point(const T* gm, T w, T x1, T x2, T x3, T* c) {
   }
 }
 
-// One thread per cell.  When a wave's connectivity and outputs fit LDS (256 cells x nlocp entries <= 64 KiB),
-// both are staged through it so that the global loads and stores are contiguous 16-byte accesses.
+// y_e = K_e u_e for one cell by sum factorisation, one Gauss-point slice at a time along the last axis (which
+// bounds the registers); gm holds the cell's geometry record (affine C or the map's coefficients).
 template <typename T, int D, int K, bool AFF>
-__global__ __launch_bounds__(256) void k_mf_cell(int ncells, const int* __restrict__ conn, const T* __restrict__ geo,
-                                                 MfTables<T> tb, const T* __restrict__ u, T* __restrict__ Y,
-                                                 const int* __restrict__ skip, int nlog) {
+__device__ __forceinline__ void cell_action(const T* ue, const T* gm, const MfTables<T>& tb, T* v) {
   constexpr int NL = D == 2 ? K * K : K * K * K;
-  constexpr int NP = (NL + 3) / 4 * 4;
-  constexpr int NC = D == 2 ? 3 : 6;
-  constexpr int NG = AFF ? NC : (D == 2 ? 7 : 22);
-  constexpr int ES = sizeof(T) > 4 ? (int)sizeof(T) : 4;
-  constexpr bool STAGE = 256 * NP * ES <= 65536;
-  constexpr int VW = 16 / (int)sizeof(T);
-  typedef T V16 __attribute__((ext_vector_type(VW)));
-  __shared__ __attribute__((aligned(16))) char lds[STAGE ? 256 * NP * ES : 16];
-  if (skip && *skip) return;
-  const int lb = xcd_block(nlog);
-  if (lb < 0) return;
-  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
-  const int e = lb * 256 + (int)threadIdx.x;
-  const bool valid = e < ncells;
-  const int64_t total = (int64_t)ncells * NP;
-  const int64_t wbase = (int64_t)(lb * 256 + wv * 64) * NP;  // first entry of this wave's cells
-  char* wlds = lds + wv * 64 * NP * ES;
-
-  int cidx[NP];
-  if constexpr (STAGE) {
-    int* li = reinterpret_cast<int*>(wlds);
-#pragma unroll
-    for (int j = 0; j < NP / 4; ++j) {
-      const int q = j * 64 + lane;
-      const int64_t off = wbase + 4 * (int64_t)q;
-      int4 c4 = make_int4(-1, -1, -1, -1);
-      if (off < total) c4 = *reinterpret_cast<const int4*>(conn + off);
-      *reinterpret_cast<int4*>(li + 4 * q) = c4;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a4 = 0; a4 < NP / 4; ++a4) {
-      const int4 c4 = *reinterpret_cast<const int4*>(li + lane * NP + 4 * a4);
-      cidx[4 * a4] = c4.x;
-      cidx[4 * a4 + 1] = c4.y;
-      cidx[4 * a4 + 2] = c4.z;
-      cidx[4 * a4 + 3] = c4.w;
-    }
-  } else {
-#pragma unroll
-    for (int a4 = 0; a4 < NP / 4; ++a4) {
-      int4 c4 = make_int4(-1, -1, -1, -1);
-      if (valid) c4 = *reinterpret_cast<const int4*>(conn + (int64_t)e * NP + 4 * a4);
-      cidx[4 * a4] = c4.x;
-      cidx[4 * a4 + 1] = c4.y;
-      cidx[4 * a4 + 2] = c4.z;
-      cidx[4 * a4 + 3] = c4.w;
-    }
-  }
-  // gather u_e (constrained DoFs, padding and cells past the end read as zero)
-  T ue[NL];
-#pragma unroll
-  for (int a = 0; a < NL; ++a) ue[a] = cidx[a] >= 0 ? u[cidx[a]] : (T)0;
-  T gm[NG];
-#pragma unroll
-  for (int c = 0; c < NG; ++c) gm[c] = valid ? geo[(int64_t)c * ncells + e] : (T)(c == NG - 1 ? 1 : 0);
-  if constexpr (!AFF) {
-    if (!valid) {  // a harmless unit square / cube for the idle lanes
-#pragma unroll
-      for (int c = 0; c < NG; ++c) gm[c] = 0;
-      if constexpr (D == 2) { gm[0] = 1; gm[3] = 1; gm[6] = 1; }
-      else { gm[0] = 1; gm[4] = 1; gm[8] = 1; gm[21] = 1; }
-    }
-  }
-  T v[NL];
 #pragma unroll
   for (int a = 0; a < NL; ++a) v[a] = 0;
 
@@ -262,6 +195,90 @@ __global__ __launch_bounds__(256) void k_mf_cell(int ncells, const int* __restri
     }
   }
 
+}
+
+// geometry record of cell e (a harmless unit square / cube for the idle lanes past the last cell)
+template <typename T, int D, bool AFF>
+__device__ __forceinline__ void load_geometry(const T* __restrict__ geo, int ncells, int e, bool valid, T* gm) {
+  constexpr int NC = D == 2 ? 3 : 6;
+  constexpr int NG = AFF ? NC : (D == 2 ? 7 : 22);
+#pragma unroll
+  for (int c = 0; c < NG; ++c) gm[c] = valid ? geo[(int64_t)c * ncells + e] : (T)(c == NG - 1 ? 1 : 0);
+  if constexpr (!AFF) {
+    if (!valid) {
+#pragma unroll
+      for (int c = 0; c < NG; ++c) gm[c] = 0;
+      if constexpr (D == 2) { gm[0] = 1; gm[3] = 1; gm[6] = 1; }
+      else { gm[0] = 1; gm[4] = 1; gm[8] = 1; gm[21] = 1; }
+    }
+  }
+}
+
+// One thread per cell.  When a wave's connectivity and outputs fit LDS (256 cells x nlocp entries <= 64 KiB),
+// both are staged through it so that the global loads and stores are contiguous 16-byte accesses.
+template <typename T, int D, int K, bool AFF>
+__global__ __launch_bounds__(256) void k_mf_cell(int ncells, const int* __restrict__ conn, const T* __restrict__ geo,
+                                                 MfTables<T> tb, const T* __restrict__ u, T* __restrict__ Y,
+                                                 const int* __restrict__ skip, int nlog) {
+  constexpr int NL = D == 2 ? K * K : K * K * K;
+  constexpr int NP = (NL + 3) / 4 * 4;
+  constexpr int NC = D == 2 ? 3 : 6;
+  constexpr int NG = AFF ? NC : (D == 2 ? 7 : 22);
+  constexpr int ES = sizeof(T) > 4 ? (int)sizeof(T) : 4;
+  constexpr bool STAGE = 256 * NP * ES <= 65536;
+  constexpr int VW = 16 / (int)sizeof(T);
+  typedef T V16 __attribute__((ext_vector_type(VW)));
+  __shared__ __attribute__((aligned(16))) char lds[STAGE ? 256 * NP * ES : 16];
+  if (skip && *skip) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  const int e = lb * 256 + (int)threadIdx.x;
+  const bool valid = e < ncells;
+  const int64_t total = (int64_t)ncells * NP;
+  const int64_t wbase = (int64_t)(lb * 256 + wv * 64) * NP;  // first entry of this wave's cells
+  char* wlds = lds + wv * 64 * NP * ES;
+
+  int cidx[NP];
+  if constexpr (STAGE) {
+    int* li = reinterpret_cast<int*>(wlds);
+#pragma unroll
+    for (int j = 0; j < NP / 4; ++j) {
+      const int q = j * 64 + lane;
+      const int64_t off = wbase + 4 * (int64_t)q;
+      int4 c4 = make_int4(-1, -1, -1, -1);
+      if (off < total) c4 = *reinterpret_cast<const int4*>(conn + off);
+      *reinterpret_cast<int4*>(li + 4 * q) = c4;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a4 = 0; a4 < NP / 4; ++a4) {
+      const int4 c4 = *reinterpret_cast<const int4*>(li + lane * NP + 4 * a4);
+      cidx[4 * a4] = c4.x;
+      cidx[4 * a4 + 1] = c4.y;
+      cidx[4 * a4 + 2] = c4.z;
+      cidx[4 * a4 + 3] = c4.w;
+    }
+  } else {
+#pragma unroll
+    for (int a4 = 0; a4 < NP / 4; ++a4) {
+      int4 c4 = make_int4(-1, -1, -1, -1);
+      if (valid) c4 = *reinterpret_cast<const int4*>(conn + (int64_t)e * NP + 4 * a4);
+      cidx[4 * a4] = c4.x;
+      cidx[4 * a4 + 1] = c4.y;
+      cidx[4 * a4 + 2] = c4.z;
+      cidx[4 * a4 + 3] = c4.w;
+    }
+  }
+  // gather u_e (constrained DoFs, padding and cells past the end read as zero)
+  T ue[NL];
+#pragma unroll
+  for (int a = 0; a < NL; ++a) ue[a] = cidx[a] >= 0 ? u[cidx[a]] : (T)0;
+  T gm[NG];
+  load_geometry<T, D, AFF>(geo, ncells, e, valid, gm);
+  T v[NL];
+  cell_action<T, D, K, AFF>(ue, gm, tb, v);
+
   // store y_e (padding entries are written as zero)
   if constexpr (STAGE) {
     T* lt = reinterpret_cast<T*>(wlds);
@@ -334,6 +351,180 @@ __global__ __launch_bounds__(256) void k_mf_gather(int n, const int* __restrict_
   if (flags & F_D_OUT) dout[i] = c1 * ui + c2 * dinv[i] * r;
 }
 
+// Several right-hand sides (nr columns, n x nr interleaved vectors): each thread applies its cell to the columns
+// in turn, reusing its connectivity and the geometry held in registers.  Y holds one plane of cell outputs per
+// column, Y[k * ncells * nlocp + e * nlocp + a], written through LDS as contiguous 16-byte stores (as for one
+// right-hand side).
+template <typename T, int D, int K, bool AFF>
+__global__ __launch_bounds__(256) void k_mf_cell_mr(int ncells, int nr, const int* __restrict__ conn,
+                                                    const T* __restrict__ geo, MfTables<T> tb,
+                                                    const T* __restrict__ u, T* __restrict__ Y,
+                                                    const int* __restrict__ skip, int nlog) {
+  constexpr int NL = D == 2 ? K * K : K * K * K;
+  constexpr int NP = (NL + 3) / 4 * 4;
+  constexpr int NC = D == 2 ? 3 : 6;
+  constexpr int NG = AFF ? NC : (D == 2 ? 7 : 22);
+  constexpr int ES = sizeof(T) > 4 ? (int)sizeof(T) : 4;
+  constexpr bool STAGE = 256 * NP * ES <= 65536;
+  constexpr int VW = 16 / (int)sizeof(T);
+  typedef T V16 __attribute__((ext_vector_type(VW)));
+  __shared__ __attribute__((aligned(16))) char lds[STAGE ? 256 * NP * ES : 16];
+  if (skip && *skip) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  const int e = lb * 256 + (int)threadIdx.x;
+  const bool valid = e < ncells;
+  const int64_t total = (int64_t)ncells * NP;
+  const int64_t wbase = (int64_t)(lb * 256 + wv * 64) * NP;
+  char* wlds = lds + wv * 64 * NP * ES;
+  int cidx[NP];
+  if constexpr (STAGE) {
+    int* li = reinterpret_cast<int*>(wlds);
+#pragma unroll
+    for (int j = 0; j < NP / 4; ++j) {
+      const int q = j * 64 + lane;
+      const int64_t off = wbase + 4 * (int64_t)q;
+      int4 c4 = make_int4(-1, -1, -1, -1);
+      if (off < total) c4 = *reinterpret_cast<const int4*>(conn + off);
+      *reinterpret_cast<int4*>(li + 4 * q) = c4;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a4 = 0; a4 < NP / 4; ++a4) {
+      const int4 c4 = *reinterpret_cast<const int4*>(li + lane * NP + 4 * a4);
+      cidx[4 * a4] = c4.x;
+      cidx[4 * a4 + 1] = c4.y;
+      cidx[4 * a4 + 2] = c4.z;
+      cidx[4 * a4 + 3] = c4.w;
+    }
+  } else {
+#pragma unroll
+    for (int a4 = 0; a4 < NP / 4; ++a4) {
+      int4 c4 = make_int4(-1, -1, -1, -1);
+      if (valid) c4 = *reinterpret_cast<const int4*>(conn + (int64_t)e * NP + 4 * a4);
+      cidx[4 * a4] = c4.x;
+      cidx[4 * a4 + 1] = c4.y;
+      cidx[4 * a4 + 2] = c4.z;
+      cidx[4 * a4 + 3] = c4.w;
+    }
+  }
+  T gm[NG];
+  load_geometry<T, D, AFF>(geo, ncells, e, valid, gm);
+  // 32-bit element offsets (n * nr < 2^31 is checked at set-up) keep the per-node addresses to one register each
+#pragma unroll
+  for (int a = 0; a < NL; ++a) cidx[a] = cidx[a] >= 0 ? cidx[a] * nr : -1;
+#pragma unroll 1
+  for (int k = 0; k < nr; ++k) {
+    // the geometric factors at the Gauss points do not depend on the column; without this (empty) register
+    // constraint the compiler keeps all of them live across the loop, which exhausts the registers in 3D
+#pragma unroll
+    for (int c = 0; c < NG; ++c) asm volatile("" : "+v"(gm[c]));
+    T ue[NL];
+#pragma unroll
+    for (int a = 0; a < NL; ++a) ue[a] = cidx[a] >= 0 ? u[cidx[a] + k] : (T)0;
+    T v[NL];
+    cell_action<T, D, K, AFF>(ue, gm, tb, v);
+    T* plane = Y + (int64_t)k * total;
+    if constexpr (STAGE) {
+      T* lt = reinterpret_cast<T*>(wlds);
+      __syncthreads();  // the tile is free: connectivity read (first column) or previous column stored
+#pragma unroll
+      for (int a0 = 0; a0 < NP; a0 += VW) {
+        V16 t;
+#pragma unroll
+        for (int m = 0; m < VW; ++m) t[m] = (a0 + m < NL) ? v[a0 + m] : (T)0;
+        *reinterpret_cast<V16*>(lt + lane * NP + a0) = t;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < NP / VW; ++j) {
+        const int q = j * 64 + lane;
+        const int64_t off = wbase + (int64_t)VW * q;
+        if (off < total) *reinterpret_cast<V16*>(plane + off) = *reinterpret_cast<const V16*>(lt + VW * q);
+      }
+    } else if (valid) {
+#pragma unroll
+      for (int a0 = 0; a0 < NP; a0 += VW) {
+        V16 t;
+#pragma unroll
+        for (int m = 0; m < VW; ++m) t[m] = (a0 + m < NL) ? v[a0 + m] : (T)0;
+        *reinterpret_cast<V16*>(plane + (int64_t)e * NP + a0) = t;
+      }
+    }
+  }
+}
+
+// One thread per (DoF, column), columns fastest: the column's sum over the DoF's cell outputs in ascending (cell,
+// node) order, then the epilogue of the multi-RHS level kernels for that entry.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mf_gather_mr(int n, int nr, int64_t plane, const int* __restrict__ inc_ptr,
+                                                      const int* __restrict__ inc, const T* __restrict__ Y,
+                                                      const T* __restrict__ cd, const T* __restrict__ u,
+                                                      const T* __restrict__ b, T* rho, T* x,
+                                                      const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
+                                                      const int* __restrict__ skip, int nlog) {
+  if (skip && *skip) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int64_t t = (int64_t)lb * 256 + threadIdx.x;
+  const int64_t i = t / nr;
+  const int k = (int)(t - i * nr);
+  if (i >= n) return;
+  const int s0 = inc_ptr[i], s1 = inc_ptr[i + 1];
+  const T* yk = Y + (int64_t)k * plane;
+  T acc = 0;
+  if (s0 == s1) {
+    acc = cd[i] * u[t];
+  } else {
+    int j = s0;
+    for (; j + 8 <= s1; j += 8) {
+      T yv[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) yv[m] = yk[inc[j + m]];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) acc += yv[m];
+    }
+    for (; j < s1; ++j) acc += yk[inc[j]];
+  }
+  if (flags & F_PLAIN) {
+    rho[t] = acc;
+    return;
+  }
+  const T r = ((flags & F_RHO_FROM_B) ? b[t] : rho[t]) - acc;
+  if (flags & F_RHO_STORE) rho[t] = r;
+  const T ui = u[t];
+  if (flags & F_X_ASSIGN)
+    x[t] = ui;
+  else if (flags & F_X_ADD)
+    x[t] += ui;
+  if (flags & F_D_OUT) dout[t] = c1 * ui + c2 * dinv[i] * r;
+}
+
+template <typename T, int D, int K>
+void launch_cell_mr(const MfOp& m, int nr, const MfTables<T>& tb, const T* geo, const T* u, T* Y, const int* skip,
+                    hipStream_t s) {
+  const int nlog = (m.ncells + 255) / 256;
+  constexpr int NL = D == 2 ? K * K : K * K * K;
+  if (m.nlocp != (NL + 3) / 4 * 4) throw std::runtime_error("matrix-free operator: connectivity stride mismatch");
+  if (m.affine)
+    hipLaunchKernelGGL((k_mf_cell_mr<T, D, K, true>), dim3(xcd_grid(nlog)), dim3(256), 0, s, m.ncells, nr, m.conn,
+                       geo, tb, u, Y, skip, nlog);
+  else
+    hipLaunchKernelGGL((k_mf_cell_mr<T, D, K, false>), dim3(xcd_grid(nlog)), dim3(256), 0, s, m.ncells, nr, m.conn,
+                       geo, tb, u, Y, skip, nlog);
+}
+
+template <typename T>
+void launch_gather_mr(const MfOp& m, int nr, const T* Y, const T* cd, const T* dinv, const T* u, const T* b, T* rho,
+                      T* x, T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s) {
+  const int64_t threads = (int64_t)m.n * nr;
+  const int nlog = (int)((threads + 255) / 256);
+  const int64_t plane = (int64_t)m.ncells * m.nlocp;
+  hipLaunchKernelGGL((k_mf_gather_mr<T>), dim3(xcd_grid(nlog)), dim3(256), 0, s, m.n, nr, plane, m.inc_ptr, m.inc,
+                     Y, cd, u, b, rho, x, dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
+}
+
 template <typename T, int D, int K>
 void launch_cell(const MfOp& m, const MfTables<T>& tb, const T* geo, const T* u, T* Y, const int* skip,
                  hipStream_t s) {
@@ -373,6 +564,31 @@ void launch_mf_apply(const MfOp& m, const MfTables<T>& tb, const T* geo, const T
                      rho, x, dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
   check_launch("k_mf_gather");
 }
+template <typename T>
+void launch_mf_apply_mr(const MfOp& m, int nr, const MfTables<T>& tb, const T* geo, const T* cd, T* Y, const T* dinv,
+                        const T* u, const T* b, T* rho, T* x, T* dout, double c1, double c2, int flags,
+                        const int* skip, hipStream_t s) {
+  if (m.n <= 0) return;
+  if (nr != 2 && nr != 4 && nr != 8 && nr != 16) throw std::runtime_error("matrix-free operator: unsupported nrhs");
+  switch (m.d * 10 + m.k) {
+    case 22: launch_cell_mr<T, 2, 2>(m, nr, tb, geo, u, Y, skip, s); break;
+    case 23: launch_cell_mr<T, 2, 3>(m, nr, tb, geo, u, Y, skip, s); break;
+    case 24: launch_cell_mr<T, 2, 4>(m, nr, tb, geo, u, Y, skip, s); break;
+    case 32: launch_cell_mr<T, 3, 2>(m, nr, tb, geo, u, Y, skip, s); break;
+    case 33: launch_cell_mr<T, 3, 3>(m, nr, tb, geo, u, Y, skip, s); break;
+    case 34: launch_cell_mr<T, 3, 4>(m, nr, tb, geo, u, Y, skip, s); break;
+    default: throw std::runtime_error("matrix-free operator: unsupported dimension or degree");
+  }
+  check_launch("k_mf_cell_mr");
+  launch_gather_mr<T>(m, nr, Y, cd, dinv, u, b, rho, x, dout, c1, c2, flags, skip, s);
+  check_launch("k_mf_gather_mr");
+}
+template void launch_mf_apply_mr<float>(const MfOp&, int, const MfTables<float>&, const float*, const float*, float*,
+                                        const float*, const float*, const float*, float*, float*, float*, double,
+                                        double, int, const int*, hipStream_t);
+template void launch_mf_apply_mr<double>(const MfOp&, int, const MfTables<double>&, const double*, const double*,
+                                         double*, const double*, const double*, const double*, double*, double*,
+                                         double*, double, double, int, const int*, hipStream_t);
 template void launch_mf_apply<float>(const MfOp&, const MfTables<float>&, const float*, const float*, float*,
                                      const float*, const float*, const float*, float*, float*, float*, double, double,
                                      int, const int*, hipStream_t);

@@ -176,8 +176,9 @@ struct MatFreeDev {
   int p = 0;
   int64_t nincid = 0;
   DBuf<int32_t> conn, inc_ptr, inc;
-  DBuf<double> geo64, cd64, y64;
-  DBuf<float> geo32, cd32, y32;
+  DBuf<double> geo64, cd64, y64, y64mr;
+  DBuf<float> geo32, cd32, y32, y32mr;
+  int mr_cap = 0;  // columns the multi-right-hand-side cell outputs (y32mr / y64mr) have room for
   MfTables<float> t32;
   MfTables<double> t64;
   double bytes32 = 0, bytes64 = 0;  // algorithmic bytes of one application (7 vector streams included)
@@ -218,7 +219,7 @@ struct DevLevel {
   DBuf<char> b, x, rho, dA, dB;
   int64_t vec_cap = 0;
   double bytes_apply = 0;
-  const MatFreeDev* mf = nullptr;  // l = 0: matrix-free operator in use for one right-hand side (null: CSR)
+  const MatFreeDev* mf = nullptr;  // l = 0: matrix-free operator in use (null: CSR)
 };
 
 struct PcgScalars;  // device-side PCG state (defined in the solver)

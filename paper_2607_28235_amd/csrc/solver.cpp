@@ -190,7 +190,7 @@ constexpr int kCodeSplit = 100;
 // level for one right-hand side, a block-row kernel on coarse levels whose block rows fit LDS, the
 // lanes-per-row kernel otherwise.
 LevelKernel level_kernel(const Analysis& an, const DevLevel& D, int l, int nr, int esz) {
-  if (l == 0 && nr == 1 && D.mf) return LevelKernel::MatFree;
+  if (l == 0 && D.mf) return LevelKernel::MatFree;
   if (nr == 1 && D.fb[D.shape].nrb > 0 && (l == 0 || D.shape == kLocalFirst + kLocalGeoms)) return LevelKernel::Stream;
   if (l > 0 && nr == 1 && D.maxnb > 0 && an.B >= 8 && (int64_t)D.maxnb * an.B >= 256 &&
       (int64_t)D.maxnb * an.B * esz <= 65536)
@@ -229,12 +229,22 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
   switch (level_kernel(c.an, D, l, nr, (int)sizeof(T))) {
     case LevelKernel::MatFree: {
       const MatFreeDev& F = *D.mf;
-      if constexpr (sizeof(T) == 4)
-        launch_mf_apply<float>(F.op, F.t32, F.geo32.p, F.cd32.p, F.y32.p, op.dinv, u, b, rho, x,
-                               dout, c1, c2, flags, skip, s);
-      else
-        launch_mf_apply<double>(F.op, F.t64, F.geo64.p, F.cd64.p, F.y64.p, op.dinv, u, b, rho,
-                                x, dout, c1, c2, flags, skip, s);
+      if (nr > 1 && nr > F.mr_cap) throw std::runtime_error("matrix-free operator: multi-RHS outputs not allocated");
+      if constexpr (sizeof(T) == 4) {
+        if (nr == 1)
+          launch_mf_apply<float>(F.op, F.t32, F.geo32.p, F.cd32.p, F.y32.p, op.dinv, u, b, rho, x, dout, c1, c2,
+                                 flags, skip, s);
+        else
+          launch_mf_apply_mr<float>(F.op, nr, F.t32, F.geo32.p, F.cd32.p, F.y32mr.p, op.dinv, u, b, rho, x, dout,
+                                    c1, c2, flags, skip, s);
+      } else {
+        if (nr == 1)
+          launch_mf_apply<double>(F.op, F.t64, F.geo64.p, F.cd64.p, F.y64.p, op.dinv, u, b, rho, x, dout, c1, c2,
+                                  flags, skip, s);
+        else
+          launch_mf_apply_mr<double>(F.op, nr, F.t64, F.geo64.p, F.cd64.p, F.y64mr.p, op.dinv, u, b, rho, x, dout,
+                                     c1, c2, flags, skip, s);
+      }
       break;
     }
     case LevelKernel::Stream:
@@ -280,6 +290,17 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
 static void ensure_level_vectors(Ctx& c, int nr) {
   const size_t s = c.fp32 ? sizeof(float) : sizeof(double);
   const int L = c.an.nlevels() - 1;
+  MatFreeDev& F = c.dv.mf;
+  if (c.dv.lv[0].mf && nr > 1 && F.mr_cap < nr) {
+    // cell outputs of the matrix-free operator for nr columns (float64 for PCG's A p, plus the V-cycle precision)
+    const int64_t entries = (int64_t)F.op.ncells * F.op.nlocp * nr;
+    if (entries >= (int64_t(1) << 31) || (int64_t)F.op.n * nr >= (int64_t(1) << 31))
+      throw Error{R3MG_ERR_INVALID, "matrix-free operator: too many cell-local entries for this many right-hand sides"};
+    F.y64mr.alloc((size_t)entries);
+    if (c.fp32) F.y32mr.alloc((size_t)entries);
+    F.mr_cap = nr;
+    drop_graphs(c.dv);
+  }
   for (int l = 0; l <= L; ++l) {
     DevLevel& D = c.dv.lv[l];
     if (D.vec_cap >= D.n * nr) continue;
@@ -310,8 +331,9 @@ static void ensure_pcg_vectors(Ctx& c, int nr) {
     const int64_t nlog_vec = (n + 255) / 256;
     size_t nrb_max = 0;
     for (int sh = 0; sh < kStreamShapes; ++sh) nrb_max = std::max(nrb_max, (size_t)dv.lv[0].fb[sh].nrb);
-    dv.partials.alloc(
-        std::max<size_t>({(size_t)4096, (size_t)(nlog_spmv * nr), (size_t)(nlog_vec * 2 * nr), nrb_max}));
+    // (nr > 1: room for the per-column dot of PCG in its fixed partition, at most 1024 blocks per column)
+    dv.partials.alloc(std::max<size_t>({(size_t)4096, (size_t)(nlog_spmv * nr), (size_t)(nlog_vec * 2 * nr), nrb_max,
+                                        nr > 1 ? (size_t)1024 * nr : (size_t)0}));
     drop_graphs(dv);
   }
   if (!dv.state.p) {
@@ -353,6 +375,7 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
   for (int l = 0; l < L; ++l) {
     if (dv.tuned.count({l, tag})) continue;
     DevLevel& D = dv.lv[l];
+    if (l == 0 && D.mf) continue;  // the matrix-free operator applies the fine level
     LevelOp<T> op = level_op<T>(c, l);
     float best = 1e30f;
     int bestCode = D.lanes;
@@ -399,7 +422,7 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
   }
   // PCG's float64 q = A p and <p, q>: lanes kernel with fused partial dots (at most 8 lanes: bounded number of
   // partials), or the local-column / column-split kernel followed by the per-column dot in a fixed partition
-  if (!dv.tuned.count({-1, nr * 2})) {
+  if (!dv.tuned.count({-1, nr * 2}) && !dv.lv[0].mf) {
     LevelOp<double> op = level_op<double>(c, 0);
     DevLevel& D0 = dv.lv[0];
     float best = 1e30f;
@@ -965,6 +988,11 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
     launch_level_stream<double>(D0.shape, D0.fb[D0.shape], op64, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0,
                                 F_PLAIN, skip, nullptr, s);
     np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+  } else if (D0.mf) {
+    // q = A p with the matrix-free operator for NR columns, then the per-column <p, q> in a fixed partition
+    apply_level<double>(c, 0, NR, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
+    need_partials(dv, (int64_t)1024 * NR);
+    np = launch_pcg_dot_mr(n, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
   } else {
     auto it = dv.tuned.find({-1, NR * 2});
     if (it != dv.tuned.end() && (it->second < 0 || it->second >= kCodeSplit)) {  // then the per-column dot
@@ -1341,6 +1369,9 @@ void detach_matrix_free(HandleImpl& h) {
   F.geo32.release();
   F.cd32.release();
   F.y32.release();
+  F.y64mr.release();
+  F.y32mr.release();
+  F.mr_cap = 0;
   if (was_on) drop_graphs(dv);
 }
 

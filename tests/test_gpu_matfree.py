@@ -222,3 +222,41 @@ def test_matrix_free_full_size(cfg):
     assert _rel(xs, x_csr.cpu().numpy()) < 1e-9
     assert np.linalg.norm(w.rhs - A @ xs) <= 1.01e-10 * np.linalg.norm(w.rhs)
     h.close()
+
+
+@pytest.mark.parametrize("case,nr", [("2d_q3_multilinear", 4), ("3d_q2_affine", 16), ("3d_q3_affine", 2)])
+def test_matrix_free_multi_rhs(case, nr):
+    """Several right-hand sides through the matrix-free operator (cell kernel looping over the columns, per-DoF
+    gather of 16-byte column groups): the float64 V-cycle of every column against the oracle (1e-11), and the
+    block PCG in both V-cycle precisions against the oracle per column (iterations within one, solutions within
+    1e-9)."""
+    _need_gpu()
+    P = _P()
+    spec = {c[0]: c for c in CASES}[case]
+    _, d, N, p, jit, pc, leaf, kap = spec
+    _case(f"matrix-free multi-RHS {case} nr={nr}")
+    prob = F.structured_qp(d, N, p, jitter=jit, cfg=6)
+    g = F.rng(6, F.PURPOSE_RHS)
+    Bm = np.stack([F.nodal_rhs(prob, g.standard_normal(prob.n), jitter=jit, cfg=6) for _ in range(nr)])
+    ho = O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=pc, leaf_size=leaf, max_coarse_dofs=300)
+    ref = [O.pcg(ho, Bm[j], rtol=1e-10)[:2] for j in range(nr)]
+    for fp32 in (0, 1):
+        o = P.Options(dim=d, coarse_degree=pc, leaf_size=leaf, max_coarse_dofs=300, vcycle_fp32=fp32)
+        h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o)
+        h.set_matrix_free(prob.cells, p)
+        if not fp32:
+            R = np.random.default_rng(9).standard_normal((nr, prob.n))
+            R[:, ho.constrained] = 0.0
+            Z = torch.zeros(nr, prob.n, dtype=torch.float64, device="cuda")
+            h.vcycle(_t(R), Z)
+            torch.cuda.synchronize()
+            for j in range(nr):
+                assert _rel(Z[j].cpu().numpy(), O.vcycle(ho, R[j])) < 1e-11, j
+        X = torch.zeros(nr, prob.n, dtype=torch.float64, device="cuda")
+        iters, relres, ok = h.pcg(_t(Bm), X, rtol=1e-10, maxit=200)
+        assert ok
+        for j in range(nr):
+            xo, ko = ref[j]
+            assert abs(int(iters[j]) - ko) <= 1, (fp32, j, iters[j], ko)
+            assert _rel(X[j].cpu().numpy(), xo) < 1e-9, (fp32, j)
+        h.close()
