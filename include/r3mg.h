@@ -145,9 +145,10 @@ r3mg_status r3mg_update_values(r3mg_handle h, const double* vals_dev, void* stre
  *   degree  p in 1..3;   kappa  host float64 per cell, positive, or NULL for 1
  * The operator is applied to y = A v for a fixed pseudo-random v and compared with the CSR matrix; a maximum
  * difference above 1e-10 max|A v| (wrong degree, node order, geometry or quadrature) is R3MG_ERR_INVALID and
- * leaves the CSR matrix in use.  Once set, every single-right-hand-side application of the fine operator
- * (smoother, residual, PCG's A p) is matrix-free; multi-right-hand-side solves keep the CSR kernels.
- * Results then differ from the CSR path by rounding only.  Synchronises. */
+ * leaves the CSR matrix in use.  Once set, every application of the fine operator (smoother, residual, PCG's
+ * A p; one or several right-hand sides) is matrix-free.  Results then differ from the CSR path by rounding
+ * only.  Several right-hand sides need ncells (p+1)^d nrhs < 2^31 and n nrhs < 2^31 (R3MG_ERR_INVALID at the
+ * solve otherwise).  Synchronises. */
 r3mg_status r3mg_set_matrix_free(r3mg_handle h, const int32_t* cells, int64_t ncells, int degree, const double* kappa,
                                  void* stream);
 
