@@ -134,7 +134,7 @@ def test_adjoint_gradient_matches_oracle(adjoint_small):
         return np.linalg.solve(A.toarray(), rhs), A
     Lo, go, uo, lo = O.loss_and_gradient(solve, prob.cells, prob.Ke, kappa, prob.mass_rhs_weights, ut, prob.boundary)
     assert _rel(u.detach().cpu().numpy(), uo) < 1e-10
-    assert abs(float(L) - Lo) <= 1e-9 * Lo
+    assert abs(float(L.detach()) - Lo) <= 1e-9 * Lo
     assert _rel(g, go) < 1e-8
     # Euler identity: sum_e kappa_e g_e = -(u - u_t)^T u
     uu = u.detach().cpu().numpy()
