@@ -133,7 +133,7 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
   if (opt.leaf_size < 1 || opt.max_levels < 0 || opt.max_levels == 1 || opt.max_coarse_dofs < 1 ||
       opt.cheb_degree < 1 || opt.pre_steps < 0 || opt.post_steps < 0 || opt.lanczos_steps < 1 ||
       !(opt.cheb_boost > 0.0) || !(opt.cheb_ratio > 1.0) || opt.fine_kernel < -1 ||
-      opt.fine_kernel >= kStreamShapes || opt.multi_rhs_kernel < -1 || opt.multi_rhs_kernel > 3)
+      opt.fine_kernel >= kFineShapes || opt.multi_rhs_kernel < -1 || opt.multi_rhs_kernel > 3)
     throw err(R3MG_ERR_INVALID, "invalid option value");
   if (n < 1 || n >= (int64_t(1) << 31)) throw err(R3MG_ERR_INVALID, "n out of range");
   if (!coords || !row_ptr || !col_idx || !vals) throw err(R3MG_ERR_INVALID, "null input");
@@ -638,6 +638,16 @@ void encode_fine(Analysis& an) {
     });
     H.rowptr[H.n] = (int32_t)nnz;
     encode_local_blocks(H.rowptr.data(), col.data(), H.n, H.n, 0, H.loc);
+    // FP32 V-cycle: where the 2048-nonzero blocks need a second, mostly idle round of resident workgroups and
+    // 3072-nonzero blocks fit in one, the level takes the larger blocks (the same row sums in the same order)
+    if (an.opt.vcycle_fp32 && (int64_t)H.loc.rb.size() - 1 > kResidentBlocks) {
+      LocalBlocks l3;
+      encode_local_blocks(H.rowptr.data(), col.data(), H.n, H.n, 3, l3);
+      if ((int64_t)l3.rb.size() - 1 <= kResidentBlocks) {
+        H.loc = std::move(l3);
+        H.loc_geom = 3;
+      }
+    }
   }
 }
 

@@ -74,15 +74,19 @@ struct FineBlocks {
 // With partials != null (F_PLAIN only; shapes 0..8) the launch writes partial sums of u_i (A u)_i to
 // partials[0..np) and returns np (<= fb.nrb).
 constexpr int kCsrGeoms = 3;
-constexpr int kStreamShapes = 10;
+constexpr int kFineShapes = 10;    // shapes 0..9 serve the fine level
+constexpr int kStreamShapes = 11;  // shape 10: the vector kernel over geometry-3 blocks (agglomerated levels)
 constexpr int kLocalFirst = 6;
 constexpr int kStreamCapOf[kCsrGeoms] = {2048, 4096, 4096};
 constexpr int kStreamRowsOf[kCsrGeoms] = {64, 128, 64};
-constexpr int kLocalGeoms = 3;
-constexpr int kLocalCap[kLocalGeoms] = {2048, 4096, 4096};
-constexpr int kLocalRows[kLocalGeoms] = {64, 64, 128};
-constexpr int kLocalUcap[kLocalGeoms] = {256, 1024, 1024};
-constexpr int kLocalIdxBytes[kLocalGeoms] = {1, 2, 2};
+constexpr int kResidentBlocks = 2048;  // workgroups of 256 threads resident at once: 256 CUs x 8
+constexpr int kLocalGeoms = 3;     // local geometries of the fine level (shapes 6..8)
+constexpr int kLocalGeomsAll = 4;  // geometry 3 (1-byte positions, 3072 nonzeros, 64 rows, 256 columns): the 2D
+                                   // agglomerated levels, whose rows of ~70 nonzeros fill larger blocks
+constexpr int kLocalCap[kLocalGeomsAll] = {2048, 4096, 4096, 3072};
+constexpr int kLocalRows[kLocalGeomsAll] = {64, 64, 128, 64};
+constexpr int kLocalUcap[kLocalGeomsAll] = {256, 1024, 1024, 256};
+constexpr int kLocalIdxBytes[kLocalGeomsAll] = {1, 2, 2, 1};
 constexpr int kFinePad = 4;
 template <typename T>
 int launch_level_stream(int shape, const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,

@@ -100,7 +100,8 @@ struct HostLevel {           // agglomerated level l >= 1 (boxes of the R-tree a
   // l < L, when no block row is wider than 256 columns: the level as CSR (row (K, q) starts at
   // B^2 bptr[K] + q nb_K B) and its 1-byte local-column row blocks
   std::vector<int32_t> rowptr;
-  LocalBlocks loc;
+  LocalBlocks loc;   // local-column blocks of geometry loc_geom (0: 2048 nonzeros, 3: 3072 nonzeros)
+  int loc_geom = 0;
 };
 
 struct Analysis {
@@ -198,9 +199,9 @@ struct DevLevel {
   double lam_hi = 0, lam_lo = 0, lam_hat = 0;
   int lanes = 8;  // lanes per row of the SpMV kernels
   DBuf<int32_t> rb[3];  // l = 0: CSR row blocks of the single-RHS row-block kernels, per geometry
-  DBuf<int32_t> lrb[3], lubp[3], lucol[3];  // l = 0: local-column row blocks, per geometry
-  DBuf<uint8_t> lidx[3];
-  DBuf<int32_t> lmeta[3];  // l = 0: per-block records of the local-column blocks (FineBlocks::meta)
+  DBuf<int32_t> lrb[kLocalGeomsAll], lubp[kLocalGeomsAll], lucol[kLocalGeomsAll];  // local-column blocks per geometry
+  DBuf<uint8_t> lidx[kLocalGeomsAll];
+  DBuf<int32_t> lmeta[kLocalGeomsAll];  // per-block records of the local-column blocks (FineBlocks::meta)
   FineBlocks fb[kStreamShapes];  // l = 0: row blocks of every kernel shape
   double shape_bytes[kStreamShapes] = {};  // algorithmic bytes of one application with each shape
   int shape = 0;        // l = 0: kernel shape chosen by timing at set-up

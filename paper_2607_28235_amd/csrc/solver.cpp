@@ -191,7 +191,7 @@ constexpr int kCodeSplit = 100;
 // lanes-per-row kernel otherwise.
 LevelKernel level_kernel(const Analysis& an, const DevLevel& D, int l, int nr, int esz) {
   if (l == 0 && D.mf) return LevelKernel::MatFree;
-  if (nr == 1 && D.fb[D.shape].nrb > 0 && (l == 0 || D.shape == kLocalFirst + kLocalGeoms)) return LevelKernel::Stream;
+  if (nr == 1 && D.fb[D.shape].nrb > 0 && (l == 0 || D.shape >= kLocalFirst + kLocalGeoms)) return LevelKernel::Stream;
   if (l > 0 && nr == 1 && D.maxnb > 0 && an.B >= 8 && (int64_t)D.maxnb * an.B >= 256 &&
       (int64_t)D.maxnb * an.B * esz <= 65536)
     return LevelKernel::BlockRowWG;
@@ -205,10 +205,11 @@ std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int 
   switch (level_kernel(an, D, l, 1, esz)) {
     case LevelKernel::Stream:
       if (D.shape >= kLocalFirst) {
-        const int g = D.shape == kLocalFirst + kLocalGeoms ? 0 : D.shape - kLocalFirst;
+        const bool vec = D.shape >= kLocalFirst + kLocalGeoms;  // shapes 9 (geometry 0) and 10 (geometry 3)
+        const int g = !vec ? D.shape - kLocalFirst : D.shape == kLocalFirst + kLocalGeoms ? 0 : 3;
         return std::string("k_level_local<") + t + ",u" + std::to_string(8 * kLocalIdxBytes[g]) + "," +
                std::to_string(kLocalCap[g]) + "," + std::to_string(kLocalRows[g]) + "," +
-               std::to_string(kLocalUcap[g]) + (D.shape == kLocalFirst + kLocalGeoms ? ",vec>" : ",block>");
+               std::to_string(kLocalUcap[g]) + (vec ? ",vec>" : ",block>");
       }
       return std::string("k_level_stream<") + t + "," + std::to_string(kStreamCapOf[D.shape % kCsrGeoms]) + "," +
              std::to_string(kStreamRowsOf[D.shape % kCsrGeoms]) + (D.shape >= kCsrGeoms ? ",pipe16>" : ",block>");
@@ -721,7 +722,7 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
   float best[kStreamShapes];
   for (int sh = 0; sh < kStreamShapes; ++sh) best[sh] = 1e30f;
   for (int round = 0; round < 2; ++round) {
-    for (int sh = 0; sh < kStreamShapes; ++sh) {
+    for (int sh = 0; sh < kFineShapes; ++sh) {
       float ms;
       if (c.fp32) {
         LevelOp<float> op = level_op<float>(c, 0);
@@ -742,7 +743,7 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
     }
   }
   int bestS = 0;
-  for (int sh = 1; sh < kStreamShapes; ++sh)
+  for (int sh = 1; sh < kFineShapes; ++sh)
     if (best[sh] < 0.97f * best[bestS]) bestS = sh;
   D.shape = bestS;
   D.bytes_apply = D.shape_bytes[D.shape];
@@ -752,7 +753,7 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
 
 // uploads local-column row blocks into slot g of a level and points the kernel shape kLocalFirst + g at them
 static void upload_local(DevLevel& D, int g, const LocalBlocks& lb, const std::vector<int32_t>& rowptr,
-                         hipStream_t s) {
+                         hipStream_t s, int slot = -1) {
   D.lrb[g].upload(lb.rb, s);
   D.lubp[g].upload(lb.ubp, s);
   D.lucol[g].upload(lb.ucol, s);
@@ -764,7 +765,7 @@ static void upload_local(DevLevel& D, int g, const LocalBlocks& lb, const std::v
     meta[4 * b + 2] = lb.ubp[b];
   }
   D.lmeta[g].upload(meta, s);
-  FineBlocks& f = D.fb[kLocalFirst + g];
+  FineBlocks& f = D.fb[slot >= 0 ? slot : kLocalFirst + g];
   f.nrb = (int)lb.rb.size() - 1;
   f.rb = D.lrb[g].p;
   f.ubp = D.lubp[g].p;
@@ -875,10 +876,11 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     D.bytes_apply = (double)D.nnz * sv + (double)nblk * 4 + (double)(H.nbox + 1) * 4 + 7.0 * D.n * sv;
     if (!H.rowptr.empty()) {  // narrow block rows: the level is also held as 1-byte local-column blocks
       D.rowptr.upload(H.rowptr, s);
-      upload_local(D, 0, H.loc, H.rowptr, s);
-      D.fb[kLocalFirst + kLocalGeoms] = D.fb[kLocalFirst];
-      D.shape = kLocalFirst + kLocalGeoms;
-      D.bytes_apply = local_bytes(D.nnz, D.n, 0, H.loc, sv);
+      // the vector kernel: shape 9 over 2048-nonzero blocks, shape 10 over 3072-nonzero blocks
+      D.shape = kLocalFirst + kLocalGeoms + (H.loc_geom == 3 ? 1 : 0);
+      upload_local(D, H.loc_geom, H.loc, H.rowptr, s, D.shape);
+      D.shape_bytes[D.shape] = local_bytes(D.nnz, D.n, H.loc_geom, H.loc, sv);
+      D.bytes_apply = D.shape_bytes[D.shape];
     }
   }
   numeric_setup(h, s);

@@ -288,15 +288,23 @@ def test_full_size_2d_q3_pcg(full2d, fp32):
     r = c.b - c.prob.scipy() @ xs
     assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(c.b)
     assert _rel(xs, c.xo) < 1e-9
-    # sampled V-cycle parity at full size (float64 path only)
+    # V-cycle parity at full size.  FP32 V-cycle: level 1 (2,554 blocks of 2048 nonzeros, more than the 2,048
+    # resident workgroups) is applied over 3072-nonzero blocks; the bar is rounding of float32 level values and
+    # vectors through 3 smoothed levels (13 level applications each), well above eps32 = 6e-8 times that depth
+    # (measured: 4.2e-7)
+    g = np.random.default_rng(11)
+    rv = g.standard_normal(c.prob.n)
+    rv[c.ho.constrained] = 0.0
+    z = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+    h.vcycle(_t(rv), z)
+    torch.cuda.synchronize()
+    err = _rel(z.cpu().numpy(), O.vcycle(c.ho, rv))
+    print(f"full2d fp32={fp32}: V-cycle relative difference from the oracle {err:.2e}")
     if not fp32:
-        g = np.random.default_rng(11)
-        rv = g.standard_normal(c.prob.n)
-        rv[c.ho.constrained] = 0.0
-        z = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
-        h.vcycle(_t(rv), z)
-        torch.cuda.synchronize()
-        assert _rel(z.cpu().numpy(), O.vcycle(c.ho, rv)) < 1e-11
+        assert err < 1e-11
+    else:
+        assert "3072" in h.info()[1]["kernel"] and "2048" in h.info()[2]["kernel"], h.info()
+        assert err < 2e-5, err
 
 
 @pytest.mark.parametrize("shape", list(range(10)))
