@@ -38,7 +38,9 @@ typedef struct r3mg_handle_* r3mg_handle;
 
 /* Largest coarsest level, in DoFs, that the dense float64 Cholesky inverse takes: two n x n float64 arrays,
    2 x 34 GB at this size.  The paper's coarsest solve is a sparse direct one (Section 6); this library inverts
-   the coarsest operator densely on the device, which fits HBM up to this size. */
+   the coarsest operator densely on the device, which fits HBM up to this size.  Up to 10,240 DoFs the inverse's
+   upper-triangular 64 x 64 tiles are kept as well (about half its size), and V-cycles over up to 4 right-hand
+   sides read those instead of the whole inverse. */
 #define R3MG_MAX_COARSEST_DOFS 65536
 
 typedef enum {

@@ -135,6 +135,17 @@ void launch_vc_exit(int n, int nr, const int* perm, const T* x0, const T* dpend,
                     hipStream_t s);
 template <typename T>
 void launch_dense_apply(int nc, int nr, const double* cinv, const T* b, T* x, const int* skip, hipStream_t s);
+// The same product with the symmetric inverse read once: its upper-triangular 64 x 64 tiles (I <= J), listed in
+// `tiles` as (I, J) pairs and packed in that order, each row-major and zero beyond nc.  Pass 1 forms every
+// tile's row products and, off the diagonal, its transposed products, into part (nt x nt x 64 x nr float64,
+// slot (R, S) of row block R); pass 2 sums each row block's nt slots in index order.  nr = 1, 2 or 4.
+constexpr int kDenseTile = 64;
+constexpr int kDenseSymMaxTiles = 160;  // coarsest sizes up to 10,240: 422 MB of packed tiles at most
+constexpr int kDenseSymMaxNR = 4;
+void launch_dense_pack_sym(int nc, int ntiles, const double* full, const int* tiles, double* packed, hipStream_t s);
+template <typename T>
+void launch_dense_apply_sym(int nc, int nt, int nr, const double* packed, const int* tiles, double* part,
+                            const T* b, T* x, const int* skip, hipStream_t s);
 void launch_gather_cols(int n, int nr, int nuser, const int* perm, const double* user, int64_t ld_user,
                         double* out, hipStream_t s);
 void launch_scatter_cols(int n, int nr, int nuser, const int* perm, const double* in, double* user,

@@ -1903,6 +1903,128 @@ void launch_dense_apply(int nc, int nr, const double* cinv, const T* b, T* x, co
 template void launch_dense_apply<float>(int, int, const double*, const float*, float*, const int*, hipStream_t);
 template void launch_dense_apply<double>(int, int, const double*, const double*, double*, const int*, hipStream_t);
 
+// Symmetric dense coarsest product.  Pass 1: one workgroup per upper tile (I, J); wave w holds the tile's rows
+// 16 w .. 16 w + 15 in registers, lane = column.  The row products are summed over the 64 lanes by a transposing
+// butterfly (each step halves the rows a lane keeps and doubles the columns summed), which leaves lane l with
+// row 8 b5 + 4 b4 + 2 b3 + b2 of its wave (b = bits of l); the transposed products of an off-diagonal tile are
+// summed over the four waves in order.
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_dense_sym_tiles(int nc, int nt, const double* __restrict__ packed,
+                                                         const int2* __restrict__ tiles, const T* __restrict__ b,
+                                                         double* part, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double sh[4][64];
+  const int t = blockIdx.x;
+  const int2 ij = tiles[t];
+  const int I = ij.x, J = ij.y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double* a = packed + (int64_t)t * (kDenseTile * kDenseTile) + (16 * w) * kDenseTile + lane;
+  double m[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) m[k] = a[k * kDenseTile];
+  const int cj = J * kDenseTile + lane;
+  const int ri = I * kDenseTile + 16 * w;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+  const int myrow = (b5 ? 8 : 0) + (b4 ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
+  for (int c = 0; c < NR; ++c) {
+    const double xj = cj < nc ? (double)b[(int64_t)cj * NR + c] : 0.0;
+    double h8[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double lo = m[q] * xj, hi = m[8 + q] * xj;
+      h8[q] = (b5 ? hi : lo) + __shfl_xor(b5 ? lo : hi, 32, 64);
+    }
+    double h4[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h4[q] = (b4 ? h8[4 + q] : h8[q]) + __shfl_xor(b4 ? h8[q] : h8[4 + q], 16, 64);
+    double h2[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) h2[q] = (b3 ? h4[2 + q] : h4[q]) + __shfl_xor(b3 ? h4[q] : h4[2 + q], 8, 64);
+    double h1 = (b2 ? h2[1] : h2[0]) + __shfl_xor(b2 ? h2[0] : h2[1], 4, 64);
+    h1 += __shfl_xor(h1, 2, 64);
+    h1 += __shfl_xor(h1, 1, 64);
+    if ((lane & 3) == 0)
+      part[(((int64_t)I * nt + J) * kDenseTile + 16 * w + myrow) * NR + c] = h1;
+    if (I != J) {  // uniform over the workgroup
+      double cs = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int r = ri + k;
+        cs += m[k] * (r < nc ? (double)b[(int64_t)r * NR + c] : 0.0);
+      }
+      sh[w][lane] = cs;
+      __syncthreads();
+      if (w == 0)
+        part[(((int64_t)J * nt + I) * kDenseTile + lane) * NR + c] = (sh[0][lane] + sh[1][lane]) +
+                                                                      (sh[2][lane] + sh[3][lane]);
+      __syncthreads();
+    }
+  }
+}
+
+// Pass 2: rows 16 Q .. 16 Q + 15 of row block R = blockIdx.x / 4 (Q = blockIdx.x % 4) sum their nt slots: slot
+// S is taken by group S % 16 in index order, then the 16 groups are added in order.
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_dense_sym_reduce(int nc, int nt, const double* __restrict__ part, T* x,
+                                                          const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double sh[16][17];
+  const int R = blockIdx.x >> 2, i = 16 * (blockIdx.x & 3) + (threadIdx.x & 15), g = threadIdx.x >> 4;
+  const int row = R * kDenseTile + i;
+  for (int c = 0; c < NR; ++c) {
+    double acc = 0;
+#pragma unroll 4
+    for (int S = g; S < nt; S += 16) acc += part[(((int64_t)R * nt + S) * kDenseTile + i) * NR + c];
+    sh[g][threadIdx.x & 15] = acc;
+    __syncthreads();
+    if (g == 0 && row < nc) {
+      double t = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) t += sh[k][threadIdx.x & 15];
+      x[(int64_t)row * NR + c] = (T)t;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dense_pack_sym(int nc, const double* __restrict__ full,
+                                                        const int2* __restrict__ tiles, double* packed) {
+  const int t = blockIdx.x;
+  const int2 ij = tiles[t];
+  for (int e = threadIdx.x; e < kDenseTile * kDenseTile; e += 256) {
+    const int i = ij.x * kDenseTile + e / kDenseTile, j = ij.y * kDenseTile + e % kDenseTile;
+    packed[(int64_t)t * (kDenseTile * kDenseTile) + e] = (i < nc && j < nc) ? full[(int64_t)i * nc + j] : 0.0;
+  }
+}
+void launch_dense_pack_sym(int nc, int ntiles, const double* full, const int* tiles, double* packed, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_pack_sym, dim3(ntiles), dim3(256), 0, s, nc, full,
+                     reinterpret_cast<const int2*>(tiles), packed);
+  check_launch("k_dense_pack_sym");
+}
+
+template <typename T>
+void launch_dense_apply_sym(int nc, int nt, int nr, const double* packed, const int* tiles, double* part,
+                            const T* b, T* x, const int* skip, hipStream_t s) {
+  const int ntiles = nt * (nt + 1) / 2;
+  const int2* tl = reinterpret_cast<const int2*>(tiles);
+  switch (nr) {
+#define R3_DS(NRV)                                                                                               \
+  hipLaunchKernelGGL((k_dense_sym_tiles<T, NRV>), dim3(ntiles), dim3(256), 0, s, nc, nt, packed, tl, b, part, skip); \
+  hipLaunchKernelGGL((k_dense_sym_reduce<T, NRV>), dim3(4 * nt), dim3(256), 0, s, nc, nt, part, x, skip);       \
+  break;
+    case 1: R3_DS(1)
+    case 2: R3_DS(2)
+    case 4: R3_DS(4)
+#undef R3_DS
+    default: throw std::runtime_error("symmetric dense coarsest product: unsupported nrhs block");
+  }
+  check_launch("k_dense_sym");
+}
+template void launch_dense_apply_sym<float>(int, int, int, const double*, const int*, double*, const float*, float*,
+                                            const int*, hipStream_t);
+template void launch_dense_apply_sym<double>(int, int, int, const double*, const int*, double*, const double*,
+                                             double*, const int*, hipStream_t);
+
 __global__ void k_gather_cols(int n, int nr, int nuser, const int* __restrict__ perm,
                               const double* __restrict__ user, int64_t ld, double* out) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;

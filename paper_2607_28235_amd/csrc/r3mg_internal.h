@@ -228,9 +228,13 @@ struct PcgScalars;  // device-side PCG state (defined in the solver)
 struct Device {
   int dev = 0;
   std::vector<DevLevel> lv;
-  // dense coarsest: inverse (nL x nL float64, row-major)
+  // dense coarsest: inverse (nL x nL float64, row-major); for up to kDenseSymMaxTiles tile rows also its upper
+  // 64 x 64 tiles packed (csym, tile list ctile) and the pass-1 slots for up to 4 columns (cpart)
   DBuf<double> cinv;
   int64_t nc = 0;
+  DBuf<double> csym, cpart;
+  DBuf<int32_t> ctile;
+  int ct = 0;  // tile rows of csym; 0 = the full inverse only
   // fine-level helpers
   DBuf<int32_t> perm;   // internal -> user
   DBuf<int64_t> src;    // internal nnz -> user nnz

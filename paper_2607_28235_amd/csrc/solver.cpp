@@ -507,7 +507,10 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   T* b = b_override ? const_cast<T*>(b_override) : vbuf<T>(D.b);
   T* x = vbuf<T>(D.x);
   if (l == L) {
-    launch_dense_apply<T>((int)dv.nc, nr, dv.cinv.p, b, x, skip, s);
+    if (dv.ct > 0 && nr <= kDenseSymMaxNR)
+      launch_dense_apply_sym<T>((int)dv.nc, dv.ct, nr, dv.csym.p, dv.ctile.p, dv.cpart.p, b, x, skip, s);
+    else
+      launch_dense_apply<T>((int)dv.nc, nr, dv.cinv.p, b, x, skip, s);
     return nullptr;
   }
   const r3mg_options& o = an.opt;
@@ -699,6 +702,29 @@ void numeric_setup(HandleImpl& h, hipStream_t s) {
     R3MG_HIP_CHECK(hipMemcpyAsync(&bad, dv.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
     R3MG_HIP_CHECK(hipStreamSynchronize(s));
     if (bad) throw Error{R3MG_ERR_NOT_SPD, "coarsest operator is not positive definite"};
+    // the symmetric inverse's upper tiles, read once per product by up to kDenseSymMaxNR columns (the pass-1
+    // slots cost nr/16 of the bytes saved, so wider blocks keep the full inverse)
+    const int nt = (int)((D.n + kDenseTile - 1) / kDenseTile);
+    dv.ct = 0;
+    dv.csym.release();
+    dv.cpart.release();
+    dv.ctile.release();
+    if (nt <= kDenseSymMaxTiles) {
+      std::vector<int32_t> tl;
+      tl.reserve((size_t)nt * (nt + 1));
+      for (int I = 0; I < nt; ++I)
+        for (int J = I; J < nt; ++J) {
+          tl.push_back(I);
+          tl.push_back(J);
+        }
+      const int ntiles = nt * (nt + 1) / 2;
+      dv.ctile.upload(tl, s);
+      dv.csym.alloc((size_t)ntiles * kDenseTile * kDenseTile);
+      dv.cpart.alloc((size_t)nt * nt * kDenseTile * kDenseSymMaxNR);
+      launch_dense_pack_sym((int)D.n, ntiles, dv.cinv.p, dv.ctile.p, dv.csym.p, s);
+      R3MG_HIP_CHECK(hipStreamSynchronize(s));
+      dv.ct = nt;
+    }
   }
   drop_graphs(dv);
 }
