@@ -72,13 +72,15 @@ typedef struct {
   int vcycle_fp32;      /* 0 = float64 V-cycle; 1 = float32 V-cycle inside float64 CG [0] */
   int use_graph;        /* 1 = replay PCG iterations from a captured hipGraph [1] */
   int fine_kernel;      /* row-block kernel of the fine level for one right-hand side: -1 = the fastest of
-                           shapes 0..9 timed at r3mg_factor [-1]; 0..9 = that shape.  0..2: CSR row blocks of
+                           shapes 0..10 timed at r3mg_factor [-1]; 0..10 = that shape.  0..2: CSR row blocks of
                            (2048 nonzeros, 64 rows), (4096, 128), (4096, 64); 3..5: the same blocks in a
                            persistent pipelined kernel; 6..8: local-column blocks (each block's distinct columns
                            staged once; 1-byte positions with 2048 nonzeros, 64 rows, 256 columns; 2-byte with
-                           (4096, 64, 1024) and (4096, 128, 1024)); 9: shape 6 with vector loads.  Every shape sums a row
-                           in the same order, so results do not depend on this choice when no row has more than
-                           256 nonzeros. */
+                           (4096, 64, 1024) and (4096, 128, 1024)); 9: shape 6 with vector loads; 10: the
+                           kernel of shape 9 over 1-byte blocks of (3072 nonzeros, 128 rows, 256 columns).  With
+                           the float32 V-cycle, PCG's float64 operator takes the fastest shape in float64, timed
+                           separately.  Every shape sums a row in the same order, so results do not depend on this
+                           choice when no row has more than 256 nonzeros. */
   int multi_rhs_kernel; /* fine-level kernel for several right-hand sides: -1 = the fastest timed at the first
                            multi-RHS solve [-1]; 0 = lanes-per-row CSR kernel (each lane all columns of its
                            nonzeros); 1 / 2 = local-column blocks with 1- / 2-byte positions (each block's distinct

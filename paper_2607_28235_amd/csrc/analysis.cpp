@@ -614,7 +614,7 @@ static void encode_local_blocks(const int32_t* rowptr, const int32_t* col, int64
 
 void encode_fine(Analysis& an) {
   encode_csr_blocks(an);
-  for (int g = 0; g < kLocalGeoms; ++g) encode_local_blocks(an.rowptr.data(), an.col.data(), an.n, an.n, g, an.loc[g]);
+  for (int g = 0; g <= kLocalGeoms; ++g) encode_local_blocks(an.rowptr.data(), an.col.data(), an.n, an.n, g, an.loc[g]);
   // agglomerated levels with narrow block rows (the 2D hierarchies): CSR row pointers and 1-byte local blocks
   const int L = an.nlevels() - 1;
   const int B = an.B;
@@ -641,11 +641,11 @@ void encode_fine(Analysis& an) {
     // FP32 V-cycle: where the 2048-nonzero blocks need a second, mostly idle round of resident workgroups and
     // 3072-nonzero blocks fit in one, the level takes the larger blocks (the same row sums in the same order)
     if (an.opt.vcycle_fp32 && (int64_t)H.loc.rb.size() - 1 > kResidentBlocks) {
-      LocalBlocks l3;
-      encode_local_blocks(H.rowptr.data(), col.data(), H.n, H.n, 3, l3);
-      if ((int64_t)l3.rb.size() - 1 <= kResidentBlocks) {
-        H.loc = std::move(l3);
-        H.loc_geom = 3;
+      LocalBlocks l4;
+      encode_local_blocks(H.rowptr.data(), col.data(), H.n, H.n, 4, l4);
+      if ((int64_t)l4.rb.size() - 1 <= kResidentBlocks) {
+        H.loc = std::move(l4);
+        H.loc_geom = 4;
       }
     }
   }

@@ -70,23 +70,27 @@ struct FineBlocks {
 //         columns), (2-byte, 4096, 64, 1024), (2-byte, 4096, 128, 1024); blocks of several rows hold at most
 //         capacity - 3 nonzeros;
 //   9     the blocks of shape 6 with 16-byte value loads and 4-byte loads of four packed positions (values and
-//         positions must carry kFinePad padding entries).
+//         positions must carry kFinePad padding entries);
+//   10    the kernel of shape 9 over 1-byte local-column blocks of (3072 nonzeros, 128 rows, 256 columns)
+//         (local geometry 3), which keep half again as many loads in flight per workgroup;
+//   11    the kernel of shape 9 over (3072, 64, 256) blocks (local geometry 4): agglomerated levels only.
 // With partials != null (F_PLAIN only; shapes 0..8) the launch writes partial sums of u_i (A u)_i to
 // partials[0..np) and returns np (<= fb.nrb).
 constexpr int kCsrGeoms = 3;
-constexpr int kFineShapes = 10;    // shapes 0..9 serve the fine level
-constexpr int kStreamShapes = 11;  // shape 10: the vector kernel over geometry-3 blocks (agglomerated levels)
+constexpr int kFineShapes = 11;    // shapes 0..10 serve the fine level
+constexpr int kStreamShapes = 12;  // shape 11: the vector kernel over geometry-4 blocks (agglomerated levels)
 constexpr int kLocalFirst = 6;
 constexpr int kStreamCapOf[kCsrGeoms] = {2048, 4096, 4096};
 constexpr int kStreamRowsOf[kCsrGeoms] = {64, 128, 64};
 constexpr int kResidentBlocks = 2048;  // workgroups of 256 threads resident at once: 256 CUs x 8
-constexpr int kLocalGeoms = 3;     // local geometries of the fine level (shapes 6..8)
-constexpr int kLocalGeomsAll = 4;  // geometry 3 (1-byte positions, 3072 nonzeros, 64 rows, 256 columns): the 2D
-                                   // agglomerated levels, whose rows of ~70 nonzeros fill larger blocks
-constexpr int kLocalCap[kLocalGeomsAll] = {2048, 4096, 4096, 3072};
-constexpr int kLocalRows[kLocalGeomsAll] = {64, 64, 128, 64};
-constexpr int kLocalUcap[kLocalGeomsAll] = {256, 1024, 1024, 256};
-constexpr int kLocalIdxBytes[kLocalGeomsAll] = {1, 2, 2, 1};
+constexpr int kLocalGeoms = 3;     // local geometries of the block kernels (shapes 6..8)
+constexpr int kLocalGeomsAll = 5;  // geometries 3 and 4 (1-byte positions, 3072 nonzeros, 256 columns) are read by
+                                   // the vector kernel only: 128-row blocks on the fine level (shape 10), 64-row
+                                   // blocks on the 2D agglomerated levels, whose rows hold ~70 nonzeros (shape 11)
+constexpr int kLocalCap[kLocalGeomsAll] = {2048, 4096, 4096, 3072, 3072};
+constexpr int kLocalRows[kLocalGeomsAll] = {64, 64, 128, 128, 64};
+constexpr int kLocalUcap[kLocalGeomsAll] = {256, 1024, 1024, 256, 256};
+constexpr int kLocalIdxBytes[kLocalGeomsAll] = {1, 2, 2, 1, 1};
 constexpr int kFinePad = 4;
 template <typename T>
 int launch_level_stream(int shape, const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,

@@ -925,7 +925,8 @@ int launch_level_stream(int shape, const FineBlocks& fb, const LevelOp<T>& op, c
     case 7: np = launch_stream_local<T, uint16_t, 4096, 64, 1024>(R3MG_ARGS); break;
     case 8: np = launch_stream_local<T, uint16_t, 4096, 128, 1024>(R3MG_ARGS); break;
     case 9: np = launch_stream_local_vec<T, 2048, 64, 256>(R3MG_ARGS); break;
-    case 10: np = launch_stream_local_vec<T, 3072, 64, 256>(R3MG_ARGS); break;
+    case 10: np = launch_stream_local_vec<T, 3072, 128, 256>(R3MG_ARGS); break;
+    case 11: np = launch_stream_local_vec<T, 3072, 64, 256>(R3MG_ARGS); break;
     default: throw std::runtime_error("unknown row-block shape");
   }
 #undef R3MG_ARGS

@@ -100,7 +100,7 @@ struct HostLevel {           // agglomerated level l >= 1 (boxes of the R-tree a
   // l < L, when no block row is wider than 256 columns: the level as CSR (row (K, q) starts at
   // B^2 bptr[K] + q nb_K B) and its 1-byte local-column row blocks
   std::vector<int32_t> rowptr;
-  LocalBlocks loc;   // local-column blocks of geometry loc_geom (0: 2048 nonzeros, 3: 3072 nonzeros)
+  LocalBlocks loc;   // local-column blocks of geometry loc_geom (0: 2048 nonzeros, 4: 3072 nonzeros)
   int loc_geom = 0;
 };
 
@@ -117,7 +117,7 @@ struct Analysis {
   // fine-level row blocks: CSR geometries (2048/64, 4096/128, 4096/64 nonzeros/rows) and local-column
   // geometries (block offsets, distinct-column offsets and lists, local column index bytes per nonzero)
   std::vector<int32_t> rb[3];
-  LocalBlocks loc[3];
+  LocalBlocks loc[4];
   std::vector<uint8_t> constrained;      // internal order
   std::vector<uint8_t> constrained_user; // caller's order
   std::vector<int32_t> owner;            // internal point -> level-1 box, -1 if constrained
@@ -205,6 +205,7 @@ struct DevLevel {
   FineBlocks fb[kStreamShapes];  // l = 0: row blocks of every kernel shape
   double shape_bytes[kStreamShapes] = {};  // algorithmic bytes of one application with each shape
   int shape = 0;        // l = 0: kernel shape chosen by timing at set-up
+  int shape64 = 0;      // l = 0: shape of the float64 operator PCG applies (with a float64 V-cycle: shape)
   int maxnb = 0;     // l >= 1: largest number of stored blocks in a block row
   // transfer to the next level
   DBuf<double> xi64;     // l = 0: n x d

@@ -205,8 +205,8 @@ std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int 
   switch (level_kernel(an, D, l, 1, esz)) {
     case LevelKernel::Stream:
       if (D.shape >= kLocalFirst) {
-        const bool vec = D.shape >= kLocalFirst + kLocalGeoms;  // shapes 9 (geometry 0) and 10 (geometry 3)
-        const int g = !vec ? D.shape - kLocalFirst : D.shape == kLocalFirst + kLocalGeoms ? 0 : 3;
+        const bool vec = D.shape >= kLocalFirst + kLocalGeoms;  // shapes 9, 10, 11: geometries 0, 3, 4
+        const int g = !vec ? D.shape - kLocalFirst : D.shape == kLocalFirst + kLocalGeoms ? 0 : D.shape - 7;
         return std::string("k_level_local<") + t + ",u" + std::to_string(8 * kLocalIdxBytes[g]) + "," +
                std::to_string(kLocalCap[g]) + "," + std::to_string(kLocalRows[g]) + "," +
                std::to_string(kLocalUcap[g]) + (vec ? ",vec>" : ",block>");
@@ -248,12 +248,13 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
       }
       break;
     }
-    case LevelKernel::Stream:
+    case LevelKernel::Stream: {
       op.ptr = D.rowptr.p;  // CSR row pointers (coarse levels: of the block-row layout)
       op.idx = D.col.p;     // CSR columns (fine level only; coarse rows never take the long-row path)
-      launch_level_stream<T>(D.shape, D.fb[D.shape], op, u, b, rho, x, dout, c1, c2, flags, skip,
-                             nullptr, s);
+      const int sh = (l == 0 && sizeof(T) == 8) ? D.shape64 : D.shape;
+      launch_level_stream<T>(sh, D.fb[sh], op, u, b, rho, x, dout, c1, c2, flags, skip, nullptr, s);
       break;
+    }
     case LevelKernel::BlockRowWG:
       launch_level_blockrow_wg<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags, skip, s);
       break;
@@ -738,7 +739,7 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
   ensure_level_vectors(c, 1);
   DevLevel& D = dv.lv[0];
   if (an.opt.fine_kernel >= 0) {
-    D.shape = an.opt.fine_kernel;
+    D.shape = D.shape64 = an.opt.fine_kernel;
     D.bytes_apply = D.shape_bytes[D.shape];
     return;
   }
@@ -771,10 +772,32 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
   int bestS = 0;
   for (int sh = 1; sh < kFineShapes; ++sh)
     if (best[sh] < 0.97f * best[bestS]) bestS = sh;
-  D.shape = bestS;
+  D.shape = D.shape64 = bestS;
   D.bytes_apply = D.shape_bytes[D.shape];
   R3MG_HIP_CHECK(hipMemsetAsync(D.x.p, 0, D.x.n, s));
   R3MG_HIP_CHECK(hipMemsetAsync(D.rho.p, 0, D.rho.n, s));
+  if (!c.fp32) return;
+  // float32 V-cycle: PCG's float64 operator y = A p is timed on its own (the float64 values double the LDS
+  // staging, so another shape can win); the same two rounds and 3% rule
+  DBuf<double> u64, y64;
+  u64.alloc((size_t)an.n);
+  y64.alloc((size_t)an.n);
+  R3MG_HIP_CHECK(hipMemsetAsync(u64.p, 0, u64.n * sizeof(double), s));
+  LevelOp<double> op = level_op<double>(c, 0);
+  for (int sh = 0; sh < kStreamShapes; ++sh) best[sh] = 1e30f;
+  for (int round = 0; round < 2; ++round)
+    for (int sh = 0; sh < kFineShapes; ++sh) {
+      const float ms = time_launches(s, 20, [&] {
+        launch_level_stream<double>(sh, D.fb[sh], op, u64.p, nullptr, y64.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN,
+                                    nullptr, nullptr, s);
+      });
+      best[sh] = std::min(best[sh], ms);
+    }
+  bestS = 0;
+  for (int sh = 1; sh < kFineShapes; ++sh)
+    if (best[sh] < 0.97f * best[bestS]) bestS = sh;
+  D.shape64 = bestS;
+  R3MG_HIP_CHECK(hipStreamSynchronize(s));
 }
 
 // uploads local-column row blocks into slot g of a level and points the kernel shape kLocalFirst + g at them
@@ -857,9 +880,11 @@ void device_setup(HandleImpl& h, hipStream_t s) {
       upload_local(D, g, an.loc[g], an.rowptr, s);
       D.shape_bytes[kLocalFirst + g] = local_bytes(an.nnz, an.n, g, an.loc[g], sv0);
     }
-    // shape 9: the vector-load kernel over the blocks of local geometry 0
+    // shape 9: the vector-load kernel over the blocks of local geometry 0; shape 10: the same over geometry 3
     D.fb[kLocalFirst + kLocalGeoms] = D.fb[kLocalFirst];
     D.shape_bytes[kLocalFirst + kLocalGeoms] = D.shape_bytes[kLocalFirst];
+    upload_local(D, 3, an.loc[3], an.rowptr, s, kLocalFirst + kLocalGeoms + 1);
+    D.shape_bytes[kLocalFirst + kLocalGeoms + 1] = local_bytes(an.nnz, an.n, 3, an.loc[3], sv0);
     D.dinv64.alloc(D.n);
     if (fp32) {
       D.xi32.alloc(D.xi64.n);
@@ -902,8 +927,8 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     D.bytes_apply = (double)D.nnz * sv + (double)nblk * 4 + (double)(H.nbox + 1) * 4 + 7.0 * D.n * sv;
     if (!H.rowptr.empty()) {  // narrow block rows: the level is also held as 1-byte local-column blocks
       D.rowptr.upload(H.rowptr, s);
-      // the vector kernel: shape 9 over 2048-nonzero blocks, shape 10 over 3072-nonzero blocks
-      D.shape = kLocalFirst + kLocalGeoms + (H.loc_geom == 3 ? 1 : 0);
+      // the vector kernel: shape 9 over 2048-nonzero blocks, shape 11 over (3072, 64-row) blocks
+      D.shape = H.loc_geom == 4 ? kLocalFirst + kLocalGeoms + 2 : kLocalFirst + kLocalGeoms;
       upload_local(D, H.loc_geom, H.loc, H.rowptr, s, D.shape);
       D.shape_bytes[D.shape] = local_bytes(D.nnz, D.n, H.loc_geom, H.loc, sv);
       D.bytes_apply = D.shape_bytes[D.shape];
@@ -1013,7 +1038,7 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
   } else if (NR == 1 && D0.fb[D0.shape].nrb > 0) {
     // q = A p with the fine row-block kernel, then <p, q> in a fixed partition: the iterates do not depend on
     // the kernel shape chosen by timing
-    launch_level_stream<double>(D0.shape, D0.fb[D0.shape], op64, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0,
+    launch_level_stream<double>(D0.shape64, D0.fb[D0.shape64], op64, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0,
                                 F_PLAIN, skip, nullptr, s);
     np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
   } else if (D0.mf) {

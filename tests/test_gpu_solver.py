@@ -307,7 +307,7 @@ def test_full_size_2d_q3_pcg(full2d, fp32):
         assert err < 2e-5, err
 
 
-@pytest.mark.parametrize("shape", list(range(10)))
+@pytest.mark.parametrize("shape", list(range(11)))
 def test_fine_kernel_shapes_full_size(full2d, shape):
     """Every row-block kernel shape of the fine level (CSR blocks, one workgroup each; the same blocks in the
     persistent pipelined kernel, several blocks per workgroup at this size; local-column blocks with 1- and 2-byte
@@ -373,7 +373,7 @@ def dense_row():
     return prob, A2, b, ho
 
 
-@pytest.mark.parametrize("shape", list(range(10)))
+@pytest.mark.parametrize("shape", list(range(11)))
 def test_fine_kernel_long_row(dense_row, shape):
     prob, A2, b, ho = dense_row
     _case(f"dense-row fine kernel shape {shape}")
