@@ -1018,9 +1018,10 @@ void level_apply(HandleImpl& h, int level, const double* x, double* y, hipStream
   }
 }
 
-// one PCG iteration (all launches skip once every column has converged)
+// One PCG iteration (all launches skip once every column has converged).  part 0: the whole iteration; part 1:
+// q = A p, alpha, the x and r updates and the convergence check; part 2: the V-cycle, z, beta and the new p.
 template <typename T>
-static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
+static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s, int part = 0) {
   Analysis& an = c.an;
   Device& dv = c.dv;
   const int L = an.nlevels() - 1;
@@ -1030,51 +1031,54 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s) {
   LevelOp<double> op64 = level_op<double>(c, 0);
   const int n = (int)an.n;
   need_partials(dv, (int64_t)((n + 255) / 256) * 2 * NR);
-  int np;
-  if (NR == 1 && D0.mf) {
-    // q = A p with the matrix-free operator, then <p, q> in the fixed partition
-    apply_level<double>(c, 0, 1, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
-    np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
-  } else if (NR == 1 && D0.fb[D0.shape].nrb > 0) {
-    // q = A p with the fine row-block kernel, then <p, q> in a fixed partition: the iterates do not depend on
-    // the kernel shape chosen by timing
-    launch_level_stream<double>(D0.shape64, D0.fb[D0.shape64], op64, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0,
-                                F_PLAIN, skip, nullptr, s);
-    np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
-  } else if (D0.mf) {
-    // q = A p with the matrix-free operator for NR columns, then the per-column <p, q> in a fixed partition
-    apply_level<double>(c, 0, NR, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
-    need_partials(dv, (int64_t)1024 * NR);
-    np = launch_pcg_dot_mr(n, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
-  } else {
-    auto it = dv.tuned.find({-1, NR * 2});
-    if (it != dv.tuned.end() && (it->second < 0 || it->second >= kCodeSplit)) {  // then the per-column dot
-      op64.ptr = D0.rowptr.p;
-      op64.idx = D0.col.p;
-      bool ok;
-      if (it->second < 0)
-        ok = launch_level_local_mr<double>(-1 - it->second, D0.fb[kLocalFirst - 1 - it->second], op64, NR, dv.pp.p,
-                                           nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
-      else
-        ok = launch_level_split<double>(op64, NR, it->second - kCodeSplit, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr,
-                                        0.0, 0.0, F_PLAIN, skip, s);
-      if (!ok) throw std::runtime_error("multi-RHS fine-level kernel: unsupported shape");
+  if (part != 2) {
+    int np;
+    if (NR == 1 && D0.mf) {
+      // q = A p with the matrix-free operator, then <p, q> in the fixed partition
+      apply_level<double>(c, 0, 1, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
+      np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+    } else if (NR == 1 && D0.fb[D0.shape].nrb > 0) {
+      // q = A p with the fine row-block kernel, then <p, q> in a fixed partition: the iterates do not depend on
+      // the kernel shape chosen by timing
+      launch_level_stream<double>(D0.shape64, D0.fb[D0.shape64], op64, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0,
+                                  F_PLAIN, skip, nullptr, s);
+      np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+    } else if (D0.mf) {
+      // q = A p with the matrix-free operator for NR columns, then the per-column <p, q> in a fixed partition
+      apply_level<double>(c, 0, NR, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
       need_partials(dv, (int64_t)1024 * NR);
       np = launch_pcg_dot_mr(n, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
     } else {
-      if (it != dv.tuned.end()) op64.lanes = it->second;
-      need_partials(dv, (int64_t)((n + 256 / op64.lanes - 1) / (256 / op64.lanes)) * NR);
-      np = launch_spmv_dot(op64, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+      auto it = dv.tuned.find({-1, NR * 2});
+      if (it != dv.tuned.end() && (it->second < 0 || it->second >= kCodeSplit)) {  // then the per-column dot
+        op64.ptr = D0.rowptr.p;
+        op64.idx = D0.col.p;
+        bool ok;
+        if (it->second < 0)
+          ok = launch_level_local_mr<double>(-1 - it->second, D0.fb[kLocalFirst - 1 - it->second], op64, NR, dv.pp.p,
+                                             nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
+        else
+          ok = launch_level_split<double>(op64, NR, it->second - kCodeSplit, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr,
+                                          0.0, 0.0, F_PLAIN, skip, s);
+        if (!ok) throw std::runtime_error("multi-RHS fine-level kernel: unsupported shape");
+        need_partials(dv, (int64_t)1024 * NR);
+        np = launch_pcg_dot_mr(n, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+      } else {
+        if (it != dv.tuned.end()) op64.lanes = it->second;
+        need_partials(dv, (int64_t)((n + 256 / op64.lanes - 1) / (256 / op64.lanes)) * NR);
+        np = launch_spmv_dot(op64, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+      }
     }
+    const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
+    const T* dinv0;
+    if constexpr (sizeof(T) == 4) dinv0 = D0.dinv32.p; else dinv0 = D0.dinv64.p;
+    T* b0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : nullptr;
+    launch_pcg_xr<T>(n, NR, st, dv.partials.p, np, dv.px.p, dv.pr.p, dv.pp.p, dv.pq.p, dv.partials.p, b0, dinv0,
+                     smooth0 ? vbuf<T>(D0.dA) : nullptr, 2.0 / (D0.lam_hi + D0.lam_lo), s);
+    launch_pcg_check(NR, st, dv.partials.p, (n + 255) / 256, s);
   }
-  const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
-  const T* dinv0;
-  if constexpr (sizeof(T) == 4) dinv0 = D0.dinv32.p; else dinv0 = D0.dinv64.p;
-  T* b0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : nullptr;
-  launch_pcg_xr<T>(n, NR, st, dv.partials.p, np, dv.px.p, dv.pr.p, dv.pp.p, dv.pq.p, dv.partials.p, b0, dinv0,
-                   smooth0 ? vbuf<T>(D0.dA) : nullptr, 2.0 / (D0.lam_hi + D0.lam_lo), s);
+  if (part == 1) return;
   const int nv = (n + 255) / 256;
-  launch_pcg_check(NR, st, dv.partials.p, nv, s);
   const T* bl0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : reinterpret_cast<const T*>(dv.pr.p);
   T* pend = nullptr;
   if (L > 0) {
@@ -1141,16 +1145,16 @@ static int read_all_done(Device& dv, hipStream_t s) {
 }
 
 template <typename T>
-static hipGraphExec_t iteration_graph(Ctx& c, int NR, bool flexible) {
+static hipGraphExec_t iteration_graph(Ctx& c, int NR, bool flexible, int part) {
   Device& dv = c.dv;
-  const int key = NR * 2 + (flexible ? 1 : 0);
+  const int key = (NR * 2 + (flexible ? 1 : 0)) * 3 + part;
   auto it = dv.graphs.find(key);
   if (it != dv.graphs.end()) return it->second;
   if (!dv.cap_stream) R3MG_HIP_CHECK(hipStreamCreateWithFlags(&dv.cap_stream, hipStreamNonBlocking));
   hipGraph_t g;
   R3MG_HIP_CHECK(hipStreamBeginCapture(dv.cap_stream, hipStreamCaptureModeThreadLocal));
   try {
-    pcg_iteration<T>(c, NR, flexible, dv.cap_stream);
+    pcg_iteration<T>(c, NR, flexible, dv.cap_stream, part);
   } catch (...) {
     (void)hipStreamEndCapture(dv.cap_stream, &g);
     throw;
@@ -1180,12 +1184,16 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
   launch_gather_cols(n, NR, nb, dv.perm.p, b + (int64_t)c0 * n, n, dv.pb.p, s);
   launch_gather_cols(n, NR, nb, dv.perm.p, x + (int64_t)c0 * n, n, dv.px.p, s);
   pcg_start<T>(c, NR, rtol, atol, flexible, s);
-  hipGraphExec_t ex = nullptr;
-  if (an.opt.use_graph) ex = iteration_graph<T>(c, NR, flexible);
+  hipGraphExec_t ex[3] = {nullptr, nullptr, nullptr};
+  if (an.opt.use_graph)
+    for (int part = 0; part < 3; ++part) ex[part] = iteration_graph<T>(c, NR, flexible, part);
   // The host keeps one iteration ahead of the device: iteration k+1 is enqueued before the state after iteration
   // k is read back (its kernels skip themselves once every column has converged), so the device does not idle
   // while the host decides.  When the residual history predicts that the iteration in flight converges, the
   // host waits for it instead of enqueuing one more (a skipped iteration still costs a full launch sequence).
+  // An iteration that is itself predicted to converge is enqueued without its V-cycle half (part 1 only); that
+  // half follows once its check has been read and failed, so the converging iteration does not queue ~60
+  // kernels that would only skip themselves.
   if (!dv.ev[0]) {
     R3MG_HIP_CHECK(hipEventCreateWithFlags(&dv.ev[0], hipEventDisableTiming));
     R3MG_HIP_CHECK(hipEventCreateWithFlags(&dv.ev[1], hipEventDisableTiming));
@@ -1196,29 +1204,44 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
     R3MG_HIP_CHECK(hipMemcpyAsync(&snap[k & 1], dv.state.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     R3MG_HIP_CHECK(hipEventRecord(dv.ev[k & 1], s));
   };
-  auto launch_one = [&]() {
-    if (ex)
-      R3MG_HIP_CHECK(hipGraphLaunch(ex, s));
+  auto launch_part = [&](int part) {
+    if (ex[part])
+      R3MG_HIP_CHECK(hipGraphLaunch(ex[part], s));
     else
-      pcg_iteration<T>(c, NR, flexible, s);
+      pcg_iteration<T>(c, NR, flexible, s, part);
+  };
+  bool split_pending = false;  // the last iteration enqueued stopped after its convergence check
+  auto launch_one = [&](bool split) {
+    launch_part(split ? 1 : 0);
     ++k;
     snapshot();
+    split_pending = split;
   };
   PcgState st;
+  // whether every open column is predicted to pass the stop test `steps` iterations after the last known one
+  // (the last residual reduction repeated)
+  auto converges_in = [&](const std::vector<double>& rr1, const std::vector<double>& rr2, int steps) {
+    if (rr2.empty()) return false;
+    for (int j = 0; j < nb; ++j) {
+      if (st.done[j]) continue;
+      if (!(rr2[j] > 0.0)) return false;
+      const double q = rr1[j] / rr2[j];
+      double r = rr1[j];
+      for (int t = 0; t < steps; ++t) r *= q;
+      if (!(r <= st.tau2[j])) return false;
+    }
+    return true;
+  };
   auto run_iterations = [&]() {
     std::vector<double> rr1, rr2;  // recursive residuals after the last two known iterations
     int kn = k - 1;                // last snapshot read by the host
+    split_pending = false;
     snapshot();                    // the state before the first iteration of this run
     while (true) {
-      // one iteration in flight (snapshot kn + 1 pending): enqueue another unless it is predicted to converge
-      if (k == kn + 1 && k < maxit) {
-        bool predicted = !rr2.empty();
-        for (int j = 0; j < nb && predicted; ++j) {
-          if (st.done[j]) continue;
-          predicted = rr2[j] > 0.0 && rr1[j] * (rr1[j] / rr2[j]) <= st.tau2[j];
-        }
-        if (!predicted) launch_one();
-      }
+      // one iteration in flight (snapshot kn + 1 pending): enqueue another unless the one in flight is predicted
+      // to converge or stopped after its check
+      if (k == kn + 1 && k < maxit && !split_pending && !converges_in(rr1, rr2, 1))
+        launch_one(converges_in(rr1, rr2, 2));
       R3MG_HIP_CHECK(hipEventSynchronize(dv.ev[(kn + 1) & 1]));
       std::memcpy(&st, &snap[(kn + 1) & 1], sizeof(PcgState));
       ++kn;
@@ -1227,7 +1250,11 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
       rr1.assign(st.rr, st.rr + nb);
       if (k == kn) {  // nothing in flight
         if (k >= maxit) break;
-        launch_one();
+        if (split_pending) {  // the iteration predicted to converge did not: its V-cycle half follows
+          launch_part(2);
+          split_pending = false;
+        }
+        launch_one(converges_in(rr1, rr2, 1));
       }
     }
   };
