@@ -103,6 +103,14 @@ template <typename T>
 void launch_level_blockrow(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
                            double c2, int flags, const int* skip, hipStream_t s);
 
+// Boxes of 4, 9 or 16 rows (2D agglomerated levels, p' = 1, 2, 3) with block rows of at most 64 * kBoxRowMaxNP
+// entries: one wave per box, each lane owning positions of the block row in all the box's rows.
+constexpr int kBoxRowMaxNP = 3;
+bool boxrow_supported(int blk, int maxnb);
+template <typename T>
+void launch_level_boxrow(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
+                         double c2, int flags, const int* skip, hipStream_t s);
+
 // Wide block rows (maxnb * blk large): one workgroup per (box, 8-row chunk).
 template <typename T>
 void launch_level_blockrow_wg(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout,

@@ -1324,6 +1324,112 @@ template void launch_level_blockrow<float>(const LevelOp<float>&, int, const flo
 template void launch_level_blockrow<double>(const LevelOp<double>&, int, const double*, const double*, double*,
                                             double*, double*, double, double, int, const int*, hipStream_t);
 
+// Box-row kernel (2D agglomerated levels: boxes of BLK = 4, 9 or 16 rows): one wave per box K.  Lane p owns the
+// positions p + 64 m (m < NP) of the box's block row (w = nb BLK entries; position j BLK + c is column
+// bcol[j0 + j] BLK + c): it gathers u there once and multiplies it with that position's value in each of the
+// BLK rows, so every value load is a coalesced 256-byte row segment and no column list or LDS staging is
+// needed.  The BLK row sums over the 64 lanes come out of a transposing butterfly over 16 slots (each step halves
+// the rows a lane keeps and doubles the lanes summed), in a fixed order; lane l then holds row
+// 8 b5 + 4 b4 + 2 b3 + b2 (b = bits of l) and the lanes with l % 4 == 0 apply the epilogue of k_level.
+template <typename T, int BLK, int NP>
+__global__ __launch_bounds__(256) void k_level_boxrow(int nbox, const int* __restrict__ bptr,
+                                                      const int* __restrict__ bcol, const T* __restrict__ val,
+                                                      const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
+                                                      const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
+                                                      const int* __restrict__ skip, int nlog) {
+  static_assert(BLK <= 16, "rows per box");
+  if (skip && *skip) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int K = lb * 4 + wv;
+  if (K >= nbox) return;  // whole wave leaves; no barrier follows
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+  const int myrow = (b5 ? 8 : 0) + (b4 ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
+  const bool owner = (lane & 3) == 0 && myrow < BLK;
+  const int row = K * BLK + myrow;
+  T p_old = 0, p_u = 0, p_x = 0, p_di = 0;
+  if (owner && !(flags & F_PLAIN)) {
+    p_old = (flags & F_RHO_FROM_B) ? b[row] : rho[row];
+    p_u = u[row];
+    if (flags & F_X_ADD) p_x = x[row];
+    if (flags & F_D_OUT) p_di = dinv[row];
+  }
+  const int j0 = bptr[K], w = (bptr[K + 1] - j0) * BLK;
+  const T* vb = val + (int64_t)BLK * BLK * j0;  // row q of the box at vb + q w
+  T acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0;
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const int p = lane + 64 * m;
+    if (p < w) {
+      T v[BLK];
+#pragma unroll
+      for (int q = 0; q < BLK; ++q) v[q] = __builtin_nontemporal_load(vb + (int64_t)q * w + p);
+      const int j = p / BLK, c = p - j * BLK;
+      const T uv = u[(int64_t)bcol[j0 + j] * BLK + c];
+#pragma unroll
+      for (int q = 0; q < BLK; ++q) acc[q] += v[q] * uv;
+    }
+  }
+  T h8[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) h8[q] = (b5 ? acc[8 + q] : acc[q]) + __shfl_xor(b5 ? acc[q] : acc[8 + q], 32, 64);
+  T h4[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) h4[q] = (b4 ? h8[4 + q] : h8[q]) + __shfl_xor(b4 ? h8[q] : h8[4 + q], 16, 64);
+  T h2[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) h2[q] = (b3 ? h4[2 + q] : h4[q]) + __shfl_xor(b3 ? h4[q] : h4[2 + q], 8, 64);
+  T t = (b2 ? h2[1] : h2[0]) + __shfl_xor(b2 ? h2[0] : h2[1], 4, 64);
+  t += __shfl_xor(t, 2, 64);
+  t += __shfl_xor(t, 1, 64);
+  if (owner) {
+    if (flags & F_PLAIN) {
+      rho[row] = t;
+    } else {
+      const T r = p_old - t;
+      if (flags & F_RHO_STORE) rho[row] = r;
+      if (flags & F_X_ASSIGN)
+        x[row] = p_u;
+      else if (flags & F_X_ADD)
+        x[row] = p_x + p_u;
+      if (flags & F_D_OUT) dout[row] = c1 * p_u + c2 * p_di * r;
+    }
+  }
+}
+
+bool boxrow_supported(int blk, int maxnb) {
+  return (blk == 4 || blk == 9 || blk == 16) && maxnb > 0 && (int64_t)maxnb * blk <= 64 * kBoxRowMaxNP;
+}
+
+template <typename T>
+void launch_level_boxrow(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
+                         double c2, int flags, const int* skip, hipStream_t s) {
+  if (!boxrow_supported(op.blk, maxnb)) throw std::runtime_error("box-row kernel: unsupported box shape");
+  const int nbox = op.n / op.blk;
+  const int nlog = (nbox + 3) / 4;
+  if (nlog == 0) return;
+  const int np = (maxnb * op.blk + 63) / 64;
+#define R3_BR(B, N)                                                                                                \
+  hipLaunchKernelGGL((k_level_boxrow<T, B, N>), dim3(xcd_grid(nlog)), dim3(256), 0, s, nbox, op.ptr, op.idx, op.val, \
+                     u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog)
+  if (op.blk == 4) {
+    if (np == 1) R3_BR(4, 1); else if (np == 2) R3_BR(4, 2); else R3_BR(4, 3);
+  } else if (op.blk == 9) {
+    if (np == 1) R3_BR(9, 1); else if (np == 2) R3_BR(9, 2); else R3_BR(9, 3);
+  } else {
+    if (np == 1) R3_BR(16, 1); else if (np == 2) R3_BR(16, 2); else R3_BR(16, 3);
+  }
+#undef R3_BR
+  check_launch("k_level_boxrow");
+}
+template void launch_level_boxrow<float>(const LevelOp<float>&, int, const float*, const float*, float*, float*,
+                                         float*, double, double, int, const int*, hipStream_t);
+template void launch_level_boxrow<double>(const LevelOp<double>&, int, const double*, const double*, double*,
+                                          double*, double*, double, double, int, const int*, hipStream_t);
+
 // Wide block rows (3D agglomerated levels): one 256-thread workgroup per (box K, chunk of 8 of its B rows),
 // grid = nbox * ceil(B/8).  The workgroup stages the nb*B entries of u touched by box K in LDS, then each wave
 // computes two rows against the LDS copy with coalesced value loads; threads 0..7 apply the epilogue.

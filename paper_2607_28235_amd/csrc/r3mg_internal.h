@@ -206,6 +206,7 @@ struct DevLevel {
   double shape_bytes[kStreamShapes] = {};  // algorithmic bytes of one application with each shape
   int shape = 0;        // l = 0: kernel shape chosen by timing at set-up
   int shape64 = 0;      // l = 0: shape of the float64 operator PCG applies (with a float64 V-cycle: shape)
+  bool boxrow = false;  // l >= 1: applied by the box-row kernel (boxes of 4, 9 or 16 rows)
   int maxnb = 0;     // l >= 1: largest number of stored blocks in a block row
   // transfer to the next level
   DBuf<double> xi64;     // l = 0: n x d
@@ -269,7 +270,7 @@ struct HandleImpl {
 };
 
 // kernel family that applies a level operator (solver.cpp chooses; r3mg_info reports it)
-enum class LevelKernel { Stream, BlockRowWG, BlockRow, Lanes, MatFree };
+enum class LevelKernel { Stream, BoxRow, BlockRowWG, BlockRow, Lanes, MatFree };
 LevelKernel level_kernel(const Analysis& an, const DevLevel& D, int l, int nr, int esz);
 std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int esz);
 

@@ -191,6 +191,7 @@ constexpr int kCodeSplit = 100;
 // lanes-per-row kernel otherwise.
 LevelKernel level_kernel(const Analysis& an, const DevLevel& D, int l, int nr, int esz) {
   if (l == 0 && D.mf) return LevelKernel::MatFree;
+  if (l > 0 && nr == 1 && D.boxrow) return LevelKernel::BoxRow;
   if (nr == 1 && D.fb[D.shape].nrb > 0 && (l == 0 || D.shape >= kLocalFirst + kLocalGeoms)) return LevelKernel::Stream;
   if (l > 0 && nr == 1 && D.maxnb > 0 && an.B >= 8 && (int64_t)D.maxnb * an.B >= 256 &&
       (int64_t)D.maxnb * an.B * esz <= 65536)
@@ -216,6 +217,7 @@ std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int 
     case LevelKernel::MatFree:
       return std::string("k_mf_cell<") + t + "," + std::to_string(D.mf->op.d) + "D,Q" + std::to_string(D.mf->p) +
              (D.mf->affine ? ",affine>" : ",multilinear>") + "+k_mf_gather<" + t + ">";
+    case LevelKernel::BoxRow: return std::string("k_level_boxrow<") + t + "," + std::to_string(an.B) + ">";
     case LevelKernel::BlockRowWG: return std::string("k_level_blockrow_wg<") + t + ">";
     case LevelKernel::BlockRow: return std::string("k_level_blockrow<") + t + ">";
     default: return std::string("k_level<") + t + ">";
@@ -255,6 +257,9 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
       launch_level_stream<T>(sh, D.fb[sh], op, u, b, rho, x, dout, c1, c2, flags, skip, nullptr, s);
       break;
     }
+    case LevelKernel::BoxRow:
+      launch_level_boxrow<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags, skip, s);
+      break;
     case LevelKernel::BlockRowWG:
       launch_level_blockrow_wg<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags, skip, s);
       break;
@@ -925,7 +930,11 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     D.lanes = lanes_for((double)(D.nnz) / (double)std::max<int64_t>(1, D.n));
     const double sv = fp32 ? 4 : 8;
     D.bytes_apply = (double)D.nnz * sv + (double)nblk * 4 + (double)(H.nbox + 1) * 4 + 7.0 * D.n * sv;
-    if (!H.rowptr.empty()) {  // narrow block rows: the level is also held as 1-byte local-column blocks
+    // boxes of 4, 9 or 16 rows (2D) take the box-row kernel, which reads only the values, block columns and
+    // block-row offsets; a float32 level large enough for the 3072-nonzero local blocks keeps the vector kernel,
+    // which measured faster there (7.9 against 8.2 us on level 1 of the 2D Q3 hierarchy)
+    D.boxrow = boxrow_supported(B, D.maxnb) && !(H.loc_geom == 4 && fp32);
+    if (!D.boxrow && !H.rowptr.empty()) {  // narrow block rows: the level is held as 1-byte local-column blocks
       D.rowptr.upload(H.rowptr, s);
       // the vector kernel: shape 9 over 2048-nonzero blocks, shape 11 over (3072, 64-row) blocks
       D.shape = H.loc_geom == 4 ? kLocalFirst + kLocalGeoms + 2 : kLocalFirst + kLocalGeoms;

@@ -306,8 +306,9 @@ def test_full_size_2d_q3_pcg(full2d, fp32):
     r = c.b - c.prob.scipy() @ xs
     assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(c.b)
     assert _rel(xs, c.xo) < 1e-9
-    # V-cycle parity at full size.  FP32 V-cycle: level 1 (2,554 blocks of 2048 nonzeros, more than the 2,048
-    # resident workgroups) is applied over 3072-nonzero blocks; the bar is rounding of float32 level values and
+    # V-cycle parity at full size.  The agglomerated levels (boxes of 9 rows) are applied by the box-row kernel,
+    # except level 1 of the FP32 V-cycle (2,554 blocks of 2048 nonzeros, more than the 2,048 resident workgroups),
+    # which takes 3072-nonzero local blocks.  FP32 V-cycle: the bar is rounding of float32 level values and
     # vectors through 3 smoothed levels (13 level applications each), well above eps32 = 6e-8 times that depth
     # (measured: 4.2e-7)
     g = np.random.default_rng(11)
@@ -319,9 +320,10 @@ def test_full_size_2d_q3_pcg(full2d, fp32):
     err = _rel(z.cpu().numpy(), O.vcycle(c.ho, rv))
     print(f"full2d fp32={fp32}: V-cycle relative difference from the oracle {err:.2e}")
     if not fp32:
+        assert all(h.info()[l]["kernel"] == "k_level_boxrow<double,9>" for l in (1, 2)), h.info()
         assert err < 1e-11
     else:
-        assert "3072" in h.info()[1]["kernel"] and "2048" in h.info()[2]["kernel"], h.info()
+        assert "3072" in h.info()[1]["kernel"] and h.info()[2]["kernel"] == "k_level_boxrow<float,9>", h.info()
         assert err < 2e-5, err
 
 
