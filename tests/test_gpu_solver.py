@@ -143,6 +143,40 @@ def test_block_vcycle_matches_oracle(small3d, nrhs):
         assert _rel(Z[j].cpu().numpy(), O.vcycle(c.ho, R[j])) < 1e-11, j
 
 
+@pytest.mark.parametrize("pc", [1, 3])
+def test_box_row_kernel_other_box_sizes(pc):
+    """2D Q3 with p' = 1 (boxes of 4 rows, block rows of up to 40 entries: one position per lane) and p' = 3
+    (boxes of 16 rows, block rows of up to 160 entries: three positions per lane), applied by the box-row kernel.
+    Float64 V-cycle against the oracle; PCG in both V-cycle precisions against the oracle's iteration count and
+    the true residual."""
+    _need_gpu()
+    _case(f"2D Q3 32x32 jittered, p'={pc}, leaf 128, up to 4 levels")
+    P = _P()
+    prob = F.structured_qp(2, 32, 3, jitter=0.2, cfg=2)
+    b = F.nodal_rhs(prob, F.rng(2, F.PURPOSE_RHS).standard_normal(prob.n), jitter=0.2, cfg=2)
+    c = Case(prob, b, pc, 128, 4, 2, 2, max_coarse=200)
+    info = c.h.info()
+    assert [lv["n"] for lv in info] == [lv.A.shape[0] for lv in c.ho.levels]
+    assert len(info) >= 3
+    assert all(info[l]["kernel"] == f"k_level_boxrow<double,{(pc + 1) ** 2}>" for l in range(1, len(info) - 1)), info
+    g = np.random.default_rng(7)
+    r = g.standard_normal(prob.n)
+    r[c.ho.constrained] = 0.0
+    z = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+    c.h.vcycle(_t(r), z)
+    torch.cuda.synchronize()
+    assert _rel(z.cpu().numpy(), O.vcycle(c.ho, r)) < 1e-11
+    _, ko, _, _, _ = O.pcg(c.ho, b, rtol=1e-10)
+    import dataclasses
+    for h in (c.h, P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val,
+                               dataclasses.replace(c.opts, vcycle_fp32=1))):
+        x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        iters, _, ok = h.pcg(_t(b), x, rtol=1e-10, maxit=200)
+        assert ok and abs(int(iters[0]) - ko) <= 1, (iters, ko)
+        res = b - prob.scipy() @ x.cpu().numpy()
+        assert np.linalg.norm(res) <= 1.01e-10 * np.linalg.norm(b)
+
+
 @pytest.mark.parametrize("name", ["cfg1", "small2d", "small3d"])
 def test_vcycle_symmetric_positive_on_gpu(name, request):
     c = request.getfixturevalue(name)
