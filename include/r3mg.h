@@ -96,9 +96,10 @@ typedef struct {
   double lambda_hi;        /* Chebyshev interval (0 on the dense coarsest level) */
   double lambda_lo;
   double bytes_per_apply;  /* algorithmic bytes of one smoother operator application in the V-cycle precision */
-  char kernel[48];         /* kernel applying the level for one right-hand side, e.g. "k_level_stream<float,2048,64>"
-                              (row-block capacity, rows per block); "dense" on the coarsest level; "" before
-                              r3mg_factor */
+  char kernel[48];         /* kernel applying the level for one right-hand side in the V-cycle precision, e.g.
+                              "k_level_local<float,u8,3072,128,256,vec>" (position bytes, block capacity, rows
+                              per block, distinct columns, form) or "k_level_boxrow<float,9>" (rows per box);
+                              "dense" on the coarsest level; "" before r3mg_factor */
 } r3mg_level_info;
 
 /* Fill *opt with the defaults listed above. */
