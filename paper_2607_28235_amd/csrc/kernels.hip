@@ -779,8 +779,15 @@ __global__ __launch_bounds__(256) void k_level_local_vec(int nrb, const int4* __
     for (int m = 0; m < NCH; ++m) {
       const int e = a0 + 4 * (threadIdx.x + m * 256);
       if (e < e1) {
-        li[m] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(lidx + e));
-        vv[m] = __builtin_nontemporal_load(reinterpret_cast<const V4*>(val + e));
+        const uint32_t* lp = reinterpret_cast<const uint32_t*>(lidx + e);
+        const V4* vp = reinterpret_cast<const V4*>(val + e);
+        if (flags & F_KEEP) {
+          li[m] = *lp;
+          vv[m] = *vp;
+        } else {
+          li[m] = __builtin_nontemporal_load(lp);
+          vv[m] = __builtin_nontemporal_load(vp);
+        }
       }
     }
     int rp = e1;
@@ -1366,7 +1373,8 @@ __global__ __launch_bounds__(256) void k_level_boxrow(int nbox, const int* __res
     if (p < w) {
       T v[BLK];
 #pragma unroll
-      for (int q = 0; q < BLK; ++q) v[q] = __builtin_nontemporal_load(vb + (int64_t)q * w + p);
+      for (int q = 0; q < BLK; ++q)
+        v[q] = (flags & F_KEEP) ? vb[(int64_t)q * w + p] : __builtin_nontemporal_load(vb + (int64_t)q * w + p);
       const int j = p / BLK, c = p - j * BLK;
       const T uv = u[(int64_t)bcol[j0 + j] * BLK + c];
 #pragma unroll

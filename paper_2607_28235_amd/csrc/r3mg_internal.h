@@ -207,6 +207,7 @@ struct DevLevel {
   int shape = 0;        // l = 0: kernel shape chosen by timing at set-up
   int shape64 = 0;      // l = 0: shape of the float64 operator PCG applies (with a float64 V-cycle: shape)
   bool boxrow = false;  // l >= 1: applied by the box-row kernel (boxes of 4, 9 or 16 rows)
+  int keep32 = 0, keep64 = 0;  // F_KEEP for the float32 / float64 applications (matrix stream small enough)
   int maxnb = 0;     // l >= 1: largest number of stored blocks in a block row
   // transfer to the next level
   DBuf<double> xi64;     // l = 0: n x d

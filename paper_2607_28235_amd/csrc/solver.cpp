@@ -224,6 +224,12 @@ std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int 
   }
 }
 
+// F_KEEP when the level's matrix stream in precision T is small enough to stay in the caches
+template <typename T>
+static int keep_flag(const DevLevel& D) {
+  return sizeof(T) == 4 ? D.keep32 : D.keep64;
+}
+
 template <typename T>
 void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T* dout, double c1, double c2, int flags,
                  const int* skip, hipStream_t s) {
@@ -254,11 +260,12 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
       op.ptr = D.rowptr.p;  // CSR row pointers (coarse levels: of the block-row layout)
       op.idx = D.col.p;     // CSR columns (fine level only; coarse rows never take the long-row path)
       const int sh = (l == 0 && sizeof(T) == 8) ? D.shape64 : D.shape;
-      launch_level_stream<T>(sh, D.fb[sh], op, u, b, rho, x, dout, c1, c2, flags, skip, nullptr, s);
+      launch_level_stream<T>(sh, D.fb[sh], op, u, b, rho, x, dout, c1, c2, flags | keep_flag<T>(D), skip, nullptr,
+                             s);
       break;
     }
     case LevelKernel::BoxRow:
-      launch_level_boxrow<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags, skip, s);
+      launch_level_boxrow<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags | keep_flag<T>(D), skip, s);
       break;
     case LevelKernel::BlockRowWG:
       launch_level_blockrow_wg<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags, skip, s);
@@ -760,15 +767,15 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
         LevelOp<float> op = level_op<float>(c, 0);
         ms = time_launches(s, 20, [&] {
           launch_level_stream<float>(sh, D.fb[sh], op, vbuf<float>(D.dA), vbuf<float>(D.b),
-                                     vbuf<float>(D.rho), vbuf<float>(D.x), vbuf<float>(D.dB), 0.0, 0.0, fl, nullptr,
-                                     nullptr, s);
+                                     vbuf<float>(D.rho), vbuf<float>(D.x), vbuf<float>(D.dB), 0.0, 0.0,
+                                     fl | D.keep32, nullptr, nullptr, s);
         });
       } else {
         LevelOp<double> op = level_op<double>(c, 0);
         ms = time_launches(s, 20, [&] {
           launch_level_stream<double>(sh, D.fb[sh], op, vbuf<double>(D.dA), vbuf<double>(D.b),
-                                      vbuf<double>(D.rho), vbuf<double>(D.x), vbuf<double>(D.dB), 0.0, 0.0, fl,
-                                      nullptr, nullptr, s);
+                                      vbuf<double>(D.rho), vbuf<double>(D.x), vbuf<double>(D.dB), 0.0, 0.0,
+                                      fl | D.keep64, nullptr, nullptr, s);
         });
       }
       best[sh] = std::min(best[sh], ms);
@@ -793,8 +800,8 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
   for (int round = 0; round < 2; ++round)
     for (int sh = 0; sh < kFineShapes; ++sh) {
       const float ms = time_launches(s, 20, [&] {
-        launch_level_stream<double>(sh, D.fb[sh], op, u64.p, nullptr, y64.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN,
-                                    nullptr, nullptr, s);
+        launch_level_stream<double>(sh, D.fb[sh], op, u64.p, nullptr, y64.p, nullptr, nullptr, 0.0, 0.0,
+                                    F_PLAIN | D.keep64, nullptr, nullptr, s);
       });
       best[sh] = std::min(best[sh], ms);
     }
@@ -885,6 +892,9 @@ void device_setup(HandleImpl& h, hipStream_t s) {
       upload_local(D, g, an.loc[g], an.rowptr, s);
       D.shape_bytes[kLocalFirst + g] = local_bytes(an.nnz, an.n, g, an.loc[g], sv0);
     }
+    // matrix read with ordinary loads when its stream (values and 1-byte positions) fits the caches
+    D.keep32 = (double)an.nnz * (4 + 1) <= kKeepCachedBytes ? F_KEEP : 0;
+    D.keep64 = (double)an.nnz * (8 + 1) <= kKeepCachedBytes ? F_KEEP : 0;
     // shape 9: the vector-load kernel over the blocks of local geometry 0; shape 10: the same over geometry 3
     D.fb[kLocalFirst + kLocalGeoms] = D.fb[kLocalFirst];
     D.shape_bytes[kLocalFirst + kLocalGeoms] = D.shape_bytes[kLocalFirst];
@@ -934,6 +944,8 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     // block-row offsets; a float32 level large enough for the 3072-nonzero local blocks keeps the vector kernel,
     // which measured faster there (7.9 against 8.2 us on level 1 of the 2D Q3 hierarchy)
     D.boxrow = boxrow_supported(B, D.maxnb) && !(H.loc_geom == 4 && fp32);
+    D.keep32 = (double)D.nnz * (4 + 1) <= kKeepCachedBytes ? F_KEEP : 0;
+    D.keep64 = (double)D.nnz * (8 + 1) <= kKeepCachedBytes ? F_KEEP : 0;
     if (!D.boxrow && !H.rowptr.empty()) {  // narrow block rows: the level is held as 1-byte local-column blocks
       D.rowptr.upload(H.rowptr, s);
       // the vector kernel: shape 9 over 2048-nonzero blocks, shape 11 over (3072, 64-row) blocks
@@ -1050,7 +1062,7 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s, int part
       // q = A p with the fine row-block kernel, then <p, q> in a fixed partition: the iterates do not depend on
       // the kernel shape chosen by timing
       launch_level_stream<double>(D0.shape64, D0.fb[D0.shape64], op64, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0,
-                                  F_PLAIN, skip, nullptr, s);
+                                  F_PLAIN | D0.keep64, skip, nullptr, s);
       np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
     } else if (D0.mf) {
       // q = A p with the matrix-free operator for NR columns, then the per-column <p, q> in a fixed partition
