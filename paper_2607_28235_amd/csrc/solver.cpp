@@ -941,9 +941,8 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     const double sv = fp32 ? 4 : 8;
     D.bytes_apply = (double)D.nnz * sv + (double)nblk * 4 + (double)(H.nbox + 1) * 4 + 7.0 * D.n * sv;
     // boxes of 4, 9 or 16 rows (2D) take the box-row kernel, which reads only the values, block columns and
-    // block-row offsets; a float32 level large enough for the 3072-nonzero local blocks keeps the vector kernel,
-    // which measured faster there (7.9 against 8.2 us on level 1 of the 2D Q3 hierarchy)
-    D.boxrow = boxrow_supported(B, D.maxnb) && !(H.loc_geom == 4 && fp32);
+    // block-row offsets; the local-column blocks remain for wider block rows
+    D.boxrow = boxrow_supported(B, D.maxnb);
     D.keep32 = (double)D.nnz * (4 + 1) <= kKeepCachedBytes ? F_KEEP : 0;
     D.keep64 = (double)D.nnz * (8 + 1) <= kKeepCachedBytes ? F_KEEP : 0;
     if (!D.boxrow && !H.rowptr.empty()) {  // narrow block rows: the level is held as 1-byte local-column blocks
