@@ -16,8 +16,8 @@ enum : int {
   F_X_ADD = 16,       // x += u
   F_D_OUT = 32,       // dout := c1 u + c2 dinv rho_new
   F_KEEP = 64,        // read the matrix with ordinary loads, so that it can stay in the caches between the
-                      // back-to-back applications of a smoothing sweep (k_level_local_vec and k_level_boxrow;
-                      // without it they read it with nontemporal loads)
+                      // back-to-back applications of a smoothing sweep (k_level_local_vec, k_level_boxrow and the
+                      // block-row kernels; without it they read it with nontemporal loads)
 };
 // Largest matrix stream (values, positions, column lists) of a level that is read with F_KEEP: the 2D Q3 fine
 // level in float32 (80 MB) gained, a 3D fine level of ~800 MB lost (its matrix evicted the vectors).

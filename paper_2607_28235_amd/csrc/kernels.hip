@@ -282,6 +282,17 @@ template void launch_level<double>(const LevelOp<double>&, int, const double*, c
 // order, the same for every row-block shape: a_v = prod[s+v] + prod[s+v+4] + ... (v = 0..3, in increasing
 // position), row sum = (a_0 + a_2) + (a_1 + a_3).  With TPR = 2 each lane carries two of the four partial sums.
 // Lane sub = 0 of the group holds the result.
+// Matrix load of the fused level kernels: ordinary with KEEP (the level's matrix fits the caches and is applied
+// again right away), nontemporal otherwise.  A compile-time choice: a run-time select between the two would be
+// folded into one ordinary load.
+template <bool KEEP, typename P>
+__device__ inline P ld_matrix(const P* ptr) {
+  if constexpr (KEEP)
+    return *ptr;
+  else
+    return __builtin_nontemporal_load(ptr);
+}
+
 template <typename T, int TPR>
 __device__ inline T row_sum_canonical(const T* prod, int s, int e, int sub) {
   static_assert(TPR == 4 || TPR == 2, "lanes per row");
@@ -727,7 +738,7 @@ __global__ __launch_bounds__(256) void k_level_local(int nrb, const int* __restr
 // positions) from the block's first entry rounded down to a multiple of four (outside entries masked; values and
 // positions carry kFinePad padding entries), stages the four products with one aligned LDS write, and each wave
 // loads its rows' row pointers once and spreads them with lane shuffles.
-template <typename T, int CAP, int RPB, int UCAP>
+template <typename T, int CAP, int RPB, int UCAP, bool KEEP>
 __global__ __launch_bounds__(256) void k_level_local_vec(int nrb, const int4* __restrict__ meta,
                                                          const int* __restrict__ ucol,
                                                          const uint8_t* __restrict__ lidx, const int* __restrict__ ptr,
@@ -781,13 +792,8 @@ __global__ __launch_bounds__(256) void k_level_local_vec(int nrb, const int4* __
       if (e < e1) {
         const uint32_t* lp = reinterpret_cast<const uint32_t*>(lidx + e);
         const V4* vp = reinterpret_cast<const V4*>(val + e);
-        if (flags & F_KEEP) {
-          li[m] = *lp;
-          vv[m] = *vp;
-        } else {
-          li[m] = __builtin_nontemporal_load(lp);
-          vv[m] = __builtin_nontemporal_load(vp);
-        }
+        li[m] = ld_matrix<KEEP>(lp);
+        vv[m] = ld_matrix<KEEP>(vp);
       }
     }
     int rp = e1;
@@ -909,9 +915,14 @@ static int launch_stream_local_vec(const FineBlocks& fb, const LevelOp<T>& op, c
   if (partials) throw std::runtime_error("local-column vector kernel: no partial sums");
   const int nrb = fb.nrb;
   if (!fb.meta) throw std::runtime_error("local-column vector kernel: block records missing");
-  hipLaunchKernelGGL((k_level_local_vec<T, CAP, RPB, UCAP>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb,
-                     reinterpret_cast<const int4*>(fb.meta), fb.ucol, static_cast<const uint8_t*>(fb.lidx), op.ptr,
-                     op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip);
+  if (flags & F_KEEP)
+    hipLaunchKernelGGL((k_level_local_vec<T, CAP, RPB, UCAP, true>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb,
+                       reinterpret_cast<const int4*>(fb.meta), fb.ucol, static_cast<const uint8_t*>(fb.lidx), op.ptr,
+                       op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip);
+  else
+    hipLaunchKernelGGL((k_level_local_vec<T, CAP, RPB, UCAP, false>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb,
+                       reinterpret_cast<const int4*>(fb.meta), fb.ucol, static_cast<const uint8_t*>(fb.lidx), op.ptr,
+                       op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip);
   return nrb;
 }
 
@@ -1234,7 +1245,7 @@ int launch_pcg_dot_mr(int n, int nr, const double* p, const double* q, double* p
 // blocks of B consecutive columns, staged in LDS once and shared by the B rows).  Each lane then sums its
 // columns in ascending order, the L lane sums of a row are added in lane order through LDS, and lane q applies
 // the epilogue of row (K, q).  Dynamic LDS: 4 waves x (maxw + 64) entries, maxw = max_K nb_K * B.
-template <typename T, int KMAX>
+template <typename T, int KMAX, bool KEEP>
 __global__ __launch_bounds__(256) void k_level_blockrow(int nbox, int blk, int maxw, const int* __restrict__ bptr,
                                                         const int* __restrict__ bcol, const T* __restrict__ val,
                                                         const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
@@ -1259,7 +1270,7 @@ __global__ __launch_bounds__(256) void k_level_blockrow(int nbox, int blk, int m
 #pragma unroll
   for (int m = 0; m < KMAX; ++m) {
     const int p = sv + L * m;
-    v[m] = (active && p < w) ? __builtin_nontemporal_load(vrow + p) : (T)0;
+    v[m] = (active && p < w) ? ld_matrix<KEEP>(vrow + p) : (T)0;
   }
   const int row = K * blk + lane;
   T p_old = 0, p_u = 0, p_x = 0, p_di = 0;
@@ -1322,8 +1333,12 @@ void launch_level_blockrow(const LevelOp<T>& op, int maxnb, const T* u, const T*
   const size_t shm = blockrow_lds_bytes(op.blk, maxw, sizeof(T));
   if (shm > 65536) throw std::runtime_error("block-row kernel: block row too wide for LDS");
   if (op.blk > 64) throw std::runtime_error("block-row kernel: more than 64 rows per box");
-  hipLaunchKernelGGL((k_level_blockrow<T, 16>), dim3(xcd_grid(nlog)), dim3(256), shm, s, nbox, op.blk, maxw, op.ptr,
-                     op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
+  if (flags & F_KEEP)
+    hipLaunchKernelGGL((k_level_blockrow<T, 16, true>), dim3(xcd_grid(nlog)), dim3(256), shm, s, nbox, op.blk, maxw,
+                       op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
+  else
+    hipLaunchKernelGGL((k_level_blockrow<T, 16, false>), dim3(xcd_grid(nlog)), dim3(256), shm, s, nbox, op.blk, maxw,
+                       op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
   check_launch("k_level_blockrow");
 }
 template void launch_level_blockrow<float>(const LevelOp<float>&, int, const float*, const float*, float*, float*,
@@ -1338,7 +1353,7 @@ template void launch_level_blockrow<double>(const LevelOp<double>&, int, const d
 // needed.  The BLK row sums over the 64 lanes come out of a transposing butterfly over 16 slots (each step halves
 // the rows a lane keeps and doubles the lanes summed), in a fixed order; lane l then holds row
 // 8 b5 + 4 b4 + 2 b3 + b2 (b = bits of l) and the lanes with l % 4 == 0 apply the epilogue of k_level.
-template <typename T, int BLK, int NP>
+template <typename T, int BLK, int NP, bool KEEP>
 __global__ __launch_bounds__(256) void k_level_boxrow(int nbox, const int* __restrict__ bptr,
                                                       const int* __restrict__ bcol, const T* __restrict__ val,
                                                       const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
@@ -1374,7 +1389,7 @@ __global__ __launch_bounds__(256) void k_level_boxrow(int nbox, const int* __res
       T v[BLK];
 #pragma unroll
       for (int q = 0; q < BLK; ++q)
-        v[q] = (flags & F_KEEP) ? vb[(int64_t)q * w + p] : __builtin_nontemporal_load(vb + (int64_t)q * w + p);
+        v[q] = ld_matrix<KEEP>(vb + (int64_t)q * w + p);
       const int j = p / BLK, c = p - j * BLK;
       const T uv = u[(int64_t)bcol[j0 + j] * BLK + c];
 #pragma unroll
@@ -1420,9 +1435,15 @@ void launch_level_boxrow(const LevelOp<T>& op, int maxnb, const T* u, const T* b
   const int nlog = (nbox + 3) / 4;
   if (nlog == 0) return;
   const int np = (maxnb * op.blk + 63) / 64;
-#define R3_BR(B, N)                                                                                                \
-  hipLaunchKernelGGL((k_level_boxrow<T, B, N>), dim3(xcd_grid(nlog)), dim3(256), 0, s, nbox, op.ptr, op.idx, op.val, \
-                     u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog)
+#define R3_BR(B, N)                                                                                               \
+  do {                                                                                                            \
+    if (flags & F_KEEP)                                                                                           \
+      hipLaunchKernelGGL((k_level_boxrow<T, B, N, true>), dim3(xcd_grid(nlog)), dim3(256), 0, s, nbox, op.ptr,   \
+                         op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);           \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_level_boxrow<T, B, N, false>), dim3(xcd_grid(nlog)), dim3(256), 0, s, nbox, op.ptr,  \
+                         op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);           \
+  } while (0)
   if (op.blk == 4) {
     if (np == 1) R3_BR(4, 1); else if (np == 2) R3_BR(4, 2); else R3_BR(4, 3);
   } else if (op.blk == 9) {
@@ -1441,7 +1462,7 @@ template void launch_level_boxrow<double>(const LevelOp<double>&, int, const dou
 // Wide block rows (3D agglomerated levels): one 256-thread workgroup per (box K, chunk of 8 of its B rows),
 // grid = nbox * ceil(B/8).  The workgroup stages the nb*B entries of u touched by box K in LDS, then each wave
 // computes two rows against the LDS copy with coalesced value loads; threads 0..7 apply the epilogue.
-template <typename T>
+template <typename T, bool KEEP>
 __global__ __launch_bounds__(256) void k_level_blockrow_wg(int nbox, int blk, int nchunk, const int* __restrict__ bptr,
                                                            const int* __restrict__ bcol, const T* __restrict__ val,
                                                            const T* __restrict__ u, const T* __restrict__ b, T* rho,
@@ -1475,8 +1496,8 @@ __global__ __launch_bounds__(256) void k_level_blockrow_wg(int nbox, int blk, in
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const int p = p0 + lane + 64 * m;
-        ta[m] = p < w ? __builtin_nontemporal_load(va + p) : (T)0;
-        tb[m] = (hb && p < w) ? __builtin_nontemporal_load(va + w + p) : (T)0;
+        ta[m] = p < w ? ld_matrix<KEEP>(va + p) : (T)0;
+        tb[m] = (hb && p < w) ? ld_matrix<KEEP>(va + w + p) : (T)0;
       }
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
@@ -1523,8 +1544,12 @@ void launch_level_blockrow_wg(const LevelOp<T>& op, int maxnb, const T* u, const
   if (nlog == 0) return;
   const size_t shm = sizeof(T) * (size_t)maxnb * op.blk;
   if (shm > 65536) throw std::runtime_error("block-row kernel: block row too wide for LDS");
-  hipLaunchKernelGGL((k_level_blockrow_wg<T>), dim3(xcd_grid(nlog)), dim3(256), shm, s, nbox, op.blk, nchunk, op.ptr,
-                     op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
+  if (flags & F_KEEP)
+    hipLaunchKernelGGL((k_level_blockrow_wg<T, true>), dim3(xcd_grid(nlog)), dim3(256), shm, s, nbox, op.blk, nchunk,
+                       op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
+  else
+    hipLaunchKernelGGL((k_level_blockrow_wg<T, false>), dim3(xcd_grid(nlog)), dim3(256), shm, s, nbox, op.blk, nchunk,
+                       op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);
   check_launch("k_level_blockrow_wg");
 }
 template void launch_level_blockrow_wg<float>(const LevelOp<float>&, int, const float*, const float*, float*, float*,

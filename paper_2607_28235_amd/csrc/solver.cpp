@@ -268,10 +268,10 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
       launch_level_boxrow<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags | keep_flag<T>(D), skip, s);
       break;
     case LevelKernel::BlockRowWG:
-      launch_level_blockrow_wg<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags, skip, s);
+      launch_level_blockrow_wg<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags | keep_flag<T>(D), skip, s);
       break;
     case LevelKernel::BlockRow:
-      launch_level_blockrow<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags, skip, s);
+      launch_level_blockrow<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags | keep_flag<T>(D), skip, s);
       break;
     default: {
       if (nr > 1) {
@@ -943,8 +943,10 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     // boxes of 4, 9 or 16 rows (2D) take the box-row kernel, which reads only the values, block columns and
     // block-row offsets; the local-column blocks remain for wider block rows
     D.boxrow = boxrow_supported(B, D.maxnb);
-    D.keep32 = (double)D.nnz * (4 + 1) <= kKeepCachedBytes ? F_KEEP : 0;
-    D.keep64 = (double)D.nnz * (8 + 1) <= kKeepCachedBytes ? F_KEEP : 0;
+    // the box-row and block-row kernels stream the values only
+    const int ib = (D.boxrow || H.rowptr.empty()) ? 0 : 1;
+    D.keep32 = (double)D.nnz * (4 + ib) <= kKeepCachedBytes ? F_KEEP : 0;
+    D.keep64 = (double)D.nnz * (8 + ib) <= kKeepCachedBytes ? F_KEEP : 0;
     if (!D.boxrow && !H.rowptr.empty()) {  // narrow block rows: the level is held as 1-byte local-column blocks
       D.rowptr.upload(H.rowptr, s);
       // the vector kernel: shape 9 over 2048-nonzero blocks, shape 11 over (3072, 64-row) blocks
