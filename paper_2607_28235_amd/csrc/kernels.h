@@ -19,8 +19,8 @@ enum : int {
                       // back-to-back applications of a smoothing sweep (k_level_local_vec, k_level_boxrow and the
                       // block-row kernels; without it they read it with nontemporal loads)
 };
-// Largest matrix stream (values, positions, column lists) of a level that is read with F_KEEP: the 2D Q3 fine
-// level in float32 (80 MB) gained, a 3D fine level of ~800 MB lost (its matrix evicted the vectors).
+// Largest matrix stream (values and positions) of a level that is read with F_KEEP: the 2D Q3 fine level (73 MB
+// in float32, 132 MB in float64) gained, a 3D fine level of ~700 MB lost (its matrix evicted the vectors).
 constexpr double kKeepCachedBytes = 128.0 * 1024 * 1024;
 
 constexpr int kMaxNR = 16;
