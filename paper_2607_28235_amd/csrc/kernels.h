@@ -113,9 +113,21 @@ void launch_level_blockrow(const LevelOp<T>& op, int maxnb, const T* u, const T*
 // entries: one wave per box, each lane owning positions of the block row in all the box's rows.
 constexpr int kBoxRowMaxNP = 3;
 bool boxrow_supported(int blk, int maxnb);
+// Restriction fused into a box-row launch (2D, four children per parent box, boxes 4 G .. 4 G + 3 the children
+// of parent G): the launch's residuals rho = b - A x of each parent's children are restricted with the
+// children's 1D factors pt (2 k^2 per child, k = p' + 1) into bnext[G B + a], and dnext = dinv_next bnext
+// inv_theta_next when dnext is set; the same sums in the same order as launch_restrict_c.  rho is still stored.
+template <typename T>
+struct BoxRestrict {
+  const T* pt = nullptr;
+  T* bnext = nullptr;
+  const T* dinv_next = nullptr;
+  T* dnext = nullptr;
+  T inv_theta_next = 0;
+};
 template <typename T>
 void launch_level_boxrow(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
-                         double c2, int flags, const int* skip, hipStream_t s);
+                         double c2, int flags, const int* skip, hipStream_t s, const BoxRestrict<T>* rs = nullptr);
 
 // Wide block rows (maxnb * blk large): one workgroup per (box, 8-row chunk).
 template <typename T>

@@ -1346,6 +1346,17 @@ template void launch_level_blockrow<float>(const LevelOp<float>&, int, const flo
 template void launch_level_blockrow<double>(const LevelOp<double>&, int, const double*, const double*, double*,
                                             double*, double*, double, double, int, const int*, hipStream_t);
 
+// Residual staging of the fused restriction: wave w's rows at [w BLK, (w + 1) BLK) of one LDS array.
+template <typename T, int BLK>
+__device__ inline T* rsh_data() {
+  __shared__ T rsh[4 * BLK];
+  return rsh;
+}
+template <typename T, int BLK>
+__device__ inline void rsh_store(int wv, int row, T r) {
+  rsh_data<T, BLK>()[wv * BLK + row] = r;
+}
+
 // Box-row kernel (2D agglomerated levels: boxes of BLK = 4, 9 or 16 rows): one wave per box K.  Lane p owns the
 // positions p + 64 m (m < NP) of the box's block row (w = nb BLK entries; position j BLK + c is column
 // bcol[j0 + j] BLK + c): it gathers u there once and multiplies it with that position's value in each of the
@@ -1353,12 +1364,14 @@ template void launch_level_blockrow<double>(const LevelOp<double>&, int, const d
 // needed.  The BLK row sums over the 64 lanes come out of a transposing butterfly over 16 slots (each step halves
 // the rows a lane keeps and doubles the lanes summed), in a fixed order; lane l then holds row
 // 8 b5 + 4 b4 + 2 b3 + b2 (b = bits of l) and the lanes with l % 4 == 0 apply the epilogue of k_level.
-template <typename T, int BLK, int NP, bool KEEP>
+// With RESTRICT (nbox a multiple of 4, workgroup G = the four children of parent box G) the workgroup then
+// restricts its residuals into the parent's entries of the next level (BoxRestrict).
+template <typename T, int BLK, int NP, bool KEEP, bool RESTRICT>
 __global__ __launch_bounds__(256) void k_level_boxrow(int nbox, const int* __restrict__ bptr,
                                                       const int* __restrict__ bcol, const T* __restrict__ val,
                                                       const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
                                                       const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
-                                                      const int* __restrict__ skip, int nlog) {
+                                                      const int* __restrict__ skip, int nlog, BoxRestrict<T> rs) {
   static_assert(BLK <= 16, "rows per box");
   if (skip && *skip) return;
   const int lb = xcd_block(nlog);
@@ -1419,6 +1432,26 @@ __global__ __launch_bounds__(256) void k_level_boxrow(int nbox, const int* __res
       else if (flags & F_X_ADD)
         x[row] = p_x + p_u;
       if (flags & F_D_OUT) dout[row] = c1 * p_u + c2 * p_di * r;
+      if constexpr (RESTRICT) rsh_store<T, BLK>(wv, myrow, r);
+    }
+  }
+  if constexpr (RESTRICT) {
+    __syncthreads();  // every wave is present: nbox is a multiple of 4
+    if (wv == 0 && lane < BLK) {
+      constexpr int k = BLK == 4 ? 2 : BLK == 9 ? 3 : 4, kk = k * k;
+      const int q0 = lane % k, q1 = lane / k;
+      const T* src = rsh_data<T, BLK>();
+      T sum = 0;
+      for (int C = 0; C < 4; ++C) {
+        const T* m = rs.pt + (int64_t)(lb * 4 + C) * 2 * kk;
+        const T* sc = src + C * BLK;
+        int qc = 0;
+        for (int a1 = 0; a1 < k; ++a1)
+          for (int a0 = 0; a0 < k; ++a0, ++qc) sum += (m[a0 * k + q0] * m[kk + a1 * k + q1]) * sc[qc];
+      }
+      const int64_t tq = (int64_t)lb * BLK + lane;
+      rs.bnext[tq] = sum;
+      if (rs.dnext) rs.dnext[tq] = rs.dinv_next[tq] * sum * rs.inv_theta_next;
     }
   }
 }
@@ -1429,20 +1462,33 @@ bool boxrow_supported(int blk, int maxnb) {
 
 template <typename T>
 void launch_level_boxrow(const LevelOp<T>& op, int maxnb, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
-                         double c2, int flags, const int* skip, hipStream_t s) {
+                         double c2, int flags, const int* skip, hipStream_t s, const BoxRestrict<T>* rs) {
   if (!boxrow_supported(op.blk, maxnb)) throw std::runtime_error("box-row kernel: unsupported box shape");
   const int nbox = op.n / op.blk;
   const int nlog = (nbox + 3) / 4;
   if (nlog == 0) return;
+  if (rs && (nbox % 4 != 0 || (flags & F_PLAIN) || !rs->pt || !rs->bnext))
+    throw std::runtime_error("box-row kernel: fused restriction needs four boxes per parent and a residual");
   const int np = (maxnb * op.blk + 63) / 64;
+  const BoxRestrict<T> ra = rs ? *rs : BoxRestrict<T>{};
 #define R3_BR(B, N)                                                                                               \
   do {                                                                                                            \
-    if (flags & F_KEEP)                                                                                           \
-      hipLaunchKernelGGL((k_level_boxrow<T, B, N, true>), dim3(xcd_grid(nlog)), dim3(256), 0, s, nbox, op.ptr,   \
-                         op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);           \
-    else                                                                                                          \
-      hipLaunchKernelGGL((k_level_boxrow<T, B, N, false>), dim3(xcd_grid(nlog)), dim3(256), 0, s, nbox, op.ptr,  \
-                         op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog);           \
+    if (rs) {                                                                                                     \
+      if (flags & F_KEEP)                                                                                         \
+        hipLaunchKernelGGL((k_level_boxrow<T, B, N, true, true>), dim3(xcd_grid(nlog)), dim3(256), 0, s, nbox,   \
+                           op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog,  \
+                           ra);                                                                                   \
+      else                                                                                                        \
+        hipLaunchKernelGGL((k_level_boxrow<T, B, N, false, true>), dim3(xcd_grid(nlog)), dim3(256), 0, s, nbox,  \
+                           op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog,  \
+                           ra);                                                                                   \
+    } else if (flags & F_KEEP) {                                                                                  \
+      hipLaunchKernelGGL((k_level_boxrow<T, B, N, true, false>), dim3(xcd_grid(nlog)), dim3(256), 0, s, nbox,    \
+                         op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog, ra); \
+    } else {                                                                                                      \
+      hipLaunchKernelGGL((k_level_boxrow<T, B, N, false, false>), dim3(xcd_grid(nlog)), dim3(256), 0, s, nbox,   \
+                         op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog, ra); \
+    }                                                                                                             \
   } while (0)
   if (op.blk == 4) {
     if (np == 1) R3_BR(4, 1); else if (np == 2) R3_BR(4, 2); else R3_BR(4, 3);
@@ -1455,9 +1501,11 @@ void launch_level_boxrow(const LevelOp<T>& op, int maxnb, const T* u, const T* b
   check_launch("k_level_boxrow");
 }
 template void launch_level_boxrow<float>(const LevelOp<float>&, int, const float*, const float*, float*, float*,
-                                         float*, double, double, int, const int*, hipStream_t);
+                                         float*, double, double, int, const int*, hipStream_t,
+                                         const BoxRestrict<float>*);
 template void launch_level_boxrow<double>(const LevelOp<double>&, int, const double*, const double*, double*,
-                                          double*, double*, double, double, int, const int*, hipStream_t);
+                                          double*, double*, double, double, int, const int*, hipStream_t,
+                                          const BoxRestrict<double>*);
 
 // Wide block rows (3D agglomerated levels): one 256-thread workgroup per (box K, chunk of 8 of its B rows),
 // grid = nbox * ceil(B/8).  The workgroup stages the nb*B entries of u touched by box K in LDS, then each wave

@@ -232,7 +232,7 @@ static int keep_flag(const DevLevel& D) {
 
 template <typename T>
 void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T* dout, double c1, double c2, int flags,
-                 const int* skip, hipStream_t s) {
+                 const int* skip, hipStream_t s, const BoxRestrict<T>* rs = nullptr) {
   LevelOp<T> op = level_op<T>(c, l);
   DevLevel& D = c.dv.lv[l];
   switch (level_kernel(c.an, D, l, nr, (int)sizeof(T))) {
@@ -265,7 +265,7 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
       break;
     }
     case LevelKernel::BoxRow:
-      launch_level_boxrow<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags | keep_flag<T>(D), skip, s);
+      launch_level_boxrow<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags | keep_flag<T>(D), skip, s, rs);
       break;
     case LevelKernel::BlockRowWG:
       launch_level_blockrow_wg<T>(op, D.maxnb, u, b, rho, x, dout, c1, c2, flags | keep_flag<T>(D), skip, s);
@@ -535,12 +535,12 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   bool x_zero = true, rho_is_b = true;
   const int total_spmv = K * (o.pre_steps + o.post_steps);
   int done_spmv = 0;
-  auto F = [&](T* u, T* dout, double c1, double c2, bool dout_on) {
+  auto F = [&](T* u, T* dout, double c1, double c2, bool dout_on, const BoxRestrict<T>* rs = nullptr) {
     int fl = (rho_is_b ? F_RHO_FROM_B : 0) | (x_zero ? F_X_ASSIGN : F_X_ADD);
     ++done_spmv;
     if (done_spmv < total_spmv) fl |= F_RHO_STORE;  // the level's last residual is never read
     if (dout_on) fl |= F_D_OUT;
-    apply_level<T>(c, l, nr, u, b, rho, x, dout, c1, c2, fl, skip, s);
+    apply_level<T>(c, l, nr, u, b, rho, x, dout, c1, c2, fl, skip, s, rs);
     x_zero = false;
     rho_is_b = false;
   };
@@ -563,24 +563,37 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
     }
     pend = u;
   }
-  if (pend) F(pend, nullptr, 0.0, 0.0, false);  // commit the last direction: rho = b - A x
-
   // restriction of the residual, fused with the first direction of the next level
-  const T* src = rho_is_b ? b : rho;
   DevLevel& N = dv.lv[l + 1];
   const bool next_smooth = (l + 1 < L) && o.pre_steps > 0;
   const double next_inv_theta = next_smooth ? 2.0 / (N.lam_hi + N.lam_lo) : 0.0;
   T* dnext = next_smooth ? vbuf<T>(N.dA) : nullptr;
   const T* dinv_next = nullptr;
   if constexpr (sizeof(T) == 4) dinv_next = N.dinv32.p; else dinv_next = N.dinv64.p;
-  if (l == 0) {
+  const T* pt = nullptr;
+  if (l > 0) {
+    if constexpr (sizeof(T) == 4) pt = D.pt32.p; else pt = D.pt64.p;
+  }
+  // a box-row level whose boxes come in fours per parent restricts inside the launch that forms its residual
+  const bool fused = pend && l > 0 && level_kernel(an, D, l, nr, (int)sizeof(T)) == LevelKernel::BoxRow &&
+                     N.child_shift == 2 && D.nbox == 4 * N.nbox && an.d == 2;
+  BoxRestrict<T> rs;
+  if (fused) {
+    rs.pt = pt;
+    rs.bnext = vbuf<T>(N.b);
+    rs.dinv_next = dinv_next;
+    rs.dnext = dnext;
+    rs.inv_theta_next = (T)next_inv_theta;
+  }
+  if (pend) F(pend, nullptr, 0.0, 0.0, false, fused ? &rs : nullptr);  // commit the last direction: rho = b - A x
+  const T* src = rho_is_b ? b : rho;
+  if (fused) {
+  } else if (l == 0) {
     const T* xi;
     if constexpr (sizeof(T) == 4) xi = D.xi32.p; else xi = D.xi64.p;
     launch_restrict0<T>((int)N.nbox, an.n, an.d, an.pc, nr, D.leaf_off.p, D.owner.p, xi, src, vbuf<T>(N.b), dinv_next,
                         dnext, next_inv_theta, skip, s);
   } else {
-    const T* pt;
-    if constexpr (sizeof(T) == 4) pt = D.pt32.p; else pt = D.pt64.p;
     launch_restrict_c<T>((int)N.nbox, (int)D.nbox, N.child_shift, an.d, an.pc, nr, pt, src, vbuf<T>(N.b),
                          dinv_next, dnext, next_inv_theta, skip, s);
   }
