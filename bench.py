@@ -69,7 +69,7 @@ def main():
                     help="also run a plain 256 MiB device copy (the HBM-counter calibration kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload not in ("solve2d", "solve3d"):
@@ -450,7 +450,7 @@ def bench_adjoint(args):
 
 
 # Section 6.1 tables on the structured Q1 square (p' = 0 and 1), for context only -- the paper's R-tree (Boost's
-# R*-tree, m = 2) differs from this build's bisection tree: per (agglomeration, table), rows of (refinements,
+# R*-tree, m = 2) differs from this library's bisection tree: per (agglomeration, table), rows of (refinements,
 # levels, the paper's iterations and condition estimates for p' = 0, then for p' = 1).
 # (ref, levels, paper iters / cond with the lower coarse degree, then with the higher one)
 PAPER_Q1 = {

@@ -503,7 +503,7 @@ def test_condition_estimate_and_absolute_stop(small2d):
 def q1_sweep():
     """Structured Q1 unit square after 6 and 7 refinements (4,225 and 16,641 DoFs, the paper's Table of fixed
     H/h), point agglomeration with leaf size M = 8 (the paper's m = 2 leaves corner boxes with fewer free points
-    than Q^1 needs under this build's unisolvence test), leaf level skipped, two levels, V(2,2) Chebyshev-3, stop
+    than Q^1 needs under this library's unisolvence test), leaf level skipped, two levels, V(2,2) Chebyshev-3, stop
     at a 1e-6 reduction or 1e-9 absolute (Section 6)."""
     _need_gpu()
     P = _P()
