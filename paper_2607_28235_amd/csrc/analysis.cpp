@@ -158,6 +158,15 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
         throw err(R3MG_ERR_INVALID, "columns must be strictly ascending within a row");
       if (!std::isfinite(vals[p])) throw err(R3MG_ERR_INVALID, "non-finite matrix value");
     }
+  // the Jacobi smoother divides by the diagonal: every row, constrained ones included (their identity rows),
+  // must store a positive diagonal entry (Section 6 smoother; the coarse levels are checked at r3mg_factor)
+  for (int64_t i = 0; i < n; ++i) {
+    double dg = 0.0;
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+      if (col_idx[p] == i) dg = vals[p];
+    if (!(dg > 0.0))
+      throw err(R3MG_ERR_NOT_SPD, "non-positive or missing diagonal entry in row " + std::to_string((long long)i));
+  }
   an->user_rowptr.assign(row_ptr, row_ptr + n + 1);
   an->user_col.assign(col_idx, col_idx + nnz);
 

@@ -135,10 +135,10 @@ def test_adjoint_gradient_matches_oracle(adjoint_small):
     Lo, go, uo, lo = O.loss_and_gradient(solve, prob.cells, prob.Ke, kappa, prob.mass_rhs_weights, ut, prob.boundary)
     assert _rel(u.detach().cpu().numpy(), uo) < 1e-10
     assert abs(float(L.detach()) - Lo) <= 1e-9 * Lo
-    assert _rel(g, go) < 1e-8
+    assert _rel(g, go) < 1e-9
     # Euler identity: sum_e kappa_e g_e = -(u - u_t)^T u
     uu = u.detach().cpu().numpy()
-    assert abs(kappa @ g + (uu - ut) @ uu) <= 1e-8 * abs((uu - ut) @ uu)
+    assert abs(kappa @ g + (uu - ut) @ uu) <= 1e-9 * abs((uu - ut) @ uu)
 
 
 def test_adjoint_gradient_finite_differences(adjoint_small):

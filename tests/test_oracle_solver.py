@@ -220,3 +220,24 @@ def test_adjoint_gradient_dense_formula():
                     dA[c[a], c[bb]] += prob.Ke[a, bb]
         du = -np.linalg.solve(A, dA @ u)
         assert abs((u - ut) @ du - g[e]) <= 1e-10 * max(1.0, abs(g[e]))
+
+
+def test_pcg_batched_columns_match_direct_solves():
+    """O12: independent PCG per right-hand side, each frozen on its own convergence.  Pinned against a dense
+    direct solve of every column, a zero column (0 iterations, x = 0) and a scaled column (the stop rule is
+    relative, so a scaled right-hand side takes the same iterations and gives the scaled solution)."""
+    w = F.workload(1)
+    A = w.problem.scipy()
+    h = O.build_hierarchy(w.problem.coords, A, coarse_degree=1, leaf_size=64, max_levels=2,
+                          pre_steps=1, post_steps=1)
+    g = np.random.default_rng(11)
+    b1 = g.standard_normal(w.problem.n)
+    b1[w.problem.boundary] = 0.0
+    Bm = np.stack([w.rhs, np.zeros(w.problem.n), 1e6 * w.rhs, b1])
+    X, iters = O.pcg_batched(h, Bm, rtol=1e-13)
+    Xs = np.linalg.solve(A.toarray(), Bm.T).T
+    for j in (0, 2, 3):
+        assert np.linalg.norm(X[j] - Xs[j]) <= 1e-11 * np.linalg.norm(Xs[j])
+    assert iters[1] == 0 and np.all(X[1] == 0.0)
+    assert iters[2] == iters[0] and iters[0] > 0
+    np.testing.assert_allclose(X[2], 1e6 * X[0], rtol=0, atol=1e-9 * np.abs(X[2]).max())
