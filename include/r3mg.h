@@ -185,6 +185,14 @@ r3mg_status r3mg_pcg_solve_ex(r3mg_handle h, const double* b_dev, double* x_dev,
 r3mg_status r3mg_pcg_solve_group(int count, r3mg_handle* hs, const double* const* b, double* const* x,
                                  double rtol, int maxit, void* stream, int* iters, double* relres);
 
+/* Convergence history of the last PCG solve on the handle (r3mg_pcg_solve, r3mg_pcg_solve_ex, or this handle's
+ * problem in r3mg_pcg_solve_group): rr[j] = ||r_j||_2, the recursive residual norm after j iterations, for
+ * j = 0 .. iters of column `col` (0 <= col < 16) of the last block of at most 16 right-hand sides solved.  *count
+ * receives iters + 1 (0 before any solve); min(cap, *count) entries are written (rr may be NULL to query the
+ * count).  After a residual-replacement restart (float32 V-cycle) the entries that follow it are the norms of the
+ * restarted recursion.  Synchronises.  Errors: INVALID (col or cap out of range, handle not factored). */
+r3mg_status r3mg_pcg_history(r3mg_handle h, int col, double* rr, int cap, int* count);
+
 /* Per-level statistics: levels has room for *nlevels entries on input; on output *nlevels = level count
  * (levels may be NULL to query the count). */
 r3mg_status r3mg_info(r3mg_handle h, r3mg_level_info* levels, int* nlevels);
@@ -206,10 +214,13 @@ r3mg_status r3mg_export_level(r3mg_handle h, int level, int64_t* row_ptr, int32_
                               int64_t* nrows, int64_t* nnz);
 
 /* Average device time of one launch of the level-`level` fused smoother kernel (SpMV + Chebyshev update) in
- * the V-cycle precision, over `reps` back-to-back launches timed with hipEvents on `stream`, and the
- * algorithmic HBM bytes of one launch.  Diagnostic entry point for roofline measurement. */
-r3mg_status r3mg_time_smoother_kernel(r3mg_handle h, int level, int reps, void* stream, double* ms_per_launch,
-                                      double* bytes_per_launch);
+ * the V-cycle precision, timed with hipEvents on `stream`, and the bytes one launch of the level's storage format
+ * moves (matrix as stored, row data, 7 vector streams).  flush_bytes = 0: `reps` back-to-back launches, as a
+ * smoothing sweep runs them (the caches may keep part of the matrix between launches); flush_bytes > 0: each
+ * launch timed alone after a pass that reads and writes flush_bytes of other device memory (allocated for the
+ * call), so that its operands come from HBM.  Diagnostic entry point for roofline measurement. */
+r3mg_status r3mg_time_smoother_kernel(r3mg_handle h, int level, int reps, int64_t flush_bytes, void* stream,
+                                      double* ms_per_launch, double* bytes_per_launch);
 
 /* Adjoint gradient of a per-cell coefficient (standard adjoint method; not in the paper):
  * g[e] = - sum_{a,b unconstrained} lam[c_ea] Ke_e[a,b] u[c_eb], cells (device, ncells x nloc int32, caller's

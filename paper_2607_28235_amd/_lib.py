@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID", -2: "NOT_UNISOLVENT"
 EXPORTED = [
     "r3mg_analyze_cells", "r3mg_set_matrix_free",
     "r3mg_default_options", "r3mg_analyze", "r3mg_factor", "r3mg_setup", "r3mg_update_values", "r3mg_vcycle",
-    "r3mg_level_apply", "r3mg_pcg_solve", "r3mg_pcg_solve_ex", "r3mg_pcg_solve_group", "r3mg_info", "r3mg_export_partition",
+    "r3mg_level_apply", "r3mg_pcg_solve", "r3mg_pcg_solve_ex", "r3mg_pcg_solve_group", "r3mg_pcg_history",
+    "r3mg_info", "r3mg_export_partition",
     "r3mg_export_P", "r3mg_export_level", "r3mg_time_smoother_kernel", "r3mg_cell_grad", "r3mg_assembler_create",
     "r3mg_assemble", "r3mg_assembler_free", "r3mg_rtree", "r3mg_free", "r3mg_status_string", "r3mg_last_error",
 ]
@@ -98,11 +99,12 @@ def lib():
     L.r3mg_pcg_solve.argtypes = [vp, vp, vp, i32, dbl, i32, vp, vp, vp]
     L.r3mg_pcg_solve_ex.argtypes = [vp, vp, vp, i32, dbl, dbl, i32, vp, vp, vp, vp]
     L.r3mg_pcg_solve_group.argtypes = [i32, vp, vp, vp, dbl, i32, vp, vp, vp]
+    L.r3mg_pcg_history.argtypes = [vp, i32, vp, i32, P(i32)]
     L.r3mg_info.argtypes = [vp, vp, P(i32)]
     L.r3mg_export_partition.argtypes = [vp, i32, vp, vp]
     L.r3mg_export_P.argtypes = [vp, i32, vp, vp, vp, P(i64), P(i64)]
     L.r3mg_export_level.argtypes = [vp, i32, vp, vp, vp, P(i64), P(i64)]
-    L.r3mg_time_smoother_kernel.argtypes = [vp, i32, i32, vp, P(dbl), P(dbl)]
+    L.r3mg_time_smoother_kernel.argtypes = [vp, i32, i32, i64, vp, P(dbl), P(dbl)]
     L.r3mg_cell_grad.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp, i64, vp]
     L.r3mg_assembler_create.argtypes = [vp, vp, i32, i64, P(vp)]
     L.r3mg_assemble.argtypes = [vp, vp, vp, i64, vp, vp]
@@ -242,15 +244,25 @@ class Hierarchy:
         _check(st, "r3mg_pcg_solve_ex", allow_not_converged=not raise_not_converged)
         return (iters, relres, st == OK, cond) if return_cond else (iters, relres, st == OK)
 
+    def history(self, col: int = 0) -> np.ndarray:
+        """Recursive residual norms ||r_j||, j = 0..iters, of column `col` of the last PCG solve."""
+        cnt = C.c_int(0)
+        _check(lib().r3mg_pcg_history(self._h, col, None, 0, C.byref(cnt)), "r3mg_pcg_history")
+        out = np.zeros(cnt.value, dtype=np.float64)
+        if cnt.value:
+            _check(lib().r3mg_pcg_history(self._h, col, _ptr(out), cnt.value, C.byref(cnt)), "r3mg_pcg_history")
+        return out
+
     def cell_grad(self, cells_dev, Ke_dev, ke_stride: int, u, lam, g, stream=None):
         ncells, nloc = cells_dev.shape
         _check(lib().r3mg_cell_grad(self._h, _dev(cells_dev), nloc, _dev(Ke_dev), ke_stride, _dev(u), _dev(lam),
                                     _dev(g), ncells, _stream(stream)), "r3mg_cell_grad")
 
-    def time_smoother_kernel(self, level: int, reps: int, stream=None):
+    def time_smoother_kernel(self, level: int, reps: int, stream=None, flush_bytes: int = 0):
+        """(ms per launch, bytes per launch); flush_bytes > 0 times each launch alone after evicting the caches."""
         ms, by = C.c_double(), C.c_double()
-        _check(lib().r3mg_time_smoother_kernel(self._h, level, reps, _stream(stream), C.byref(ms), C.byref(by)),
-               "r3mg_time_smoother_kernel")
+        _check(lib().r3mg_time_smoother_kernel(self._h, level, reps, int(flush_bytes), _stream(stream), C.byref(ms),
+                                               C.byref(by)), "r3mg_time_smoother_kernel")
         return ms.value, by.value
 
     # --- host queries ----------------------------------------------------------------------------

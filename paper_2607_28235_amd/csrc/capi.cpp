@@ -218,6 +218,15 @@ r3mg_status r3mg_pcg_solve_group(int count, r3mg_handle* hs, const double* const
   });
 }
 
+r3mg_status r3mg_pcg_history(r3mg_handle h, int col, double* rr, int cap, int* count) {
+  return guard([&] {
+    require_factored(h);
+    if (!count || col < 0 || col >= kMaxNR || cap < 0) throw Error{R3MG_ERR_INVALID, "bad history arguments"};
+    *count = residual_history(h->impl, col, rr, cap);
+    return R3MG_OK;
+  });
+}
+
 r3mg_status r3mg_info(r3mg_handle h, r3mg_level_info* levels, int* nlevels) {
   return guard([&] {
     if (!h || !nlevels) throw Error{R3MG_ERR_INVALID, "null argument"};
@@ -380,14 +389,14 @@ r3mg_status r3mg_export_level(r3mg_handle h, int level, int64_t* row_ptr, int32_
   });
 }
 
-r3mg_status r3mg_time_smoother_kernel(r3mg_handle h, int level, int reps, void* stream, double* ms_per_launch,
-                                      double* bytes_per_launch) {
+r3mg_status r3mg_time_smoother_kernel(r3mg_handle h, int level, int reps, int64_t flush_bytes, void* stream,
+                                      double* ms_per_launch, double* bytes_per_launch) {
   return guard([&] {
     require_factored(h);
     const int L = h->impl.an->nlevels() - 1;
-    if (level < 0 || level >= L || reps < 1 || !ms_per_launch || !bytes_per_launch)
+    if (level < 0 || level >= L || reps < 1 || flush_bytes < 0 || !ms_per_launch || !bytes_per_launch)
       throw Error{R3MG_ERR_INVALID, "bad timing arguments"};
-    time_smoother_kernel(h->impl, level, reps, S(stream), ms_per_launch, bytes_per_launch);
+    time_smoother_kernel(h->impl, level, reps, flush_bytes, S(stream), ms_per_launch, bytes_per_launch);
     return R3MG_OK;
   });
 }

@@ -25,14 +25,20 @@ constexpr double kKeepCachedBytes = 128.0 * 1024 * 1024;
 
 constexpr int kMaxNR = 16;
 
+// Device-side PCG state of one block of up to kMaxNR columns.  all_done must stay the first word: every kernel
+// of an iteration reads it through the `skip` pointer and returns at once when it is set.
 struct PcgState {
-  int all_done, nr, flexible, pad;
+  int all_done, nr, flexible, restart;  // restart: set by the true-residual check when a converged column's true
+                                        // residual fails the stop rule (float32 V-cycle: residual replacement)
   int iters[kMaxNR];
   int done[kMaxNR];
-  double gamma[kMaxNR], alpha[kMaxNR], beta[kMaxNR], rr[kMaxNR], rr0[kMaxNR], tau2[kMaxNR];
+  double gamma[kMaxNR], alpha[kMaxNR], beta[kMaxNR], rr[kMaxNR], rr_prev[kMaxNR], rr0[kMaxNR], tau2[kMaxNR],
+      rr_true[kMaxNR];
   // CG coefficients per iteration j < hist_rows (Lanczos condition estimate): alpha_j of column k at
-  // hist[2 j kMaxNR + k], beta_j at hist[(2 j + 1) kMaxNR + k]
+  // hist[2 j kMaxNR + k], beta_j at hist[(2 j + 1) kMaxNR + k]; squared recursive residual norms ||r_j||^2,
+  // j = 0..hist_rows, at rhist[j kMaxNR + k]
   double* hist;
+  double* rhist;
   int hist_rows, pad2;
 };
 
@@ -207,12 +213,6 @@ bool launch_level_split(const LevelOp<T>& op, int nr, int G, const T* u, const T
 template <typename T>
 bool launch_level_local_mr(int geom, const FineBlocks& fb, const LevelOp<T>& op, int nr, const T* u, const T* b,
                            T* rho, T* x, T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s);
-// partial sums of p_k q_k per column of n x nr interleaved vectors in a fixed partition:
-// partials[blk * nr + k]; returns the number of blocks (<= 1024)
-int launch_pcg_dot_mr(int n, int nr, const double* p, const double* q, double* partials, const int* skip,
-                      hipStream_t s);
-// partial sums of p_i q_i for one PCG column in a fixed partition (returns the count, <= 1024)
-int launch_pcg_dot(int n, const double* p, const double* q, double* partials, const int* skip, hipStream_t s);
 // partial sums of w_i x_i y_i (w may be null) -> partials (returns count)
 int launch_dot(int64_t n, const double* w, const double* x, const double* y, double* partials, hipStream_t s);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);   // y = a x + b y
@@ -261,25 +261,40 @@ void launch_mf_apply_mr(const MfOp& m, int nr, const MfTables<T>& tb, const T* g
 // dense Cholesky (lower, in place, row-major n x n) and inverse; *bad set on a non-positive pivot
 void dense_cholesky_inverse(int n, double* A, double* Inv, int* bad, hipStream_t s);
 
-// PCG (float64)
-template <typename T>
-void launch_pcg_xr(int n, int nr, PcgState* st, const double* partials_pq, int npart, double* x, double* r,
-                   const double* p, const double* q, double* partials_rr, T* b0, const T* dinv0, T* d0,
-                   double inv_theta0, hipStream_t s);
+// PCG (float64).  Each reduction is a vector kernel storing per-block partial sums (at most kPcgBlocks blocks,
+// a partition that depends only on n and nr, so the iterates do not depend on the kernel that formed A p)
+// followed by a one-block kernel that sums them in index order and updates the scalars of `st`.
+constexpr int kPcgBlocks = 1024;
+// <p, q> per column (n x nr interleaved) and alpha = gamma / <p, q> (0 for converged columns); skips when
+// st->all_done.  nr in {1, 2, 4, 8, 16}.
+void launch_pcg_dot_alpha(int n, int nr, const double* p, const double* q, double* partials, PcgState* st,
+                          hipStream_t s);
+// alpha from partials[b * nr + k], b < npart, formed by another kernel (the lanes kernel's fused dot)
 void launch_pcg_alpha(int nr, PcgState* st, const double* partials, int npart, hipStream_t s);
-void launch_pcg_check(int nr, PcgState* st, const double* partials, int npart, hipStream_t s);
+// x += alpha p; r -= alpha q; ||r||^2 and the stop test (iteration counts, done flags, all_done, residual
+// history); V-cycle entry b0 = (T) r (float32 V-cycle only) and d0 = dinv0 b0 / theta0 when d0 is set
 template <typename T>
-void launch_pcg_z(int n, int nr, PcgState* st, const T* x0, const T* dpend, double* z, const double* r,
-                  const double* q, double* partials, hipStream_t s);
-void launch_pcg_beta(int nr, PcgState* st, const double* partials, int npart, hipStream_t s);
+void launch_pcg_xr(int n, int nr, PcgState* st, double* x, double* r, const double* p, const double* q,
+                   double* partials, T* b0, const T* dinv0, T* d0, double inv_theta0, hipStream_t s);
+// z = (double)(x0 + dpend) (dpend may be null).  mode 0: nothing else (st may be null); mode 1 (PCG start):
+// p = z and gamma = <r, z>; mode 2 (iteration): beta = <r, z> / gamma, or -alpha <q, z> / gamma with q set
+// (flexible), and gamma = <r, z>.  Modes 1 and 2 skip when st->all_done.
+template <typename T>
+void launch_pcg_z(int n, int nr, PcgState* st, int mode, const T* x0, const T* dpend, double* z, const double* r,
+                  const double* q, double* p, double* partials, hipStream_t s);
 void launch_pcg_p(int n, int nr, PcgState* st, const double* z, double* p, hipStream_t s);
-// init: r = b - q; partial rr
-int launch_residual(int n, int nr, const double* b, const double* q, double* r, double* partials, hipStream_t s);
-void launch_pcg_init(int nr, PcgState* st, const double* partials, int npart, double rtol, double atol, int flexible,
-                     double* hist, int hist_rows,
-                     hipStream_t s);
-void launch_pcg_init_gamma(int n, int nr, PcgState* st, const double* partials, int npart, const double* z,
-                           double* p, hipStream_t s);
+// r = b - q and the initial state: ||r_0||^2, tau^2 = max(rtol^2 ||r_0||^2, atol^2), done flags (columns
+// k >= nr_active are done from the start).  restart = 1: a restart from the true residual that keeps tau^2,
+// ||r_0||^2 and the iteration counts of every column.
+void launch_pcg_residual_init(int n, int nr, const double* b, const double* q, double* r, double* partials,
+                              PcgState* st, int restart, double rtol, double atol, int nr_active, int flexible,
+                              double* hist, double* rhist, int hist_rows, hipStream_t s);
+// ||b - q||^2 per column into st->rr_true; st->restart = 1 if a converged column fails its stop rule with it.
+// Never skips (it runs after the iterations).
+void launch_pcg_true_residual(int n, int nr, const double* b, const double* q, double* partials, PcgState* st,
+                              hipStream_t s);
+// copy *st to host-mapped pinned memory (device address of a hipHostMalloc buffer)
+void launch_pcg_state_out(const PcgState* st, PcgState* host_mapped, hipStream_t s);
 template <typename T>
 void launch_vc_prep(int n, int nr, const double* r, T* b0, const T* dinv0, T* d0, double inv_theta0,
                     const int* skip, hipStream_t s);

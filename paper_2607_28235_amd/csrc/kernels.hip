@@ -1195,47 +1195,6 @@ template bool launch_level_local_mr<double>(int, const FineBlocks&, const LevelO
                                             const double*, double*, double*, double*, double, double, int, const int*,
                                             hipStream_t);
 
-// <p_k, q_k> per column k of n x NR interleaved vectors in a fixed partition: thread t of a block always handles
-// column t % NR (256 % NR == 0) of 256-row chunks (coalesced), the lanes of one column are combined by a
-// butterfly, the four waves in order.  partials[blk * NR + k]; returns the number of blocks.
-template <int NR>
-__global__ __launch_bounds__(256) void k_pcg_dot_mr(int n, const double* __restrict__ p, const double* __restrict__ q,
-                                                    double* partials, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  __shared__ double sh[4][NR];
-  double acc = 0;
-  const int64_t tot = (int64_t)n * NR;
-  for (int64_t base = (int64_t)blockIdx.x * 256 * NR; base < tot; base += (int64_t)gridDim.x * 256 * NR)
-#pragma unroll
-    for (int m = 0; m < NR; ++m) {
-      const int64_t o = base + threadIdx.x + 256 * m;
-      if (o < tot) acc += p[o] * q[o];
-    }
-#pragma unroll
-  for (int off = 32; off >= NR; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  const int lane = threadIdx.x & 63;
-  if (lane < NR) sh[threadIdx.x >> 6][lane] = acc;
-  __syncthreads();
-  if (threadIdx.x < NR) {
-    const int kk = threadIdx.x;
-    partials[(int64_t)blockIdx.x * NR + kk] = (sh[0][kk] + sh[1][kk]) + (sh[2][kk] + sh[3][kk]);
-  }
-}
-int launch_pcg_dot_mr(int n, int nr, const double* p, const double* q, double* partials, const int* skip,
-                      hipStream_t s) {
-  int g = (n + 255) / 256;
-  if (g > 1024) g = 1024;
-  if (g < 1) g = 1;
-  switch (nr) {
-    case 2: hipLaunchKernelGGL(k_pcg_dot_mr<2>, dim3(g), dim3(256), 0, s, n, p, q, partials, skip); break;
-    case 4: hipLaunchKernelGGL(k_pcg_dot_mr<4>, dim3(g), dim3(256), 0, s, n, p, q, partials, skip); break;
-    case 8: hipLaunchKernelGGL(k_pcg_dot_mr<8>, dim3(g), dim3(256), 0, s, n, p, q, partials, skip); break;
-    case 16: hipLaunchKernelGGL(k_pcg_dot_mr<16>, dim3(g), dim3(256), 0, s, n, p, q, partials, skip); break;
-    default: throw std::runtime_error("unsupported nrhs block");
-  }
-  check_launch("k_pcg_dot_mr");
-  return g;
-}
 
 
 // Block-row variant of the fused kernel for the agglomerated levels, one right-hand side.  One wave per box K,
@@ -2530,25 +2489,6 @@ void launch_lanczos_start(int n, const int* perm, double* v, hipStream_t s) {
 }
 
 // per-block partial sums of w_i x_i y_i (fixed grid of at most 1024 blocks, grid-stride)
-// <p, q> of one PCG column in a fixed partition (at most 1024 blocks, grid-stride), independent of the kernel
-// that formed q: partials[0..g) for k_pcg_alpha.
-__global__ __launch_bounds__(256) void k_pcg_dot(int n, const double* __restrict__ p, const double* __restrict__ q,
-                                                 double* partials, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  __shared__ double sh[4];
-  double acc = 0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) acc += p[i] * q[i];
-  const double t = block_sum256(acc, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = t;
-}
-int launch_pcg_dot(int n, const double* p, const double* q, double* partials, const int* skip, hipStream_t s) {
-  int g = (n + 255) / 256;
-  if (g > 1024) g = 1024;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_pcg_dot, dim3(g), dim3(256), 0, s, n, p, q, partials, skip);
-  check_launch("k_pcg_dot");
-  return g;
-}
 __global__ __launch_bounds__(256) void k_dot(int64_t n, const double* __restrict__ w, const double* __restrict__ x,
                                              const double* __restrict__ y, double* partials) {
   __shared__ double sh[4];
@@ -2756,51 +2696,17 @@ void dense_cholesky_inverse(int n, double* A, double* Inv, int* bad, hipStream_t
 // =============================================================================================
 // PCG (float64 outer iteration; scalars live on the device)
 // =============================================================================================
-// sum of partials[b * nr + k] over b < npart by one 1024-thread block (fixed order: deterministic);
-// the total is returned in thread 0.  sh must hold 16 doubles.
-__device__ inline double sum_partials(const double* __restrict__ partials, int npart, int nr, int k, double* sh) {
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-  int b = threadIdx.x;
-  for (; b + 3 * 1024 < npart; b += 4 * 1024) {
-    a0 += partials[(int64_t)b * nr + k];
-    a1 += partials[(int64_t)(b + 1024) * nr + k];
-    a2 += partials[(int64_t)(b + 2048) * nr + k];
-    a3 += partials[(int64_t)(b + 3072) * nr + k];
-  }
-  for (; b < npart; b += 1024) a0 += partials[(int64_t)b * nr + k];
-  double v = wave_sum((a0 + a1) + (a2 + a3), 64);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double r = 0;
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < 16; ++i) r += sh[i];
-  }
-  __syncthreads();
-  return r;
-}
+// Every reduction is a vector kernel that stores per-block partial sums, followed by a one-block kernel that sums
+// them in index order and updates the scalars in PcgState.  Vector kernels are grid-stride with at most
+// kPcgBlocks blocks, so the partition of every reduction depends only on n and NR and a reduction's result never
+// depends on the kernel that formed its operands.  (Finishing a reduction inside the vector kernel, in the block
+// that arrives last, was measured slower: the device-scope release each block must issue before taking its
+// ticket writes back its die's L2, and 1024 of them cost 60-80 us per kernel against ~4 us for the extra
+// launch.)  Vectors are n x NR interleaved; thread t of a block always handles column t % NR of 256-row chunks
+// (256 % NR == 0), so consecutive threads touch consecutive elements.
 
-__global__ __launch_bounds__(1024) void k_pcg_alpha(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
-  __shared__ double sh[16];
-  if (st->all_done) return;
-  for (int k = 0; k < nr; ++k) {
-    const double pq = sum_partials(partials, npart, nr, k, sh);
-    if (threadIdx.x == 0) {
-      st->alpha[k] = st->done[k] ? 0.0 : st->gamma[k] / pq;
-      const int j = st->iters[k];
-      if (!st->done[k] && st->hist && j < st->hist_rows) st->hist[(int64_t)2 * j * kMaxNR + k] = st->alpha[k];
-    }
-  }
-}
-void launch_pcg_alpha(int nr, PcgState* st, const double* partials, int npart, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1024), 0, s, nr, st, partials, npart);
-  check_launch("k_pcg_alpha");
-}
-
-// x += alpha p; r -= alpha q; partial ||r||^2; V-cycle entry b0 = (T) r, d0 = dinv0 b0 / theta0
-// Block lb covers rows [256 lb, 256 lb + 256) of the n x NR interleaved vectors; thread t handles the
-// elements 256 NR lb + t + 256 m (m < NR), all of column k = t % NR (256 % NR == 0): consecutive threads touch
-// consecutive elements.  Column sums: butterfly over the lanes of one column, then the four waves in order.
+// Per-column block sums: butterfly over the lanes of one column, then the four waves in order; thread k < NR
+// writes out[k].
 template <int NR>
 __device__ inline void column_partials(double acc, double* sh, double* out) {
 #pragma unroll
@@ -2814,156 +2720,249 @@ __device__ inline void column_partials(double acc, double* sh, double* out) {
   }
 }
 
-template <typename T, int NR>
-__global__ __launch_bounds__(256) void k_pcg_xr(int n, PcgState* st, double* x, double* r, const double* __restrict__ p,
-                                                const double* __restrict__ q, double* partials, T* b0,
-                                                const T* __restrict__ dinv0, T* d0, T inv_theta0, int nlog) {
+// Column totals of part[b * stride + k] (k < NR, b < nb) by one 256-thread block: thread t sums blocks t / NR,
+// t / NR + 256 / NR, ... of column t % NR in index order, then column_partials.  tot (shared) is valid in every
+// thread on return.
+template <int NR>
+__device__ inline void column_totals(const double* __restrict__ part, int nb, int stride, double* sh, double* tot) {
+  const int k = threadIdx.x % NR;
+  double acc = 0;
+  for (int b = threadIdx.x / NR; b < nb; b += 256 / NR) acc += part[(int64_t)b * stride + k];
+  column_partials<NR>(acc, sh, tot);
+  __syncthreads();
+}
+
+inline int pcg_grid(int n) {
+  const int g = (n + 255) / 256;
+  return std::max(1, std::min(g, kPcgBlocks));
+}
+
+#define R3_NR_SWITCH(nr, MACRO)                                   \
+  switch (nr) {                                                   \
+    case 1: MACRO(1); break;                                      \
+    case 2: MACRO(2); break;                                      \
+    case 4: MACRO(4); break;                                      \
+    case 8: MACRO(8); break;                                      \
+    case 16: MACRO(16); break;                                    \
+    default: throw std::runtime_error("unsupported nrhs block");  \
+  }
+
+__device__ inline void pcg_set_alpha(PcgState* st, int k, double pq) {
+  st->alpha[k] = st->done[k] ? 0.0 : st->gamma[k] / pq;
+  const int j = st->iters[k];
+  if (!st->done[k] && st->hist && j < st->hist_rows) st->hist[(int64_t)2 * j * kMaxNR + k] = st->alpha[k];
+}
+
+// <p, q> per column: partials[b * NR + k]
+template <int NR>
+__global__ __launch_bounds__(256) void k_pcg_dot(int n, const double* __restrict__ p, const double* __restrict__ q,
+                                                 double* partials, const PcgState* __restrict__ st) {
   __shared__ double sh[4 * NR];
   if (st->all_done) return;
-  const int lb = xcd_block(nlog);
-  if (lb < 0) return;
-  const int k = threadIdx.x % NR;
-  const double al = st->alpha[k];
-  const int64_t tot = (int64_t)n * NR;
-  const int64_t base = (int64_t)lb * 256 * NR;
   double acc = 0;
+  const int64_t tn = (int64_t)n * NR;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * NR; base < tn; base += (int64_t)gridDim.x * 256 * NR)
 #pragma unroll
-  for (int m = 0; m < NR; ++m) {
-    const int64_t o = base + threadIdx.x + 256 * m;
-    if (o < tot) {
-      x[o] += al * p[o];
-      const double rv = r[o] - al * q[o];
-      r[o] = rv;
-      acc += rv * rv;
-      if (b0) {
-        const T bv = (T)rv;
-        b0[o] = bv;
-        if (d0) d0[o] = dinv0[o / NR] * bv * inv_theta0;
-      } else if (d0) {
-        d0[o] = dinv0[o / NR] * (T)rv * inv_theta0;
-      }
+    for (int m = 0; m < NR; ++m) {
+      const int64_t o = base + threadIdx.x + 256 * m;
+      if (o < tn) acc += p[o] * q[o];
     }
-  }
-  column_partials<NR>(acc, sh, partials + (int64_t)lb * NR);
+  column_partials<NR>(acc, sh, partials + (int64_t)blockIdx.x * NR);
 }
-template <typename T>
-void launch_pcg_xr(int n, int nr, PcgState* st, const double* partials_pq, int npart, double* x, double* r,
-                   const double* p, const double* q, double* partials_rr, T* b0, const T* dinv0, T* d0,
-                   double inv_theta0, hipStream_t s) {
-  launch_pcg_alpha(nr, st, partials_pq, npart, s);
-  const int nlog = (n + 255) / 256;
-  dim3 g(xcd_grid(nlog));
-#define R3_XR(NRV) \
-  hipLaunchKernelGGL((k_pcg_xr<T, NRV>), g, dim3(256), 0, s, n, st, x, r, p, q, partials_rr, b0, dinv0, d0, (T)inv_theta0, nlog)
-  switch (nr) {
-    case 1: R3_XR(1); break;
-    case 2: R3_XR(2); break;
-    case 4: R3_XR(4); break;
-    case 8: R3_XR(8); break;
-    case 16: R3_XR(16); break;
-    default: throw std::runtime_error("unsupported nrhs block");
-  }
-#undef R3_XR
-  check_launch("k_pcg_xr");
+template <int NR>
+__global__ __launch_bounds__(256) void k_pcg_alpha_nr(PcgState* st, const double* __restrict__ partials, int nb) {
+  __shared__ double sh[4 * NR];
+  __shared__ double tot[NR];
+  if (st->all_done) return;
+  column_totals<NR>(partials, nb, NR, sh, tot);
+  if (threadIdx.x < NR) pcg_set_alpha(st, threadIdx.x, tot[threadIdx.x]);
 }
-template void launch_pcg_xr<float>(int, int, PcgState*, const double*, int, double*, double*, const double*,
-                                   const double*, double*, float*, const float*, float*, double, hipStream_t);
-template void launch_pcg_xr<double>(int, int, PcgState*, const double*, int, double*, double*, const double*,
-                                    const double*, double*, double*, const double*, double*, double, hipStream_t);
+void launch_pcg_dot_alpha(int n, int nr, const double* p, const double* q, double* partials, PcgState* st,
+                          hipStream_t s) {
+  const int g = pcg_grid(n);
+#define R3_DA(NRV)                                                                                 \
+  hipLaunchKernelGGL((k_pcg_dot<NRV>), dim3(g), dim3(256), 0, s, n, p, q, partials, st);           \
+  hipLaunchKernelGGL((k_pcg_alpha_nr<NRV>), dim3(1), dim3(256), 0, s, st, partials, g)
+  R3_NR_SWITCH(nr, R3_DA)
+#undef R3_DA
+  check_launch("k_pcg_dot / k_pcg_alpha");
+}
 
-__global__ __launch_bounds__(1024) void k_pcg_check(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
+// alpha from partials formed by another kernel (the lanes kernel's fused dot: up to one partial per 32 rows),
+// one 1024-thread block summing each column in a fixed order
+__global__ __launch_bounds__(1024) void k_pcg_alpha(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
   __shared__ double sh[16];
   if (st->all_done) return;
-  int all = 1;
   for (int k = 0; k < nr; ++k) {
-    const double rr = sum_partials(partials, npart, nr, k, sh);
-    if (threadIdx.x == 0 && !st->done[k]) {
-      st->rr[k] = rr;
-      st->iters[k] += 1;
-      if (rr <= st->tau2[k]) st->done[k] = 1;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int b = threadIdx.x;
+    for (; b + 3 * 1024 < npart; b += 4 * 1024) {
+      a0 += partials[(int64_t)b * nr + k];
+      a1 += partials[(int64_t)(b + 1024) * nr + k];
+      a2 += partials[(int64_t)(b + 2048) * nr + k];
+      a3 += partials[(int64_t)(b + 3072) * nr + k];
     }
-    if (threadIdx.x == 0) all &= st->done[k];
+    for (; b < npart; b += 1024) a0 += partials[(int64_t)b * nr + k];
+    const double v = wave_sum((a0 + a1) + (a2 + a3), 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double pq = 0;
+      for (int i = 0; i < 16; ++i) pq += sh[i];
+      pcg_set_alpha(st, k, pq);
+    }
+    __syncthreads();
   }
-  if (threadIdx.x == 0) st->all_done = all;
 }
-void launch_pcg_check(int nr, PcgState* st, const double* partials, int npart, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(1024), 0, s, nr, st, partials, npart);
-  check_launch("k_pcg_check");
+void launch_pcg_alpha(int nr, PcgState* st, const double* partials, int npart, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1024), 0, s, nr, st, partials, npart);
+  check_launch("k_pcg_alpha");
 }
 
-// z = x0 + dpend (float64); partials of <r,z> and <q,z>
+// x += alpha p; r -= alpha q; ||r||^2 partials; V-cycle entry b0 = (T) r, d0 = dinv0 b0 / theta0
 template <typename T, int NR>
-__global__ __launch_bounds__(256) void k_pcg_z(int n, PcgState* st, const T* __restrict__ x0, const T* __restrict__ dp,
-                                               double* z, const double* __restrict__ r, const double* __restrict__ q,
-                                               double* partials, int nlog) {
+__global__ __launch_bounds__(256) void k_pcg_xr(int n, const PcgState* __restrict__ st, double* x, double* r,
+                                                const double* __restrict__ p, const double* __restrict__ q,
+                                                double* partials, T* b0, const T* __restrict__ dinv0, T* d0,
+                                                T inv_theta0) {
   __shared__ double sh[4 * NR];
   if (st->all_done) return;
-  const int lb = xcd_block(nlog);
-  if (lb < 0) return;
-  const int64_t tot = (int64_t)n * NR;
-  const int64_t base = (int64_t)lb * 256 * NR;
-  double a1 = 0, a2 = 0;
+  const int k = threadIdx.x % NR;
+  const double al = st->alpha[k];
+  const int64_t tn = (int64_t)n * NR;
+  double acc = 0;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * NR; base < tn; base += (int64_t)gridDim.x * 256 * NR)
 #pragma unroll
-  for (int m = 0; m < NR; ++m) {
-    const int64_t o = base + threadIdx.x + 256 * m;
-    if (o < tot) {
-      T v = x0[o];
-      if (dp) v += dp[o];
-      const double zv = (double)v;
-      z[o] = zv;
-      a1 += r[o] * zv;
-      if (q) a2 += q[o] * zv;
+    for (int m = 0; m < NR; ++m) {
+      const int64_t o = base + threadIdx.x + 256 * m;
+      if (o < tn) {
+        x[o] += al * p[o];
+        const double rv = r[o] - al * q[o];
+        r[o] = rv;
+        acc += rv * rv;
+        if (b0) {
+          const T bv = (T)rv;
+          b0[o] = bv;
+          if (d0) d0[o] = dinv0[o / NR] * bv * inv_theta0;
+        } else if (d0) {
+          d0[o] = dinv0[o / NR] * (T)rv * inv_theta0;
+        }
+      }
     }
+  column_partials<NR>(acc, sh, partials + (int64_t)blockIdx.x * NR);
+}
+// the stop test of every open column (iteration count, squared residual and its history, done flag), all_done
+template <int NR>
+__global__ __launch_bounds__(256) void k_pcg_check(PcgState* st, const double* __restrict__ partials, int nb) {
+  __shared__ double sh[4 * NR];
+  __shared__ double tot[NR];
+  if (st->all_done) return;
+  column_totals<NR>(partials, nb, NR, sh, tot);
+  if (threadIdx.x == 0) {
+    int all = 1;
+    for (int c = 0; c < NR; ++c) {
+      if (!st->done[c]) {
+        const double rr = tot[c];
+        st->rr_prev[c] = st->rr[c];
+        st->rr[c] = rr;
+        const int j = st->iters[c] + 1;
+        st->iters[c] = j;
+        if (st->rhist && j <= st->hist_rows) st->rhist[(int64_t)j * kMaxNR + c] = rr;
+        if (rr <= st->tau2[c]) st->done[c] = 1;
+      }
+      all &= st->done[c];
+    }
+    st->all_done = all;
   }
-  double* out = partials + (int64_t)lb * 2 * NR;
+}
+template <typename T>
+void launch_pcg_xr(int n, int nr, PcgState* st, double* x, double* r, const double* p, const double* q,
+                   double* partials, T* b0, const T* dinv0, T* d0, double inv_theta0, hipStream_t s) {
+  const int g = pcg_grid(n);
+#define R3_XR(NRV)                                                                                              \
+  hipLaunchKernelGGL((k_pcg_xr<T, NRV>), dim3(g), dim3(256), 0, s, n, st, x, r, p, q, partials, b0, dinv0, d0, \
+                     (T)inv_theta0);                                                                           \
+  hipLaunchKernelGGL((k_pcg_check<NRV>), dim3(1), dim3(256), 0, s, st, partials, g)
+  R3_NR_SWITCH(nr, R3_XR)
+#undef R3_XR
+  check_launch("k_pcg_xr / k_pcg_check");
+}
+template void launch_pcg_xr<float>(int, int, PcgState*, double*, double*, const double*, const double*, double*,
+                                   float*, const float*, float*, double, hipStream_t);
+template void launch_pcg_xr<double>(int, int, PcgState*, double*, double*, const double*, const double*, double*,
+                                    double*, const double*, double*, double, hipStream_t);
+
+// z = x0 + dpend (in float64); mode 1: p = z; modes 1, 2: partials of <r, z> and (q set) <q, z>
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_pcg_z(int n, const PcgState* __restrict__ st, int mode,
+                                               const T* __restrict__ x0, const T* __restrict__ dp, double* z,
+                                               const double* __restrict__ r, const double* __restrict__ q,
+                                               double* pvec, double* partials) {
+  __shared__ double sh[4 * NR];
+  if (mode != 0 && st->all_done) return;
+  const int64_t tn = (int64_t)n * NR;
+  double a1 = 0, a2 = 0;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * NR; base < tn; base += (int64_t)gridDim.x * 256 * NR)
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      const int64_t o = base + threadIdx.x + 256 * m;
+      if (o < tn) {
+        T v = x0[o];
+        if (dp) v += dp[o];
+        const double zv = (double)v;
+        z[o] = zv;
+        if (mode == 1) pvec[o] = zv;
+        if (mode != 0) {
+          a1 += r[o] * zv;
+          if (q) a2 += q[o] * zv;
+        }
+      }
+    }
+  if (mode == 0) return;
+  double* out = partials + (int64_t)blockIdx.x * 2 * NR;
   column_partials<NR>(a1, sh, out);
   __syncthreads();
   column_partials<NR>(a2, sh, out + NR);
 }
-template <typename T>
-void launch_pcg_z(int n, int nr, PcgState* st, const T* x0, const T* dpend, double* z, const double* r,
-                  const double* q, double* partials, hipStream_t s) {
-  const int nlog = (n + 255) / 256;
-  dim3 g(xcd_grid(nlog));
-#define R3_Z(NRV) hipLaunchKernelGGL((k_pcg_z<T, NRV>), g, dim3(256), 0, s, n, st, x0, dpend, z, r, q, partials, nlog)
-  switch (nr) {
-    case 1: R3_Z(1); break;
-    case 2: R3_Z(2); break;
-    case 4: R3_Z(4); break;
-    case 8: R3_Z(8); break;
-    case 16: R3_Z(16); break;
-    default: throw std::runtime_error("unsupported nrhs block");
-  }
-#undef R3_Z
-  check_launch("k_pcg_z");
-}
-template void launch_pcg_z<float>(int, int, PcgState*, const float*, const float*, double*, const double*,
-                                  const double*, double*, hipStream_t);
-template void launch_pcg_z<double>(int, int, PcgState*, const double*, const double*, double*, const double*,
-                                   const double*, double*, hipStream_t);
-
-// beta: standard (gamma'/gamma) or flexible (-alpha <z,q> / gamma); partials hold [rz(0..nr-1), qz(0..nr-1)]
-__global__ __launch_bounds__(1024) void k_pcg_beta(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
-  __shared__ double sh[16];
+// mode 1: gamma = <r, z>; mode 2: beta (standard gamma'/gamma, or flexible -alpha <q, z> / gamma) and gamma
+template <int NR>
+__global__ __launch_bounds__(256) void k_pcg_beta(PcgState* st, int mode, const double* __restrict__ partials,
+                                                  int nb) {
+  __shared__ double sh[4 * NR];
+  __shared__ double rz[NR], qz[NR];
   if (st->all_done) return;
-  for (int k = 0; k < nr; ++k) {
-    const double rz = sum_partials(partials, npart, 2 * nr, k, sh);
-    const double qz = sum_partials(partials, npart, 2 * nr, nr + k, sh);
-    if (threadIdx.x == 0 && !st->done[k]) {
-      const double g = st->gamma[k];
-      st->beta[k] = st->flexible ? (-st->alpha[k] * qz) / g : rz / g;
-      st->gamma[k] = rz;
-      const int j = st->iters[k] - 1;  // the check of iteration j has counted it
-      if (st->hist && j >= 0 && j < st->hist_rows) st->hist[(int64_t)(2 * j + 1) * kMaxNR + k] = st->beta[k];
+  column_totals<NR>(partials, nb, 2 * NR, sh, rz);
+  column_totals<NR>(partials + NR, nb, 2 * NR, sh, qz);
+  if (threadIdx.x < NR) {
+    const int c = threadIdx.x;
+    if (mode == 1) {
+      st->gamma[c] = rz[c];
+    } else if (!st->done[c]) {
+      const double g = st->gamma[c];
+      st->beta[c] = st->flexible ? (-st->alpha[c] * qz[c]) / g : rz[c] / g;
+      st->gamma[c] = rz[c];
+      const int j = st->iters[c] - 1;  // the stop test of iteration j has counted it
+      if (st->hist && j >= 0 && j < st->hist_rows) st->hist[(int64_t)(2 * j + 1) * kMaxNR + c] = st->beta[c];
     }
   }
 }
-void launch_pcg_beta(int nr, PcgState* st, const double* partials, int npart, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1024), 0, s, nr, st, partials, npart);
-  check_launch("k_pcg_beta");
+template <typename T>
+void launch_pcg_z(int n, int nr, PcgState* st, int mode, const T* x0, const T* dpend, double* z, const double* r,
+                  const double* q, double* p, double* partials, hipStream_t s) {
+  const int g = pcg_grid(n);
+#define R3_Z(NRV)                                                                                                  \
+  hipLaunchKernelGGL((k_pcg_z<T, NRV>), dim3(g), dim3(256), 0, s, n, st, mode, x0, dpend, z, r, q, p, partials); \
+  if (mode != 0) hipLaunchKernelGGL((k_pcg_beta<NRV>), dim3(1), dim3(256), 0, s, st, mode, partials, g)
+  R3_NR_SWITCH(nr, R3_Z)
+#undef R3_Z
+  check_launch("k_pcg_z / k_pcg_beta");
 }
+template void launch_pcg_z<float>(int, int, PcgState*, int, const float*, const float*, double*, const double*,
+                                  const double*, double*, double*, hipStream_t);
+template void launch_pcg_z<double>(int, int, PcgState*, int, const double*, const double*, double*, const double*,
+                                   const double*, double*, double*, hipStream_t);
 
-__global__ void k_pcg_p(int n, int nr, PcgState* st, const double* __restrict__ z, double* p) {
+__global__ void k_pcg_p(int n, int nr, const PcgState* __restrict__ st, const double* __restrict__ z, double* p) {
   if (st->all_done) return;
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (int64_t)n * nr) return;
@@ -2977,100 +2976,110 @@ void launch_pcg_p(int n, int nr, PcgState* st, const double* z, double* p, hipSt
   check_launch("k_pcg_p");
 }
 
-// r = b - q with partial ||r||^2 per column
+// ||b - q||^2 partials per column; with r set, r = b - q as well
 template <int NR>
-__global__ __launch_bounds__(256) void k_residual(int n, const double* __restrict__ b, const double* __restrict__ q,
-                                                  double* r, double* partials) {
+__global__ __launch_bounds__(256) void k_pcg_residual(int n, const double* __restrict__ b, const double* __restrict__ q,
+                                                      double* r, double* partials) {
   __shared__ double sh[4 * NR];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  double acc[NR];
+  const int64_t tn = (int64_t)n * NR;
+  double acc = 0;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * NR; base < tn; base += (int64_t)gridDim.x * 256 * NR)
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    acc[k] = 0;
-    if (i < n) {
-      const int64_t o = (int64_t)i * NR + k;
-      const double v = b[o] - q[o];
-      r[o] = v;
-      acc[k] = v * v;
+    for (int m = 0; m < NR; ++m) {
+      const int64_t o = base + threadIdx.x + 256 * m;
+      if (o < tn) {
+        const double v = b[o] - q[o];
+        if (r) r[o] = v;
+        acc += v * v;
+      }
     }
-  }
-#pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    double v = wave_sum(acc[k], 64);
-    if ((threadIdx.x & 63) == 0) sh[(threadIdx.x >> 6) * NR + k] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < NR) {
-    const int k = threadIdx.x;
-    partials[(int64_t)blockIdx.x * NR + k] = (sh[k] + sh[NR + k]) + (sh[2 * NR + k] + sh[3 * NR + k]);
-  }
+  column_partials<NR>(acc, sh, partials + (int64_t)blockIdx.x * NR);
 }
-int launch_residual(int n, int nr, const double* b, const double* q, double* r, double* partials, hipStream_t s) {
-  const int g = (n + 255) / 256;
-#define R3_R(NRV) hipLaunchKernelGGL((k_residual<NRV>), dim3(g), dim3(256), 0, s, n, b, q, r, partials)
-  switch (nr) {
-    case 1: R3_R(1); break;
-    case 2: R3_R(2); break;
-    case 4: R3_R(4); break;
-    case 8: R3_R(8); break;
-    case 16: R3_R(16); break;
-    default: throw std::runtime_error("unsupported nrhs block");
-  }
-#undef R3_R
-  check_launch("k_residual");
-  return g;
-}
-
-__global__ __launch_bounds__(1024) void k_pcg_init(int nr, PcgState* st, const double* __restrict__ partials, int npart,
-                                                  double rtol, double atol, int nr_active, int flexible, double* hist,
-                                                  int hist_rows) {
-  __shared__ double sh[16];
-  int all = 1;
-  for (int k = 0; k < nr; ++k) {
-    const double rr = sum_partials(partials, npart, nr, k, sh);
-    if (threadIdx.x == 0) {
-      st->rr0[k] = rr;
-      st->rr[k] = rr;
-      st->tau2[k] = fmax(rtol * rtol * rr, atol * atol);  // ||r|| <= max(rtol ||r0||, atol)
-      st->iters[k] = 0;
-      st->alpha[k] = 0;
-      st->beta[k] = 0;
-      st->done[k] = (k >= nr_active) || (rr <= st->tau2[k]);
-      all &= st->done[k];
-    }
-  }
+// the initial state (fresh solve, or a restart from the true residual that keeps tau^2, ||r_0||^2 and the
+// iteration counts)
+template <int NR>
+__global__ __launch_bounds__(256) void k_pcg_init(PcgState* st, const double* __restrict__ partials, int nb,
+                                                  int restart, double rtol, double atol, int nr_active, int flexible,
+                                                  double* hist, double* rhist, int hist_rows) {
+  __shared__ double sh[4 * NR];
+  __shared__ double tot[NR];
+  column_totals<NR>(partials, nb, NR, sh, tot);
   if (threadIdx.x == 0) {
+    int all = 1;
+    for (int c = 0; c < NR; ++c) {
+      const double rr = tot[c];
+      if (!restart) {
+        st->rr0[c] = rr;
+        st->tau2[c] = fmax(rtol * rtol * rr, atol * atol);  // ||r|| <= max(rtol ||r0||, atol)
+        st->iters[c] = 0;
+        if (rhist && hist_rows >= 0) rhist[c] = rr;
+      }
+      st->rr[c] = rr;
+      st->rr_prev[c] = rr;
+      st->rr_true[c] = rr;
+      st->alpha[c] = 0;
+      st->beta[c] = 0;
+      st->done[c] = (c >= nr_active) || (rr <= st->tau2[c]);
+      all &= st->done[c];
+    }
     st->all_done = all;
-    st->nr = nr;
+    st->nr = NR;
     st->flexible = flexible;
+    st->restart = 0;
     st->hist = hist;
+    st->rhist = rhist;
     st->hist_rows = hist_rows;
   }
 }
-void launch_pcg_init(int nr, PcgState* st, const double* partials, int npart, double rtol, double atol, int flexible,
-                     double* hist, int hist_rows, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(1024), 0, s, nr, st, partials, npart, rtol, atol, nr, flexible, hist,
-                     hist_rows);
-  check_launch("k_pcg_init");
+void launch_pcg_residual_init(int n, int nr, const double* b, const double* q, double* r, double* partials,
+                              PcgState* st, int restart, double rtol, double atol, int nr_active, int flexible,
+                              double* hist, double* rhist, int hist_rows, hipStream_t s) {
+  const int g = pcg_grid(n);
+#define R3_RI(NRV)                                                                                               \
+  hipLaunchKernelGGL((k_pcg_residual<NRV>), dim3(g), dim3(256), 0, s, n, b, q, r, partials);                    \
+  hipLaunchKernelGGL((k_pcg_init<NRV>), dim3(1), dim3(256), 0, s, st, partials, g, restart, rtol, atol, nr_active, \
+                     flexible, hist, rhist, hist_rows)
+  R3_NR_SWITCH(nr, R3_RI)
+#undef R3_RI
+  check_launch("k_pcg_residual / k_pcg_init");
 }
 
-__global__ __launch_bounds__(1024) void k_pcg_gamma(int nr, PcgState* st, const double* __restrict__ partials, int npart) {
-  __shared__ double sh[16];
-  for (int k = 0; k < nr; ++k) {
-    const double rz = sum_partials(partials, npart, 2 * nr, k, sh);
-    if (threadIdx.x == 0) st->gamma[k] = rz;
+// the true residual recorded, and a restart flagged when a column the recursive residual declared converged fails
+// the stop rule with it
+template <int NR>
+__global__ __launch_bounds__(256) void k_pcg_true_check(PcgState* st, const double* __restrict__ partials, int nb) {
+  __shared__ double sh[4 * NR];
+  __shared__ double tot[NR];
+  column_totals<NR>(partials, nb, NR, sh, tot);
+  if (threadIdx.x == 0) {
+    int rs = 0;
+    for (int c = 0; c < NR; ++c) {
+      st->rr_true[c] = tot[c];
+      if (st->done[c] && tot[c] > st->tau2[c]) rs = 1;
+    }
+    st->restart = rs;
   }
 }
-__global__ void k_copy(int64_t count, const double* __restrict__ a, double* b) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < count) b[i] = a[i];
+void launch_pcg_true_residual(int n, int nr, const double* b, const double* q, double* partials, PcgState* st,
+                              hipStream_t s) {
+  const int g = pcg_grid(n);
+#define R3_TR(NRV)                                                                                           \
+  hipLaunchKernelGGL((k_pcg_residual<NRV>), dim3(g), dim3(256), 0, s, n, b, q, nullptr, partials);          \
+  hipLaunchKernelGGL((k_pcg_true_check<NRV>), dim3(1), dim3(256), 0, s, st, partials, g)
+  R3_NR_SWITCH(nr, R3_TR)
+#undef R3_TR
+  check_launch("k_pcg_residual / k_pcg_true_check");
 }
-void launch_pcg_init_gamma(int n, int nr, PcgState* st, const double* partials, int npart, const double* z,
-                           double* p, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_gamma, dim3(1), dim3(1024), 0, s, nr, st, partials, npart);
-  const int64_t tot = (int64_t)n * nr;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, tot, z, p);
-  check_launch("k_pcg_gamma");
+
+// the state, word by word, into host-mapped pinned memory
+__global__ void k_pcg_state_out(const uint64_t* __restrict__ src, uint64_t* dst, int words) {
+  for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+}
+void launch_pcg_state_out(const PcgState* st, PcgState* host_mapped, hipStream_t s) {
+  static_assert(sizeof(PcgState) % 8 == 0, "PcgState is copied in 8-byte words");
+  hipLaunchKernelGGL(k_pcg_state_out, dim3(1), dim3(256), 0, s, reinterpret_cast<const uint64_t*>(st),
+                     reinterpret_cast<uint64_t*>(host_mapped), (int)(sizeof(PcgState) / 8));
+  check_launch("k_pcg_state_out");
 }
 
 template <typename T>

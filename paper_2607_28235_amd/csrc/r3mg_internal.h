@@ -68,6 +68,7 @@ struct DBuf {
     hipError_t e = hipMalloc(&p, count * sizeof(T));
     if (e != hipSuccess) {
       p = nullptr;
+      (void)hipGetLastError();  // the failed allocation must not be reported by a later launch check
       throw Error{R3MG_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
     }
     n = count;
@@ -245,7 +246,7 @@ struct Device {
   DBuf<double> px, pr, pp, pq, pz, pb;
   DBuf<double> partials;  // reduction partials
   DBuf<char> state;       // PcgState
-  DBuf<double> hist;      // CG coefficients per iteration (PcgState::hist)
+  DBuf<double> hist;      // CG coefficients and squared residual norms per iteration (PcgState::hist, rhist)
   int hist_rows = 0;
   DBuf<int> flag;         // set-up error flag
   int64_t pcg_cap = 0;
@@ -253,10 +254,18 @@ struct Device {
   std::map<int, hipGraphExec_t> graphs;
   std::map<int, hipGraph_t> graph_defs;
   hipStream_t cap_stream = nullptr;
-  void* pinned = nullptr;  // host pinned buffer: PcgState copy + two per-iteration PcgState snapshots
-  void* pinned_part = nullptr;  // host pinned buffer: reduction partials read back after a solve
-  size_t pinned_part_bytes = 0;
+  void* pinned = nullptr;      // host pinned buffer: the PcgState read back at the end of a chunk of iterations
+  void* pinned_dev = nullptr;  // its device address (written by a kernel, no copy engine involved)
   hipEvent_t ev[2] = {nullptr, nullptr};
+  // iterations of the last converged solve per (nr, precision) key: the rtol and atol it ran to, the iterations
+  // of its slowest column and their mean squared residual reduction per iteration (the first chunk of the next
+  // solve is enqueued from it)
+  struct SolveRecord {
+    double rtol = 0, atol = 0, q = 0;
+    int iters = 0;
+  };
+  std::map<int, SolveRecord> last_solve;
+  int last_restarts = 0;  // residual-replacement restarts of the last solve (float32 V-cycle)
   // autotuned SpMM lanes per (level, nrhs)
   std::map<std::pair<int, int>, int> tuned;
   MatFreeDev mf;
@@ -285,7 +294,11 @@ r3mg_status pcg_solve(HandleImpl& h, const double* b, double* x, int nrhs, doubl
                       int* iters, double* relres);
 r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double* const* x, double rtol, int maxit,
                       hipStream_t s, int* iters, double* relres);
-void time_smoother_kernel(HandleImpl& h, int level, int reps, hipStream_t s, double* ms, double* bytes);
+// residual norms ||r_j||_2, j = 0..iters, of column col of the last block solved on the handle (rr may be null);
+// returns iters + 1 (0 before any solve)
+int residual_history(HandleImpl& h, int col, double* rr, int cap);
+void time_smoother_kernel(HandleImpl& h, int level, int reps, int64_t flush_bytes, hipStream_t s, double* ms,
+                          double* bytes);
 // matrix-free fine operator: upload, check against the CSR operator, switch level 0 to it; detach returns to CSR
 void attach_matrix_free(HandleImpl& h, MatFreeHost&& m, hipStream_t s);
 void detach_matrix_free(HandleImpl& h);

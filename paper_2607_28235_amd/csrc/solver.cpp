@@ -147,7 +147,6 @@ Device::~Device() {
     if (e) (void)hipEventDestroy(e);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (pinned) (void)hipHostFree(pinned);
-  if (pinned_part) (void)hipHostFree(pinned_part);
 }
 
 struct Ctx {
@@ -345,17 +344,21 @@ static void ensure_pcg_vectors(Ctx& c, int nr) {
     const int64_t nlog_vec = (n + 255) / 256;
     size_t nrb_max = 0;
     for (int sh = 0; sh < kStreamShapes; ++sh) nrb_max = std::max(nrb_max, (size_t)dv.lv[0].fb[sh].nrb);
-    // (nr > 1: room for the per-column dot of PCG in its fixed partition, at most 1024 blocks per column)
+    // (the PCG reductions: two partials per column and block, at most kPcgBlocks blocks)
     dv.partials.alloc(std::max<size_t>({(size_t)4096, (size_t)(nlog_spmv * nr), (size_t)(nlog_vec * 2 * nr), nrb_max,
-                                        nr > 1 ? (size_t)1024 * nr : (size_t)0}));
+                                        (size_t)kPcgBlocks * 2 * nr}));
     drop_graphs(dv);
   }
   if (!dv.state.p) {
     dv.state.alloc(sizeof(PcgState));
     R3MG_HIP_CHECK(hipMemset(dv.state.p, 0, sizeof(PcgState)));
   }
-  // pinned host memory: one PcgState for reads of the state, then the two per-iteration snapshot slots
-  if (!dv.pinned) R3MG_HIP_CHECK(hipHostMalloc(&dv.pinned, 3 * sizeof(PcgState) + 64, hipHostMallocDefault));
+  // pinned host memory for the state read back at the end of a chunk of iterations, written by a kernel through
+  // its device address
+  if (!dv.pinned) {
+    R3MG_HIP_CHECK(hipHostMalloc(&dv.pinned, sizeof(PcgState) + 64, hipHostMallocDefault));
+    R3MG_HIP_CHECK(hipHostGetDevicePointer(&dv.pinned_dev, dv.pinned, 0));
+  }
 }
 
 // Multi-RHS SpMM tile autotuner: the lanes-per-row tile of every level kernel (and of PCG's float64 SpMV) is
@@ -441,11 +444,17 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
     DevLevel& D0 = dv.lv[0];
     float best = 1e30f;
     int bestCode = 1;
+    // every candidate ends with alpha in the state: time them on a cleared state (not converged, gamma = 0)
+    R3MG_HIP_CHECK(hipMemsetAsync(dv.state.p, 0, sizeof(PcgState), s));
+    PcgState* st0 = reinterpret_cast<PcgState*>(dv.state.p);
     if (forced <= 0)
       for (int G = 1; G <= 8; G <<= 1) {
         op.lanes = G;
         need_partials(dv, (int64_t)((c.an.n + 256 / G - 1) / (256 / G)) * nr);
-        const float ms = time_launches(s, 5, [&] { launch_spmv_dot(op, nr, dv.pp.p, dv.pq.p, dv.partials.p, nullptr, s); });
+        const float ms = time_launches(s, 5, [&] {
+          const int np = launch_spmv_dot(op, nr, dv.pp.p, dv.pq.p, dv.partials.p, nullptr, s);
+          launch_pcg_alpha(nr, st0, dv.partials.p, np, s);
+        });
         if (ms < best) {
           best = ms;
           bestCode = G;
@@ -453,14 +462,14 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
       }
     op.ptr = D0.rowptr.p;
     op.idx = D0.col.p;
-    need_partials(dv, (int64_t)1024 * nr);
+    need_partials(dv, (int64_t)kPcgBlocks * 2 * nr);
     for (int g = 0; g < 2; ++g) {
       if (forced != -1 && forced != 1 + g) continue;
       bool ok = true;
       const float ms = time_launches(s, 5, [&] {
         ok = launch_level_local_mr<double>(g, D0.fb[kLocalFirst + g], op, nr, dv.pp.p, nullptr, dv.pq.p, nullptr,
                                            nullptr, 0.0, 0.0, F_PLAIN, nullptr, s);
-        if (ok) launch_pcg_dot_mr((int)c.an.n, nr, dv.pp.p, dv.pq.p, dv.partials.p, nullptr, s);
+        if (ok) launch_pcg_dot_alpha((int)c.an.n, nr, dv.pp.p, dv.pq.p, dv.partials.p, st0, s);
       });
       if (ok && ms < best) {
         best = ms;
@@ -473,7 +482,7 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
         const float ms = time_launches(s, 5, [&] {
           ok = launch_level_split<double>(op, nr, G, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN,
                                           nullptr, s);
-          if (ok) launch_pcg_dot_mr((int)c.an.n, nr, dv.pp.p, dv.pq.p, dv.partials.p, nullptr, s);
+          if (ok) launch_pcg_dot_alpha((int)c.an.n, nr, dv.pp.p, dv.pq.p, dv.partials.p, st0, s);
         });
         if (ok && ms < best) {
           best = ms;
@@ -1021,10 +1030,8 @@ static void vcycle_api_t(HandleImpl& h, const double* r, double* z, int nrhs, hi
     } else {
       // x0 + pend -> pz (float64 interleaved) -> scatter the real columns
       ensure_pcg_vectors(c, NR);
-      PcgState* st = reinterpret_cast<PcgState*>(dv.state.p);
-      need_partials(dv, (int64_t)((an.n + 255) / 256) * 2 * NR);
-      R3MG_HIP_CHECK(hipMemsetAsync(dv.state.p, 0, sizeof(PcgState), s));
-      launch_pcg_z<T>((int)an.n, NR, st, vbuf<T>(D0.x), pend, dv.pz.p, dv.pz.p, nullptr, dv.partials.p, s);
+      launch_pcg_z<T>((int)an.n, NR, nullptr, 0, vbuf<T>(D0.x), pend, dv.pz.p, nullptr, nullptr, nullptr, dv.partials.p,
+                      s);
       launch_scatter_cols((int)an.n, NR, nb, dv.perm.p, dv.pz.p, z + (int64_t)c0 * an.n, an.n, s);
     }
   }
@@ -1054,7 +1061,7 @@ void level_apply(HandleImpl& h, int level, const double* x, double* y, hipStream
 }
 
 // One PCG iteration (all launches skip once every column has converged).  part 0: the whole iteration; part 1:
-// q = A p, alpha, the x and r updates and the convergence check; part 2: the V-cycle, z, beta and the new p.
+// q = A p, alpha, the x and r updates and the stop test; part 2: the V-cycle, z, beta and the new p.
 template <typename T>
 static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s, int part = 0) {
   Analysis& an = c.an;
@@ -1065,27 +1072,20 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s, int part
   DevLevel& D0 = dv.lv[0];
   LevelOp<double> op64 = level_op<double>(c, 0);
   const int n = (int)an.n;
-  need_partials(dv, (int64_t)((n + 255) / 256) * 2 * NR);
+  need_partials(dv, (int64_t)kPcgBlocks * 2 * NR);
   if (part != 2) {
-    int np;
-    if (NR == 1 && D0.mf) {
-      // q = A p with the matrix-free operator, then <p, q> in the fixed partition
-      apply_level<double>(c, 0, 1, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
-      np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+    // q = A p, then alpha from <p, q> in the fixed partition of the dot kernel (the iterates do not depend on
+    // the kernel that formed q), except after the lanes kernel, whose fused dot has its own partition
+    if (D0.mf) {
+      apply_level<double>(c, 0, NR, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
+      launch_pcg_dot_alpha(n, NR, dv.pp.p, dv.pq.p, dv.partials.p, st, s);
     } else if (NR == 1 && D0.fb[D0.shape].nrb > 0) {
-      // q = A p with the fine row-block kernel, then <p, q> in a fixed partition: the iterates do not depend on
-      // the kernel shape chosen by timing
       launch_level_stream<double>(D0.shape64, D0.fb[D0.shape64], op64, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0,
                                   F_PLAIN | D0.keep64, skip, nullptr, s);
-      np = launch_pcg_dot(n, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
-    } else if (D0.mf) {
-      // q = A p with the matrix-free operator for NR columns, then the per-column <p, q> in a fixed partition
-      apply_level<double>(c, 0, NR, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
-      need_partials(dv, (int64_t)1024 * NR);
-      np = launch_pcg_dot_mr(n, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+      launch_pcg_dot_alpha(n, 1, dv.pp.p, dv.pq.p, dv.partials.p, st, s);
     } else {
       auto it = dv.tuned.find({-1, NR * 2});
-      if (it != dv.tuned.end() && (it->second < 0 || it->second >= kCodeSplit)) {  // then the per-column dot
+      if (it != dv.tuned.end() && (it->second < 0 || it->second >= kCodeSplit)) {
         op64.ptr = D0.rowptr.p;
         op64.idx = D0.col.p;
         bool ok;
@@ -1096,45 +1096,47 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s, int part
           ok = launch_level_split<double>(op64, NR, it->second - kCodeSplit, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr,
                                           0.0, 0.0, F_PLAIN, skip, s);
         if (!ok) throw std::runtime_error("multi-RHS fine-level kernel: unsupported shape");
-        need_partials(dv, (int64_t)1024 * NR);
-        np = launch_pcg_dot_mr(n, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+        launch_pcg_dot_alpha(n, NR, dv.pp.p, dv.pq.p, dv.partials.p, st, s);
       } else {
         if (it != dv.tuned.end()) op64.lanes = it->second;
         need_partials(dv, (int64_t)((n + 256 / op64.lanes - 1) / (256 / op64.lanes)) * NR);
-        np = launch_spmv_dot(op64, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+        const int np = launch_spmv_dot(op64, NR, dv.pp.p, dv.pq.p, dv.partials.p, skip, s);
+        launch_pcg_alpha(NR, st, dv.partials.p, np, s);
       }
     }
     const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
     const T* dinv0;
     if constexpr (sizeof(T) == 4) dinv0 = D0.dinv32.p; else dinv0 = D0.dinv64.p;
     T* b0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : nullptr;
-    launch_pcg_xr<T>(n, NR, st, dv.partials.p, np, dv.px.p, dv.pr.p, dv.pp.p, dv.pq.p, dv.partials.p, b0, dinv0,
+    launch_pcg_xr<T>(n, NR, st, dv.px.p, dv.pr.p, dv.pp.p, dv.pq.p, dv.partials.p, b0, dinv0,
                      smooth0 ? vbuf<T>(D0.dA) : nullptr, 2.0 / (D0.lam_hi + D0.lam_lo), s);
-    launch_pcg_check(NR, st, dv.partials.p, (n + 255) / 256, s);
   }
   if (part == 1) return;
-  const int nv = (n + 255) / 256;
+  // The V-cycle does not read the skip flag: it only writes level work vectors and z, so running it after every
+  // column has converged changes nothing (converged columns keep alpha = 0, beta and p), and a flag read at the
+  // start of each of its ~45 kernels would put one more memory latency on each of them.
   const T* bl0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : reinterpret_cast<const T*>(dv.pr.p);
   T* pend = nullptr;
-  if (L > 0) {
-    pend = vcycle_rec<T>(c, 0, NR, bl0, skip, s);
-  }
+  if (L > 0) pend = vcycle_rec<T>(c, 0, NR, bl0, nullptr, s);
   const T* x0 = (L > 0) ? vbuf<T>(D0.x) : bl0;
-  launch_pcg_z<T>(n, NR, st, x0, pend, dv.pz.p, dv.pr.p, flexible ? dv.pq.p : nullptr, dv.partials.p, s);
-  launch_pcg_beta(NR, st, dv.partials.p, nv, s);
+  launch_pcg_z<T>(n, NR, st, 2, x0, pend, dv.pz.p, dv.pr.p, flexible ? dv.pq.p : nullptr, nullptr, dv.partials.p, s);
   launch_pcg_p(n, NR, st, dv.pz.p, dv.pp.p, s);
 }
 
-// room for the CG coefficients of maxit iterations (a reallocation invalidates the captured graphs)
+// room for the CG coefficients and residual norms of maxit iterations (a reallocation invalidates the captured
+// graphs)
 static void ensure_hist(Device& dv, int maxit) {
-  if (dv.hist_rows >= maxit) return;
-  dv.hist.alloc((size_t)2 * kMaxNR * maxit);
+  if (dv.hist_rows >= maxit && dv.hist.p) return;
+  dv.hist.alloc((size_t)(3 * (size_t)maxit + 1) * kMaxNR);
   dv.hist_rows = maxit;
   drop_graphs(dv);
 }
+static double* rhist_of(Device& dv) { return dv.hist.p + (size_t)2 * kMaxNR * dv.hist_rows; }
 
+// r = b - A x; z = B r; p = z; gamma = <r, z>.  restart: from the true residual of the current x, keeping the
+// stop thresholds and iteration counts (residual replacement).
 template <typename T>
-static void pcg_start(Ctx& c, int NR, double rtol, double atol, bool flexible, hipStream_t s) {
+static void pcg_start(Ctx& c, int NR, int nb, double rtol, double atol, bool flexible, bool restart, hipStream_t s) {
   Analysis& an = c.an;
   Device& dv = c.dv;
   const int L = an.nlevels() - 1;
@@ -1142,13 +1144,10 @@ static void pcg_start(Ctx& c, int NR, double rtol, double atol, bool flexible, h
   PcgState* st = reinterpret_cast<PcgState*>(dv.state.p);
   const int* skip = reinterpret_cast<const int*>(dv.state.p);
   DevLevel& D0 = dv.lv[0];
-  LevelOp<double> op64 = level_op<double>(c, 0);
-  need_partials(dv, (int64_t)((n + 255) / 256) * 2 * NR);
-  // r = b - A x0
+  need_partials(dv, (int64_t)kPcgBlocks * 2 * NR);
   apply_level<double>(c, 0, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
-  int np = launch_residual(n, NR, dv.pb.p, dv.pq.p, dv.pr.p, dv.partials.p, s);
-  launch_pcg_init(NR, st, dv.partials.p, np, rtol, atol, flexible ? 1 : 0, dv.hist.p, dv.hist_rows, s);
-  // z = B r; p = z; gamma = <r, z>
+  launch_pcg_residual_init(n, NR, dv.pb.p, dv.pq.p, dv.pr.p, dv.partials.p, st, restart ? 1 : 0, rtol, atol, nb,
+                           flexible ? 1 : 0, dv.hist.p, rhist_of(dv), dv.hist_rows, s);
   const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
   const T* dinv0;
   if constexpr (sizeof(T) == 4) dinv0 = D0.dinv32.p; else dinv0 = D0.dinv64.p;
@@ -1157,26 +1156,9 @@ static void pcg_start(Ctx& c, int NR, double rtol, double atol, bool flexible, h
                     skip, s);
   const T* bl0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : reinterpret_cast<const T*>(dv.pr.p);
   T* pend = nullptr;
-  if (L > 0) pend = vcycle_rec<T>(c, 0, NR, bl0, skip, s);
+  if (L > 0) pend = vcycle_rec<T>(c, 0, NR, bl0, nullptr, s);
   const T* x0 = (L > 0) ? vbuf<T>(D0.x) : bl0;
-  launch_pcg_z<T>(n, NR, st, x0, pend, dv.pz.p, dv.pr.p, nullptr, dv.partials.p, s);
-  launch_pcg_init_gamma(n, NR, st, dv.partials.p, (n + 255) / 256, dv.pz.p, dv.pp.p, s);
-}
-
-static PcgState read_state(Device& dv, hipStream_t s) {
-  R3MG_HIP_CHECK(hipMemcpyAsync(dv.pinned, dv.state.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-  R3MG_HIP_CHECK(hipStreamSynchronize(s));
-  PcgState st;
-  std::memcpy(&st, dv.pinned, sizeof(PcgState));
-  return st;
-}
-
-static int read_all_done(Device& dv, hipStream_t s) {
-  R3MG_HIP_CHECK(hipMemcpyAsync(dv.pinned, dv.state.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  R3MG_HIP_CHECK(hipStreamSynchronize(s));
-  int v;
-  std::memcpy(&v, dv.pinned, sizeof(int));
-  return v;
+  launch_pcg_z<T>(n, NR, st, 1, x0, pend, dv.pz.p, dv.pr.p, nullptr, dv.pp.p, dv.partials.p, s);
 }
 
 template <typename T>
@@ -1202,6 +1184,61 @@ static hipGraphExec_t iteration_graph(Ctx& c, int NR, bool flexible, int part) {
   return ex;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Host side of the solve.  Convergence is decided on the device: every kernel of an iteration returns at once
+// when all columns have converged, so iterations may be enqueued ahead without reading anything back.  The host
+// enqueues the whole predicted solve as one chunk (captured iteration graphs back to back) and reads the state
+// once at its end; only when the prediction fell short does it enqueue a further chunk.  The iteration predicted
+// to converge is enqueued as its first half (part 1), whose stop test needs no V-cycle; the second half follows
+// only if that test failed.  The chunk ends on the device with the float32 V-cycle's true-residual check
+// (residual replacement), the write-back of the solution and the state copied into pinned host memory, so a
+// solve that converges as predicted synchronises once.
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+int record_key(int NR, bool fp32) { return NR * 2 + (fp32 ? 1 : 0); }
+
+// iterations to enqueue before the first read: those of the last converged solve with the same key and stop
+// rule, else the count its mean residual reduction needs for rtol, else 3
+int predict_first(const Device& dv, int key, double rtol, double atol, int maxit) {
+  int k = 3;
+  auto it = dv.last_solve.find(key);
+  if (it != dv.last_solve.end()) {
+    const Device::SolveRecord& r = it->second;
+    if (r.rtol == rtol && r.atol == atol)
+      k = r.iters;
+    else if (r.q > 0.0 && r.q < 1.0 && rtol > 0.0)
+      k = (int)std::ceil(2.0 * std::log(rtol) / std::log(r.q));
+  }
+  return std::max(0, std::min(maxit, std::max(1, k)));
+}
+
+// further iterations the open columns of a state need, assuming each repeats its last residual reduction
+int predict_more(const PcgState& st, int nb) {
+  int m = 1;
+  for (int j = 0; j < nb; ++j) {
+    if (st.done[j]) continue;
+    const double rr = st.rr[j], rp = st.rr_prev[j], tau = st.tau2[j];
+    if (!(rp > 0.0) || !(rr > 0.0) || !(rr < rp) || !(tau > 0.0)) continue;
+    const double need = std::ceil(std::log(tau / rr) / std::log(rr / rp));
+    if (need > m) m = (int)std::min(need, 1000.0);
+  }
+  return m;
+}
+
+void record_solve(Device& dv, int key, double rtol, double atol, const PcgState& st, int nb) {
+  int kmax = 0;
+  double q = 0.0;
+  for (int j = 0; j < nb; ++j)
+    if (st.iters[j] >= kmax && st.iters[j] > 0) {
+      kmax = st.iters[j];
+      q = (st.rr0[j] > 0.0 && st.rr[j] > 0.0) ? std::pow(st.rr[j] / st.rr0[j], 1.0 / st.iters[j]) : 0.0;
+    }
+  if (kmax > 0) dv.last_solve[key] = Device::SolveRecord{rtol, atol, q, kmax};
+}
+
+}  // namespace
+
 template <typename T>
 static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, int nb, double rtol, double atol,
                              int maxit, hipStream_t s, int* iters, double* relres, double* cond) {
@@ -1212,143 +1249,82 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
   while (NR < nb) NR <<= 1;
   ensure_level_vectors(c, NR);
   ensure_pcg_vectors(c, NR);
-  ensure_hist(dv, maxit);
+  ensure_hist(dv, std::max(maxit, 1));
   autotune_spmm<T>(c, NR, s);
   const int n = (int)an.n;
   const bool flexible = sizeof(T) == 4;
-  launch_gather_cols(n, NR, nb, dv.perm.p, b + (int64_t)c0 * n, n, dv.pb.p, s);
-  launch_gather_cols(n, NR, nb, dv.perm.p, x + (int64_t)c0 * n, n, dv.px.p, s);
-  pcg_start<T>(c, NR, rtol, atol, flexible, s);
-  hipGraphExec_t ex[3] = {nullptr, nullptr, nullptr};
-  if (an.opt.use_graph)
-    for (int part = 0; part < 3; ++part) ex[part] = iteration_graph<T>(c, NR, flexible, part);
-  // The host keeps one iteration ahead of the device: iteration k+1 is enqueued before the state after iteration
-  // k is read back (its kernels skip themselves once every column has converged), so the device does not idle
-  // while the host decides.  When the residual history predicts that the iteration in flight converges, the
-  // host waits for it instead of enqueuing one more (a skipped iteration still costs a full launch sequence).
-  // An iteration that is itself predicted to converge is enqueued without its V-cycle half (part 1 only); that
-  // half follows once its check has been read and failed, so the converging iteration does not queue ~60
-  // kernels that would only skip themselves.
+  PcgState* dst = reinterpret_cast<PcgState*>(dv.state.p);
   if (!dv.ev[0]) {
     R3MG_HIP_CHECK(hipEventCreateWithFlags(&dv.ev[0], hipEventDisableTiming));
     R3MG_HIP_CHECK(hipEventCreateWithFlags(&dv.ev[1], hipEventDisableTiming));
   }
-  PcgState* snap = reinterpret_cast<PcgState*>(static_cast<char*>(dv.pinned) + sizeof(PcgState));  // 2 slots
-  int k = 0;  // iterations enqueued; snapshot j (state after iteration j) lands in slot j & 1
-  auto snapshot = [&]() {
-    R3MG_HIP_CHECK(hipMemcpyAsync(&snap[k & 1], dv.state.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-    R3MG_HIP_CHECK(hipEventRecord(dv.ev[k & 1], s));
-  };
+  launch_gather_cols(n, NR, nb, dv.perm.p, b + (int64_t)c0 * n, n, dv.pb.p, s);
+  launch_gather_cols(n, NR, nb, dv.perm.p, x + (int64_t)c0 * n, n, dv.px.p, s);
+  pcg_start<T>(c, NR, nb, rtol, atol, flexible, false, s);
+  hipGraphExec_t ex[3] = {nullptr, nullptr, nullptr};
+  if (an.opt.use_graph)
+    for (int part = 0; part < 3; ++part) ex[part] = iteration_graph<T>(c, NR, flexible, part);
   auto launch_part = [&](int part) {
     if (ex[part])
       R3MG_HIP_CHECK(hipGraphLaunch(ex[part], s));
     else
       pcg_iteration<T>(c, NR, flexible, s, part);
   };
-  bool split_pending = false;  // the last iteration enqueued stopped after its convergence check
-  auto launch_one = [&](bool split) {
-    launch_part(split ? 1 : 0);
-    ++k;
-    snapshot();
-    split_pending = split;
+  int k = 0;           // iterations enqueued
+  bool split = false;  // the last one enqueued stopped after its stop test
+  auto enqueue_to = [&](int target) {
+    if (split && k < target) {
+      launch_part(2);
+      split = false;
+    }
+    while (k < target) {
+      const bool last = k + 1 == target;
+      launch_part(last ? 1 : 0);
+      ++k;
+      split = last;
+    }
   };
   PcgState st;
-  // whether every open column is predicted to pass the stop test `steps` iterations after the last known one
-  // (the last residual reduction repeated)
-  auto converges_in = [&](const std::vector<double>& rr1, const std::vector<double>& rr2, int steps) {
-    if (rr2.empty()) return false;
-    for (int j = 0; j < nb; ++j) {
-      if (st.done[j]) continue;
-      if (!(rr2[j] > 0.0)) return false;
-      const double q = rr1[j] / rr2[j];
-      double r = rr1[j];
-      for (int t = 0; t < steps; ++t) r *= q;
-      if (!(r <= st.tau2[j])) return false;
+  auto finish_chunk = [&]() {
+    if (flexible) {
+      // true residual of x (into z, which the next iteration's second half rewrites before reading it)
+      apply_level<double>(c, 0, NR, dv.px.p, nullptr, dv.pz.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+      launch_pcg_true_residual(n, NR, dv.pb.p, dv.pz.p, dv.partials.p, dst, s);
     }
-    return true;
-  };
-  auto run_iterations = [&]() {
-    std::vector<double> rr1, rr2;  // recursive residuals after the last two known iterations
-    int kn = k - 1;                // last snapshot read by the host
-    split_pending = false;
-    snapshot();                    // the state before the first iteration of this run
-    while (true) {
-      // one iteration in flight (snapshot kn + 1 pending): enqueue another unless the one in flight is predicted
-      // to converge or stopped after its check
-      if (k == kn + 1 && k < maxit && !split_pending && !converges_in(rr1, rr2, 1))
-        launch_one(converges_in(rr1, rr2, 2));
-      R3MG_HIP_CHECK(hipEventSynchronize(dv.ev[(kn + 1) & 1]));
-      std::memcpy(&st, &snap[(kn + 1) & 1], sizeof(PcgState));
-      ++kn;
-      if (st.all_done) break;
-      rr2.swap(rr1);
-      rr1.assign(st.rr, st.rr + nb);
-      if (k == kn) {  // nothing in flight
-        if (k >= maxit) break;
-        if (split_pending) {  // the iteration predicted to converge did not: its V-cycle half follows
-          launch_part(2);
-          split_pending = false;
-        }
-        launch_one(converges_in(rr1, rr2, 1));
-      }
-    }
-  };
-  int restarts = 0;
-  const int nparts = (n + 255) / 256;
-  for (;;) {
-    run_iterations();
-    if (!flexible || restarts >= 2) {
-      // the final state is known; write the solution back
-      launch_scatter_cols(n, NR, nb, dv.perm.p, dv.px.p, x + (int64_t)c0 * n, n, s);
-      R3MG_HIP_CHECK(hipStreamSynchronize(s));
-      break;
-    }
-    // residual replacement (float32 V-cycle): confirm the recursive residual with the true one; the solution is
-    // written back in the same sequence (one synchronisation) and again after a restart
-    apply_level<double>(c, 0, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
-    const int np = launch_residual(n, NR, dv.pb.p, dv.pq.p, dv.pz.p, dv.partials.p, s);
-    if (np != nparts) throw Error{R3MG_ERR_INVALID, "internal: residual partition"};
-    const size_t need = (size_t)np * NR * sizeof(double);
-    if (dv.pinned_part_bytes < need) {
-      if (dv.pinned_part) R3MG_HIP_CHECK(hipHostFree(dv.pinned_part));
-      dv.pinned_part = nullptr;
-      R3MG_HIP_CHECK(hipHostMalloc(&dv.pinned_part, need, hipHostMallocDefault));
-      dv.pinned_part_bytes = need;
-    }
-    R3MG_HIP_CHECK(hipMemcpyAsync(dv.pinned_part, dv.partials.p, need, hipMemcpyDeviceToHost, s));
     launch_scatter_cols(n, NR, nb, dv.perm.p, dv.px.p, x + (int64_t)c0 * n, n, s);
-    R3MG_HIP_CHECK(hipStreamSynchronize(s));
-    const double* part = static_cast<const double*>(dv.pinned_part);
-    bool all_ok = true;
-    for (int j = 0; j < nb; ++j) {
-      double rr = 0;
-      for (int p = 0; p < np; ++p) rr += part[(size_t)p * NR + j];
-      if (st.done[j] && rr > st.tau2[j]) all_ok = false;
+    launch_pcg_state_out(dst, static_cast<PcgState*>(dv.pinned_dev), s);
+    R3MG_HIP_CHECK(hipEventRecord(dv.ev[0], s));
+    R3MG_HIP_CHECK(hipEventSynchronize(dv.ev[0]));
+    std::memcpy(&st, dv.pinned, sizeof(PcgState));
+  };
+  const int key = record_key(NR, flexible);
+  enqueue_to(predict_first(dv, key, rtol, atol, maxit));
+  int restarts = 0;
+  for (;;) {
+    finish_chunk();
+    if (st.all_done) {
+      // residual replacement (float32 V-cycle): a column whose true residual fails the stop rule restarts from it,
+      // at most twice per solve
+      if (!(flexible && st.restart && restarts < 2 && k < maxit)) break;
+      ++restarts;
+      pcg_start<T>(c, NR, nb, rtol, atol, flexible, true, s);
+      split = false;
+      enqueue_to(std::min(maxit, k + 2));
+      continue;
     }
-    if (all_ok || k >= maxit) break;
-    // restart from the true residual for every column (converged ones stay converged: their r is small)
-    ++restarts;
-    std::vector<int> iters_keep(st.iters, st.iters + kMaxNR);
-    pcg_start<T>(c, NR, 0.0, 0.0, flexible, s);  // tau2 restored below
-    PcgState st2 = read_state(dv, s);
-    for (int j = 0; j < NR; ++j) {
-      st2.tau2[j] = st.tau2[j];
-      st2.rr0[j] = st.rr0[j];
-      st2.iters[j] = iters_keep[j];
-      st2.done[j] = (j >= nb) ? 1 : (st2.rr[j] <= st.tau2[j]);
-    }
-    int all = 1;
-    for (int j = 0; j < NR; ++j) all &= st2.done[j];
-    st2.all_done = all;
-    R3MG_HIP_CHECK(hipMemcpyAsync(dv.state.p, &st2, sizeof(PcgState), hipMemcpyHostToDevice, s));
-    R3MG_HIP_CHECK(hipStreamSynchronize(s));
+    if (k >= maxit) break;
+    enqueue_to(std::min(maxit, k + predict_more(st, nb)));
   }
+  dv.last_restarts = restarts;
   bool conv = true;
   for (int j = 0; j < nb; ++j) {
+    const double rr = flexible ? st.rr_true[j] : st.rr[j];
     if (iters) iters[c0 + j] = st.iters[j];
-    if (relres) relres[c0 + j] = st.rr0[j] > 0 ? std::sqrt(st.rr[j] / st.rr0[j]) : 0.0;
-    conv &= st.done[j] != 0;
+    if (relres) relres[c0 + j] = st.rr0[j] > 0 ? std::sqrt(rr / st.rr0[j]) : 0.0;
+    // the float32 V-cycle reports convergence only when the true residual passes the stop rule as well
+    conv &= st.done[j] != 0 && (!flexible || rr <= st.tau2[j]);
   }
+  if (conv && restarts == 0) record_solve(dv, key, rtol, atol, st, nb);
   if (cond) {
     int mmax = 0;
     for (int j = 0; j < nb; ++j) mmax = std::max(mmax, std::min(st.iters[j], dv.hist_rows));
@@ -1379,82 +1355,173 @@ r3mg_status pcg_solve(HandleImpl& h, const double* b, double* x, int nrhs, doubl
   return res;
 }
 
-// Several problems in one launch sequence: their iterations are captured into one hipGraph with one branch per
-// problem, replayed until every problem has converged.
+int residual_history(HandleImpl& h, int col, double* rr, int cap) {
+  Device& dv = *h.dev;
+  if (!dv.hist.p || col < 0 || col >= kMaxNR) return 0;
+  PcgState st;
+  R3MG_HIP_CHECK(hipMemcpy(&st, dv.state.p, sizeof(PcgState), hipMemcpyDeviceToHost));
+  const int m = std::min(st.iters[col], dv.hist_rows) + 1;
+  if (rr && cap > 0) {
+    std::vector<double> v((size_t)m * kMaxNR);
+    R3MG_HIP_CHECK(hipMemcpy(v.data(), rhist_of(dv), v.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int j = 0; j < std::min(m, cap); ++j) rr[j] = std::sqrt(v[(size_t)j * kMaxNR + col]);
+  }
+  return m;
+}
+
+// Several problems in one launch sequence: one iteration of every problem is captured into one hipGraph with
+// one branch per problem, and the graph is replayed in chunks as in pcg_block (whole iterations only: a problem
+// restarted by residual replacement must not receive the second half of an iteration); at the end of a chunk
+// every problem's state lands in one pinned array, read after one synchronisation.  Problems with a float32
+// V-cycle get the same true-residual check and restart.
+namespace {
+struct BranchStreams {
+  std::vector<hipStream_t> s;
+  ~BranchStreams() {
+    for (auto q : s) (void)hipStreamDestroy(q);
+  }
+};
+// capture-only streams, created once per thread and device and reused by every group solve
+std::vector<hipStream_t>& branch_streams(int dev, int count) {
+  static thread_local std::map<int, BranchStreams> pool;
+  BranchStreams& b = pool[dev];
+  while ((int)b.s.size() < count + 1) {
+    hipStream_t q;
+    R3MG_HIP_CHECK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    b.s.push_back(q);
+  }
+  return b.s;
+}
+}  // namespace
+
 r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double* const* x, double rtol, int maxit,
                       hipStream_t s, int* iters, double* relres) {
-  std::vector<hipStream_t> br(count);
-  for (int k = 0; k < count; ++k) R3MG_HIP_CHECK(hipStreamCreateWithFlags(&br[k], hipStreamNonBlocking));
-  hipStream_t cap;
-  R3MG_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  int dev = 0;
+  R3MG_HIP_CHECK(hipGetDevice(&dev));
+  std::vector<hipStream_t>& br = branch_streams(dev, count);
+  hipStream_t cap = br[count];
   hipGraph_t g = nullptr;
   hipGraphExec_t ex = nullptr;
   std::vector<hipEvent_t> evs;
+  void* pin = nullptr;
   auto cleanup = [&]() {
     if (ex) (void)hipGraphExecDestroy(ex);
     if (g) (void)hipGraphDestroy(g);
     for (auto e : evs) (void)hipEventDestroy(e);
-    for (auto q : br) (void)hipStreamDestroy(q);
-    (void)hipStreamDestroy(cap);
+    if (pin) (void)hipHostFree(pin);
   };
+  auto is32 = [&](int k) { return hs[k]->an->opt.vcycle_fp32 != 0; };
   try {
+    R3MG_HIP_CHECK(hipHostMalloc(&pin, (size_t)count * sizeof(PcgState) + 64, hipHostMallocDefault));
+    void* pin_dev = nullptr;
+    R3MG_HIP_CHECK(hipHostGetDevicePointer(&pin_dev, pin, 0));
     // set-up of every problem (plain launches on s)
     for (int k = 0; k < count; ++k) {
       HandleImpl& h = *hs[k];
-      Ctx c{*h.an, *h.dev, h.an->opt.vcycle_fp32 != 0};
+      Ctx c{*h.an, *h.dev, is32(k)};
       ensure_level_vectors(c, 1);
       ensure_pcg_vectors(c, 1);
-      ensure_hist(*h.dev, maxit);
+      ensure_hist(*h.dev, std::max(maxit, 1));
       const int n = (int)h.an->n;
       launch_gather_cols(n, 1, 1, h.dev->perm.p, b[k], n, h.dev->pb.p, s);
       launch_gather_cols(n, 1, 1, h.dev->perm.p, x[k], n, h.dev->px.p, s);
       if (c.fp32)
-        pcg_start<float>(c, 1, rtol, 0.0, true, s);
+        pcg_start<float>(c, 1, 1, rtol, 0.0, true, false, s);
       else
-        pcg_start<double>(c, 1, rtol, 0.0, false, s);
+        pcg_start<double>(c, 1, 1, rtol, 0.0, false, false, s);
     }
-    R3MG_HIP_CHECK(hipStreamSynchronize(s));
     // capture one iteration of every problem, each on its own branch
-    hipEvent_t fork;
-    R3MG_HIP_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-    evs.push_back(fork);
-    R3MG_HIP_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    R3MG_HIP_CHECK(hipEventRecord(fork, cap));
-    for (int k = 0; k < count; ++k) {
-      HandleImpl& h = *hs[k];
-      Ctx c{*h.an, *h.dev, h.an->opt.vcycle_fp32 != 0};
-      R3MG_HIP_CHECK(hipStreamWaitEvent(br[k], fork, 0));
-      if (c.fp32)
-        pcg_iteration<float>(c, 1, true, br[k]);
-      else
-        pcg_iteration<double>(c, 1, false, br[k]);
-      hipEvent_t j;
-      R3MG_HIP_CHECK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
-      evs.push_back(j);
-      R3MG_HIP_CHECK(hipEventRecord(j, br[k]));
-      R3MG_HIP_CHECK(hipStreamWaitEvent(cap, j, 0));
+    {
+      hipEvent_t fork;
+      R3MG_HIP_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+      evs.push_back(fork);
+      R3MG_HIP_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      try {
+        R3MG_HIP_CHECK(hipEventRecord(fork, cap));
+        for (int k = 0; k < count; ++k) {
+          HandleImpl& h = *hs[k];
+          Ctx c{*h.an, *h.dev, is32(k)};
+          R3MG_HIP_CHECK(hipStreamWaitEvent(br[k], fork, 0));
+          if (c.fp32)
+            pcg_iteration<float>(c, 1, true, br[k]);
+          else
+            pcg_iteration<double>(c, 1, false, br[k]);
+          hipEvent_t j;
+          R3MG_HIP_CHECK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
+          evs.push_back(j);
+          R3MG_HIP_CHECK(hipEventRecord(j, br[k]));
+          R3MG_HIP_CHECK(hipStreamWaitEvent(cap, j, 0));
+        }
+      } catch (...) {
+        hipGraph_t dead;
+        (void)hipStreamEndCapture(cap, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        throw;
+      }
+      R3MG_HIP_CHECK(hipStreamEndCapture(cap, &g));
+      R3MG_HIP_CHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
     }
-    R3MG_HIP_CHECK(hipStreamEndCapture(cap, &g));
-    R3MG_HIP_CHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
-    int it = 0;
+    hipEvent_t done_ev;
+    R3MG_HIP_CHECK(hipEventCreateWithFlags(&done_ev, hipEventDisableTiming));
+    evs.push_back(done_ev);
+    std::vector<PcgState> st(count);
+    const PcgState* hst = static_cast<const PcgState*>(pin);
+    int k = 0;
+    auto enqueue_to = [&](int target) {
+      for (; k < target; ++k) R3MG_HIP_CHECK(hipGraphLaunch(ex, s));
+    };
+    auto finish_chunk = [&]() {
+      for (int q = 0; q < count; ++q) {
+        HandleImpl& h = *hs[q];
+        Device& dv = *h.dev;
+        PcgState* dst = reinterpret_cast<PcgState*>(dv.state.p);
+        if (is32(q)) {
+          Ctx c{*h.an, dv, true};
+          apply_level<double>(c, 0, 1, dv.px.p, nullptr, dv.pz.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+          launch_pcg_true_residual((int)h.an->n, 1, dv.pb.p, dv.pz.p, dv.partials.p, dst, s);
+        }
+        launch_scatter_cols((int)h.an->n, 1, 1, dv.perm.p, dv.px.p, x[q], h.an->n, s);
+        launch_pcg_state_out(dst, static_cast<PcgState*>(pin_dev) + q, s);
+      }
+      R3MG_HIP_CHECK(hipEventRecord(done_ev, s));
+      R3MG_HIP_CHECK(hipEventSynchronize(done_ev));
+      std::memcpy(st.data(), hst, (size_t)count * sizeof(PcgState));
+    };
+    int first = 0;
+    for (int q = 0; q < count; ++q)
+      first = std::max(first, predict_first(*hs[q]->dev, record_key(1, is32(q)), rtol, 0.0, maxit));
+    enqueue_to(first);
+    std::vector<int> restarts(count, 0);
     for (;;) {
-      bool all = true;
-      for (int k = 0; k < count; ++k) all &= read_all_done(*hs[k]->dev, s) != 0;
-      if (all || it >= maxit) break;
-      R3MG_HIP_CHECK(hipGraphLaunch(ex, s));
-      ++it;
+      finish_chunk();
+      bool all = true, restarted = false;
+      int more = 1;
+      for (int q = 0; q < count; ++q) {
+        if (!st[q].all_done) {
+          all = false;
+          more = std::max(more, predict_more(st[q], 1));
+        } else if (is32(q) && st[q].restart && restarts[q] < 2 && k < maxit) {
+          ++restarts[q];
+          Ctx c{*hs[q]->an, *hs[q]->dev, true};
+          pcg_start<float>(c, 1, 1, rtol, 0.0, true, true, s);
+          restarted = true;
+          all = false;
+        }
+      }
+      if (all || k >= maxit) break;
+      if (restarted) more = std::max(more, 2);
+      enqueue_to(std::min(maxit, k + more));
     }
     r3mg_status res = R3MG_OK;
-    for (int k = 0; k < count; ++k) {
-      HandleImpl& h = *hs[k];
-      PcgState st = read_state(*h.dev, s);
-      const int n = (int)h.an->n;
-      launch_scatter_cols(n, 1, 1, h.dev->perm.p, h.dev->px.p, x[k], n, s);
-      if (iters) iters[k] = st.iters[0];
-      if (relres) relres[k] = st.rr0[0] > 0 ? std::sqrt(st.rr[0] / st.rr0[0]) : 0.0;
-      if (!st.done[0]) res = R3MG_NOT_CONVERGED;
+    for (int q = 0; q < count; ++q) {
+      const bool f32 = is32(q);
+      const double rr = f32 ? st[q].rr_true[0] : st[q].rr[0];
+      if (iters) iters[q] = st[q].iters[0];
+      if (relres) relres[q] = st[q].rr0[0] > 0 ? std::sqrt(rr / st[q].rr0[0]) : 0.0;
+      const bool conv = st[q].done[0] && (!f32 || rr <= st[q].tau2[0]);
+      if (!conv) res = R3MG_NOT_CONVERGED;
+      if (conv && restarts[q] == 0) record_solve(*hs[q]->dev, record_key(1, f32), rtol, 0.0, st[q], 1);
     }
-    R3MG_HIP_CHECK(hipStreamSynchronize(s));
     cleanup();
     return res;
   } catch (...) {
@@ -1578,7 +1645,8 @@ void attach_matrix_free(HandleImpl& h, MatFreeHost&& m, hipStream_t s) {
   drop_graphs(dv);
 }
 
-void time_smoother_kernel(HandleImpl& h, int level, int reps, hipStream_t s, double* ms, double* bytes) {
+void time_smoother_kernel(HandleImpl& h, int level, int reps, int64_t flush_bytes, hipStream_t s, double* ms,
+                          double* bytes) {
   Analysis& an = *h.an;
   Device& dv = *h.dev;
   Ctx c{an, dv, an.opt.vcycle_fp32 != 0};
@@ -1588,28 +1656,52 @@ void time_smoother_kernel(HandleImpl& h, int level, int reps, hipStream_t s, dou
   R3MG_HIP_CHECK(hipEventCreate(&e0));
   R3MG_HIP_CHECK(hipEventCreate(&e1));
   const int fl = F_RHO_STORE | F_X_ADD | F_D_OUT;
-  auto run = [&](int count) {
-    for (int r = 0; r < count; ++r) {
-      if (c.fp32) {
-        float* u = vbuf<float>((r & 1) ? D.dB : D.dA);
-        float* w = vbuf<float>((r & 1) ? D.dA : D.dB);
-        apply_level<float>(c, level, 1, u, vbuf<float>(D.b), vbuf<float>(D.rho), vbuf<float>(D.x), w, 0.0, 0.0, fl,
-                           nullptr, s);
-      } else {
-        double* u = vbuf<double>((r & 1) ? D.dB : D.dA);
-        double* w = vbuf<double>((r & 1) ? D.dA : D.dB);
-        apply_level<double>(c, level, 1, u, vbuf<double>(D.b), vbuf<double>(D.rho), vbuf<double>(D.x), w, 0.0, 0.0,
-                            fl, nullptr, s);
-      }
+  auto launch = [&](int r) {
+    if (c.fp32) {
+      float* u = vbuf<float>((r & 1) ? D.dB : D.dA);
+      float* w = vbuf<float>((r & 1) ? D.dA : D.dB);
+      apply_level<float>(c, level, 1, u, vbuf<float>(D.b), vbuf<float>(D.rho), vbuf<float>(D.x), w, 0.0, 0.0, fl,
+                         nullptr, s);
+    } else {
+      double* u = vbuf<double>((r & 1) ? D.dB : D.dA);
+      double* w = vbuf<double>((r & 1) ? D.dA : D.dB);
+      apply_level<double>(c, level, 1, u, vbuf<double>(D.b), vbuf<double>(D.rho), vbuf<double>(D.x), w, 0.0, 0.0,
+                          fl, nullptr, s);
     }
   };
-  run(3);
-  R3MG_HIP_CHECK(hipEventRecord(e0, s));
-  run(reps);
-  R3MG_HIP_CHECK(hipEventRecord(e1, s));
-  R3MG_HIP_CHECK(hipEventSynchronize(e1));
   float t = 0;
-  R3MG_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+  try {
+    for (int r = 0; r < 3; ++r) launch(r);
+    if (flush_bytes <= 0) {
+      // back to back, as a smoothing sweep runs them
+      R3MG_HIP_CHECK(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) launch(r);
+      R3MG_HIP_CHECK(hipEventRecord(e1, s));
+      R3MG_HIP_CHECK(hipEventSynchronize(e1));
+      R3MG_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+    } else {
+      // each launch alone, after a pass that reads and writes flush_bytes of other memory (more than the caches
+      // hold), so that the matrix and vectors come from HBM
+      DBuf<double> fb;
+      const int64_t nf = std::max<int64_t>(1, flush_bytes / 8);
+      fb.alloc((size_t)nf);
+      R3MG_HIP_CHECK(hipMemsetAsync(fb.p, 0, (size_t)nf * 8, s));
+      for (int r = 0; r < reps; ++r) {
+        launch_axpby(nf, 1.0, fb.p, 1.0, fb.p, s);
+        R3MG_HIP_CHECK(hipEventRecord(e0, s));
+        launch(r);
+        R3MG_HIP_CHECK(hipEventRecord(e1, s));
+        R3MG_HIP_CHECK(hipEventSynchronize(e1));
+        float tr = 0;
+        R3MG_HIP_CHECK(hipEventElapsedTime(&tr, e0, e1));
+        t += tr;
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *ms = (double)t / reps;
