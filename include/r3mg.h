@@ -160,6 +160,27 @@ r3mg_status r3mg_set_matrix_free(r3mg_handle h, const int32_t* cells, int64_t nc
 /* z = B r, one V-cycle (Section 4) in the handle's V-cycle precision, for nrhs right-hand sides. */
 r3mg_status r3mg_vcycle(r3mg_handle h, const double* r_dev, double* z_dev, int nrhs, void* stream);
 
+/* Capacity of the device scratch that r3mg_vcycle_noalloc takes its work vectors from (64 MiB, a static device
+ * array of the library that every GPU using it holds until the process ends). */
+#define R3MG_NOALLOC_SCRATCH_BYTES (64 << 20)
+
+/* r3mg_vcycle for callers that cannot allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  The same V-cycle as r3mg_vcycle, with the same kernels and bitwise the same
+ * results, for nrhs in {1, 2, 4, 8, 16} right-hand sides, with the level work vectors (5 per level, n_l x nrhs
+ * values in the V-cycle precision, each rounded up to 256 bytes) taken from the library's static device scratch
+ * of R3MG_NOALLOC_SCRATCH_BYTES instead of the handle's buffers.  For nrhs > 1 the fine-level kernel is the one
+ * the handle's timing chose for that many columns (r3mg_vcycle and r3mg_pcg_solve time the candidates at their
+ * first call with that many; this call does not time, since timing synchronises), the default lanes kernel
+ * before any such call.  The call allocates no device or host memory,
+ * does not synchronise and launches kernels only (the carved work vectors are zeroed by a fill kernel), so it
+ * may be captured into a graph.  r_dev, z_dev: device float64, nrhs columns of n (caller's numbering; z is
+ * written).  The handle's device must be current.  All calls on one GPU share its scratch, which keeps the last
+ * call's contents: calls that overlap on one GPU (two streams, two threads, two handles) race.  Errors: INVALID
+ * for another nrhs, for work vectors larger than the scratch (the message states both sizes), for a matrix-free
+ * fine operator with nrhs > 1 whose cell outputs have not been sized by a call of r3mg_vcycle or r3mg_pcg_solve
+ * with at least that many columns, or when the handle's device is not current; nothing is launched then. */
+r3mg_status r3mg_vcycle_noalloc(r3mg_handle h, const double* r_dev, double* z_dev, int nrhs, void* stream);
+
 /* y = A_l x on level `level` in float64 (level 0 in the caller's numbering, coarse levels in box * B + q
  * numbering), or, for level == -1, the fine operator as PCG applies it.  Diagnostic/parity entry point. */
 r3mg_status r3mg_level_apply(r3mg_handle h, int level, const double* x_dev, double* y_dev, void* stream);

@@ -3,7 +3,8 @@
 The solver lives in libr3mg.so (C ABI in include/r3mg.h); this package only marshals arguments to it and
 adds the differentiable solve (autograd.py).  Nothing here falls back to a CPU implementation.
 """
-from ._lib import (Assembler, Hierarchy, Options, R3mgError, lib, rtree, solve_group, EXPORTED, LIB_PATH)
+from ._lib import (Assembler, Hierarchy, Options, R3mgError, lib, rtree, solve_group, EXPORTED, LIB_PATH,
+                   NOALLOC_SCRATCH_BYTES)
 
 
 def __getattr__(name):
@@ -15,4 +16,4 @@ def __getattr__(name):
 
 
 __all__ = ["Assembler", "Hierarchy", "Options", "R3mgError", "lib", "rtree", "solve_group", "EXPORTED",
-           "LIB_PATH", "AdjointPoisson", "PoissonSolve"]
+           "LIB_PATH", "NOALLOC_SCRATCH_BYTES", "AdjointPoisson", "PoissonSolve"]

@@ -16,12 +16,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libr3mg.so")
 
 OK, NOT_CONVERGED = 0, 1
+NOALLOC_SCRATCH_BYTES = 64 << 20   # R3MG_NOALLOC_SCRATCH_BYTES
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID", -2: "NOT_UNISOLVENT", -3: "DEGENERATE_BOX",
                 -4: "NOT_SPD", -5: "OOM", -6: "HIP"}
 
 EXPORTED = [
     "r3mg_analyze_cells", "r3mg_set_matrix_free",
     "r3mg_default_options", "r3mg_analyze", "r3mg_factor", "r3mg_setup", "r3mg_update_values", "r3mg_vcycle",
+    "r3mg_vcycle_noalloc",
     "r3mg_level_apply", "r3mg_pcg_solve", "r3mg_pcg_solve_ex", "r3mg_pcg_solve_group", "r3mg_pcg_history",
     "r3mg_info", "r3mg_export_partition",
     "r3mg_export_P", "r3mg_export_level", "r3mg_time_smoother_kernel", "r3mg_cell_grad", "r3mg_assembler_create",
@@ -95,6 +97,7 @@ def lib():
     L.r3mg_update_values.argtypes = [vp, vp, vp]
     L.r3mg_set_matrix_free.argtypes = [vp, vp, i64, i32, vp, vp]
     L.r3mg_vcycle.argtypes = [vp, vp, vp, i32, vp]
+    L.r3mg_vcycle_noalloc.argtypes = [vp, vp, vp, i32, vp]
     L.r3mg_level_apply.argtypes = [vp, i32, vp, vp, vp]
     L.r3mg_pcg_solve.argtypes = [vp, vp, vp, i32, dbl, i32, vp, vp, vp]
     L.r3mg_pcg_solve_ex.argtypes = [vp, vp, vp, i32, dbl, dbl, i32, vp, vp, vp, vp]
@@ -227,6 +230,11 @@ class Hierarchy:
     def vcycle(self, r, z, stream=None):
         nrhs = 1 if r.dim() == 1 else r.shape[0]
         _check(lib().r3mg_vcycle(self._h, _dev(r), _dev(z), nrhs, _stream(stream)), "r3mg_vcycle")
+
+    def vcycle_noalloc(self, r, z, stream=None):
+        """z = B r with the work vectors in the library's static device scratch (no allocation)."""
+        nrhs = 1 if r.dim() == 1 else r.shape[0]
+        _check(lib().r3mg_vcycle_noalloc(self._h, _dev(r), _dev(z), nrhs, _stream(stream)), "r3mg_vcycle_noalloc")
 
     def level_apply(self, level: int, x, y, stream=None):
         _check(lib().r3mg_level_apply(self._h, level, _dev(x), _dev(y), _stream(stream)), "r3mg_level_apply")

@@ -177,6 +177,15 @@ r3mg_status r3mg_vcycle(r3mg_handle h, const double* r_dev, double* z_dev, int n
   });
 }
 
+r3mg_status r3mg_vcycle_noalloc(r3mg_handle h, const double* r_dev, double* z_dev, int nrhs, void* stream) {
+  return guard([&] {
+    require_factored(h);
+    if (!r_dev || !z_dev) throw Error{R3MG_ERR_INVALID, "bad vcycle arguments"};
+    vcycle_noalloc(h->impl, r_dev, z_dev, nrhs, S(stream));
+    return R3MG_OK;
+  });
+}
+
 r3mg_status r3mg_level_apply(r3mg_handle h, int level, const double* x_dev, double* y_dev, void* stream) {
   return guard([&] {
     require_factored(h);

@@ -198,6 +198,10 @@ struct DevLevel {
   DBuf<double> dinv64;
   DBuf<float> dinv32;
   double lam_hi = 0, lam_lo = 0, lam_hat = 0;
+  // Chebyshev coefficients of the level's smoother (set with the interval): first direction scale 1/theta, then
+  // (c1, c2) of steps k = 1..K-1
+  double cheb_inv_theta = 0;
+  std::vector<double> cheb_c1, cheb_c2;
   int lanes = 8;  // lanes per row of the SpMV kernels
   DBuf<int32_t> rb[3];  // l = 0: CSR row blocks of the single-RHS row-block kernels, per geometry
   DBuf<int32_t> lrb[kLocalGeomsAll], lubp[kLocalGeomsAll], lucol[kLocalGeomsAll];  // local-column blocks per geometry
@@ -288,6 +292,8 @@ std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int 
 void device_setup(HandleImpl& h, hipStream_t s);
 void update_values(HandleImpl& h, const double* vals_dev, hipStream_t s);
 void vcycle_api(HandleImpl& h, const double* r, double* z, int nrhs, hipStream_t s);
+// the same V-cycle with its work vectors in the static device scratch (no allocation, no synchronisation)
+void vcycle_noalloc(HandleImpl& h, const double* r, double* z, int nrhs, hipStream_t s);
 void level_apply(HandleImpl& h, int level, const double* x, double* y, hipStream_t s);
 r3mg_status pcg_solve(HandleImpl& h, const double* b, double* x, int nrhs, double rtol, double atol, int maxit,
                       hipStream_t s, double* cond,

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "noalloc.h"
 #include "r3mg_internal.h"
 
 namespace r3mg {
@@ -153,7 +154,19 @@ struct Ctx {
   Analysis& an;
   Device& dv;
   bool fp32;
+  // V-cycle work vectors of this call, kWorkSlots per level (null: the handle's own buffers, DevLevel::b ...)
+  char* const* work = nullptr;
 };
+
+// V-cycle work vector `slot` of level l: the call's table, else the handle's buffer
+enum : int { W_B = 0, W_X, W_RHO, W_DA, W_DB, kWorkSlots };
+template <typename T>
+T* wv(Ctx& c, int l, int slot) {
+  if (c.work) return reinterpret_cast<T*>(c.work[(size_t)l * kWorkSlots + slot]);
+  DevLevel& D = c.dv.lv[l];
+  DBuf<char>* bufs[kWorkSlots] = {&D.b, &D.x, &D.rho, &D.dA, &D.dB};
+  return reinterpret_cast<T*>(bufs[slot]->p);
+}
 
 template <typename T>
 LevelOp<T> level_op(Ctx& c, int l) {
@@ -526,8 +539,8 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   Device& dv = c.dv;
   const int L = an.nlevels() - 1;
   DevLevel& D = dv.lv[l];
-  T* b = b_override ? const_cast<T*>(b_override) : vbuf<T>(D.b);
-  T* x = vbuf<T>(D.x);
+  T* b = b_override ? const_cast<T*>(b_override) : wv<T>(c, l, W_B);
+  T* x = wv<T>(c, l, W_X);
   if (l == L) {
     if (dv.ct > 0 && nr <= kDenseSymMaxNR)
       launch_dense_apply_sym<T>((int)dv.nc, dv.ct, nr, dv.csym.p, dv.ctile.p, dv.cpart.p, b, x, skip, s);
@@ -537,10 +550,9 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   }
   const r3mg_options& o = an.opt;
   const int K = o.cheb_degree;
-  const Cheb ch = cheb_coeffs(D.lam_lo, D.lam_hi, K);
   LevelOp<T> op = level_op<T>(c, l);
-  T* rho = vbuf<T>(D.rho);
-  T* buf[2] = {vbuf<T>(D.dA), vbuf<T>(D.dB)};
+  T* rho = wv<T>(c, l, W_RHO);
+  T* buf[2] = {wv<T>(c, l, W_DA), wv<T>(c, l, W_DB)};
   bool x_zero = true, rho_is_b = true;
   const int total_spmv = K * (o.pre_steps + o.post_steps);
   int done_spmv = 0;
@@ -563,11 +575,11 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
       u = buf[0];  // D^{-1} b / theta prepared by the caller
     } else {
       u = other(pend);
-      F(pend, u, 0.0, ch.inv_theta, true);
+      F(pend, u, 0.0, D.cheb_inv_theta, true);
     }
     for (int k = 1; k < K; ++k) {
       T* w = other(u);
-      F(u, w, ch.c1[k - 1], ch.c2[k - 1], true);
+      F(u, w, D.cheb_c1[k - 1], D.cheb_c2[k - 1], true);
       u = w;
     }
     pend = u;
@@ -576,7 +588,7 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   DevLevel& N = dv.lv[l + 1];
   const bool next_smooth = (l + 1 < L) && o.pre_steps > 0;
   const double next_inv_theta = next_smooth ? 2.0 / (N.lam_hi + N.lam_lo) : 0.0;
-  T* dnext = next_smooth ? vbuf<T>(N.dA) : nullptr;
+  T* dnext = next_smooth ? wv<T>(c, l + 1, W_DA) : nullptr;
   const T* dinv_next = nullptr;
   if constexpr (sizeof(T) == 4) dinv_next = N.dinv32.p; else dinv_next = N.dinv64.p;
   const T* pt = nullptr;
@@ -589,7 +601,7 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   BoxRestrict<T> rs;
   if (fused) {
     rs.pt = pt;
-    rs.bnext = vbuf<T>(N.b);
+    rs.bnext = wv<T>(c, l + 1, W_B);
     rs.dinv_next = dinv_next;
     rs.dnext = dnext;
     rs.inv_theta_next = (T)next_inv_theta;
@@ -600,10 +612,10 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   } else if (l == 0) {
     const T* xi;
     if constexpr (sizeof(T) == 4) xi = D.xi32.p; else xi = D.xi64.p;
-    launch_restrict0<T>((int)N.nbox, an.n, an.d, an.pc, nr, D.leaf_off.p, D.owner.p, xi, src, vbuf<T>(N.b), dinv_next,
+    launch_restrict0<T>((int)N.nbox, an.n, an.d, an.pc, nr, D.leaf_off.p, D.owner.p, xi, src, wv<T>(c, l + 1, W_B), dinv_next,
                         dnext, next_inv_theta, skip, s);
   } else {
-    launch_restrict_c<T>((int)N.nbox, (int)D.nbox, N.child_shift, an.d, an.pc, nr, pt, src, vbuf<T>(N.b),
+    launch_restrict_c<T>((int)N.nbox, (int)D.nbox, N.child_shift, an.d, an.pc, nr, pt, src, wv<T>(c, l + 1, W_B),
                          dinv_next, dnext, next_inv_theta, skip, s);
   }
 
@@ -613,11 +625,11 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   if (l == 0) {
     const T* xi;
     if constexpr (sizeof(T) == 4) xi = D.xi32.p; else xi = D.xi64.p;
-    launch_prolong0<T>((int)D.n, an.d, an.pc, nr, D.owner.p, xi, vbuf<T>(N.x), pend_c, v, skip, s);
+    launch_prolong0<T>((int)D.n, an.d, an.pc, nr, D.owner.p, xi, wv<T>(c, l + 1, W_X), pend_c, v, skip, s);
   } else {
     const T* pt;
     if constexpr (sizeof(T) == 4) pt = D.pt32.p; else pt = D.pt64.p;
-    launch_prolong_c<T>((int)D.nbox, N.child_shift, an.d, an.pc, nr, pt, vbuf<T>(N.x), pend_c, v, skip, s);
+    launch_prolong_c<T>((int)D.nbox, N.child_shift, an.d, an.pc, nr, pt, wv<T>(c, l + 1, W_X), pend_c, v, skip, s);
   }
 
   // post-smoothing from the corrected iterate
@@ -628,11 +640,11 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   T* u = v;
   for (int app = 0; app < o.post_steps; ++app) {
     T* w = other(u);
-    F(u, w, 0.0, ch.inv_theta, true);  // x += u, rho -= A u, first direction
+    F(u, w, 0.0, D.cheb_inv_theta, true);  // x += u, rho -= A u, first direction
     u = w;
     for (int k = 1; k < K; ++k) {
       T* w2 = other(u);
-      F(u, w2, ch.c1[k - 1], ch.c2[k - 1], true);
+      F(u, w2, D.cheb_c1[k - 1], D.cheb_c2[k - 1], true);
       u = w2;
     }
   }
@@ -684,6 +696,10 @@ static void lanczos_level(Ctx& c, int l, hipStream_t s) {
   D.lam_hat = sturm_max(alpha, beta);
   D.lam_hi = an.opt.cheb_boost * D.lam_hat;
   D.lam_lo = D.lam_hi / an.opt.cheb_ratio;
+  const Cheb ch = cheb_coeffs(D.lam_lo, D.lam_hi, an.opt.cheb_degree);
+  D.cheb_inv_theta = ch.inv_theta;
+  D.cheb_c1 = ch.c1;
+  D.cheb_c2 = ch.c2;
 }
 
 void numeric_setup(HandleImpl& h, hipStream_t s) {
@@ -981,6 +997,8 @@ void device_setup(HandleImpl& h, hipStream_t s) {
   numeric_setup(h, s);
   tune_stream_shape(h, s);
   R3MG_HIP_CHECK(hipStreamSynchronize(s));
+  // the allocation-free V-cycle's scratch address on this device, looked up once at set-up
+  (void)scratch_device_ptr(dv.dev);
 }
 
 void update_values(HandleImpl& h, const double* vals_dev, hipStream_t s) {
@@ -1042,6 +1060,59 @@ void vcycle_api(HandleImpl& h, const double* r, double* z, int nrhs, hipStream_t
     vcycle_api_t<float>(h, r, z, nrhs, s);
   else
     vcycle_api_t<double>(h, r, z, nrhs, s);
+}
+
+// The V-cycle of vcycle_api_t for one block of nrhs in {1, 2, 4, 8, 16} columns, with the level work vectors
+// carved from the static device scratch: kWorkSlots per level, n_l x nrhs values each, every one starting on a
+// 256-byte boundary, zeroed by a fill kernel first (every call starts as the first call of vcycle_api_t does, on
+// freshly cleared buffers).  Nothing is allocated, on the device or the host, and nothing synchronises.
+constexpr int kNoallocMaxLevels = 32;
+template <typename T>
+static void vcycle_noalloc_t(HandleImpl& h, const double* r, double* z, int nrhs, hipStream_t s) {
+  Analysis& an = *h.an;
+  Device& dv = *h.dev;
+  const int L = an.nlevels() - 1;
+  const int NR = nrhs;
+  if (NR != 1 && NR != 2 && NR != 4 && NR != 8 && NR != 16)
+    throw Error{R3MG_ERR_INVALID, "r3mg_vcycle_noalloc: nrhs must be 1, 2, 4, 8 or 16"};
+  if (L + 1 > kNoallocMaxLevels) throw Error{R3MG_ERR_INVALID, "r3mg_vcycle_noalloc: too many levels"};
+  int cur = -1;
+  R3MG_HIP_CHECK(hipGetDevice(&cur));
+  if (cur != dv.dev) throw Error{R3MG_ERR_INVALID, "r3mg_vcycle_noalloc: the handle's device is not current"};
+  DevLevel& D0 = dv.lv[0];
+  if (D0.mf && NR > 1 && dv.mf.mr_cap < NR)
+    throw Error{R3MG_ERR_INVALID,
+                "r3mg_vcycle_noalloc: the matrix-free operator's cell outputs are not sized for this many columns"};
+  size_t offs[kNoallocMaxLevels * kWorkSlots];
+  size_t off = 0;
+  for (int l = 0; l <= L; ++l)
+    for (int w = 0; w < kWorkSlots; ++w) {
+      offs[(size_t)l * kWorkSlots + w] = off;
+      off += ((size_t)dv.lv[l].n * NR * sizeof(T) + 255) / 256 * 256;
+    }
+  if (off > kNoallocScratchBytes)
+    throw Error{R3MG_ERR_INVALID, "r3mg_vcycle_noalloc: the work vectors need " + std::to_string(off) +
+                                      " bytes, more than the scratch's " + std::to_string(kNoallocScratchBytes)};
+  char* base = static_cast<char*>(scratch_device_ptr(dv.dev));
+  char* work[kNoallocMaxLevels * kWorkSlots];
+  for (int i = 0; i < (L + 1) * kWorkSlots; ++i) work[i] = base + offs[i];
+  scratch_zero(base, off, s);
+  Ctx c{an, dv, sizeof(T) == 4, work};
+  T* b0 = wv<T>(c, 0, W_B);
+  const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
+  const T* dinv0;
+  if constexpr (sizeof(T) == 4) dinv0 = D0.dinv32.p; else dinv0 = D0.dinv64.p;
+  launch_vc_entry<T>((int)an.n, NR, dv.perm.p, r, an.n, b0, dinv0, smooth0 ? wv<T>(c, 0, W_DA) : nullptr,
+                     2.0 / (D0.lam_hi + D0.lam_lo), s);
+  T* pend = (L == 0) ? nullptr : vcycle_rec<T>(c, 0, NR, nullptr, nullptr, s);
+  launch_vc_exit<T>((int)an.n, NR, dv.perm.p, wv<T>(c, 0, W_X), pend, z, an.n, s);
+}
+
+void vcycle_noalloc(HandleImpl& h, const double* r, double* z, int nrhs, hipStream_t s) {
+  if (h.an->opt.vcycle_fp32)
+    vcycle_noalloc_t<float>(h, r, z, nrhs, s);
+  else
+    vcycle_noalloc_t<double>(h, r, z, nrhs, s);
 }
 
 void level_apply(HandleImpl& h, int level, const double* x, double* y, hipStream_t s) {
