@@ -13,7 +13,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libr3mg.so")
+# R3MG_LIBRARY selects another build of the same library (the host-sanitized test build)
+LIB_PATH = os.environ.get("R3MG_LIBRARY") or os.path.join(_HERE, "libr3mg.so")
 
 OK, NOT_CONVERGED = 0, 1
 NOALLOC_SCRATCH_BYTES = 64 << 20   # R3MG_NOALLOC_SCRATCH_BYTES
@@ -43,7 +44,8 @@ class _Options(C.Structure):
                 ("max_coarse_dofs", C.c_int), ("skip_leaf_level", C.c_int), ("cheb_degree", C.c_int),
                 ("pre_steps", C.c_int), ("post_steps", C.c_int), ("lanczos_steps", C.c_int),
                 ("cheb_boost", C.c_double), ("cheb_ratio", C.c_double), ("vcycle_fp32", C.c_int),
-                ("use_graph", C.c_int), ("fine_kernel", C.c_int), ("multi_rhs_kernel", C.c_int)]
+                ("use_graph", C.c_int), ("fine_kernel", C.c_int), ("multi_rhs_kernel", C.c_int),
+                ("matrix_cache", C.c_int)]
 
 
 class _LevelInfo(C.Structure):
@@ -70,6 +72,7 @@ class Options:
     use_graph: int = 1
     fine_kernel: int = -1
     multi_rhs_kernel: int = -1
+    matrix_cache: int = -1
 
     def _c(self) -> _Options:
         return _Options(**dataclasses.asdict(self))

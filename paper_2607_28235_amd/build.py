@@ -58,6 +58,57 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host-sanitized variant for testing the host code on the CPU: the analysis, the matrix-free set-up and the C ABI
+# are compiled with AddressSanitizer and UndefinedBehaviorSanitizer on their host side only (device code is never
+# sanitized), and linked with the ordinary objects of the other sources.  Load it with R3MG_LIBRARY pointing at it
+# and the compiler's ASan runtime preloaded (sanitizer_runtime()).
+SAN_LIB = os.path.join(HERE, "libr3mg_san.so")
+SAN_DIR = os.path.join(HERE, "_build_san")
+SAN_SOURCES = ["analysis.cpp", "matfree.cpp", "capi.cpp"]
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
+def sanitizer_runtime() -> str:
+    """Path of the ASan runtime matching hipcc's compiler (to LD_PRELOAD into an unsanitized Python)."""
+    r = subprocess.run([os.path.join(os.path.dirname(_hipcc()), "..", "llvm", "bin", "clang"),
+                        "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.exists(path):
+        raise RuntimeError("ASan runtime of the ROCm compiler not found")
+    return path
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    os.makedirs(SAN_DIR, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        if src not in SAN_SOURCES:
+            obj = os.path.join(BUILD_DIR, src + ".o")
+            if not os.path.exists(obj):
+                build()
+            objs.append(obj)
+            continue
+        obj = os.path.join(SAN_DIR, src + ".o")
+        cmd = [_hipcc(), *COMMON, *PER_FILE.get(src, []), *SAN_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        objs.append(obj)
+    # no sanitizer flags at the link: the sanitizer entry points stay undefined in the library and are resolved
+    # from the runtime preloaded into the process (its ASan runtime carries the UBSan handlers as well)
+    cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", SAN_LIB, *objs, "-pthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print("built", SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--sanitized" in sys.argv:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)

@@ -881,6 +881,13 @@ static double local_bytes(int64_t nnz, int64_t n, int g, const LocalBlocks& lb, 
          4.0 * (nrb + 1) + 7.0 * n * sv;
 }
 
+// F_KEEP (ordinary matrix loads) for a level whose matrix stream takes `bytes`, per r3mg_options::matrix_cache
+static int keep_rule(const r3mg_options& o, double bytes) {
+  if (o.matrix_cache == 0) return 0;
+  if (o.matrix_cache == 1) return F_KEEP;
+  return bytes <= kKeepCachedBytes ? F_KEEP : 0;
+}
+
 void device_setup(HandleImpl& h, hipStream_t s) {
   Analysis& an = *h.an;
   h.dev = std::make_unique<Device>();
@@ -931,8 +938,8 @@ void device_setup(HandleImpl& h, hipStream_t s) {
       D.shape_bytes[kLocalFirst + g] = local_bytes(an.nnz, an.n, g, an.loc[g], sv0);
     }
     // matrix read with ordinary loads when its stream (values and 1-byte positions) fits the caches
-    D.keep32 = (double)an.nnz * (4 + 1) <= kKeepCachedBytes ? F_KEEP : 0;
-    D.keep64 = (double)an.nnz * (8 + 1) <= kKeepCachedBytes ? F_KEEP : 0;
+    D.keep32 = keep_rule(an.opt, (double)an.nnz * (4 + 1));
+    D.keep64 = keep_rule(an.opt, (double)an.nnz * (8 + 1));
     // shape 9: the vector-load kernel over the blocks of local geometry 0; shape 10: the same over geometry 3
     D.fb[kLocalFirst + kLocalGeoms] = D.fb[kLocalFirst];
     D.shape_bytes[kLocalFirst + kLocalGeoms] = D.shape_bytes[kLocalFirst];
@@ -983,8 +990,8 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     D.boxrow = boxrow_supported(B, D.maxnb);
     // the box-row and block-row kernels stream the values only
     const int ib = (D.boxrow || H.rowptr.empty()) ? 0 : 1;
-    D.keep32 = (double)D.nnz * (4 + ib) <= kKeepCachedBytes ? F_KEEP : 0;
-    D.keep64 = (double)D.nnz * (8 + ib) <= kKeepCachedBytes ? F_KEEP : 0;
+    D.keep32 = keep_rule(an.opt, (double)D.nnz * (4 + ib));
+    D.keep64 = keep_rule(an.opt, (double)D.nnz * (8 + ib));
     if (!D.boxrow && !H.rowptr.empty()) {  // narrow block rows: the level is held as 1-byte local-column blocks
       D.rowptr.upload(H.rowptr, s);
       // the vector kernel: shape 9 over 2048-nonzero blocks, shape 11 over (3072, 64-row) blocks

@@ -125,6 +125,36 @@ def test_vcycle_matches_oracle_fp64(name, request):
         assert _rel(z.cpu().numpy(), zo) < 1e-11
 
 
+@pytest.mark.parametrize("name", ["small2d", "small3d"])
+def test_vcycle_matrix_load_modes(name, request):
+    """The level kernels read the matrix with nontemporal loads (matrix_cache = 0, the form the large 3D fine
+    levels take) or with ordinary loads (1, the form of levels that fit the caches): the same arithmetic, so the
+    V-cycle agrees with the oracle under both and is bitwise the same, in both precisions."""
+    c = request.getfixturevalue(name)
+    P = _P()
+    import dataclasses
+    g = np.random.default_rng(3)
+    r = g.standard_normal(c.prob.n)
+    r[c.ho.constrained] = 0.0
+    zo = O.vcycle(c.ho, r)
+    for fp32 in (0, 1):
+        out = []
+        for mode in (0, 1, -1):
+            _case(f"vcycle {name} matrix_cache={mode} fp32={fp32}")
+            h = P.Hierarchy(c.prob.coords, c.prob.row_ptr, c.prob.col, c.prob.val,
+                            dataclasses.replace(c.opts, matrix_cache=mode, vcycle_fp32=fp32))
+            z = torch.zeros(c.prob.n, dtype=torch.float64, device="cuda")
+            h.vcycle(_t(r), z)
+            torch.cuda.synchronize()
+            zz = z.cpu().numpy()
+            if not fp32:
+                assert _rel(zz, zo) < 1e-11
+            out.append(zz)
+            h.close()
+        np.testing.assert_array_equal(out[0], out[1])
+        np.testing.assert_array_equal(out[0], out[2])
+
+
 @pytest.mark.parametrize("nrhs", [2, 3, 4, 8])
 def test_block_vcycle_matches_oracle(small3d, nrhs):
     """V-cycles over several columns, per column against the oracle.  The coarsest level (216 DoFs: four 64-row
