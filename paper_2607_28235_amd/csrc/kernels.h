@@ -258,8 +258,10 @@ void launch_mf_apply_mr(const MfOp& m, int nr, const MfTables<T>& tb, const T* g
                         const T* u, const T* b, T* rho, T* x, T* dout, double c1, double c2, int flags,
                         const int* skip, hipStream_t s);
 
-// dense Cholesky (lower, in place, row-major n x n) and inverse; *bad set on a non-positive pivot
-void dense_cholesky_inverse(int n, double* A, double* Inv, int* bad, hipStream_t s);
+// Dense Cholesky factorisation A = L L^T (lower, in place, row-major n x n) and inverse A^{-1} = L^{-T} L^{-1}
+// into Inv (full), in 64 x 64 tiles on the FP64 matrix cores; *bad set on a non-positive pivot.  ws: ceil(n/64)
+// x 64 x 64 doubles (inverted diagonal tiles); Y: n x n doubles of scratch (L^{-1}).
+void dense_cholesky_inverse(int n, double* A, double* Inv, double* ws, double* Y, int* bad, hipStream_t s);
 
 // PCG (float64).  Each reduction is a vector kernel storing per-block partial sums (at most kPcgBlocks blocks,
 // a partition that depends only on n and nr, so the iterates do not depend on the kernel that formed A p)

@@ -2526,19 +2526,112 @@ void launch_lanczos_u(int64_t n, const double* dinv, const double* Av, double be
 }
 
 // =============================================================================================
-// Dense Cholesky (right-looking, 64-wide panels) and explicit inverse, float64, row-major in place.
+// Dense Cholesky factorisation and explicit inverse of the coarsest operator (float64, row-major, n x n).
+// Blocked in 64 x 64 tiles; every tile product runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+//   1. A = L L^T, right-looking by block columns k: the diagonal tile is factored in LDS and inverted
+//      (D_k = L_kk^{-1}); the panel below becomes A[i,k] D_k^T; the trailing lower tiles lose A[i,k] A[j,k]^T.
+//   2. Y = L^{-1}, forward by block rows k: Y[k, 0..k] <- D_k Y[k, 0..k] (Y starts at zero; Y[k,k] = D_k),
+//      then Y[r, 0..k] -= L[r,k] Y[k, 0..k] for r > k.
+//   3. A^{-1} = Y^T Y: upper tile (I, J), I <= J, sums Y[M,I]^T Y[M,J] over M >= J and is stored with its
+//      mirror (L^{-T} L^{-1} = (L L^T)^{-1}).
+// About n^3 / 3 flops in each step (the triangular structure is skipped), against n^3 / 3 + 2 n^3 for two full
+// triangular solves on the identity.  Tiles reaching past n are padded with the identity on a diagonal tile
+// and zeros elsewhere.  A non-positive pivot sets *bad (the factorisation then continues with pivot 1).
 // =============================================================================================
-constexpr int NB = 64;
+constexpr int DT = 64;
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-// factor the diagonal block A[k0:k0+nb, k0:k0+nb] in one workgroup (LDS); lower triangle holds L
-__global__ __launch_bounds__(256) void k_chol_diag(int n, int k0, double* A, int* bad) {
-  __shared__ double s[NB][NB + 1];
-  const int nb = min(NB, n - k0);
-  for (int e = threadIdx.x; e < nb * nb; e += 256) s[e / nb][e % nb] = A[(int64_t)(k0 + e / nb) * n + k0 + e % nb];
+// X[i][j] = M[(R + i) n + C + j] inside the matrix, outside it 1 on the diagonal of a diagonal tile (diag_pad)
+// and 0 elsewhere; stored s[i][j], or s[j][i] with trans.  The tile product reads its operands as s[k][index]
+// with the index running across the lanes, so an operand whose index is its row is loaded transposed.
+__device__ inline void dt_load(double (*s)[DT + 1], const double* __restrict__ M, int n, int R, int C, bool trans,
+                               bool diag_pad) {
+  for (int e = threadIdx.x; e < DT * DT; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    double v = (diag_pad && i == j) ? 1.0 : 0.0;
+    if (R + i < n && C + j < n) v = M[(int64_t)(R + i) * n + C + j];
+    if (trans)
+      s[j][i] = v;
+    else
+      s[i][j] = v;
+  }
+}
+
+// acc += sum over k < 64 of Aop(i, k) Bop(k, j), Aop(i, k) = sa[k][i], Bop(k, j) = sb[k][j].  Wave w owns the
+// output rows 32 (w / 2) .. + 31 and columns 32 (w % 2) .. + 31 as 2 x 2 subtiles of 16 x 16.  Lane l supplies
+// A[l % 16][l / 16] of each 16 x 4 left operand and B[l / 16][l % 16] of each 4 x 16 right operand, and element r
+// of its result is C[4 r + l / 16][l % 16] (the instruction's layout, checked on gfx950).
+__device__ inline void dt_mfma(const double (*sa)[DT + 1], const double (*sb)[DT + 1], v4d acc[2][2]) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  const int li = l & 15, lk = l >> 4;
+#pragma unroll 4
+  for (int k = 0; k < DT; k += 4) {
+    const double a0 = sa[k + lk][r0 + li], a1 = sa[k + lk][r0 + 16 + li];
+    const double b0 = sb[k + lk][c0 + li], b1 = sb[k + lk][c0 + 16 + li];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+__device__ inline void dt_zero(v4d acc[2][2]) {
+  for (int s = 0; s < 2; ++s)
+    for (int t = 0; t < 2; ++t) acc[s][t] = v4d{0.0, 0.0, 0.0, 0.0};
+}
+
+// f(row, col, value) for every element of the wave's part of the tile
+template <typename F>
+__device__ inline void dt_each(const v4d acc[2][2], F f) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  for (int s = 0; s < 2; ++s)
+    for (int t = 0; t < 2; ++t)
+      for (int r = 0; r < 4; ++r) f(r0 + 16 * s + 4 * r + (l >> 4), c0 + 16 * t + (l & 15), acc[s][t][r]);
+}
+
+// M tile (R, C) -= acc (sub) or = acc, inside the matrix
+__device__ inline void dt_store(const v4d acc[2][2], double* M, int n, int R, int C, bool sub) {
+  dt_each(acc, [&](int i, int j, double v) {
+    if (R + i < n && C + j < n) {
+      double* p = M + (int64_t)(R + i) * n + C + j;
+      *p = sub ? *p - v : v;
+    }
+  });
+}
+
+// sum over m in [m0, m1) of x[m sx] y[m sy] from LDS, in eight interleaved partial sums combined in a fixed
+// order, so that the loads of eight terms are in flight together
+__device__ inline double dt_dot8(const double* x, int sx, const double* y, int sy, int m0, int m1) {
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int m = m0;
+  for (; m + 8 <= m1; m += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += x[(m + u) * sx] * y[(m + u) * sy];
+  for (int u = 0; m < m1; ++m, ++u) a[u] += x[m * sx] * y[m * sy];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// 1. Diagonal tile k0, by one wave: Cholesky in LDS by columns (lane l owns row l and sums its own dot products),
+// then the inverse D by rows of D (lane l owns column l).  With a single wave every barrier is nearly free; four
+// waves and 192 workgroup barriers took 113 us per tile.  L goes back to A (zero above the diagonal), D to Dk
+// (64 x 64, zero above the diagonal).
+__global__ __launch_bounds__(64) void k_dchol_diag(int n, int k0, double* A, double* Dk, int* bad) {
+  __shared__ double s[DT][DT + 1];
+  __shared__ double d[DT][DT + 1];
+  const int l = threadIdx.x;
+  for (int e = l; e < DT * DT; e += 64) {
+    const int i = e >> 6, j = e & 63;
+    double v = (i == j) ? 1.0 : 0.0;
+    if (k0 + i < n && k0 + j < n) v = A[(int64_t)(k0 + i) * n + k0 + j];
+    s[i][j] = v;
+  }
   __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (threadIdx.x == 0) {
-      double piv = s[j][j];
+  for (int j = 0; j < DT; ++j) {
+    const double acc = dt_dot8(&s[l][0], 1, &s[j][0], 1, 0, j);
+    if (l == j) {
+      double piv = s[j][j] - acc;
       if (!(piv > 0.0)) {
         *bad = 1;
         piv = 1.0;
@@ -2546,151 +2639,144 @@ __global__ __launch_bounds__(256) void k_chol_diag(int n, int k0, double* A, int
       s[j][j] = sqrt(piv);
     }
     __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < nb; i += 256) s[i][j] /= s[j][j];
-    __syncthreads();
-    for (int e = threadIdx.x; e < nb * nb; e += 256) {
-      const int i = e / nb, c = e % nb;
-      if (i > j && c > j && c <= i) s[i][c] -= s[i][j] * s[c][j];
-    }
+    if (l > j) s[l][j] = (s[l][j] - acc) / s[j][j];
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    const int i = e / nb, c = e % nb;
-    A[(int64_t)(k0 + i) * n + k0 + c] = (c <= i) ? s[i][c] : 0.0;
+  for (int i = 0; i < DT; ++i) {
+    const double acc = dt_dot8(&s[i][0], 1, &d[0][l], DT + 1, l, i);
+    d[i][l] = (i < l) ? 0.0 : (i == l) ? 1.0 / s[l][l] : -acc / s[i][i];
+    __syncthreads();
+  }
+  for (int e = l; e < DT * DT; e += 64) {
+    const int i = e >> 6, j = e & 63;
+    if (k0 + i < n && k0 + j < n) A[(int64_t)(k0 + i) * n + k0 + j] = (j <= i) ? s[i][j] : 0.0;
+    Dk[e] = d[i][j];
   }
 }
 
-// panel below the diagonal block: A[i, k0:k0+nb] <- A[i, k0:k0+nb] L_kk^{-T}; one thread per row
-__global__ __launch_bounds__(256) void k_chol_panel(int n, int k0, double* A) {
-  __shared__ double L[NB][NB + 1];
-  const int nb = min(NB, n - k0);
-  for (int e = threadIdx.x; e < nb * nb; e += 256) L[e / nb][e % nb] = A[(int64_t)(k0 + e / nb) * n + k0 + e % nb];
+// 1. Panel: tile (k0 + 64 (1 + blockIdx.x), k0) of A becomes A_ik D_k^T (each workgroup owns its tile's rows).
+__global__ __launch_bounds__(256) void k_dchol_panel(int n, int k0, double* A, const double* __restrict__ Dk) {
+  __shared__ double sa[DT][DT + 1];
+  __shared__ double sb[DT][DT + 1];
+  const int R = k0 + DT * (1 + blockIdx.x);
+  dt_load(sa, A, n, R, k0, true, false);   // Aop(i, k) = A_ik[i][k]
+  // Bop(k, j) = D_k[j][k]
+  for (int e = threadIdx.x; e < DT * DT; e += 256) sb[e & 63][e >> 6] = Dk[e];
   __syncthreads();
-  const int i = k0 + nb + blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  double x[NB];
-  double* row = A + (int64_t)i * n + k0;
-  for (int c = 0; c < nb; ++c) {
-    double v = row[c];
-    for (int m = 0; m < c; ++m) v -= x[m] * L[c][m];
-    x[c] = v / L[c][c];
-  }
-  for (int c = 0; c < nb; ++c) row[c] = x[c];
+  v4d acc[2][2];
+  dt_zero(acc);
+  dt_mfma(sa, sb, acc);
+  dt_store(acc, A, n, R, k0, false);
 }
 
-// C[i][j] -= sum_m A(i, m) B(m, j) on an m x n tile set, k = kk <= 64.
-// A(i,m) = a[i*lda + m] (or a[m*lda + i] if ta), B(m,j) = b[m*ldb + j] (or b[j*ldb + m] if tb).
-// 64x64 output tile per workgroup, 256 threads, 4x4 outputs per thread.
-__global__ __launch_bounds__(256) void k_gemm_sub(int M, int N, int kk, const double* __restrict__ a, int64_t lda, int ta,
-                                                  const double* __restrict__ b, int64_t ldb, int tb, double* c,
-                                                  int64_t ldc, int lower_only, int row0, int col0) {
-  __shared__ double sa[NB][NB + 1];
-  __shared__ double sb[NB][NB + 1];
-  const int ti = blockIdx.y * NB, tj = blockIdx.x * NB;
-  if (lower_only && tj > ti + NB - 1 + (row0 - col0)) return;
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int r = e / NB, m = e % NB;
-    double va = 0, vb = 0;
-    if (ti + r < M && m < kk) va = ta ? a[(int64_t)m * lda + ti + r] : a[(int64_t)(ti + r) * lda + m];
-    if (tj + r < N && m < kk) vb = tb ? b[(int64_t)(tj + r) * ldb + m] : b[(int64_t)m * ldb + tj + r];
-    sa[r][m] = va;
-    sb[r][m] = vb;  // sb[j][m] = B(m, j)
-  }
+// 1. Trailing update of the lower tiles (I, J), k0 < J <= I: A_IJ -= A_Ik A_Jk^T.  blockIdx.x enumerates the
+// pairs row by row (I = k0/64 + 1 + a, J = k0/64 + 1 + b, b <= a).
+__global__ __launch_bounds__(256) void k_dchol_update(int n, int k0, double* A) {
+  __shared__ double sa[DT][DT + 1];
+  __shared__ double sb[DT][DT + 1];
+  int a = (int)((sqrt(8.0 * blockIdx.x + 1.0) - 1.0) * 0.5);
+  while ((a + 1) * (a + 2) / 2 <= (int)blockIdx.x) ++a;
+  while (a * (a + 1) / 2 > (int)blockIdx.x) --a;
+  const int b = (int)blockIdx.x - a * (a + 1) / 2;
+  const int RI = k0 + DT * (1 + a), RJ = k0 + DT * (1 + b);
+  dt_load(sa, A, n, RI, k0, true, false);    // Aop(i, k) = A_Ik[i][k]
+  dt_load(sb, A, n, RJ, k0, true, false);    // Bop(k, j) = A_Jk[j][k]
   __syncthreads();
-  const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
-  double acc[4][4] = {};
-  for (int m = 0; m < kk; ++m) {
-    double av[4], bv[4];
-    for (int u = 0; u < 4; ++u) { av[u] = sa[tr + u][m]; bv[u] = sb[tc + u][m]; }
-    for (int u = 0; u < 4; ++u)
-      for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
-  }
-  for (int u = 0; u < 4; ++u)
-    for (int v = 0; v < 4; ++v) {
-      const int i = ti + tr + u, j = tj + tc + v;
-      if (i < M && j < N) c[(int64_t)i * ldc + j] -= acc[u][v];
-    }
+  v4d acc[2][2];
+  dt_zero(acc);
+  dt_mfma(sa, sb, acc);
+  dt_store(acc, A, n, RI, RJ, true);
 }
 
-// left triangular solves on all columns of X (n x n): forward L y = x (lower=1) or backward L^T y = x
-// within the diagonal block k0; one thread per column
-__global__ __launch_bounds__(256) void k_trsm_cols(int n, int k0, const double* __restrict__ Lm, double* X, int fwd) {
-  __shared__ double L[NB][NB + 1];
-  const int nb = min(NB, n - k0);
-  for (int e = threadIdx.x; e < nb * nb; e += 256) L[e / nb][e % nb] = Lm[(int64_t)(k0 + e / nb) * n + k0 + e % nb];
+// 2. Block row k of Y: tile (k, j) for j = blockIdx.x <= k: Y_kj <- D_k Y_kj, except Y_kk = D_k.
+__global__ __launch_bounds__(256) void k_dinv_row(int n, int kb, const double* __restrict__ Dk, double* Y) {
+  __shared__ double sa[DT][DT + 1];
+  __shared__ double sb[DT][DT + 1];
+  const int j = blockIdx.x, R = DT * kb, C = DT * j;
+  if (j == kb) {
+    for (int e = threadIdx.x; e < DT * DT; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      if (R + r < n && C + c < n) Y[(int64_t)(R + r) * n + C + c] = Dk[e];
+    }
+    return;
+  }
+  for (int e = threadIdx.x; e < DT * DT; e += 256) sa[e & 63][e >> 6] = Dk[e];   // Aop(i, k) = D_k[i][k]
+  dt_load(sb, Y, n, R, C, false, false);                                         // Bop(k, j) = Y_kj[k][j]
   __syncthreads();
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  double x[NB];
-  for (int r = 0; r < nb; ++r) x[r] = X[(int64_t)(k0 + r) * n + j];
-  if (fwd) {
-    for (int r = 0; r < nb; ++r) {
-      double v = x[r];
-      for (int m = 0; m < r; ++m) v -= L[r][m] * x[m];
-      x[r] = v / L[r][r];
-    }
-  } else {
-    for (int r = nb - 1; r >= 0; --r) {
-      double v = x[r];
-      for (int m = r + 1; m < nb; ++m) v -= L[m][r] * x[m];
-      x[r] = v / L[r][r];
-    }
-  }
-  for (int r = 0; r < nb; ++r) X[(int64_t)(k0 + r) * n + j] = x[r];
+  v4d acc[2][2];
+  dt_zero(acc);
+  dt_mfma(sa, sb, acc);
+  __syncthreads();
+  dt_store(acc, Y, n, R, C, false);
 }
 
-__global__ void k_identity(int n, double* X) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)n * n) return;
-  X[t] = (t / n == t % n) ? 1.0 : 0.0;
+// 2. Rows below block row k: tile (r, j), r = kb + 1 + blockIdx.x / (kb + 1), j = blockIdx.x % (kb + 1):
+// Y_rj -= L_rk Y_kj.
+__global__ __launch_bounds__(256) void k_dinv_update(int n, int kb, const double* __restrict__ L, double* Y) {
+  __shared__ double sa[DT][DT + 1];
+  __shared__ double sb[DT][DT + 1];
+  const int r = kb + 1 + (int)blockIdx.x / (kb + 1), j = (int)blockIdx.x % (kb + 1);
+  dt_load(sa, L, n, DT * r, DT * kb, true, false);   // Aop(i, k) = L_rk[i][k]
+  dt_load(sb, Y, n, DT * kb, DT * j, false, false);  // Bop(k, j) = Y_kj[k][j]
+  __syncthreads();
+  v4d acc[2][2];
+  dt_zero(acc);
+  dt_mfma(sa, sb, acc);
+  dt_store(acc, Y, n, DT * r, DT * j, true);
 }
 
-void dense_cholesky_inverse(int n, double* A, double* Inv, int* bad, hipStream_t s) {
-  const int nblk = (n + NB - 1) / NB;
-  for (int kb = 0; kb < nblk; ++kb) {
-    const int k0 = kb * NB;
-    const int nb = std::min(NB, n - k0);
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, n, k0, A, bad);
-    const int rest = n - k0 - nb;
-    if (rest > 0) {
-      hipLaunchKernelGGL(k_chol_panel, dim3((rest + 255) / 256), dim3(256), 0, s, n, k0, A);
-      // trailing update A22 -= L21 L21^T (full square; only the lower part is used later)
-      const int r0 = k0 + nb;
-      dim3 g((rest + NB - 1) / NB, (rest + NB - 1) / NB);
-      hipLaunchKernelGGL(k_gemm_sub, g, dim3(256), 0, s, rest, rest, nb, A + (int64_t)r0 * n + k0, (int64_t)n, 0,
-                         A + (int64_t)r0 * n + k0, (int64_t)n, 1, A + (int64_t)r0 * n + r0, (int64_t)n, 0, 0, 0);
+// 3. Upper tile (I, J) of A^{-1} = Y^T Y and its mirror; blockIdx.x enumerates the pairs I <= J row by row.
+__global__ __launch_bounds__(256) void k_dinv_gram(int n, int nt, const double* __restrict__ Y, double* Inv) {
+  __shared__ double sa[DT][DT + 1];
+  __shared__ double sb[DT][DT + 1];
+  int rem = (int)blockIdx.x, I = 0;
+  while (rem >= nt - I) {
+    rem -= nt - I;
+    ++I;
+  }
+  const int J = I + rem;
+  v4d acc[2][2];
+  dt_zero(acc);
+  for (int M = J; M < nt; ++M) {
+    dt_load(sa, Y, n, DT * M, DT * I, false, false);   // Aop(i, k) = Y_MI[k][i]
+    dt_load(sb, Y, n, DT * M, DT * J, false, false);   // Bop(k, j) = Y_MJ[k][j]
+    __syncthreads();
+    dt_mfma(sa, sb, acc);
+    __syncthreads();
+  }
+  dt_store(acc, Inv, n, DT * I, DT * J, false);
+  if (I != J) {  // the mirror tile, staged in LDS so that its rows are written contiguously
+    dt_each(acc, [&](int i, int j, double v) { sa[i][j] = v; });
+    __syncthreads();
+    for (int e = threadIdx.x; e < DT * DT; e += 256) {
+      const int r = e >> 6, c = e & 63;  // mirror row r = tile column r
+      if (DT * J + r < n && DT * I + c < n) Inv[(int64_t)(DT * J + r) * n + DT * I + c] = sa[c][r];
     }
   }
-  check_launch("cholesky");
-  // zero the strict upper triangle is not needed: the solves below only read the lower triangle
-  const int64_t nn = (int64_t)n * n;
-  hipLaunchKernelGGL(k_identity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, n, Inv);
-  // forward: L Y = I
-  for (int kb = 0; kb < nblk; ++kb) {
-    const int k0 = kb * NB;
-    const int nb = std::min(NB, n - k0);
-    hipLaunchKernelGGL(k_trsm_cols, dim3((n + 255) / 256), dim3(256), 0, s, n, k0, A, Inv, 1);
-    const int rest = n - k0 - nb;
-    if (rest > 0) {
-      dim3 g((n + NB - 1) / NB, (rest + NB - 1) / NB);
-      // Y[r0:, :] -= L[r0:, k0:k0+nb] Y[k0:k0+nb, :]
-      hipLaunchKernelGGL(k_gemm_sub, g, dim3(256), 0, s, rest, n, nb, A + (int64_t)(k0 + nb) * n + k0, (int64_t)n, 0,
-                         Inv + (int64_t)k0 * n, (int64_t)n, 0, Inv + (int64_t)(k0 + nb) * n, (int64_t)n, 0, 0, 0);
+}
+
+// ws: nt * 64 * 64 doubles (the inverted diagonal tiles); Y: n * n doubles of scratch
+void dense_cholesky_inverse(int n, double* A, double* Inv, double* ws, double* Y, int* bad, hipStream_t s) {
+  const int nt = (n + DT - 1) / DT;
+  for (int kb = 0; kb < nt; ++kb) {
+    const int k0 = kb * DT;
+    double* Dk = ws + (size_t)kb * DT * DT;
+    hipLaunchKernelGGL(k_dchol_diag, dim3(1), dim3(64), 0, s, n, k0, A, Dk, bad);
+    const int below = nt - kb - 1;
+    if (below > 0) {
+      hipLaunchKernelGGL(k_dchol_panel, dim3(below), dim3(256), 0, s, n, k0, A, Dk);
+      hipLaunchKernelGGL(k_dchol_update, dim3(below * (below + 1) / 2), dim3(256), 0, s, n, k0, A);
     }
   }
-  // backward: L^T X = Y
-  for (int kb = nblk - 1; kb >= 0; --kb) {
-    const int k0 = kb * NB;
-    hipLaunchKernelGGL(k_trsm_cols, dim3((n + 255) / 256), dim3(256), 0, s, n, k0, A, Inv, 0);
-    if (k0 > 0) {
-      const int nb = std::min(NB, n - k0);
-      dim3 g((n + NB - 1) / NB, (k0 + NB - 1) / NB);
-      // X[0:k0, :] -= L[k0:k0+nb, 0:k0]^T X[k0:k0+nb, :]
-      hipLaunchKernelGGL(k_gemm_sub, g, dim3(256), 0, s, k0, n, nb, A + (int64_t)k0 * n, (int64_t)n, 1,
-                         Inv + (int64_t)k0 * n, (int64_t)n, 0, Inv, (int64_t)n, 0, 0, 0);
-    }
+  check_launch("dense Cholesky");
+  hipMemsetAsync(Y, 0, (size_t)n * n * sizeof(double), s);
+  for (int kb = 0; kb < nt; ++kb) {
+    hipLaunchKernelGGL(k_dinv_row, dim3(kb + 1), dim3(256), 0, s, n, kb, ws + (size_t)kb * DT * DT, Y);
+    const int below = nt - kb - 1;
+    if (below > 0) hipLaunchKernelGGL(k_dinv_update, dim3(below * (kb + 1)), dim3(256), 0, s, n, kb, A, Y);
   }
-  check_launch("inverse");
+  hipLaunchKernelGGL(k_dinv_gram, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, n, nt, Y, Inv);
+  check_launch("dense inverse");
 }
 
 // =============================================================================================

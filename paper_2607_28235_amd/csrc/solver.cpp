@@ -748,7 +748,10 @@ void numeric_setup(HandleImpl& h, hipStream_t s) {
     launch_to_dense((int)D.nbox, B, D.bptr.p, D.bcol.p, D.val64.p, dense.p, s);
     dv.cinv.alloc((size_t)D.n * D.n);
     R3MG_HIP_CHECK(hipMemsetAsync(dv.flag.p, 0, sizeof(int), s));
-    dense_cholesky_inverse((int)D.n, dense.p, dv.cinv.p, dv.flag.p, s);
+    DBuf<double> tiles, ybuf;
+    tiles.alloc((size_t)((D.n + 63) / 64) * 64 * 64);
+    ybuf.alloc((size_t)D.n * D.n);
+    dense_cholesky_inverse((int)D.n, dense.p, dv.cinv.p, tiles.p, ybuf.p, dv.flag.p, s);
     int bad = 0;
     R3MG_HIP_CHECK(hipMemcpyAsync(&bad, dv.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
     R3MG_HIP_CHECK(hipStreamSynchronize(s));
