@@ -85,7 +85,8 @@ typedef struct {
                            multi-RHS solve [-1]; 0 = lanes-per-row CSR kernel (each lane all columns of its
                            nonzeros); 1 / 2 = local-column blocks with 1- / 2-byte positions (each block's distinct
                            columns gathered once per column group); 3 = CSR with the columns split over lanes (each
-                           nonzero's u row read as consecutive 16-byte pieces) */
+                           nonzero's u row read as consecutive 16-byte pieces); 4 = the same with each
+                           nonzero's value and column loaded once per row and shared by shuffles */
   int matrix_cache;     /* how the level kernels read matrix values: -1 = with ordinary loads where a level's
                            matrix stream is at most 128 MiB (it can stay in the caches across a smoothing sweep),
                            with nontemporal loads elsewhere [-1]; 0 = nontemporal loads on every level; 1 =

@@ -207,6 +207,11 @@ void launch_lanczos_start(int n, const int* perm, double* v, hipStream_t s);
 template <typename T>
 bool launch_level_split(const LevelOp<T>& op, int nr, int G, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
                         double c2, int flags, const int* skip, hipStream_t s);
+// The same product with each nonzero's value and column loaded once per row group and shared by shuffles (the G
+// lanes of a row load G consecutive entries at a time).  Same arguments and conditions as launch_level_split.
+template <typename T>
+bool launch_level_split2(const LevelOp<T>& op, int nr, int G, const T* u, const T* b, T* rho, T* x, T* dout,
+                         double c1, double c2, int flags, const int* skip, hipStream_t s);
 // Multi-right-hand-side form of the local-column kernel over the blocks of local geometry geom (0: 1-byte
 // positions, 256 distinct columns; 1: 2-byte, 1024): nr in {2, 4, 8, 16} (float: 4, 8, 16).  Same flags and
 // epilogue as launch_level.  Returns false (nothing launched) for an unsupported nr or geometry.

@@ -1021,6 +1021,96 @@ __global__ __launch_bounds__(256) void k_level_split(int n, int G, const int* __
   }
 }
 
+// The same product with each nonzero's value and column read once: the G lanes of a row load G consecutive
+// entries of the row at a time (one value and one column each, coalesced), then NG steps follow in which lane
+// (s, j) takes entry t S + s of that chunk from its owner lane by a shuffle and reads column group j of the
+// entry's u row (16 bytes).  Per G entries a lane issues 2 + NG loads instead of 3 per entry it owns, which
+// halves the address work of the gathers' texture-address unit.  Same epilogue as k_level_split.
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_level_split2(int n, int G, const int* __restrict__ ptr,
+                                                      const int* __restrict__ idx, const T* __restrict__ val,
+                                                      const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
+                                                      const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
+                                                      const int* __restrict__ skip, int nlog) {
+  constexpr int GW = 16 / (int)sizeof(T);
+  constexpr int NG = NR / GW;
+  static_assert(NR % GW == 0, "column groups");
+  typedef T VG __attribute__((ext_vector_type(GW)));
+  if (skip && *skip) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int rpb = 256 / G;
+  const int li = threadIdx.x % G;
+  const int gbase = (int)(threadIdx.x & 63) - li;  // the row group's first lane in the wave
+  const int j = li % NG, sv = li / NG, S = G / NG;
+  const int row = lb * rpb + threadIdx.x / G;
+  VG acc = (VG)0;
+  int s = 0, e = 0;
+  if (row < n) {
+    s = ptr[row];
+    e = ptr[row + 1];
+  }
+  // every lane of a row group runs the same chunks, so a shuffle only ever reads an active lane of its group
+  for (int c0 = s; c0 < e; c0 += G) {
+    const int p = c0 + li;
+    const T a_l = p < e ? val[p] : (T)0;
+    const int i_l = p < e ? idx[p] : 0;
+#pragma unroll
+    for (int t = 0; t < NG; ++t) {
+      const int src = gbase + t * S + sv;
+      const T a = __shfl(a_l, src, 64);
+      const int64_t ci = (int64_t)__shfl(i_l, src, 64);
+      const VG uv = *reinterpret_cast<const VG*>(u + ci * NR + j * GW);
+      acc += a * uv;
+    }
+  }
+  for (int off = NG; off < G; off <<= 1)
+#pragma unroll
+    for (int w = 0; w < GW; ++w) acc[w] += __shfl_xor(acc[w], off, 64);
+  if (sv == 0 && row < n) {
+    const int64_t o = (int64_t)row * NR + j * GW;
+    if (flags & F_PLAIN) {
+      *reinterpret_cast<VG*>(rho + o) = acc;
+    } else {
+      const VG old = (flags & F_RHO_FROM_B) ? *reinterpret_cast<const VG*>(b + o) : *reinterpret_cast<VG*>(rho + o);
+      const VG r = old - acc;
+      if (flags & F_RHO_STORE) *reinterpret_cast<VG*>(rho + o) = r;
+      const VG ui = *reinterpret_cast<const VG*>(u + o);
+      if (flags & F_X_ASSIGN)
+        *reinterpret_cast<VG*>(x + o) = ui;
+      else if (flags & F_X_ADD)
+        *reinterpret_cast<VG*>(x + o) = *reinterpret_cast<VG*>(x + o) + ui;
+      if (flags & F_D_OUT) *reinterpret_cast<VG*>(dout + o) = c1 * ui + (c2 * dinv[row]) * r;
+    }
+  }
+}
+
+template <typename T>
+bool launch_level_split2(const LevelOp<T>& op, int nr, int G, const T* u, const T* b, T* rho, T* x, T* dout,
+                         double c1, double c2, int flags, const int* skip, hipStream_t s) {
+  constexpr int GW = 16 / (int)sizeof(T);
+  if (nr % GW != 0 || G < nr / GW || G > 64 || (G & (G - 1)) != 0 || op.blk != 1) return false;
+  const int rpb = 256 / G;
+  const int nlog = (op.n + rpb - 1) / rpb;
+  if (nlog == 0) return true;
+#define R3MG_SPLIT2(NRV)                                                                                          \
+  hipLaunchKernelGGL((k_level_split2<T, NRV>), dim3(xcd_grid(nlog)), dim3(256), 0, s, op.n, G, op.ptr, op.idx,   \
+                     op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip, nlog)
+  switch (nr) {
+    case 4: R3MG_SPLIT2(4); break;
+    case 8: R3MG_SPLIT2(8); break;
+    case 16: R3MG_SPLIT2(16); break;
+    default: return false;
+  }
+#undef R3MG_SPLIT2
+  check_launch("k_level_split2");
+  return true;
+}
+template bool launch_level_split2<float>(const LevelOp<float>&, int, int, const float*, const float*, float*, float*,
+                                         float*, double, double, int, const int*, hipStream_t);
+template bool launch_level_split2<double>(const LevelOp<double>&, int, int, const double*, const double*, double*,
+                                          double*, double*, double, double, int, const int*, hipStream_t);
+
 template <typename T>
 bool launch_level_split(const LevelOp<T>& op, int nr, int G, const T* u, const T* b, T* rho, T* x, T* dout, double c1,
                         double c2, int flags, const int* skip, hipStream_t s) {

@@ -194,9 +194,20 @@ LevelOp<T> level_op(Ctx& c, int l) {
 }
 
 // Tuned multi-RHS kernel codes, per (level, nr, precision): G in 1..64 = lanes-per-row CSR/block-row kernel with
-// G lanes; kCodeSplit + G = column-split CSR kernel with G lanes; -1 - g = local-column kernel over local
-// geometry g.  Level -1 holds PCG's float64 q = A p (with its dot products).
+// G lanes; kCodeSplit + G = column-split CSR kernel with G lanes; kCodeSplit2 + G = the column-split kernel with
+// shared entry loads; -1 - g = local-column kernel over local geometry g.  Level -1 holds PCG's float64 q = A p
+// (with its dot products).
 constexpr int kCodeSplit = 100;
+constexpr int kCodeSplit2 = 200;
+
+// the column-split kernel a code >= kCodeSplit names
+template <typename T>
+static bool launch_split_code(int code, const LevelOp<T>& op, int nr, const T* u, const T* b, T* rho, T* x, T* dout,
+                              double c1, double c2, int flags, const int* skip, hipStream_t s) {
+  if (code >= kCodeSplit2)
+    return launch_level_split2<T>(op, nr, code - kCodeSplit2, u, b, rho, x, dout, c1, c2, flags, skip, s);
+  return launch_level_split<T>(op, nr, code - kCodeSplit, u, b, rho, x, dout, c1, c2, flags, skip, s);
+}
 
 // Kernel that applies level l for nr right-hand sides in element size esz: the row-block kernel on the fine
 // level for one right-hand side, a block-row kernel on coarse levels whose block rows fit LDS, the
@@ -301,7 +312,7 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
           if (it->second >= kCodeSplit) {  // fine level: column-split CSR kernel
             op.ptr = D.rowptr.p;
             op.idx = D.col.p;
-            if (!launch_level_split<T>(op, nr, it->second - kCodeSplit, u, b, rho, x, dout, c1, c2, flags, skip, s))
+            if (!launch_split_code<T>(it->second, op, nr, u, b, rho, x, dout, c1, c2, flags, skip, s))
               throw std::runtime_error("multi-RHS column-split kernel: unsupported shape");
             break;
           }
@@ -446,6 +457,15 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
           });
           consider(kCodeSplit + G, ms, ok, true);
         }
+      if (forced == -1 || forced == 4)
+        for (int G = 1; G <= 64; G <<= 1) {
+          bool ok = true;
+          const float ms = time_launches(s, 5, [&] {
+            ok = launch_level_split2<T>(opc, nr, G, vbuf<T>(D.dA), vbuf<T>(D.b), vbuf<T>(D.rho), vbuf<T>(D.x),
+                                        vbuf<T>(D.dB), 0.0, 0.0, fl, nullptr, s);
+          });
+          consider(kCodeSplit2 + G, ms, ok, true);
+        }
     }
     dv.tuned[{l, tag}] = bestCode;
     R3MG_HIP_CHECK(hipMemsetAsync(D.x.p, 0, D.x.n, s));
@@ -500,6 +520,19 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
         if (ok && ms < best) {
           best = ms;
           bestCode = kCodeSplit + G;
+        }
+      }
+    if (forced == -1 || forced == 4)
+      for (int G = 1; G <= 64; G <<= 1) {
+        bool ok = true;
+        const float ms = time_launches(s, 5, [&] {
+          ok = launch_level_split2<double>(op, nr, G, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN,
+                                           nullptr, s);
+          if (ok) launch_pcg_dot_alpha((int)c.an.n, nr, dv.pp.p, dv.pq.p, dv.partials.p, st0, s);
+        });
+        if (ok && ms < best) {
+          best = ms;
+          bestCode = kCodeSplit2 + G;
         }
       }
     dv.tuned[{-1, nr * 2}] = bestCode;
@@ -1174,8 +1207,8 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s, int part
           ok = launch_level_local_mr<double>(-1 - it->second, D0.fb[kLocalFirst - 1 - it->second], op64, NR, dv.pp.p,
                                              nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
         else
-          ok = launch_level_split<double>(op64, NR, it->second - kCodeSplit, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr,
-                                          0.0, 0.0, F_PLAIN, skip, s);
+          ok = launch_split_code<double>(it->second, op64, NR, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0,
+                                         F_PLAIN, skip, s);
         if (!ok) throw std::runtime_error("multi-RHS fine-level kernel: unsupported shape");
         launch_pcg_dot_alpha(n, NR, dv.pp.p, dv.pq.p, dv.partials.p, st, s);
       } else {

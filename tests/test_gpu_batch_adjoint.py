@@ -39,11 +39,11 @@ def small3d_q3():
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
-@pytest.mark.parametrize("kernel", [-1, 0, 1, 2, 3])
+@pytest.mark.parametrize("kernel", [-1, 0, 1, 2, 3, 4])
 def test_sixteen_rhs_block_pcg(small3d_q3, fp32, kernel):
     """16 right-hand sides in lockstep match the oracle per column, with the fine-level multi-RHS kernel chosen by
     timing (-1) or forced: lanes-per-row CSR (0), local-column blocks with 1-byte (1) or 2-byte (2) positions,
-    CSR with the columns split over lanes (3)."""
+    CSR with the columns split over lanes (3), the same with shared entry loads (4)."""
     import paper_2607_28235_amd as P
     w = small3d_q3
     prob = w.problem

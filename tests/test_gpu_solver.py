@@ -261,7 +261,7 @@ def test_pcg_fp32_vcycle(name, request):
     assert _rel(xs, x_tight) < 1e-9
 
 
-@pytest.mark.parametrize("kernel", [-1, 0, 1, 2, 3])
+@pytest.mark.parametrize("kernel", [-1, 0, 1, 2, 3, 4])
 def test_multi_rhs_matches_single(small2d, kernel):
     c = small2d
     _case(f"multi-rhs 3 columns small2d kernel={kernel}")
