@@ -83,9 +83,13 @@ typedef struct {
                            choice when no row has more than 256 nonzeros. */
   int multi_rhs_kernel; /* fine-level kernel for several right-hand sides: -1 = the fastest timed at the first
                            multi-RHS solve [-1]; 0 = lanes-per-row CSR kernel (each lane all columns of its
-                           nonzeros); 1 / 2 = local-column blocks with 1- / 2-byte positions (each block's distinct
-                           columns gathered once per column group); 3 = CSR with the columns split over lanes (each
-                           nonzero's u row read as consecutive 16-byte pieces); 4 = the same with each
+                           nonzeros); 1 / 2 = row blocks staged in LDS (values, 2-byte column positions and
+                           u at the block's distinct columns; each thread sums one row's 16-byte column chunk):
+                           one persistent workgroup per compute unit that loads the next block while summing
+                           one (1), or one workgroup per block (2), for 16 float or 8 / 16 double right-hand
+                           sides (other counts: the lanes kernel); 3 = CSR with the
+                           columns split over lanes (each nonzero's u row read as consecutive 16-byte pieces);
+                           4 = the same with each
                            nonzero's value and column loaded once per row and shared by shuffles */
   int matrix_cache;     /* how the level kernels read matrix values: -1 = with ordinary loads where a level's
                            matrix stream is at most 128 MiB (it can stay in the caches across a smoothing sweep),

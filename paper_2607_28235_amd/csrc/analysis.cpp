@@ -549,22 +549,21 @@ static void encode_csr_blocks(Analysis& an) {
   }
 }
 
-// Local-column row blocks of geometry g over a CSR pattern: rows are taken greedily (within independent row
-// segments) while the block stays within `rows` rows, `cap` - 3 nonzeros and `ucap` distinct columns; the
+// Local-column row blocks over a CSR pattern: rows are taken greedily (within independent row segments) while
+// the block stays within `rows` rows, `cap` nonzeros and `ucap` distinct columns; the
 // distinct columns are listed in ascending order and every nonzero stores the position of its column in the
 // list.  A single row beyond the limits forms a block of its own with its full column list (the kernel reads
-// such a block through the CSR columns).
-static void encode_local_blocks(const int32_t* rowptr, const int32_t* col, int64_t n, int64_t ncol, int g,
-                                LocalBlocks& out) {
+// such a block through the CSR columns).  Positions take `ib` bytes; `pad` zero entries follow the last one.
+static void encode_local_blocks(const int32_t* rowptr, const int32_t* col, int64_t n, int64_t ncol, int cap,
+                                int rows, int ucap, int ib, int pad, LocalBlocks& out) {
   const int64_t nnz = rowptr[n];
-  const int cap = kLocalCap[g] - 3, rows = kLocalRows[g], ucap = kLocalUcap[g], ib = kLocalIdxBytes[g];
   const int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(256, n / 4096));
   struct Seg {
     std::vector<int32_t> ends, ucnt, ucol;
   };
   std::vector<Seg> segs((size_t)nseg);
   std::vector<uint8_t>& lidx = out.lidx;
-  lidx.assign((size_t)(nnz + kFinePad) * ib, 0);  // padding: the vector kernel's 4-byte loads
+  lidx.assign((size_t)(nnz + pad) * ib, 0);  // padding: the vector kernels' wide loads
   parallel_for(nseg, [&](int64_t sg) {
     static thread_local std::vector<uint8_t> mark;
     static thread_local std::vector<int32_t> pos;
@@ -622,9 +621,29 @@ static void encode_local_blocks(const int32_t* rowptr, const int32_t* col, int64
   }
 }
 
+// the blocks of local geometry g (the 16-byte loads of the block kernels start up to 3 entries before a block)
+static void encode_local_geom(const int32_t* rowptr, const int32_t* col, int64_t n, int g, LocalBlocks& out) {
+  encode_local_blocks(rowptr, col, n, n, kLocalCap[g] - 3, kLocalRows[g], kLocalUcap[g], kLocalIdxBytes[g], kFinePad,
+                      out);
+}
+
+void encode_mr_blocks(const Analysis& an, int cls, MrHost& out) {
+  encode_local_blocks(an.rowptr.data(), an.col.data(), an.n, an.n, kMrCap[cls], kMrRows[cls], kMrUcap[cls], 2, kMrPad,
+                      out.lb);
+  const int64_t nrb = (int64_t)out.lb.rb.size() - 1;
+  out.ord.assign((size_t)an.n, 0);
+  parallel_for(nrb, [&](int64_t k) {
+    const int32_t r0 = out.lb.rb[k], r1 = out.lb.rb[k + 1];
+    for (int32_t r = r0; r < r1; ++r) out.ord[r] = r;
+    std::stable_sort(out.ord.begin() + r0, out.ord.begin() + r1, [&](int32_t a, int32_t b) {
+      return an.rowptr[a + 1] - an.rowptr[a] > an.rowptr[b + 1] - an.rowptr[b];
+    });
+  });
+}
+
 void encode_fine(Analysis& an) {
   encode_csr_blocks(an);
-  for (int g = 0; g <= kLocalGeoms; ++g) encode_local_blocks(an.rowptr.data(), an.col.data(), an.n, an.n, g, an.loc[g]);
+  for (int g = 0; g <= kLocalGeoms; ++g) encode_local_geom(an.rowptr.data(), an.col.data(), an.n, g, an.loc[g]);
   // agglomerated levels with narrow block rows (the 2D hierarchies): CSR row pointers and 1-byte local blocks
   const int L = an.nlevels() - 1;
   const int B = an.B;
@@ -647,12 +666,12 @@ void encode_fine(Analysis& an) {
       }
     });
     H.rowptr[H.n] = (int32_t)nnz;
-    encode_local_blocks(H.rowptr.data(), col.data(), H.n, H.n, 0, H.loc);
+    encode_local_geom(H.rowptr.data(), col.data(), H.n, 0, H.loc);
     // FP32 V-cycle: where the 2048-nonzero blocks need a second, mostly idle round of resident workgroups and
     // 3072-nonzero blocks fit in one, the level takes the larger blocks (the same row sums in the same order)
     if (an.opt.vcycle_fp32 && (int64_t)H.loc.rb.size() - 1 > kResidentBlocks) {
       LocalBlocks l4;
-      encode_local_blocks(H.rowptr.data(), col.data(), H.n, H.n, 4, l4);
+      encode_local_geom(H.rowptr.data(), col.data(), H.n, 4, l4);
       if ((int64_t)l4.rb.size() - 1 <= kResidentBlocks) {
         H.loc = std::move(l4);
         H.loc_geom = 4;

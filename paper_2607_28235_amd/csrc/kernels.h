@@ -212,12 +212,44 @@ bool launch_level_split(const LevelOp<T>& op, int nr, int G, const T* u, const T
 template <typename T>
 bool launch_level_split2(const LevelOp<T>& op, int nr, int G, const T* u, const T* b, T* rho, T* x, T* dout,
                          double c1, double c2, int flags, const int* skip, hipStream_t s);
-// Multi-right-hand-side form of the local-column kernel over the blocks of local geometry geom (0: 1-byte
-// positions, 256 distinct columns; 1: 2-byte, 1024): nr in {2, 4, 8, 16} (float: 4, 8, 16).  Same flags and
-// epilogue as launch_level.  Returns false (nothing launched) for an unsupported nr or geometry.
+// Fine-level blocks of the LDS-staged multi-right-hand-side kernel (device pointers), one set per staging class.
+// A block is a run of consecutive rows rb[b] .. rb[b+1]; its distinct columns are ucol[ubp[b] .. ubp[b+1])
+// (ascending); every nonzero stores the 2-byte position of its column in that list (lidx, kMrPad zero entries
+// after the last); ord[rb[b] + i] is the block's i-th row in order of decreasing length.  A block beyond the
+// class's staging capacity holds a single row, read through the CSR columns.
+struct MrBlocks {
+  int nrb = 0;
+  int cls = -1;
+  const int* rb = nullptr;
+  const int* ubp = nullptr;
+  const int* ucol = nullptr;
+  const uint16_t* lidx = nullptr;
+  const int* ord = nullptr;
+  const int* meta = nullptr;  // per block (first row, first nonzero, first distinct column, 0), nrb + 1 records
+};
+// Staging classes (element type, right-hand sides): 0 = (float, 16), 1 = (double, 16), 2 = (double, 8).  Per
+// block at most kMrCap nonzeros, kMrUcap distinct columns and kMrRows rows (256 threads / 16-byte chunks per
+// column); the LDS of one workgroup (values, positions, u at the distinct columns) stays within 80 KiB, so two
+// workgroups share a compute unit.
+constexpr int kMrClasses = 3;
+constexpr int kMrCap[kMrClasses] = {6144, 3072, 3840};
+constexpr int kMrUcap[kMrClasses] = {640, 384, 640};
+constexpr int kMrRows[kMrClasses] = {64, 32, 64};
+constexpr int kMrPad = 8;
+// staging class of nr right-hand sides in element size esz (-1: none)
+inline int mr_class(int nr, int esz) {
+  if (esz == 4) return nr == 16 ? 0 : -1;
+  return nr == 16 ? 1 : nr == 8 ? 2 : -1;
+}
+// Multi-right-hand-side fine-level kernel over the blocks of staging class mr_class(nr, sizeof(T)): per block,
+// values, positions and u at the distinct columns are staged in LDS; each row is summed in ascending entry order by
+// the threads of its 16-byte column chunks, rows taking the row slots in order of decreasing length.  pipelined:
+// one persistent workgroup per compute unit with two LDS stages, the next block's loads in flight while a block is
+// summed; else one workgroup per block.  Same flags and epilogue as launch_level.  Returns false (nothing
+// launched) when nr has no staging class or mb belongs to another class.
 template <typename T>
-bool launch_level_local_mr(int geom, const FineBlocks& fb, const LevelOp<T>& op, int nr, const T* u, const T* b,
-                           T* rho, T* x, T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s);
+bool launch_level_lmr(const MrBlocks& mb, const LevelOp<T>& op, int nr, bool pipelined, const T* u, const T* b,
+                      T* rho, T* x, T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s);
 // partial sums of w_i x_i y_i (w may be null) -> partials (returns count)
 int launch_dot(int64_t n, const double* w, const double* x, const double* y, double* partials, hipStream_t s);
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);   // y = a x + b y

@@ -1138,152 +1138,394 @@ template bool launch_level_split<float>(const LevelOp<float>&, int, int, const f
 template bool launch_level_split<double>(const LevelOp<double>&, int, int, const double*, const double*, double*,
                                          double*, double*, double, double, int, const int*, hipStream_t);
 
-// Multi-right-hand-side local-column kernel (NR columns, interleaved n x NR vectors).  One workgroup per
-// local-column row block: the block's values and column positions are staged in LDS once; then for each group of
-// GW = 16 / sizeof(T) columns, u at the block's distinct columns is gathered with one 16-byte load per column
-// into LDS, each row is summed by TPR = 256 / RPB lanes (lane s takes the row's entries s, s + TPR, ...; the lane
-// sums are combined by a butterfly) and lane 0 of the row applies the epilogue of k_level to the GW columns with
-// 16-byte loads and stores.  A block with more than UCAP distinct columns is a single row, summed by the whole
-// workgroup through the CSR columns.
-template <typename T, int NR, typename IX, int CAP, int RPB, int UCAP>
-__global__ __launch_bounds__(256) void k_level_local_mr(int nrb, const int* __restrict__ rb,
-                                                        const int* __restrict__ ubp, const int* __restrict__ ucol,
-                                                        const IX* __restrict__ lidx, const int* __restrict__ ptr,
-                                                        const int* __restrict__ idx, const T* __restrict__ val,
-                                                        const T* __restrict__ u, const T* __restrict__ b, T* rho,
-                                                        T* x, const T* __restrict__ dinv, T* dout, T c1, T c2,
-                                                        int flags, const int* __restrict__ skip) {
-  constexpr int GW = 16 / (int)sizeof(T);
-  constexpr int NG = NR / GW;
-  constexpr int TPR = 256 / RPB;
-  static_assert(NR % GW == 0, "column groups");
-  typedef T VG __attribute__((ext_vector_type(GW)));
+// Sum over the entries [k, z) of one row from LDS: values svs[k], column positions sps[k] into the staged u rows
+// usq[p * CH] (16-byte chunks).  Single entries up to a multiple of 4 from vb (the block's aligned start); then
+// groups of 8 (two aligned LDS words of 4 values and of 4 positions each), the next group's values and positions
+// read together with the current group's u rows, so that one LDS round trip serves 8 entries; then 4-entry groups
+// and single entries.  The entries are added in ascending order.
+template <typename T, typename VT, int CH>
+__device__ __forceinline__ VT lmr_row_sum(const T* svs, const uint16_t* sps, const VT* usq, int vb, int k, int z) {
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  typedef unsigned short S4 __attribute__((ext_vector_type(4)));
+  VT t = (VT)0;
+  for (; k < z && ((k - vb) & 3); ++k) t += svs[k] * usq[sps[k] * CH];
+  if (k + 8 <= z) {
+    T4 a0 = *reinterpret_cast<const T4*>(svs + k), a1 = *reinterpret_cast<const T4*>(svs + k + 4);
+    S4 p0 = *reinterpret_cast<const S4*>(sps + k), p1 = *reinterpret_cast<const S4*>(sps + k + 4);
+    for (;;) {
+      const VT w0 = usq[p0.x * CH], w1 = usq[p0.y * CH], w2 = usq[p0.z * CH], w3 = usq[p0.w * CH];
+      const VT w4 = usq[p1.x * CH], w5 = usq[p1.y * CH], w6 = usq[p1.z * CH], w7 = usq[p1.w * CH];
+      const T4 c0 = a0, c1 = a1;
+      k += 8;
+      const bool more = k + 8 <= z;
+      if (more) {
+        a0 = *reinterpret_cast<const T4*>(svs + k);
+        a1 = *reinterpret_cast<const T4*>(svs + k + 4);
+        p0 = *reinterpret_cast<const S4*>(sps + k);
+        p1 = *reinterpret_cast<const S4*>(sps + k + 4);
+      }
+      t += c0.x * w0;
+      t += c0.y * w1;
+      t += c0.z * w2;
+      t += c0.w * w3;
+      t += c1.x * w4;
+      t += c1.y * w5;
+      t += c1.z * w6;
+      t += c1.w * w7;
+      if (!more) break;
+    }
+  }
+  for (; k + 4 <= z; k += 4) {
+    const T4 a = *reinterpret_cast<const T4*>(svs + k);
+    const S4 p = *reinterpret_cast<const S4*>(sps + k);
+    const VT w0 = usq[p.x * CH], w1 = usq[p.y * CH], w2 = usq[p.z * CH], w3 = usq[p.w * CH];
+    t += a.x * w0;
+    t += a.y * w1;
+    t += a.z * w2;
+    t += a.w * w3;
+  }
+  for (; k < z; ++k) t += svs[k] * usq[sps[k] * CH];
+  return t;
+}
+
+// j-th of the SPLIT cut points of a row's entries [ka, kz) (j = 0: ka, j = SPLIT: kz): the j / SPLIT point rounded
+// down to a multiple of 4 entries from vb, so that every part but the first starts aligned
+template <int SPLIT>
+__device__ __forceinline__ int lmr_cut(int vb, int ka, int kz, int j) {
+  if (j <= 0) return ka;
+  if (j >= SPLIT) return kz;
+  const int c = ka + (int)((int64_t)(kz - ka) * j / SPLIT);
+  return min(max(vb + ((c - vb) & ~3), ka), kz);
+}
+
+// epilogue of the fused level kernel for one 16-byte chunk (offset o) of row `row`
+template <typename T, typename VT>
+__device__ __forceinline__ void lmr_epilogue(int row, int64_t o, VT t, const T* __restrict__ u,
+                                             const T* __restrict__ b, T* rho, T* x, const T* __restrict__ dinv,
+                                             T* dout, T c1, T c2, int flags) {
+  if (flags & F_PLAIN) {
+    *reinterpret_cast<VT*>(rho + o) = t;
+    return;
+  }
+  const VT old = (flags & F_RHO_FROM_B) ? *reinterpret_cast<const VT*>(b + o) : *reinterpret_cast<VT*>(rho + o);
+  const VT r = old - t;
+  if (flags & F_RHO_STORE) *reinterpret_cast<VT*>(rho + o) = r;
+  const VT ui = *reinterpret_cast<const VT*>(u + o);
+  if (flags & F_X_ASSIGN)
+    *reinterpret_cast<VT*>(x + o) = ui;
+  else if (flags & F_X_ADD)
+    *reinterpret_cast<VT*>(x + o) = *reinterpret_cast<VT*>(x + o) + ui;
+  if (flags & F_D_OUT) *reinterpret_cast<VT*>(dout + o) = c1 * ui + (c2 * dinv[row]) * r;
+}
+
+// Multi-right-hand-side fine-level kernel with LDS staging (NR columns, interleaved n x NR vectors).  One
+// workgroup of TPB = 512 threads per block of consecutive rows (MrBlocks); with at most 80 KiB of LDS, two share
+// a compute unit (16 waves).  The block's values and 2-byte column positions and u at its distinct columns
+// (CH = NR sizeof(T) / 16 chunks of 16 bytes per column) are staged in LDS with 16-byte loads (nontemporal for the
+// matrix), all issued before the first LDS store, so that a workgroup keeps ~60 KB of loads in flight; the column
+// list carries one padding entry after its last (read by a block without columns).  Thread t then owns chunk
+// q = t % CH of half h = (t / CH) % 2 of row slot t / (2 CH): half 0 sums the row's entries below an aligned
+// midpoint, half 1 the rest (each in ascending order, from LDS), the two half sums are added across lanes, and
+// half 0 applies the epilogue of k_level to its chunk.  With ord, rows take the slots in order of decreasing
+// length, so that the rows of a wave have similar lengths.  A block beyond the staging capacity holds one row,
+// which the workgroup sums from global memory: phase j takes the entries j, j + TPB / CH, ..., and the phase sums
+// are added in phase order.
+template <typename T, int NR, int CAP, int UCAP>
+__global__ __launch_bounds__(512) void k_level_lmr(int nrb, const int* __restrict__ rb, const int* __restrict__ ubp,
+                                                   const int* __restrict__ ucol, const uint16_t* __restrict__ lidx,
+                                                   const int* __restrict__ ord, const int* __restrict__ ptr,
+                                                   const int* __restrict__ idx, const T* __restrict__ val,
+                                                   const T* __restrict__ u, const T* __restrict__ b, T* rho, T* x,
+                                                   const T* __restrict__ dinv, T* dout, T c1, T c2, int flags,
+                                                   const int* __restrict__ skip) {
+  constexpr int TPB = 512;
+  constexpr int VW = 16 / (int)sizeof(T);  // elements per 16-byte chunk
+  constexpr int CH = NR / VW;              // chunks per column
+  constexpr int RMAX = 256 / CH;           // row slots
+  constexpr int NPH = TPB / CH;            // phases of the single-row path
+  constexpr int NVC = CAP / VW + 2;        // value chunks of CAP entries from a 16-byte aligned start
+  constexpr int NPC = CAP / 8 + 2;         // position chunks (8 per 16 bytes)
+  constexpr int NV = (NVC + TPB - 1) / TPB, NP = (NPC + TPB - 1) / TPB, NU = (UCAP * CH + TPB - 1) / TPB;
+  static_assert(NR % VW == 0 && 64 % (2 * CH) == 0 && CAP % 8 == 0 && UCAP * CH >= TPB, "staging geometry");
+  typedef T VT __attribute__((ext_vector_type(VW)));
+  typedef unsigned int U4 __attribute__((ext_vector_type(4)));
   if (skip && *skip) return;
   const int lb = xcd_block(nrb);
   if (lb < 0) return;
-  __shared__ T sval[CAP];
-  __shared__ IX spos[CAP];
-  __shared__ VG us[UCAP];
-  __shared__ VG shr[4];
+  __shared__ VT sv[NVC + 1];  // the last entry of each array takes the stores of threads beyond the block
+  __shared__ U4 sp[NPC + 1];
+  __shared__ VT us[UCAP * CH + 1];
+  const int tid = threadIdx.x;
+  const int q = tid % CH, h = (tid / CH) & 1, slot = tid / (2 * CH);
   const int r0 = rb[lb], r1 = rb[lb + 1];
   const int e0 = ptr[r0], e1 = ptr[r1];
-  const int nz = e1 - e0;
   const int u0 = ubp[lb], nu = ubp[lb + 1] - u0;
-  const bool staged = nu <= UCAP;
-  const int rl = threadIdx.x / TPR, sub = threadIdx.x % TPR;
-  const int row = r0 + rl;
-  int rs = 0, re = 0;
-  if (staged) {
-    constexpr int EPT = CAP / 256;
-    T vv[EPT];
-    IX pp[EPT];
+  const int vb = e0 & ~(VW - 1), pb = e0 & ~7;
+  const int nvc = (e1 - vb + VW - 1) / VW, npc = (e1 - pb + 7) / 8;
+  VT t = (VT)0;
+  int row = -1;
+  if (nu <= UCAP && nvc <= NVC && npc <= NPC) {  // uniform over the workgroup
+    // the row of this thread's slot and its entry range, loaded first so that they overlap the staging
+    const int nrow = r1 - r0;
+    const int rr = ord ? ord[r0 + min(slot, nrow - 1)] : r0 + min(slot, nrow - 1);
+    const int ka = ptr[rr], kz = ptr[rr + 1];
+    // every thread issues all its loads before the first LDS store, with no divergent branch around them (a load
+    // under one is waited for at the branch's end): indices beyond the block are clamped to its last chunk, and
+    // threads beyond it store into a spare LDS entry
+    VT vv[NV];
+    U4 pv[NP];
+    int uc[NU];
+    VT uv[NU];
+    const int vlast = max(nvc - 1, 0), plast = max(npc - 1, 0), ulast = max(nu * CH - 1, 0);
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) {
-      const int e = threadIdx.x + 256 * m;
-      if (e < nz) {
-        vv[m] = __builtin_nontemporal_load(val + e0 + e);
-        pp[m] = __builtin_nontemporal_load(lidx + e0 + e);
-      }
+    for (int m = 0; m < NV; ++m)
+      vv[m] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(val + vb) + min(tid + TPB * m, vlast));
+#pragma unroll
+    for (int m = 0; m < NP; ++m)
+      pv[m] = __builtin_nontemporal_load(reinterpret_cast<const U4*>(lidx + pb) + min(tid + TPB * m, plast));
+#pragma unroll
+    for (int m = 0; m < NU; ++m) uc[m] = ucol[u0 + min(tid + TPB * m, ulast) / CH];
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      const int i = min(tid + TPB * m, ulast);
+      uv[m] = *reinterpret_cast<const VT*>(u + (int64_t)uc[m] * NR + (i % CH) * VW);
     }
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) {
-      const int e = threadIdx.x + 256 * m;
-      if (e < nz) {
-        sval[e] = vv[m];
-        spos[e] = pp[m];
-      }
+    for (int m = 0; m < NV; ++m) {
+      const int i = tid + TPB * m;
+      sv[i < nvc ? i : NVC] = vv[m];
     }
-    if (row < r1) {
-      rs = ptr[row] - e0;
-      re = ptr[row + 1] - e0;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      const int i = tid + TPB * m;
+      sp[i < npc ? i : NPC] = pv[m];
+    }
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      const int i = tid + TPB * m;
+      us[i < nu * CH ? i : UCAP * CH] = uv[m];
+    }
+    if (slot < nrow) row = rr;
+    asm volatile("" ::"v"(ka), "v"(kz));  // keeps the entry-range loads ahead of the barrier
+    __syncthreads();
+    if (row >= 0) {
+      t = lmr_row_sum<T, VT, CH>(reinterpret_cast<const T*>(sv) - vb, reinterpret_cast<const uint16_t*>(sp) - pb,
+                                 us + q, vb, lmr_cut<2>(vb, ka, kz, h), lmr_cut<2>(vb, ka, kz, h + 1));
+    }
+#pragma unroll
+    for (int w = 0; w < VW; ++w) t[w] += __shfl_xor(t[w], CH, 64);  // half sums of the row (same on both halves)
+  } else {  // one row beyond the staging capacity (r1 == r0 + 1)
+    const int ph = tid / CH;
+    VT acc = (VT)0;
+    for (int e = e0 + ph; e < e1; e += NPH)
+      acc += val[e] * *reinterpret_cast<const VT*>(u + (int64_t)idx[e] * NR + q * VW);
+    us[tid] = acc;
+    __syncthreads();
+    if (ph == 0) {
+      for (int j = 0; j < NPH; ++j) t += us[j * CH + q];
+      row = r0;
     }
   }
-  for (int g = 0; g < NG; ++g) {
-    VG t;
-    int trow = -1;
-    if (staged) {
-      for (int c = threadIdx.x; c < nu; c += 256)
-        us[c] = *reinterpret_cast<const VG*>(u + (int64_t)ucol[u0 + c] * NR + g * GW);
-      __syncthreads();
-      VG acc = (VG)0;
-      for (int kk = rs + sub; kk < re; kk += TPR) acc += sval[kk] * us[spos[kk]];
+  if (row >= 0 && h == 0) lmr_epilogue<T, VT>(row, (int64_t)row * NR + q * VW, t, u, b, rho, x, dinv, dout, c1, c2, flags);
+}
+
+// Pipelined form of k_level_lmr: one persistent workgroup of 1024 threads per compute unit walks a contiguous run of blocks (runs
+// of neighbouring blocks stay on one XCD, whose L2 then serves the columns they share) with two LDS stages.  While
+// block i is summed from one stage, block i+1's values, positions, row-pointer and row-order slices and u at its
+// distinct columns arrive in the other by direct global-to-LDS loads (no registers held; the loads of a wave fill
+// 64 consecutive 16-byte or 4-byte LDS slots), so the HBM stream never waits for the sums.  Block records
+// (first row, first nonzero, first distinct column) are read two blocks ahead and the distinct-column indices one
+// block ahead.  The two stages alternate in a loop unrolled by two, so that each LDS access names a fixed stage.
+// Row order and epilogue are those of k_level_lmr; each row is summed in four aligned parts (16 waves per compute
+// unit), added across lanes.
+template <typename T, int NR, int CAP, int UCAP>
+struct LmrStage {
+  static constexpr int VW = 16 / (int)sizeof(T), CH = NR / VW, RMAX = 256 / CH;
+  static constexpr int NVC = CAP / VW + 2, NPC = CAP / 8 + 2, NUC = UCAP * CH;
+  typedef T VT __attribute__((ext_vector_type(VW)));
+  typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+  VT sv[NVC];
+  U4 sp[NPC];
+  VT us[NUC];
+  int rp[RMAX + 1];
+  int ord[RMAX];
+};
+
+__device__ __forceinline__ void lds_dma16(const void* g, void* l) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
+                                   (__attribute__((address_space(3))) void*)l, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_dma4(const void* g, void* l) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
+                                   (__attribute__((address_space(3))) void*)l, 4, 0, 0);
+}
+
+template <typename T, int NR, int CAP, int UCAP>
+__global__ __launch_bounds__(1024) void k_level_lmr_pipe(int nrb, int nwg, const int4* __restrict__ meta,
+                                                         const int* __restrict__ ucol, const uint16_t* __restrict__ lidx,
+                                                         const int* __restrict__ ord, const int* __restrict__ ptr,
+                                                         const int* __restrict__ idx, const T* __restrict__ val,
+                                                         const T* __restrict__ u, const T* __restrict__ b, T* rho,
+                                                         T* x, const T* __restrict__ dinv, T* dout, T c1, T c2,
+                                                         int flags, const int* __restrict__ skip) {
+  typedef LmrStage<T, NR, CAP, UCAP> S;
+  typedef typename S::VT VT;
+  constexpr int TPB = 1024, SPLIT = 4;
+  constexpr int VW = S::VW, CH = S::CH, RMAX = S::RMAX, NVC = S::NVC, NPC = S::NPC, NUC = S::NUC;
+  constexpr int NU = (NUC + TPB - 1) / TPB, NPH = TPB / CH;
+  static_assert(RMAX <= 64 && RMAX * CH * SPLIT == TPB && NUC >= TPB, "stage geometry");
+  if (skip && *skip) return;
+  const int lw = xcd_block(nwg);
+  if (lw < 0) return;
+  const int bb = (int)((int64_t)lw * nrb / nwg), be = (int)((int64_t)(lw + 1) * nrb / nwg);
+  if (bb >= be) return;
+  __shared__ S st[2];
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const int q = tid % CH, h = (tid / CH) % SPLIT, slot = tid / (CH * SPLIT);
+
+  auto staged = [&](int4 m0, int4 m1) {
+    const int vb = m0.y & ~(VW - 1), pb = m0.y & ~7;
+    return m1.z - m0.z <= UCAP && (m1.y - vb + VW - 1) / VW <= NVC && (m1.y - pb + 7) / 8 <= NPC;
+  };
+  auto load_uc = [&](int4 m0, int4 m1, int* uc) {
+    const int last = max((m1.z - m0.z) * CH - 1, 0);
 #pragma unroll
-      for (int off = TPR / 2; off > 0; off >>= 1)
+    for (int m = 0; m < NU; ++m) uc[m] = ucol[m0.z + min(tid + TPB * m, last) / CH];
+  };
+  // direct loads of block (m0, m1) into stage D
+  auto issue = [&](S& D, int4 m0, int4 m1, const int* uc) {
+    if (!staged(m0, m1)) return;
+    const int vb = m0.y & ~(VW - 1), pb = m0.y & ~7;
+    const int nvc = (m1.y - vb + VW - 1) / VW, npc = (m1.y - pb + 7) / 8, nuc = (m1.z - m0.z) * CH;
+    const int nrow = m1.x - m0.x;
+    for (int base = wv * 64; base < nvc; base += TPB)
+      if (base + ln < nvc) lds_dma16(val + vb + (int64_t)(base + ln) * VW, &D.sv[base]);
+    for (int base = wv * 64; base < npc; base += TPB)
+      if (base + ln < npc) lds_dma16(lidx + pb + (int64_t)(base + ln) * 8, &D.sp[base]);
 #pragma unroll
-        for (int w = 0; w < GW; ++w) acc[w] += __shfl_xor(acc[w], off, 64);
-      t = acc;
-      if (sub == 0 && row < r1) trow = row;
-      __syncthreads();  // us is restaged by the next group
-    } else {  // one long row
-      VG acc = (VG)0;
-      for (int e = e0 + threadIdx.x; e < e1; e += 256)
-        acc += val[e] * *reinterpret_cast<const VG*>(u + (int64_t)idx[e] * NR + g * GW);
-#pragma unroll
-      for (int w = 0; w < GW; ++w) acc[w] = wave_sum(acc[w], 64);
-      if ((threadIdx.x & 63) == 0) shr[threadIdx.x >> 6] = acc;
-      __syncthreads();
-      t = (shr[0] + shr[1]) + (shr[2] + shr[3]);
-      if (threadIdx.x == 0) trow = r0;
-      __syncthreads();
+    for (int m = 0; m < NU; ++m) {
+      const int base = m * TPB + wv * 64;
+      if (base < nuc && base + ln < nuc)
+        lds_dma16(u + (int64_t)uc[m] * NR + ((base + ln) % CH) * VW, &D.us[base]);
     }
-    if (trow >= 0) {
-      const int64_t o = (int64_t)trow * NR + g * GW;
-      if (flags & F_PLAIN) {
-        *reinterpret_cast<VG*>(rho + o) = t;
-      } else {
-        const VG old = (flags & F_RHO_FROM_B) ? *reinterpret_cast<const VG*>(b + o) : *reinterpret_cast<VG*>(rho + o);
-        const VG r = old - t;
-        if (flags & F_RHO_STORE) *reinterpret_cast<VG*>(rho + o) = r;
-        const VG ui = *reinterpret_cast<const VG*>(u + o);
-        if (flags & F_X_ASSIGN)
-          *reinterpret_cast<VG*>(x + o) = ui;
-        else if (flags & F_X_ADD)
-          *reinterpret_cast<VG*>(x + o) = *reinterpret_cast<VG*>(x + o) + ui;
-        if (flags & F_D_OUT) *reinterpret_cast<VG*>(dout + o) = c1 * ui + (c2 * dinv[trow]) * r;
+    if (wv < 2 && wv * 64 + ln <= nrow) lds_dma4(ptr + m0.x + wv * 64 + ln, &D.rp[wv * 64]);
+    if (ord && wv == 2 && ln < nrow) lds_dma4(ord + m0.x + ln, &D.ord[0]);
+  };
+  // row sums of block (m0, m1) from stage D (part h of SPLIT per thread, parts added across lanes), then the
+  // epilogue
+  auto compute = [&](S& D, int4 m0, int4 m1) {
+    VT t = (VT)0;
+    int row = -1;
+    if (staged(m0, m1)) {
+      const int nrow = m1.x - m0.x;
+      if (slot < nrow) {
+        const int lr = ord ? D.ord[slot] - m0.x : slot;
+        row = m0.x + lr;
+        const int vb = m0.y & ~(VW - 1), pb = m0.y & ~7;
+        const int ka = D.rp[lr], kz = D.rp[lr + 1];
+        t = lmr_row_sum<T, VT, CH>(reinterpret_cast<const T*>(D.sv) - vb,
+                                   reinterpret_cast<const uint16_t*>(D.sp) - pb, D.us + q, vb,
+                                   lmr_cut<SPLIT>(vb, ka, kz, h), lmr_cut<SPLIT>(vb, ka, kz, h + 1));
+      }
+#pragma unroll
+      for (int w = 0; w < VW; ++w) {
+        t[w] += __shfl_xor(t[w], CH, 64);
+        t[w] += __shfl_xor(t[w], 2 * CH, 64);
+      }
+    } else {  // one row beyond the stage capacity: summed from global memory, phase sums added in phase order
+      const int ph = tid / CH;
+      VT acc = (VT)0;
+      for (int e = m0.y + ph; e < m1.y; e += NPH)
+        acc += val[e] * *reinterpret_cast<const VT*>(u + (int64_t)idx[e] * NR + q * VW);
+      D.us[tid] = acc;
+      __syncthreads();
+      if (ph == 0) {  // the next step's barrier precedes any reuse of the stage
+        for (int j = 0; j < NPH; ++j) t += D.us[j * CH + q];
+        row = m0.x;
       }
     }
+    if (row >= 0 && h == 0)
+      lmr_epilogue<T, VT>(row, (int64_t)row * NR + q * VW, t, u, b, rho, x, dinv, dout, c1, c2, flags);
+  };
+
+  int uc[NU];
+  int4 m0 = meta[bb], m1 = meta[bb + 1];
+  load_uc(m0, m1, uc);
+  issue(st[0], m0, m1, uc);
+  int4 m2 = bb + 2 <= nrb ? meta[bb + 2] : m1;
+  if (bb + 1 < be) load_uc(m1, m2, uc);
+  // block bi in stage A: wait for its loads, start block bi + 1's into stage B, prefetch for bi + 2, sum bi
+  auto step = [&](S& A, S& B, int bi) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (bi + 1 < be) issue(B, m1, m2, uc);
+    const int4 m3 = bi + 3 <= nrb ? meta[bi + 3] : m2;
+    if (bi + 2 < be) load_uc(m2, m3, uc);
+    compute(A, m0, m1);
+    m0 = m1;
+    m1 = m2;
+    m2 = m3;
+  };
+  for (int bi = bb; bi < be; bi += 2) {
+    step(st[0], st[1], bi);
+    if (bi + 1 < be) step(st[1], st[0], bi + 1);
   }
 }
 
-template <typename T, int NR, typename IX, int CAP, int RPB, int UCAP>
-static void launch_local_mr_t(const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
+template <typename T, int NR, int CLS>
+static void launch_lmr_t(const MrBlocks& mb, const LevelOp<T>& op, const int* ord, const T* u, const T* b, T* rho,
+                         T* x, T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL((k_level_lmr<T, NR, kMrCap[CLS], kMrUcap[CLS]>), dim3(xcd_grid(mb.nrb)), dim3(512), 0, s, mb.nrb,
+                     mb.rb, mb.ubp, mb.ucol, mb.lidx, ord, op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1,
+                     (T)c2, flags, skip);
+}
+
+template <typename T, int NR, int CLS>
+static void launch_lmr_pipe_t(const MrBlocks& mb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
                               T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s) {
-  hipLaunchKernelGGL((k_level_local_mr<T, NR, IX, CAP, RPB, UCAP>), dim3(xcd_grid(fb.nrb)), dim3(256), 0, s, fb.nrb,
-                     fb.rb, fb.ubp, fb.ucol, static_cast<const IX*>(fb.lidx), op.ptr, op.idx, op.val, u, b, rho, x,
-                     op.dinv, dout, (T)c1, (T)c2, flags, skip);
+  static const int cus = [] {
+    int d = 0, v = 0;
+    if (hipGetDevice(&d) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess)
+      v = 256;
+    return std::max(v, 1);
+  }();
+  const int nwg = std::min(mb.nrb, cus);
+  hipLaunchKernelGGL((k_level_lmr_pipe<T, NR, kMrCap[CLS], kMrUcap[CLS]>), dim3(xcd_grid(nwg)), dim3(1024), 0, s,
+                     mb.nrb, nwg, reinterpret_cast<const int4*>(mb.meta), mb.ucol, mb.lidx, mb.ord, op.ptr, op.idx,
+                     op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip);
 }
 
 template <typename T>
-bool launch_level_local_mr(int geom, const FineBlocks& fb, const LevelOp<T>& op, int nr, const T* u, const T* b,
-                           T* rho, T* x, T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s) {
-  constexpr int GW = 16 / (int)sizeof(T);
-  if (fb.nrb == 0 || nr % GW != 0 || (geom != 0 && geom != 1)) return false;
-#define R3MG_MR(NRV)                                                                                              \
-  do {                                                                                                            \
-    if (geom == 0)                                                                                                \
-      launch_local_mr_t<T, (NRV < GW ? GW : NRV), uint8_t, 2048, 64, 256>(fb, op, u, b, rho, x, dout, c1, c2, flags, \
-                                                                          skip, s);                                \
-    else                                                                                                          \
-      launch_local_mr_t<T, (NRV < GW ? GW : NRV), uint16_t, 4096, 64, 1024>(fb, op, u, b, rho, x, dout, c1, c2,    \
-                                                                            flags, skip, s);                       \
-  } while (0)
-  switch (nr) {
-    case 2: R3MG_MR(2); break;
-    case 4: R3MG_MR(4); break;
-    case 8: R3MG_MR(8); break;
-    case 16: R3MG_MR(16); break;
-    default: return false;
+bool launch_level_lmr(const MrBlocks& mb, const LevelOp<T>& op, int nr, bool pipelined, const T* u, const T* b,
+                      T* rho, T* x, T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s) {
+  const int cls = mr_class(nr, (int)sizeof(T));
+  if (cls < 0 || mb.cls != cls || mb.nrb <= 0 || op.blk != 1) return false;
+  if constexpr (sizeof(T) == 4) {
+    if (pipelined)
+      launch_lmr_pipe_t<float, 16, 0>(mb, op, u, b, rho, x, dout, c1, c2, flags, skip, s);
+    else
+      launch_lmr_t<float, 16, 0>(mb, op, mb.ord, u, b, rho, x, dout, c1, c2, flags, skip, s);
+  } else {
+    if (cls == 1) {
+      if (pipelined)
+        launch_lmr_pipe_t<double, 16, 1>(mb, op, u, b, rho, x, dout, c1, c2, flags, skip, s);
+      else
+        launch_lmr_t<double, 16, 1>(mb, op, mb.ord, u, b, rho, x, dout, c1, c2, flags, skip, s);
+    } else {
+      if (pipelined)
+        launch_lmr_pipe_t<double, 8, 2>(mb, op, u, b, rho, x, dout, c1, c2, flags, skip, s);
+      else
+        launch_lmr_t<double, 8, 2>(mb, op, mb.ord, u, b, rho, x, dout, c1, c2, flags, skip, s);
+    }
   }
-#undef R3MG_MR
-  check_launch("k_level_local_mr");
+  check_launch(pipelined ? "k_level_lmr_pipe" : "k_level_lmr");
   return true;
 }
-template bool launch_level_local_mr<float>(int, const FineBlocks&, const LevelOp<float>&, int, const float*,
-                                           const float*, float*, float*, float*, double, double, int, const int*,
-                                           hipStream_t);
-template bool launch_level_local_mr<double>(int, const FineBlocks&, const LevelOp<double>&, int, const double*,
-                                            const double*, double*, double*, double*, double, double, int, const int*,
-                                            hipStream_t);
+template bool launch_level_lmr<float>(const MrBlocks&, const LevelOp<float>&, int, bool, const float*, const float*,
+                                      float*, float*, float*, double, double, int, const int*, hipStream_t);
+template bool launch_level_lmr<double>(const MrBlocks&, const LevelOp<double>&, int, bool, const double*,
+                                       const double*, double*, double*, double*, double, double, int, const int*,
+                                       hipStream_t);
 
 
 

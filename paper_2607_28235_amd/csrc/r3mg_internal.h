@@ -88,6 +88,11 @@ struct LocalBlocks {  // local-column row blocks of a CSR pattern (device form: 
   std::vector<uint8_t> lidx;  // 1 or 2 bytes per nonzero, plus kFinePad padding entries
 };
 
+struct MrHost {  // blocks of one staging class of the multi-right-hand-side kernel (device form: MrBlocks)
+  LocalBlocks lb;
+  std::vector<int32_t> ord;  // per block, its rows in order of decreasing row length
+};
+
 struct HostLevel {           // agglomerated level l >= 1 (boxes of the R-tree at `depth`)
   int depth = 0;
   int64_t nbox = 0;
@@ -144,6 +149,8 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
                                   const int32_t* cells = nullptr, int64_t ncells = 0, int nloc = 0);
 
 void encode_fine(Analysis& an);
+// blocks of staging class cls (kMrCap / kMrRows / kMrUcap) of the multi-right-hand-side kernel over the fine level
+void encode_mr_blocks(const Analysis& an, int cls, MrHost& out);
 
 // bisection R-tree (Section 3, Section 4 point-based agglomeration); offsets[k] per depth k
 void bisection_rtree(const double* coords, int64_t n, int d, int leaf, int& depth, std::vector<int32_t>& order,
@@ -208,6 +215,11 @@ struct DevLevel {
   DBuf<uint8_t> lidx[kLocalGeomsAll];
   DBuf<int32_t> lmeta[kLocalGeomsAll];  // per-block records of the local-column blocks (FineBlocks::meta)
   FineBlocks fb[kStreamShapes];  // l = 0: row blocks of every kernel shape
+  // l = 0: blocks of the LDS-staged multi-right-hand-side kernel per staging class, built at the first
+  // multi-right-hand-side tuning that needs them
+  DBuf<int32_t> mrb[kMrClasses], mubp[kMrClasses], mucol[kMrClasses], mord[kMrClasses], mmeta[kMrClasses];
+  DBuf<uint16_t> mlidx[kMrClasses];
+  MrBlocks mr[kMrClasses];
   double shape_bytes[kStreamShapes] = {};  // algorithmic bytes of one application with each shape
   int shape = 0;        // l = 0: kernel shape chosen by timing at set-up
   int shape64 = 0;      // l = 0: shape of the float64 operator PCG applies (with a float64 V-cycle: shape)

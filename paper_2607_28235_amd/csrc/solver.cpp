@@ -195,8 +195,8 @@ LevelOp<T> level_op(Ctx& c, int l) {
 
 // Tuned multi-RHS kernel codes, per (level, nr, precision): G in 1..64 = lanes-per-row CSR/block-row kernel with
 // G lanes; kCodeSplit + G = column-split CSR kernel with G lanes; kCodeSplit2 + G = the column-split kernel with
-// shared entry loads; -1 - g = local-column kernel over local geometry g.  Level -1 holds PCG's float64 q = A p
-// (with its dot products).
+// shared entry loads; -1 / -2 = LDS-staged kernel, pipelined / one workgroup per block.  Level -1 holds PCG's
+// float64 q = A p (with its dot products).
 constexpr int kCodeSplit = 100;
 constexpr int kCodeSplit2 = 200;
 
@@ -245,6 +245,43 @@ std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int 
     case LevelKernel::BlockRow: return std::string("k_level_blockrow<") + t + ">";
     default: return std::string("k_level<") + t + ">";
   }
+}
+
+// Blocks of staging class cls of the LDS-staged multi-RHS kernel over the fine CSR level, encoded on the host and
+// uploaded the first time a tuning needs them (false: no staging class, or the fine level is matrix-free)
+static bool ensure_mr_blocks(Ctx& c, int cls, hipStream_t s) {
+  DevLevel& D = c.dv.lv[0];
+  if (cls < 0 || D.mf) return false;
+  if (D.mr[cls].nrb > 0) return true;
+  MrHost h;
+  encode_mr_blocks(c.an, cls, h);
+  D.mrb[cls].upload(h.lb.rb, s);
+  D.mubp[cls].upload(h.lb.ubp, s);
+  h.lb.ucol.push_back(0);  // padding entry: the kernel's clamped staging loads of a block without columns
+  D.mucol[cls].upload(h.lb.ucol, s);
+  D.mord[cls].upload(h.ord, s);
+  {
+    std::vector<int32_t> meta(h.lb.rb.size() * 4, 0);
+    for (size_t k = 0; k < h.lb.rb.size(); ++k) {
+      meta[4 * k] = h.lb.rb[k];
+      meta[4 * k + 1] = c.an.rowptr[h.lb.rb[k]];
+      meta[4 * k + 2] = h.lb.ubp[k];
+    }
+    D.mmeta[cls].upload(meta, s);
+    R3MG_HIP_CHECK(hipStreamSynchronize(s));
+  }
+  D.mlidx[cls].upload(reinterpret_cast<const uint16_t*>(h.lb.lidx.data()), h.lb.lidx.size() / 2, s);
+  R3MG_HIP_CHECK(hipStreamSynchronize(s));  // the host vectors are released on return
+  MrBlocks& m = D.mr[cls];
+  m.cls = cls;
+  m.rb = D.mrb[cls].p;
+  m.ubp = D.mubp[cls].p;
+  m.ucol = D.mucol[cls].p;
+  m.lidx = D.mlidx[cls].p;
+  m.ord = D.mord[cls].p;
+  m.meta = D.mmeta[cls].p;
+  m.nrb = (int)h.lb.rb.size() - 1;
+  return true;
 }
 
 // F_KEEP when the level's matrix stream in precision T is small enough to stay in the caches
@@ -300,13 +337,13 @@ void apply_level(Ctx& c, int l, int nr, const T* u, const T* b, T* rho, T* x, T*
       if (nr > 1) {
         auto it = c.dv.tuned.find({l, nr * 2 + (sizeof(T) == 4 ? 1 : 0)});
         if (it != c.dv.tuned.end()) {
-          if (it->second < 0) {  // fine level: local-column multi-RHS kernel
-            const int g = -1 - it->second;
+          if (it->second < 0) {  // fine level: LDS-staged multi-RHS kernel (-1: pipelined, -2: block per workgroup)
             op.ptr = D.rowptr.p;
             op.idx = D.col.p;
-            if (!launch_level_local_mr<T>(g, D.fb[kLocalFirst + g], op, nr, u, b, rho, x, dout, c1, c2, flags, skip,
-                                          s))
-              throw std::runtime_error("multi-RHS local-column kernel: unsupported block");
+            const int cls = mr_class(nr, (int)sizeof(T));
+            if (cls < 0 || !launch_level_lmr<T>(D.mr[cls], op, nr, it->second == -1, u, b, rho, x, dout, c1, c2,
+                                                flags | keep_flag<T>(D), skip, s))
+              throw std::runtime_error("multi-RHS LDS-staged kernel: no blocks for this shape");
             break;
           }
           if (it->second >= kCodeSplit) {  // fine level: column-split CSR kernel
@@ -411,7 +448,7 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
   Device& dv = c.dv;
   const int L = c.an.nlevels() - 1;
   const int tag = nr * 2 + (sizeof(T) == 4 ? 1 : 0);
-  const int forced = c.an.opt.multi_rhs_kernel;  // -1 timed, 0 lanes, 1 / 2 local-column, 3 column-split
+  const int forced = c.an.opt.multi_rhs_kernel;  // -1 timed, 0 lanes, 1 / 2 LDS-staged, 3 / 4 column-split
   const int fl = F_RHO_STORE | F_X_ADD | F_D_OUT;
   for (int l = 0; l < L; ++l) {
     if (dv.tuned.count({l, tag})) continue;
@@ -439,12 +476,13 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
       LevelOp<T> opc = op;
       opc.ptr = D.rowptr.p;
       opc.idx = D.col.p;
+      const int cls = mr_class(nr, (int)sizeof(T));
       for (int g = 0; g < 2; ++g) {
-        if (forced != -1 && forced != 1 + g) continue;
+        if ((forced != -1 && forced != 1 + g) || !ensure_mr_blocks(c, cls, s)) continue;
         bool ok = true;
         const float ms = time_launches(s, 5, [&] {
-          ok = launch_level_local_mr<T>(g, D.fb[kLocalFirst + g], opc, nr, vbuf<T>(D.dA), vbuf<T>(D.b), vbuf<T>(D.rho),
-                                        vbuf<T>(D.x), vbuf<T>(D.dB), 0.0, 0.0, fl, nullptr, s);
+          ok = launch_level_lmr<T>(D.mr[cls], opc, nr, g == 0, vbuf<T>(D.dA), vbuf<T>(D.b), vbuf<T>(D.rho),
+                                   vbuf<T>(D.x), vbuf<T>(D.dB), 0.0, 0.0, fl | keep_flag<T>(D), nullptr, s);
         });
         consider(-1 - g, ms, ok, true);
       }
@@ -496,12 +534,13 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
     op.ptr = D0.rowptr.p;
     op.idx = D0.col.p;
     need_partials(dv, (int64_t)kPcgBlocks * 2 * nr);
+    const int cls = mr_class(nr, 8);
     for (int g = 0; g < 2; ++g) {
-      if (forced != -1 && forced != 1 + g) continue;
+      if ((forced != -1 && forced != 1 + g) || !ensure_mr_blocks(c, cls, s)) continue;
       bool ok = true;
       const float ms = time_launches(s, 5, [&] {
-        ok = launch_level_local_mr<double>(g, D0.fb[kLocalFirst + g], op, nr, dv.pp.p, nullptr, dv.pq.p, nullptr,
-                                           nullptr, 0.0, 0.0, F_PLAIN, nullptr, s);
+        ok = launch_level_lmr<double>(D0.mr[cls], op, nr, g == 0, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0,
+                                      0.0, F_PLAIN | D0.keep64, nullptr, s);
         if (ok) launch_pcg_dot_alpha((int)c.an.n, nr, dv.pp.p, dv.pq.p, dv.partials.p, st0, s);
       });
       if (ok && ms < best) {
@@ -1203,9 +1242,11 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s, int part
         op64.ptr = D0.rowptr.p;
         op64.idx = D0.col.p;
         bool ok;
-        if (it->second < 0)
-          ok = launch_level_local_mr<double>(-1 - it->second, D0.fb[kLocalFirst - 1 - it->second], op64, NR, dv.pp.p,
-                                             nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
+        if (it->second < 0) {
+          const int cls = mr_class(NR, 8);
+          ok = cls >= 0 && launch_level_lmr<double>(D0.mr[cls], op64, NR, it->second == -1, dv.pp.p, nullptr, dv.pq.p,
+                                                    nullptr, nullptr, 0.0, 0.0, F_PLAIN | D0.keep64, skip, s);
+        }
         else
           ok = launch_split_code<double>(it->second, op64, NR, dv.pp.p, nullptr, dv.pq.p, nullptr, nullptr, 0.0, 0.0,
                                          F_PLAIN, skip, s);

@@ -42,8 +42,8 @@ def small3d_q3():
 @pytest.mark.parametrize("kernel", [-1, 0, 1, 2, 3, 4])
 def test_sixteen_rhs_block_pcg(small3d_q3, fp32, kernel):
     """16 right-hand sides in lockstep match the oracle per column, with the fine-level multi-RHS kernel chosen by
-    timing (-1) or forced: lanes-per-row CSR (0), local-column blocks with 1-byte (1) or 2-byte (2) positions,
-    CSR with the columns split over lanes (3), the same with shared entry loads (4)."""
+    timing (-1) or forced: lanes-per-row CSR (0), row blocks staged in LDS with length-sorted (1) or ordered (2)
+    rows, CSR with the columns split over lanes (3), the same with shared entry loads (4)."""
     import paper_2607_28235_amd as P
     w = small3d_q3
     prob = w.problem
@@ -66,6 +66,65 @@ def test_sixteen_rhs_block_pcg(small3d_q3, fp32, kernel):
     X2 = torch.zeros_like(X)
     iters2, _, _ = h.pcg(_t(w.rhs), X2, rtol=1e-10, maxit=200)
     assert np.array_equal(iters, iters2) and torch.equal(X, X2)
+
+
+@pytest.fixture(scope="module")
+def q3_long_row():
+    """The Q3 8^3 cube plus delta sum_j (e_i - e_j)(e_i - e_j)^T over 700 seeded free DoFs j (a graph Laplacian
+    term: the matrix stays symmetric positive definite).  Row i then has more distinct columns than any staging
+    class of the LDS-staged kernel holds (at most 640), so that kernel sums it from global memory."""
+    _need_gpu()
+    import scipy.sparse as sp
+    w = F.workload(4, scale=8)
+    prob = w.problem
+    A = prob.scipy().tocsr()
+    free = np.flatnonzero(~prob.boundary)
+    g = np.random.default_rng(77)
+    i = int(free[len(free) // 2])
+    S = g.choice(free[free != i], size=700, replace=False)
+    delta = 1e-2 * float(A[i, i])
+    rows = np.concatenate([[i], S, np.full(len(S), i), S])
+    cols = np.concatenate([[i], S, S, np.full(len(S), i)])
+    vals = np.concatenate([[delta * len(S)], np.full(len(S), delta), np.full(2 * len(S), -delta)])
+    A2 = (A + sp.csr_matrix((vals, (rows, cols)), shape=A.shape)).tocsr()
+    A2.sort_indices()
+    assert A2.indptr[i + 1] - A2.indptr[i] > 700
+    ho = O.build_hierarchy(prob.coords, A2, coarse_degree=2, leaf_size=256, max_coarse_dofs=600)
+    return prob, A2, ho
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("nrhs,fp32", [(16, 1), (16, 0), (8, 0)])
+def test_lds_staged_kernel_with_long_row(q3_long_row, kernel, nrhs, fp32):
+    """The LDS-staged multi-RHS kernel in each staging class ((float, 16), (double, 16), (double, 8)) with
+    length-sorted (1) or ordered (2) rows, on a matrix with one row beyond every staging capacity: V-cycles per
+    column against the oracle's, and a lockstep PCG solve (whose float64 operator also takes the kernel) against
+    the oracle's solution."""
+    import paper_2607_28235_amd as P
+    prob, A2, ho = q3_long_row
+    _case(f"LDS-staged kernel long row kernel={kernel} nrhs={nrhs} fp32={fp32} n={prob.n}")
+    o = P.Options(dim=3, coarse_degree=2, leaf_size=256, max_coarse_dofs=600, vcycle_fp32=fp32,
+                  multi_rhs_kernel=kernel)
+    h = P.Hierarchy(prob.coords, A2.indptr.astype(np.int64), A2.indices.astype(np.int32), A2.data, o)
+    g = np.random.default_rng(300 + nrhs)
+    R = g.standard_normal((nrhs, prob.n))
+    R[:, ho.constrained] = 0.0
+    Z = torch.zeros(nrhs, prob.n, dtype=torch.float64, device="cuda")
+    h.vcycle(_t(R), Z)
+    torch.cuda.synchronize()
+    Zh = Z.cpu().numpy()
+    for j in range(nrhs):
+        assert _rel(Zh[j], O.vcycle(ho, R[j])) < (2e-5 if fp32 else 1e-11), j
+    X = torch.zeros(nrhs, prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok = h.pcg(_t(R), X, rtol=1e-10, maxit=200)
+    assert ok
+    Xh = X.cpu().numpy()
+    for j in (0, nrhs - 1):
+        xo, ko, _, _, _ = O.pcg(ho, R[j], rtol=1e-13)
+        assert _rel(Xh[j], xo) < 1e-9, j
+    res = R - (A2 @ Xh.T).T
+    assert np.all(np.linalg.norm(res, axis=1) <= 1.01e-10 * np.linalg.norm(R, axis=1))
+    h.close()
 
 
 def test_uneven_group_in_one_graph():
