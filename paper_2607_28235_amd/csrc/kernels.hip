@@ -1198,24 +1198,36 @@ __device__ __forceinline__ int lmr_cut(int vb, int ka, int kz, int j) {
   return min(max(vb + ((c - vb) & ~3), ka), kz);
 }
 
-// epilogue of the fused level kernel for one 16-byte chunk (offset o) of row `row`
+// Epilogue of the fused level kernel for one 16-byte chunk (offset o) of one row, in two parts: the operands it
+// reads (loaded before the row sum, so that their latency overlaps it), then, from the row sum t, the values it
+// writes: rn (-> rho), xn (-> x), dn (-> dout).
 template <typename T, typename VT>
-__device__ __forceinline__ void lmr_epilogue(int row, int64_t o, VT t, const T* __restrict__ u,
-                                             const T* __restrict__ b, T* rho, T* x, const T* __restrict__ dinv,
-                                             T* dout, T c1, T c2, int flags) {
+__device__ __forceinline__ void lmr_epi_load(int row, int64_t o, const T* __restrict__ u, const T* __restrict__ b,
+                                             const T* rho, const T* x, const T* __restrict__ dinv, int flags, VT& old,
+                                             VT& ui, VT& xo, T& di) {
+  if (flags & F_PLAIN) return;
+  // no branch around the loads (a load under one is waited for at its end, and with it every older load, such as
+  // the next block's staging): x and dinv are read whether or not the flags use them
+  const T* ob = (flags & F_RHO_FROM_B) ? b : rho;
+  old = *reinterpret_cast<const VT*>(ob + o);
+  ui = *reinterpret_cast<const VT*>(u + o);
+  xo = *reinterpret_cast<const VT*>(x + o);
+  di = dinv[row];
+}
+template <typename T, typename VT>
+__device__ __forceinline__ void lmr_epi_store(int64_t o, VT t, VT old, VT ui, VT xo, T di, T c1, T c2, T* rho, T* x,
+                                              T* dout, int flags) {
   if (flags & F_PLAIN) {
     *reinterpret_cast<VT*>(rho + o) = t;
     return;
   }
-  const VT old = (flags & F_RHO_FROM_B) ? *reinterpret_cast<const VT*>(b + o) : *reinterpret_cast<VT*>(rho + o);
   const VT r = old - t;
   if (flags & F_RHO_STORE) *reinterpret_cast<VT*>(rho + o) = r;
-  const VT ui = *reinterpret_cast<const VT*>(u + o);
   if (flags & F_X_ASSIGN)
     *reinterpret_cast<VT*>(x + o) = ui;
   else if (flags & F_X_ADD)
-    *reinterpret_cast<VT*>(x + o) = *reinterpret_cast<VT*>(x + o) + ui;
-  if (flags & F_D_OUT) *reinterpret_cast<VT*>(dout + o) = c1 * ui + (c2 * dinv[row]) * r;
+    *reinterpret_cast<VT*>(x + o) = xo + ui;
+  if (flags & F_D_OUT) *reinterpret_cast<VT*>(dout + o) = c1 * ui + (c2 * di) * r;
 }
 
 // Multi-right-hand-side fine-level kernel with LDS staging (NR columns, interleaved n x NR vectors).  One
@@ -1264,11 +1276,15 @@ __global__ __launch_bounds__(512) void k_level_lmr(int nrb, const int* __restric
   const int nvc = (e1 - vb + VW - 1) / VW, npc = (e1 - pb + 7) / 8;
   VT t = (VT)0;
   int row = -1;
+  VT eold = (VT)0, eui = (VT)0, exo = (VT)0;
+  T edi = 0;
   if (nu <= UCAP && nvc <= NVC && npc <= NPC) {  // uniform over the workgroup
-    // the row of this thread's slot and its entry range, loaded first so that they overlap the staging
+    // the row of this thread's slot, its entry range and the epilogue's operands, loaded first so that they
+    // overlap the staging
     const int nrow = r1 - r0;
     const int rr = ord ? ord[r0 + min(slot, nrow - 1)] : r0 + min(slot, nrow - 1);
     const int ka = ptr[rr], kz = ptr[rr + 1];
+    lmr_epi_load<T, VT>(rr, (int64_t)rr * NR + q * VW, u, b, rho, x, dinv, flags, eold, eui, exo, edi);
     // every thread issues all its loads before the first LDS store, with no divergent branch around them (a load
     // under one is waited for at the branch's end): indices beyond the block are clamped to its last chunk, and
     // threads beyond it store into a spare LDS entry
@@ -1324,9 +1340,11 @@ __global__ __launch_bounds__(512) void k_level_lmr(int nrb, const int* __restric
     if (ph == 0) {
       for (int j = 0; j < NPH; ++j) t += us[j * CH + q];
       row = r0;
+      lmr_epi_load<T, VT>(row, (int64_t)row * NR + q * VW, u, b, rho, x, dinv, flags, eold, eui, exo, edi);
     }
   }
-  if (row >= 0 && h == 0) lmr_epilogue<T, VT>(row, (int64_t)row * NR + q * VW, t, u, b, rho, x, dinv, dout, c1, c2, flags);
+  if (row >= 0 && h == 0)
+    lmr_epi_store<T, VT>((int64_t)row * NR + q * VW, t, eold, eui, exo, edi, c1, c2, rho, x, dout, flags);
 }
 
 // Pipelined form of k_level_lmr: one persistent workgroup of 1024 threads per compute unit walks a contiguous run of blocks (runs
@@ -1337,7 +1355,8 @@ __global__ __launch_bounds__(512) void k_level_lmr(int nrb, const int* __restric
 // (first row, first nonzero, first distinct column) are read two blocks ahead and the distinct-column indices one
 // block ahead.  The two stages alternate in a loop unrolled by two, so that each LDS access names a fixed stage.
 // Row order and epilogue are those of k_level_lmr; each row is summed in four aligned parts (16 waves per compute
-// unit), added across lanes.
+// unit), added across lanes.  A block's epilogue operands are loaded before its row sums, and its stores are
+// issued at the start of the next step.
 template <typename T, int NR, int CAP, int UCAP>
 struct LmrStage {
   static constexpr int VW = 16 / (int)sizeof(T), CH = NR / VW, RMAX = 256 / CH;
@@ -1379,9 +1398,16 @@ __global__ __launch_bounds__(1024) void k_level_lmr_pipe(int nrb, int nwg, const
   if (lw < 0) return;
   const int bb = (int)((int64_t)lw * nrb / nwg), be = (int)((int64_t)(lw + 1) * nrb / nwg);
   if (bb >= be) return;
-  __shared__ S st[2];
+  // two LDS objects (not one array), so that the compiler sees that the loads into one stage never write the other
+  __shared__ S st0, st1;
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   const int q = tid % CH, h = (tid / CH) % SPLIT, slot = tid / (CH * SPLIT);
+  // float: epilogue operands loaded before the row sums and stores issued one step later (double: both after the
+  // row sums; its registers allow neither)
+  constexpr bool DEFER = sizeof(T) == 4;
+  VT eold = (VT)0, eui = (VT)0, exo = (VT)0, et = (VT)0;
+  T edi = 0;
+  int prow = -1;  // DEFER: row of the stores still to issue (-1: none)
 
   auto staged = [&](int4 m0, int4 m1) {
     const int vb = m0.y & ~(VW - 1), pb = m0.y & ~7;
@@ -1415,12 +1441,14 @@ __global__ __launch_bounds__(1024) void k_level_lmr_pipe(int nrb, int nwg, const
   // epilogue
   auto compute = [&](S& D, int4 m0, int4 m1) {
     VT t = (VT)0;
-    int row = -1;
     if (staged(m0, m1)) {
       const int nrow = m1.x - m0.x;
+      int row = -1;
       if (slot < nrow) {
         const int lr = ord ? D.ord[slot] - m0.x : slot;
         row = m0.x + lr;
+        if (DEFER && h == 0)
+          lmr_epi_load<T, VT>(row, (int64_t)row * NR + q * VW, u, b, rho, x, dinv, flags, eold, eui, exo, edi);
         const int vb = m0.y & ~(VW - 1), pb = m0.y & ~7;
         const int ka = D.rp[lr], kz = D.rp[lr + 1];
         t = lmr_row_sum<T, VT, CH>(reinterpret_cast<const T*>(D.sv) - vb,
@@ -1432,7 +1460,19 @@ __global__ __launch_bounds__(1024) void k_level_lmr_pipe(int nrb, int nwg, const
         t[w] += __shfl_xor(t[w], CH, 64);
         t[w] += __shfl_xor(t[w], 2 * CH, 64);
       }
-    } else {  // one row beyond the stage capacity: summed from global memory, phase sums added in phase order
+      if (row >= 0 && h == 0) {
+        if (DEFER) {
+          prow = row;
+          et = t;
+        } else {
+          VT lo = (VT)0, lu = (VT)0, lx = (VT)0;
+          T ld = 0;
+          lmr_epi_load<T, VT>(row, (int64_t)row * NR + q * VW, u, b, rho, x, dinv, flags, lo, lu, lx, ld);
+          lmr_epi_store<T, VT>((int64_t)row * NR + q * VW, t, lo, lu, lx, ld, c1, c2, rho, x, dout, flags);
+        }
+      }
+    } else {  // one row beyond the stage capacity: summed from global memory, phase sums added in phase order, and
+              // its epilogue applied at once (no load of this path is left in flight)
       const int ph = tid / CH;
       VT acc = (VT)0;
       for (int e = m0.y + ph; e < m1.y; e += NPH)
@@ -1441,35 +1481,48 @@ __global__ __launch_bounds__(1024) void k_level_lmr_pipe(int nrb, int nwg, const
       __syncthreads();
       if (ph == 0) {  // the next step's barrier precedes any reuse of the stage
         for (int j = 0; j < NPH; ++j) t += D.us[j * CH + q];
-        row = m0.x;
+        const int row = m0.x;
+        VT lo = (VT)0, lu = (VT)0, lx = (VT)0;
+        T ld = 0;
+        lmr_epi_load<T, VT>(row, (int64_t)row * NR + q * VW, u, b, rho, x, dinv, flags, lo, lu, lx, ld);
+        lmr_epi_store<T, VT>((int64_t)row * NR + q * VW, t, lo, lu, lx, ld, c1, c2, rho, x, dout, flags);
       }
     }
-    if (row >= 0 && h == 0)
-      lmr_epilogue<T, VT>(row, (int64_t)row * NR + q * VW, t, u, b, rho, x, dinv, dout, c1, c2, flags);
+  };
+  // DEFER: the stores of the previous block's rows, issued at the start of the next step (their operands are then
+  // known to be loaded), so that they are acknowledged while a block is summed rather than at the next wait
+  auto flush = [&] {
+    if (DEFER && prow >= 0)
+      lmr_epi_store<T, VT>((int64_t)prow * NR + q * VW, et, eold, eui, exo, edi, c1, c2, rho, x, dout, flags);
+    prow = -1;
   };
 
   int uc[NU];
   int4 m0 = meta[bb], m1 = meta[bb + 1];
   load_uc(m0, m1, uc);
-  issue(st[0], m0, m1, uc);
+  issue(st0, m0, m1, uc);
   int4 m2 = bb + 2 <= nrb ? meta[bb + 2] : m1;
   if (bb + 1 < be) load_uc(m1, m2, uc);
   // block bi in stage A: wait for its loads, start block bi + 1's into stage B, prefetch for bi + 2, sum bi
-  auto step = [&](S& A, S& B, int bi) {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  // (the stages come in as restrict pointers: the compiler then knows that the loads into B never write A and does
+  // not wait for them before reading A)
+  auto step = [&](S* __restrict__ A, S* __restrict__ B, int bi) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) (expcnt, lgkmcnt unconstrained), visible to the compiler
     __syncthreads();
-    if (bi + 1 < be) issue(B, m1, m2, uc);
+    flush();
+    if (bi + 1 < be) issue(*B, m1, m2, uc);
     const int4 m3 = bi + 3 <= nrb ? meta[bi + 3] : m2;
     if (bi + 2 < be) load_uc(m2, m3, uc);
-    compute(A, m0, m1);
+    compute(*A, m0, m1);
     m0 = m1;
     m1 = m2;
     m2 = m3;
   };
   for (int bi = bb; bi < be; bi += 2) {
-    step(st[0], st[1], bi);
-    if (bi + 1 < be) step(st[1], st[0], bi + 1);
+    step(&st0, &st1, bi);
+    if (bi + 1 < be) step(&st1, &st0, bi + 1);
   }
+  flush();
 }
 
 template <typename T, int NR, int CLS>
