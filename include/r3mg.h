@@ -252,6 +252,14 @@ r3mg_status r3mg_export_level(r3mg_handle h, int level, int64_t* row_ptr, int32_
 r3mg_status r3mg_time_smoother_kernel(r3mg_handle h, int level, int reps, int64_t flush_bytes, void* stream,
                                       double* ms_per_launch, double* bytes_per_launch);
 
+/* The same for nrhs right-hand sides (1, 2, 4, 8 or 16; interleaved vectors, as the block V-cycle applies the
+ * level): the multi-right-hand-side kernels are tuned for nrhs first if no solve has tuned them, and the bytes are
+ * those of the tuned kernel's storage format (fine level with the LDS-staged kernel: values, 2-byte positions,
+ * distinct-column lists, block records, row order and row pointers; CSR kernels: values, 4-byte columns and row
+ * pointers) plus 7 vector streams of nrhs columns.  R3MG_ERR_INVALID for another nrhs or bad arguments. */
+r3mg_status r3mg_time_smoother_kernel_nrhs(r3mg_handle h, int level, int nrhs, int reps, int64_t flush_bytes,
+                                           void* stream, double* ms_per_launch, double* bytes_per_launch);
+
 /* Adjoint gradient of a per-cell coefficient (standard adjoint method; not in the paper):
  * g[e] = - sum_{a,b unconstrained} lam[c_ea] Ke_e[a,b] u[c_eb], cells (device, ncells x nloc int32, caller's
  * numbering), Ke (device float64, nloc x nloc per cell at stride ke_stride doubles; 0 = one shared matrix),

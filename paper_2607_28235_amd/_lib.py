@@ -27,7 +27,8 @@ EXPORTED = [
     "r3mg_vcycle_noalloc",
     "r3mg_level_apply", "r3mg_pcg_solve", "r3mg_pcg_solve_ex", "r3mg_pcg_solve_group", "r3mg_pcg_history",
     "r3mg_info", "r3mg_export_partition",
-    "r3mg_export_P", "r3mg_export_level", "r3mg_time_smoother_kernel", "r3mg_cell_grad", "r3mg_assembler_create",
+    "r3mg_export_P", "r3mg_export_level", "r3mg_time_smoother_kernel", "r3mg_time_smoother_kernel_nrhs",
+    "r3mg_cell_grad", "r3mg_assembler_create",
     "r3mg_assemble", "r3mg_assembler_free", "r3mg_rtree", "r3mg_free", "r3mg_status_string", "r3mg_last_error",
 ]
 
@@ -111,6 +112,7 @@ def lib():
     L.r3mg_export_P.argtypes = [vp, i32, vp, vp, vp, P(i64), P(i64)]
     L.r3mg_export_level.argtypes = [vp, i32, vp, vp, vp, P(i64), P(i64)]
     L.r3mg_time_smoother_kernel.argtypes = [vp, i32, i32, i64, vp, P(dbl), P(dbl)]
+    L.r3mg_time_smoother_kernel_nrhs.argtypes = [vp, i32, i32, i32, i64, vp, P(dbl), P(dbl)]
     L.r3mg_cell_grad.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp, i64, vp]
     L.r3mg_assembler_create.argtypes = [vp, vp, i32, i64, P(vp)]
     L.r3mg_assemble.argtypes = [vp, vp, vp, i64, vp, vp]
@@ -269,11 +271,12 @@ class Hierarchy:
         _check(lib().r3mg_cell_grad(self._h, _dev(cells_dev), nloc, _dev(Ke_dev), ke_stride, _dev(u), _dev(lam),
                                     _dev(g), ncells, _stream(stream)), "r3mg_cell_grad")
 
-    def time_smoother_kernel(self, level: int, reps: int, stream=None, flush_bytes: int = 0):
-        """(ms per launch, bytes per launch); flush_bytes > 0 times each launch alone after evicting the caches."""
+    def time_smoother_kernel(self, level: int, reps: int, stream=None, flush_bytes: int = 0, nrhs: int = 1):
+        """(ms per launch, bytes per launch) of the level's fused smoother kernel for nrhs right-hand sides;
+        flush_bytes > 0 times each launch alone after evicting the caches."""
         ms, by = C.c_double(), C.c_double()
-        _check(lib().r3mg_time_smoother_kernel(self._h, level, reps, int(flush_bytes), _stream(stream), C.byref(ms),
-                                               C.byref(by)), "r3mg_time_smoother_kernel")
+        _check(lib().r3mg_time_smoother_kernel_nrhs(self._h, level, nrhs, reps, int(flush_bytes), _stream(stream),
+                                                    C.byref(ms), C.byref(by)), "r3mg_time_smoother_kernel_nrhs")
         return ms.value, by.value
 
     # --- host queries ----------------------------------------------------------------------------

@@ -399,16 +399,23 @@ r3mg_status r3mg_export_level(r3mg_handle h, int level, int64_t* row_ptr, int32_
   });
 }
 
-r3mg_status r3mg_time_smoother_kernel(r3mg_handle h, int level, int reps, int64_t flush_bytes, void* stream,
-                                      double* ms_per_launch, double* bytes_per_launch) {
+r3mg_status r3mg_time_smoother_kernel_nrhs(r3mg_handle h, int level, int nrhs, int reps, int64_t flush_bytes,
+                                           void* stream, double* ms_per_launch, double* bytes_per_launch) {
   return guard([&] {
     require_factored(h);
     const int L = h->impl.an->nlevels() - 1;
     if (level < 0 || level >= L || reps < 1 || flush_bytes < 0 || !ms_per_launch || !bytes_per_launch)
       throw Error{R3MG_ERR_INVALID, "bad timing arguments"};
-    time_smoother_kernel(h->impl, level, reps, flush_bytes, S(stream), ms_per_launch, bytes_per_launch);
+    if (nrhs < 1 || nrhs > 16 || (nrhs & (nrhs - 1)) != 0)
+      throw Error{R3MG_ERR_INVALID, "nrhs must be 1, 2, 4, 8 or 16"};
+    time_smoother_kernel(h->impl, level, nrhs, reps, flush_bytes, S(stream), ms_per_launch, bytes_per_launch);
     return R3MG_OK;
   });
+}
+
+r3mg_status r3mg_time_smoother_kernel(r3mg_handle h, int level, int reps, int64_t flush_bytes, void* stream,
+                                      double* ms_per_launch, double* bytes_per_launch) {
+  return r3mg_time_smoother_kernel_nrhs(h, level, 1, reps, flush_bytes, stream, ms_per_launch, bytes_per_launch);
 }
 
 r3mg_status r3mg_cell_grad(r3mg_handle h, const int32_t* cells_dev, int nloc, const double* Ke_dev, int64_t ke_stride,

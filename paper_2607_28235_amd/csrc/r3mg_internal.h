@@ -315,8 +315,8 @@ r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double
 // residual norms ||r_j||_2, j = 0..iters, of column col of the last block solved on the handle (rr may be null);
 // returns iters + 1 (0 before any solve)
 int residual_history(HandleImpl& h, int col, double* rr, int cap);
-void time_smoother_kernel(HandleImpl& h, int level, int reps, int64_t flush_bytes, hipStream_t s, double* ms,
-                          double* bytes);
+void time_smoother_kernel(HandleImpl& h, int level, int nrhs, int reps, int64_t flush_bytes, hipStream_t s,
+                          double* ms, double* bytes);
 // matrix-free fine operator: upload, check against the CSR operator, switch level 0 to it; detach returns to CSR
 void attach_matrix_free(HandleImpl& h, MatFreeHost&& m, hipStream_t s);
 void detach_matrix_free(HandleImpl& h);

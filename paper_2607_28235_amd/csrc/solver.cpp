@@ -1800,12 +1800,39 @@ void attach_matrix_free(HandleImpl& h, MatFreeHost&& m, hipStream_t s) {
   drop_graphs(dv);
 }
 
-void time_smoother_kernel(HandleImpl& h, int level, int reps, int64_t flush_bytes, hipStream_t s, double* ms,
-                          double* bytes) {
+// bytes one application of level l for nr right-hand sides moves in the storage format of the kernel that applies
+// it (fine level with several right-hand sides: the tuned kernel's format), 7 vector streams included
+static double level_bytes(Ctx& c, int l, int nr, int esz) {
+  DevLevel& D = c.dv.lv[l];
+  const double vec = 7.0 * (double)D.n * esz;
+  if (nr == 1) return D.bytes_apply;
+  if (l == 0 && !D.mf) {
+    auto it = c.dv.tuned.find({0, nr * 2 + (esz == 4 ? 1 : 0)});
+    const double nnz = (double)D.nnz, n = (double)D.n;
+    const int cls = mr_class(nr, esz);
+    if (it != c.dv.tuned.end() && it->second < 0 && cls >= 0) {
+      // values, 2-byte positions, distinct-column lists, block records, row order and row pointers
+      const double nuc = (double)D.mucol[cls].n - 1, nrb = (double)D.mr[cls].nrb;
+      return nnz * (esz + 2) + 4.0 * nuc + 16.0 * (nrb + 1) + 4.0 * n + 4.0 * (n + 1) + vec * nr;
+    }
+    return nnz * (esz + 4) + 4.0 * (n + 1) + vec * nr;  // CSR kernels
+  }
+  return D.bytes_apply + vec * (nr - 1);
+}
+
+void time_smoother_kernel(HandleImpl& h, int level, int nrhs, int reps, int64_t flush_bytes, hipStream_t s,
+                          double* ms, double* bytes) {
   Analysis& an = *h.an;
   Device& dv = *h.dev;
   Ctx c{an, dv, an.opt.vcycle_fp32 != 0};
-  ensure_level_vectors(c, 1);
+  ensure_level_vectors(c, nrhs);
+  if (nrhs > 1) {
+    ensure_pcg_vectors(c, nrhs);
+    if (c.fp32)
+      autotune_spmm<float>(c, nrhs, s);
+    else
+      autotune_spmm<double>(c, nrhs, s);
+  }
   DevLevel& D = dv.lv[level];
   hipEvent_t e0, e1;
   R3MG_HIP_CHECK(hipEventCreate(&e0));
@@ -1815,12 +1842,12 @@ void time_smoother_kernel(HandleImpl& h, int level, int reps, int64_t flush_byte
     if (c.fp32) {
       float* u = vbuf<float>((r & 1) ? D.dB : D.dA);
       float* w = vbuf<float>((r & 1) ? D.dA : D.dB);
-      apply_level<float>(c, level, 1, u, vbuf<float>(D.b), vbuf<float>(D.rho), vbuf<float>(D.x), w, 0.0, 0.0, fl,
+      apply_level<float>(c, level, nrhs, u, vbuf<float>(D.b), vbuf<float>(D.rho), vbuf<float>(D.x), w, 0.0, 0.0, fl,
                          nullptr, s);
     } else {
       double* u = vbuf<double>((r & 1) ? D.dB : D.dA);
       double* w = vbuf<double>((r & 1) ? D.dA : D.dB);
-      apply_level<double>(c, level, 1, u, vbuf<double>(D.b), vbuf<double>(D.rho), vbuf<double>(D.x), w, 0.0, 0.0,
+      apply_level<double>(c, level, nrhs, u, vbuf<double>(D.b), vbuf<double>(D.rho), vbuf<double>(D.x), w, 0.0, 0.0,
                           fl, nullptr, s);
     }
   };
@@ -1860,7 +1887,7 @@ void time_smoother_kernel(HandleImpl& h, int level, int reps, int64_t flush_byte
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *ms = (double)t / reps;
-  *bytes = D.bytes_apply;
+  *bytes = level_bytes(c, level, nrhs, c.fp32 ? 4 : 8);
 }
 
 }  // namespace r3mg

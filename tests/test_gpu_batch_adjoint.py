@@ -127,6 +127,32 @@ def test_lds_staged_kernel_with_long_row(q3_long_row, kernel, nrhs, fp32):
     h.close()
 
 
+@pytest.mark.parametrize("kernel", [1, 2, 4])
+def test_time_smoother_kernel_nrhs(small3d_q3, kernel):
+    """Timing of the fine-level smoother kernel for 16 right-hand sides: the kernels are tuned on demand (no solve
+    before), the bytes are those of the tuned kernel's format (LDS-staged kernels: values, 2-byte positions and the
+    block's lists; CSR kernels: values and 4-byte columns) plus 7 vector streams of 16 columns, and other counts of
+    right-hand sides are refused."""
+    import paper_2607_28235_amd as P
+    prob = small3d_q3.problem
+    _case(f"time_smoother_kernel nrhs=16 kernel={kernel} n={prob.n}")
+    o = P.Options(dim=3, coarse_degree=2, leaf_size=256, max_coarse_dofs=600, vcycle_fp32=1, multi_rhs_kernel=kernel)
+    h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o)
+    ms, by = h.time_smoother_kernel(0, 5, nrhs=16)
+    ms_cold, _ = h.time_smoother_kernel(0, 2, flush_bytes=1 << 26, nrhs=16)
+    assert ms > 0 and ms_cold > 0
+    nnz, n = prob.nnz, prob.n
+    vec = 7 * n * 4 * 16
+    if kernel == 4:
+        assert by == pytest.approx(nnz * 8 + 4 * (n + 1) + vec, rel=1e-12)
+    else:
+        assert nnz * 6 + vec < by < nnz * 8 + vec
+    for bad in (3, 32):
+        with pytest.raises(P.R3mgError):
+            h.time_smoother_kernel(0, 1, nrhs=bad)
+    h.close()
+
+
 def test_uneven_group_in_one_graph():
     """Several independent problems of different sizes solved in one captured launch sequence."""
     _need_gpu()
