@@ -95,6 +95,12 @@ typedef struct {
                            matrix stream is at most 128 MiB (it can stay in the caches across a smoothing sweep),
                            with nontemporal loads elsewhere [-1]; 0 = nontemporal loads on every level; 1 =
                            ordinary loads on every level.  The results do not depend on it. */
+  int tune_cache;       /* 1 = kernel choices made by timing (the fine level's row-block shape, the multi-RHS
+                           kernels) are looked up in and added to the persisted tuning cache, keyed by the device
+                           and the handle's level structure (the file named by the R3MG_TUNE_CACHE environment
+                           variable, an empty value for none, else $HOME/.cache/r3mg/tune-cache.txt) [1]; 0 = every
+                           handle times its kernels.  Choices forced by fine_kernel or multi_rhs_kernel are never
+                           cached. */
 } r3mg_options;
 
 typedef struct {

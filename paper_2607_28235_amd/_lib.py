@@ -46,7 +46,7 @@ class _Options(C.Structure):
                 ("pre_steps", C.c_int), ("post_steps", C.c_int), ("lanczos_steps", C.c_int),
                 ("cheb_boost", C.c_double), ("cheb_ratio", C.c_double), ("vcycle_fp32", C.c_int),
                 ("use_graph", C.c_int), ("fine_kernel", C.c_int), ("multi_rhs_kernel", C.c_int),
-                ("matrix_cache", C.c_int)]
+                ("matrix_cache", C.c_int), ("tune_cache", C.c_int)]
 
 
 class _LevelInfo(C.Structure):
@@ -74,6 +74,7 @@ class Options:
     fine_kernel: int = -1
     multi_rhs_kernel: int = -1
     matrix_cache: int = -1
+    tune_cache: int = 1
 
     def _c(self) -> _Options:
         return _Options(**dataclasses.asdict(self))

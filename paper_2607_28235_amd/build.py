@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libr3mg.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "matfree.hip", "noalloc.hip", "solver.cpp", "capi.cpp", "analysis.cpp", "matfree.cpp"]
+SOURCES = ["kernels.hip", "matfree.hip", "noalloc.hip", "solver.cpp", "capi.cpp", "analysis.cpp", "matfree.cpp",
+           "tunecache.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]

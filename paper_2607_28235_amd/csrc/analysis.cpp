@@ -134,7 +134,7 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
       opt.cheb_degree < 1 || opt.pre_steps < 0 || opt.post_steps < 0 || opt.lanczos_steps < 1 ||
       !(opt.cheb_boost > 0.0) || !(opt.cheb_ratio > 1.0) || opt.fine_kernel < -1 ||
       opt.fine_kernel >= kFineShapes || opt.multi_rhs_kernel < -1 || opt.multi_rhs_kernel > 4 ||
-      opt.matrix_cache < -1 || opt.matrix_cache > 1)
+      opt.matrix_cache < -1 || opt.matrix_cache > 1 || opt.tune_cache < 0 || opt.tune_cache > 1)
     throw err(R3MG_ERR_INVALID, "invalid option value");
   if (n < 1 || n >= (int64_t(1) << 31)) throw err(R3MG_ERR_INVALID, "n out of range");
   if (!coords || !row_ptr || !col_idx || !vals) throw err(R3MG_ERR_INVALID, "null input");

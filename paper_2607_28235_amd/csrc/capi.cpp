@@ -86,6 +86,7 @@ void r3mg_default_options(r3mg_options* o) {
   o->fine_kernel = -1;
   o->multi_rhs_kernel = -1;
   o->matrix_cache = -1;
+  o->tune_cache = 1;
 }
 
 r3mg_status r3mg_analyze(const double* coords, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,

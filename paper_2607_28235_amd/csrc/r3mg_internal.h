@@ -247,6 +247,7 @@ struct PcgScalars;  // device-side PCG state (defined in the solver)
 
 struct Device {
   int dev = 0;
+  std::string tune_sig;  // tuning-cache key prefix of this handle: device and level structure (set at set-up)
   std::vector<DevLevel> lv;
   // dense coarsest: inverse (nL x nL float64, row-major); for up to kDenseSymMaxTiles tile rows also its upper
   // 64 x 64 tiles packed (csym, tile list ctile) and the pass-1 slots for up to 4 columns (cpart)

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "tunecache.h"
 #include "noalloc.h"
 #include "r3mg_internal.h"
 
@@ -442,6 +443,22 @@ static float time_launches(hipStream_t s, int reps, const std::function<void()>&
   return ms / reps;
 }
 
+// whether a multi-RHS kernel code read from the tuning cache can apply level l (-1: PCG's float64 operator) for nr
+// columns of element size esz (building the LDS-staged kernel's blocks when it names that kernel)
+static bool valid_mr_code(Ctx& c, int l, int nr, int esz, int code, hipStream_t s) {
+  auto pow2 = [](int g, int hi) { return g >= 1 && g <= hi && (g & (g - 1)) == 0; };
+  if (l > 0) return pow2(code, 64);
+  if (l < 0 && pow2(code, 8)) return true;
+  if (l == 0 && pow2(code, 64)) return true;
+  if (code == -1 || code == -2) return ensure_mr_blocks(c, mr_class(nr, esz), s);
+  return pow2(code - kCodeSplit, 64) || pow2(code - kCodeSplit2, 64);
+}
+
+// tuning-cache key of a multi-RHS choice
+static std::string mr_tune_key(const Device& dv, int l, int nr, int esz) {
+  return dv.tune_sig + "/mr/" + std::to_string(l) + "/" + std::to_string(nr) + "/" + std::to_string(esz);
+}
+
 template <typename T>
 static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
   if (nr <= 1) return;
@@ -449,11 +466,18 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
   const int L = c.an.nlevels() - 1;
   const int tag = nr * 2 + (sizeof(T) == 4 ? 1 : 0);
   const int forced = c.an.opt.multi_rhs_kernel;  // -1 timed, 0 lanes, 1 / 2 LDS-staged, 3 / 4 column-split
+  const bool cache = forced == -1 && c.an.opt.tune_cache != 0 && !dv.tune_sig.empty();
   const int fl = F_RHO_STORE | F_X_ADD | F_D_OUT;
   for (int l = 0; l < L; ++l) {
     if (dv.tuned.count({l, tag})) continue;
     DevLevel& D = dv.lv[l];
     if (l == 0 && D.mf) continue;  // the matrix-free operator applies the fine level
+    int cached = 0;
+    if (cache && tune_cache_get(mr_tune_key(dv, l, nr, (int)sizeof(T)), &cached) &&
+        valid_mr_code(c, l, nr, (int)sizeof(T), cached, s)) {
+      dv.tuned[{l, tag}] = cached;
+      continue;
+    }
     LevelOp<T> op = level_op<T>(c, l);
     float best = 1e30f;
     int bestCode = D.lanes;
@@ -506,10 +530,18 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
         }
     }
     dv.tuned[{l, tag}] = bestCode;
+    if (cache) tune_cache_put(mr_tune_key(dv, l, nr, (int)sizeof(T)), bestCode);
     R3MG_HIP_CHECK(hipMemsetAsync(D.x.p, 0, D.x.n, s));
   }
   // PCG's float64 q = A p and <p, q>: lanes kernel with fused partial dots (at most 8 lanes: bounded number of
   // partials), or the local-column / column-split kernel followed by the per-column dot in a fixed partition
+  int cached = 0;
+  if (!dv.tuned.count({-1, nr * 2}) && !dv.lv[0].mf && cache &&
+      tune_cache_get(mr_tune_key(dv, -1, nr, 8), &cached) && valid_mr_code(c, -1, nr, 8, cached, s)) {
+    dv.tuned[{-1, nr * 2}] = cached;
+    if (cached >= 1 && cached <= 8) need_partials(dv, (int64_t)((c.an.n + 256 / cached - 1) / (256 / cached)) * nr);
+    else need_partials(dv, (int64_t)kPcgBlocks * 2 * nr);
+  }
   if (!dv.tuned.count({-1, nr * 2}) && !dv.lv[0].mf) {
     LevelOp<double> op = level_op<double>(c, 0);
     DevLevel& D0 = dv.lv[0];
@@ -575,6 +607,7 @@ static void autotune_spmm(Ctx& c, int nr, hipStream_t s) {
         }
       }
     dv.tuned[{-1, nr * 2}] = bestCode;
+    if (cache) tune_cache_put(mr_tune_key(dv, -1, nr, 8), bestCode);
   }
   R3MG_HIP_CHECK(hipStreamSynchronize(s));
 }
@@ -855,6 +888,25 @@ void numeric_setup(HandleImpl& h, hipStream_t s) {
   drop_graphs(dv);
 }
 
+// Tuning-cache key prefix of a handle: the device, and a hash of what decides the kernel choices (dimension,
+// coarse degree, the fine row pointers and a strided sample of its columns, every level's size and stored
+// nonzeros, the V-cycle precision and the matrix-cache mode).  Numeric values do not enter.
+static std::string tune_signature(const Analysis& an, const Device& dv) {
+  uint64_t hsh = fnv1a(an.rowptr.data(), an.rowptr.size() * sizeof(int32_t));
+  const size_t nc = an.col.size(), step = std::max<size_t>(1, nc / 65536);
+  for (size_t i = 0; i < nc; i += step) hsh = fnv1a(&an.col[i], sizeof(int32_t), hsh);
+  const int64_t meta[] = {an.d, an.pc, an.B, an.n, an.nnz, an.opt.vcycle_fp32, an.opt.matrix_cache,
+                          (int64_t)dv.lv.size()};
+  hsh = fnv1a(meta, sizeof meta, hsh);
+  for (const DevLevel& D : dv.lv) {
+    const int64_t v[2] = {D.n, D.nnz};
+    hsh = fnv1a(v, sizeof v, hsh);
+  }
+  char buf[24];
+  std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)hsh);
+  return tune_device_key(dv.dev) + "/" + buf;
+}
+
 // Fine-level row-block shape: each candidate shape runs the V-cycle-precision smoother step on level 0 (3
 // warm-up + 5 timed launches, hipEvents); the fastest is kept for every later single-RHS application.
 static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
@@ -865,6 +917,17 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
   DevLevel& D = dv.lv[0];
   if (an.opt.fine_kernel >= 0) {
     D.shape = D.shape64 = an.opt.fine_kernel;
+    D.bytes_apply = D.shape_bytes[D.shape];
+    return;
+  }
+  // the tuning cache holds shape + 100 shape64
+  const bool cache = an.opt.tune_cache != 0 && !dv.tune_sig.empty();
+  const std::string key = dv.tune_sig + "/fine1/" + (c.fp32 ? "f32" : "f64");
+  int cached = 0;
+  if (cache && tune_cache_get(key, &cached) && cached >= 0 && cached % 100 < kFineShapes &&
+      cached / 100 < kFineShapes && (c.fp32 || cached / 100 == cached % 100)) {
+    D.shape = cached % 100;
+    D.shape64 = cached / 100;
     D.bytes_apply = D.shape_bytes[D.shape];
     return;
   }
@@ -901,7 +964,10 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
   D.bytes_apply = D.shape_bytes[D.shape];
   R3MG_HIP_CHECK(hipMemsetAsync(D.x.p, 0, D.x.n, s));
   R3MG_HIP_CHECK(hipMemsetAsync(D.rho.p, 0, D.rho.n, s));
-  if (!c.fp32) return;
+  if (!c.fp32) {
+    if (cache) tune_cache_put(key, D.shape + 100 * D.shape64);
+    return;
+  }
   // float32 V-cycle: PCG's float64 operator y = A p is timed on its own (the float64 values double the LDS
   // staging, so another shape can win); the same two rounds and 3% rule
   DBuf<double> u64, y64;
@@ -922,6 +988,7 @@ static void tune_stream_shape(HandleImpl& h, hipStream_t s) {
   for (int sh = 1; sh < kFineShapes; ++sh)
     if (best[sh] < 0.97f * best[bestS]) bestS = sh;
   D.shape64 = bestS;
+  if (cache) tune_cache_put(key, D.shape + 100 * D.shape64);
   R3MG_HIP_CHECK(hipStreamSynchronize(s));
 }
 
@@ -1077,6 +1144,7 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     }
   }
   numeric_setup(h, s);
+  dv.tune_sig = tune_signature(an, dv);
   tune_stream_shape(h, s);
   R3MG_HIP_CHECK(hipStreamSynchronize(s));
   // the allocation-free V-cycle's scratch address on this device, looked up once at set-up

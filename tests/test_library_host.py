@@ -146,8 +146,10 @@ def test_invalid_arguments():
     with pytest.raises(P.R3mgError) as e:
         P.Hierarchy(p.coords, p.row_ptr, p.col, p.val, P.Options(dim=2, max_levels=1), factor=False)
     assert e.value.code == "INVALID"
-    # fine-level shapes are 0..10 (-1: timed); multi-RHS kernels 0..4 (-1: timed); matrix load modes -1..1
-    for kw in ({"fine_kernel": 11}, {"fine_kernel": -2}, {"multi_rhs_kernel": 5}, {"matrix_cache": 2}):
+    # fine-level shapes are 0..10 (-1: timed); multi-RHS kernels 0..4 (-1: timed); matrix load modes -1..1;
+    # tuning cache 0..1
+    for kw in ({"fine_kernel": 11}, {"fine_kernel": -2}, {"multi_rhs_kernel": 5}, {"matrix_cache": 2},
+               {"tune_cache": 2}, {"tune_cache": -1}):
         with pytest.raises(P.R3mgError) as e:
             P.Hierarchy(p.coords, p.row_ptr, p.col, p.val, P.Options(dim=2, **kw), factor=False)
         assert e.value.code == "INVALID", kw
