@@ -304,6 +304,22 @@ void dense_cholesky_inverse(int n, double* A, double* Inv, double* ws, double* Y
 // a partition that depends only on n and nr, so the iterates do not depend on the kernel that formed A p)
 // followed by a one-block kernel that sums them in index order and updates the scalars of `st`.
 constexpr int kPcgBlocks = 1024;
+// One right-hand side: the scalar steps folded into the vector kernels after their reductions (every block forms
+// the total from the per-block partials in the order of the one-block kernels; block 0 records it in the state).
+// partials: 4 pcg_blocks(n) entries, area 0 <p, q>, area 1 ||r||^2, area 2 <r, z> and <q, z>.  An iteration is
+// q = A p; launch_pcg_dot; launch_pcg_xr1 (alpha, x, r); the V-cycle; launch_pcg_z1 (stop test, z); launch_pcg_p1
+// (beta, p).  Enqueued as two halves, the stop test ends the first (launch_pcg_check1) and launch_pcg_z1 runs
+// without it.  launch_pcg_z with mode 1 at the start of a solve must write its partials to area 2.
+int pcg_blocks(int n);
+void launch_pcg_dot(int n, const double* p, const double* q, double* partials, PcgState* st, hipStream_t s);
+template <typename T>
+void launch_pcg_xr1(int n, PcgState* st, double* x, double* r, const double* p, const double* q, double* partials,
+                    T* b0, const T* dinv0, T* d0, double inv_theta0, hipStream_t s);
+template <typename T>
+void launch_pcg_z1(int n, PcgState* st, bool check, const T* x0, const T* dpend, double* z, const double* r,
+                   const double* q, double* partials, hipStream_t s);
+void launch_pcg_check1(int n, PcgState* st, const double* partials, hipStream_t s);
+void launch_pcg_p1(int n, PcgState* st, const double* z, double* p, const double* partials, hipStream_t s);
 // <p, q> per column (n x nr interleaved) and alpha = gamma / <p, q> (0 for converged columns); skips when
 // st->all_done.  nr in {1, 2, 4, 8, 16}.
 void launch_pcg_dot_alpha(int n, int nr, const double* p, const double* q, double* partials, PcgState* st,

@@ -3447,6 +3447,142 @@ void launch_pcg_p(int n, int nr, PcgState* st, const double* z, double* p, hipSt
   check_launch("k_pcg_p");
 }
 
+// One right-hand side: the scalar steps folded into the vector kernels that follow their reductions.  Every block of
+// the next kernel forms the reduction's total itself from the per-block partials (column_totals<1>: the same sums in
+// the same order as the one-block kernels above, so the same bits in every block) and block 0 records it in the
+// state; each reduction has its own partials area, so that no block overwrites partials another block still reads:
+// area 0 (g entries) <p, q>, area 1 (g) ||r||^2, area 2 (2 g) <r, z> and <q, z>, g = pcg_grid(n).  gamma is formed
+// from area 2 by the kernel that needs it, so no kernel writes a state scalar that another block of it reads.
+int pcg_blocks(int n) { return pcg_grid(n); }
+
+void launch_pcg_dot(int n, const double* p, const double* q, double* partials, PcgState* st, hipStream_t s) {
+  hipLaunchKernelGGL((k_pcg_dot<1>), dim3(pcg_grid(n)), dim3(256), 0, s, n, p, q, partials, st);
+  check_launch("k_pcg_dot");
+}
+
+// alpha = gamma / <p, q> (gamma = <r, z> from area 2); x += alpha p; r -= alpha q; ||r||^2 partials to area 1;
+// V-cycle entry b0 = (T) r, d0 = dinv0 b0 / theta0
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_xr1(int n, PcgState* st, double* x, double* r,
+                                                 const double* __restrict__ p, const double* __restrict__ q,
+                                                 double* partials, int g, T* b0, const T* __restrict__ dinv0, T* d0,
+                                                 T inv_theta0) {
+  __shared__ double sh[4];
+  __shared__ double gam[1], pq[1];
+  if (st->all_done) return;
+  column_totals<1>(partials + 2 * g, g, 2, sh, gam);
+  column_totals<1>(partials, g, 1, sh, pq);
+  const double al = st->done[0] ? 0.0 : gam[0] / pq[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->gamma[0] = gam[0];
+    pcg_set_alpha(st, 0, pq[0]);
+  }
+  double acc = 0;
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < n; o += (int64_t)gridDim.x * 256) {
+    x[o] += al * p[o];
+    const double rv = r[o] - al * q[o];
+    r[o] = rv;
+    acc += rv * rv;
+    if (b0) {
+      const T bv = (T)rv;
+      b0[o] = bv;
+      if (d0) d0[o] = dinv0[o] * bv * inv_theta0;
+    } else if (d0) {
+      d0[o] = dinv0[o] * (T)rv * inv_theta0;
+    }
+  }
+  column_partials<1>(acc, sh, partials + g + blockIdx.x);
+}
+template <typename T>
+void launch_pcg_xr1(int n, PcgState* st, double* x, double* r, const double* p, const double* q, double* partials,
+                    T* b0, const T* dinv0, T* d0, double inv_theta0, hipStream_t s) {
+  const int g = pcg_grid(n);
+  hipLaunchKernelGGL((k_pcg_xr1<T>), dim3(g), dim3(256), 0, s, n, st, x, r, p, q, partials, g, b0, dinv0, d0,
+                     (T)inv_theta0);
+  check_launch("k_pcg_xr1");
+}
+template void launch_pcg_xr1<float>(int, PcgState*, double*, double*, const double*, const double*, double*, float*,
+                                    const float*, float*, double, hipStream_t);
+template void launch_pcg_xr1<double>(int, PcgState*, double*, double*, const double*, const double*, double*,
+                                     double*, const double*, double*, double, hipStream_t);
+
+// check set: the stop test of the column (from the ||r||^2 partials of area 1, block 0 records it); z = x0 + dpend;
+// <r, z> and (q set) <q, z> partials to area 2
+template <typename T>
+__global__ __launch_bounds__(256) void k_pcg_z1(int n, PcgState* st, int check, const T* __restrict__ x0,
+                                                const T* __restrict__ dp, double* z, const double* __restrict__ r,
+                                                const double* __restrict__ q, double* partials, int g) {
+  __shared__ double sh[4];
+  __shared__ double rr[1];
+  if (st->all_done) return;
+  if (check) column_totals<1>(partials + g, g, 1, sh, rr);
+  if (check && blockIdx.x == 0 && threadIdx.x == 0 && !st->done[0]) {
+    st->rr_prev[0] = st->rr[0];
+    st->rr[0] = rr[0];
+    const int j = st->iters[0] + 1;
+    st->iters[0] = j;
+    if (st->rhist && j <= st->hist_rows) st->rhist[(int64_t)j * kMaxNR] = rr[0];
+    if (rr[0] <= st->tau2[0]) st->done[0] = 1;
+    st->all_done = st->done[0];
+  }
+  double a1 = 0, a2 = 0;
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < n; o += (int64_t)gridDim.x * 256) {
+    T v = x0[o];
+    if (dp) v += dp[o];
+    const double zv = (double)v;
+    z[o] = zv;
+    a1 += r[o] * zv;
+    if (q) a2 += q[o] * zv;
+  }
+  double* out = partials + 2 * g + (int64_t)blockIdx.x * 2;
+  column_partials<1>(a1, sh, out);
+  __syncthreads();
+  column_partials<1>(a2, sh, out + 1);
+}
+template <typename T>
+void launch_pcg_z1(int n, PcgState* st, bool check, const T* x0, const T* dpend, double* z, const double* r,
+                   const double* q, double* partials, hipStream_t s) {
+  const int g = pcg_grid(n);
+  hipLaunchKernelGGL((k_pcg_z1<T>), dim3(g), dim3(256), 0, s, n, st, check ? 1 : 0, x0, dpend, z, r, q, partials,
+                     g);
+  check_launch("k_pcg_z1");
+}
+template void launch_pcg_z1<float>(int, PcgState*, bool, const float*, const float*, double*, const double*,
+                                   const double*, double*, hipStream_t);
+template void launch_pcg_z1<double>(int, PcgState*, bool, const double*, const double*, double*, const double*,
+                                    const double*, double*, hipStream_t);
+
+// the stop test alone (from area 1), for an iteration enqueued as two halves
+void launch_pcg_check1(int n, PcgState* st, const double* partials, hipStream_t s) {
+  const int g = pcg_grid(n);
+  hipLaunchKernelGGL((k_pcg_check<1>), dim3(1), dim3(256), 0, s, st, partials + g, g);
+  check_launch("k_pcg_check");
+}
+
+// beta (standard <r, z> / gamma or flexible -alpha <q, z> / gamma, from area 2; block 0 records it); p = z + beta p
+__global__ __launch_bounds__(256) void k_pcg_p1(int n, PcgState* st, const double* __restrict__ z, double* p,
+                                                const double* __restrict__ partials, int g) {
+  __shared__ double sh[4];
+  __shared__ double rz[1], qz[1];
+  if (st->all_done || st->done[0]) return;
+  column_totals<1>(partials + 2 * g, g, 2, sh, rz);
+  column_totals<1>(partials + 2 * g + 1, g, 2, sh, qz);
+  const double gold = st->gamma[0];
+  const double be = st->flexible ? (-st->alpha[0] * qz[0]) / gold : rz[0] / gold;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->beta[0] = be;
+    const int j = st->iters[0] - 1;  // the stop test of iteration j has counted it
+    if (st->hist && j >= 0 && j < st->hist_rows) st->hist[(int64_t)(2 * j + 1) * kMaxNR] = be;
+  }
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < n; o += (int64_t)gridDim.x * 256)
+    p[o] = z[o] + be * p[o];
+}
+void launch_pcg_p1(int n, PcgState* st, const double* z, double* p, const double* partials, hipStream_t s) {
+  const int g = pcg_grid(n);
+  hipLaunchKernelGGL(k_pcg_p1, dim3(g), dim3(256), 0, s, n, st, z, p, partials, g);
+  check_launch("k_pcg_p1");
+}
+
 // ||b - q||^2 partials per column; with r set, r = b - q as well
 template <int NR>
 __global__ __launch_bounds__(256) void k_pcg_residual(int n, const double* __restrict__ b, const double* __restrict__ q,

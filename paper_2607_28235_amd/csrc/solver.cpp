@@ -1281,6 +1281,38 @@ void level_apply(HandleImpl& h, int level, const double* x, double* y, hipStream
   }
 }
 
+// q = A p in float64 for NR columns with the kernel PCG's operator uses (the matrix-free operator, the fine level's
+// single-RHS shape for float64, else the tuned multi-RHS kernel), without a dot product
+static void pcg_operator(Ctx& c, int NR, const double* p, double* q, const int* skip, hipStream_t s) {
+  Device& dv = c.dv;
+  DevLevel& D0 = dv.lv[0];
+  LevelOp<double> op64 = level_op<double>(c, 0);
+  if (D0.mf) {
+    apply_level<double>(c, 0, NR, p, nullptr, q, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
+    return;
+  }
+  if (NR == 1 && D0.fb[D0.shape].nrb > 0) {
+    launch_level_stream<double>(D0.shape64, D0.fb[D0.shape64], op64, p, nullptr, q, nullptr, nullptr, 0, 0,
+                                F_PLAIN | D0.keep64, skip, nullptr, s);
+    return;
+  }
+  auto it = dv.tuned.find({-1, NR * 2});
+  if (it != dv.tuned.end() && (it->second < 0 || it->second >= kCodeSplit)) {
+    op64.ptr = D0.rowptr.p;
+    op64.idx = D0.col.p;
+    const int cls = mr_class(NR, 8);
+    const bool ok = it->second < 0
+                        ? cls >= 0 && launch_level_lmr<double>(D0.mr[cls], op64, NR, it->second == -1, p, nullptr, q,
+                                                               nullptr, nullptr, 0.0, 0.0, F_PLAIN | D0.keep64, skip, s)
+                        : launch_split_code<double>(it->second, op64, NR, p, nullptr, q, nullptr, nullptr, 0.0, 0.0,
+                                                    F_PLAIN, skip, s);
+    if (!ok) throw std::runtime_error("multi-RHS fine-level kernel: unsupported shape");
+    return;
+  }
+  if (it != dv.tuned.end()) op64.lanes = it->second;
+  launch_level<double>(op64, NR, p, nullptr, q, nullptr, nullptr, 0.0, 0.0, F_PLAIN, skip, s);
+}
+
 // One PCG iteration (all launches skip once every column has converged).  part 0: the whole iteration; part 1:
 // q = A p, alpha, the x and r updates and the stop test; part 2: the V-cycle, z, beta and the new p.
 template <typename T>
@@ -1293,7 +1325,33 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s, int part
   DevLevel& D0 = dv.lv[0];
   LevelOp<double> op64 = level_op<double>(c, 0);
   const int n = (int)an.n;
-  need_partials(dv, (int64_t)kPcgBlocks * 2 * NR);
+  need_partials(dv, (int64_t)kPcgBlocks * std::max(2 * NR, 4));
+  if (NR == 1) {
+    // one column: q = A p, <p, q>, then alpha, the stop test and beta folded into the vector kernels that follow
+    // their reductions (4 launches besides the operator and the V-cycle)
+    double* P = dv.partials.p;
+    const T* dinv0;
+    if constexpr (sizeof(T) == 4) dinv0 = D0.dinv32.p; else dinv0 = D0.dinv64.p;
+    if (part != 2) {
+      pcg_operator(c, 1, dv.pp.p, dv.pq.p, skip, s);
+      launch_pcg_dot(n, dv.pp.p, dv.pq.p, P, st, s);
+      const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
+      T* b0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : nullptr;
+      launch_pcg_xr1<T>(n, st, dv.px.p, dv.pr.p, dv.pp.p, dv.pq.p, P, b0, dinv0, smooth0 ? vbuf<T>(D0.dA) : nullptr,
+                        2.0 / (D0.lam_hi + D0.lam_lo), s);
+      if (part == 1) {
+        launch_pcg_check1(n, st, P, s);
+        return;
+      }
+    }
+    const T* bl0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : reinterpret_cast<const T*>(dv.pr.p);
+    T* pend = nullptr;
+    if (L > 0) pend = vcycle_rec<T>(c, 0, 1, bl0, nullptr, s);
+    const T* x0 = (L > 0) ? vbuf<T>(D0.x) : bl0;
+    launch_pcg_z1<T>(n, st, part == 0, x0, pend, dv.pz.p, dv.pr.p, flexible ? dv.pq.p : nullptr, P, s);
+    launch_pcg_p1(n, st, dv.pz.p, dv.pp.p, P, s);
+    return;
+  }
   if (part != 2) {
     // q = A p, then alpha from <p, q> in the fixed partition of the dot kernel (the iterates do not depend on
     // the kernel that formed q), except after the lanes kernel, whose fused dot has its own partition
@@ -1367,8 +1425,8 @@ static void pcg_start(Ctx& c, int NR, int nb, double rtol, double atol, bool fle
   PcgState* st = reinterpret_cast<PcgState*>(dv.state.p);
   const int* skip = reinterpret_cast<const int*>(dv.state.p);
   DevLevel& D0 = dv.lv[0];
-  need_partials(dv, (int64_t)kPcgBlocks * 2 * NR);
-  apply_level<double>(c, 0, NR, dv.px.p, nullptr, dv.pq.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+  need_partials(dv, (int64_t)kPcgBlocks * std::max(2 * NR, 4));
+  pcg_operator(c, NR, dv.px.p, dv.pq.p, nullptr, s);
   launch_pcg_residual_init(n, NR, dv.pb.p, dv.pq.p, dv.pr.p, dv.partials.p, st, restart ? 1 : 0, rtol, atol, nb,
                            flexible ? 1 : 0, dv.hist.p, rhist_of(dv), dv.hist_rows, s);
   const bool smooth0 = (L > 0) && an.opt.pre_steps > 0;
@@ -1381,7 +1439,9 @@ static void pcg_start(Ctx& c, int NR, int nb, double rtol, double atol, bool fle
   T* pend = nullptr;
   if (L > 0) pend = vcycle_rec<T>(c, 0, NR, bl0, nullptr, s);
   const T* x0 = (L > 0) ? vbuf<T>(D0.x) : bl0;
-  launch_pcg_z<T>(n, NR, st, 1, x0, pend, dv.pz.p, dv.pr.p, nullptr, dv.pp.p, dv.partials.p, s);
+  // one column: <r, z> partials in area 2, where the first iteration's alpha kernel forms gamma from them
+  double* zpart = NR == 1 ? dv.partials.p + 2 * pcg_blocks(n) : dv.partials.p;
+  launch_pcg_z<T>(n, NR, st, 1, x0, pend, dv.pz.p, dv.pr.p, nullptr, dv.pp.p, zpart, s);
 }
 
 template <typename T>
@@ -1511,7 +1571,7 @@ static r3mg_status pcg_block(HandleImpl& h, const double* b, double* x, int c0, 
   auto finish_chunk = [&]() {
     if (flexible) {
       // true residual of x (into z, which the next iteration's second half rewrites before reading it)
-      apply_level<double>(c, 0, NR, dv.px.p, nullptr, dv.pz.p, nullptr, nullptr, 0, 0, F_PLAIN, nullptr, s);
+      pcg_operator(c, NR, dv.px.p, dv.pz.p, nullptr, s);
       launch_pcg_true_residual(n, NR, dv.pb.p, dv.pz.p, dv.partials.p, dst, s);
     }
     launch_scatter_cols(n, NR, nb, dv.perm.p, dv.px.p, x + (int64_t)c0 * n, n, s);
