@@ -153,6 +153,53 @@ def test_time_smoother_kernel_nrhs(small3d_q3, kernel):
     h.close()
 
 
+@pytest.fixture(scope="module")
+def cfg4_24():
+    """Config 4 at 24^3 cells (389,017 DoFs, 16 right-hand sides) with at most 500 coarse DoFs: levels 389,017 /
+    6,912 / 864 / 108, the same level kinds as the 48^3 workload (CSR fine level, two block-row levels, dense
+    coarsest); the oracle's solutions of columns 0 and 15."""
+    _need_gpu()
+    _case("config 4 at 24^3 inputs and oracle")
+    w = F.workload(4, scale=24)
+    prob = w.problem
+    ho = O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=2, leaf_size=256, max_coarse_dofs=500,
+                           skip_leaf_level=True)
+    ref = {j: (O.pcg(ho, w.rhs[j], rtol=1e-10)[1], O.pcg(ho, w.rhs[j], rtol=1e-13)[0]) for j in (0, 15)}
+    return w, ho, ref
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("fp32", [1, 0])
+def test_config4_reduced_with_full_size_kernels(cfg4_24, fp32):
+    """Config 4 at 24^3 with the kernels r3mg_info names for the 48^3 workload: the fine level's 2048-nonzero CSR
+    row-block kernel (the shape the timing picks at 48^3, pinned here), the block-row workgroup kernel on both
+    agglomerated levels, the dense coarsest inverse; the 16-column multi-RHS kernels as timed.  Lockstep PCG of
+    the 16 columns: columns 0 and 15 against the oracle (iterations within one, solution within 1e-9 of the
+    rtol-1e-13 solution), every column's true residual at the stop rule."""
+    import paper_2607_28235_amd as P
+    w, ho, ref = cfg4_24
+    prob = w.problem
+    _case(f"config 4 at 24^3 fp32={fp32}")
+    o = P.Options(dim=3, coarse_degree=2, leaf_size=256, max_coarse_dofs=500, skip_leaf_level=1, fine_kernel=0,
+                  vcycle_fp32=fp32)
+    h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o)
+    t = "float" if fp32 else "double"
+    info = h.info()
+    assert [lv["n"] for lv in info] == [lv.A.shape[0] for lv in ho.levels] == [389017, 6912, 864, 108]
+    assert [lv["kernel"] for lv in info] == [f"k_level_stream<{t},2048,64,block>", f"k_level_blockrow_wg<{t}>",
+                                             f"k_level_blockrow_wg<{t}>", "dense"]
+    X = torch.zeros(16, prob.n, dtype=torch.float64, device="cuda")
+    iters, relres, ok = h.pcg(_t(w.rhs), X, rtol=1e-10, maxit=200)
+    assert ok
+    Xh = X.cpu().numpy()
+    for j, (ko, xt) in ref.items():
+        assert abs(int(iters[j]) - ko) <= 1, (j, iters[j], ko)
+        assert _rel(Xh[j], xt) < 1e-9, j
+    R = w.rhs - (prob.scipy() @ Xh.T).T
+    assert np.all(np.linalg.norm(R, axis=1) <= 1.01e-10 * np.linalg.norm(w.rhs, axis=1))
+    h.close()
+
+
 def test_uneven_group_in_one_graph():
     """Several independent problems of different sizes solved in one captured launch sequence."""
     _need_gpu()

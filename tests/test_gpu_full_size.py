@@ -11,6 +11,8 @@ The oracle needs minutes at these sizes, so its outputs were computed once by te
   the loss against the oracle, the adjoint gradient against the oracle's at the 32 seeded cells and at 1024
   sampled cells, central differences on the 32 cells, and the Euler identity sum_e kappa_e g_e = -(u - u_t)^T u.
 
+The host analysis of the cube (partition, box bounds, fine transfer) is compared with the oracle's in full.
+
 A relative 2-norm error is estimated from the samples: sqrt(n / m * sum over the m samples of the squared
 difference) / (the reference's 2-norm).
 """
@@ -59,6 +61,43 @@ def cube():
     _case("full-size 3D Q2 64^3 inputs")
     w = F.workload(3)
     return w, _gold(3)
+
+
+def test_full_size_3d_q2_partition(cube):
+    """Host analysis of the same cube (no device work): constrained set, level sizes, every level's partition and
+    box bounds and the fine transfer's sparsity bit-exact against the oracle, its values to 1e-15 (the oracle's
+    Galerkin products are left out at this size; the V-cycle tests below compare the operators' action)."""
+    import paper_2607_28235_amd as P
+    from oracle import hierarchy as OH, rtree as ORT
+    w, gold = cube
+    prob = w.problem
+    _case("full-size 3D Q2 64^3 partition against the oracle")
+    h = P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val,
+                    P.Options(dim=3, coarse_degree=w.coarse_degree, leaf_size=w.leaf_size,
+                              max_coarse_dofs=w.max_coarse_dofs, skip_leaf_level=int(w.skip_leaf_level)),
+                    factor=False)
+    C = OH.constrained_set(prob.scipy())
+    np.testing.assert_array_equal(C, prob.boundary)
+    tree = ORT.bisection_rtree(prob.coords, w.leaf_size)
+    B = (w.coarse_degree + 1) ** 3
+    depths = ORT.select_levels(tree, 3, B, max_levels=w.max_levels, max_coarse_dofs=w.max_coarse_dofs,
+                               skip_leaf_level=bool(w.skip_leaf_level))
+    info = h.info()
+    assert [lv["n"] for lv in info] == gold["levels"] and len(info) == len(depths) + 1
+    for l, dep in enumerate(depths, start=1):
+        own, lo, hi = h.export_partition(l)
+        olo, ohi = tree.boxes(prob.coords, dep)
+        np.testing.assert_array_equal(own, tree.owner(dep))
+        np.testing.assert_array_equal(lo, olo)
+        np.testing.assert_array_equal(hi, ohi)
+        assert info[l]["n"] == olo.shape[0] * B
+    olo, ohi = tree.boxes(prob.coords, depths[0])
+    ip, ix, dt = OH.prolongation_fine(prob.coords, C, tree.owner(depths[0]), olo, ohi, w.coarse_degree)
+    rp, cl, vl = h.export_P(0)
+    np.testing.assert_array_equal(rp, ip)
+    np.testing.assert_array_equal(cl, ix)
+    np.testing.assert_allclose(vl, dt, rtol=0, atol=1e-15)
+    h.close()
 
 
 @pytest.mark.parametrize("fp32", [0, 1])

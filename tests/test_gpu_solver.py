@@ -207,6 +207,42 @@ def test_box_row_kernel_other_box_sizes(pc):
         assert np.linalg.norm(res) <= 1.01e-10 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("pc,N,p,leaf,mc", [(1, 10, 3, 64, 300), (3, 12, 2, 256, 2000)])
+def test_3d_coarse_kernels_other_box_sizes(pc, N, p, leaf, mc):
+    """3D with p' = 1 (boxes of 8 functions: Q3 10^3, levels 29,791 / 4,096 / 512 / 64) and p' = 3 (boxes of 64:
+    Q2 12^3, levels 15,625 / 4,096 / 512): the agglomerated levels' kernels, the restriction and prolongation
+    between them and the coarsest solve with B != 27.  Float64 V-cycle against the oracle; PCG in both V-cycle
+    precisions against the oracle's iterations and rtol-1e-13 solution."""
+    _need_gpu()
+    _case(f"3D Q{p} {N}^3, p'={pc}, leaf {leaf}, <= {mc} coarse DoFs")
+    P = _P()
+    prob = F.structured_qp(3, N, p, cfg=4)
+    b = F.nodal_rhs(prob, F.rng(4, F.PURPOSE_RHS).standard_normal(prob.n), cfg=4)
+    c = Case(prob, b, pc, leaf, 0, 2, 2, max_coarse=mc)
+    info = c.h.info()
+    assert [lv["n"] for lv in info] == [lv.A.shape[0] for lv in c.ho.levels]
+    assert len(info) >= 3 and all(lv["n"] % (pc + 1) ** 3 == 0 for lv in info[1:])
+    g = np.random.default_rng(11)
+    r = g.standard_normal(prob.n)
+    r[c.ho.constrained] = 0.0
+    z = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+    c.h.vcycle(_t(r), z)
+    torch.cuda.synchronize()
+    assert _rel(z.cpu().numpy(), O.vcycle(c.ho, r)) < 1e-11
+    _, ko, _, _, _ = O.pcg(c.ho, b, rtol=1e-10)
+    x_tight = O.pcg(c.ho, b, rtol=1e-13)[0]
+    import dataclasses
+    for h in (c.h, P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val,
+                               dataclasses.replace(c.opts, vcycle_fp32=1))):
+        x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        iters, _, ok = h.pcg(_t(b), x, rtol=1e-10, maxit=200)
+        assert ok and abs(int(iters[0]) - ko) <= 1, (iters, ko)
+        xs = x.cpu().numpy()
+        assert _rel(xs, x_tight) < 1e-9
+        res = b - prob.scipy() @ xs
+        assert np.linalg.norm(res) <= 1.01e-10 * np.linalg.norm(b)
+
+
 @pytest.mark.parametrize("name", ["cfg1", "small2d", "small3d"])
 def test_vcycle_symmetric_positive_on_gpu(name, request):
     c = request.getfixturevalue(name)
