@@ -178,10 +178,22 @@ void launch_dense_apply(int nc, int nr, const double* cinv, const T* b, T* x, co
 constexpr int kDenseTile = 64;
 constexpr int kDenseSymMaxTiles = 160;  // coarsest sizes up to 10,240: 422 MB of packed tiles at most
 constexpr int kDenseSymMaxNR = 4;
-void launch_dense_pack_sym(int nc, int ntiles, const double* full, const int* tiles, double* packed, hipStream_t s);
+// packs the upper tiles of the full inverse, rounded to M (float64, or float32 for the float32 V-cycle)
+template <typename M>
+void launch_dense_pack_sym(int nc, int ntiles, const double* full, const int* tiles, M* packed, hipStream_t s);
+// Prolongation fused into pass 2: the coarsest level's x (box G = rows G*B .. G*B+B-1) goes on to the level above
+// as v[C*B+q'] = sum_q P~_C[q'][q] x[G*B+q] for the children C of G (nbox boxes there, child_shift shift), in
+// k_prolong_c's order.
 template <typename T>
-void launch_dense_apply_sym(int nc, int nt, int nr, const double* packed, const int* tiles, double* part,
-                            const T* b, T* x, const int* skip, hipStream_t s);
+struct DenseProlong {
+  int nbox_coarse = 0;  // boxes of the coarsest level
+  int nbox = 0, shift = 0, d = 2, pc = 1;
+  const T* pt = nullptr;
+  T* v = nullptr;
+};
+template <typename T, typename M>
+void launch_dense_apply_sym(int nc, int nt, int nr, const M* packed, const int* tiles, double* part, const T* b,
+                            T* x, const DenseProlong<T>* pr, const int* skip, hipStream_t s);
 void launch_gather_cols(int n, int nr, int nuser, const int* perm, const double* user, int64_t ld_user,
                         double* out, hipStream_t s);
 void launch_scatter_cols(int n, int nr, int nuser, const int* perm, const double* in, double* user,

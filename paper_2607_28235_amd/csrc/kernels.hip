@@ -2016,6 +2016,21 @@ int launch_spmv_dot(const LevelOp<double>& op, int nr, const double* p, double* 
 // =============================================================================================
 // Transfers
 // =============================================================================================
+// Several right-hand sides (nr > 1, interleaved: entry i of column c at i * nr + c): the transfer kernels below
+// give each thread a chunk of VW = min(nr, 16 bytes / sizeof(T)) adjacent columns, loaded and stored as one
+// vector, so the basis functions and transfer entries are formed once per chunk instead of once per column.
+// Each column is summed in the same order as the one-column kernel, except k_restrict0_mr (points in index order).
+template <typename T, int W>
+struct ColVec {
+  typedef T type __attribute__((ext_vector_type(W)));
+};
+template <typename T>
+constexpr int col_vw() {
+  return 16 / (int)sizeof(T);
+}
+// the vector path needs 16-byte aligned vectors (always so for the library's buffers)
+static inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 // Restriction to the first agglomerated level: b1[K*B+q] = sum_{i in K, i free} phi^K_q(xi_i) src_i.
 // One workgroup of W waves per box (W = 1, 2 or 4: about one per 128-point chunk of an average box).  Wave w takes the box's points in chunks of 128
 // (chunk w, w + W, ...), two points per lane: the lane's two products per q go to LDS ([q][lane]), then
@@ -2096,6 +2111,74 @@ __global__ __launch_bounds__(256) void k_restrict0(Basis1D<T> bs, int nr, const 
   }
 }
 
+// Restriction to the first agglomerated level for nr > 1 columns: one workgroup per box K, thread (g, j) takes the
+// KB consecutive coarse functions q = KB g .. KB g + KB - 1 (same q1, q2) and column chunk j.  The box's points go
+// through LDS 32 at a time: their 1D basis values (one thread per point) and their nr entries of src (zero at
+// constrained points); each thread then adds phi_q(xi_i) src_i over the 32 points in index order, phi_q formed as
+// l0[q0] (l1[q1] l2[q2]).
+template <typename T, int D, int KB, int VW>
+__global__ __launch_bounds__(512) void k_restrict0_mr(Basis1D<T> bs, int nr, const int* __restrict__ leaf_off,
+                                                      const int* __restrict__ owner, const T* __restrict__ xi,
+                                                      const T* __restrict__ src, T* bnext,
+                                                      const T* __restrict__ dinv_next, T* dnext, T inv_theta_next,
+                                                      const int* __restrict__ skip) {
+  using VT = typename ColVec<T, VW>::type;
+  constexpr int B = D == 3 ? KB * KB * KB : KB * KB;
+  constexpr int P = 32;
+  constexpr int LW = D * KB;  // 1D values per point
+  if (skip && *skip) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  VT* ss = reinterpret_cast<VT*>(smem_raw);                 // [P][nch] entries of src
+  const int nch = nr / VW;
+  T* lt = reinterpret_cast<T*>(ss + P * nch);               // [P][LW] 1D values
+  const int K = blockIdx.x;
+  const int i0 = leaf_off[K], i1 = leaf_off[K + 1];
+  const int g = threadIdx.x / nch, j = threadIdx.x - g * nch;
+  const bool active = g < B / KB;
+  const int q1 = g % KB, q2 = g / KB;
+  VT acc[KB];
+#pragma unroll
+  for (int a = 0; a < KB; ++a) acc[a] = (VT)0;
+  for (int base = i0; base < i1; base += P) {
+    const int np = min(P, i1 - base);
+    for (int t = threadIdx.x; t < np * nch; t += blockDim.x) {
+      const int pp = t / nch, jj = t - pp * nch;
+      const int i = base + pp;
+      ss[t] = owner[i] >= 0 ? *reinterpret_cast<const VT*>(src + (int64_t)i * nr + jj * VW) : (VT)0;
+    }
+    if (threadIdx.x < np) {
+      const int i = base + threadIdx.x;
+      T l[3][4];
+#pragma unroll
+      for (int a = 0; a < D; ++a) lag1d_k<T, KB>(bs, xi[(int64_t)i * D + a], l[a]);
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int m = 0; m < KB; ++m) lt[threadIdx.x * LW + a * KB + m] = l[a][m];
+    }
+    __syncthreads();
+    if (active) {
+      for (int pp = 0; pp < np; ++pp) {
+        const T* lp = lt + pp * LW;
+        T l12 = lp[KB + q1];
+        if (D == 3) l12 *= lp[2 * KB + q2];
+        const VT sv = ss[pp * nch + j];
+#pragma unroll
+        for (int a = 0; a < KB; ++a) acc[a] += (lp[a] * l12) * sv;
+      }
+    }
+    __syncthreads();
+  }
+  if (active) {
+#pragma unroll
+    for (int a = 0; a < KB; ++a) {
+      const int64_t row = (int64_t)K * B + g * KB + a;
+      *reinterpret_cast<VT*>(bnext + row * nr + j * VW) = acc[a];
+      if (dnext) *reinterpret_cast<VT*>(dnext + row * nr + j * VW) = (dinv_next[row] * acc[a]) * inv_theta_next;
+    }
+  }
+}
+
 template <typename T>
 void launch_restrict0(int nbox, int64_t n_points, int d, int pc, int nr, const int* leaf_off, const int* owner,
                       const T* xi, const T* src, T* bnext, const T* dinv_next, T* dnext, double inv_theta_next,
@@ -2109,6 +2192,36 @@ void launch_restrict0(int nbox, int64_t n_points, int d, int pc, int nr, const i
   auto lds = [&](int w) { return sizeof(T) * ((size_t)w * (B * 65 + 64) + (size_t)w * 64); };
   while (W > 1 && lds(W) > 65536) W >>= 1;
   const Basis1D<T> bs = make_basis<T>(pc);
+  constexpr int VW = col_vw<T>();
+  if (nr > 1 && nr % std::min(nr, VW) == 0 && aligned16(src) && aligned16(bnext) && (!dnext || aligned16(dnext))) {
+    const int vw = std::min(nr, VW), nch = nr / vw;
+    const int thr = ((B / k) * nch + 63) / 64 * 64;
+    if (thr > 512) throw std::runtime_error("restriction: too many columns");
+    const size_t shm = sizeof(T) * ((size_t)32 * nr + (size_t)32 * d * k);
+#define R3MG_R0M(DD, KK)                                                                                           \
+  do {                                                                                                             \
+    if (vw == 2)                                                                                                   \
+      hipLaunchKernelGGL((k_restrict0_mr<T, DD, KK, 2>), dim3(nbox), dim3(thr), shm, s, bs, nr, leaf_off, owner, xi, \
+                         src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);                                     \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_restrict0_mr<T, DD, KK, VW>), dim3(nbox), dim3(thr), shm, s, bs, nr, leaf_off, owner,    \
+                         xi, src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);                                 \
+  } while (0)
+    switch (d * 8 + k) {
+      case 17: R3MG_R0M(2, 1); break;
+      case 18: R3MG_R0M(2, 2); break;
+      case 19: R3MG_R0M(2, 3); break;
+      case 20: R3MG_R0M(2, 4); break;
+      case 25: R3MG_R0M(3, 1); break;
+      case 26: R3MG_R0M(3, 2); break;
+      case 27: R3MG_R0M(3, 3); break;
+      case 28: R3MG_R0M(3, 4); break;
+      default: throw std::runtime_error("restriction: unsupported dimension or degree");
+    }
+#undef R3MG_R0M
+    check_launch("k_restrict0_mr");
+    return;
+  }
 #define R3MG_R0(DD, KK)                                                                                           \
   hipLaunchKernelGGL((k_restrict0<T, DD, KK>), dim3(nbox), dim3(64 * W), lds(W), s, bs, nr, leaf_off, owner, xi, src, \
                      bnext, dinv_next, dnext, (T)inv_theta_next, skip)
@@ -2165,12 +2278,75 @@ __global__ __launch_bounds__(256) void k_prolong0(int n, Basis1D<T> bs, int nr, 
   }
 }
 
+// The same for nr > 1 columns: thread (i, j) takes fine point i and column chunk j (chunks of one point adjacent).
+template <typename T, int D, int KB, int VW>
+__global__ __launch_bounds__(256) void k_prolong0_mr(int n, Basis1D<T> bs, int nr, const int* __restrict__ owner,
+                                                     const T* __restrict__ xi, const T* __restrict__ e,
+                                                     const T* __restrict__ epend, T* v, const int* __restrict__ skip,
+                                                     int nlog) {
+  using VT = typename ColVec<T, VW>::type;
+  constexpr int B = D == 3 ? KB * KB * KB : KB * KB;
+  if (skip && *skip) return;
+  const int lb = xcd_block(nlog);
+  if (lb < 0) return;
+  const int nch = nr / VW;
+  const int64_t t = (int64_t)lb * 256 + threadIdx.x;
+  if (t >= (int64_t)n * nch) return;
+  const int i = (int)(t / nch), j = (int)(t - (int64_t)i * nch);
+  VT* out = reinterpret_cast<VT*>(v + (int64_t)i * nr + j * VW);
+  const int K = owner[i];
+  if (K < 0) {
+    *out = (VT)0;
+    return;
+  }
+  T l[3][4];
+#pragma unroll
+  for (int a = 0; a < D; ++a) lag1d_k<T, KB>(bs, xi[(int64_t)i * D + a], l[a]);
+  VT sum = (VT)0;
+  for_each_phi<T, D, KB>(l, [&](int q, T ph) {
+    const int64_t o = ((int64_t)K * B + q) * nr + j * VW;
+    VT ev = *reinterpret_cast<const VT*>(e + o);
+    if (epend) ev += *reinterpret_cast<const VT*>(epend + o);
+    sum += ph * ev;
+  });
+  *out = sum;
+}
+
 template <typename T>
 void launch_prolong0(int n, int d, int pc, int nr, const int* owner, const T* xi, const T* e, const T* epend,
                      T* v, const int* skip, hipStream_t s) {
+  const Basis1D<T> bs = make_basis<T>(pc);
+  constexpr int VW = col_vw<T>();
+  if (nr > 1 && nr % std::min(nr, VW) == 0 && aligned16(e) && (!epend || aligned16(epend)) && aligned16(v)) {
+    const int vw = std::min(nr, VW), nch = nr / vw;
+    const int nlogm = (int)(((int64_t)n * nch + 255) / 256);
+    if (nlogm == 0) return;
+#define R3MG_P0M(DD, KK)                                                                                            \
+  do {                                                                                                              \
+    if (vw == 2)                                                                                                    \
+      hipLaunchKernelGGL((k_prolong0_mr<T, DD, KK, 2>), dim3(xcd_grid(nlogm)), dim3(256), 0, s, n, bs, nr, owner, xi, \
+                         e, epend, v, skip, nlogm);                                                                   \
+    else                                                                                                            \
+      hipLaunchKernelGGL((k_prolong0_mr<T, DD, KK, VW>), dim3(xcd_grid(nlogm)), dim3(256), 0, s, n, bs, nr, owner,    \
+                         xi, e, epend, v, skip, nlogm);                                                               \
+  } while (0)
+    switch (d * 8 + pc + 1) {
+      case 17: R3MG_P0M(2, 1); break;
+      case 18: R3MG_P0M(2, 2); break;
+      case 19: R3MG_P0M(2, 3); break;
+      case 20: R3MG_P0M(2, 4); break;
+      case 25: R3MG_P0M(3, 1); break;
+      case 26: R3MG_P0M(3, 2); break;
+      case 27: R3MG_P0M(3, 3); break;
+      case 28: R3MG_P0M(3, 4); break;
+      default: throw std::runtime_error("prolongation: unsupported dimension or degree");
+    }
+#undef R3MG_P0M
+    check_launch("k_prolong0_mr");
+    return;
+  }
   const int nlog = (n + 255) / 256;
   if (nlog == 0) return;
-  const Basis1D<T> bs = make_basis<T>(pc);
 #define R3MG_P0(DD, KK)                                                                                            \
   hipLaunchKernelGGL((k_prolong0<T, DD, KK>), dim3(xcd_grid(nlog)), dim3(256), 0, s, n, bs, nr, owner, xi, e, epend, v, \
                      skip, nlog)
@@ -2267,6 +2443,54 @@ __global__ __launch_bounds__(256) void k_restrict_c(int nbox_next, int nbox, int
   }
 }
 
+// The same for nr > 1 columns: one workgroup per parent box G, thread (q, j) takes coarse function q and column
+// chunk j.  The children's 1D injection factors are staged in LDS once, each child's B x nr entries (contiguous in
+// src) one child at a time.
+template <typename T, int VW>
+__global__ __launch_bounds__(512) void k_restrict_c_mr(int nbox_next, int nbox, int shift, int d, int k, int nr,
+                                                       const T* __restrict__ pt, const T* __restrict__ src, T* bnext,
+                                                       const T* __restrict__ dinv_next, T* dnext, T inv_theta_next,
+                                                       const int* __restrict__ skip) {
+  using VT = typename ColVec<T, VW>::type;
+  if (skip && *skip) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int kk = k * k;
+  const int nch = nr / VW;
+  VT* srcs = reinterpret_cast<VT*>(smem_raw);  // [B][nch] of the current child
+  T* pts = reinterpret_cast<T*>(srcs + B * nch);
+  const int G = blockIdx.x;
+  const int c0 = G << shift;
+  const int nc = min(nbox, (G + 1) << shift) - c0;
+  for (int t = threadIdx.x; t < nc * d * kk; t += blockDim.x) pts[t] = pt[(int64_t)c0 * d * kk + t];
+  const int q = threadIdx.x / nch, j = threadIdx.x - q * nch;
+  const bool active = q < B;
+  const int q0 = q % k, q1 = (q / k) % k, q2 = q / kk;
+  VT acc = (VT)0;
+  for (int C = 0; C < nc; ++C) {
+    __syncthreads();
+    const VT* sg = reinterpret_cast<const VT*>(src + (int64_t)(c0 + C) * B * nr);
+    for (int t = threadIdx.x; t < B * nch; t += blockDim.x) srcs[t] = sg[t];
+    __syncthreads();
+    if (active) {
+      const T* m = pts + C * d * kk;
+      int qc = 0;
+      for (int a2 = 0; a2 < (d == 3 ? k : 1); ++a2)
+        for (int a1 = 0; a1 < k; ++a1)
+          for (int a0 = 0; a0 < k; ++a0, ++qc) {
+            T w = m[a0 * k + q0] * m[kk + a1 * k + q1];
+            if (d == 3) w *= m[2 * kk + a2 * k + q2];
+            acc += w * srcs[qc * nch + j];
+          }
+    }
+  }
+  if (active) {
+    const int64_t row = (int64_t)G * B + q;
+    *reinterpret_cast<VT*>(bnext + row * nr + j * VW) = acc;
+    if (dnext) *reinterpret_cast<VT*>(dnext + row * nr + j * VW) = (dinv_next[row] * acc) * inv_theta_next;
+  }
+}
+
 template <typename T>
 void launch_restrict_c(int nbox_next, int nbox, int shift, int d, int pc, int nr, const T* pt, const T* src,
                        T* bnext, const T* dinv_next, T* dnext, double inv_theta_next, const int* skip,
@@ -2275,6 +2499,21 @@ void launch_restrict_c(int nbox_next, int nbox, int shift, int d, int pc, int nr
   const int B = (d == 3) ? k * k * k : k * k;
   if (nbox_next == 0) return;
   if (B > 64) throw std::runtime_error("restriction: more than 64 coarse functions per box");
+  constexpr int VW = col_vw<T>();
+  if (nr > 1 && nr % std::min(nr, VW) == 0 && aligned16(src) && aligned16(bnext) && (!dnext || aligned16(dnext))) {
+    const int vw = std::min(nr, VW), nch = nr / vw;
+    const int thr = (B * nch + 63) / 64 * 64;
+    if (thr > 512) throw std::runtime_error("restriction: too many columns");
+    const size_t shmm = sizeof(T) * ((size_t)B * nr + (size_t)(1 << shift) * d * k * k);
+    if (vw == 2)
+      hipLaunchKernelGGL((k_restrict_c_mr<T, 2>), dim3(nbox_next), dim3(thr), shmm, s, nbox_next, nbox, shift, d, k, nr,
+                         pt, src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);
+    else
+      hipLaunchKernelGGL((k_restrict_c_mr<T, VW>), dim3(nbox_next), dim3(thr), shmm, s, nbox_next, nbox, shift, d, k,
+                         nr, pt, src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);
+    check_launch("k_restrict_c_mr");
+    return;
+  }
   const size_t shm = sizeof(T) * (size_t)4 * (1 << shift) * (B + d * k * k);
   hipLaunchKernelGGL((k_restrict_c<T>), dim3((unsigned)((nbox_next + 3) / 4)), dim3(256), shm, s, nbox_next, nbox, shift,
                      d, k, nr, pt, src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);
@@ -2308,11 +2547,50 @@ __global__ __launch_bounds__(256) void k_prolong_c(int nbox, int shift, int d, i
   }
 }
 
+// The same for nr > 1 columns: thread (C B + q', j) takes one fine entry and column chunk j.
+template <typename T, int VW>
+__global__ __launch_bounds__(256) void k_prolong_c_mr(int nbox, int shift, int d, int k, int nr,
+                                                      const T* __restrict__ pt, const T* __restrict__ e,
+                                                      const T* __restrict__ epend, T* v, const int* __restrict__ skip) {
+  using VT = typename ColVec<T, VW>::type;
+  if (skip && *skip) return;
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int nch = nr / VW;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)nbox * B * nch) return;
+  const int64_t row = t / nch;
+  const int j = (int)(t - row * nch);
+  const int C = (int)(row / B), qc = (int)(row - (int64_t)C * B);
+  const int G = C >> shift;
+  VT sum = (VT)0;
+  for (int q = 0; q < B; ++q) {
+    const int64_t o = ((int64_t)G * B + q) * nr + j * VW;
+    VT ev = *reinterpret_cast<const VT*>(e + o);
+    if (epend) ev += *reinterpret_cast<const VT*>(epend + o);
+    sum += pt_entry(pt, C, d, k, qc, q) * ev;
+  }
+  *reinterpret_cast<VT*>(v + row * nr + j * VW) = sum;
+}
+
 template <typename T>
 void launch_prolong_c(int nbox, int shift, int d, int pc, int nr, const T* pt, const T* e, const T* epend, T* v,
                       const int* skip, hipStream_t s) {
   const int k = pc + 1;
   const int B = (d == 3) ? k * k * k : k * k;
+  constexpr int VW = col_vw<T>();
+  if (nr > 1 && nr % std::min(nr, VW) == 0 && aligned16(e) && (!epend || aligned16(epend)) && aligned16(v)) {
+    const int vw = std::min(nr, VW);
+    const int64_t totm = (int64_t)nbox * B * (nr / vw);
+    if (totm == 0) return;
+    if (vw == 2)
+      hipLaunchKernelGGL((k_prolong_c_mr<T, 2>), dim3((unsigned)((totm + 255) / 256)), dim3(256), 0, s, nbox, shift, d,
+                         k, nr, pt, e, epend, v, skip);
+    else
+      hipLaunchKernelGGL((k_prolong_c_mr<T, VW>), dim3((unsigned)((totm + 255) / 256)), dim3(256), 0, s, nbox, shift,
+                         d, k, nr, pt, e, epend, v, skip);
+    check_launch("k_prolong_c_mr");
+    return;
+  }
   const int64_t tot = (int64_t)nbox * B;
   hipLaunchKernelGGL((k_prolong_c<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nbox, shift, d, k, nr, pt,
                      e, epend, v, skip);
@@ -2436,12 +2714,13 @@ template void launch_dense_apply<float>(int, int, const double*, const float*, f
 template void launch_dense_apply<double>(int, int, const double*, const double*, double*, const int*, hipStream_t);
 
 // Symmetric dense coarsest product.  Pass 1: one workgroup per upper tile (I, J); wave w holds the tile's rows
-// 16 w .. 16 w + 15 in registers, lane = column.  The row products are summed over the 64 lanes by a transposing
+// 16 w .. 16 w + 15 in registers (stored as M = float64, or float32 for the float32 V-cycle, and widened to
+// float64: the products and partial sums are float64 either way), lane = column.  The row products are summed over the 64 lanes by a transposing
 // butterfly (each step halves the rows a lane keeps and doubles the columns summed), which leaves lane l with
 // row 8 b5 + 4 b4 + 2 b3 + b2 of its wave (b = bits of l); the transposed products of an off-diagonal tile are
 // summed over the four waves in order.
-template <typename T, int NR>
-__global__ __launch_bounds__(256) void k_dense_sym_tiles(int nc, int nt, const double* __restrict__ packed,
+template <typename T, typename M, int NR>
+__global__ __launch_bounds__(256) void k_dense_sym_tiles(int nc, int nt, const M* __restrict__ packed,
                                                          const int2* __restrict__ tiles, const T* __restrict__ b,
                                                          double* part, const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -2450,10 +2729,10 @@ __global__ __launch_bounds__(256) void k_dense_sym_tiles(int nc, int nt, const d
   const int2 ij = tiles[t];
   const int I = ij.x, J = ij.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double* a = packed + (int64_t)t * (kDenseTile * kDenseTile) + (16 * w) * kDenseTile + lane;
+  const M* a = packed + (int64_t)t * (kDenseTile * kDenseTile) + (16 * w) * kDenseTile + lane;
   double m[16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) m[k] = a[k * kDenseTile];
+  for (int k = 0; k < 16; ++k) m[k] = (double)a[k * kDenseTile];
   const int cj = J * kDenseTile + lane;
   const int ri = I * kDenseTile + 16 * w;
   const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
@@ -2494,8 +2773,24 @@ __global__ __launch_bounds__(256) void k_dense_sym_tiles(int nc, int nt, const d
   }
 }
 
-// Pass 2: rows 16 Q .. 16 Q + 15 of row block R = blockIdx.x / 4 (Q = blockIdx.x % 4) sum their nt slots: slot
-// S is taken by group S % 16 in index order, then the 16 groups are added in order.
+// Pass 2: the sum of row `row`'s nt slots, as taken by thread (g, i) of a 16 x 16 group (g = slot group, i =
+// row): slot S is taken by group S % 16 in index order, the group sums go to sh[g][i], and sum16 adds the 16 groups
+// in order.
+__device__ inline double dense_slot_sum(int nt, const double* __restrict__ part, int row, int g, int nr, int c) {
+  const int R = row / kDenseTile, i = row - R * kDenseTile;
+  double acc = 0;
+#pragma unroll 4
+  for (int S = g; S < nt; S += 16) acc += part[(((int64_t)R * nt + S) * kDenseTile + i) * nr + c];
+  return acc;
+}
+__device__ inline double dense_sum16(const double (*sh)[17], int i) {
+  double t = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) t += sh[k][i];
+  return t;
+}
+
+// Pass 2 alone: rows 16 Q .. 16 Q + 15 of row block R = blockIdx.x / 4 (Q = blockIdx.x % 4).
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_dense_sym_reduce(int nc, int nt, const double* __restrict__ part, T* x,
                                                           const int* __restrict__ skip) {
@@ -2504,45 +2799,92 @@ __global__ __launch_bounds__(256) void k_dense_sym_reduce(int nc, int nt, const 
   const int R = blockIdx.x >> 2, i = 16 * (blockIdx.x & 3) + (threadIdx.x & 15), g = threadIdx.x >> 4;
   const int row = R * kDenseTile + i;
   for (int c = 0; c < NR; ++c) {
-    double acc = 0;
-#pragma unroll 4
-    for (int S = g; S < nt; S += 16) acc += part[(((int64_t)R * nt + S) * kDenseTile + i) * NR + c];
-    sh[g][threadIdx.x & 15] = acc;
+    sh[g][threadIdx.x & 15] = dense_slot_sum(nt, part, row, g, NR, c);
     __syncthreads();
-    if (g == 0 && row < nc) {
-      double t = 0;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) t += sh[k][threadIdx.x & 15];
-      x[(int64_t)row * NR + c] = (T)t;
-    }
+    if (g == 0 && row < nc) x[(int64_t)row * NR + c] = (T)dense_sum16(sh, threadIdx.x & 15);
     __syncthreads();
   }
 }
 
+// Pass 2 fused with the prolongation to the level above (k_prolong_c with no pending direction): one workgroup
+// per parent box G of that level (= box G of the coarsest level, B rows).  Its B rows of x are summed from the
+// slots as in k_dense_sym_reduce (16 rows at a time), stored, and kept in LDS; then thread (C, q') of G's
+// children forms v[C*B+q'] = sum_q P~_C[q'][q] x[G*B+q] in ascending q.
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_dense_sym_reduce_prolong(int nbox, int shift, int d, int k, int nt,
+                                                                  const double* __restrict__ part, T* x,
+                                                                  const T* __restrict__ pt, T* v,
+                                                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double sh[16][17];
+  __shared__ T xs[64 * NR];
+  const int B = (d == 3) ? k * k * k : k * k;
+  const int G = blockIdx.x;
+  const int g = threadIdx.x >> 4, i = threadIdx.x & 15;
+  for (int r0 = 0; r0 < B; r0 += 16) {
+    const int r = r0 + i;
+    for (int c = 0; c < NR; ++c) {
+      if (r < B) sh[g][i] = dense_slot_sum(nt, part, G * B + r, g, NR, c);
+      __syncthreads();
+      if (g == 0 && r < B) {
+        const T t = (T)dense_sum16(sh, i);
+        x[((int64_t)G * B + r) * NR + c] = t;
+        xs[r * NR + c] = t;
+      }
+      __syncthreads();
+    }
+  }
+  const int c0 = G << shift;
+  const int nch = min(nbox, (G + 1) << shift) - c0;
+  for (int t = threadIdx.x; t < nch * B; t += blockDim.x) {
+    const int C = c0 + t / B, qc = t % B;
+    for (int c = 0; c < NR; ++c) {
+      T s = 0;
+      for (int q = 0; q < B; ++q) s += pt_entry(pt, C, d, k, qc, q) * xs[q * NR + c];
+      v[((int64_t)C * B + qc) * NR + c] = s;
+    }
+  }
+}
+
+template <typename M>
 __global__ __launch_bounds__(256) void k_dense_pack_sym(int nc, const double* __restrict__ full,
-                                                        const int2* __restrict__ tiles, double* packed) {
+                                                        const int2* __restrict__ tiles, M* packed) {
   const int t = blockIdx.x;
   const int2 ij = tiles[t];
   for (int e = threadIdx.x; e < kDenseTile * kDenseTile; e += 256) {
     const int i = ij.x * kDenseTile + e / kDenseTile, j = ij.y * kDenseTile + e % kDenseTile;
-    packed[(int64_t)t * (kDenseTile * kDenseTile) + e] = (i < nc && j < nc) ? full[(int64_t)i * nc + j] : 0.0;
+    packed[(int64_t)t * (kDenseTile * kDenseTile) + e] = (i < nc && j < nc) ? (M)full[(int64_t)i * nc + j] : (M)0;
   }
 }
-void launch_dense_pack_sym(int nc, int ntiles, const double* full, const int* tiles, double* packed, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_pack_sym, dim3(ntiles), dim3(256), 0, s, nc, full,
+template <typename M>
+void launch_dense_pack_sym(int nc, int ntiles, const double* full, const int* tiles, M* packed, hipStream_t s) {
+  hipLaunchKernelGGL((k_dense_pack_sym<M>), dim3(ntiles), dim3(256), 0, s, nc, full,
                      reinterpret_cast<const int2*>(tiles), packed);
   check_launch("k_dense_pack_sym");
 }
+template void launch_dense_pack_sym<double>(int, int, const double*, const int*, double*, hipStream_t);
+template void launch_dense_pack_sym<float>(int, int, const double*, const int*, float*, hipStream_t);
 
-template <typename T>
-void launch_dense_apply_sym(int nc, int nt, int nr, const double* packed, const int* tiles, double* part,
-                            const T* b, T* x, const int* skip, hipStream_t s) {
+template <typename T, typename M>
+void launch_dense_apply_sym(int nc, int nt, int nr, const M* packed, const int* tiles, double* part, const T* b,
+                            T* x, const DenseProlong<T>* pr, const int* skip, hipStream_t s) {
   const int ntiles = nt * (nt + 1) / 2;
   const int2* tl = reinterpret_cast<const int2*>(tiles);
+  int B = 0;
+  if (pr) {
+    B = pr->d == 3 ? (pr->pc + 1) * (pr->pc + 1) * (pr->pc + 1) : (pr->pc + 1) * (pr->pc + 1);
+    if (B > 64 || (int64_t)B * pr->nbox_coarse != nc)
+      throw std::runtime_error("dense coarsest product: prolongation boxes do not match the coarsest level");
+  }
   switch (nr) {
-#define R3_DS(NRV)                                                                                               \
-  hipLaunchKernelGGL((k_dense_sym_tiles<T, NRV>), dim3(ntiles), dim3(256), 0, s, nc, nt, packed, tl, b, part, skip); \
-  hipLaunchKernelGGL((k_dense_sym_reduce<T, NRV>), dim3(4 * nt), dim3(256), 0, s, nc, nt, part, x, skip);       \
+#define R3_DS(NRV)                                                                                                  \
+  hipLaunchKernelGGL((k_dense_sym_tiles<T, M, NRV>), dim3(ntiles), dim3(256), 0, s, nc, nt, packed, tl, b, part,   \
+                     skip);                                                                                         \
+  if (pr)                                                                                                           \
+    hipLaunchKernelGGL((k_dense_sym_reduce_prolong<T, NRV>), dim3(pr->nbox_coarse), dim3(256), 0, s, pr->nbox,     \
+                       pr->shift, pr->d, pr->pc + 1, nt, part, x, pr->pt, pr->v, skip);                             \
+  else                                                                                                              \
+    hipLaunchKernelGGL((k_dense_sym_reduce<T, NRV>), dim3(4 * nt), dim3(256), 0, s, nc, nt, part, x, skip);        \
   break;
     case 1: R3_DS(1)
     case 2: R3_DS(2)
@@ -2552,10 +2894,14 @@ void launch_dense_apply_sym(int nc, int nt, int nr, const double* packed, const 
   }
   check_launch("k_dense_sym");
 }
-template void launch_dense_apply_sym<float>(int, int, int, const double*, const int*, double*, const float*, float*,
-                                            const int*, hipStream_t);
-template void launch_dense_apply_sym<double>(int, int, int, const double*, const int*, double*, const double*,
-                                             double*, const int*, hipStream_t);
+template void launch_dense_apply_sym<float, float>(int, int, int, const float*, const int*, double*, const float*,
+                                                   float*, const DenseProlong<float>*, const int*, hipStream_t);
+template void launch_dense_apply_sym<float, double>(int, int, int, const double*, const int*, double*,
+                                                    const float*, float*, const DenseProlong<float>*, const int*,
+                                                    hipStream_t);
+template void launch_dense_apply_sym<double, double>(int, int, int, const double*, const int*, double*,
+                                                     const double*, double*, const DenseProlong<double>*,
+                                                     const int*, hipStream_t);
 
 __global__ void k_gather_cols(int n, int nr, int nuser, const int* __restrict__ perm,
                               const double* __restrict__ user, int64_t ld, double* out) {

@@ -250,10 +250,12 @@ struct Device {
   std::string tune_sig;  // tuning-cache key prefix of this handle: device and level structure (set at set-up)
   std::vector<DevLevel> lv;
   // dense coarsest: inverse (nL x nL float64, row-major); for up to kDenseSymMaxTiles tile rows also its upper
-  // 64 x 64 tiles packed (csym, tile list ctile) and the pass-1 slots for up to 4 columns (cpart)
+  // 64 x 64 tiles packed (csym in float64, or csym32 rounded to float32 for a float32 V-cycle; tile list ctile)
+  // and the pass-1 slots for up to 4 columns (cpart)
   DBuf<double> cinv;
   int64_t nc = 0;
   DBuf<double> csym, cpart;
+  DBuf<float> csym32;
   DBuf<int32_t> ctile;
   int ct = 0;  // tile rows of csym; 0 = the full inverse only
   // fine-level helpers

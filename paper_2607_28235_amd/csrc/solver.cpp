@@ -632,6 +632,31 @@ static Cheb cheb_coeffs(double lo, double hi, int K) {
   return ch;
 }
 
+// Coarsest solve x = A_L^{-1} b: the symmetric inverse's packed tiles (float32 tiles for the float32 V-cycle) for
+// up to kDenseSymMaxNR columns, else the full float64 inverse.  With pr, the prolongation to the level above
+// follows (fused into the tiled product's last pass, else k_prolong_c).
+template <typename T>
+static void coarsest_apply(Ctx& c, int nr, const T* b, T* x, const DenseProlong<T>* pr, const int* skip,
+                           hipStream_t s) {
+  Device& dv = c.dv;
+  if (dv.ct > 0 && nr <= kDenseSymMaxNR) {
+    if constexpr (sizeof(T) == 4) {
+      if (dv.csym32.p) {
+        launch_dense_apply_sym<T, float>((int)dv.nc, dv.ct, nr, dv.csym32.p, dv.ctile.p, dv.cpart.p, b, x, pr, skip,
+                                         s);
+        return;
+      }
+    }
+    if (dv.csym.p) {
+      launch_dense_apply_sym<T, double>((int)dv.nc, dv.ct, nr, dv.csym.p, dv.ctile.p, dv.cpart.p, b, x, pr, skip,
+                                        s);
+      return;
+    }
+  }
+  launch_dense_apply<T>((int)dv.nc, nr, dv.cinv.p, b, x, skip, s);
+  if (pr) launch_prolong_c<T>(pr->nbox, pr->shift, c.an.d, c.an.pc, nr, pr->pt, x, nullptr, pr->v, skip, s);
+}
+
 // ---------------------------------------------------------------------------------------------
 // V-cycle (recursive).  On entry the level's right-hand side is in lv[l].b (or b_override at level 0) and,
 // when pre_steps > 0 and l < L, lv[l].dA holds the first Chebyshev direction D^{-1} b / theta.  On return
@@ -647,10 +672,7 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   T* b = b_override ? const_cast<T*>(b_override) : wv<T>(c, l, W_B);
   T* x = wv<T>(c, l, W_X);
   if (l == L) {
-    if (dv.ct > 0 && nr <= kDenseSymMaxNR)
-      launch_dense_apply_sym<T>((int)dv.nc, dv.ct, nr, dv.csym.p, dv.ctile.p, dv.cpart.p, b, x, skip, s);
-    else
-      launch_dense_apply<T>((int)dv.nc, nr, dv.cinv.p, b, x, skip, s);
+    coarsest_apply<T>(c, nr, b, x, nullptr, skip, s);
     return nullptr;
   }
   const r3mg_options& o = an.opt;
@@ -725,15 +747,25 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
   }
 
   // coarse correction
-  T* pend_c = vcycle_rec<T>(c, l + 1, nr, nullptr, skip, s);
   T* v = buf[0];
-  if (l == 0) {
+  if (l + 1 == L && l > 0) {
+    // the coarsest solve, with the prolongation to this level fused into its last pass
+    DenseProlong<T> pr;
+    pr.nbox_coarse = (int)N.nbox;
+    pr.nbox = (int)D.nbox;
+    pr.shift = N.child_shift;
+    pr.d = an.d;
+    pr.pc = an.pc;
+    pr.pt = pt;
+    pr.v = v;
+    coarsest_apply<T>(c, nr, wv<T>(c, l + 1, W_B), wv<T>(c, l + 1, W_X), &pr, skip, s);
+  } else if (l == 0) {
+    T* pend_c = vcycle_rec<T>(c, l + 1, nr, nullptr, skip, s);
     const T* xi;
     if constexpr (sizeof(T) == 4) xi = D.xi32.p; else xi = D.xi64.p;
     launch_prolong0<T>((int)D.n, an.d, an.pc, nr, D.owner.p, xi, wv<T>(c, l + 1, W_X), pend_c, v, skip, s);
   } else {
-    const T* pt;
-    if constexpr (sizeof(T) == 4) pt = D.pt32.p; else pt = D.pt64.p;
+    T* pend_c = vcycle_rec<T>(c, l + 1, nr, nullptr, skip, s);
     launch_prolong_c<T>((int)D.nbox, N.child_shift, an.d, an.pc, nr, pt, wv<T>(c, l + 1, W_X), pend_c, v, skip, s);
   }
 
@@ -866,6 +898,7 @@ void numeric_setup(HandleImpl& h, hipStream_t s) {
     const int nt = (int)((D.n + kDenseTile - 1) / kDenseTile);
     dv.ct = 0;
     dv.csym.release();
+    dv.csym32.release();
     dv.cpart.release();
     dv.ctile.release();
     if (nt <= kDenseSymMaxTiles) {
@@ -878,9 +911,15 @@ void numeric_setup(HandleImpl& h, hipStream_t s) {
         }
       const int ntiles = nt * (nt + 1) / 2;
       dv.ctile.upload(tl, s);
-      dv.csym.alloc((size_t)ntiles * kDenseTile * kDenseTile);
+      // the float32 V-cycle reads the tiles rounded to float32 (half the bytes; products still in float64)
+      if (c.fp32) {
+        dv.csym32.alloc((size_t)ntiles * kDenseTile * kDenseTile);
+        launch_dense_pack_sym<float>((int)D.n, ntiles, dv.cinv.p, dv.ctile.p, dv.csym32.p, s);
+      } else {
+        dv.csym.alloc((size_t)ntiles * kDenseTile * kDenseTile);
+        launch_dense_pack_sym<double>((int)D.n, ntiles, dv.cinv.p, dv.ctile.p, dv.csym.p, s);
+      }
       dv.cpart.alloc((size_t)nt * nt * kDenseTile * kDenseSymMaxNR);
-      launch_dense_pack_sym((int)D.n, ntiles, dv.cinv.p, dv.ctile.p, dv.csym.p, s);
       R3MG_HIP_CHECK(hipStreamSynchronize(s));
       dv.ct = nt;
     }
