@@ -767,44 +767,43 @@ __global__ __launch_bounds__(256) void k_level_local_vec(int nrb, const int4* __
   const bool staged = nu <= UCAP;
   const int rl = threadIdx.x / TPR, sub = threadIdx.x % TPR;
   const int prow = r0 + rl;
-  const bool pre = sub == 0 && prow < r1 && !(flags & F_PLAIN);
+  // The loads below are unconditional per thread (clamped addresses; out-of-range values are never used): loads
+  // under lane-dependent branches are waited for at the branch's end, which put the block's value stream behind
+  // its column list.  Here the column list, values, positions and row pointers are in flight together, and only
+  // the gather of u waits for the column list.
+  const int prc = min(prow, r1 - 1);  // blocks hold at least one row
   T p_old = 0, p_x = 0, p_u = 0, p_di = 0;
-  if (pre) {
-    p_old = (flags & F_RHO_FROM_B) ? b[prow] : rho[prow];
-    p_u = u[prow];
-    if (flags & F_X_ADD) p_x = x[prow];
-    if (flags & F_D_OUT) p_di = dinv[prow];
+  if (!(flags & F_PLAIN)) {
+    p_old = (flags & F_RHO_FROM_B) ? b[prc] : rho[prc];
+    p_u = u[prc];
+    if (flags & F_X_ADD) p_x = x[prc];
+    if (flags & F_D_OUT) p_di = dinv[prc];
   }
   T t = 0;
   if (staged) {
-    T ug[UPT];
+    int uc[UPT];
 #pragma unroll
-    for (int m = 0; m < UPT; ++m) {
-      const int c = threadIdx.x + m * 256;
-      if (c < nu) ug[m] = u[ucol[u0 + c]];
-    }
+    for (int m = 0; m < UPT; ++m) uc[m] = ucol[u0 + min((int)threadIdx.x + m * 256, nu - 1)];  // nu >= 1
     const int a0 = e0 & ~3;
     uint32_t li[NCH];
     V4 vv[NCH];
 #pragma unroll
     for (int m = 0; m < NCH; ++m) {
       const int e = a0 + 4 * (threadIdx.x + m * 256);
-      if (e < e1) {
-        const uint32_t* lp = reinterpret_cast<const uint32_t*>(lidx + e);
-        const V4* vp = reinterpret_cast<const V4*>(val + e);
-        li[m] = ld_matrix<KEEP>(lp);
-        vv[m] = ld_matrix<KEEP>(vp);
-      }
+      const int ec = e < e1 ? e : a0;
+      li[m] = ld_matrix<KEEP>(reinterpret_cast<const uint32_t*>(lidx + ec));
+      vv[m] = ld_matrix<KEEP>(reinterpret_cast<const V4*>(val + ec));
     }
-    int rp = e1;
-    if (lane <= RPW) {
-      const int rr = r0 + wv * RPW + lane;
-      rp = ptr[rr < r1 ? rr : r1];
-    }
+    const int rp = ptr[min(r0 + wv * RPW + min(lane, RPW), r1)];  // lanes 0..RPW: this wave's row pointers
+    // slots nu .. UCAP-1 take copies and are never read (positions are below nu); no branch lets the gather sink
 #pragma unroll
-    for (int m = 0; m < UPT; ++m) {
-      const int c = threadIdx.x + m * 256;
-      if (c < nu) us[c] = ug[m];
+    for (int m = 0; m < UPT; ++m) us[threadIdx.x + m * 256] = u[uc[m]];
+    // keep the streamed entries ahead of the barrier (the compiler would otherwise sink some loads past it)
+#pragma unroll
+    for (int m = 0; m < NCH; ++m) {
+      asm volatile("" ::"v"(li[m]));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) asm volatile("" ::"v"(vv[m][q]));
     }
     __syncthreads();
 #pragma unroll
@@ -1720,38 +1719,47 @@ __global__ __launch_bounds__(256) void k_level_boxrow(int nbox, const int* __res
   if (skip && *skip) return;
   const int lb = xcd_block(nlog);
   if (lb < 0) return;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is uniform: the box's block-row record then comes through scalar loads
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int K = lb * 4 + wv;
   if (K >= nbox) return;  // whole wave leaves; no barrier follows
   const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
   const int myrow = (b5 ? 8 : 0) + (b4 ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
   const bool owner = (lane & 3) == 0 && myrow < BLK;
-  const int row = K * BLK + myrow;
+  const int row = K * BLK + min(myrow, BLK - 1);  // clamped: every lane loads, only owners use the values
+  // All loads below are unconditional per lane (clamped addresses, masked values): a load under a lane-dependent
+  // branch would be waited for at the branch's end, which serialised the box's round trips.
   T p_old = 0, p_u = 0, p_x = 0, p_di = 0;
-  if (owner && !(flags & F_PLAIN)) {
+  if (!(flags & F_PLAIN)) {
     p_old = (flags & F_RHO_FROM_B) ? b[row] : rho[row];
     p_u = u[row];
     if (flags & F_X_ADD) p_x = x[row];
     if (flags & F_D_OUT) p_di = dinv[row];
   }
-  const int j0 = bptr[K], w = (bptr[K + 1] - j0) * BLK;
+  const int j0 = bptr[K], w = (bptr[K + 1] - j0) * BLK;  // w >= BLK: every box holds its diagonal block
   const T* vb = val + (int64_t)BLK * BLK * j0;  // row q of the box at vb + q w
   T acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0;
+  int pc[NP];
+  int cj[NP];
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
-    const int p = lane + 64 * m;
-    if (p < w) {
-      T v[BLK];
+    pc[m] = min(lane + 64 * m, w - 1);
+    cj[m] = bcol[j0 + pc[m] / BLK];
+  }
+  T v[NP][BLK];
 #pragma unroll
-      for (int q = 0; q < BLK; ++q)
-        v[q] = ld_matrix<KEEP>(vb + (int64_t)q * w + p);
-      const int j = p / BLK, c = p - j * BLK;
-      const T uv = u[(int64_t)bcol[j0 + j] * BLK + c];
+  for (int m = 0; m < NP; ++m)
 #pragma unroll
-      for (int q = 0; q < BLK; ++q) acc[q] += v[q] * uv;
-    }
+    for (int q = 0; q < BLK; ++q) v[m][q] = ld_matrix<KEEP>(vb + (int64_t)q * w + pc[m]);
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const int c = pc[m] - (pc[m] / BLK) * BLK;
+    const T ug = u[(int64_t)cj[m] * BLK + c];
+    const T uv = lane + 64 * m < w ? ug : (T)0;
+#pragma unroll
+    for (int q = 0; q < BLK; ++q) acc[q] += v[m][q] * uv;
   }
   T h8[8];
 #pragma unroll
@@ -2057,27 +2065,29 @@ __global__ __launch_bounds__(256) void k_restrict0(Basis1D<T> bs, int nr, const 
   for (int c = 0; c < nr; ++c) {
     T tot = 0;  // lane q's running sum (q = lane < B)
     for (int base = i0 + wv * 128; base < i1; base += W * 128) {
+      // both points' loads are unconditional (clamped to the box's last point) and masked afterwards, so that
+      // they are in flight together
       const int ia = base + lane, ib = base + 64 + lane;
-      const bool oka = ia < i1 && owner[ia] >= 0, okb = ib < i1 && owner[ib] >= 0;
-      T la[3][4], lbv[3][4];
-      T ra = 0, rb = 0;
-      if (oka) {
-        ra = src[(int64_t)ia * nr + c];
+      const int iac = min(ia, i1 - 1), ibc = min(ib, i1 - 1);
+      const int owa = owner[iac], owb = owner[ibc];
+      T ra = src[(int64_t)iac * nr + c], rb = src[(int64_t)ibc * nr + c];
+      T xa[3], xb[3];
 #pragma unroll
-        for (int a = 0; a < D; ++a) lag1d_k<T, KB>(bs, xi[(int64_t)ia * D + a], la[a]);
-      } else {
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-          for (int j = 0; j < KB; ++j) la[a][j] = 0;
+      for (int a = 0; a < D; ++a) {
+        xa[a] = xi[(int64_t)iac * D + a];
+        xb[a] = xi[(int64_t)ibc * D + a];
       }
-      if (okb) {
-        rb = src[(int64_t)ib * nr + c];
+      const bool oka = ia < i1 && owa >= 0, okb = ib < i1 && owb >= 0;
+      ra = oka ? ra : (T)0;
+      rb = okb ? rb : (T)0;
+      T la[3][4], lbv[3][4];
 #pragma unroll
-        for (int a = 0; a < D; ++a) lag1d_k<T, KB>(bs, xi[(int64_t)ib * D + a], lbv[a]);
+      for (int a = 0; a < D; ++a) {
+        lag1d_k<T, KB>(bs, xa[a], la[a]);
+        lag1d_k<T, KB>(bs, xb[a], lbv[a]);
       }
       for_each_phi<T, D, KB>(la, [&](int qq, T ph) { sh[qq * 65 + lane] = ph * ra; });
-      if (okb) for_each_phi<T, D, KB>(lbv, [&](int qq, T ph) { sh[qq * 65 + lane] += ph * rb; });
+      for_each_phi<T, D, KB>(lbv, [&](int qq, T ph) { sh[qq * 65 + lane] += ph * rb; });
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -2144,7 +2154,8 @@ __global__ __launch_bounds__(512) void k_restrict0_mr(Basis1D<T> bs, int nr, con
     for (int t = threadIdx.x; t < np * nch; t += blockDim.x) {
       const int pp = t / nch, jj = t - pp * nch;
       const int i = base + pp;
-      ss[t] = owner[i] >= 0 ? *reinterpret_cast<const VT*>(src + (int64_t)i * nr + jj * VW) : (VT)0;
+      const VT sv = *reinterpret_cast<const VT*>(src + (int64_t)i * nr + jj * VW);
+      ss[t] = owner[i] >= 0 ? sv : (VT)0;
     }
     if (threadIdx.x < np) {
       const int i = base + threadIdx.x;
