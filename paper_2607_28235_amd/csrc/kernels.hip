@@ -3355,44 +3355,101 @@ __device__ inline double dt_dot8(const double* x, int sx, const double* y, int s
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
-// 1. Diagonal tile k0, by one wave: Cholesky in LDS by columns (lane l owns row l and sums its own dot products),
-// then the inverse D by rows of D (lane l owns column l).  With a single wave every barrier is nearly free; four
-// waves and 192 workgroup barriers took 113 us per tile.  L goes back to A (zero above the diagonal), D to Dk
-// (64 x 64, zero above the diagonal).
+// 1. Diagonal tile k0, by one wave.  Cholesky by columns (left-looking): lane l keeps row l of the tile in
+// registers, and the rows of L go to LDS as they become final (zero elsewhere), so that step j reads row j of L as
+// 16-byte broadcasts and each lane forms its dot product with its own registers; segments of eight entries that
+// are still zero are not read.  Then the inverse D = L^{-1} by rows of D: lane l keeps column l of D in registers
+// (zero above the diagonal), so that row i of D needs row i of L only.  L goes back to A (zero above the
+// diagonal), D to Dk (64 x 64, zero above the diagonal).  The steps are generated by template recursion, so every
+// register index is a constant; the pivots' square roots are broadcast with a lane shuffle, and one barrier per
+// column orders the LDS rows.  (Forming row J of D in the same step as column J of L, for two independent chains,
+// needed 387 registers and ran slower.)
+constexpr int kDiagLD = DT + 2;  // LDS row stride: 16-byte aligned rows, 4-way conflicts at most for row-per-lane reads
+
+// sum over m < 8 ceil(J / 8) of x[m] w[m] (w: an LDS row whose entries from J on are zero), in two interleaved
+// partial sums (four ran slower)
+template <int J, bool XW>
+__device__ __forceinline__ double diag_dot(const double (&x)[DT], const double* w) {
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int c = 0; c < (J + 7) / 8; ++c)
+#pragma unroll
+    for (int t = 0; t < 8; t += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(w + 8 * c + t);
+      if (XW) {
+        a0 += x[8 * c + t] * v.x;
+        a1 += x[8 * c + t + 1] * v.y;
+      } else {
+        a0 += v.x * x[8 * c + t];
+        a1 += v.y * x[8 * c + t + 1];
+      }
+    }
+  return a0 + a1;
+}
+
+template <int J>
+struct DiagChol {
+  static __device__ __forceinline__ void run(double (&r)[DT], double* s, int l, int* bad) {
+    if constexpr (J < DT) {
+      const double acc = diag_dot<J, true>(r, s + J * kDiagLD);  // sum over m < J of L[l][m] L[J][m]
+      double piv = r[J] - acc;  // left-looking: r[J] still holds the tile's entry
+      if (l == J && !(piv > 0.0)) {
+        *bad = 1;
+        piv = 1.0;
+      }
+      const double ljj = __shfl(sqrt(piv), J, 64);
+      if (l >= J) {
+        const double v = (l == J) ? ljj : (r[J] - acc) / ljj;
+        s[l * kDiagLD + J] = v;
+        r[J] = v;
+      }
+      __syncthreads();
+      DiagChol<J + 1>::run(r, s, l, bad);
+    }
+  }
+};
+
+template <int I>
+struct DiagInv {
+  // d[i][l] = -(sum over l <= m < i of L[i][m] d[m][l]) / L[i][i] (i > l), 1 / L[i][i] (i = l), 0 (i < l);
+  // d[m][l] = 0 for m < l, so the sum may run over m < i
+  static __device__ __forceinline__ void run(double (&d)[DT], const double* s, int l) {
+    if constexpr (I < DT) {
+      const double* ri = s + I * kDiagLD;
+      const double acc = diag_dot<I, false>(d, ri);
+      const double lii = ri[I];
+      d[I] = (I < l) ? 0.0 : (I == l) ? 1.0 / lii : -acc / lii;
+      DiagInv<I + 1>::run(d, s, l);
+    }
+  }
+};
+
 __global__ __launch_bounds__(64) void k_dchol_diag(int n, int k0, double* A, double* Dk, int* bad) {
-  __shared__ double s[DT][DT + 1];
-  __shared__ double d[DT][DT + 1];
+  __shared__ __align__(16) double s[DT * kDiagLD];
   const int l = threadIdx.x;
   for (int e = l; e < DT * DT; e += 64) {
     const int i = e >> 6, j = e & 63;
     double v = (i == j) ? 1.0 : 0.0;
     if (k0 + i < n && k0 + j < n) v = A[(int64_t)(k0 + i) * n + k0 + j];
-    s[i][j] = v;
+    s[i * kDiagLD + j] = v;
   }
   __syncthreads();
-  for (int j = 0; j < DT; ++j) {
-    const double acc = dt_dot8(&s[l][0], 1, &s[j][0], 1, 0, j);
-    if (l == j) {
-      double piv = s[j][j] - acc;
-      if (!(piv > 0.0)) {
-        *bad = 1;
-        piv = 1.0;
-      }
-      s[j][j] = sqrt(piv);
-    }
-    __syncthreads();
-    if (l > j) s[l][j] = (s[l][j] - acc) / s[j][j];
-    __syncthreads();
-  }
-  for (int i = 0; i < DT; ++i) {
-    const double acc = dt_dot8(&s[i][0], 1, &d[0][l], DT + 1, l, i);
-    d[i][l] = (i < l) ? 0.0 : (i == l) ? 1.0 / s[l][l] : -acc / s[i][i];
-    __syncthreads();
-  }
+  double r[DT];
+#pragma unroll
+  for (int m = 0; m < DT; ++m) r[m] = s[l * kDiagLD + m];
+  __syncthreads();
+  for (int e = l; e < DT * kDiagLD; e += 64) s[e] = 0.0;
+  __syncthreads();
+  DiagChol<0>::run(r, s, l, bad);
+  double d[DT];
+#pragma unroll
+  for (int m = 0; m < DT; ++m) d[m] = 0.0;
+  DiagInv<0>::run(d, s, l);
+#pragma unroll
+  for (int i = 0; i < DT; ++i) Dk[i * DT + l] = d[i];
   for (int e = l; e < DT * DT; e += 64) {
     const int i = e >> 6, j = e & 63;
-    if (k0 + i < n && k0 + j < n) A[(int64_t)(k0 + i) * n + k0 + j] = (j <= i) ? s[i][j] : 0.0;
-    Dk[e] = d[i][j];
+    if (k0 + i < n && k0 + j < n) A[(int64_t)(k0 + i) * n + k0 + j] = s[i * kDiagLD + j];
   }
 }
 
