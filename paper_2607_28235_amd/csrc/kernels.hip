@@ -3611,12 +3611,23 @@ __device__ inline void column_partials(double acc, double* sh, double* out) {
 template <int NR>
 __device__ inline void column_totals(const double* __restrict__ part, int nb, int stride, double* sh, double* tot) {
   const int k = threadIdx.x % NR;
+  constexpr int S = 256 / NR;
   double acc = 0;
-  for (int b = threadIdx.x / NR; b < nb; b += 256 / NR) acc += part[(int64_t)b * stride + k];
+  // four of the thread's partials at a time: loads issued together (clamped), added in index order
+  for (int b0 = threadIdx.x / NR; b0 < nb; b0 += 4 * S) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = part[(int64_t)min(b0 + u * S, nb - 1) * stride + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (b0 + u * S < nb) acc += v[u];
+  }
   column_partials<NR>(acc, sh, tot);
   __syncthreads();
 }
 
+// grid-stride steps of the one-column PCG vector kernels whose loads are issued together
+constexpr int kPcgU = 4;
 inline int pcg_grid(int n) {
   const int g = (n + 255) / 256;
   return std::max(1, std::min(g, kPcgBlocks));
@@ -3646,12 +3657,26 @@ __global__ __launch_bounds__(256) void k_pcg_dot(int n, const double* __restrict
   if (st->all_done) return;
   double acc = 0;
   const int64_t tn = (int64_t)n * NR;
-  for (int64_t base = (int64_t)blockIdx.x * 256 * NR; base < tn; base += (int64_t)gridDim.x * 256 * NR)
+  // U grid-stride steps at a time: their loads are issued together (clamped addresses), then summed in the
+  // element order of one step after another
+  constexpr int U = NR >= 4 ? 1 : 4 / NR;
+  const int64_t step = (int64_t)gridDim.x * 256 * NR;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * NR; base < tn; base += U * step) {
+    double pv[U][NR], qv[U][NR];
 #pragma unroll
-    for (int m = 0; m < NR; ++m) {
-      const int64_t o = base + threadIdx.x + 256 * m;
-      if (o < tn) acc += p[o] * q[o];
-    }
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < NR; ++m) {
+        const int64_t o = min(base + u * step + threadIdx.x + 256 * m, tn - 1);
+        pv[u][m] = p[o];
+        qv[u][m] = q[o];
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < NR; ++m)
+        if (base + u * step + threadIdx.x + 256 * m < tn) acc += pv[u][m] * qv[u][m];
+  }
   column_partials<NR>(acc, sh, partials + (int64_t)blockIdx.x * NR);
 }
 template <int NR>
@@ -3892,17 +3917,37 @@ __global__ __launch_bounds__(256) void k_pcg_xr1(int n, PcgState* st, double* x,
     pcg_set_alpha(st, 0, pq[0]);
   }
   double acc = 0;
-  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < n; o += (int64_t)gridDim.x * 256) {
-    x[o] += al * p[o];
-    const double rv = r[o] - al * q[o];
-    r[o] = rv;
-    acc += rv * rv;
-    if (b0) {
-      const T bv = (T)rv;
-      b0[o] = bv;
-      if (d0) d0[o] = dinv0[o] * bv * inv_theta0;
-    } else if (d0) {
-      d0[o] = dinv0[o] * (T)rv * inv_theta0;
+  // kPcgU grid-stride steps at a time, loads issued together (clamped addresses), in the element order of the
+  // steps one after another
+  const int64_t step = (int64_t)gridDim.x * 256;
+  for (int64_t o0 = (int64_t)blockIdx.x * 256 + threadIdx.x; o0 < n; o0 += kPcgU * step) {
+    double xv[kPcgU], pv[kPcgU], rv[kPcgU], qv[kPcgU];
+    T dv[kPcgU];
+#pragma unroll
+    for (int u = 0; u < kPcgU; ++u) {
+      const int64_t o = min(o0 + u * step, (int64_t)n - 1);
+      xv[u] = x[o];
+      pv[u] = p[o];
+      rv[u] = r[o];
+      qv[u] = q[o];
+      dv[u] = d0 ? dinv0[o] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPcgU; ++u) {
+      const int64_t o = o0 + u * step;
+      if (o < n) {
+        x[o] = xv[u] + al * pv[u];
+        const double r1 = rv[u] - al * qv[u];
+        r[o] = r1;
+        acc += r1 * r1;
+        if (b0) {
+          const T bv = (T)r1;
+          b0[o] = bv;
+          if (d0) d0[o] = dv[u] * bv * inv_theta0;
+        } else if (d0) {
+          d0[o] = dv[u] * (T)r1 * inv_theta0;
+        }
+      }
     }
   }
   column_partials<1>(acc, sh, partials + g + blockIdx.x);
@@ -3940,13 +3985,30 @@ __global__ __launch_bounds__(256) void k_pcg_z1(int n, PcgState* st, int check, 
     st->all_done = st->done[0];
   }
   double a1 = 0, a2 = 0;
-  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < n; o += (int64_t)gridDim.x * 256) {
-    T v = x0[o];
-    if (dp) v += dp[o];
-    const double zv = (double)v;
-    z[o] = zv;
-    a1 += r[o] * zv;
-    if (q) a2 += q[o] * zv;
+  const int64_t step = (int64_t)gridDim.x * 256;
+  for (int64_t o0 = (int64_t)blockIdx.x * 256 + threadIdx.x; o0 < n; o0 += kPcgU * step) {
+    T xv[kPcgU], dv[kPcgU];
+    double rv[kPcgU], qv[kPcgU];
+#pragma unroll
+    for (int u = 0; u < kPcgU; ++u) {
+      const int64_t o = min(o0 + u * step, (int64_t)n - 1);
+      xv[u] = x0[o];
+      dv[u] = dp ? dp[o] : (T)0;
+      rv[u] = r[o];
+      qv[u] = q ? q[o] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPcgU; ++u) {
+      const int64_t o = o0 + u * step;
+      if (o < n) {
+        T v = xv[u];
+        if (dp) v += dv[u];
+        const double zv = (double)v;
+        z[o] = zv;
+        a1 += rv[u] * zv;
+        if (q) a2 += qv[u] * zv;
+      }
+    }
   }
   double* out = partials + 2 * g + (int64_t)blockIdx.x * 2;
   column_partials<1>(a1, sh, out);
@@ -3988,8 +4050,21 @@ __global__ __launch_bounds__(256) void k_pcg_p1(int n, PcgState* st, const doubl
     const int j = st->iters[0] - 1;  // the stop test of iteration j has counted it
     if (st->hist && j >= 0 && j < st->hist_rows) st->hist[(int64_t)(2 * j + 1) * kMaxNR] = be;
   }
-  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < n; o += (int64_t)gridDim.x * 256)
-    p[o] = z[o] + be * p[o];
+  const int64_t step = (int64_t)gridDim.x * 256;
+  for (int64_t o0 = (int64_t)blockIdx.x * 256 + threadIdx.x; o0 < n; o0 += kPcgU * step) {
+    double zv[kPcgU], pv[kPcgU];
+#pragma unroll
+    for (int u = 0; u < kPcgU; ++u) {
+      const int64_t o = min(o0 + u * step, (int64_t)n - 1);
+      zv[u] = z[o];
+      pv[u] = p[o];
+    }
+#pragma unroll
+    for (int u = 0; u < kPcgU; ++u) {
+      const int64_t o = o0 + u * step;
+      if (o < n) p[o] = zv[u] + be * pv[u];
+    }
+  }
 }
 void launch_pcg_p1(int n, PcgState* st, const double* z, double* p, const double* partials, hipStream_t s) {
   const int g = pcg_grid(n);
