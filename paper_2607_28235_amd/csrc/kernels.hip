@@ -2739,17 +2739,26 @@ __global__ __launch_bounds__(256) void k_dense_sym_tiles(int nc, int nt, const M
   const int t = blockIdx.x;
   const int2 ij = tiles[t];
   const int I = ij.x, J = ij.y;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const M* a = packed + (int64_t)t * (kDenseTile * kDenseTile) + (16 * w) * kDenseTile + lane;
   double m[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) m[k] = (double)a[k * kDenseTile];
   const int cj = J * kDenseTile + lane;
   const int ri = I * kDenseTile + 16 * w;
+  // the entries of b are loaded up front from clamped addresses and masked (loads under a lane-dependent
+  // condition would each be waited for); the wave's 16 rows of b are the same for all its lanes
+  T bj[NR], br[16][NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    bj[c] = b[(int64_t)min(cj, nc - 1) * NR + c];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) br[k][c] = (I != J) ? b[(int64_t)min(ri + k, nc - 1) * NR + c] : (T)0;
+  }
   const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
   const int myrow = (b5 ? 8 : 0) + (b4 ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
   for (int c = 0; c < NR; ++c) {
-    const double xj = cj < nc ? (double)b[(int64_t)cj * NR + c] : 0.0;
+    const double xj = cj < nc ? (double)bj[c] : 0.0;
     double h8[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -2770,10 +2779,7 @@ __global__ __launch_bounds__(256) void k_dense_sym_tiles(int nc, int nt, const M
     if (I != J) {  // uniform over the workgroup
       double cs = 0;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int r = ri + k;
-        cs += m[k] * (r < nc ? (double)b[(int64_t)r * NR + c] : 0.0);
-      }
+      for (int k = 0; k < 16; ++k) cs += m[k] * (ri + k < nc ? (double)br[k][c] : 0.0);
       sh[w][lane] = cs;
       __syncthreads();
       if (w == 0)

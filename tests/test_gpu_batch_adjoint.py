@@ -42,8 +42,9 @@ def small3d_q3():
 @pytest.mark.parametrize("kernel", [-1, 0, 1, 2, 3, 4])
 def test_sixteen_rhs_block_pcg(small3d_q3, fp32, kernel):
     """16 right-hand sides in lockstep match the oracle per column, with the fine-level multi-RHS kernel chosen by
-    timing (-1) or forced: lanes-per-row CSR (0), row blocks staged in LDS with length-sorted (1) or ordered (2)
-    rows, CSR with the columns split over lanes (3), the same with shared entry loads (4)."""
+    timing (-1) or forced: lanes-per-row CSR (0), row blocks staged in LDS by a persistent pipelined workgroup per
+    compute unit (1) or one workgroup per block (2), CSR with the columns split over lanes (3), the same with
+    shared entry loads (4)."""
     import paper_2607_28235_amd as P
     w = small3d_q3
     prob = w.problem
@@ -96,8 +97,8 @@ def q3_long_row():
 @pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("nrhs,fp32", [(16, 1), (16, 0), (8, 0)])
 def test_lds_staged_kernel_with_long_row(q3_long_row, kernel, nrhs, fp32):
-    """The LDS-staged multi-RHS kernel in each staging class ((float, 16), (double, 16), (double, 8)) with
-    length-sorted (1) or ordered (2) rows, on a matrix with one row beyond every staging capacity: V-cycles per
+    """The LDS-staged multi-RHS kernel in each staging class ((float, 16), (double, 16), (double, 8)), pipelined (1)
+    or one workgroup per block (2), on a matrix with one row beyond every staging capacity: V-cycles per
     column against the oracle's, and a lockstep PCG solve (whose float64 operator also takes the kernel) against
     the oracle's solution."""
     import paper_2607_28235_amd as P
