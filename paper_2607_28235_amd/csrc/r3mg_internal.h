@@ -245,8 +245,14 @@ struct DevLevel {
 
 struct PcgScalars;  // device-side PCG state (defined in the solver)
 
+// a fresh value for Device::graph_epoch (unique over the process)
+uint64_t next_graph_epoch();
+
 struct Device {
   int dev = 0;
+  // changes whenever this device's captured graphs are dropped (a buffer they use was reallocated, new values,
+  // another operator): graphs captured elsewhere from this handle (a group solve) are valid while it is unchanged
+  uint64_t graph_epoch = next_graph_epoch();
   std::string tune_sig;  // tuning-cache key prefix of this handle: device and level structure (set at set-up)
   std::vector<DevLevel> lv;
   // dense coarsest: inverse (nL x nL float64, row-major); for up to kDenseSymMaxTiles tile rows also its upper

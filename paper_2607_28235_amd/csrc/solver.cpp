@@ -10,9 +10,12 @@
 // residual at the start of an application and the residual that is restricted are obtained from the last
 // direction instead of a separate b - A x pass.  In exact arithmetic the iterates equal the textbook ones.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -22,6 +25,11 @@
 #include "r3mg_internal.h"
 
 namespace r3mg {
+
+uint64_t next_graph_epoch() {
+  static std::atomic<uint64_t> epoch{0};
+  return ++epoch;
+}
 
 namespace {
 
@@ -139,6 +147,7 @@ void drop_graphs(Device& dv) {
   for (auto& kv : dv.graph_defs) (void)hipGraphDestroy(kv.second);
   dv.graphs.clear();
   dv.graph_defs.clear();
+  dv.graph_epoch = next_graph_epoch();
 }
 
 }  // namespace
@@ -1355,7 +1364,7 @@ static void pcg_operator(Ctx& c, int NR, const double* p, double* q, const int* 
 // One PCG iteration (all launches skip once every column has converged).  part 0: the whole iteration; part 1:
 // q = A p, alpha, the x and r updates and the stop test; part 2: the V-cycle, z, beta and the new p.
 template <typename T>
-static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s, int part = 0) {
+static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s, int part = 0, bool vcycle_skips = false) {
   Analysis& an = c.an;
   Device& dv = c.dv;
   const int L = an.nlevels() - 1;
@@ -1385,7 +1394,9 @@ static void pcg_iteration(Ctx& c, int NR, bool flexible, hipStream_t s, int part
     }
     const T* bl0 = (sizeof(T) == 4) ? vbuf<T>(D0.b) : reinterpret_cast<const T*>(dv.pr.p);
     T* pend = nullptr;
-    if (L > 0) pend = vcycle_rec<T>(c, 0, 1, bl0, nullptr, s);
+    // with vcycle_skips (group solves, where problems converge at different iterations) the V-cycle's kernels
+    // return at once after convergence; otherwise they do not read the flag (one memory latency less each)
+    if (L > 0) pend = vcycle_rec<T>(c, 0, 1, bl0, vcycle_skips ? skip : nullptr, s);
     const T* x0 = (L > 0) ? vbuf<T>(D0.x) : bl0;
     launch_pcg_z1<T>(n, st, part == 0, x0, pend, dv.pz.p, dv.pr.p, flexible ? dv.pq.p : nullptr, P, s);
     launch_pcg_p1(n, st, dv.pz.p, dv.pp.p, P, s);
@@ -1691,8 +1702,10 @@ int residual_history(HandleImpl& h, int col, double* rr, int cap) {
   return m;
 }
 
-// Several problems in one launch sequence: one iteration of every problem is captured into one hipGraph with
-// one branch per problem, and the graph is replayed in chunks as in pcg_block (whole iterations only: a problem
+// Several problems in one launch sequence: one iteration of every problem (its two halves, so that the stop test
+// comes before the V-cycle, whose kernels return at once for a converged problem) is captured into one hipGraph
+// with one branch per problem, and the graph is replayed
+// in chunks as in pcg_block (whole iterations only: a problem
 // restarted by residual replacement must not receive the second half of an iteration); at the end of a chunk
 // every problem's state lands in one pinned array, read after one synchronisation.  Problems with a float32
 // V-cycle get the same true-residual check and restart.
@@ -1714,6 +1727,27 @@ std::vector<hipStream_t>& branch_streams(int dev, int count) {
   }
   return b.s;
 }
+
+// The instantiated group graphs, by device and (handle, graph epoch, V-cycle precision) of every problem in order:
+// a later group solve of the same handles, none of whose graphs was dropped since, replays it without capturing
+// again.  A key never matches a freed or changed handle (epochs are unique), and at most kGroupGraphs are kept.
+struct GroupGraph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  std::vector<hipEvent_t> evs;  // the capture's fork and join events, kept with the graph
+  uint64_t used = 0;
+};
+constexpr size_t kGroupGraphs = 16;
+std::mutex g_group_mu;
+std::map<std::vector<uint64_t>, GroupGraph> g_group_graphs;
+uint64_t g_group_clock = 0;
+
+void destroy_group_graph(GroupGraph& gg) {
+  if (gg.ex) (void)hipGraphExecDestroy(gg.ex);
+  if (gg.g) (void)hipGraphDestroy(gg.g);
+  for (auto e : gg.evs) (void)hipEventDestroy(e);
+  gg = GroupGraph{};
+}
 }  // namespace
 
 r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double* const* x, double rtol, int maxit,
@@ -1722,13 +1756,13 @@ r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double
   R3MG_HIP_CHECK(hipGetDevice(&dev));
   std::vector<hipStream_t>& br = branch_streams(dev, count);
   hipStream_t cap = br[count];
-  hipGraph_t g = nullptr;
+  GroupGraph fresh;       // a graph captured by this call, until it is cached
   hipGraphExec_t ex = nullptr;
   std::vector<hipEvent_t> evs;
   void* pin = nullptr;
+  std::unique_lock<std::mutex> lk(g_group_mu, std::defer_lock);
   auto cleanup = [&]() {
-    if (ex) (void)hipGraphExecDestroy(ex);
-    if (g) (void)hipGraphDestroy(g);
+    destroy_group_graph(fresh);
     for (auto e : evs) (void)hipEventDestroy(e);
     if (pin) (void)hipHostFree(pin);
   };
@@ -1752,11 +1786,22 @@ r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double
       else
         pcg_start<double>(c, 1, 1, rtol, 0.0, false, false, s);
     }
-    // capture one iteration of every problem, each on its own branch
-    {
+    // one iteration of every problem, each on its own branch: the cached graph of these handles, else captured now
+    std::vector<uint64_t> key{(uint64_t)dev};
+    for (int k = 0; k < count; ++k) {
+      key.push_back((uint64_t)(uintptr_t)hs[k]);
+      key.push_back(hs[k]->dev->graph_epoch);
+      key.push_back(is32(k) ? 1 : 0);
+    }
+    lk.lock();  // held until the solve ends: the cached graph is not evicted or replayed by another call meanwhile
+    auto hit = g_group_graphs.find(key);
+    if (hit != g_group_graphs.end()) {
+      hit->second.used = ++g_group_clock;
+      ex = hit->second.ex;
+    } else {
       hipEvent_t fork;
       R3MG_HIP_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-      evs.push_back(fork);
+      fresh.evs.push_back(fork);
       R3MG_HIP_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
       try {
         R3MG_HIP_CHECK(hipEventRecord(fork, cap));
@@ -1764,13 +1809,17 @@ r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double
           HandleImpl& h = *hs[k];
           Ctx c{*h.an, *h.dev, is32(k)};
           R3MG_HIP_CHECK(hipStreamWaitEvent(br[k], fork, 0));
-          if (c.fp32)
-            pcg_iteration<float>(c, 1, true, br[k]);
-          else
-            pcg_iteration<double>(c, 1, false, br[k]);
+          // the iteration in its two halves: the stop test precedes the V-cycle, whose kernels then return at
+          // once in the iteration where the problem converges (problems converge at different iterations)
+          for (int part = 1; part <= 2; ++part) {
+            if (c.fp32)
+              pcg_iteration<float>(c, 1, true, br[k], part, true);
+            else
+              pcg_iteration<double>(c, 1, false, br[k], part, true);
+          }
           hipEvent_t j;
           R3MG_HIP_CHECK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
-          evs.push_back(j);
+          fresh.evs.push_back(j);
           R3MG_HIP_CHECK(hipEventRecord(j, br[k]));
           R3MG_HIP_CHECK(hipStreamWaitEvent(cap, j, 0));
         }
@@ -1780,8 +1829,19 @@ r3mg_status pcg_group(int count, HandleImpl** hs, const double* const* b, double
         if (dead) (void)hipGraphDestroy(dead);
         throw;
       }
-      R3MG_HIP_CHECK(hipStreamEndCapture(cap, &g));
-      R3MG_HIP_CHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+      R3MG_HIP_CHECK(hipStreamEndCapture(cap, &fresh.g));
+      R3MG_HIP_CHECK(hipGraphInstantiate(&fresh.ex, fresh.g, nullptr, nullptr, 0));
+      ex = fresh.ex;
+      if (g_group_graphs.size() >= kGroupGraphs) {  // evict the least recently used
+        auto old = g_group_graphs.begin();
+        for (auto it = g_group_graphs.begin(); it != g_group_graphs.end(); ++it)
+          if (it->second.used < old->second.used) old = it;
+        destroy_group_graph(old->second);
+        g_group_graphs.erase(old);
+      }
+      fresh.used = ++g_group_clock;
+      g_group_graphs[key] = fresh;
+      fresh = GroupGraph{};  // owned by the cache now
     }
     hipEvent_t done_ev;
     R3MG_HIP_CHECK(hipEventCreateWithFlags(&done_ev, hipEventDisableTiming));

@@ -202,7 +202,9 @@ def test_config4_reduced_with_full_size_kernels(cfg4_24, fp32):
 
 
 def test_uneven_group_in_one_graph():
-    """Several independent problems of different sizes solved in one captured launch sequence."""
+    """Several independent problems of different sizes solved in one captured launch sequence.  A second group solve
+    of the same handles replays the cached graph and gives bitwise the same solutions; after new values on one
+    handle (its graphs dropped) the group is captured again and still solves."""
     _need_gpu()
     import paper_2607_28235_amd as P
     batch = F.uneven_batch([8, 10, 12, 14])
@@ -220,6 +222,18 @@ def test_uneven_group_in_one_graph():
     for (prob, b), x, it, ref in zip(batch, xs, iters, refs):
         assert abs(int(it) - ref[1]) <= 1
         assert _rel(x.cpu().numpy(), ref[0]) < 1e-9
+    xs2 = [torch.zeros_like(x) for x in xs]
+    iters2, _, ok2 = P.solve_group(hs, bs, xs2, rtol=1e-10, maxit=200)
+    assert ok2 and list(iters2) == list(iters)
+    assert all(torch.equal(a, c) for a, c in zip(xs, xs2))
+    prob0 = batch[0][0]
+    hs[0].update_values(_t(prob0.val))
+    torch.cuda.synchronize()
+    xs3 = [torch.zeros_like(x) for x in xs]
+    iters3, _, ok3 = P.solve_group(hs, bs, xs3, rtol=1e-10, maxit=200)
+    assert ok3 and list(iters3) == list(iters)
+    for x3, ref in zip(xs3, refs):
+        assert _rel(x3.cpu().numpy(), ref[0]) < 1e-9
 
 
 def _cfg5(N):
