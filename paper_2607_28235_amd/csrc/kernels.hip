@@ -1242,7 +1242,7 @@ __device__ __forceinline__ void lmr_epi_store(int64_t o, VT t, VT old, VT ui, VT
 // which the workgroup sums from global memory: phase j takes the entries j, j + TPB / CH, ..., and the phase sums
 // are added in phase order.
 template <typename T, int NR, int CAP, int UCAP>
-__global__ __launch_bounds__(512) void k_level_lmr(int nrb, const int* __restrict__ rb, const int* __restrict__ ubp,
+__global__ __launch_bounds__(512) void k_level_lmr(int nrb, const int4* __restrict__ meta,
                                                    const int* __restrict__ ucol, const uint16_t* __restrict__ lidx,
                                                    const int* __restrict__ ord, const int* __restrict__ ptr,
                                                    const int* __restrict__ idx, const T* __restrict__ val,
@@ -1268,9 +1268,12 @@ __global__ __launch_bounds__(512) void k_level_lmr(int nrb, const int* __restric
   __shared__ VT us[UCAP * CH + 1];
   const int tid = threadIdx.x;
   const int q = tid % CH, h = (tid / CH) & 1, slot = tid / (2 * CH);
-  const int r0 = rb[lb], r1 = rb[lb + 1];
-  const int e0 = ptr[r0], e1 = ptr[r1];
-  const int u0 = ubp[lb], nu = ubp[lb + 1] - u0;
+  // first row, first nonzero and first distinct column of this block and of the next: one round trip, after
+  // which the value and position streams can be issued
+  const int4 m0 = meta[lb], m1 = meta[lb + 1];
+  const int r0 = m0.x, r1 = m1.x;
+  const int e0 = m0.y, e1 = m1.y;
+  const int u0 = m0.z, nu = m1.z - u0;
   const int vb = e0 & ~(VW - 1), pb = e0 & ~7;
   const int nvc = (e1 - vb + VW - 1) / VW, npc = (e1 - pb + 7) / 8;
   VT t = (VT)0;
@@ -1527,9 +1530,10 @@ __global__ __launch_bounds__(1024) void k_level_lmr_pipe(int nrb, int nwg, const
 template <typename T, int NR, int CLS>
 static void launch_lmr_t(const MrBlocks& mb, const LevelOp<T>& op, const int* ord, const T* u, const T* b, T* rho,
                          T* x, T* dout, double c1, double c2, int flags, const int* skip, hipStream_t s) {
+  if (!mb.meta) throw std::runtime_error("LDS-staged multi-RHS kernel: block records missing");
   hipLaunchKernelGGL((k_level_lmr<T, NR, kMrCap[CLS], kMrUcap[CLS]>), dim3(xcd_grid(mb.nrb)), dim3(512), 0, s, mb.nrb,
-                     mb.rb, mb.ubp, mb.ucol, mb.lidx, ord, op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1,
-                     (T)c2, flags, skip);
+                     reinterpret_cast<const int4*>(mb.meta), mb.ucol, mb.lidx, ord, op.ptr, op.idx, op.val, u, b,
+                     rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip);
 }
 
 template <typename T, int NR, int CLS>
