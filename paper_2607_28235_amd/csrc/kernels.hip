@@ -3478,15 +3478,26 @@ __global__ __launch_bounds__(256) void k_dchol_panel(int n, int k0, double* A, c
   dt_store(acc, A, n, R, k0, false);
 }
 
-// 1. Trailing update of the lower tiles (I, J), k0 < J <= I: A_IJ -= A_Ik A_Jk^T.  blockIdx.x enumerates the
-// pairs row by row (I = k0/64 + 1 + a, J = k0/64 + 1 + b, b <= a).
-__global__ __launch_bounds__(256) void k_dchol_update(int n, int k0, double* A) {
+// 1. Trailing update of the lower tiles (I, J), k0 < J <= I: A_IJ -= A_Ik A_Jk^T, with I = k0/64 + 1 + a and
+// J = k0/64 + 1 + b.  part 0: every pair (b <= a), enumerated row by row; part 1: the next column only (b = 0,
+// a = blockIdx.x); part 2: the other columns (1 <= b <= a), enumerated row by row.
+__global__ __launch_bounds__(256) void k_dchol_update(int n, int k0, double* A, int part) {
   __shared__ double sa[DT][DT + 1];
   __shared__ double sb[DT][DT + 1];
-  int a = (int)((sqrt(8.0 * blockIdx.x + 1.0) - 1.0) * 0.5);
-  while ((a + 1) * (a + 2) / 2 <= (int)blockIdx.x) ++a;
-  while (a * (a + 1) / 2 > (int)blockIdx.x) --a;
-  const int b = (int)blockIdx.x - a * (a + 1) / 2;
+  int a, b;
+  if (part == 1) {
+    a = (int)blockIdx.x;
+    b = 0;
+  } else {
+    a = (int)((sqrt(8.0 * blockIdx.x + 1.0) - 1.0) * 0.5);
+    while ((a + 1) * (a + 2) / 2 <= (int)blockIdx.x) ++a;
+    while (a * (a + 1) / 2 > (int)blockIdx.x) --a;
+    b = (int)blockIdx.x - a * (a + 1) / 2;
+    if (part == 2) {  // pairs of the triangle without column 0
+      ++a;
+      ++b;
+    }
+  }
   const int RI = k0 + DT * (1 + a), RJ = k0 + DT * (1 + b);
   dt_load(sa, A, n, RI, k0, true, false);    // Aop(i, k) = A_Ik[i][k]
   dt_load(sb, A, n, RJ, k0, true, false);    // Bop(k, j) = A_Jk[j][k]
@@ -3565,8 +3576,34 @@ __global__ __launch_bounds__(256) void k_dinv_gram(int n, int nt, const double* 
 }
 
 // ws: nt * 64 * 64 doubles (the inverted diagonal tiles); Y: n * n doubles of scratch
+// The factorisation looks one step ahead: step kb's update of the next column (part 1) stays on s, while the
+// update of the other columns (part 2) runs on a second stream, so that diagonal tile and panel kb + 1, which
+// touch column kb + 1 only, overlap it.  Part 1 of step kb + 1 writes column kb + 2, which part 2 of step kb also
+// writes, so it waits for that; parts 2 follow one another on the second stream.
+namespace {
+struct LookAhead {
+  hipStream_t s2 = nullptr;
+  std::vector<hipEvent_t> ev;
+  ~LookAhead() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+    if (s2) (void)hipStreamDestroy(s2);
+  }
+  hipEvent_t event() {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      throw std::runtime_error("dense Cholesky: event creation failed");
+    ev.push_back(e);
+    return e;
+  }
+};
+}  // namespace
+
 void dense_cholesky_inverse(int n, double* A, double* Inv, double* ws, double* Y, int* bad, hipStream_t s) {
   const int nt = (n + DT - 1) / DT;
+  LookAhead la;
+  if (hipStreamCreateWithFlags(&la.s2, hipStreamNonBlocking) != hipSuccess)
+    throw std::runtime_error("dense Cholesky: stream creation failed");
+  hipEvent_t prev2 = nullptr;  // part 2 of the previous step done
   for (int kb = 0; kb < nt; ++kb) {
     const int k0 = kb * DT;
     double* Dk = ws + (size_t)kb * DT * DT;
@@ -3574,9 +3611,21 @@ void dense_cholesky_inverse(int n, double* A, double* Inv, double* ws, double* Y
     const int below = nt - kb - 1;
     if (below > 0) {
       hipLaunchKernelGGL(k_dchol_panel, dim3(below), dim3(256), 0, s, n, k0, A, Dk);
-      hipLaunchKernelGGL(k_dchol_update, dim3(below * (below + 1) / 2), dim3(256), 0, s, n, k0, A);
+      if (prev2 && hipStreamWaitEvent(s, prev2, 0) != hipSuccess)
+        throw std::runtime_error("dense Cholesky: stream wait failed");
+      hipLaunchKernelGGL(k_dchol_update, dim3(below), dim3(256), 0, s, n, k0, A, 1);
+      if (below > 1) {
+        hipEvent_t main = la.event();
+        if (hipEventRecord(main, s) != hipSuccess || hipStreamWaitEvent(la.s2, main, 0) != hipSuccess)
+          throw std::runtime_error("dense Cholesky: event record failed");
+        hipLaunchKernelGGL(k_dchol_update, dim3((below - 1) * below / 2), dim3(256), 0, la.s2, n, k0, A, 2);
+        prev2 = la.event();
+        if (hipEventRecord(prev2, la.s2) != hipSuccess) throw std::runtime_error("dense Cholesky: event record failed");
+      }
     }
   }
+  if (prev2 && hipStreamWaitEvent(s, prev2, 0) != hipSuccess)
+    throw std::runtime_error("dense Cholesky: stream wait failed");
   check_launch("dense Cholesky");
   hipMemsetAsync(Y, 0, (size_t)n * n * sizeof(double), s);
   for (int kb = 0; kb < nt; ++kb) {
