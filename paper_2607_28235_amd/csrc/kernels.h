@@ -149,9 +149,10 @@ template <typename T>
 void launch_restrict0(int nbox, int64_t n_points, int d, int pc, int nr, const int* leaf_off, const int* owner,
                       const T* xi, const T* src, T* bnext, const T* dinv_next, T* dnext, double inv_theta_next,
                       const int* skip, hipStream_t s);
+// (several columns: one workgroup per level-1 box, nbox boxes with points leaf_off[K] .. leaf_off[K+1] - 1)
 template <typename T>
-void launch_prolong0(int n, int d, int pc, int nr, const int* owner, const T* xi, const T* e, const T* epend,
-                     T* v, const int* skip, hipStream_t s);
+void launch_prolong0(int n, int nbox, int d, int pc, int nr, const int* leaf_off, const int* owner, const T* xi,
+                     const T* e, const T* epend, T* v, const int* skip, hipStream_t s);
 template <typename T>
 void launch_restrict_c(int nbox_next, int nbox, int shift, int d, int pc, int nr, const T* pt, const T* src,
                        T* bnext, const T* dinv_next, T* dnext, double inv_theta_next, const int* skip,

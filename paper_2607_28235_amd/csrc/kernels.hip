@@ -2293,57 +2293,61 @@ __global__ __launch_bounds__(256) void k_prolong0(int n, Basis1D<T> bs, int nr, 
   }
 }
 
-// The same for nr > 1 columns: thread (i, j) takes fine point i and column chunk j (chunks of one point adjacent).
+// The same for nr > 1 columns: one workgroup per level-1 box K (its points are leaf_off[K] .. leaf_off[K+1] - 1,
+// owned by K or constrained).  The box's B coarse entries of e + epend (all columns) are formed once in LDS; thread
+// (i, j) of the box then takes fine point i and column chunk j (chunks of one point adjacent), in k_prolong0's
+// order.  Reading the entries from LDS instead of L2 for every point and chunk was what bounded the kernel.
 template <typename T, int D, int KB, int VW>
-__global__ __launch_bounds__(256) void k_prolong0_mr(int n, Basis1D<T> bs, int nr, const int* __restrict__ owner,
-                                                     const T* __restrict__ xi, const T* __restrict__ e,
-                                                     const T* __restrict__ epend, T* v, const int* __restrict__ skip,
-                                                     int nlog) {
+__global__ __launch_bounds__(256) void k_prolong0_mr(Basis1D<T> bs, int nr, const int* __restrict__ leaf_off,
+                                                     const int* __restrict__ owner, const T* __restrict__ xi,
+                                                     const T* __restrict__ e, const T* __restrict__ epend, T* v,
+                                                     const int* __restrict__ skip) {
   using VT = typename ColVec<T, VW>::type;
   constexpr int B = D == 3 ? KB * KB * KB : KB * KB;
   if (skip && *skip) return;
-  const int lb = xcd_block(nlog);
-  if (lb < 0) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  VT* es = reinterpret_cast<VT*>(smem_raw);  // [B][nch]
   const int nch = nr / VW;
-  const int64_t t = (int64_t)lb * 256 + threadIdx.x;
-  if (t >= (int64_t)n * nch) return;
-  const int i = (int)(t / nch), j = (int)(t - (int64_t)i * nch);
-  VT* out = reinterpret_cast<VT*>(v + (int64_t)i * nr + j * VW);
-  const int K = owner[i];
-  if (K < 0) {
-    *out = (VT)0;
-    return;
-  }
-  T l[3][4];
-#pragma unroll
-  for (int a = 0; a < D; ++a) lag1d_k<T, KB>(bs, xi[(int64_t)i * D + a], l[a]);
-  VT sum = (VT)0;
-  for_each_phi<T, D, KB>(l, [&](int q, T ph) {
-    const int64_t o = ((int64_t)K * B + q) * nr + j * VW;
+  const int K = blockIdx.x;
+  const int i0 = leaf_off[K], i1 = leaf_off[K + 1];
+  for (int t = threadIdx.x; t < B * nch; t += blockDim.x) {
+    const int64_t o = (int64_t)K * B * nr + (int64_t)t * VW;  // entry (K B + t / nch), chunk t % nch
     VT ev = *reinterpret_cast<const VT*>(e + o);
     if (epend) ev += *reinterpret_cast<const VT*>(epend + o);
-    sum += ph * ev;
-  });
-  *out = sum;
+    es[t] = ev;
+  }
+  __syncthreads();
+  const int total = (i1 - i0) * nch;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int i = i0 + idx / nch, j = idx - (idx / nch) * nch;
+    const int ow = owner[i];  // unconditional loads; a constrained point's value is replaced by zero
+    T l[3][4];
+#pragma unroll
+    for (int a = 0; a < D; ++a) lag1d_k<T, KB>(bs, xi[(int64_t)i * D + a], l[a]);
+    VT sum = (VT)0;
+    for_each_phi<T, D, KB>(l, [&](int q, T ph) { sum += ph * es[q * nch + j]; });
+    *reinterpret_cast<VT*>(v + (int64_t)i * nr + j * VW) = ow < 0 ? (VT)0 : sum;
+  }
 }
 
 template <typename T>
-void launch_prolong0(int n, int d, int pc, int nr, const int* owner, const T* xi, const T* e, const T* epend,
-                     T* v, const int* skip, hipStream_t s) {
+void launch_prolong0(int n, int nbox, int d, int pc, int nr, const int* leaf_off, const int* owner, const T* xi,
+                     const T* e, const T* epend, T* v, const int* skip, hipStream_t s) {
   const Basis1D<T> bs = make_basis<T>(pc);
   constexpr int VW = col_vw<T>();
   if (nr > 1 && nr % std::min(nr, VW) == 0 && aligned16(e) && (!epend || aligned16(epend)) && aligned16(v)) {
     const int vw = std::min(nr, VW), nch = nr / vw;
-    const int nlogm = (int)(((int64_t)n * nch + 255) / 256);
-    if (nlogm == 0) return;
-#define R3MG_P0M(DD, KK)                                                                                            \
-  do {                                                                                                              \
-    if (vw == 2)                                                                                                    \
-      hipLaunchKernelGGL((k_prolong0_mr<T, DD, KK, 2>), dim3(xcd_grid(nlogm)), dim3(256), 0, s, n, bs, nr, owner, xi, \
-                         e, epend, v, skip, nlogm);                                                                   \
-    else                                                                                                            \
-      hipLaunchKernelGGL((k_prolong0_mr<T, DD, KK, VW>), dim3(xcd_grid(nlogm)), dim3(256), 0, s, n, bs, nr, owner,    \
-                         xi, e, epend, v, skip, nlogm);                                                               \
+    const int k = pc + 1, B = (d == 3) ? k * k * k : k * k;
+    if (nbox == 0) return;
+    const size_t shm = (size_t)16 * B * nch;
+#define R3MG_P0M(DD, KK)                                                                                           \
+  do {                                                                                                             \
+    if (vw == 2)                                                                                                   \
+      hipLaunchKernelGGL((k_prolong0_mr<T, DD, KK, 2>), dim3(nbox), dim3(256), shm, s, bs, nr, leaf_off, owner, xi, \
+                         e, epend, v, skip);                                                                         \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_prolong0_mr<T, DD, KK, VW>), dim3(nbox), dim3(256), shm, s, bs, nr, leaf_off, owner,    \
+                         xi, e, epend, v, skip);                                                                     \
   } while (0)
     switch (d * 8 + pc + 1) {
       case 17: R3MG_P0M(2, 1); break;
@@ -2379,10 +2383,10 @@ void launch_prolong0(int n, int d, int pc, int nr, const int* owner, const T* xi
 #undef R3MG_P0
   check_launch("k_prolong0");
 }
-template void launch_prolong0<float>(int, int, int, int, const int*, const float*, const float*, const float*,
-                                     float*, const int*, hipStream_t);
-template void launch_prolong0<double>(int, int, int, int, const int*, const double*, const double*, const double*,
-                                      double*, const int*, hipStream_t);
+template void launch_prolong0<float>(int, int, int, int, int, const int*, const int*, const float*, const float*,
+                                     const float*, float*, const int*, hipStream_t);
+template void launch_prolong0<double>(int, int, int, int, int, const int*, const int*, const double*,
+                                      const double*, const double*, double*, const int*, hipStream_t);
 
 // P~ entry [q'][q] of child box c: prod_a M_c[a][q'_a][q_a]
 template <typename T>

@@ -772,7 +772,8 @@ T* vcycle_rec(Ctx& c, int l, int nr, const T* b_override, const int* skip, hipSt
     T* pend_c = vcycle_rec<T>(c, l + 1, nr, nullptr, skip, s);
     const T* xi;
     if constexpr (sizeof(T) == 4) xi = D.xi32.p; else xi = D.xi64.p;
-    launch_prolong0<T>((int)D.n, an.d, an.pc, nr, D.owner.p, xi, wv<T>(c, l + 1, W_X), pend_c, v, skip, s);
+    launch_prolong0<T>((int)D.n, (int)N.nbox, an.d, an.pc, nr, D.leaf_off.p, D.owner.p, xi, wv<T>(c, l + 1, W_X),
+                       pend_c, v, skip, s);
   } else {
     T* pend_c = vcycle_rec<T>(c, l + 1, nr, nullptr, skip, s);
     launch_prolong_c<T>((int)D.nbox, N.child_shift, an.d, an.pc, nr, pt, wv<T>(c, l + 1, W_X), pend_c, v, skip, s);
