@@ -2125,13 +2125,15 @@ __global__ __launch_bounds__(256) void k_restrict0(Basis1D<T> bs, int nr, const 
   }
 }
 
-// Restriction to the first agglomerated level for nr > 1 columns: one workgroup per box K, thread (g, j) takes the
-// KB consecutive coarse functions q = KB g .. KB g + KB - 1 (same q1, q2) and column chunk j.  The box's points go
-// through LDS 32 at a time: their 1D basis values (one thread per point) and their nr entries of src (zero at
-// constrained points); each thread then adds phi_q(xi_i) src_i over the 32 points in index order, phi_q formed as
-// l0[q0] (l1[q1] l2[q2]).
+// Restriction to the first agglomerated level for nr > 1 columns: one workgroup per box K, in teams of tsize
+// threads.  Thread (g, j) of a team takes the KB consecutive coarse functions q = KB g .. KB g + KB - 1 (same q1,
+// q2) and column chunk j.  Team t takes the box's points in chunks of 32 (chunks t, t + nteam, ...) through its own
+// LDS: the chunk's 1D basis values (one thread per point) and nr entries of src (zero at constrained points); each
+// thread adds phi_q(xi_i) src_i over the chunk's points in index order, phi_q formed as l0[q0] (l1[q1] l2[q2]).
+// The team sums are then added in team order.  A team is one wave when its threads fit one (four teams, synchronised
+// per wave), else the whole workgroup (one team).
 template <typename T, int D, int KB, int VW>
-__global__ __launch_bounds__(512) void k_restrict0_mr(Basis1D<T> bs, int nr, const int* __restrict__ leaf_off,
+__global__ __launch_bounds__(512) void k_restrict0_mr(Basis1D<T> bs, int nr, int tsize, const int* __restrict__ leaf_off,
                                                       const int* __restrict__ owner, const T* __restrict__ xi,
                                                       const T* __restrict__ src, T* bnext,
                                                       const T* __restrict__ dinv_next, T* dnext, T inv_theta_next,
@@ -2142,36 +2144,48 @@ __global__ __launch_bounds__(512) void k_restrict0_mr(Basis1D<T> bs, int nr, con
   constexpr int LW = D * KB;  // 1D values per point
   if (skip && *skip) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  VT* ss = reinterpret_cast<VT*>(smem_raw);                 // [P][nch] entries of src
   const int nch = nr / VW;
-  T* lt = reinterpret_cast<T*>(ss + P * nch);               // [P][LW] 1D values
+  const int nteam = blockDim.x / tsize, team = threadIdx.x / tsize, tt = threadIdx.x - team * tsize;
+  const bool wave_teams = nteam > 1;  // then tsize == 64
+  const size_t region = ((size_t)P * nch * sizeof(VT) + (size_t)P * LW * sizeof(T) + 15) / 16 * 16;
+  VT* ss = reinterpret_cast<VT*>(smem_raw + team * region);  // [P][nch] entries of src
+  T* lt = reinterpret_cast<T*>(ss + P * nch);                  // [P][LW] 1D values
+  auto team_sync = [&]() {
+    if (wave_teams) {
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
+  };
   const int K = blockIdx.x;
   const int i0 = leaf_off[K], i1 = leaf_off[K + 1];
-  const int g = threadIdx.x / nch, j = threadIdx.x - g * nch;
+  const int g = tt / nch, j = tt - g * nch;
   const bool active = g < B / KB;
   const int q1 = g % KB, q2 = g / KB;
   VT acc[KB];
 #pragma unroll
   for (int a = 0; a < KB; ++a) acc[a] = (VT)0;
-  for (int base = i0; base < i1; base += P) {
+  for (int base = i0 + team * P; base < i1; base += nteam * P) {
     const int np = min(P, i1 - base);
-    for (int t = threadIdx.x; t < np * nch; t += blockDim.x) {
+    for (int t = tt; t < np * nch; t += tsize) {
       const int pp = t / nch, jj = t - pp * nch;
       const int i = base + pp;
       const VT sv = *reinterpret_cast<const VT*>(src + (int64_t)i * nr + jj * VW);
       ss[t] = owner[i] >= 0 ? sv : (VT)0;
     }
-    if (threadIdx.x < np) {
-      const int i = base + threadIdx.x;
+    if (tt < np) {
+      const int i = base + tt;
       T l[3][4];
 #pragma unroll
       for (int a = 0; a < D; ++a) lag1d_k<T, KB>(bs, xi[(int64_t)i * D + a], l[a]);
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int m = 0; m < KB; ++m) lt[threadIdx.x * LW + a * KB + m] = l[a][m];
+        for (int m = 0; m < KB; ++m) lt[tt * LW + a * KB + m] = l[a][m];
     }
-    __syncthreads();
+    team_sync();
     if (active) {
       for (int pp = 0; pp < np; ++pp) {
         const T* lp = lt + pp * LW;
@@ -2182,7 +2196,20 @@ __global__ __launch_bounds__(512) void k_restrict0_mr(Basis1D<T> bs, int nr, con
         for (int a = 0; a < KB; ++a) acc[a] += (lp[a] * l12) * sv;
       }
     }
+    team_sync();
+  }
+  if (wave_teams) {  // team sums through LDS, added in team order by team 0
+    VT* comb = reinterpret_cast<VT*>(smem_raw + nteam * region);  // [nteam][KB][64]
+#pragma unroll
+    for (int a = 0; a < KB; ++a) comb[(team * KB + a) * 64 + tt] = acc[a];
     __syncthreads();
+    if (team != 0) return;
+#pragma unroll
+    for (int a = 0; a < KB; ++a) {
+      VT t = comb[a * 64 + tt];
+      for (int u = 1; u < nteam; ++u) t += comb[(u * KB + a) * 64 + tt];
+      acc[a] = t;
+    }
   }
   if (active) {
 #pragma unroll
@@ -2210,17 +2237,20 @@ void launch_restrict0(int nbox, int64_t n_points, int d, int pc, int nr, const i
   constexpr int VW = col_vw<T>();
   if (nr > 1 && nr % std::min(nr, VW) == 0 && aligned16(src) && aligned16(bnext) && (!dnext || aligned16(dnext))) {
     const int vw = std::min(nr, VW), nch = nr / vw;
-    const int thr = ((B / k) * nch + 63) / 64 * 64;
-    if (thr > 512) throw std::runtime_error("restriction: too many columns");
-    const size_t shm = sizeof(T) * ((size_t)32 * nr + (size_t)32 * d * k);
+    const int tsize = ((B / k) * nch + 63) / 64 * 64;  // threads of a team
+    if (tsize > 512) throw std::runtime_error("restriction: too many columns");
+    const int nteam = tsize == 64 ? 4 : 1, thr = tsize * nteam;
+    const size_t esz = vw * sizeof(T);  // bytes of one column chunk
+    const size_t region = ((size_t)32 * nch * esz + (size_t)32 * d * k * sizeof(T) + 15) / 16 * 16;
+    const size_t shm = nteam * region + (nteam > 1 ? (size_t)nteam * k * 64 * esz : 0);
 #define R3MG_R0M(DD, KK)                                                                                           \
   do {                                                                                                             \
     if (vw == 2)                                                                                                   \
-      hipLaunchKernelGGL((k_restrict0_mr<T, DD, KK, 2>), dim3(nbox), dim3(thr), shm, s, bs, nr, leaf_off, owner, xi, \
-                         src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);                                     \
+      hipLaunchKernelGGL((k_restrict0_mr<T, DD, KK, 2>), dim3(nbox), dim3(thr), shm, s, bs, nr, tsize, leaf_off,    \
+                         owner, xi, src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);                          \
     else                                                                                                           \
-      hipLaunchKernelGGL((k_restrict0_mr<T, DD, KK, VW>), dim3(nbox), dim3(thr), shm, s, bs, nr, leaf_off, owner,    \
-                         xi, src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);                                 \
+      hipLaunchKernelGGL((k_restrict0_mr<T, DD, KK, VW>), dim3(nbox), dim3(thr), shm, s, bs, nr, tsize, leaf_off,   \
+                         owner, xi, src, bnext, dinv_next, dnext, (T)inv_theta_next, skip);                          \
   } while (0)
     switch (d * 8 + k) {
       case 17: R3MG_R0M(2, 1); break;
