@@ -3719,6 +3719,32 @@ __device__ inline void column_totals(const double* __restrict__ part, int nb, in
   __syncthreads();
 }
 
+// Two one-column totals at once, each exactly as column_totals<1> forms it (pa[b * sa] and pb[b * sb], b < nb):
+// the loads of both are in flight together.  ta, tb (shared) are valid in every thread on return.
+__device__ inline void column_totals2(const double* __restrict__ pa, int sa, const double* __restrict__ pb, int sb,
+                                      int nb, double* sh, double* ta, double* tb) {
+  double acca = 0, accb = 0;
+  for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * 256) {
+    double va[4], vb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t b = min(b0 + u * 256, nb - 1);
+      va[u] = pa[b * sa];
+      vb[u] = pb[b * sb];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (b0 + u * 256 < nb) {
+        acca += va[u];
+        accb += vb[u];
+      }
+  }
+  column_partials<1>(acca, sh, ta);
+  __syncthreads();
+  column_partials<1>(accb, sh, tb);
+  __syncthreads();
+}
+
 // grid-stride steps of the one-column PCG vector kernels whose loads are issued together
 constexpr int kPcgU = 4;
 inline int pcg_grid(int n) {
@@ -4002,8 +4028,7 @@ __global__ __launch_bounds__(256) void k_pcg_xr1(int n, PcgState* st, double* x,
   __shared__ double sh[4];
   __shared__ double gam[1], pq[1];
   if (st->all_done) return;
-  column_totals<1>(partials + 2 * g, g, 2, sh, gam);
-  column_totals<1>(partials, g, 1, sh, pq);
+  column_totals2(partials + 2 * g, 2, partials, 1, g, sh, gam, pq);
   const double al = st->done[0] ? 0.0 : gam[0] / pq[0];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->gamma[0] = gam[0];
@@ -4134,8 +4159,7 @@ __global__ __launch_bounds__(256) void k_pcg_p1(int n, PcgState* st, const doubl
   __shared__ double sh[4];
   __shared__ double rz[1], qz[1];
   if (st->all_done || st->done[0]) return;
-  column_totals<1>(partials + 2 * g, g, 2, sh, rz);
-  column_totals<1>(partials + 2 * g + 1, g, 2, sh, qz);
+  column_totals2(partials + 2 * g, 2, partials + 2 * g + 1, 2, g, sh, rz, qz);
   const double gold = st->gamma[0];
   const double be = st->flexible ? (-st->alpha[0] * qz[0]) / gold : rz[0] / gold;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
