@@ -334,8 +334,17 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
           an->xi[p * d + a] = (an->coords_int[p * d + a] - H1.lo[k * d + a]) / (H1.hi[k * d + a] - H1.lo[k * d + a]);
     }
   {
-    std::atomic<int64_t> bad{-1};
-    std::atomic<int> bad_kind{0};
+    // The box reported does not depend on the order in which the threads reach the boxes: the lowest box that
+    // owns fewer than B points if there is one, else the lowest box among those whose Cholesky fails at the
+    // earliest column (stage 0: too few points, stage j + 1: pivot j).
+    const int64_t nbox1 = H1.nbox;
+    std::atomic<int64_t> bad{-1};  // stage * nbox1 + box, the least over the failing boxes
+    auto note_bad = [&](int64_t stage, int64_t k) {
+      const int64_t key = stage * nbox1 + k;
+      int64_t cur = bad.load();
+      while ((cur < 0 || key < cur) && !bad.compare_exchange_weak(cur, key)) {
+      }
+    };
     const int k1 = pc + 1;
     parallel_for(H1.nbox, [&](int64_t k) {
       std::vector<double> G(B * B, 0.0), L(B * B, 0.0), phi(B);
@@ -356,9 +365,7 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
           for (int j = 0; j < B; ++j) G[i * B + j] += phi[i] * phi[j];
       }
       if (cnt < B) {
-        int64_t expect = -1;
-        bad.compare_exchange_strong(expect, k);
-        bad_kind = 1;
+        note_bad(0, k);
         return;
       }
       double dmax = 0;
@@ -368,8 +375,7 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
         double piv = G[j * B + j];
         for (int c = 0; c < j; ++c) piv -= L[j * B + c] * L[j * B + c];
         if (!(piv > tol)) {
-          int64_t expect = -1;
-          bad.compare_exchange_strong(expect, k);
+          note_bad(1 + j, k);
           return;
         }
         L[j * B + j] = std::sqrt(piv);
@@ -380,7 +386,7 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
         }
       }
     });
-    if (bad >= 0) throw err(R3MG_ERR_NOT_UNISOLVENT, "box " + std::to_string((long long)bad.load()) +
+    if (bad >= 0) throw err(R3MG_ERR_NOT_UNISOLVENT, "box " + std::to_string((long long)(bad.load() % nbox1)) +
                                                     " cannot interpolate Q^p' from its owned points");
   }
   for (int l = 2; l <= L; ++l) check_degenerate(l);

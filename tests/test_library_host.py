@@ -256,13 +256,18 @@ def test_simplicial_analysis_matches_oracle(p, pc):
 
 def test_simplicial_cell_boxes_not_unisolvent_like_the_oracle():
     """First-come ownership on a triangulation can leave a leaf box whose owned points do not determine Q^p';
-    library and oracle reject the same box."""
+    library and oracle reject the same box.  Several boxes fail here and the library checks boxes on several
+    threads, so the analysis is repeated: the box it reports must not depend on the threads' order."""
     prob = F.simplicial_pp(24, 2, jitter=0.2, cfg=2)
     o = P.Options(dim=2, coarse_degree=2, leaf_size=8, max_coarse_dofs=200)
-    with pytest.raises(P.R3mgError) as e:
-        P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o, factor=False, cells=prob.cells)
-    assert e.value.code == "NOT_UNISOLVENT"
-    box = re.search(r"box (\d+)", str(e.value)).group(1)
+    boxes = set()
+    for _ in range(6):
+        with pytest.raises(P.R3mgError) as e:
+            P.Hierarchy(prob.coords, prob.row_ptr, prob.col, prob.val, o, factor=False, cells=prob.cells)
+        assert e.value.code == "NOT_UNISOLVENT"
+        boxes.add(re.search(r"box (\d+)", str(e.value)).group(1))
+    assert len(boxes) == 1
+    box = boxes.pop()
     from oracle.hierarchy import R3mgError as OracleError
     with pytest.raises(OracleError) as eo:
         O.build_hierarchy(prob.coords, prob.scipy(), coarse_degree=2, leaf_size=8, max_coarse_dofs=200,
