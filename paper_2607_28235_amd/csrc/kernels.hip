@@ -3332,14 +3332,37 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // with the index running across the lanes, so an operand whose index is its row is loaded transposed.
 __device__ inline void dt_load(double (*s)[DT + 1], const double* __restrict__ M, int n, int R, int C, bool trans,
                                bool diag_pad) {
-  for (int e = threadIdx.x; e < DT * DT; e += 256) {
-    const int i = e >> 6, j = e & 63;
-    double v = (diag_pad && i == j) ? 1.0 : 0.0;
-    if (R + i < n && C + j < n) v = M[(int64_t)(R + i) * n + C + j];
+  // element (i, j) = (threadIdx.x / 64 + 4 q, threadIdx.x % 64) for q < 16; the 16 loads come from clamped
+  // addresses and are all issued before the first is used, and entries outside the matrix are masked afterwards
+  // (a load under a lane-dependent condition would be waited for on its own)
+  constexpr int K = DT * DT / 256;
+  const int j = threadIdx.x & 63, i0 = threadIdx.x >> 6;
+  const int64_t cj = min(C + j, n - 1);
+  double v[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) v[q] = M[(int64_t)min(R + i0 + 4 * q, n - 1) * n + cj];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int i = i0 + 4 * q;
+    const double x = (R + i < n && C + j < n) ? v[q] : (diag_pad && i == j) ? 1.0 : 0.0;
     if (trans)
-      s[j][i] = v;
+      s[j][i] = x;
     else
-      s[i][j] = v;
+      s[i][j] = x;
+  }
+}
+
+// a 64 x 64 tile of 64 x 64 values stored contiguously (row-major) into LDS, transposed: s[e % 64][e / 64] = T[e]
+// (all loads issued before the first store)
+__device__ inline void dt_load_packed_t(double (*s)[DT + 1], const double* __restrict__ T) {
+  constexpr int K = DT * DT / 256;
+  double v[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) v[q] = T[threadIdx.x + 256 * q];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    s[e & 63][e >> 6] = v[q];
   }
 }
 
@@ -3377,14 +3400,32 @@ __device__ inline void dt_each(const v4d acc[2][2], F f) {
       for (int r = 0; r < 4; ++r) f(r0 + 16 * s + 4 * r + (l >> 4), c0 + 16 * t + (l & 15), acc[s][t][r]);
 }
 
-// M tile (R, C) -= acc (sub) or = acc, inside the matrix
+// M tile (R, C) -= acc (sub) or = acc, inside the matrix.  For sub, the old values are loaded first from
+// clamped addresses, all before the first is used.
 __device__ inline void dt_store(const v4d acc[2][2], double* M, int n, int R, int C, bool sub) {
-  dt_each(acc, [&](int i, int j, double v) {
-    if (R + i < n && C + j < n) {
-      double* p = M + (int64_t)(R + i) * n + C + j;
-      *p = sub ? *p - v : v;
-    }
-  });
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+  double old[2][2][4];
+  if (sub) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = r0 + 16 * s + 4 * r + (l >> 4), j = c0 + 16 * t + (l & 15);
+          old[s][t][r] = M[(int64_t)min(R + i, n - 1) * n + min(C + j, n - 1)];
+        }
+  }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + 16 * s + 4 * r + (l >> 4), j = c0 + 16 * t + (l & 15);
+        if (R + i < n && C + j < n) M[(int64_t)(R + i) * n + C + j] = sub ? old[s][t][r] - acc[s][t][r] : acc[s][t][r];
+      }
 }
 
 // sum over m in [m0, m1) of x[m sx] y[m sy] from LDS, in eight interleaved partial sums combined in a fixed
@@ -3471,11 +3512,15 @@ struct DiagInv {
 __global__ __launch_bounds__(64) void k_dchol_diag(int n, int k0, double* A, double* Dk, int* bad) {
   __shared__ __align__(16) double s[DT * kDiagLD];
   const int l = threadIdx.x;
-  for (int e = l; e < DT * DT; e += 64) {
-    const int i = e >> 6, j = e & 63;
-    double v = (i == j) ? 1.0 : 0.0;
-    if (k0 + i < n && k0 + j < n) v = A[(int64_t)(k0 + i) * n + k0 + j];
-    s[i * kDiagLD + j] = v;
+  {
+    // row i, column l of the tile: all 64 loads from clamped addresses first, entries outside the matrix masked
+    // afterwards (identity there)
+    double v[DT];
+    const int64_t cl = min(k0 + l, n - 1);
+#pragma unroll
+    for (int i = 0; i < DT; ++i) v[i] = A[(int64_t)min(k0 + i, n - 1) * n + cl];
+#pragma unroll
+    for (int i = 0; i < DT; ++i) s[i * kDiagLD + l] = (k0 + i < n && k0 + l < n) ? v[i] : (i == l) ? 1.0 : 0.0;
   }
   __syncthreads();
   double r[DT];
@@ -3504,7 +3549,7 @@ __global__ __launch_bounds__(256) void k_dchol_panel(int n, int k0, double* A, c
   const int R = k0 + DT * (1 + blockIdx.x);
   dt_load(sa, A, n, R, k0, true, false);   // Aop(i, k) = A_ik[i][k]
   // Bop(k, j) = D_k[j][k]
-  for (int e = threadIdx.x; e < DT * DT; e += 256) sb[e & 63][e >> 6] = Dk[e];
+  dt_load_packed_t(sb, Dk);
   __syncthreads();
   v4d acc[2][2];
   dt_zero(acc);
@@ -3548,13 +3593,18 @@ __global__ __launch_bounds__(256) void k_dinv_row(int n, int kb, const double* _
   __shared__ double sb[DT][DT + 1];
   const int j = blockIdx.x, R = DT * kb, C = DT * j;
   if (j == kb) {
-    for (int e = threadIdx.x; e < DT * DT; e += 256) {
-      const int r = e >> 6, c = e & 63;
-      if (R + r < n && C + c < n) Y[(int64_t)(R + r) * n + C + c] = Dk[e];
+    constexpr int K = DT * DT / 256;
+    double v[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = Dk[threadIdx.x + 256 * q];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const int e = threadIdx.x + 256 * q, r = e >> 6, c = e & 63;
+      if (R + r < n && C + c < n) Y[(int64_t)(R + r) * n + C + c] = v[q];
     }
     return;
   }
-  for (int e = threadIdx.x; e < DT * DT; e += 256) sa[e & 63][e >> 6] = Dk[e];   // Aop(i, k) = D_k[i][k]
+  dt_load_packed_t(sa, Dk);   // Aop(i, k) = D_k[i][k]
   dt_load(sb, Y, n, R, C, false, false);                                         // Bop(k, j) = Y_kj[k][j]
   __syncthreads();
   v4d acc[2][2];
