@@ -3056,7 +3056,9 @@ void launch_diag_inv(int n, int blk, const int* ptr, const int* idx, const doubl
 // One 256-thread workgroup per stored output block.  The host lists, per block, the rows i of K whose sorted
 // columns meet box K' with the column run [s, e).  Eight 32-lane groups take eight entries at a time: group g
 // evaluates phi^K(x_i) and T_i into LDS; then every thread adds sum_g phi_g[q] T_g[q'] to the entries (q, q') it
-// owns.  The summation order is fixed (deterministic).
+// owns.  For T_i the group's 32 lanes take 32 entries of the run at a time: each loads its entry's column, value,
+// owner and coordinates (all 32 chains in flight together) and puts the 1D tables of x_j into LDS; then lane q'
+// adds the products of those entries in the run's order.  The summation order is fixed (deterministic).
 template <int EMAX>
 __global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, const int* __restrict__ brow,
                                                    const int* __restrict__ bptr, const int* __restrict__ gal_ptr,
@@ -3065,6 +3067,9 @@ __global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, co
                                                    const double* __restrict__ val, double* out) {
   __shared__ double spi[8][64];
   __shared__ double sT[8][64];
+  __shared__ double sl[8][32][12];  // per group: the 1D tables l[a][j] (at 4 a + j) of 32 entries' x_j
+  __shared__ double sv[8][32];      // their values A_ij
+  __shared__ int sf[8][32];         // their column is free (owner >= 0)
   const int64_t blkid = blockIdx.x;
   const int K = brow[blkid];
   const int slot = (int)(blkid - bptr[K]);
@@ -3089,17 +3094,56 @@ __global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, co
       double li[3][4];
       for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)i * d + a], li[a]);
       for (int q = lt; q < B; q += 32) spi[g][q] = phi_q<double>(li, d, k, q);
-      for (int q = lt; q < B; q += 32) {
-        double t = 0;
-        for (int p = s; p < e; ++p) {
-          const int j = col[p];
-          if (owner[j] < 0) continue;
-          double lj[3][4];
-          for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)j * d + a], lj[a]);
-          t += val[p] * phi_q<double>(lj, d, k, q);
-        }
-        sT[g][q] = t;
+      // lane lt owns q' = lt and lt + 32 (B <= 64); the digits of q' in base k pick the 1D tables
+      int qd[2][3];
+      double t[2] = {0.0, 0.0};
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int q = lt + 32 * m;
+        qd[m][0] = q % k;
+        qd[m][1] = 4 + (q / k) % k;
+        qd[m][2] = 8 + (q / k / k) % k;
       }
+      for (int p0 = s; p0 < e; p0 += 32) {
+        const int p = min(p0 + lt, e - 1);  // clamped: every lane loads, the lanes past the run store nothing
+        const int j = col[p];
+        const double v = val[p];
+        const int own = owner[j];
+        double lj[3][4] = {};
+        for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)j * d + a], lj[a]);
+        if (p0 + lt < e) {
+          sv[g][lt] = v;
+          sf[g][lt] = own >= 0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) sl[g][lt][4 * a + jj] = lj[a][jj];
+        }
+        // the group is half a wave: its LDS writes and reads stay in program order within the wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int cnt = min(32, e - p0);
+        for (int u = 0; u < cnt; ++u) {
+          if (!sf[g][u]) continue;  // the same for all lanes of the group
+          const double vu = sv[g][u];
+          const double* L = sl[g][u];
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+            if (lt + 32 * m < B) {
+              double ph = L[qd[m][0]];  // phi_q' = l0[q0] l1[q1] (l2[q2]), in phi_q's order
+              ph *= L[qd[m][1]];
+              if (d == 3) ph *= L[qd[m][2]];
+              t[m] += vu * ph;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+        if (lt + 32 * m < B) sT[g][lt + 32 * m] = t[m];
     } else {
       for (int q = lt; q < B; q += 32) {
         spi[g][q] = 0.0;
