@@ -68,7 +68,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (the HBM-counter calibration kernel)")
     ap.add_argument("--fine-kernel", type=int, default=-1,
-                    help="pin the fine-level row-block shape (0..10; -1: chosen by timing at set-up), e.g. for "
+                    help="pin the fine-level row-block shape (0..12; -1: chosen by timing at set-up), e.g. for "
                          "hardware-counter runs that must see one kernel")
     args = ap.parse_args()
     if args.gpus != 1:

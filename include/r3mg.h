@@ -72,12 +72,13 @@ typedef struct {
   int vcycle_fp32;      /* 0 = float64 V-cycle; 1 = float32 V-cycle inside float64 CG [0] */
   int use_graph;        /* 1 = replay PCG iterations from a captured hipGraph [1] */
   int fine_kernel;      /* row-block kernel of the fine level for one right-hand side: -1 = the fastest of
-                           shapes 0..10 timed at r3mg_factor [-1]; 0..10 = that shape.  0..2: CSR row blocks of
+                           shapes 0..12 timed at r3mg_factor [-1]; 0..12 = that shape.  0..2: CSR row blocks of
                            (2048 nonzeros, 64 rows), (4096, 128), (4096, 64); 3..5: the same blocks in a
                            persistent pipelined kernel; 6..8: local-column blocks (each block's distinct columns
                            staged once; 1-byte positions with 2048 nonzeros, 64 rows, 256 columns; 2-byte with
                            (4096, 64, 1024) and (4096, 128, 1024)); 9: shape 6 with vector loads; 10: the
-                           kernel of shape 9 over 1-byte blocks of (3072 nonzeros, 128 rows, 256 columns).  With
+                           kernel of shape 9 over 1-byte blocks of (3072 nonzeros, 128 rows, 256 columns); 11, 12:
+                           the blocks of shapes 9 and 10 taken two per workgroup (more loads in flight).  With
                            the float32 V-cycle, PCG's float64 operator takes the fastest shape in float64, timed
                            separately.  Every shape sums a row in the same order, so results do not depend on this
                            choice when no row has more than 256 nonzeros. */
@@ -113,7 +114,8 @@ typedef struct {
   double bytes_per_apply;  /* algorithmic bytes of one smoother operator application in the V-cycle precision */
   char kernel[48];         /* kernel applying the level for one right-hand side in the V-cycle precision, e.g.
                               "k_level_local<float,u8,3072,128,256,vec>" (position bytes, block capacity, rows
-                              per block, distinct columns, form) or "k_level_boxrow<float,9>" (rows per box);
+                              per block, distinct columns, form: block, vec, or vec2 for two blocks per workgroup) or
+                              "k_level_boxrow<float,9>" (rows per box);
                               "dense" on the coarsest level; "" before r3mg_factor */
 } r3mg_level_info;
 

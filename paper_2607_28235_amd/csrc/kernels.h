@@ -85,12 +85,16 @@ struct FineBlocks {
 //         positions must carry kFinePad padding entries);
 //   10    the kernel of shape 9 over 1-byte local-column blocks of (3072 nonzeros, 128 rows, 256 columns)
 //         (local geometry 3), which keep half again as many loads in flight per workgroup;
-//   11    the kernel of shape 9 over (3072, 64, 256) blocks (local geometry 4): agglomerated levels only.
+//   11    the blocks of shape 9 taken two per workgroup (k_level_local_vec_nb): both blocks' loads in flight
+//         before the first barrier, each block summed as by shape 9;
+//   12    the blocks of shape 10 taken two per workgroup;
+//   13    the kernel of shape 9 over (3072, 64, 256) blocks (local geometry 4): agglomerated levels only.
 // With partials != null (F_PLAIN only; shapes 0..8) the launch writes partial sums of u_i (A u)_i to
 // partials[0..np) and returns np (<= fb.nrb).
 constexpr int kCsrGeoms = 3;
-constexpr int kFineShapes = 11;    // shapes 0..10 serve the fine level
-constexpr int kStreamShapes = 12;  // shape 11: the vector kernel over geometry-4 blocks (agglomerated levels)
+constexpr int kFineShapes = 13;    // shapes 0..12 serve the fine level
+constexpr int kStreamShapes = 14;  // shape 13: the vector kernel over geometry-4 blocks (agglomerated levels)
+constexpr int kAggVecShape = 13;
 constexpr int kLocalFirst = 6;
 constexpr int kStreamCapOf[kCsrGeoms] = {2048, 4096, 4096};
 constexpr int kStreamRowsOf[kCsrGeoms] = {64, 128, 64};
@@ -98,7 +102,7 @@ constexpr int kResidentBlocks = 2048;  // workgroups of 256 threads resident at 
 constexpr int kLocalGeoms = 3;     // local geometries of the block kernels (shapes 6..8)
 constexpr int kLocalGeomsAll = 5;  // geometries 3 and 4 (1-byte positions, 3072 nonzeros, 256 columns) are read by
                                    // the vector kernel only: 128-row blocks on the fine level (shape 10), 64-row
-                                   // blocks on the 2D agglomerated levels, whose rows hold ~70 nonzeros (shape 11)
+                                   // blocks on the 2D agglomerated levels, whose rows hold ~70 nonzeros (shape 13)
 constexpr int kLocalCap[kLocalGeomsAll] = {2048, 4096, 4096, 3072, 3072};
 constexpr int kLocalRows[kLocalGeomsAll] = {64, 64, 128, 128, 64};
 constexpr int kLocalUcap[kLocalGeomsAll] = {256, 1024, 1024, 256, 256};

@@ -843,6 +843,153 @@ __global__ __launch_bounds__(256) void k_level_local_vec(int nrb, const int4* __
   }
 }
 
+// The same over pairs of blocks: a workgroup takes NB = 2 consecutive blocks and issues the loads of both before
+// the first barrier, so that two blocks' streams are in flight per workgroup; each block is summed exactly as by
+// k_level_local_vec.
+template <typename T, int CAP, int RPB, int UCAP, bool KEEP, int NB>
+__global__ __launch_bounds__(256) void k_level_local_vec_nb(int nrb, const int4* __restrict__ meta,
+                                                         const int* __restrict__ ucol,
+                                                         const uint8_t* __restrict__ lidx, const int* __restrict__ ptr,
+                                                         const int* __restrict__ idx, const T* __restrict__ val,
+                                                         const T* __restrict__ u, const T* __restrict__ b, T* rho,
+                                                         T* x, const T* __restrict__ dinv, T* dout, T c1, T c2,
+                                                         int flags, const int* __restrict__ skip) {
+  using V4 = typename Vec4<T>::type;
+  constexpr int TPR = 256 / RPB;
+  constexpr int RPW = 64 / TPR;
+  constexpr int NCH = CAP / 1024;
+  constexpr int UPT = UCAP / 256;
+  static_assert(CAP % 1024 == 0 && UCAP % 256 == 0 && (NB == 1 || NB == 2), "local block shape");
+  if (skip && *skip) return;
+  const int lg = xcd_block((nrb + NB - 1) / NB);
+  if (lg < 0) return;
+  __shared__ T us[NB][UCAP];
+  __shared__ __align__(32) T prod[NB][CAP];
+  __shared__ T shr[NB][4];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rl = threadIdx.x / TPR, sub = threadIdx.x % TPR;
+  // per block: first row, first nonzero and first distinct column of it and of the next (one round trip); a
+  // missing second block (odd nrb) repeats the last one and stores nothing
+  int r0[NB], r1[NB], e0[NB], e1[NB], u0[NB], nu[NB];
+  bool live[NB];
+#pragma unroll
+  for (int h = 0; h < NB; ++h) {
+    live[h] = lg * NB + h < nrb;
+    const int lb = min(lg * NB + h, nrb - 1);
+    const int4 m0 = meta[lb], m1 = meta[lb + 1];
+    r0[h] = m0.x;
+    r1[h] = m1.x;
+    e0[h] = m0.y;
+    e1[h] = m1.y;
+    u0[h] = m0.z;
+    nu[h] = m1.z - m0.z;
+  }
+  // The loads below are unconditional per thread (clamped addresses; out-of-range values are never used): loads
+  // under lane-dependent branches are waited for at the branch's end, which put the block's value stream behind
+  // its column list.  Here the column list, values, positions and row pointers are in flight together, and only
+  // the gather of u waits for the column list.
+  T p_old[NB], p_x[NB], p_u[NB], p_di[NB];
+#pragma unroll
+  for (int h = 0; h < NB; ++h) {
+    const int prc = min(r0[h] + rl, r1[h] - 1);  // blocks hold at least one row
+    p_old[h] = p_x[h] = p_u[h] = p_di[h] = 0;
+    if (!(flags & F_PLAIN)) {
+      p_old[h] = (flags & F_RHO_FROM_B) ? b[prc] : rho[prc];
+      p_u[h] = u[prc];
+      if (flags & F_X_ADD) p_x[h] = x[prc];
+      if (flags & F_D_OUT) p_di[h] = dinv[prc];
+    }
+  }
+  int uc[NB][UPT];
+  uint32_t li[NB][NCH];
+  V4 vv[NB][NCH];
+  int rp[NB];
+#pragma unroll
+  for (int h = 0; h < NB; ++h) {
+    if (nu[h] > UCAP) continue;  // one long row, summed below (uniform over the workgroup)
+#pragma unroll
+    for (int m = 0; m < UPT; ++m) uc[h][m] = ucol[u0[h] + min((int)threadIdx.x + m * 256, nu[h] - 1)];  // nu >= 1
+    const int a0 = e0[h] & ~3;
+#pragma unroll
+    for (int m = 0; m < NCH; ++m) {
+      const int e = a0 + 4 * (threadIdx.x + m * 256);
+      const int ec = e < e1[h] ? e : a0;
+      li[h][m] = ld_matrix<KEEP>(reinterpret_cast<const uint32_t*>(lidx + ec));
+      vv[h][m] = ld_matrix<KEEP>(reinterpret_cast<const V4*>(val + ec));
+    }
+    rp[h] = ptr[min(r0[h] + wv * RPW + min(lane, RPW), r1[h])];  // lanes 0..RPW: this wave's row pointers
+  }
+  // slots nu .. UCAP-1 take copies and are never read (positions are below nu); no branch lets the gather sink
+#pragma unroll
+  for (int h = 0; h < NB; ++h) {
+    if (nu[h] > UCAP) continue;
+#pragma unroll
+    for (int m = 0; m < UPT; ++m) us[h][threadIdx.x + m * 256] = u[uc[h][m]];
+  }
+  // keep the streamed entries ahead of the barrier (the compiler would otherwise sink some loads past it)
+#pragma unroll
+  for (int h = 0; h < NB; ++h) {
+    if (nu[h] > UCAP) continue;
+#pragma unroll
+    for (int m = 0; m < NCH; ++m) {
+      asm volatile("" ::"v"(li[h][m]));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) asm volatile("" ::"v"(vv[h][m][q]));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < NB; ++h) {
+    if (nu[h] > UCAP) continue;
+    const int a0 = e0[h] & ~3;
+#pragma unroll
+    for (int m = 0; m < NCH; ++m) {
+      const int e = a0 + 4 * (threadIdx.x + m * 256);
+      if (e < e1[h]) {
+        V4 g;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          g[q] = (e + q >= e0[h] && e + q < e1[h]) ? us[h][(li[h][m] >> (8 * q)) & 0xff] : (T)0;
+        *reinterpret_cast<V4*>(&prod[h][e - a0]) = vv[h][m] * g;
+      }
+    }
+  }
+  __syncthreads();
+  T t[NB];
+#pragma unroll
+  for (int h = 0; h < NB; ++h) {
+    if (nu[h] <= UCAP) {
+      const int a0 = e0[h] & ~3;
+      const int rs = __shfl(rp[h], lane / TPR, 64), re = __shfl(rp[h], lane / TPR + 1, 64);
+      t[h] = row_sum_canonical<T, TPR>(prod[h], rs - a0, re - a0, sub);
+    } else {  // one long row
+      T acc = 0;
+      for (int e = e0[h] + threadIdx.x; e < e1[h]; e += 256) acc += val[e] * u[idx[e]];
+      acc = wave_sum(acc, 64);
+      if (lane == 0) shr[h][wv] = acc;
+      __syncthreads();
+      t[h] = (shr[h][0] + shr[h][1]) + (shr[h][2] + shr[h][3]);
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < NB; ++h) {
+    const bool staged = nu[h] <= UCAP;
+    const int row = r0[h] + rl;
+    if (!live[h] || sub != 0 || row >= r1[h] || !(staged || rl == 0)) continue;
+    if (flags & F_PLAIN) {
+      rho[row] = t[h];
+    } else {
+      const T r = p_old[h] - t[h];
+      if (flags & F_RHO_STORE) rho[row] = r;
+      if (flags & F_X_ASSIGN)
+        x[row] = p_u[h];
+      else if (flags & F_X_ADD)
+        x[row] = p_x[h] + p_u[h];
+      if (flags & F_D_OUT) dout[row] = c1 * p_u[h] + c2 * p_di[h] * r;
+    }
+  }
+}
+
 template <typename T, int CAP, int RPB>
 static int launch_stream_block(const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
                                T* dout, double c1, double c2, int flags, const int* skip, double* partials,
@@ -907,21 +1054,32 @@ static int launch_stream_local(const FineBlocks& fb, const LevelOp<T>& op, const
   return nrb;
 }
 
-template <typename T, int CAP, int RPB, int UCAP>
+template <typename T, int CAP, int RPB, int UCAP, int NB>
 static int launch_stream_local_vec(const FineBlocks& fb, const LevelOp<T>& op, const T* u, const T* b, T* rho, T* x,
                                    T* dout, double c1, double c2, int flags, const int* skip, double* partials,
                                    hipStream_t s) {
   if (partials) throw std::runtime_error("local-column vector kernel: no partial sums");
   const int nrb = fb.nrb;
   if (!fb.meta) throw std::runtime_error("local-column vector kernel: block records missing");
-  if (flags & F_KEEP)
-    hipLaunchKernelGGL((k_level_local_vec<T, CAP, RPB, UCAP, true>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb,
-                       reinterpret_cast<const int4*>(fb.meta), fb.ucol, static_cast<const uint8_t*>(fb.lidx), op.ptr,
-                       op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip);
-  else
-    hipLaunchKernelGGL((k_level_local_vec<T, CAP, RPB, UCAP, false>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb,
-                       reinterpret_cast<const int4*>(fb.meta), fb.ucol, static_cast<const uint8_t*>(fb.lidx), op.ptr,
-                       op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip);
+  const int4* meta = reinterpret_cast<const int4*>(fb.meta);
+  const uint8_t* lidx = static_cast<const uint8_t*>(fb.lidx);
+  if constexpr (NB == 1) {
+    if (flags & F_KEEP)
+      hipLaunchKernelGGL((k_level_local_vec<T, CAP, RPB, UCAP, true>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb, meta,
+                         fb.ucol, lidx, op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip);
+    else
+      hipLaunchKernelGGL((k_level_local_vec<T, CAP, RPB, UCAP, false>), dim3(xcd_grid(nrb)), dim3(256), 0, s, nrb,
+                         meta, fb.ucol, lidx, op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags,
+                         skip);
+  } else {
+    const dim3 grid(xcd_grid((nrb + NB - 1) / NB));
+    if (flags & F_KEEP)
+      hipLaunchKernelGGL((k_level_local_vec_nb<T, CAP, RPB, UCAP, true, NB>), grid, dim3(256), 0, s, nrb, meta, fb.ucol,
+                         lidx, op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip);
+    else
+      hipLaunchKernelGGL((k_level_local_vec_nb<T, CAP, RPB, UCAP, false, NB>), grid, dim3(256), 0, s, nrb, meta,
+                         fb.ucol, lidx, op.ptr, op.idx, op.val, u, b, rho, x, op.dinv, dout, (T)c1, (T)c2, flags, skip);
+  }
   return nrb;
 }
 
@@ -941,9 +1099,11 @@ int launch_level_stream(int shape, const FineBlocks& fb, const LevelOp<T>& op, c
     case 6: np = launch_stream_local<T, uint8_t, 2048, 64, 256>(R3MG_ARGS); break;
     case 7: np = launch_stream_local<T, uint16_t, 4096, 64, 1024>(R3MG_ARGS); break;
     case 8: np = launch_stream_local<T, uint16_t, 4096, 128, 1024>(R3MG_ARGS); break;
-    case 9: np = launch_stream_local_vec<T, 2048, 64, 256>(R3MG_ARGS); break;
-    case 10: np = launch_stream_local_vec<T, 3072, 128, 256>(R3MG_ARGS); break;
-    case 11: np = launch_stream_local_vec<T, 3072, 64, 256>(R3MG_ARGS); break;
+    case 9: np = launch_stream_local_vec<T, 2048, 64, 256, 1>(R3MG_ARGS); break;
+    case 10: np = launch_stream_local_vec<T, 3072, 128, 256, 1>(R3MG_ARGS); break;
+    case 11: np = launch_stream_local_vec<T, 2048, 64, 256, 2>(R3MG_ARGS); break;
+    case 12: np = launch_stream_local_vec<T, 3072, 128, 256, 2>(R3MG_ARGS); break;
+    case 13: np = launch_stream_local_vec<T, 3072, 64, 256, 1>(R3MG_ARGS); break;
     default: throw std::runtime_error("unknown row-block shape");
   }
 #undef R3MG_ARGS

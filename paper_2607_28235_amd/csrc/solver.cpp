@@ -239,11 +239,15 @@ std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int 
   switch (level_kernel(an, D, l, 1, esz)) {
     case LevelKernel::Stream:
       if (D.shape >= kLocalFirst) {
-        const bool vec = D.shape >= kLocalFirst + kLocalGeoms;  // shapes 9, 10, 11: geometries 0, 3, 4
-        const int g = !vec ? D.shape - kLocalFirst : D.shape == kLocalFirst + kLocalGeoms ? 0 : D.shape - 7;
+        // shapes 9..13 (vector kernel): geometries 0, 3, 0, 3, 4; shapes 11 and 12 ("vec2") take two blocks per
+        // workgroup
+        const bool vec = D.shape >= kLocalFirst + kLocalGeoms;
+        static const int vec_geom[5] = {0, 3, 0, 3, 4};
+        const int g = !vec ? D.shape - kLocalFirst : vec_geom[D.shape - kLocalFirst - kLocalGeoms];
+        const bool two = D.shape == 11 || D.shape == 12;
         return std::string("k_level_local<") + t + ",u" + std::to_string(8 * kLocalIdxBytes[g]) + "," +
                std::to_string(kLocalCap[g]) + "," + std::to_string(kLocalRows[g]) + "," +
-               std::to_string(kLocalUcap[g]) + (vec ? ",vec>" : ",block>");
+               std::to_string(kLocalUcap[g]) + (!vec ? ",block>" : two ? ",vec2>" : ",vec>");
       }
       return std::string("k_level_stream<") + t + "," + std::to_string(kStreamCapOf[D.shape % kCsrGeoms]) + "," +
              std::to_string(kStreamRowsOf[D.shape % kCsrGeoms]) + (D.shape >= kCsrGeoms ? ",pipe16>" : ",block>");
@@ -1136,6 +1140,11 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     D.shape_bytes[kLocalFirst + kLocalGeoms] = D.shape_bytes[kLocalFirst];
     upload_local(D, 3, an.loc[3], an.rowptr, s, kLocalFirst + kLocalGeoms + 1);
     D.shape_bytes[kLocalFirst + kLocalGeoms + 1] = local_bytes(an.nnz, an.n, 3, an.loc[3], sv0);
+    // shapes 11 and 12: the blocks of shapes 9 and 10, two per workgroup
+    for (int sh : {11, 12}) {
+      D.fb[sh] = D.fb[sh - 2];
+      D.shape_bytes[sh] = D.shape_bytes[sh - 2];
+    }
     D.dinv64.alloc(D.n);
     if (fp32) {
       D.xi32.alloc(D.xi64.n);
@@ -1185,8 +1194,8 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     D.keep64 = keep_rule(an.opt, (double)D.nnz * (8 + ib));
     if (!D.boxrow && !H.rowptr.empty()) {  // narrow block rows: the level is held as 1-byte local-column blocks
       D.rowptr.upload(H.rowptr, s);
-      // the vector kernel: shape 9 over 2048-nonzero blocks, shape 11 over (3072, 64-row) blocks
-      D.shape = H.loc_geom == 4 ? kLocalFirst + kLocalGeoms + 2 : kLocalFirst + kLocalGeoms;
+      // the vector kernel: shape 9 over 2048-nonzero blocks, shape 13 over (3072, 64-row) blocks
+      D.shape = H.loc_geom == 4 ? kAggVecShape : kLocalFirst + kLocalGeoms;
       upload_local(D, H.loc_geom, H.loc, H.rowptr, s, D.shape);
       D.shape_bytes[D.shape] = local_bytes(D.nnz, D.n, H.loc_geom, H.loc, sv);
       D.bytes_apply = D.shape_bytes[D.shape];

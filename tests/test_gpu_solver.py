@@ -425,7 +425,7 @@ def test_full_size_2d_q3_pcg(full2d, fp32):
         assert err < 2e-5, err
 
 
-@pytest.mark.parametrize("shape", list(range(11)))
+@pytest.mark.parametrize("shape", list(range(13)))
 def test_fine_kernel_shapes_full_size(full2d, shape):
     """Every row-block kernel shape of the fine level (CSR blocks, one workgroup each; the same blocks in the
     persistent pipelined kernel, several blocks per workgroup at this size; local-column blocks with 1- and 2-byte
@@ -491,7 +491,7 @@ def dense_row():
     return prob, A2, b, ho
 
 
-@pytest.mark.parametrize("shape", list(range(11)))
+@pytest.mark.parametrize("shape", list(range(13)))
 def test_fine_kernel_long_row(dense_row, shape):
     prob, A2, b, ho = dense_row
     _case(f"dense-row fine kernel shape {shape}")
@@ -515,6 +515,44 @@ def test_fine_kernel_long_row(dense_row, shape):
     assert ok and abs(int(iters[0]) - ko) <= 1, (iters, ko)
     assert _rel(x.cpu().numpy(), xo) < 1e-9
     h.close()
+
+
+@pytest.mark.parametrize("case", ["small2d", "small3d", "full2d", "dense_row"])
+def test_two_block_shapes_bitwise(case, request):
+    """Shapes 11 and 12 take the blocks of shapes 9 and 10 two per workgroup and sum each block as alone: the
+    operator, the float64 and float32 V-cycles and PCG give bitwise the same results (the dense-row case has a
+    block with one long row; the cases differ in the parity of the block count)."""
+    P = _P()
+    if case == "dense_row":
+        prob, A2, b, _ = request.getfixturevalue("dense_row")
+        coords, rp, cl, vl = prob.coords, A2.indptr.astype(np.int64), A2.indices.astype(np.int32), A2.data
+        base = P.Options(dim=2, coarse_degree=2, leaf_size=128, max_levels=4, max_coarse_dofs=100)
+    else:
+        c = request.getfixturevalue(case)
+        coords, rp, cl, vl, b, base = c.prob.coords, c.prob.row_ptr, c.prob.col, c.prob.val, c.b, c.opts
+    import dataclasses
+    n = len(rp) - 1
+    r = np.random.default_rng(14).standard_normal(n)
+    for one, two in ((9, 11), (10, 12)):
+        out = []
+        for sh in (one, two):
+            _case(f"{case} fine kernel shape {sh}")
+            row = []
+            for fp32 in (0, 1):
+                h = P.Hierarchy(coords, rp, cl, vl, dataclasses.replace(base, fine_kernel=sh, vcycle_fp32=fp32))
+                y = torch.zeros(n, dtype=torch.float64, device="cuda")
+                h.level_apply(0, _t(r), y)
+                z = torch.zeros(n, dtype=torch.float64, device="cuda")
+                h.vcycle(_t(r), z)
+                x = torch.zeros(n, dtype=torch.float64, device="cuda")
+                iters, _, ok = h.pcg(_t(b), x, rtol=1e-10, maxit=300)
+                torch.cuda.synchronize()
+                assert ok
+                row += [y.cpu().numpy(), z.cpu().numpy(), x.cpu().numpy(), np.asarray(iters)]
+                h.close()
+            out.append(row)
+        for a, bb in zip(*out):
+            assert np.array_equal(a, bb), (case, one, two)
 
 
 @pytest.mark.parametrize("nrhs", [1, 4])

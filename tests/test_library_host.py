@@ -146,14 +146,14 @@ def test_invalid_arguments():
     with pytest.raises(P.R3mgError) as e:
         P.Hierarchy(p.coords, p.row_ptr, p.col, p.val, P.Options(dim=2, max_levels=1), factor=False)
     assert e.value.code == "INVALID"
-    # fine-level shapes are 0..10 (-1: timed); multi-RHS kernels 0..4 (-1: timed); matrix load modes -1..1;
+    # fine-level shapes are 0..12 (-1: timed); multi-RHS kernels 0..4 (-1: timed); matrix load modes -1..1;
     # tuning cache 0..1
-    for kw in ({"fine_kernel": 11}, {"fine_kernel": -2}, {"multi_rhs_kernel": 5}, {"matrix_cache": 2},
+    for kw in ({"fine_kernel": 13}, {"fine_kernel": -2}, {"multi_rhs_kernel": 5}, {"matrix_cache": 2},
                {"tune_cache": 2}, {"tune_cache": -1}):
         with pytest.raises(P.R3mgError) as e:
             P.Hierarchy(p.coords, p.row_ptr, p.col, p.val, P.Options(dim=2, **kw), factor=False)
         assert e.value.code == "INVALID", kw
-    P.Hierarchy(p.coords, p.row_ptr, p.col, p.val, P.Options(dim=2, fine_kernel=10), factor=False).close()
+    P.Hierarchy(p.coords, p.row_ptr, p.col, p.val, P.Options(dim=2, fine_kernel=12), factor=False).close()
     cl = p.col.copy()
     cl[[0, 1]] = cl[[1, 0]] if p.row_ptr[1] > 1 else cl[[0, 1]]
     rp = p.row_ptr.copy()
