@@ -3644,15 +3644,16 @@ __device__ inline double dt_dot8(const double* x, int sx, const double* y, int s
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
-// 1. Diagonal tile k0, by one wave.  Cholesky by columns (left-looking): lane l keeps row l of the tile in
-// registers, and the rows of L go to LDS as they become final (zero elsewhere), so that step j reads row j of L as
-// 16-byte broadcasts and each lane forms its dot product with its own registers; segments of eight entries that
-// are still zero are not read.  Then the inverse D = L^{-1} by rows of D: lane l keeps column l of D in registers
-// (zero above the diagonal), so that row i of D needs row i of L only.  L goes back to A (zero above the
-// diagonal), D to Dk (64 x 64, zero above the diagonal).  The steps are generated by template recursion, so every
-// register index is a constant; the pivots' square roots are broadcast with a lane shuffle, and one barrier per
-// column orders the LDS rows.  (Forming row J of D in the same step as column J of L, for two independent chains,
-// needed 387 registers and ran slower.)
+// 1. Diagonal tile k0, by two waves.  Wave 0: Cholesky by columns (left-looking): lane l keeps row l of the tile
+// in registers, and the rows of L go to LDS as they become final (zero elsewhere), so that step j reads row j of L
+// as 16-byte broadcasts and each lane forms its dot product with its own registers; segments of eight entries that
+// are still zero are not read.  Wave 1: the inverse D = L^{-1} by rows of D: lane l keeps column l of D in
+// registers (zero above the diagonal), so that row i of D needs row i of L only, which is final once column i is;
+// so wave 1 forms row j - 1 of D while wave 0 forms column j of L.  L goes back to A (zero above the diagonal), D
+// to Dk (64 x 64, zero above the diagonal).  The steps are generated by template recursion, so every register
+// index is a constant; the pivots' square roots are broadcast with a lane shuffle, and one barrier per step orders
+// the LDS rows.  (Forming row J of D in the same step as column J of L in one wave needed 387 registers and ran
+// slower.)
 constexpr int kDiagLD = DT + 2;  // LDS row stride: 16-byte aligned rows, 4-way conflicts at most for row-per-lane reads
 
 // sum over m < 8 ceil(J / 8) of x[m] w[m] (w: an LDS row whose entries from J on are zero), in two interleaved
@@ -3676,71 +3677,85 @@ __device__ __forceinline__ double diag_dot(const double (&x)[DT], const double* 
   return a0 + a1;
 }
 
+// column J of L (left-looking): lane l >= J finishes L[l][J] and puts it in LDS
 template <int J>
-struct DiagChol {
-  static __device__ __forceinline__ void run(double (&r)[DT], double* s, int l, int* bad) {
-    if constexpr (J < DT) {
-      const double acc = diag_dot<J, true>(r, s + J * kDiagLD);  // sum over m < J of L[l][m] L[J][m]
-      double piv = r[J] - acc;  // left-looking: r[J] still holds the tile's entry
-      if (l == J && !(piv > 0.0)) {
-        *bad = 1;
-        piv = 1.0;
-      }
-      const double ljj = __shfl(sqrt(piv), J, 64);
-      if (l >= J) {
-        const double v = (l == J) ? ljj : (r[J] - acc) / ljj;
-        s[l * kDiagLD + J] = v;
-        r[J] = v;
-      }
-      __syncthreads();
-      DiagChol<J + 1>::run(r, s, l, bad);
-    }
+__device__ __forceinline__ void diag_chol_col(double (&r)[DT], double* s, int l, int* bad) {
+  const double acc = diag_dot<J, true>(r, s + J * kDiagLD);  // sum over m < J of L[l][m] L[J][m]
+  double piv = r[J] - acc;  // left-looking: r[J] still holds the tile's entry
+  if (l == J && !(piv > 0.0)) {
+    *bad = 1;
+    piv = 1.0;
   }
-};
+  const double ljj = __shfl(sqrt(piv), J, 64);
+  if (l >= J) {
+    const double v = (l == J) ? ljj : (r[J] - acc) / ljj;
+    s[l * kDiagLD + J] = v;
+    r[J] = v;
+  }
+}
 
+// row I of D = L^{-1} (column l of D in lane l): d[I][l] = -(sum over l <= m < I of L[I][m] d[m][l]) / L[I][I]
+// (I > l), 1 / L[I][I] (I = l), 0 (I < l); d[m][l] = 0 for m < l, so the sum may run over m < I.  It needs row I
+// of L only.
 template <int I>
-struct DiagInv {
-  // d[i][l] = -(sum over l <= m < i of L[i][m] d[m][l]) / L[i][i] (i > l), 1 / L[i][i] (i = l), 0 (i < l);
-  // d[m][l] = 0 for m < l, so the sum may run over m < i
-  static __device__ __forceinline__ void run(double (&d)[DT], const double* s, int l) {
-    if constexpr (I < DT) {
-      const double* ri = s + I * kDiagLD;
-      const double acc = diag_dot<I, false>(d, ri);
-      const double lii = ri[I];
-      d[I] = (I < l) ? 0.0 : (I == l) ? 1.0 / lii : -acc / lii;
-      DiagInv<I + 1>::run(d, s, l);
+__device__ __forceinline__ void diag_inv_row(double (&d)[DT], const double* s, int l) {
+  const double* ri = s + I * kDiagLD;
+  const double acc = diag_dot<I, false>(d, ri);
+  const double lii = ri[I];
+  d[I] = (I < l) ? 0.0 : (I == l) ? 1.0 / lii : -acc / lii;
+}
+
+// Step J of the two waves: wave 0 forms column J of L, wave 1 row J - 1 of D (row J - 1 of L is final after
+// column J - 1); one barrier per step orders the LDS rows.
+template <int J>
+struct DiagSteps {
+  static __device__ __forceinline__ void run(double (&r)[DT], double (&d)[DT], double* s, int l, bool w0, int* bad) {
+    if constexpr (J <= DT) {
+      if (w0) {
+        if constexpr (J < DT) diag_chol_col<J>(r, s, l, bad);
+      } else {
+        if constexpr (J > 0) diag_inv_row<J - 1>(d, s, l);
+      }
+      if constexpr (J < DT) __syncthreads();
+      DiagSteps<J + 1>::run(r, d, s, l, w0, bad);
     }
   }
 };
 
-__global__ __launch_bounds__(64) void k_dchol_diag(int n, int k0, double* A, double* Dk, int* bad) {
+__global__ __launch_bounds__(128) void k_dchol_diag(int n, int k0, double* A, double* Dk, int* bad) {
   __shared__ __align__(16) double s[DT * kDiagLD];
-  const int l = threadIdx.x;
+  const int l = threadIdx.x & 63;
+  const bool w0 = threadIdx.x < 64;
   {
-    // row i, column l of the tile: all 64 loads from clamped addresses first, entries outside the matrix masked
-    // afterwards (identity there)
-    double v[DT];
+    // rows 2 q + w, column l of the tile: all 32 loads of a lane from clamped addresses first, entries outside
+    // the matrix masked afterwards (identity there)
+    const int w = threadIdx.x >> 6;
+    double v[DT / 2];
     const int64_t cl = min(k0 + l, n - 1);
 #pragma unroll
-    for (int i = 0; i < DT; ++i) v[i] = A[(int64_t)min(k0 + i, n - 1) * n + cl];
+    for (int q = 0; q < DT / 2; ++q) v[q] = A[(int64_t)min(k0 + 2 * q + w, n - 1) * n + cl];
 #pragma unroll
-    for (int i = 0; i < DT; ++i) s[i * kDiagLD + l] = (k0 + i < n && k0 + l < n) ? v[i] : (i == l) ? 1.0 : 0.0;
+    for (int q = 0; q < DT / 2; ++q) {
+      const int i = 2 * q + w;
+      s[i * kDiagLD + l] = (k0 + i < n && k0 + l < n) ? v[q] : (i == l) ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
   double r[DT];
 #pragma unroll
   for (int m = 0; m < DT; ++m) r[m] = s[l * kDiagLD + m];
   __syncthreads();
-  for (int e = l; e < DT * kDiagLD; e += 64) s[e] = 0.0;
+  for (int e = threadIdx.x; e < DT * kDiagLD; e += 128) s[e] = 0.0;
   __syncthreads();
-  DiagChol<0>::run(r, s, l, bad);
   double d[DT];
 #pragma unroll
   for (int m = 0; m < DT; ++m) d[m] = 0.0;
-  DiagInv<0>::run(d, s, l);
+  DiagSteps<0>::run(r, d, s, l, w0, bad);
+  if (!w0) {
 #pragma unroll
-  for (int i = 0; i < DT; ++i) Dk[i * DT + l] = d[i];
-  for (int e = l; e < DT * DT; e += 64) {
+    for (int i = 0; i < DT; ++i) Dk[i * DT + l] = d[i];
+  }
+  for (int e = threadIdx.x; e < DT * DT; e += 128) {
     const int i = e >> 6, j = e & 63;
     if (k0 + i < n && k0 + j < n) A[(int64_t)(k0 + i) * n + k0 + j] = s[i * kDiagLD + j];
   }
@@ -3895,7 +3910,7 @@ void dense_cholesky_inverse(int n, double* A, double* Inv, double* ws, double* Y
   for (int kb = 0; kb < nt; ++kb) {
     const int k0 = kb * DT;
     double* Dk = ws + (size_t)kb * DT * DT;
-    hipLaunchKernelGGL(k_dchol_diag, dim3(1), dim3(64), 0, s, n, k0, A, Dk, bad);
+    hipLaunchKernelGGL(k_dchol_diag, dim3(1), dim3(128), 0, s, n, k0, A, Dk, bad);
     const int below = nt - kb - 1;
     if (below > 0) {
       hipLaunchKernelGGL(k_dchol_panel, dim3(below), dim3(256), 0, s, n, k0, A, Dk);
