@@ -2075,29 +2075,49 @@ void time_smoother_kernel(HandleImpl& h, int level, int nrhs, int reps, int64_t 
   R3MG_HIP_CHECK(hipEventCreate(&e0));
   R3MG_HIP_CHECK(hipEventCreate(&e1));
   const int fl = F_RHO_STORE | F_X_ADD | F_D_OUT;
-  auto launch = [&](int r) {
+  auto launch_on = [&](int r, hipStream_t st) {
     if (c.fp32) {
       float* u = vbuf<float>((r & 1) ? D.dB : D.dA);
       float* w = vbuf<float>((r & 1) ? D.dA : D.dB);
       apply_level<float>(c, level, nrhs, u, vbuf<float>(D.b), vbuf<float>(D.rho), vbuf<float>(D.x), w, 0.0, 0.0, fl,
-                         nullptr, s);
+                         nullptr, st);
     } else {
       double* u = vbuf<double>((r & 1) ? D.dB : D.dA);
       double* w = vbuf<double>((r & 1) ? D.dA : D.dB);
       apply_level<double>(c, level, nrhs, u, vbuf<double>(D.b), vbuf<double>(D.rho), vbuf<double>(D.x), w, 0.0, 0.0,
-                          fl, nullptr, s);
+                          fl, nullptr, st);
     }
   };
+  auto launch = [&](int r) { launch_on(r, s); };
   float t = 0;
   try {
     for (int r = 0; r < 3; ++r) launch(r);
     if (flush_bytes <= 0) {
-      // back to back, as a smoothing sweep runs them
-      R3MG_HIP_CHECK(hipEventRecord(e0, s));
-      for (int r = 0; r < reps; ++r) launch(r);
-      R3MG_HIP_CHECK(hipEventRecord(e1, s));
-      R3MG_HIP_CHECK(hipEventSynchronize(e1));
-      R3MG_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+      // back to back from a captured graph, as a smoothing sweep runs inside the V-cycle's graph (eager launches
+      // would time the host's launch rate on the small levels); the graph is replayed once untimed
+      if (!dv.cap_stream) R3MG_HIP_CHECK(hipStreamCreateWithFlags(&dv.cap_stream, hipStreamNonBlocking));
+      R3MG_HIP_CHECK(hipStreamSynchronize(s));
+      hipGraph_t g = nullptr;
+      hipGraphExec_t ex = nullptr;
+      R3MG_HIP_CHECK(hipStreamBeginCapture(dv.cap_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int r = 0; r < reps; ++r) launch_on(r, dv.cap_stream);
+      } catch (...) {
+        (void)hipStreamEndCapture(dv.cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      R3MG_HIP_CHECK(hipStreamEndCapture(dv.cap_stream, &g));
+      hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (err == hipSuccess) err = hipGraphLaunch(ex, s);
+      if (err == hipSuccess) err = hipEventRecord(e0, s);
+      if (err == hipSuccess) err = hipGraphLaunch(ex, s);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+      if (ex) (void)hipGraphExecDestroy(ex);
+      (void)hipGraphDestroy(g);
+      R3MG_HIP_CHECK(err);
     } else {
       // each launch alone, after a pass that reads and writes flush_bytes of other memory (more than the caches
       // hold), so that the matrix and vectors come from HBM
