@@ -4361,7 +4361,8 @@ __global__ __launch_bounds__(256) void k_pcg_z1(int n, PcgState* st, int check, 
   __shared__ double sh[4];
   __shared__ double rr[1];
   if (st->all_done) return;
-  if (check) column_totals<1>(partials + g, g, 1, sh, rr);
+  // only block 0 records the stop test; the vector work below does not depend on it
+  if (check && blockIdx.x == 0) column_totals<1>(partials + g, g, 1, sh, rr);
   if (check && blockIdx.x == 0 && threadIdx.x == 0 && !st->done[0]) {
     st->rr_prev[0] = st->rr[0];
     st->rr[0] = rr[0];
