@@ -94,6 +94,7 @@ struct FineBlocks {
 constexpr int kCsrGeoms = 3;
 constexpr int kFineShapes = 13;    // shapes 0..12 serve the fine level
 constexpr int kStreamShapes = 14;  // shape 13: the vector kernel over geometry-4 blocks (agglomerated levels)
+constexpr int kVecTwoFirst = 11;  // shapes 11, 12: the blocks of shapes 9, 10 taken two per workgroup
 constexpr int kAggVecShape = 13;
 constexpr int kLocalFirst = 6;
 constexpr int kStreamCapOf[kCsrGeoms] = {2048, 4096, 4096};

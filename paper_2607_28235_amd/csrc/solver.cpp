@@ -244,7 +244,7 @@ std::string level_kernel_name(const Analysis& an, const DevLevel& D, int l, int 
         const bool vec = D.shape >= kLocalFirst + kLocalGeoms;
         static const int vec_geom[5] = {0, 3, 0, 3, 4};
         const int g = !vec ? D.shape - kLocalFirst : vec_geom[D.shape - kLocalFirst - kLocalGeoms];
-        const bool two = D.shape == 11 || D.shape == 12;
+        const bool two = D.shape == kVecTwoFirst || D.shape == kVecTwoFirst + 1;
         return std::string("k_level_local<") + t + ",u" + std::to_string(8 * kLocalIdxBytes[g]) + "," +
                std::to_string(kLocalCap[g]) + "," + std::to_string(kLocalRows[g]) + "," +
                std::to_string(kLocalUcap[g]) + (!vec ? ",block>" : two ? ",vec2>" : ",vec>");
@@ -1141,7 +1141,7 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     upload_local(D, 3, an.loc[3], an.rowptr, s, kLocalFirst + kLocalGeoms + 1);
     D.shape_bytes[kLocalFirst + kLocalGeoms + 1] = local_bytes(an.nnz, an.n, 3, an.loc[3], sv0);
     // shapes 11 and 12: the blocks of shapes 9 and 10, two per workgroup
-    for (int sh : {11, 12}) {
+    for (int sh : {kVecTwoFirst, kVecTwoFirst + 1}) {
       D.fb[sh] = D.fb[sh - 2];
       D.shape_bytes[sh] = D.shape_bytes[sh - 2];
     }
