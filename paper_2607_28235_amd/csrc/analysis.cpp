@@ -492,6 +492,25 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
         ++w;
       }
     }
+    // A1 is symmetric (Galerkin product of a symmetric A): only the blocks on and above the block diagonal are
+    // formed, and the transpose of each off-diagonal one fills its mirror (K', K)
+    an->gal_up.clear();
+    an->gal_mir.clear();
+    for (int64_t k = 0; k < H.nbox; ++k)
+      for (int64_t b = H.bptr[k]; b < H.bptr[k + 1]; ++b) {
+        const int32_t kp = H.bcol[b];
+        if (kp < k) continue;
+        int32_t m = -1;
+        if (kp != k) {
+          const int32_t* bc = H.bcol.data() + H.bptr[kp];
+          const int32_t* be = H.bcol.data() + H.bptr[kp + 1];
+          const int32_t* f = std::lower_bound(bc, be, (int32_t)k);
+          if (f == be || *f != k) throw err(R3MG_ERR_INVALID, "coarse block pattern is not symmetric");
+          m = (int32_t)(H.bptr[kp] + (f - bc));
+        }
+        an->gal_up.push_back((int32_t)b);
+        an->gal_mir.push_back(m);
+      }
   }
   for (int l = 2; l <= L; ++l) {
     HostLevel& P = an->lv[l - 1];

@@ -210,9 +210,10 @@ void launch_gather_vals(int64_t nnz, const int64_t* src, const double* user_vals
 // set-up kernels
 void launch_diag_inv(int n, int blk, const int* ptr, const int* idx, const double* val, double* dinv, double* diag,
                      int* bad, hipStream_t s);
-void launch_galerkin0(int64_t nblocks, int d, int pc, const int* brow, const int* bptr, const int* gal_ptr,
-                      const int* gal_ent, const int* owner, const double* xi, const int* col, const double* val,
-                      double* out, hipStream_t s);
+// nup blocks formed: up[t] (K <= K'), whose transpose also fills block mir[t] (-1 on the diagonal)
+void launch_galerkin0(int64_t nup, int d, int pc, const int* up, const int* mir, const int* brow, const int* bptr,
+                      const int* gal_ptr, const int* gal_ent, const int* owner, const double* xi, const int* col,
+                      const double* val, double* out, hipStream_t s);
 void launch_galerkin_c(int64_t nblocks, int d, int pc, int shift, int nbox_in, const int* brow, const int* bptr_out,
                        const int* bcol_out, const int* bptr_in, const int* bcol_in, const double* val_in,
                        const double* pt, double* out, hipStream_t s);

@@ -3218,9 +3218,12 @@ void launch_diag_inv(int n, int blk, const int* ptr, const int* idx, const doubl
 // evaluates phi^K(x_i) and T_i into LDS; then every thread adds sum_g phi_g[q] T_g[q'] to the entries (q, q') it
 // owns.  For T_i the group's 32 lanes take 32 entries of the run at a time: each loads its entry's column, value,
 // owner and coordinates (all 32 chains in flight together) and puts the 1D tables of x_j into LDS; then lane q'
-// adds the products of those entries in the run's order.  The summation order is fixed (deterministic).
+// adds the products of those entries in the run's order.  The summation order is fixed (deterministic).  A1 is
+// symmetric, so only the blocks with K <= K' are formed (workgroup t: block up[t]) and each off-diagonal one is
+// also stored transposed as block mir[t] = (K', K).
 template <int EMAX>
-__global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, const int* __restrict__ brow,
+__global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, const int* __restrict__ up,
+                                                   const int* __restrict__ mir, const int* __restrict__ brow,
                                                    const int* __restrict__ bptr, const int* __restrict__ gal_ptr,
                                                    const int* __restrict__ gal_ent, const int* __restrict__ owner,
                                                    const double* __restrict__ xi, const int* __restrict__ col,
@@ -3230,7 +3233,7 @@ __global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, co
   __shared__ double sl[8][32][12];  // per group: the 1D tables l[a][j] (at 4 a + j) of 32 entries' x_j
   __shared__ double sv[8][32];      // their values A_ij
   __shared__ int sf[8][32];         // their column is free (owner >= 0)
-  const int64_t blkid = blockIdx.x;
+  const int64_t blkid = up[blockIdx.x];
   const int K = brow[blkid];
   const int slot = (int)(blkid - bptr[K]);
   const int nbK = bptr[K + 1] - bptr[K];
@@ -3326,24 +3329,32 @@ __global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, co
 #pragma unroll
   for (int m = 0; m < EMAX; ++m)
     if (qi[m] >= 0) out[obase + (int64_t)qi[m] * nbK * B + (int64_t)slot * B + qj[m]] = acc[m];
+  const int mb = mir[blockIdx.x];
+  if (mb >= 0) {  // uniform over the workgroup
+    const int Km = brow[mb], slm = mb - bptr[Km], nbm = bptr[Km + 1] - bptr[Km];
+    const int64_t mbase = (int64_t)B * B * bptr[Km];
+#pragma unroll
+    for (int m = 0; m < EMAX; ++m)
+      if (qi[m] >= 0) out[mbase + (int64_t)qj[m] * nbm * B + (int64_t)slm * B + qi[m]] = acc[m];
+  }
 }
 
-void launch_galerkin0(int64_t nblocks, int d, int pc, const int* brow, const int* bptr, const int* gal_ptr,
-                      const int* gal_ent, const int* owner, const double* xi, const int* col, const double* val,
-                      double* out, hipStream_t s) {
+void launch_galerkin0(int64_t nup, int d, int pc, const int* up, const int* mir, const int* brow, const int* bptr,
+                      const int* gal_ptr, const int* gal_ent, const int* owner, const double* xi, const int* col,
+                      const double* val, double* out, hipStream_t s) {
   const int k = pc + 1;
   const int B = (d == 3) ? k * k * k : k * k;
   const int bb = B * B;
   Basis1D<double> bs = make_basis<double>(pc);
-  if (nblocks == 0) return;
+  if (nup == 0) return;
   if (bb <= 256)
-    hipLaunchKernelGGL((k_galerkin0<1>), dim3((unsigned)nblocks), dim3(256), 0, s, d, bs, brow, bptr, gal_ptr, gal_ent,
-                       owner, xi, col, val, out);
+    hipLaunchKernelGGL((k_galerkin0<1>), dim3((unsigned)nup), dim3(256), 0, s, d, bs, up, mir, brow, bptr, gal_ptr,
+                       gal_ent, owner, xi, col, val, out);
   else if (bb <= 768)
-    hipLaunchKernelGGL((k_galerkin0<3>), dim3((unsigned)nblocks), dim3(256), 0, s, d, bs, brow, bptr, gal_ptr, gal_ent,
-                       owner, xi, col, val, out);
+    hipLaunchKernelGGL((k_galerkin0<3>), dim3((unsigned)nup), dim3(256), 0, s, d, bs, up, mir, brow, bptr, gal_ptr,
+                       gal_ent, owner, xi, col, val, out);
   else
-    hipLaunchKernelGGL((k_galerkin0<16>), dim3((unsigned)nblocks), dim3(256), 0, s, d, bs, brow, bptr, gal_ptr,
+    hipLaunchKernelGGL((k_galerkin0<16>), dim3((unsigned)nup), dim3(256), 0, s, d, bs, up, mir, brow, bptr, gal_ptr,
                        gal_ent, owner, xi, col, val, out);
   check_launch("k_galerkin0");
 }

@@ -139,6 +139,8 @@ struct Analysis {
   std::vector<HostLevel> lv;             // lv[0] unused (fine level); lv[l] for l = 1..L
   std::vector<int32_t> gal_ptr;          // level-1 Galerkin work lists: per stored block, entries (row, s, e)
   std::vector<int32_t> gal_ent;
+  std::vector<int32_t> gal_up, gal_mir;  // blocks (K, K') with K <= K' that the kernel forms, and the block (K', K)
+                                         // each one's transpose fills (-1 on the diagonal)
   int nlevels() const { return (int)depths.size() + 1; }
 };
 
@@ -233,6 +235,7 @@ struct DevLevel {
   DBuf<int32_t> leaf_off;  // l = 0: nbox1 + 1 internal offsets of the level-1 boxes
   DBuf<int32_t> brow;    // l >= 1 during set-up: block -> block row
   DBuf<int32_t> gal_ptr, gal_ent;  // l = 1: Galerkin work lists
+  DBuf<int32_t> gal_up, gal_mir;   // l = 1: the blocks formed and their mirrors
   DBuf<double> pt64;     // l >= 1 (l < L): nbox x d x (p'+1)^2
   DBuf<float> pt32;
   int child_shift = 0;   // level l >= 2: 2^child_shift boxes of level l-1 per box

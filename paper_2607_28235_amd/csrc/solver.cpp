@@ -866,8 +866,8 @@ void numeric_setup(HandleImpl& h, hipStream_t s) {
     const int64_t nblk = H.bptr[H.nbox];
     if (l == 1) {
       DevLevel& F0 = dv.lv[0];
-      launch_galerkin0(nblk, an.d, an.pc, D.brow.p, D.bptr.p, D.gal_ptr.p, D.gal_ent.p, F0.owner.p, F0.xi64.p,
-                       F0.col.p, F0.val64.p, D.val64.p, s);
+      launch_galerkin0((int64_t)an.gal_up.size(), an.d, an.pc, D.gal_up.p, D.gal_mir.p, D.brow.p, D.bptr.p,
+                       D.gal_ptr.p, D.gal_ent.p, F0.owner.p, F0.xi64.p, F0.col.p, F0.val64.p, D.val64.p, s);
     } else {
       DevLevel& P = dv.lv[l - 1];
       launch_galerkin_c(nblk, an.d, an.pc, H.child_shift, (int)P.nbox, D.brow.p, D.bptr.p, D.bcol.p, P.bptr.p,
@@ -1169,6 +1169,8 @@ void device_setup(HandleImpl& h, hipStream_t s) {
     if (l == 1) {
       D.gal_ptr.upload(an.gal_ptr, s);
       D.gal_ent.upload(an.gal_ent, s);
+      D.gal_up.upload(an.gal_up, s);
+      D.gal_mir.upload(an.gal_mir, s);
     }
     D.val64.alloc((size_t)D.nnz + kFinePad);  // zero padding: the local-column kernel's vector loads
     R3MG_HIP_CHECK(hipMemsetAsync(D.val64.p, 0, D.val64.n * sizeof(double), s));
