@@ -3545,19 +3545,22 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // X[i][j] = M[(R + i) n + C + j] inside the matrix, outside it 1 on the diagonal of a diagonal tile (diag_pad)
 // and 0 elsewhere; stored s[i][j], or s[j][i] with trans.  The tile product reads its operands as s[k][index]
 // with the index running across the lanes, so an operand whose index is its row is loaded transposed.
-__device__ inline void dt_load(double (*s)[DT + 1], const double* __restrict__ M, int n, int R, int C, bool trans,
-                               bool diag_pad) {
-  // element (i, j) = (threadIdx.x / 64 + 4 q, threadIdx.x % 64) for q < 16; the 16 loads come from clamped
-  // addresses and are all issued before the first is used, and entries outside the matrix are masked afterwards
-  // (a load under a lane-dependent condition would be waited for on its own)
-  constexpr int K = DT * DT / 256;
+// element (i, j) = (threadIdx.x / 64 + 4 q, threadIdx.x % 64) of tile (R, C), q < 16, from clamped addresses (all
+// 16 loads issued before the first is used; entries outside the matrix are masked by dt_put)
+constexpr int kDtK = DT * DT / 256;
+__device__ inline void dt_fetch(double (&v)[kDtK], const double* __restrict__ M, int n, int R, int C) {
   const int j = threadIdx.x & 63, i0 = threadIdx.x >> 6;
   const int64_t cj = min(C + j, n - 1);
-  double v[K];
 #pragma unroll
-  for (int q = 0; q < K; ++q) v[q] = M[(int64_t)min(R + i0 + 4 * q, n - 1) * n + cj];
+  for (int q = 0; q < kDtK; ++q) v[q] = M[(int64_t)min(R + i0 + 4 * q, n - 1) * n + cj];
+}
+// the fetched elements into LDS (transposed if trans); entries outside the matrix read as 0, or 1 on the diagonal
+// (diag_pad)
+__device__ inline void dt_put(double (*s)[DT + 1], const double (&v)[kDtK], int n, int R, int C, bool trans,
+                              bool diag_pad) {
+  const int j = threadIdx.x & 63, i0 = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < K; ++q) {
+  for (int q = 0; q < kDtK; ++q) {
     const int i = i0 + 4 * q;
     const double x = (R + i < n && C + j < n) ? v[q] : (diag_pad && i == j) ? 1.0 : 0.0;
     if (trans)
@@ -3565,6 +3568,15 @@ __device__ inline void dt_load(double (*s)[DT + 1], const double* __restrict__ M
     else
       s[i][j] = x;
   }
+}
+// tile (R, C) into LDS: the loads come from clamped addresses and are all issued before the first is used, and
+// entries outside the matrix are masked afterwards (a load under a lane-dependent condition would be waited for
+// on its own)
+__device__ inline void dt_load(double (*s)[DT + 1], const double* __restrict__ M, int n, int R, int C, bool trans,
+                               bool diag_pad) {
+  double v[kDtK];
+  dt_fetch(v, M, n, R, C);
+  dt_put(s, v, n, R, C, trans, diag_pad);
 }
 
 // a 64 x 64 tile of 64 x 64 values stored contiguously (row-major) into LDS, transposed: s[e % 64][e / 64] = T[e]
@@ -3871,10 +3883,18 @@ __global__ __launch_bounds__(256) void k_dinv_gram(int n, int nt, const double* 
   const int J = I + rem;
   v4d acc[2][2];
   dt_zero(acc);
+  // the tiles of step M + 1 are fetched into registers while step M's product runs from LDS
+  double va[kDtK], vb[kDtK];
+  dt_fetch(va, Y, n, DT * J, DT * I);
+  dt_fetch(vb, Y, n, DT * J, DT * J);
   for (int M = J; M < nt; ++M) {
-    dt_load(sa, Y, n, DT * M, DT * I, false, false);   // Aop(i, k) = Y_MI[k][i]
-    dt_load(sb, Y, n, DT * M, DT * J, false, false);   // Bop(k, j) = Y_MJ[k][j]
+    dt_put(sa, va, n, DT * M, DT * I, false, false);   // Aop(i, k) = Y_MI[k][i]
+    dt_put(sb, vb, n, DT * M, DT * J, false, false);   // Bop(k, j) = Y_MJ[k][j]
     __syncthreads();
+    if (M + 1 < nt) {  // uniform over the workgroup
+      dt_fetch(va, Y, n, DT * (M + 1), DT * I);
+      dt_fetch(vb, Y, n, DT * (M + 1), DT * J);
+    }
     dt_mfma(sa, sb, acc);
     __syncthreads();
   }
