@@ -3627,23 +3627,27 @@ __device__ inline void dt_each(const v4d acc[2][2], F f) {
       for (int r = 0; r < 4; ++r) f(r0 + 16 * s + 4 * r + (l >> 4), c0 + 16 * t + (l & 15), acc[s][t][r]);
 }
 
-// M tile (R, C) -= acc (sub) or = acc, inside the matrix.  For sub, the old values are loaded first from
-// clamped addresses, all before the first is used.
-__device__ inline void dt_store(const v4d acc[2][2], double* M, int n, int R, int C, bool sub) {
+// the elements of tile (R, C) of M in the accumulator's layout (as dt_each visits them), from clamped addresses,
+// all loads issued before the first is used
+__device__ inline void dt_fetch_acc(double (&old)[2][2][4], const double* M, int n, int R, int C) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
-  double old[2][2][4];
-  if (sub) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+  for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = r0 + 16 * s + 4 * r + (l >> 4), j = c0 + 16 * t + (l & 15);
-          old[s][t][r] = M[(int64_t)min(R + i, n - 1) * n + min(C + j, n - 1)];
-        }
-  }
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + 16 * s + 4 * r + (l >> 4), j = c0 + 16 * t + (l & 15);
+        old[s][t][r] = M[(int64_t)min(R + i, n - 1) * n + min(C + j, n - 1)];
+      }
+}
+
+// M tile (R, C) = old - acc (sub) or = acc, inside the matrix
+__device__ inline void dt_put_acc(const v4d acc[2][2], const double (&old)[2][2][4], double* M, int n, int R, int C,
+                                  bool sub) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -3653,6 +3657,22 @@ __device__ inline void dt_store(const v4d acc[2][2], double* M, int n, int R, in
         const int i = r0 + 16 * s + 4 * r + (l >> 4), j = c0 + 16 * t + (l & 15);
         if (R + i < n && C + j < n) M[(int64_t)(R + i) * n + C + j] = sub ? old[s][t][r] - acc[s][t][r] : acc[s][t][r];
       }
+}
+
+// M tile (R, C) = acc, inside the matrix
+__device__ inline void dt_store(const v4d acc[2][2], double* M, int n, int R, int C) {
+  const double none[2][2][4] = {};
+  dt_put_acc(acc, none, M, n, R, C, false);
+}
+
+// keeps fetched values ahead of a barrier (the compiler would otherwise sink their loads past it)
+__device__ inline void dt_pin(const double (&old)[2][2][4]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) asm volatile("" ::"v"(old[s][t][r]));
 }
 
 // sum over m in [m0, m1) of x[m sx] y[m sy] from LDS, in eight interleaved partial sums combined in a fixed
@@ -3796,7 +3816,7 @@ __global__ __launch_bounds__(256) void k_dchol_panel(int n, int k0, double* A, c
   v4d acc[2][2];
   dt_zero(acc);
   dt_mfma(sa, sb, acc);
-  dt_store(acc, A, n, R, k0, false);
+  dt_store(acc, A, n, R, k0);
 }
 
 // 1. Trailing update of the lower tiles (I, J), k0 < J <= I: A_IJ -= A_Ik A_Jk^T, with I = k0/64 + 1 + a and
@@ -3820,13 +3840,16 @@ __global__ __launch_bounds__(256) void k_dchol_update(int n, int k0, double* A, 
     }
   }
   const int RI = k0 + DT * (1 + a), RJ = k0 + DT * (1 + b);
+  double old[2][2][4];
+  dt_fetch_acc(old, A, n, RI, RJ);           // the tile updated, in flight with the operands
   dt_load(sa, A, n, RI, k0, true, false);    // Aop(i, k) = A_Ik[i][k]
   dt_load(sb, A, n, RJ, k0, true, false);    // Bop(k, j) = A_Jk[j][k]
+  dt_pin(old);
   __syncthreads();
   v4d acc[2][2];
   dt_zero(acc);
   dt_mfma(sa, sb, acc);
-  dt_store(acc, A, n, RI, RJ, true);
+  dt_put_acc(acc, old, A, n, RI, RJ, true);
 }
 
 // 2. Block row k of Y: tile (k, j) for j = blockIdx.x <= k: Y_kj <- D_k Y_kj, except Y_kk = D_k.
@@ -3853,7 +3876,7 @@ __global__ __launch_bounds__(256) void k_dinv_row(int n, int kb, const double* _
   dt_zero(acc);
   dt_mfma(sa, sb, acc);
   __syncthreads();
-  dt_store(acc, Y, n, R, C, false);
+  dt_store(acc, Y, n, R, C);
 }
 
 // 2. Rows below block row k: tile (r, j), r = kb + 1 + blockIdx.x / (kb + 1), j = blockIdx.x % (kb + 1):
@@ -3862,13 +3885,16 @@ __global__ __launch_bounds__(256) void k_dinv_update(int n, int kb, const double
   __shared__ double sa[DT][DT + 1];
   __shared__ double sb[DT][DT + 1];
   const int r = kb + 1 + (int)blockIdx.x / (kb + 1), j = (int)blockIdx.x % (kb + 1);
+  double old[2][2][4];
+  dt_fetch_acc(old, Y, n, DT * r, DT * j);           // the tile updated, in flight with the operands
   dt_load(sa, L, n, DT * r, DT * kb, true, false);   // Aop(i, k) = L_rk[i][k]
   dt_load(sb, Y, n, DT * kb, DT * j, false, false);  // Bop(k, j) = Y_kj[k][j]
+  dt_pin(old);
   __syncthreads();
   v4d acc[2][2];
   dt_zero(acc);
   dt_mfma(sa, sb, acc);
-  dt_store(acc, Y, n, DT * r, DT * j, true);
+  dt_put_acc(acc, old, Y, n, DT * r, DT * j, true);
 }
 
 // 3. Upper tile (I, J) of A^{-1} = Y^T Y and its mirror; blockIdx.x enumerates the pairs I <= J row by row.
@@ -3898,7 +3924,7 @@ __global__ __launch_bounds__(256) void k_dinv_gram(int n, int nt, const double* 
     dt_mfma(sa, sb, acc);
     __syncthreads();
   }
-  dt_store(acc, Inv, n, DT * I, DT * J, false);
+  dt_store(acc, Inv, n, DT * I, DT * J);
   if (I != J) {  // the mirror tile, staged in LDS so that its rows are written contiguously
     dt_each(acc, [&](int i, int j, double v) { sa[i][j] = v; });
     __syncthreads();
@@ -3918,16 +3944,24 @@ namespace {
 struct LookAhead {
   hipStream_t s2 = nullptr;
   std::vector<hipEvent_t> ev;
+  size_t next = 0;
   ~LookAhead() {
     for (auto e : ev) (void)hipEventDestroy(e);
     if (s2) (void)hipStreamDestroy(s2);
   }
+  // all events are created before the first launch, so that the host enqueues the steps ahead of the device
+  void create(size_t count) {
+    ev.reserve(count);
+    for (size_t i = 0; i < count; ++i) {
+      hipEvent_t e;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        throw std::runtime_error("dense Cholesky: event creation failed");
+      ev.push_back(e);
+    }
+  }
   hipEvent_t event() {
-    hipEvent_t e;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-      throw std::runtime_error("dense Cholesky: event creation failed");
-    ev.push_back(e);
-    return e;
+    if (next == ev.size()) throw std::runtime_error("dense Cholesky: events exhausted");
+    return ev[next++];
   }
 };
 }  // namespace
@@ -3937,6 +3971,7 @@ void dense_cholesky_inverse(int n, double* A, double* Inv, double* ws, double* Y
   LookAhead la;
   if (hipStreamCreateWithFlags(&la.s2, hipStreamNonBlocking) != hipSuccess)
     throw std::runtime_error("dense Cholesky: stream creation failed");
+  la.create(2 * (size_t)nt);
   hipEvent_t prev2 = nullptr;  // part 2 of the previous step done
   for (int kb = 0; kb < nt; ++kb) {
     const int k0 = kb * DT;
