@@ -3937,9 +3937,10 @@ __global__ __launch_bounds__(256) void k_dinv_gram(int n, int nt, const double* 
 
 // ws: nt * 64 * 64 doubles (the inverted diagonal tiles); Y: n * n doubles of scratch
 // The factorisation looks one step ahead: step kb's update of the next column (part 1) stays on s, while the
-// update of the other columns (part 2) runs on a second stream, so that diagonal tile and panel kb + 1, which
-// touch column kb + 1 only, overlap it.  Part 1 of step kb + 1 writes column kb + 2, which part 2 of step kb also
-// writes, so it waits for that; parts 2 follow one another on the second stream.
+// update of the other columns (part 2) runs on a second stream from the end of panel kb on, so that part 1,
+// diagonal tile and panel kb + 1, which touch column kb + 1 only, overlap it.  Part 1 of step kb + 1 writes column
+// kb + 2, which part 2 of step kb also writes, so it waits for that; parts 2 follow one another on the second
+// stream.
 namespace {
 struct LookAhead {
   hipStream_t s2 = nullptr;
@@ -3980,17 +3981,22 @@ void dense_cholesky_inverse(int n, double* A, double* Inv, double* ws, double* Y
     const int below = nt - kb - 1;
     if (below > 0) {
       hipLaunchKernelGGL(k_dchol_panel, dim3(below), dim3(256), 0, s, n, k0, A, Dk);
-      if (prev2 && hipStreamWaitEvent(s, prev2, 0) != hipSuccess)
-        throw std::runtime_error("dense Cholesky: stream wait failed");
-      hipLaunchKernelGGL(k_dchol_update, dim3(below), dim3(256), 0, s, n, k0, A, 1);
+      hipEvent_t done2 = nullptr;  // part 2 of this step done
       if (below > 1) {
+        // part 2 needs this step's panel only (part 1 writes another column), so it is forked right after the
+        // panel: no event then sits between part 1 and the next diagonal tile on s
         hipEvent_t main = la.event();
         if (hipEventRecord(main, s) != hipSuccess || hipStreamWaitEvent(la.s2, main, 0) != hipSuccess)
           throw std::runtime_error("dense Cholesky: event record failed");
         hipLaunchKernelGGL(k_dchol_update, dim3((below - 1) * below / 2), dim3(256), 0, la.s2, n, k0, A, 2);
-        prev2 = la.event();
-        if (hipEventRecord(prev2, la.s2) != hipSuccess) throw std::runtime_error("dense Cholesky: event record failed");
+        done2 = la.event();
+        if (hipEventRecord(done2, la.s2) != hipSuccess) throw std::runtime_error("dense Cholesky: event record failed");
       }
+      // part 1 writes the next column, which part 2 of the previous step also writes
+      if (prev2 && hipStreamWaitEvent(s, prev2, 0) != hipSuccess)
+        throw std::runtime_error("dense Cholesky: stream wait failed");
+      hipLaunchKernelGGL(k_dchol_update, dim3(below), dim3(256), 0, s, n, k0, A, 1);
+      if (done2) prev2 = done2;
     }
   }
   if (prev2 && hipStreamWaitEvent(s, prev2, 0) != hipSuccess)
