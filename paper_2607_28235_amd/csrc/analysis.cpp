@@ -505,7 +505,8 @@ std::unique_ptr<Analysis> analyze(const double* coords, int64_t n, const int64_t
           const int32_t* bc = H.bcol.data() + H.bptr[kp];
           const int32_t* be = H.bcol.data() + H.bptr[kp + 1];
           const int32_t* f = std::lower_bound(bc, be, (int32_t)k);
-          if (f == be || *f != k) throw err(R3MG_ERR_INVALID, "coarse block pattern is not symmetric");
+          if (f == be || *f != k)
+            throw err(R3MG_ERR_NOT_SPD, "the operator's sparsity pattern is not symmetric (coarse block pattern)");
           m = (int32_t)(H.bptr[kp] + (f - bc));
         }
         an->gal_up.push_back((int32_t)b);

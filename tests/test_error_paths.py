@@ -119,3 +119,22 @@ def test_nnz_beyond_int32_is_oom_before_reading_the_pattern():
     assert st == -5                       # R3MG_ERR_OOM
     assert not h.value                    # *out stays NULL
     assert b"int32" in L.r3mg_last_error()
+
+
+def test_one_sided_coupling_is_not_spd():
+    """An entry A_ij whose transpose A_ji is missing makes the coarse block pattern asymmetric; the library, which
+    forms only the upper coarse blocks and mirrors them, rejects it at analysis as not symmetric."""
+    prob = _cfg1()
+    free = np.flatnonzero(~prob.boundary)
+    i = int(free[0])
+    dist = np.linalg.norm(prob.coords[free] - prob.coords[i], axis=1)
+    j = int(free[int(np.argmax(dist))])
+    A = prob.scipy().tolil()
+    assert A[i, j] == 0 and A[j, i] == 0
+    A[i, j] = -1e-3
+    A = A.tocsr()
+    A.sort_indices()
+    with pytest.raises(P.R3mgError) as e:
+        P.Hierarchy(prob.coords, A.indptr, A.indices, A.data,
+                    P.Options(dim=2, coarse_degree=1, leaf_size=64, max_levels=2), factor=False)
+    assert e.value.code == "NOT_SPD" and "not symmetric" in str(e.value)
