@@ -2934,24 +2934,29 @@ __global__ __launch_bounds__(256) void k_dense_sym_tiles(int nc, int nt, const M
                                                          double* part, const int* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double sh[4][64];
+  __shared__ T sbr[4][16 * NR];  // wave w's 16 rows of b (0 past the last row), read at use (fewer registers)
   const int t = blockIdx.x;
   const int2 ij = tiles[t];
   const int I = ij.x, J = ij.y;
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const M* a = packed + (int64_t)t * (kDenseTile * kDenseTile) + (16 * w) * kDenseTile + lane;
-  double m[16];
+  M m[16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) m[k] = (double)a[k * kDenseTile];
+  for (int k = 0; k < 16; ++k) m[k] = a[k * kDenseTile];
   const int cj = J * kDenseTile + lane;
   const int ri = I * kDenseTile + 16 * w;
   // the entries of b are loaded up front from clamped addresses and masked (loads under a lane-dependent
-  // condition would each be waited for); the wave's 16 rows of b are the same for all its lanes
-  T bj[NR], br[16][NR];
+  // condition would each be waited for)
+  T bj[NR];
 #pragma unroll
-  for (int c = 0; c < NR; ++c) {
-    bj[c] = b[(int64_t)min(cj, nc - 1) * NR + c];
+  for (int c = 0; c < NR; ++c) bj[c] = b[(int64_t)min(cj, nc - 1) * NR + c];
+  if (I != J) {  // uniform over the workgroup
+    if (lane < 16) {
+      const T* bp = b + (int64_t)min(ri + lane, nc - 1) * NR;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) br[k][c] = (I != J) ? b[(int64_t)min(ri + k, nc - 1) * NR + c] : (T)0;
+      for (int c = 0; c < NR; ++c) sbr[w][lane * NR + c] = ri + lane < nc ? bp[c] : (T)0;
+    }
+    __syncthreads();
   }
   const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
   const int myrow = (b5 ? 8 : 0) + (b4 ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
@@ -2960,7 +2965,7 @@ __global__ __launch_bounds__(256) void k_dense_sym_tiles(int nc, int nt, const M
     double h8[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const double lo = m[q] * xj, hi = m[8 + q] * xj;
+      const double lo = (double)m[q] * xj, hi = (double)m[8 + q] * xj;
       h8[q] = (b5 ? hi : lo) + __shfl_xor(b5 ? lo : hi, 32, 64);
     }
     double h4[4];
@@ -2977,7 +2982,7 @@ __global__ __launch_bounds__(256) void k_dense_sym_tiles(int nc, int nt, const M
     if (I != J) {  // uniform over the workgroup
       double cs = 0;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) cs += m[k] * (ri + k < nc ? (double)br[k][c] : 0.0);
+      for (int k = 0; k < 16; ++k) cs += (double)m[k] * (double)sbr[w][k * NR + c];
       sh[w][lane] = cs;
       __syncthreads();
       if (w == 0)
