@@ -2924,10 +2924,11 @@ template void launch_dense_apply<double>(int, int, const double*, const double*,
 
 // Symmetric dense coarsest product.  Pass 1: one workgroup per upper tile (I, J); wave w holds the tile's rows
 // 16 w .. 16 w + 15 in registers (stored as M = float64, or float32 for the float32 V-cycle, and widened to
-// float64: the products and partial sums are float64 either way), lane = column.  The row products are summed over the 64 lanes by a transposing
-// butterfly (each step halves the rows a lane keeps and doubles the columns summed), which leaves lane l with
-// row 8 b5 + 4 b4 + 2 b3 + b2 of its wave (b = bits of l); the transposed products of an off-diagonal tile are
-// summed over the four waves in order.
+// float64 where used: the products and partial sums are float64 either way), lane = column.  The row products
+// are summed over the 64 lanes by a transposing butterfly (each step halves the rows a lane keeps and doubles
+// the columns summed), which leaves lane l with row 8 b5 + 4 b4 + 2 b3 + b2 of its wave (b = bits of l).  The
+// transposed products of an off-diagonal tile take the wave's 16 rows of b from LDS and are summed over the four
+// waves in order.
 template <typename T, typename M, int NR>
 __global__ __launch_bounds__(256) void k_dense_sym_tiles(int nc, int nt, const M* __restrict__ packed,
                                                          const int2* __restrict__ tiles, const T* __restrict__ b,
