@@ -3227,8 +3227,8 @@ void launch_diag_inv(int n, int blk, const int* ptr, const int* idx, const doubl
 // adds the products of those entries in the run's order.  The summation order is fixed (deterministic).  A1 is
 // symmetric, so only the blocks with K <= K' are formed (workgroup t: block up[t]) and each off-diagonal one is
 // also stored transposed as block mir[t] = (K', K).
-template <int EMAX>
-__global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, const int* __restrict__ up,
+template <int D, int KB>
+__global__ __launch_bounds__(256) void k_galerkin0(Basis1D<double> bs, const int* __restrict__ up,
                                                    const int* __restrict__ mir, const int* __restrict__ brow,
                                                    const int* __restrict__ bptr, const int* __restrict__ gal_ptr,
                                                    const int* __restrict__ gal_ent, const int* __restrict__ owner,
@@ -3243,8 +3243,11 @@ __global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, co
   const int K = brow[blkid];
   const int slot = (int)(blkid - bptr[K]);
   const int nbK = bptr[K + 1] - bptr[K];
-  const int k = bs.k;
-  const int B = (d == 3) ? k * k * k : k * k;
+  // dimension and degree are compile-time (lag1d_k and the digit arithmetic below unroll), with the same
+  // operations in the same order as the run-time forms
+  constexpr int d = D, k = KB;
+  constexpr int B = D == 3 ? KB * KB * KB : KB * KB;
+  constexpr int EMAX = (B * B + 255) / 256;
   int qi[EMAX], qj[EMAX];
   double acc[EMAX];
 #pragma unroll
@@ -3261,7 +3264,8 @@ __global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, co
     if (ent < en1) {
       const int i = gal_ent[3 * ent], s = gal_ent[3 * ent + 1], e = gal_ent[3 * ent + 2];
       double li[3][4];
-      for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)i * d + a], li[a]);
+#pragma unroll
+      for (int a = 0; a < d; ++a) lag1d_k<double, KB>(bs, xi[(int64_t)i * d + a], li[a]);
       for (int q = lt; q < B; q += 32) spi[g][q] = phi_q<double>(li, d, k, q);
       // lane lt owns q' = lt and lt + 32 (B <= 64); the digits of q' in base k pick the 1D tables
       int qd[2][3];
@@ -3279,7 +3283,8 @@ __global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, co
         const double v = val[p];
         const int own = owner[j];
         double lj[3][4] = {};
-        for (int a = 0; a < d; ++a) lag1d(bs, xi[(int64_t)j * d + a], lj[a]);
+#pragma unroll
+        for (int a = 0; a < d; ++a) lag1d_k<double, KB>(bs, xi[(int64_t)j * d + a], lj[a]);
         if (p0 + lt < e) {
           sv[g][lt] = v;
           sf[g][lt] = own >= 0;
@@ -3348,20 +3353,23 @@ __global__ __launch_bounds__(256) void k_galerkin0(int d, Basis1D<double> bs, co
 void launch_galerkin0(int64_t nup, int d, int pc, const int* up, const int* mir, const int* brow, const int* bptr,
                       const int* gal_ptr, const int* gal_ent, const int* owner, const double* xi, const int* col,
                       const double* val, double* out, hipStream_t s) {
-  const int k = pc + 1;
-  const int B = (d == 3) ? k * k * k : k * k;
-  const int bb = B * B;
   Basis1D<double> bs = make_basis<double>(pc);
   if (nup == 0) return;
-  if (bb <= 256)
-    hipLaunchKernelGGL((k_galerkin0<1>), dim3((unsigned)nup), dim3(256), 0, s, d, bs, up, mir, brow, bptr, gal_ptr,
-                       gal_ent, owner, xi, col, val, out);
-  else if (bb <= 768)
-    hipLaunchKernelGGL((k_galerkin0<3>), dim3((unsigned)nup), dim3(256), 0, s, d, bs, up, mir, brow, bptr, gal_ptr,
-                       gal_ent, owner, xi, col, val, out);
-  else
-    hipLaunchKernelGGL((k_galerkin0<16>), dim3((unsigned)nup), dim3(256), 0, s, d, bs, up, mir, brow, bptr, gal_ptr,
-                       gal_ent, owner, xi, col, val, out);
+#define R3MG_G0(DD, KK)                                                                                             \
+  hipLaunchKernelGGL((k_galerkin0<DD, KK>), dim3((unsigned)nup), dim3(256), 0, s, bs, up, mir, brow, bptr, gal_ptr,  \
+                     gal_ent, owner, xi, col, val, out)
+  switch (d * 8 + pc + 1) {
+    case 17: R3MG_G0(2, 1); break;
+    case 18: R3MG_G0(2, 2); break;
+    case 19: R3MG_G0(2, 3); break;
+    case 20: R3MG_G0(2, 4); break;
+    case 25: R3MG_G0(3, 1); break;
+    case 26: R3MG_G0(3, 2); break;
+    case 27: R3MG_G0(3, 3); break;
+    case 28: R3MG_G0(3, 4); break;
+    default: throw std::runtime_error("Galerkin product: unsupported dimension or degree");
+  }
+#undef R3MG_G0
   check_launch("k_galerkin0");
 }
 
