@@ -3375,15 +3375,19 @@ void launch_galerkin0(int64_t nup, int d, int pc, const int* up, const int* mir,
 
 // Galerkin product between agglomerated levels: A_{l+1}[G,G'] = sum_{C in G, C' in G'} P~_C^T A_l[C,C'] P~_C'.
 // One workgroup per output block; A_l blocks and P~ blocks are staged in LDS (dynamic, 4 B^2 doubles).
-template <int EMAX>
-__global__ __launch_bounds__(256) void k_galerkin_c(int d, int k, int shift, int nbox_in, const int* __restrict__ brow,
+template <int D, int KB>
+__global__ __launch_bounds__(256) void k_galerkin_c(int shift, int nbox_in, const int* __restrict__ brow,
                                                     const int* __restrict__ bptr_out, const int* __restrict__ bcol_out,
                                                     const int* __restrict__ bptr_in, const int* __restrict__ bcol_in,
                                                     const double* __restrict__ val_in, const double* __restrict__ pt,
                                                     double* out) {
   extern __shared__ unsigned char smem_raw[];
-  const int B = (d == 3) ? k * k * k : k * k;
-  const int bb = B * B;
+  // dimension and degree are compile-time: the B-long loops and the index divisions below unroll or fold, with the
+  // same operations in the same order
+  constexpr int d = D, k = KB;
+  constexpr int B = D == 3 ? KB * KB * KB : KB * KB;
+  constexpr int bb = B * B;
+  constexpr int EMAX = (bb + 255) / 256;
   double* sA = reinterpret_cast<double*>(smem_raw);
   double* sPc = sA + bb;
   double* sPp = sPc + bb;
@@ -3452,22 +3456,27 @@ void launch_galerkin_c(int64_t nblocks, int d, int pc, int shift, int nbox_in, c
   const int bb = B * B;
   const size_t shm = sizeof(double) * 4 * bb;
   if (nblocks == 0) return;
-  if (shm > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_c<16>),
+  if (shm > 65536) {  // only B = 64 (3D, degree 3)
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_galerkin_c<3, 4>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) throw std::runtime_error("coarse Galerkin: LDS request too large for this device");
   }
-  if (bb <= 256) {
-    int threads = ((bb + 63) / 64) * 64;
-    hipLaunchKernelGGL((k_galerkin_c<1>), dim3((unsigned)nblocks), dim3(threads), shm, s, d, k, shift, nbox_in, brow,
-                       bptr_out, bcol_out, bptr_in, bcol_in, val_in, pt, out);
-  } else if (bb <= 768) {
-    hipLaunchKernelGGL((k_galerkin_c<3>), dim3((unsigned)nblocks), dim3(256), shm, s, d, k, shift, nbox_in, brow,
-                       bptr_out, bcol_out, bptr_in, bcol_in, val_in, pt, out);
-  } else {
-    hipLaunchKernelGGL((k_galerkin_c<16>), dim3((unsigned)nblocks), dim3(256), shm, s, d, k, shift, nbox_in, brow,
-                       bptr_out, bcol_out, bptr_in, bcol_in, val_in, pt, out);
+  const int threads = bb <= 256 ? ((bb + 63) / 64) * 64 : 256;
+#define R3MG_GC(DD, KK)                                                                                             \
+  hipLaunchKernelGGL((k_galerkin_c<DD, KK>), dim3((unsigned)nblocks), dim3(threads), shm, s, shift, nbox_in, brow,  \
+                     bptr_out, bcol_out, bptr_in, bcol_in, val_in, pt, out)
+  switch (d * 8 + pc + 1) {
+    case 17: R3MG_GC(2, 1); break;
+    case 18: R3MG_GC(2, 2); break;
+    case 19: R3MG_GC(2, 3); break;
+    case 20: R3MG_GC(2, 4); break;
+    case 25: R3MG_GC(3, 1); break;
+    case 26: R3MG_GC(3, 2); break;
+    case 27: R3MG_GC(3, 3); break;
+    case 28: R3MG_GC(3, 4); break;
+    default: throw std::runtime_error("coarse Galerkin product: unsupported dimension or degree");
   }
+#undef R3MG_GC
   check_launch("k_galerkin_c");
 }
 
