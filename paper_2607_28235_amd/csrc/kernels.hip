@@ -4727,18 +4727,27 @@ __global__ void k_assemble(int64_t nnz, const int64_t* __restrict__ sp, const in
                            int nloc, const unsigned char* __restrict__ diag_one, double* vals) {
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (s >= nnz) return;
-  if (diag_one[s]) {
-    vals[s] = 1.0;
-    return;
-  }
+  const bool one = diag_one[s];
+  const int64_t m0 = sp[s], m1 = sp[s + 1];
   const int64_t nl2 = (int64_t)nloc * nloc;
   double acc = 0;
-  for (int64_t m = sp[s]; m < sp[s + 1]; ++m) {
-    const int64_t code = contrib[m];
-    const int64_t e = code / nl2, pr = code - e * nl2;
-    acc += kappa[e] * Ke[e * ke_stride + pr];
+  // four contributions at a time, their loads issued together from clamped indices, summed in order
+  for (int64_t m = m0; m < m1; m += 4) {
+    int64_t code[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) code[u] = contrib[min(m + u, m1 - 1)];
+    double kv[4], kev[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t e = code[u] / nl2, pr = code[u] - e * nl2;
+      kv[u] = kappa[e];
+      kev[u] = Ke[e * ke_stride + pr];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (m + u < m1) acc += kv[u] * kev[u];
   }
-  vals[s] = acc;
+  vals[s] = one ? 1.0 : acc;
 }
 void launch_assemble(int64_t nnz, const int64_t* slot_ptr, const int64_t* contrib, const double* kappa,
                      const double* Ke, int64_t ke_stride, int nloc, const unsigned char* diag_one, double* vals,
